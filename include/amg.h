@@ -1,0 +1,195 @@
+/*
+ * amg.h - C ABI of libamg, an MI355X (gfx950) adaptive multigrid solver for
+ * the Wilson-Dirac equation D(U) psi = chi (Eq. (1) of Brannick, Brower,
+ * Clark, Osborn, Rebbi, "Adaptive Multigrid Algorithm for Lattice QCD",
+ * arXiv:0707.4018).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Pointers named dev_* are HIP device pointers; everything else is host.
+ *   `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued
+ *   on `stream` and may still be running when a call returns, except where a
+ *   call documents a host synchronisation.
+ * - Canonical field layout (all dev_* fields crossing the ABI): complex
+ *   numbers interleaved (re, im), lexicographic sites with x_1 fastest, then
+ *   spin, then colour:  psi[rhs][site][spin][colour].  Complex128 unless an
+ *   entry point takes an amg_prec argument.  Two dimensions: n_s = 2,
+ *   n_c = 1 (U(1)); four dimensions: n_s = 4, n_c = 3 (SU(3)).
+ * - Canonical gauge layout: U[mu][site][a][b] complex128, row-major colour,
+ *   mu = 0..nd-1 the direction of x_{mu+1}.
+ * - Gamma matrices: 2d gamma_1 = sigma_1, gamma_2 = sigma_2; 4d chiral basis
+ *   gamma_k = [[0, -i sigma_k], [i sigma_k, 0]], gamma_4 = [[0, 1], [1, 0]];
+ *   gamma_5 is diagonal, +1 on the first half of the spin components.
+ * - Coarse fields (levels >= 1) are psi[rhs][coarse site][t], t = chi*N_v + k
+ *   (chirality major), complex128.
+ * - Ownership: the caller owns every dev_* buffer and must keep inputs alive
+ *   until `stream` has passed the call.  Handles own their internal device
+ *   memory (hipMalloc) and free it in amg_destroy_*.
+ * - Errors: every call returns amg_status; nothing throws across the ABI.
+ *   Arguments are validated on the host before any launch.  A thread-local
+ *   message with details is available from amg_last_error().
+ * - Handles are not thread-safe; distinct handles may be used from distinct
+ *   threads.
+ */
+#ifndef AMG_H
+#define AMG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  AMG_OK = 0,
+  AMG_ERR_ARG = 1,     /* invalid argument (NULL, out of range, non-finite) */
+  AMG_ERR_SHAPE = 2,   /* lattice / block / layout mismatch                 */
+  AMG_ERR_NAN = 3,     /* non-finite values detected                         */
+  AMG_ERR_NOMEM = 4,   /* device allocation failed                           */
+  AMG_ERR_HIP = 5,     /* a HIP runtime call failed                          */
+  AMG_ERR_RANK = 6,    /* block near-null vectors are linearly dependent     */
+  AMG_ERR_NOCONV = 7,  /* solver hit max_iter; psi holds the best iterate    */
+  AMG_ERR_STATE = 8    /* call not valid for this handle's state             */
+} amg_status;
+
+typedef enum { AMG_F64 = 0, AMG_F32 = 1 } amg_prec;  /* complex<double>, complex<float> */
+
+typedef struct amg_gauge amg_gauge;
+typedef struct amg_solver amg_solver;
+
+typedef struct {
+  int nd;        /* 2 (U(1), Schwinger model) or 4 (SU(3)) */
+  int dims[4];   /* L_1..L_nd; even extents; dims[nd..3] ignored */
+} amg_lattice;
+
+/* Multigrid parameters.  Defaults (amg_default_params) are the paper's where
+ * it gives one: 4x4 blocks, M = 8 vectors, omega = 0.8, 2 + 2 smoothing
+ * (numerical-test section). */
+typedef struct {
+  int nlevels;          /* 2..4 */
+  int block[3][4];      /* block extents of coarsening l (fine level l -> l+1) */
+  int nvec[3];          /* N_v of coarsening l; coarse dof per site = 2*N_v    */
+  int nu_pre, nu_post;  /* MR smoothing steps before / after the coarse correction */
+  double omega;         /* MR under-relaxation                                   */
+  double coarse_tol;    /* coarsest GCR: stop when |r| <= coarse_tol |b|         */
+  int coarse_maxiter;   /* coarsest GCR iteration cap                            */
+  int coarse_restart;   /* coarsest GCR restart length (<= 32)                   */
+  int outer_restart;    /* fine FGCR restart length (<= 32)                      */
+  int inner_prec;       /* AMG_F64: FP64 V-cycle; AMG_F32: FP32 V-cycle          */
+  int p_bf16;           /* with AMG_F32: store P in bfloat16 (Galerkin uses the rounded P) */
+} amg_mg_params;
+
+typedef struct {
+  int iters;                 /* outer FGCR (or CG) iterations                  */
+  int converged;             /* true residual <= tol                           */
+  double true_rel_res;       /* |chi - D psi| / |chi|, FP64, recomputed       */
+  long long n_fine_D;        /* fine D applications (all precisions)          */
+  long long n_fine_Ddag;     /* fine D^dagger applications                    */
+  long long n_coarse;        /* coarse-level operator applications            */
+  double t_ms;               /* wall time of the call (host clock, synchronised) */
+} amg_solve_info;
+
+/* ---- errors ------------------------------------------------------------ */
+const char* amg_status_str(amg_status s);
+const char* amg_last_error(void);   /* thread-local detail of the last failure */
+
+/* ---- gauge field and the fine operator --------------------------------- */
+
+/* Copy links (canonical complex128, [nd][V][nc][nc]) into a new gauge handle
+ * with FP64 and FP32 internal copies (structure-of-arrays).  mass is m of
+ * the operator (d + m) - 1/2 sum_mu [(1 - gamma_mu) U_mu(x) delta_{x+mu,y}
+ * + (1 + gamma_mu) U_mu(x-mu)^dag delta_{x-mu,y}] (definition after Eq. (1);
+ * diagonal read as d + m).  Synchronises `stream` before returning. */
+amg_status amg_gauge_create(const amg_lattice* lat, const void* dev_links, double mass,
+                            void* stream, amg_gauge** out);
+amg_status amg_gauge_set_mass(amg_gauge* g, double mass);
+amg_status amg_gauge_destroy(amg_gauge* g);
+
+/* dev_out = D dev_in (dagger = 0) or D^dagger dev_in (dagger = 1), nrhs
+ * canonical fields of precision prec (complex128 or complex64).  In-place
+ * (dev_out == dev_in) is an error.  Computes in prec. */
+amg_status amg_apply(const amg_gauge* g, int dagger, int prec, const void* dev_in,
+                     void* dev_out, int nrhs, void* stream);
+
+/* Apply the fine stencil `iters` times on the handle's internal
+ * structure-of-arrays buffers (no layout conversion): the kernel that the
+ * solver runs, for bandwidth measurement.  Enqueued on `stream`. */
+amg_status amg_apply_internal(amg_gauge* g, int dagger, int prec, int nrhs, int iters,
+                              void* stream);
+
+/* CG on the normal equations (the paper's baseline): D^dag D psi = D^dag chi
+ * in FP64, stopping on |chi - D psi| <= tol |chi|.  info: one per call. */
+amg_status amg_cgnr_solve(const amg_gauge* g, const void* dev_chi, void* dev_psi,
+                          double tol, int max_iter, amg_solve_info* info, void* stream);
+
+/* ---- multigrid ---------------------------------------------------------- */
+void amg_default_params(amg_mg_params* p);
+
+/* Build the hierarchy from given near-null vectors (Eq. (5) and the text
+ * after it): dev_nullvecs[l] holds nvec[l] complex128 fields of level l in
+ * canonical layout, [nvec][V_l][dof_l].  Blocks are orthonormalised per
+ * chirality in FP64 (AMG_ERR_RANK on dependence), coarse operators are the
+ * Galerkin products P^dag D P (Eq. (2)).  Synchronises `stream`. */
+amg_status amg_setup(const amg_gauge* g, const amg_mg_params* p,
+                     const void* const* dev_nullvecs, void* stream, amg_solver** out);
+
+/* Adaptive setup (text from Eq. (4) to the recursion remark after Eq. (5)),
+ * level by level: vector 1 is dev_init[l][0] relaxed by nu0 MR steps on
+ * A_l v = 0; vector k > 1 is dev_init[l][k-1] after ncyc sweeps of the
+ * two-level error propagation e <- e - V(A_l e) with the k-1 vectors built
+ * so far.  dev_init[l]: nvec[l] random complex128 fields of level l
+ * (canonical).  Synchronises `stream`. */
+amg_status amg_setup_adaptive(const amg_gauge* g, const amg_mg_params* p,
+                              const void* const* dev_init, int nu0, int ncyc,
+                              void* stream, amg_solver** out);
+
+/* Reuse the setup at another fine mass: every level's diagonal shifts by
+ * (mass - current) P^dag ... P 1 P ... P (exact, also for a rounded P). */
+amg_status amg_solver_set_mass(amg_solver* s, double mass);
+amg_status amg_solver_destroy(amg_solver* s);
+
+/* Solve D psi = chi for nrhs canonical complex128 fields by FP64 flexible GCR
+ * preconditioned by one V-cycle per iteration, to |chi - D psi| <= tol |chi|
+ * (true FP64 residual).  info: array of nrhs.  Returns AMG_ERR_NOCONV if any
+ * right-hand side misses tol within max_iter (psi holds the last iterate).
+ * Synchronises `stream` once per outer iteration. */
+amg_status amg_solve(amg_solver* s, const void* dev_chi, void* dev_psi, int nrhs,
+                     double tol, int max_iter, amg_solve_info* info, void* stream);
+
+/* ---- building blocks, exposed for parity checks -------------------------- */
+
+/* Raw near-null vectors of coarsening `level` as stored (before block
+ * orthonormalisation), complex128 canonical [nvec][V_l][dof_l]. */
+amg_status amg_get_nullvecs(const amg_solver* s, int level, void* dev_out, void* stream);
+
+/* Coarse operator of level `level` >= 1 in FP64: dev_out[V_l][2nd+1][Nc][Nc]
+ * complex128, block 0 the diagonal, block 1+2mu the coupling to x+mu,
+ * block 2+2mu to x-mu, row-major [t][t'] (row = output dof). */
+amg_status amg_get_coarse_op(const amg_solver* s, int level, void* dev_out, void* stream);
+
+/* Apply the operator of `level` (0 = fine) in precision prec to nrhs
+ * canonical fields of that level's precision. */
+amg_status amg_level_apply(const amg_solver* s, int level, int dagger, int prec,
+                           const void* dev_in, void* dev_out, int nrhs, void* stream);
+
+/* Restriction r_hat = P^dag r (dir = 0) or prolongation e = P e_hat (dir = 1)
+ * between level `level` and level+1, FP64 canonical, nrhs fields. */
+amg_status amg_transfer(const amg_solver* s, int level, int dir, const void* dev_in,
+                        void* dev_out, int nrhs, void* stream);
+
+/* One V-cycle x = V(b) from the finest level, in the solver's inner
+ * precision; b and x canonical complex128, nrhs fields. */
+amg_status amg_vcycle(amg_solver* s, const void* dev_b, void* dev_x, int nrhs, void* stream);
+
+/* nu MR steps (omega from the params) on level `level` from x = 0:
+ * x = MR_nu(b), FP64 canonical. */
+amg_status amg_mr(amg_solver* s, int level, int nu, const void* dev_b, void* dev_x,
+                  int nrhs, void* stream);
+
+/* Introspection: lattice extents and dof per site of a level. */
+amg_status amg_level_info(const amg_solver* s, int level, int* dims4, int* dof, long long* V);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AMG_H */

@@ -438,10 +438,47 @@ class Hierarchy:
         return len(self.ops)
 
 
-def coarsest_solve(A: Stencil, b: np.ndarray, p: MGParams) -> np.ndarray:
-    """Approximate solve on the coarsest level: unpreconditioned GCR to coarse_tol."""
-    x, _ = fgcr(A, b, lambda r: r, p.coarse_tol, p.coarse_maxiter, p.coarse_restart)
+def gcr_coarse(A: Stencil, b: np.ndarray, tol: float, maxiter: int, restart: int) -> np.ndarray:
+    """Approximate coarsest-level solve: unpreconditioned GCR from x = 0.
+
+    The paper solves its coarsest lattice exactly; a lattice too large for
+    that is solved approximately here (the outer Krylov method is flexible).
+    Iteration it: stop if ||r|| <= tol ||b|| (recursive residual); at the
+    start of every restart cycle after the first, r = b - A x and the stored
+    directions are dropped; then z = r, w = A z, w and z are orthogonalised
+    against the stored directions (classical Gram-Schmidt coefficients
+    <w_j, w>/<w_j, w_j>), alpha = <w, r>/<w, w>, x += alpha z, r -= alpha w.
+    At most maxiter iterations; tol >= 1 returns x = 0.
+    """
+    x = np.zeros_like(b, dtype=np.complex128)
+    r = b.astype(np.complex128).copy()
+    bb = vdot(b, b).real
+    done = True if tol >= 1.0 else bb == 0.0
+    Z, W, WW = [], [], []
+    for it in range(maxiter):
+        if done:
+            break
+        if it % restart == 0 and it > 0:
+            r = b - A.apply(x)
+            Z, W, WW = [], [], []
+        z = r.copy()
+        w = A.apply(z)
+        betas = [(vdot(W[j], w) / WW[j]) if WW[j] > 0 else 0.0 for j in range(len(W))]
+        for j, beta in enumerate(betas):
+            w = w - beta * W[j]
+            z = z - beta * Z[j]
+        ww = vdot(w, w).real
+        alpha = vdot(w, r) / ww if ww > 0 else 0.0
+        x = x + alpha * z
+        r = r - alpha * w
+        Z.append(z); W.append(w); WW.append(ww)
+        done = vdot(r, r).real <= tol * tol * bb
     return x
+
+
+def coarsest_solve(A: Stencil, b: np.ndarray, p: MGParams) -> np.ndarray:
+    """Solve on the coarsest level: GCR to coarse_tol (see gcr_coarse)."""
+    return gcr_coarse(A, b, p.coarse_tol, p.coarse_maxiter, p.coarse_restart)
 
 
 def vcycle(H: Hierarchy, level: int, b: np.ndarray) -> np.ndarray:

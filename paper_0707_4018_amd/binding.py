@@ -1,0 +1,331 @@
+"""ctypes binding of include/amg.h (argument marshalling only).
+
+Device tensors are torch tensors on the current HIP device; calls are
+enqueued on torch's current stream.  Field layouts are the canonical ones of
+the C ABI: complex psi[rhs][site][spin][colour] (x_1 fastest), links
+U[mu][site][a][b], coarse fields psi[rhs][site][t].
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+
+import torch
+
+F64 = 0
+F32 = 1
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+
+def lib_path() -> str:
+    return os.path.join(_HERE, "libamg.so")
+
+
+class AMGError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: status {status} ({detail})")
+        self.status = status
+
+
+class _Lattice(C.Structure):
+    _fields_ = [("nd", C.c_int), ("dims", C.c_int * 4)]
+
+
+class _Params(C.Structure):
+    _fields_ = [
+        ("nlevels", C.c_int), ("block", (C.c_int * 4) * 3), ("nvec", C.c_int * 3),
+        ("nu_pre", C.c_int), ("nu_post", C.c_int), ("omega", C.c_double),
+        ("coarse_tol", C.c_double), ("coarse_maxiter", C.c_int), ("coarse_restart", C.c_int),
+        ("outer_restart", C.c_int), ("inner_prec", C.c_int), ("p_bf16", C.c_int),
+    ]
+
+
+class _Info(C.Structure):
+    _fields_ = [
+        ("iters", C.c_int), ("converged", C.c_int), ("true_rel_res", C.c_double),
+        ("n_fine_D", C.c_longlong), ("n_fine_Ddag", C.c_longlong), ("n_coarse", C.c_longlong),
+        ("t_ms", C.c_double),
+    ]
+
+
+_P = C.c_void_p
+_SIGS = {
+    "amg_status_str": (C.c_char_p, [C.c_int]),
+    "amg_last_error": (C.c_char_p, []),
+    "amg_default_params": (None, [C.POINTER(_Params)]),
+    "amg_gauge_create": (C.c_int, [C.POINTER(_Lattice), _P, C.c_double, _P, C.POINTER(_P)]),
+    "amg_gauge_set_mass": (C.c_int, [_P, C.c_double]),
+    "amg_gauge_destroy": (C.c_int, [_P]),
+    "amg_apply": (C.c_int, [_P, C.c_int, C.c_int, _P, _P, C.c_int, _P]),
+    "amg_apply_internal": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, C.c_int, _P]),
+    "amg_cgnr_solve": (C.c_int, [_P, _P, _P, C.c_double, C.c_int, C.POINTER(_Info), _P]),
+    "amg_setup": (C.c_int, [_P, C.POINTER(_Params), C.POINTER(_P), _P, C.POINTER(_P)]),
+    "amg_setup_adaptive": (C.c_int, [_P, C.POINTER(_Params), C.POINTER(_P), C.c_int, C.c_int, _P,
+                                     C.POINTER(_P)]),
+    "amg_solver_set_mass": (C.c_int, [_P, C.c_double]),
+    "amg_solver_destroy": (C.c_int, [_P]),
+    "amg_solve": (C.c_int, [_P, _P, _P, C.c_int, C.c_double, C.c_int, C.POINTER(_Info), _P]),
+    "amg_get_nullvecs": (C.c_int, [_P, C.c_int, _P, _P]),
+    "amg_get_coarse_op": (C.c_int, [_P, C.c_int, _P, _P]),
+    "amg_level_apply": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, _P, _P, C.c_int, _P]),
+    "amg_transfer": (C.c_int, [_P, C.c_int, C.c_int, _P, _P, C.c_int, _P]),
+    "amg_vcycle": (C.c_int, [_P, _P, _P, C.c_int, _P]),
+    "amg_mr": (C.c_int, [_P, C.c_int, C.c_int, _P, _P, C.c_int, _P]),
+    "amg_level_info": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                 C.POINTER(C.c_longlong)]),
+}
+
+
+def load_library(path: str | None = None):
+    """Load libamg.so (built in-tree by paper_0707_4018_amd.build); raise if absent."""
+    global _LIB
+    if _LIB is not None and path is None:
+        return _LIB
+    p = path or lib_path()
+    if not os.path.exists(p):
+        raise FileNotFoundError(f"{p} is missing: build it with python -m paper_0707_4018_amd.build")
+    lib = C.CDLL(p)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    if path is None:
+        _LIB = lib
+    return lib
+
+
+def _check(status: int, where: str):
+    if status != 0:
+        lib = load_library()
+        raise AMGError(status, where, f"{lib.amg_status_str(status).decode()}: {lib.amg_last_error().decode()}")
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: torch.Tensor, dtype=torch.complex128) -> C.c_void_p:
+    if not t.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    if t.dtype != dtype:
+        raise ValueError(f"expected {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+@dataclass
+class MGParams:
+    """Multigrid parameters; defaults are the paper's where it gives one."""
+    blocks: list = field(default_factory=lambda: [(4, 4)])
+    nvec: list = field(default_factory=lambda: [8])
+    nu_pre: int = 2
+    nu_post: int = 2
+    omega: float = 0.8
+    coarse_tol: float = 0.1
+    coarse_maxiter: int = 64
+    coarse_restart: int = 16
+    outer_restart: int = 16
+    inner_prec: int = F64
+    p_bf16: bool = False
+
+    def to_c(self) -> _Params:
+        p = _Params()
+        load_library().amg_default_params(C.byref(p))
+        p.nlevels = len(self.blocks) + 1
+        for l, b in enumerate(self.blocks):
+            for mu in range(4):
+                p.block[l][mu] = int(b[mu]) if mu < len(b) else 1
+            p.nvec[l] = int(self.nvec[l])
+        p.nu_pre, p.nu_post, p.omega = self.nu_pre, self.nu_post, self.omega
+        p.coarse_tol, p.coarse_maxiter, p.coarse_restart = self.coarse_tol, self.coarse_maxiter, self.coarse_restart
+        p.outer_restart, p.inner_prec, p.p_bf16 = self.outer_restart, self.inner_prec, int(self.p_bf16)
+        return p
+
+
+@dataclass
+class SolveInfo:
+    iters: int
+    converged: bool
+    true_rel_res: float
+    n_fine_D: int
+    n_fine_Ddag: int
+    n_coarse: int
+    t_ms: float
+
+    @staticmethod
+    def from_c(i: _Info) -> "SolveInfo":
+        return SolveInfo(i.iters, bool(i.converged), i.true_rel_res, i.n_fine_D, i.n_fine_Ddag, i.n_coarse, i.t_ms)
+
+
+class Gauge:
+    """A gauge field handle with the fine Wilson-Dirac operator at mass m."""
+
+    def __init__(self, links: torch.Tensor, mass: float):
+        lib = load_library()
+        nd = links.shape[0]
+        lat = _Lattice()
+        lat.nd = nd
+        self.dims = tuple(int(d) for d in reversed(links.shape[1:1 + nd]))
+        for mu in range(4):
+            lat.dims[mu] = self.dims[mu] if mu < nd else 1
+        self.nd = nd
+        self.nc = 1 if nd == 2 else 3
+        self.ns = 2 if nd == 2 else 4
+        self.V = 1
+        for d in self.dims:
+            self.V *= d
+        self._links = links.contiguous()
+        h = C.c_void_p()
+        _check(lib.amg_gauge_create(C.byref(lat), _ptr(self._links), float(mass), _stream(), C.byref(h)),
+               "amg_gauge_create")
+        self._h = h
+        self.mass = float(mass)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_mass(self, m: float):
+        _check(load_library().amg_gauge_set_mass(self._h, float(m)), "amg_gauge_set_mass")
+        self.mass = float(m)
+
+    def apply(self, psi: torch.Tensor, dagger: bool = False, prec: int = F64) -> torch.Tensor:
+        """D psi (or D^dagger psi) for psi of shape (nrhs, V, ns, nc) or (V, ns, nc)."""
+        dt = torch.complex128 if prec == F64 else torch.complex64
+        x = psi.contiguous()
+        nrhs = x.shape[0] if x.dim() == 4 else 1
+        out = torch.empty_like(x)
+        _check(load_library().amg_apply(self._h, int(dagger), prec, _ptr(x, dt), _ptr(out, dt), nrhs, _stream()),
+               "amg_apply")
+        return out
+
+    def apply_internal(self, dagger: bool, prec: int, nrhs: int, iters: int):
+        _check(load_library().amg_apply_internal(self._h, int(dagger), prec, nrhs, iters, _stream()),
+               "amg_apply_internal")
+
+    def cgnr(self, chi: torch.Tensor, tol: float = 1e-10, max_iter: int = 100000):
+        x = chi.contiguous()
+        psi = torch.empty_like(x)
+        info = _Info()
+        st = load_library().amg_cgnr_solve(self._h, _ptr(x), _ptr(psi), float(tol), int(max_iter), C.byref(info),
+                                           _stream())
+        if st not in (0, 7):
+            _check(st, "amg_cgnr_solve")
+        return psi, SolveInfo.from_c(info)
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None):
+                load_library().amg_gauge_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+
+class Solver:
+    """Multigrid hierarchy + FGCR solver bound to a Gauge."""
+
+    def __init__(self, gauge: Gauge, params: MGParams, nullvecs=None, init=None, nu0: int = 20, ncyc: int = 2):
+        lib = load_library()
+        self.gauge = gauge
+        self.params = params
+        self._p = params.to_c()
+        h = C.c_void_p()
+        if nullvecs is not None:
+            vs = [v.contiguous() for v in nullvecs]
+            arr = (C.c_void_p * len(vs))(*[_ptr(v).value for v in vs])
+            _check(lib.amg_setup(gauge.handle, C.byref(self._p), arr, _stream(), C.byref(h)), "amg_setup")
+            self._keep = vs
+        elif init is not None:
+            vs = [v.contiguous() for v in init]
+            arr = (C.c_void_p * len(vs))(*[_ptr(v).value for v in vs])
+            _check(lib.amg_setup_adaptive(gauge.handle, C.byref(self._p), arr, int(nu0), int(ncyc), _stream(),
+                                          C.byref(h)), "amg_setup_adaptive")
+            self._keep = vs
+        else:
+            raise ValueError("give nullvecs (setup) or init (adaptive setup)")
+        self._h = h
+        self.mass = gauge.mass
+
+    def set_mass(self, m: float):
+        _check(load_library().amg_solver_set_mass(self._h, float(m)), "amg_solver_set_mass")
+        self.mass = float(m)
+
+    def level_info(self, level: int):
+        dims = (C.c_int * 4)()
+        dof = C.c_int()
+        V = C.c_longlong()
+        _check(load_library().amg_level_info(self._h, level, dims, C.byref(dof), C.byref(V)), "amg_level_info")
+        return tuple(dims), dof.value, V.value
+
+    def solve(self, chi: torch.Tensor, tol: float = 1e-10, max_iter: int = 1000, raise_noconv: bool = True):
+        """psi with |chi - D psi| <= tol |chi|; chi of shape (nrhs, V, ns, nc)."""
+        x = chi.contiguous()
+        nrhs = x.shape[0] if x.dim() == 4 else 1
+        psi = torch.empty_like(x)
+        infos = (_Info * nrhs)()
+        st = load_library().amg_solve(self._h, _ptr(x), _ptr(psi), nrhs, float(tol), int(max_iter), infos, _stream())
+        if st != 0 and (raise_noconv or st != 7):
+            _check(st, "amg_solve")
+        return psi, [SolveInfo.from_c(i) for i in infos]
+
+    def vcycle(self, b: torch.Tensor) -> torch.Tensor:
+        x = b.contiguous()
+        nrhs = x.shape[0] if x.dim() == 4 else 1
+        out = torch.empty_like(x)
+        _check(load_library().amg_vcycle(self._h, _ptr(x), _ptr(out), nrhs, _stream()), "amg_vcycle")
+        return out
+
+    def mr(self, level: int, nu: int, b: torch.Tensor, nrhs: int = 1) -> torch.Tensor:
+        x = b.contiguous()
+        out = torch.empty_like(x)
+        _check(load_library().amg_mr(self._h, level, nu, _ptr(x), _ptr(out), nrhs, _stream()), "amg_mr")
+        return out
+
+    def level_apply(self, level: int, x: torch.Tensor, dagger: bool = False, prec: int = F64, nrhs: int = 1):
+        dt = torch.complex128 if prec == F64 else torch.complex64
+        xi = x.contiguous()
+        out = torch.empty_like(xi)
+        _check(load_library().amg_level_apply(self._h, level, int(dagger), prec, _ptr(xi, dt), _ptr(out, dt), nrhs,
+                                              _stream()), "amg_level_apply")
+        return out
+
+    def restrict(self, level: int, r: torch.Tensor, nrhs: int = 1) -> torch.Tensor:
+        dims, dof, V = self.level_info(level + 1)
+        out = torch.empty((nrhs, V, dof), dtype=torch.complex128, device=r.device)
+        _check(load_library().amg_transfer(self._h, level, 0, _ptr(r.contiguous()), _ptr(out), nrhs, _stream()),
+               "amg_transfer")
+        return out
+
+    def prolong(self, level: int, e: torch.Tensor, nrhs: int = 1) -> torch.Tensor:
+        dims, dof, V = self.level_info(level)
+        out = torch.empty((nrhs, V, dof), dtype=torch.complex128, device=e.device)
+        _check(load_library().amg_transfer(self._h, level, 1, _ptr(e.contiguous()), _ptr(out), nrhs, _stream()),
+               "amg_transfer")
+        return out
+
+    def coarse_op(self, level: int) -> torch.Tensor:
+        dims, dof, V = self.level_info(level)
+        ndir = 2 * self.gauge.nd + 1
+        out = torch.empty((V, ndir, dof, dof), dtype=torch.complex128, device="cuda")
+        _check(load_library().amg_get_coarse_op(self._h, level, _ptr(out), _stream()), "amg_get_coarse_op")
+        return out
+
+    def nullvecs(self, level: int) -> torch.Tensor:
+        dims, dof, V = self.level_info(level)
+        nv = self.params.nvec[level]
+        out = torch.empty((nv, V, dof), dtype=torch.complex128, device="cuda")
+        _check(load_library().amg_get_nullvecs(self._h, level, _ptr(out), _stream()), "amg_get_nullvecs")
+        return out
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None):
+                load_library().amg_solver_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass

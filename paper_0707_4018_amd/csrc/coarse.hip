@@ -1,0 +1,453 @@
+// Coarse-level kernels: the Galerkin block stencil (Eq. (2) applied to D),
+// block restriction / prolongation onto chirally split near-null vectors
+// (Eq. (5) and the construction of v_{sj}), and the setup-side helpers
+// (block orthonormalisation, Galerkin assembly).
+//
+// Coarse fields: [rhs][site][t], t = chi * N_v + k.  Coarse operator:
+// Y[site][k][col][row], k = 0 the diagonal block, k = 1 + 2 mu the coupling
+// to site + mu, k = 2 + 2 mu to site - mu; each block stored column-major so
+// that the threads of one site (one per row) read consecutive addresses.
+// D_hat^dagger = Gamma_5 D_hat Gamma_5 with Gamma_5 = diag(+1_{N_v}, -1_{N_v})
+// because P commutes with gamma_5.
+#include "common.h"
+#include "kernels.h"
+
+namespace amg {
+namespace {
+
+__device__ __forceinline__ void coords(long site, const int* dims, int nd, int* x) {
+  long rem = site;
+  for (int mu = 0; mu < nd; ++mu) { x[mu] = (int)(rem % dims[mu]); rem /= dims[mu]; }
+}
+
+__device__ __forceinline__ long neighbour(long site, const int* x, const int* dims, int nd, int dir) {
+  // dir = 2 mu (+mu) or 2 mu + 1 (-mu)
+  const int mu = dir >> 1;
+  long stride = 1;
+  for (int nu = 0; nu < mu; ++nu) stride *= dims[nu];
+  const int L = dims[mu];
+  if ((dir & 1) == 0) return (x[mu] == L - 1) ? site - (long)(L - 1) * stride : site + stride;
+  return (x[mu] == 0) ? site + (long)(L - 1) * stride : site - stride;
+}
+
+template <typename T, int NC, int DAG, int EPI>
+__global__ __launch_bounds__(256) void coarse_kernel(CoarseArgs<T> a) {
+  const int rhs = blockIdx.y;
+  if (skip_rhs(a.red.flags, rhs)) return;
+  const int nc = NC > 0 ? NC : a.g.nc;
+  const int nd = a.g.nd;
+  const int ndir = 2 * nd + 1;
+  const long V = a.g.V;
+  const long total = V * nc;
+  const long ro = (long)rhs * total;
+  const cplx<T>* __restrict__ pin = a.in + ro;
+  double acc3[3] = {0.0, 0.0, 0.0};
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
+    const long site = i / nc;
+    const int row = (int)(i - site * nc);
+    int x[4];
+    coords(site, a.g.dims, nd, x);
+    cplx<T> acc = mk<T>(0, 0);
+    for (int k = 0; k < ndir; ++k) {
+      const long nb = (k == 0) ? site : neighbour(site, x, a.g.dims, nd, k - 1);
+      const cplx<T>* __restrict__ Yk = a.Y + ((site * ndir + k) * nc) * (long)nc + row;
+      const cplx<T>* __restrict__ e = pin + nb * nc;
+      if (NC > 0) {
+#pragma unroll 8
+        for (int col = 0; col < nc; ++col) {
+          cplx<T> v = e[col];
+          if (DAG && col >= nc / 2) v = mk<T>(-v.x, -v.y);
+          cfma<T>(acc, Yk[(long)col * nc], v);
+        }
+      } else {
+        for (int col = 0; col < nc; ++col) {
+          cplx<T> v = e[col];
+          if (DAG && col >= nc / 2) v = mk<T>(-v.x, -v.y);
+          cfma<T>(acc, Yk[(long)col * nc], v);
+        }
+      }
+    }
+    if (DAG && row >= nc / 2) acc = mk<T>(-acc.x, -acc.y);
+    const cplx<T> c = pin[i];
+    if (EPI == EPI_RESID) acc = csub<T>(a.b[ro + i], acc);
+    a.out[ro + i] = acc;
+    if (a.copy_out) a.copy_out[ro + i] = c;
+    if (EPI == EPI_MRDOT) {
+      acc3[0] += (double)acc.x * c.x + (double)acc.y * c.y;
+      acc3[1] += (double)acc.x * c.y - (double)acc.y * c.x;
+      acc3[2] += (double)acc.x * acc.x + (double)acc.y * acc.y;
+    } else if (EPI == EPI_NORM) {
+      acc3[0] += (double)acc.x * acc.x + (double)acc.y * acc.y;
+    }
+  }
+  if (EPI == EPI_MRDOT) {
+    double tot[3];
+    if (grid_reduce<3>(acc3, a.red.part, a.red.ticket, rhs, tot) && threadIdx.x == 0) finalize_mr(tot, a.red, rhs);
+  } else if (EPI == EPI_NORM) {
+    double a1[1] = {acc3[0]}, tot[1];
+    if (grid_reduce<1>(a1, a.red.part, a.red.ticket, rhs, tot) && threadIdx.x == 0) a.red.scal[a.red.slot + rhs] = tot[0];
+  }
+}
+
+// Split apply (FP64) of a coarse operator for the next Galerkin product:
+// out[0] = diagonal + hops inside the next block, out[1 + dir] = the hop in
+// direction dir when it leaves the block through its face.
+__global__ __launch_bounds__(256) void coarse_split_kernel(double2* __restrict__ out, const double2* __restrict__ in,
+                                                           const double2* __restrict__ Y, CoarseGeom g,
+                                                           int b0, int b1, int b2, int b3, int nrhs) {
+  const int rhs = blockIdx.y;
+  const int nc = g.nc, nd = g.nd, ndir = 2 * nd + 1;
+  const int blk[4] = {b0, b1, b2, b3};
+  const long total = g.V * nc;
+  const long ro = (long)rhs * total;
+  const long kstride = (long)nrhs * total;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
+    const long site = i / nc;
+    const int row = (int)(i - site * nc);
+    int x[4];
+    coords(site, g.dims, nd, x);
+    double2 inner = mk<double>(0, 0);
+    for (int k = 0; k < ndir; ++k) {
+      const long nb = (k == 0) ? site : neighbour(site, x, g.dims, nd, k - 1);
+      const double2* Yk = Y + ((site * ndir + k) * nc) * (long)nc + row;
+      const double2* e = in + ro + nb * nc;
+      double2 acc = mk<double>(0, 0);
+      for (int col = 0; col < nc; ++col) cfma<double>(acc, Yk[(long)col * nc], e[col]);
+      bool cross = false;
+      if (k > 0) {
+        const int mu = (k - 1) >> 1;
+        const int face = ((k - 1) & 1) ? 0 : blk[mu] - 1;
+        cross = (x[mu] % blk[mu]) == face;
+      }
+      if (cross) {
+        out[(long)k * kstride + ro + i] = acc;
+      } else {
+        inner = cadd<double>(inner, acc);
+        if (k > 0) out[(long)k * kstride + ro + i] = mk<double>(0, 0);
+      }
+    }
+    out[ro + i] = inner;
+  }
+}
+
+__global__ __launch_bounds__(256) void coarse_massmat_kernel(double2* __restrict__ out, const double2* __restrict__ in,
+                                                             const double2* __restrict__ M, long V, int nc) {
+  const int rhs = blockIdx.y;
+  const long total = V * nc;
+  const long ro = (long)rhs * total;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
+    const long site = i / nc;
+    const int row = (int)(i - site * nc);
+    const double2* Ms = M + site * (long)nc * nc + row;
+    const double2* e = in + ro + site * nc;
+    double2 acc = mk<double>(0, 0);
+    for (int col = 0; col < nc; ++col) cfma<double>(acc, Ms[(long)col * nc], e[col]);
+    out[ro + i] = acc;
+  }
+}
+
+// ---- transfers ---------------------------------------------------------------
+
+struct BlockIdx {
+  // fine site of (coarse site j, site-in-block xi)
+  static __device__ __forceinline__ long fine_site(const TransferGeom& g, long j, int xi) {
+    long rj = j;
+    int rxi = xi;
+    long fs = 0, stride = 1;
+    for (int mu = 0; mu < g.nd; ++mu) {
+      const int jc = (int)(rj % g.cdims[mu]); rj /= g.cdims[mu];
+      const int bc = rxi % g.blk[mu]; rxi /= g.blk[mu];
+      fs += (long)(jc * g.blk[mu] + bc) * stride;
+      stride *= g.fdims[mu];
+    }
+    return fs;
+  }
+  // (coarse site, site-in-block) of a fine site
+  static __device__ __forceinline__ void coarse_of(const TransferGeom& g, long fs, long& j, int& xi) {
+    long rem = fs, cs = 1;
+    int bstride = 1;
+    j = 0; xi = 0;
+    for (int mu = 0; mu < g.nd; ++mu) {
+      const int x = (int)(rem % g.fdims[mu]); rem /= g.fdims[mu];
+      j += (long)(x / g.blk[mu]) * cs;
+      xi += (x % g.blk[mu]) * bstride;
+      cs *= g.cdims[mu];
+      bstride *= g.blk[mu];
+    }
+  }
+};
+
+template <typename T, typename PT>
+__global__ __launch_bounds__(256) void restrict_kernel(cplx<T>* __restrict__ out, const cplx<T>* __restrict__ in,
+                                                       const PT* __restrict__ P, TransferGeom g, const int* flags) {
+  const int rhs = blockIdx.y;
+  if (skip_rhs(flags, rhs)) return;
+  const int nc = 2 * g.nv, hd = g.dof / 2;
+  const long total = g.Vc * nc;
+  const long rof = (long)rhs * g.lf.per_rhs();
+  const long roc = (long)rhs * total;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
+    const long j = i / nc;
+    const int t = (int)(i - j * nc);
+    const int chi = t / g.nv, k = t - chi * g.nv;
+    cplx<T> acc = mk<T>(0, 0);
+    for (int xi = 0; xi < g.bs; ++xi) {
+      const long fs = BlockIdx::fine_site(g, j, xi);
+      const long pb = ((j * g.bs + xi) * g.dof) * (long)g.nv + k;
+      for (int h = 0; h < hd; ++h) {
+        const int comp = chi * hd + h;
+        cjfma<T>(acc, ldp<T>(P, pb + (long)comp * g.nv), in[rof + g.lf.off(fs, comp)]);
+      }
+    }
+    out[roc + i] = acc;
+  }
+}
+
+template <typename T, typename PT>
+__global__ __launch_bounds__(256) void prolong_kernel(cplx<T>* __restrict__ out, const cplx<T>* __restrict__ in,
+                                                      const PT* __restrict__ P, TransferGeom g, int accumulate,
+                                                      const int* flags) {
+  const int rhs = blockIdx.y;
+  if (skip_rhs(flags, rhs)) return;
+  const int nc = 2 * g.nv, hd = g.dof / 2;
+  const long total = g.Vf * g.dof;
+  const long rof = (long)rhs * g.lf.per_rhs();
+  const long roc = (long)rhs * g.Vc * nc;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
+    // i enumerates (component, site) with the site fastest so that stores of
+    // the structure-of-arrays planes are contiguous
+    const int comp = (int)(i / g.Vf);
+    const long fs = i - (long)comp * g.Vf;
+    long j; int xi;
+    BlockIdx::coarse_of(g, fs, j, xi);
+    const int chi = comp / hd;
+    const long pb = ((j * g.bs + xi) * g.dof + comp) * (long)g.nv;
+    const cplx<T>* e = in + roc + j * nc + chi * g.nv;
+    cplx<T> acc = mk<T>(0, 0);
+    for (int k = 0; k < g.nv; ++k) cfma<T>(acc, ldp<T>(P, pb + k), e[k]);
+    const long o = rof + g.lf.off(fs, comp);
+    out[o] = accumulate ? cadd<T>(out[o], acc) : acc;
+  }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// One wave per (coarse site j, chirality chi): gather the block vectors into
+// P and orthonormalise them by modified Gram-Schmidt applied twice, in vector
+// order, with positive real normalisation.
+__global__ __launch_bounds__(64) void orthonormalise_kernel(double2* __restrict__ P, const double2* __restrict__ vecs,
+                                                            TransferGeom g, int* err) {
+  const long j = blockIdx.x;
+  const int chi = blockIdx.y;
+  const int lane = threadIdx.x;
+  const int hd = g.dof / 2, nv = g.nv;
+  const int dim = g.bs * hd;
+  const long per = g.lf.per_rhs();
+  auto pidx = [&](int e, int k) -> long {
+    const int xi = e / hd, h = e - xi * hd;
+    return ((j * g.bs + xi) * g.dof + chi * hd + h) * (long)nv + k;
+  };
+  for (int k = 0; k < nv; ++k)
+    for (int e = lane; e < dim; e += 64) {
+      const int xi = e / hd, h = e - xi * hd;
+      const long fs = BlockIdx::fine_site(g, j, xi);
+      P[pidx(e, k)] = vecs[(long)k * per + g.lf.off(fs, chi * hd + h)];
+    }
+  for (int k = 0; k < nv; ++k) {
+    double n0 = 0.0;
+    for (int e = lane; e < dim; e += 64) { const double2 w = P[pidx(e, k)]; n0 += w.x * w.x + w.y * w.y; }
+    n0 = sqrt(wave_sum(n0));
+    for (int pass = 0; pass < 2; ++pass)
+      for (int i = 0; i < k; ++i) {
+        double dr = 0.0, di = 0.0;
+        for (int e = lane; e < dim; e += 64) {
+          const double2 q = P[pidx(e, i)], w = P[pidx(e, k)];
+          dr += q.x * w.x + q.y * w.y;
+          di += q.x * w.y - q.y * w.x;
+        }
+        dr = wave_sum(dr); di = wave_sum(di);
+        for (int e = lane; e < dim; e += 64) {
+          const double2 q = P[pidx(e, i)];
+          double2 w = P[pidx(e, k)];
+          w.x -= dr * q.x - di * q.y;
+          w.y -= dr * q.y + di * q.x;
+          P[pidx(e, k)] = w;
+        }
+      }
+    double nr = 0.0;
+    for (int e = lane; e < dim; e += 64) { const double2 w = P[pidx(e, k)]; nr += w.x * w.x + w.y * w.y; }
+    nr = sqrt(wave_sum(nr));
+    if (!(nr > 1e-10 * n0) || n0 == 0.0) {
+      if (lane == 0) *err = 1;
+      nr = 1.0;
+    }
+    const double inv = 1.0 / nr;
+    for (int e = lane; e < dim; e += 64) {
+      double2 w = P[pidx(e, k)];
+      w.x *= inv; w.y *= inv;
+      P[pidx(e, k)] = w;
+    }
+  }
+}
+
+__global__ void galerkin_scatter_kernel(double2* __restrict__ Y, const double2* __restrict__ R, long Vc, int nc,
+                                        int nk, int t0, int chunk) {
+  const long total = (long)nk * chunk * Vc * nc;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
+    long r = i;
+    const int t = (int)(r % nc); r /= nc;
+    const long xs = r % Vc; r /= Vc;
+    const int c = (int)(r % chunk); r /= chunk;
+    const int k = (int)r;
+    Y[((xs * nk + k) * nc + (t0 + c)) * (long)nc + t] = R[i];
+  }
+}
+
+__global__ void unit_coarse_kernel(double2* __restrict__ E, long Vc, int nc, int t0, int chunk) {
+  const long total = (long)chunk * Vc * nc;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
+    const int t = (int)(i % nc);
+    const int c = (int)(i / ((long)Vc * nc));
+    E[i] = mk<double>(t == t0 + c ? 1.0 : 0.0, 0.0);
+  }
+}
+
+inline unsigned nblocks(long n, long cap = 1L << 20) {
+  long b = (n + 255) / 256;
+  if (b > cap) b = cap;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+}  // namespace
+
+template <typename T>
+void launch_coarse(const CoarseArgs<T>& a, int dagger, int epi, hipStream_t st) {
+  const long total = a.g.V * a.g.nc;
+  const bool red = (epi == EPI_MRDOT || epi == EPI_NORM);
+  dim3 grid(nblocks(total, red ? RED_MAX_BLOCKS : (1L << 20)), (unsigned)a.nrhs);
+#define AMG_C(NC, DAG, EPI) hipLaunchKernelGGL((coarse_kernel<T, NC, DAG, EPI>), grid, dim3(256), 0, st, a)
+#define AMG_C_EPI(NC, DAG)                      \
+  switch (epi) {                                \
+    case EPI_PLAIN: AMG_C(NC, DAG, EPI_PLAIN); break; \
+    case EPI_MRDOT: AMG_C(NC, DAG, EPI_MRDOT); break; \
+    case EPI_RESID: AMG_C(NC, DAG, EPI_RESID); break; \
+    default: AMG_C(NC, DAG, EPI_NORM); break;   \
+  }
+  if (a.g.nc == 16) {
+    if (dagger) { AMG_C_EPI(16, 1) } else { AMG_C_EPI(16, 0) }
+  } else if (a.g.nc == 48) {
+    if (dagger) { AMG_C_EPI(48, 1) } else { AMG_C_EPI(48, 0) }
+  } else {
+    if (dagger) { AMG_C_EPI(0, 1) } else { AMG_C_EPI(0, 0) }
+  }
+#undef AMG_C_EPI
+#undef AMG_C
+}
+template void launch_coarse<double>(const CoarseArgs<double>&, int, int, hipStream_t);
+template void launch_coarse<float>(const CoarseArgs<float>&, int, int, hipStream_t);
+
+void launch_coarse_split(double2* out, const double2* in, const double2* Y, const CoarseGeom& g, const int* blk,
+                         int nrhs, hipStream_t st) {
+  dim3 grid(nblocks(g.V * g.nc), (unsigned)nrhs);
+  hipLaunchKernelGGL(coarse_split_kernel, grid, dim3(256), 0, st, out, in, Y, g, blk[0], blk[1],
+                     g.nd > 2 ? blk[2] : 1, g.nd > 3 ? blk[3] : 1, nrhs);
+}
+
+void launch_coarse_massmat(double2* out, const double2* in, const double2* M, const CoarseGeom& g, int nrhs,
+                           hipStream_t st) {
+  dim3 grid(nblocks(g.V * g.nc), (unsigned)nrhs);
+  hipLaunchKernelGGL(coarse_massmat_kernel, grid, dim3(256), 0, st, out, in, M, g.V, g.nc);
+}
+
+template <typename T>
+void launch_restrict(cplx<T>* out, const cplx<T>* in, const void* P, int pkind, const TransferGeom& g, int nrhs,
+                     const int* flags, hipStream_t st) {
+  dim3 grid(nblocks(g.Vc * 2 * g.nv), (unsigned)nrhs);
+  if (pkind == P_F64)
+    hipLaunchKernelGGL((restrict_kernel<T, double2>), grid, dim3(256), 0, st, out, in, (const double2*)P, g, flags);
+  else if (pkind == P_F32)
+    hipLaunchKernelGGL((restrict_kernel<T, float2>), grid, dim3(256), 0, st, out, in, (const float2*)P, g, flags);
+  else
+    hipLaunchKernelGGL((restrict_kernel<T, bf16x2>), grid, dim3(256), 0, st, out, in, (const bf16x2*)P, g, flags);
+}
+template void launch_restrict<double>(double2*, const double2*, const void*, int, const TransferGeom&, int, const int*, hipStream_t);
+template void launch_restrict<float>(float2*, const float2*, const void*, int, const TransferGeom&, int, const int*, hipStream_t);
+
+template <typename T>
+void launch_prolong(cplx<T>* out, const cplx<T>* in, const void* P, int pkind, const TransferGeom& g, int nrhs,
+                    int accumulate, const int* flags, hipStream_t st) {
+  dim3 grid(nblocks(g.Vf * g.dof), (unsigned)nrhs);
+  if (pkind == P_F64)
+    hipLaunchKernelGGL((prolong_kernel<T, double2>), grid, dim3(256), 0, st, out, in, (const double2*)P, g, accumulate, flags);
+  else if (pkind == P_F32)
+    hipLaunchKernelGGL((prolong_kernel<T, float2>), grid, dim3(256), 0, st, out, in, (const float2*)P, g, accumulate, flags);
+  else
+    hipLaunchKernelGGL((prolong_kernel<T, bf16x2>), grid, dim3(256), 0, st, out, in, (const bf16x2*)P, g, accumulate, flags);
+}
+template void launch_prolong<double>(double2*, const double2*, const void*, int, const TransferGeom&, int, int, const int*, hipStream_t);
+template void launch_prolong<float>(float2*, const float2*, const void*, int, const TransferGeom&, int, int, const int*, hipStream_t);
+
+void launch_orthonormalise(double2* P, const double2* vecs, const TransferGeom& g, int* err, hipStream_t st) {
+  dim3 grid((unsigned)g.Vc, 2);
+  hipLaunchKernelGGL(orthonormalise_kernel, grid, dim3(64), 0, st, P, vecs, g, err);
+}
+
+void launch_galerkin_scatter(double2* Y, const double2* R, long Vc, int nc, int nk, int t0, int chunk, hipStream_t st) {
+  hipLaunchKernelGGL(galerkin_scatter_kernel, dim3(nblocks((long)nk * chunk * Vc * nc)), dim3(256), 0, st, Y, R, Vc,
+                     nc, nk, t0, chunk);
+}
+
+void launch_unit_coarse(double2* E, long Vc, int nc, int t0, int chunk, hipStream_t st) {
+  hipLaunchKernelGGL(unit_coarse_kernel, dim3(nblocks((long)chunk * Vc * nc)), dim3(256), 0, st, E, Vc, nc, t0, chunk);
+}
+
+}  // namespace amg
+
+namespace amg {
+namespace {
+__global__ void diag_shift_kernel(double2* __restrict__ Y, const double2* __restrict__ M, long V, int nc, int ndir,
+                                  double dm) {
+  const long per = (long)nc * nc;
+  const long total = V * per;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
+    const long site = i / per, e = i - site * per;
+    double2 y = Y[site * ndir * per + e];
+    const double2 m = M[i];
+    y.x += dm * m.x; y.y += dm * m.y;
+    Y[site * ndir * per + e] = y;
+  }
+}
+}  // namespace
+
+void launch_diag_shift(double2* Y, const double2* M, long V, int nc, int ndir, double dm, hipStream_t st) {
+  long nb = (V * nc * nc + 255) / 256;
+  if (nb > (1L << 20)) nb = 1L << 20;
+  hipLaunchKernelGGL(diag_shift_kernel, dim3((unsigned)nb), dim3(256), 0, st, Y, M, V, nc, ndir, dm);
+}
+}  // namespace amg
+
+namespace amg {
+namespace {
+__global__ void block_transpose_kernel(double2* __restrict__ out, const double2* __restrict__ in, long nblocks, int nc) {
+  const long per = (long)nc * nc;
+  const long total = nblocks * per;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
+    const long b = i / per;
+    const long e = i - b * per;
+    const int row = (int)(e / nc), col = (int)(e - (long)row * nc);
+    out[i] = in[b * per + (long)col * nc + row];
+  }
+}
+}  // namespace
+
+void launch_block_transpose(double2* out, const double2* in, long nblocks, int nc, hipStream_t st) {
+  long nb = (nblocks * nc * nc + 255) / 256;
+  if (nb > (1L << 20)) nb = 1L << 20;
+  hipLaunchKernelGGL(block_transpose_kernel, dim3((unsigned)nb), dim3(256), 0, st, out, in, nblocks, nc);
+}
+}  // namespace amg

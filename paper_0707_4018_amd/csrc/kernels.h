@@ -1,0 +1,151 @@
+// Launchers of the gfx950 kernels (host-callable), shared by the runtime.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace amg {
+
+// epilogues fused into operator applications
+enum Epi {
+  EPI_PLAIN = 0,  // out = A in
+  EPI_MRDOT = 1,  // out = A in; alpha = omega <out, in> / <out, out>  -> scal[slot + 2 rhs]
+  EPI_RESID = 2,  // out = b - A in
+  EPI_NORM = 3    // out = A in; scal[slot + rhs] = <out, out>
+};
+
+constexpr int RED_MAX_BLOCKS = 1024;   // grid cap of kernels that reduce
+constexpr int GCR_KMAX = 32;           // longest GCR restart cycle
+
+// Reduction plumbing handed to every kernel that reduces or can skip rhs.
+struct RedArgs {
+  double* part = nullptr;      // partial sums scratch
+  unsigned* ticket = nullptr;  // per-rhs arrival counters (zero between launches)
+  double* scal = nullptr;      // solver scalars
+  int slot = 0;                // where this reduction writes in scal
+  double omega = 1.0;          // MR under-relaxation (EPI_MRDOT)
+  const int* flags = nullptr;  // per-rhs skip flags (nullptr: none)
+};
+
+__device__ __forceinline__ void finalize_mr(const double* tot, const RedArgs& r, int rhs) {
+  const double pp = tot[2];
+  const double s = pp > 0.0 ? r.omega / pp : 0.0;
+  r.scal[r.slot + 2 * rhs] = s * tot[0];
+  r.scal[r.slot + 2 * rhs + 1] = s * tot[1];
+}
+
+template <typename T>
+struct WilsonArgs {
+  cplx<T>* out = nullptr;
+  const cplx<T>* in = nullptr;
+  const cplx<T>* b = nullptr;       // EPI_RESID
+  cplx<T>* copy_out = nullptr;      // optional copy of `in`
+  const cplx<T>* U = nullptr;       // internal link layout of precision T
+  double mass = 0.0;
+  int L1 = 0, L2 = 0, L3 = 1, L4 = 1;
+  int nrhs = 1;
+  RedArgs red;
+};
+
+template <typename T> void launch_wilson2d(const WilsonArgs<T>& a, int dagger, int epi, hipStream_t st);
+template <typename T> void launch_wilson4d(const WilsonArgs<T>& a, int dagger, int epi, hipStream_t st);
+void launch_wilson2d_split(double2* out, const double2* in, const double2* U, double mass, int L1,
+                           int L2, int b1, int b2, int nrhs, hipStream_t st);
+void launch_wilson4d_split(double2* out, const double2* in, const double2* U, double mass,
+                           const int* dims, const int* blk, int nrhs, hipStream_t st);
+
+// ---- coarse block stencil ---------------------------------------------------
+struct CoarseGeom {
+  int nd;
+  int dims[4];
+  long V;
+  int nc;       // dof per site
+};
+
+template <typename T>
+struct CoarseArgs {
+  cplx<T>* out = nullptr;
+  const cplx<T>* in = nullptr;
+  const cplx<T>* b = nullptr;
+  cplx<T>* copy_out = nullptr;
+  const cplx<T>* Y = nullptr;   // [V][2nd+1][nc (col)][nc (row)]
+  CoarseGeom g;
+  int nrhs = 1;
+  RedArgs red;
+};
+template <typename T> void launch_coarse(const CoarseArgs<T>& a, int dagger, int epi, hipStream_t st);
+void launch_coarse_split(double2* out, const double2* in, const double2* Y, const CoarseGeom& g,
+                         const int* blk, int nrhs, hipStream_t st);
+void launch_coarse_massmat(double2* out, const double2* in, const double2* M, const CoarseGeom& g,
+                           int nrhs, hipStream_t st);
+
+// ---- transfers ----------------------------------------------------------------
+struct TransferGeom {
+  int nd;
+  int fdims[4];   // fine extents
+  int blk[4];     // block extents
+  int cdims[4];   // coarse extents
+  long Vf, Vc;
+  int bs;         // sites per block
+  int dof;        // fine dof per site
+  int nv;         // vectors per chirality
+  Layout lf;      // fine field layout
+};
+// P storage kinds
+enum PKind { P_F64 = 0, P_F32 = 1, P_BF16 = 2 };
+template <typename T>
+void launch_restrict(cplx<T>* out, const cplx<T>* in, const void* P, int pkind, const TransferGeom& g,
+                     int nrhs, const int* flags, hipStream_t st);
+template <typename T>
+void launch_prolong(cplx<T>* out, const cplx<T>* in, const void* P, int pkind, const TransferGeom& g,
+                    int nrhs, int accumulate, const int* flags, hipStream_t st);
+// block orthonormalisation (FP64): vecs [nv][per_rhs] in layout g.lf -> P [Vc][bs][dof][nv]
+void launch_orthonormalise(double2* P, const double2* vecs, const TransferGeom& g, int* err_flag,
+                           hipStream_t st);
+void launch_galerkin_scatter(double2* Y, const double2* R, long Vc, int nc, int nk, int t0, int chunk,
+                             hipStream_t st);
+void launch_unit_coarse(double2* E, long Vc, int nc, int t0, int chunk, hipStream_t st);
+// per nc x nc block: out[row*nc + col] = in[col*nc + row]
+void launch_block_transpose(double2* out, const double2* in, long nblocks, int nc, hipStream_t st);
+
+// ---- BLAS-1 and conversions ----------------------------------------------------
+template <typename Tin, typename Tout>
+void launch_convert(cplx<Tout>* out, const cplx<Tin>* in, long V, int dof, int Win, int Wout, int nrhs,
+                    hipStream_t st);
+void launch_p_convert(void* out, int pkind, const double2* in, long n, hipStream_t st);
+void launch_p_roundtrip_bf16(double2* P, long n, hipStream_t st);
+template <typename T>
+void launch_mr_update(cplx<T>* x, cplx<T>* r_out, const cplx<T>* r_in, const cplx<T>* p,
+                      const double* alpha, long n, int nrhs, int first, int update_r, const int* flags,
+                      hipStream_t st);
+template <typename T>
+void launch_norm2(const cplx<T>* v, long n, int nrhs, RedArgs red, hipStream_t st);
+// GCR building blocks; directions stored contiguously: W_j = Wb + j * dstride
+template <typename T>
+void launch_gcr_mdot(const cplx<T>* Wb, long dstride, const cplx<T>* w, int k, long n, int nrhs,
+                     RedArgs red, int beta_slot, int ww_slot, hipStream_t st);
+template <typename T>
+void launch_gcr_maxpy(cplx<T>* w, cplx<T>* z, const cplx<T>* Wb, const cplx<T>* Zb, long dstride,
+                      const cplx<T>* r, int k, long n, int nrhs, RedArgs red, int beta_slot, int ww_slot,
+                      int alpha_slot, hipStream_t st);
+template <typename T>
+void launch_gcr_update(cplx<T>* x, cplx<T>* r, const cplx<T>* z, const cplx<T>* w, long n, int nrhs,
+                       RedArgs red, int alpha_slot, int rr_slot, int bb_slot, double tol2, int* set_flags,
+                       hipStream_t st);
+template <typename T>
+void launch_set_flags(int* flags, const double* scal, int rr_slot, int bb_slot, double tol2, int nrhs,
+                      hipStream_t st);
+template <typename T>
+void launch_axpy(cplx<T>* y, const cplx<T>* x, double are, double aim, long n, int nrhs, hipStream_t st);
+template <typename T>
+void launch_scale_inv_norm(cplx<T>* v, const double* nn, long n, int nrhs, hipStream_t st);
+void launch_diag_shift(double2* Y, const double2* M, long V, int nc, int ndir, double dm, hipStream_t st);
+void launch_links4d_pack(double2* U64, float2* U32, const double2* canon, long V, hipStream_t st);
+// CG on the normal equations
+void launch_cg_update(double2* x, double2* r, const double2* p, const double2* q, long n, int nrhs,
+                      RedArgs red, int gamma_slot, int qq_slot, int rr_slot, hipStream_t st);
+void launch_cg_pupdate(double2* p, const double2* s, long n, int nrhs, const double* scal, int gnew_slot,
+                       int gold_slot, hipStream_t st);
+
+}  // namespace amg

@@ -1,0 +1,1172 @@
+// Host runtime of libamg: gauge handles, the multigrid hierarchy, setup
+// (given or adaptive near-null vectors), the V-cycle, FGCR and CGNR, and the
+// C ABI declared in include/amg.h.  Every arithmetic step runs in the gfx950
+// kernels of this library; the host only sequences launches and reads one
+// residual norm per outer iteration.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "amg.h"
+#include "kernels.h"
+
+using namespace amg;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct Fail {
+  amg_status s;
+  std::string msg;
+};
+
+[[noreturn]] void fail(amg_status s, const std::string& m) { throw Fail{s, m}; }
+
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) fail(AMG_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+#define HIPC(x) hip_check((x), #x)
+
+// Owned device allocation.
+struct Buf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  Buf() = default;
+  Buf(const Buf&) = delete;
+  Buf& operator=(const Buf&) = delete;
+  Buf(Buf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  ~Buf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  void ensure(size_t n) {
+    if (n <= bytes && p) return;
+    release();
+    if (n == 0) n = 16;
+    if (hipMalloc(&p, n) != hipSuccess) {
+      p = nullptr;
+      fail(AMG_ERR_NOMEM, "hipMalloc of " + std::to_string(n) + " bytes failed");
+    }
+    bytes = n;
+  }
+  template <typename T> T* as() const { return reinterpret_cast<T*>(p); }
+};
+
+template <typename T> struct Pick;
+template <> struct Pick<double> { static constexpr int prec = AMG_F64; };
+template <> struct Pick<float> { static constexpr int prec = AMG_F32; };
+
+// Reduction scratch + scalar / flag storage shared by a handle's kernels.
+constexpr int RHS_MAX = 64;
+struct Scratch {
+  Buf part, ticket, scal, flags;
+  double* host = nullptr;  // pinned mirror of a few scalars
+  int nslots = 0;
+  void init(int nscal, int nflags) {
+    part.ensure(sizeof(double) * (size_t)RHS_MAX * 2 * GCR_KMAX * RED_MAX_BLOCKS);
+    ticket.ensure(sizeof(unsigned) * RHS_MAX);
+    HIPC(hipMemset(ticket.p, 0, sizeof(unsigned) * RHS_MAX));
+    scal.ensure(sizeof(double) * nscal);
+    HIPC(hipMemset(scal.p, 0, sizeof(double) * nscal));
+    flags.ensure(sizeof(int) * nflags);
+    HIPC(hipMemset(flags.p, 0, sizeof(int) * nflags));
+    if (!host) HIPC(hipHostMalloc((void**)&host, sizeof(double) * RHS_MAX * 4, hipHostMallocDefault));
+    nslots = nscal;
+  }
+  ~Scratch() {
+    if (host) (void)hipHostFree(host);
+  }
+  RedArgs red(int slot, const int* fl = nullptr, double omega = 1.0) const {
+    RedArgs r;
+    r.part = part.as<double>();
+    r.ticket = ticket.as<unsigned>();
+    r.scal = scal.as<double>();
+    r.slot = slot;
+    r.omega = omega;
+    r.flags = fl;
+    return r;
+  }
+  // copy n scalars from slot to the pinned mirror and wait for them
+  const double* fetch(int slot, int n, hipStream_t st) {
+    HIPC(hipMemcpyAsync(host, scal.as<double>() + slot, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    return host;
+  }
+};
+
+// slots of one GCR instance in the scalar array
+struct GcrSlots {
+  int beta, ww, alpha, rr, bb;
+  static int size() { return RHS_MAX * GCR_KMAX * 3 + RHS_MAX * 4; }
+  void at(int base) {
+    beta = base;
+    ww = beta + RHS_MAX * GCR_KMAX * 2;
+    alpha = ww + RHS_MAX * GCR_KMAX;
+    rr = alpha + RHS_MAX * 2;
+    bb = rr + RHS_MAX;
+  }
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// gauge handle
+// ---------------------------------------------------------------------------
+struct amg_gauge {
+  int nd = 2;
+  int dims[4] = {1, 1, 1, 1};
+  long V = 0;
+  int nc = 1, ns = 2, dof = 2;
+  double mass = 0.0;
+  Buf U64, U32;
+  // internal-layout buffers for amg_apply / amg_apply_internal
+  Buf tin, tout;
+  Scratch sc;
+  // CGNR work
+  Buf cg[6];
+  template <typename T> const cplx<T>* U() const;
+  Layout lay(int prec) const { return Layout{V, dof, prec == AMG_F64 ? 1 : 2}; }
+};
+template <> const double2* amg_gauge::U<double>() const { return U64.as<double2>(); }
+template <> const float2* amg_gauge::U<float>() const { return U32.as<float2>(); }
+
+namespace {
+
+template <typename T>
+void wilson_apply(const amg_gauge& g, double mass, int dagger, int epi, const cplx<T>* in, cplx<T>* out,
+                  const cplx<T>* b, cplx<T>* copy_out, int nrhs, RedArgs red, hipStream_t st) {
+  WilsonArgs<T> a;
+  a.out = out; a.in = in; a.b = b; a.copy_out = copy_out;
+  a.U = g.U<T>();
+  a.mass = mass;
+  a.L1 = g.dims[0]; a.L2 = g.dims[1]; a.L3 = g.dims[2]; a.L4 = g.dims[3];
+  a.nrhs = nrhs;
+  a.red = red;
+  if (g.nd == 2) launch_wilson2d<T>(a, dagger, epi, st);
+  else launch_wilson4d<T>(a, dagger, epi, st);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// multigrid hierarchy
+// ---------------------------------------------------------------------------
+namespace {
+
+enum { W_B = 0, W_X, W_R, W_P, W_COUNT };
+
+struct Level {
+  bool fine = false;
+  int nd = 2;
+  int dims[4] = {1, 1, 1, 1};
+  long V = 0;
+  int dof = 0;       // current dof per site
+  int dof_max = 0;   // allocation size (coarse levels grow during adaptive setup)
+  Layout lay64, lay32;
+  // coarse operator (levels >= 1): Y [V][2nd+1][dof][dof], mass matrix M [V][dof][dof]
+  Buf Y64, Y32, M64;
+  // transfer to the next level
+  bool has_next = false;
+  int blk[4] = {1, 1, 1, 1};
+  int nv = 0, nv_max = 0;
+  Buf vecs;          // raw near-null vectors [nv][per_rhs] (lay64)
+  Buf P64, P32, Pbf; // [Vc][bs][dof][nv]
+  // work vectors (per precision)
+  Buf w64[W_COUNT], w32[W_COUNT];
+  Buf Z64, W64, Z32, W32;  // GCR directions (coarsest level)
+  int alloc_nrhs = 0;
+  // scalar slots
+  int mr_slot = 0;
+  GcrSlots gs;
+  int flag_off = 0;
+
+  long per_rhs() const { return V * dof; }
+  int ndir() const { return 2 * nd + 1; }
+  CoarseGeom cgeom() const {
+    CoarseGeom c;
+    c.nd = nd;
+    for (int i = 0; i < 4; ++i) c.dims[i] = dims[i];
+    c.V = V;
+    c.nc = dof;
+    return c;
+  }
+  template <typename T> Buf* w() { return Pick<T>::prec == AMG_F64 ? w64 : w32; }
+  template <typename T> Buf& Zd() { return Pick<T>::prec == AMG_F64 ? Z64 : Z32; }
+  template <typename T> Buf& Wd() { return Pick<T>::prec == AMG_F64 ? W64 : W32; }
+  template <typename T> Layout lay() const { return Pick<T>::prec == AMG_F64 ? lay64 : lay32; }
+  template <typename T> const cplx<T>* Y() const;
+};
+template <> const double2* Level::Y<double>() const { return Y64.as<double2>(); }
+template <> const float2* Level::Y<float>() const { return Y32.as<float2>(); }
+
+}  // namespace
+
+struct amg_solver {
+  const amg_gauge* g = nullptr;
+  amg_mg_params p;
+  double mass = 0.0;
+  std::vector<Level> lv;
+  Scratch sc;
+  int flags_base = 0;
+  // outer FGCR (fine FP64)
+  Buf ox, orr, ob, oZ, oW, otmp;
+  int o_nrhs = 0;
+  int outer_slot = 0;
+  GcrSlots og;
+  // setup temporaries
+  Buf tE, tF, tS, tR, tzero;
+  long long nD = 0, nDd = 0, nC = 0;
+};
+
+namespace {
+
+using Solver = amg_solver;
+
+TransferGeom tgeom(const Solver& S, int l, int prec) {
+  const Level& f = S.lv[l];
+  const Level& c = S.lv[l + 1];
+  TransferGeom g;
+  g.nd = f.nd;
+  g.bs = 1;
+  for (int mu = 0; mu < 4; ++mu) {
+    g.fdims[mu] = f.dims[mu];
+    g.blk[mu] = f.blk[mu];
+    g.cdims[mu] = c.dims[mu];
+    if (mu < f.nd) g.bs *= f.blk[mu];
+  }
+  g.Vf = f.V;
+  g.Vc = c.V;
+  g.dof = f.dof;
+  g.nv = f.nv;
+  g.lf = prec == AMG_F64 ? f.lay64 : f.lay32;
+  return g;
+}
+
+template <typename T>
+const void* Pstore(const Solver& S, int l, int& kind) {
+  const Level& L = S.lv[l];
+  if (Pick<T>::prec == AMG_F64) { kind = P_F64; return L.P64.p; }
+  if (S.p.p_bf16) { kind = P_BF16; return L.Pbf.p; }
+  kind = P_F32;
+  return L.P32.p;
+}
+
+// operator of level l, precision T
+template <typename T>
+void op_apply(Solver& S, int l, int dagger, int epi, const cplx<T>* in, cplx<T>* out, const cplx<T>* b,
+              cplx<T>* copy_out, int nrhs, RedArgs red, hipStream_t st) {
+  Level& L = S.lv[l];
+  if (L.fine) {
+    wilson_apply<T>(*S.g, S.mass, dagger, epi, in, out, b, copy_out, nrhs, red, st);
+    (dagger ? S.nDd : S.nD) += 1;
+  } else {
+    CoarseArgs<T> a;
+    a.out = out; a.in = in; a.b = b; a.copy_out = copy_out;
+    a.Y = L.Y<T>();
+    a.g = L.cgeom();
+    a.nrhs = nrhs;
+    a.red = red;
+    launch_coarse<T>(a, dagger, epi, st);
+    S.nC += 1;
+  }
+}
+
+void alloc_level_work(Level& L, int nrhs, int restart, bool coarsest, bool f32) {
+  if (L.alloc_nrhs >= nrhs) return;
+  const size_t n = (size_t)L.V * L.dof_max * nrhs;
+  for (int i = 0; i < W_COUNT; ++i) {
+    L.w64[i].ensure(n * sizeof(double2));
+    if (f32) L.w32[i].ensure(n * sizeof(float2));
+  }
+  if (coarsest) {
+    L.Z64.ensure(n * restart * sizeof(double2));
+    L.W64.ensure(n * restart * sizeof(double2));
+    if (f32) {
+      L.Z32.ensure(n * restart * sizeof(float2));
+      L.W32.ensure(n * restart * sizeof(float2));
+    }
+  }
+  L.alloc_nrhs = nrhs;
+}
+
+void ensure_work(Solver& S, int nrhs) {
+  if (nrhs > RHS_MAX) fail(AMG_ERR_ARG, "nrhs exceeds " + std::to_string(RHS_MAX));
+  const bool f32 = S.p.inner_prec == AMG_F32;
+  const int nl = (int)S.lv.size();
+  for (int l = 0; l < nl; ++l) {
+    // during adaptive setup every level may serve as the coarsest one
+    alloc_level_work(S.lv[l], nrhs, S.p.coarse_restart, l > 0, f32);
+  }
+  if (S.o_nrhs < nrhs) {
+    const size_t n = (size_t)S.lv[0].V * S.lv[0].dof * nrhs;
+    S.ox.ensure(n * sizeof(double2));
+    S.orr.ensure(n * sizeof(double2));
+    S.ob.ensure(n * sizeof(double2));
+    S.otmp.ensure(n * sizeof(double2));
+    S.oZ.ensure(n * S.p.outer_restart * sizeof(double2));
+    S.oW.ensure(n * S.p.outer_restart * sizeof(double2));
+    S.o_nrhs = nrhs;
+  }
+}
+
+// ---- smoother ---------------------------------------------------------------
+// first = true:  x = MR_nu(b) from x = 0, r its residual;
+// first = false: b is the current residual (may alias r), x += MR_nu(b).
+template <typename T>
+void mr_smooth(Solver& S, int l, const cplx<T>* b, cplx<T>* x, cplx<T>* r, cplx<T>* p, int nu, bool first,
+               bool need_r, int nrhs, hipStream_t st) {
+  Level& L = S.lv[l];
+  const long n = L.per_rhs();
+  if (nu == 0) {
+    if (first) {
+      HIPC(hipMemsetAsync(x, 0, sizeof(cplx<T>) * n * nrhs, st));
+      if (need_r && r != b) HIPC(hipMemcpyAsync(r, b, sizeof(cplx<T>) * n * nrhs, hipMemcpyDeviceToDevice, st));
+    }
+    return;
+  }
+  for (int i = 0; i < nu; ++i) {
+    const cplx<T>* rin = (i == 0) ? b : r;
+    op_apply<T>(S, l, 0, EPI_MRDOT, rin, p, nullptr, nullptr, nrhs, S.sc.red(L.mr_slot, nullptr, S.p.omega), st);
+    const bool upd = (i < nu - 1) || need_r;
+    launch_mr_update<T>(x, r, rin, p, S.sc.scal.as<double>() + L.mr_slot, n, nrhs, first && i == 0, upd ? 1 : 0,
+                        nullptr, st);
+  }
+}
+
+// ---- coarsest solve: GCR with restarts, stopping per rhs on the recursive
+// residual |r| <= coarse_tol |b| (device flags; later launches become no-ops)
+template <typename T>
+void coarse_gcr(Solver& S, int l, const cplx<T>* b, cplx<T>* x, int nrhs, hipStream_t st) {
+  Level& L = S.lv[l];
+  const long n = L.per_rhs();
+  const long dstride = n * nrhs;
+  Buf* w = L.w<T>();
+  cplx<T>* r = w[W_R].as<cplx<T>>();
+  cplx<T>* Zb = L.template Zd<T>().template as<cplx<T>>();
+  cplx<T>* Wb = L.template Wd<T>().template as<cplx<T>>();
+  int* flags = S.sc.flags.as<int>() + L.flag_off;
+  const int m = S.p.coarse_restart;
+  const double tol2 = S.p.coarse_tol * S.p.coarse_tol;
+  HIPC(hipMemsetAsync(x, 0, sizeof(cplx<T>) * dstride, st));
+  HIPC(hipMemcpyAsync(r, b, sizeof(cplx<T>) * dstride, hipMemcpyDeviceToDevice, st));
+  launch_norm2<T>(b, n, nrhs, S.sc.red(L.gs.bb), st);
+  launch_set_flags<T>(flags, S.sc.scal.as<double>(), L.gs.bb, L.gs.bb, tol2 >= 1.0 ? 1.0 : 0.0, nrhs, st);
+  for (int it = 0; it < S.p.coarse_maxiter; ++it) {
+    const int k = it % m;
+    if (k == 0 && it > 0)
+      op_apply<T>(S, l, 0, EPI_RESID, x, r, b, nullptr, nrhs, S.sc.red(0, flags), st);
+    cplx<T>* Wk = Wb + (long)k * dstride;
+    cplx<T>* Zk = Zb + (long)k * dstride;
+    op_apply<T>(S, l, 0, EPI_PLAIN, r, Wk, nullptr, Zk, nrhs, S.sc.red(0, flags), st);
+    launch_gcr_mdot<T>(Wb, dstride, Wk, k, n, nrhs, S.sc.red(0, flags), L.gs.beta, L.gs.ww, st);
+    launch_gcr_maxpy<T>(Wk, Zk, Wb, Zb, dstride, r, k, n, nrhs, S.sc.red(0, flags), L.gs.beta, L.gs.ww, L.gs.alpha,
+                        st);
+    launch_gcr_update<T>(x, r, Zk, Wk, n, nrhs, S.sc.red(0, flags), L.gs.alpha, L.gs.rr, L.gs.bb, tol2, flags, st);
+  }
+}
+
+// ---- V-cycle (five steps listed before Eq. (3), applied to D) ---------------
+template <typename T>
+void vcycle(Solver& S, int l, int lstop, const cplx<T>* b, cplx<T>* x, int nrhs, hipStream_t st) {
+  if (l == lstop) {
+    coarse_gcr<T>(S, l, b, x, nrhs, st);
+    return;
+  }
+  Level& L = S.lv[l];
+  Level& C = S.lv[l + 1];
+  Buf* w = L.w<T>();
+  Buf* wc = C.w<T>();
+  cplx<T>* r = w[W_R].as<cplx<T>>();
+  cplx<T>* p = w[W_P].as<cplx<T>>();
+  int pk;
+  const void* P = Pstore<T>(S, l, pk);
+  const TransferGeom tg = tgeom(S, l, Pick<T>::prec);
+  // 1. pre-relax
+  mr_smooth<T>(S, l, b, x, r, p, S.p.nu_pre, true, true, nrhs, st);
+  // 2. restrict the residual
+  cplx<T>* bc = wc[W_B].as<cplx<T>>();
+  cplx<T>* xc = wc[W_X].as<cplx<T>>();
+  launch_restrict<T>(bc, r, P, pk, tg, nrhs, nullptr, st);
+  // 3. coarse-level cycle
+  vcycle<T>(S, l + 1, lstop, bc, xc, nrhs, st);
+  // 4. coarse-grid correction
+  launch_prolong<T>(x, xc, P, pk, tg, nrhs, 1, nullptr, st);
+  // 5. post-relax on the new residual
+  op_apply<T>(S, l, 0, EPI_RESID, x, r, b, nullptr, nrhs, S.sc.red(0), st);
+  mr_smooth<T>(S, l, r, x, r, p, S.p.nu_post, false, false, nrhs, st);
+}
+
+// ---- layout helpers ---------------------------------------------------------
+// canonical (AoS complex128) <-> internal layout of level l in precision T
+template <typename T>
+void to_internal(const Solver& S, int l, const double2* canon, cplx<T>* out, int nrhs, hipStream_t st) {
+  const Level& L = S.lv[l];
+  launch_convert<double, T>(out, canon, L.V, L.dof, L.dof, L.lay<T>().W, nrhs, st);
+}
+template <typename T>
+void to_canonical(const Solver& S, int l, const cplx<T>* in, double2* canon, int nrhs, hipStream_t st) {
+  const Level& L = S.lv[l];
+  launch_convert<T, double>(canon, in, L.V, L.dof, L.lay<T>().W, L.dof, nrhs, st);
+}
+
+// ---- setup ------------------------------------------------------------------
+// Build P_l from the first L.nv raw vectors and A_{l+1} = P_l^dag A_l P_l.
+void build_transfer(Solver& S, int l, hipStream_t st) {
+  Level& F = S.lv[l];
+  Level& C = S.lv[l + 1];
+  const int nv = F.nv;
+  C.dof = 2 * nv;
+  C.lay64 = Layout{C.V, C.dof, C.dof};
+  C.lay32 = C.lay64;
+  const TransferGeom tg = tgeom(S, l, AMG_F64);
+  const long psz = (long)F.V * F.dof * nv;  // P entries
+  F.P64.ensure(psz * sizeof(double2));
+  int* err = S.sc.flags.as<int>() + S.flags_base;  // scratch flag
+  HIPC(hipMemsetAsync(err, 0, sizeof(int), st));
+  launch_orthonormalise(F.P64.as<double2>(), F.vecs.as<double2>(), tg, err, st);
+  int herr = 0;
+  HIPC(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPC(hipStreamSynchronize(st));
+  if (herr) fail(AMG_ERR_RANK, "near-null vectors are linearly dependent on a block (level " + std::to_string(l) + ")");
+  if (S.p.inner_prec == AMG_F32) {
+    if (S.p.p_bf16) {
+      launch_p_roundtrip_bf16(F.P64.as<double2>(), psz, st);
+      F.Pbf.ensure(psz * sizeof(bf16x2));
+      launch_p_convert(F.Pbf.p, P_BF16, F.P64.as<double2>(), psz, st);
+    } else {
+      F.P32.ensure(psz * sizeof(float2));
+      launch_p_convert(F.P32.p, P_F32, F.P64.as<double2>(), psz, st);
+    }
+  }
+  // Galerkin product column by column: E = unit coarse fields, F = P E,
+  // S = split(A F), R = P^dag S, scattered into Y.  Mass matrix likewise.
+  const int nc = C.dof, ndir = F.ndir();
+  const long ysz = C.V * ndir * (long)nc * nc;
+  C.Y64.ensure(ysz * sizeof(double2));
+  C.M64.ensure(C.V * (long)nc * nc * sizeof(double2));
+  const long fper = F.per_rhs();
+  int chunk = nc;
+  const long budget = 1L << 31;  // bytes for the split outputs
+  while (chunk > 1 && (long)chunk * ndir * fper * 16 > budget) chunk = (chunk + 1) / 2;
+  S.tE.ensure((size_t)chunk * C.V * nc * sizeof(double2));
+  S.tF.ensure((size_t)chunk * fper * sizeof(double2));
+  S.tS.ensure((size_t)chunk * ndir * fper * sizeof(double2));
+  S.tR.ensure((size_t)chunk * ndir * C.V * nc * sizeof(double2));
+  double2* E = S.tE.as<double2>();
+  double2* Fv = S.tF.as<double2>();
+  double2* Sv = S.tS.as<double2>();
+  double2* Rv = S.tR.as<double2>();
+  for (int t0 = 0; t0 < nc; t0 += chunk) {
+    const int ch = std::min(chunk, nc - t0);
+    launch_unit_coarse(E, C.V, nc, t0, ch, st);
+    launch_prolong<double>(Fv, E, F.P64.p, P_F64, tg, ch, 0, nullptr, st);
+    if (F.fine) {
+      const amg_gauge& g = *S.g;
+      if (g.nd == 2)
+        launch_wilson2d_split(Sv, Fv, g.U64.as<double2>(), S.mass, g.dims[0], g.dims[1], F.blk[0], F.blk[1], ch, st);
+      else
+        launch_wilson4d_split(Sv, Fv, g.U64.as<double2>(), S.mass, g.dims, F.blk, ch, st);
+    } else {
+      launch_coarse_split(Sv, Fv, F.Y64.as<double2>(), F.cgeom(), F.blk, ch, st);
+    }
+    launch_restrict<double>(Rv, Sv, F.P64.p, P_F64, tg, ndir * ch, nullptr, st);
+    launch_galerkin_scatter(C.Y64.as<double2>(), Rv, C.V, nc, ndir, t0, ch, st);
+    // mass matrix: fine level d(D)/dm = 1, coarse levels their own M
+    const double2* MF = Fv;
+    if (!F.fine) {
+      launch_coarse_massmat(Sv, Fv, F.M64.as<double2>(), F.cgeom(), ch, st);
+      MF = Sv;
+    }
+    launch_restrict<double>(Rv, MF, F.P64.p, P_F64, tg, ch, nullptr, st);
+    launch_galerkin_scatter(C.M64.as<double2>(), Rv, C.V, nc, 1, t0, ch, st);
+  }
+  if (S.p.inner_prec == AMG_F32) {
+    C.Y32.ensure(ysz * sizeof(float2));
+    launch_p_convert(C.Y32.p, P_F32, C.Y64.as<double2>(), ysz, st);
+  }
+}
+
+void check_params(const amg_gauge* g, const amg_mg_params* p) {
+  if (!g || !p) fail(AMG_ERR_ARG, "NULL gauge or params");
+  if (p->nlevels < 2 || p->nlevels > 4) fail(AMG_ERR_ARG, "nlevels must be 2..4");
+  if (p->nu_pre < 0 || p->nu_post < 0 || p->nu_pre > 64 || p->nu_post > 64) fail(AMG_ERR_ARG, "bad smoothing steps");
+  if (!(p->omega > 0.0 && p->omega < 2.0)) fail(AMG_ERR_ARG, "omega must be in (0, 2)");
+  if (!(p->coarse_tol >= 0.0) || !std::isfinite(p->coarse_tol)) fail(AMG_ERR_ARG, "bad coarse_tol");
+  if (p->coarse_maxiter < 1 || p->coarse_restart < 1 || p->coarse_restart > GCR_KMAX) fail(AMG_ERR_ARG, "bad coarse GCR limits");
+  if (p->outer_restart < 1 || p->outer_restart > GCR_KMAX) fail(AMG_ERR_ARG, "outer_restart must be 1..32");
+  if (p->inner_prec != AMG_F64 && p->inner_prec != AMG_F32) fail(AMG_ERR_ARG, "bad inner_prec");
+  int dims[4];
+  for (int mu = 0; mu < 4; ++mu) dims[mu] = g->dims[mu];
+  int dof = g->dof;
+  for (int l = 0; l + 1 < p->nlevels; ++l) {
+    if (p->nvec[l] < 1 || p->nvec[l] > 64) fail(AMG_ERR_ARG, "nvec must be 1..64");
+    for (int mu = 0; mu < g->nd; ++mu) {
+      const int b = p->block[l][mu];
+      if (b < 1 || dims[mu] % b) fail(AMG_ERR_SHAPE, "block extents must divide the lattice extents");
+      dims[mu] /= b;
+    }
+    dof = 2 * p->nvec[l];
+  }
+  (void)dof;
+}
+
+Solver* new_solver(const amg_gauge* g, const amg_mg_params* p) {
+  check_params(g, p);
+  Solver* S = new Solver();
+  S->g = g;
+  S->p = *p;
+  S->mass = g->mass;
+  S->lv.resize(p->nlevels);
+  for (int l = 0; l < p->nlevels; ++l) {
+    Level& L = S->lv[l];
+    L.nd = g->nd;
+    if (l == 0) {
+      L.fine = true;
+      for (int mu = 0; mu < 4; ++mu) L.dims[mu] = g->dims[mu];
+      L.V = g->V;
+      L.dof = L.dof_max = g->dof;
+      L.lay64 = Layout{L.V, L.dof, 1};
+      L.lay32 = Layout{L.V, L.dof, 2};
+    } else {
+      Level& F = S->lv[l - 1];
+      L.V = 1;
+      for (int mu = 0; mu < 4; ++mu) {
+        L.dims[mu] = mu < g->nd ? F.dims[mu] / p->block[l - 1][mu] : 1;
+        L.V *= L.dims[mu];
+      }
+      L.dof = L.dof_max = 2 * p->nvec[l - 1];
+      L.lay64 = L.lay32 = Layout{L.V, L.dof, L.dof};
+    }
+    if (l + 1 < p->nlevels) {
+      L.has_next = true;
+      for (int mu = 0; mu < 4; ++mu) L.blk[mu] = mu < g->nd ? p->block[l][mu] : 1;
+      L.nv = L.nv_max = p->nvec[l];
+    }
+  }
+  // scalar slots: per level MR alpha + GCR set; outer GCR set
+  int off = 0;
+  for (auto& L : S->lv) {
+    L.mr_slot = off;
+    off += 2 * RHS_MAX;
+    L.gs.at(off);
+    off += GcrSlots::size();
+  }
+  S->og.at(off);
+  off += GcrSlots::size();
+  const int nflags = RHS_MAX * ((int)S->lv.size() + 2);
+  for (size_t l = 0; l < S->lv.size(); ++l) S->lv[l].flag_off = RHS_MAX * (int)l;
+  S->flags_base = RHS_MAX * (int)S->lv.size();
+  S->sc.init(off, nflags);
+  return S;
+}
+
+void upload_vectors(Solver& S, int l, const void* dev_canon, int nv, hipStream_t st) {
+  Level& L = S.lv[l];
+  L.vecs.ensure((size_t)L.nv_max * L.V * L.dof * sizeof(double2));
+  to_internal<double>(S, l, (const double2*)dev_canon, L.vecs.as<double2>(), nv, st);
+}
+
+// nu0 MR steps on A v = 0 from v (in place), FP64, on level l
+void relax_homogeneous(Solver& S, int l, double2* v, int nu0, hipStream_t st) {
+  Level& L = S.lv[l];
+  const long n = L.per_rhs();
+  double2* r = L.w64[W_R].as<double2>();
+  double2* p = L.w64[W_P].as<double2>();
+  double2* z = S.tzero.as<double2>();
+  op_apply<double>(S, l, 0, EPI_RESID, v, r, z, nullptr, 1, S.sc.red(0), st);  // r = 0 - A v
+  for (int i = 0; i < nu0; ++i) {
+    op_apply<double>(S, l, 0, EPI_MRDOT, r, p, nullptr, nullptr, 1, S.sc.red(L.mr_slot, nullptr, S.p.omega), st);
+    launch_mr_update<double>(v, r, r, p, S.sc.scal.as<double>() + L.mr_slot, n, 1, 0, 1, nullptr, st);
+  }
+}
+
+void adaptive_level(Solver& S, int l, const void* dev_init, int nu0, int ncyc, hipStream_t st) {
+  Level& L = S.lv[l];
+  const int nv = L.nv_max;
+  const long n = L.per_rhs();
+  upload_vectors(S, l, dev_init, nv, st);
+  S.tzero.ensure(n * sizeof(double2));
+  HIPC(hipMemsetAsync(S.tzero.p, 0, n * sizeof(double2), st));
+  double2* vecs = L.vecs.as<double2>();
+  relax_homogeneous(S, l, vecs, nu0, st);
+  double2* t = L.w64[W_B].as<double2>();  // A e
+  double2* zc = S.otmp.as<double2>();
+  for (int k = 1; k <= nv; ++k) {
+    L.nv = k;
+    build_transfer(S, l, st);
+    if (k == nv) break;
+    double2* e = vecs + (long)k * n;
+    for (int c = 0; c < ncyc; ++c) {
+      op_apply<double>(S, l, 0, EPI_PLAIN, e, t, nullptr, nullptr, 1, S.sc.red(0), st);
+      // z = V(A e) with level l+1 as the coarsest; kept in the outer scratch
+      // (level l's own x buffer is written inside the cycle)
+      vcycle<double>(S, l, l + 1, t, zc, 1, st);
+      launch_axpy<double>(e, zc, -1.0, 0.0, n, 1, st);
+    }
+    launch_norm2<double>(e, n, 1, S.sc.red(L.gs.rr), st);
+    launch_scale_inv_norm<double>(e, S.sc.scal.as<double>() + L.gs.rr, n, 1, st);
+  }
+}
+
+// ---- outer FGCR (fine level, FP64) ------------------------------------------
+struct OuterResult {
+  int iters = 0;
+  bool conv = false;
+  std::vector<double> rel;
+};
+
+void precondition(Solver& S, const double2* r, double2* z, int nrhs, hipStream_t st) {
+  const int last = (int)S.lv.size() - 1;
+  if (S.p.inner_prec == AMG_F64) {
+    vcycle<double>(S, 0, last, r, z, nrhs, st);
+  } else {
+    Level& F = S.lv[0];
+    float2* r32 = F.w32[W_B].as<float2>();
+    float2* z32 = F.w32[W_X].as<float2>();
+    launch_convert<double, float>(r32, r, F.V, F.dof, F.lay64.W, F.lay32.W, nrhs, st);
+    vcycle<float>(S, 0, last, r32, z32, nrhs, st);
+    launch_convert<float, double>(z, z32, F.V, F.dof, F.lay32.W, F.lay64.W, nrhs, st);
+  }
+}
+
+OuterResult fgcr_outer(Solver& S, const double2* b, double2* x, int nrhs, double tol, int maxiter, hipStream_t st) {
+  Level& F = S.lv[0];
+  const long n = F.per_rhs();
+  const long dstride = n * nrhs;
+  double2* r = S.orr.as<double2>();
+  double2* Zb = S.oZ.as<double2>();
+  double2* Wb = S.oW.as<double2>();
+  const int m = S.p.outer_restart;
+  const GcrSlots& gs = S.og;
+  HIPC(hipMemsetAsync(x, 0, sizeof(double2) * dstride, st));
+  HIPC(hipMemcpyAsync(r, b, sizeof(double2) * dstride, hipMemcpyDeviceToDevice, st));
+  launch_norm2<double>(b, n, nrhs, S.sc.red(gs.bb), st);
+  launch_norm2<double>(r, n, nrhs, S.sc.red(gs.rr), st);
+  std::vector<double> bb(nrhs), rr(nrhs);
+  {
+    const double* h = S.sc.fetch(gs.bb, nrhs, st);
+    for (int i = 0; i < nrhs; ++i) bb[i] = h[i];
+  }
+  OuterResult res;
+  int k = 0;
+  auto read_rr = [&]() {
+    const double* h = S.sc.fetch(gs.rr, nrhs, st);
+    for (int i = 0; i < nrhs; ++i) rr[i] = h[i];
+  };
+  auto all_below = [&]() {
+    for (int i = 0; i < nrhs; ++i)
+      if (!(rr[i] <= tol * tol * bb[i])) return false;
+    return true;
+  };
+  auto true_residual = [&]() {
+    op_apply<double>(S, 0, 0, EPI_RESID, x, r, b, nullptr, nrhs, S.sc.red(0), st);
+    launch_norm2<double>(r, n, nrhs, S.sc.red(gs.rr), st);
+  };
+  read_rr();
+  for (;;) {
+    if (all_below()) {
+      true_residual();
+      read_rr();
+      if (all_below()) { res.conv = true; break; }
+      k = 0;
+    }
+    if (res.iters >= maxiter) break;
+    double2* Zk = Zb + (long)k * dstride;
+    double2* Wk = Wb + (long)k * dstride;
+    precondition(S, r, Zk, nrhs, st);
+    op_apply<double>(S, 0, 0, EPI_PLAIN, Zk, Wk, nullptr, nullptr, nrhs, S.sc.red(0), st);
+    launch_gcr_mdot<double>(Wb, dstride, Wk, k, n, nrhs, S.sc.red(0), gs.beta, gs.ww, st);
+    launch_gcr_maxpy<double>(Wk, Zk, Wb, Zb, dstride, r, k, n, nrhs, S.sc.red(0), gs.beta, gs.ww, gs.alpha, st);
+    launch_gcr_update<double>(x, r, Zk, Wk, n, nrhs, S.sc.red(0), gs.alpha, gs.rr, gs.bb, 0.0, nullptr, st);
+    res.iters++;
+    k++;
+    if (k == m) {
+      true_residual();
+      k = 0;
+    }
+    read_rr();
+  }
+  if (!res.conv) {
+    true_residual();
+    read_rr();
+  }
+  res.rel.resize(nrhs);
+  for (int i = 0; i < nrhs; ++i) res.rel[i] = bb[i] > 0 ? std::sqrt(rr[i] / bb[i]) : 0.0;
+  return res;
+}
+
+void check_ptr(const void* p, const char* what) {
+  if (!p) fail(AMG_ERR_ARG, std::string("NULL ") + what);
+}
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+#define AMG_TRY try {
+#define AMG_CATCH                                              \
+  }                                                            \
+  catch (const Fail& f) {                                      \
+    g_last_error = f.msg;                                      \
+    return f.s;                                                \
+  }                                                            \
+  catch (const std::exception& e) {                            \
+    g_last_error = e.what();                                   \
+    return AMG_ERR_HIP;                                        \
+  }                                                            \
+  return AMG_OK;
+
+extern "C" {
+
+const char* amg_status_str(amg_status s) {
+  switch (s) {
+    case AMG_OK: return "ok";
+    case AMG_ERR_ARG: return "invalid argument";
+    case AMG_ERR_SHAPE: return "shape mismatch";
+    case AMG_ERR_NAN: return "non-finite values";
+    case AMG_ERR_NOMEM: return "out of device memory";
+    case AMG_ERR_HIP: return "HIP runtime error";
+    case AMG_ERR_RANK: return "linearly dependent near-null vectors";
+    case AMG_ERR_NOCONV: return "not converged";
+    case AMG_ERR_STATE: return "invalid state";
+  }
+  return "unknown status";
+}
+
+const char* amg_last_error(void) { return g_last_error.c_str(); }
+
+void amg_default_params(amg_mg_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->nlevels = 2;
+  for (int l = 0; l < 3; ++l) {
+    for (int mu = 0; mu < 4; ++mu) p->block[l][mu] = 4;
+    p->nvec[l] = 8;
+  }
+  p->nu_pre = 2;
+  p->nu_post = 2;
+  p->omega = 0.8;
+  p->coarse_tol = 0.1;
+  p->coarse_maxiter = 64;
+  p->coarse_restart = 16;
+  p->outer_restart = 16;
+  p->inner_prec = AMG_F64;
+  p->p_bf16 = 0;
+}
+
+amg_status amg_gauge_create(const amg_lattice* lat, const void* dev_links, double mass, void* stream,
+                            amg_gauge** out) {
+  AMG_TRY
+  check_ptr(lat, "lattice");
+  check_ptr(dev_links, "links");
+  check_ptr(out, "out");
+  if (lat->nd != 2 && lat->nd != 4) fail(AMG_ERR_ARG, "nd must be 2 or 4");
+  if (!std::isfinite(mass)) fail(AMG_ERR_ARG, "mass must be finite");
+  long V = 1;
+  for (int mu = 0; mu < lat->nd; ++mu) {
+    if (lat->dims[mu] < 2 || lat->dims[mu] % 2) fail(AMG_ERR_SHAPE, "lattice extents must be even and >= 2");
+    V *= lat->dims[mu];
+  }
+  if (V > (1L << 31)) fail(AMG_ERR_SHAPE, "lattice too large");
+  hipStream_t st = as_stream(stream);
+  amg_gauge* g = new amg_gauge();
+  try {
+    g->nd = lat->nd;
+    for (int mu = 0; mu < 4; ++mu) g->dims[mu] = mu < lat->nd ? lat->dims[mu] : 1;
+    g->V = V;
+    g->nc = lat->nd == 2 ? 1 : 3;
+    g->ns = lat->nd == 2 ? 2 : 4;
+    g->dof = g->nc * g->ns;
+    g->mass = mass;
+    if (g->nd == 2) {
+      g->U64.ensure((size_t)2 * V * sizeof(double2));
+      g->U32.ensure((size_t)2 * V * sizeof(float2));
+      // canonical [mu][site] is the FP64 plane layout; FP32 interleaves (U_1, U_2) per site
+      HIPC(hipMemcpyAsync(g->U64.p, dev_links, (size_t)2 * V * sizeof(double2), hipMemcpyDeviceToDevice, st));
+      launch_convert<double, float>(g->U32.as<float2>(), (const double2*)dev_links, V, 2, 1, 2, 1, st);
+    } else {
+      g->U64.ensure((size_t)36 * V * sizeof(double2));
+      g->U32.ensure((size_t)36 * V * sizeof(float2));
+      launch_links4d_pack(g->U64.as<double2>(), g->U32.as<float2>(), (const double2*)dev_links, V, st);
+    }
+    g->sc.init(64, RHS_MAX);
+    HIPC(hipStreamSynchronize(st));
+  } catch (...) {
+    delete g;
+    throw;
+  }
+  *out = g;
+  AMG_CATCH
+}
+
+amg_status amg_gauge_set_mass(amg_gauge* g, double mass) {
+  AMG_TRY
+  check_ptr(g, "gauge");
+  if (!std::isfinite(mass)) fail(AMG_ERR_ARG, "mass must be finite");
+  g->mass = mass;
+  AMG_CATCH
+}
+
+amg_status amg_gauge_destroy(amg_gauge* g) {
+  AMG_TRY
+  delete g;
+  AMG_CATCH
+}
+
+amg_status amg_apply(const amg_gauge* gc, int dagger, int prec, const void* dev_in, void* dev_out, int nrhs,
+                     void* stream) {
+  AMG_TRY
+  check_ptr(gc, "gauge");
+  check_ptr(dev_in, "in");
+  check_ptr(dev_out, "out");
+  if (dev_in == dev_out) fail(AMG_ERR_ARG, "in-place application is not supported");
+  if (nrhs < 1 || nrhs > RHS_MAX) fail(AMG_ERR_ARG, "bad nrhs");
+  if (prec != AMG_F64 && prec != AMG_F32) fail(AMG_ERR_ARG, "bad precision");
+  amg_gauge* g = const_cast<amg_gauge*>(gc);
+  hipStream_t st = as_stream(stream);
+  const size_t n = (size_t)g->V * g->dof * nrhs;
+  const int W = prec == AMG_F64 ? 1 : 2;
+  if (prec == AMG_F64) {
+    g->tin.ensure(n * sizeof(double2));
+    g->tout.ensure(n * sizeof(double2));
+    launch_convert<double, double>(g->tin.as<double2>(), (const double2*)dev_in, g->V, g->dof, g->dof, W, nrhs, st);
+    wilson_apply<double>(*g, g->mass, dagger, EPI_PLAIN, g->tin.as<double2>(), g->tout.as<double2>(), nullptr, nullptr,
+                         nrhs, g->sc.red(0), st);
+    launch_convert<double, double>((double2*)dev_out, g->tout.as<double2>(), g->V, g->dof, W, g->dof, nrhs, st);
+  } else {
+    g->tin.ensure(n * sizeof(float2));
+    g->tout.ensure(n * sizeof(float2));
+    launch_convert<float, float>(g->tin.as<float2>(), (const float2*)dev_in, g->V, g->dof, g->dof, W, nrhs, st);
+    wilson_apply<float>(*g, g->mass, dagger, EPI_PLAIN, g->tin.as<float2>(), g->tout.as<float2>(), nullptr, nullptr,
+                        nrhs, g->sc.red(0), st);
+    launch_convert<float, float>((float2*)dev_out, g->tout.as<float2>(), g->V, g->dof, W, g->dof, nrhs, st);
+  }
+  AMG_CATCH
+}
+
+amg_status amg_apply_internal(amg_gauge* g, int dagger, int prec, int nrhs, int iters, void* stream) {
+  AMG_TRY
+  check_ptr(g, "gauge");
+  if (nrhs < 1 || nrhs > RHS_MAX || iters < 0) fail(AMG_ERR_ARG, "bad nrhs / iters");
+  if (prec != AMG_F64 && prec != AMG_F32) fail(AMG_ERR_ARG, "bad precision");
+  hipStream_t st = as_stream(stream);
+  const size_t n = (size_t)g->V * g->dof * nrhs;
+  const size_t es = prec == AMG_F64 ? sizeof(double2) : sizeof(float2);
+  if (g->tin.bytes < n * es) {
+    g->tin.ensure(n * es);
+    HIPC(hipMemsetAsync(g->tin.p, 0, n * es, st));
+  }
+  g->tout.ensure(n * es);
+  for (int i = 0; i < iters; ++i) {
+    if (prec == AMG_F64)
+      wilson_apply<double>(*g, g->mass, dagger, EPI_PLAIN, g->tin.as<double2>(), g->tout.as<double2>(), nullptr,
+                           nullptr, nrhs, g->sc.red(0), st);
+    else
+      wilson_apply<float>(*g, g->mass, dagger, EPI_PLAIN, g->tin.as<float2>(), g->tout.as<float2>(), nullptr, nullptr,
+                          nrhs, g->sc.red(0), st);
+  }
+  AMG_CATCH
+}
+
+amg_status amg_cgnr_solve(const amg_gauge* gc, const void* dev_chi, void* dev_psi, double tol, int max_iter,
+                          amg_solve_info* info, void* stream) {
+  AMG_TRY
+  check_ptr(gc, "gauge");
+  check_ptr(dev_chi, "chi");
+  check_ptr(dev_psi, "psi");
+  if (!(tol > 0.0) || max_iter < 0) fail(AMG_ERR_ARG, "bad tol / max_iter");
+  amg_gauge* g = const_cast<amg_gauge*>(gc);
+  hipStream_t st = as_stream(stream);
+  const auto t0 = std::chrono::steady_clock::now();
+  const long n = g->V * g->dof;
+  for (auto& b : g->cg) b.ensure(n * sizeof(double2));
+  double2 *b = g->cg[0].as<double2>(), *x = g->cg[1].as<double2>(), *r = g->cg[2].as<double2>(),
+          *s = g->cg[3].as<double2>(), *p = g->cg[4].as<double2>(), *q = g->cg[5].as<double2>();
+  enum { SL_BB = 0, SL_RR = 1, SL_QQ = 2, SL_G0 = 3, SL_G1 = 4 };
+  launch_convert<double, double>(b, (const double2*)dev_chi, g->V, g->dof, g->dof, 1, 1, st);
+  HIPC(hipMemsetAsync(x, 0, n * sizeof(double2), st));
+  HIPC(hipMemcpyAsync(r, b, n * sizeof(double2), hipMemcpyDeviceToDevice, st));
+  long long nD = 0, nDd = 0;
+  wilson_apply<double>(*g, g->mass, 1, EPI_NORM, r, s, nullptr, nullptr, 1, g->sc.red(SL_G0), st);
+  nDd++;
+  HIPC(hipMemcpyAsync(p, s, n * sizeof(double2), hipMemcpyDeviceToDevice, st));
+  launch_norm2<double>(b, n, 1, g->sc.red(SL_BB), st);
+  const double bb = g->sc.fetch(SL_BB, 1, st)[0];
+  double rr = bb;
+  int it = 0, gcur = SL_G0, gnext = SL_G1;
+  while (!(rr <= tol * tol * bb) && it < max_iter) {
+    wilson_apply<double>(*g, g->mass, 0, EPI_NORM, p, q, nullptr, nullptr, 1, g->sc.red(SL_QQ), st);
+    nD++;
+    launch_cg_update(x, r, p, q, n, 1, g->sc.red(0), gcur, SL_QQ, SL_RR, st);
+    wilson_apply<double>(*g, g->mass, 1, EPI_NORM, r, s, nullptr, nullptr, 1, g->sc.red(gnext), st);
+    nDd++;
+    launch_cg_pupdate(p, s, n, 1, g->sc.scal.as<double>(), gnext, gcur, st);
+    std::swap(gcur, gnext);
+    ++it;
+    rr = g->sc.fetch(SL_RR, 1, st)[0];
+  }
+  // true residual
+  wilson_apply<double>(*g, g->mass, 0, EPI_RESID, x, r, b, nullptr, 1, g->sc.red(0), st);
+  nD++;
+  launch_norm2<double>(r, n, 1, g->sc.red(SL_RR), st);
+  rr = g->sc.fetch(SL_RR, 1, st)[0];
+  launch_convert<double, double>((double2*)dev_psi, x, g->V, g->dof, 1, g->dof, 1, st);
+  HIPC(hipStreamSynchronize(st));
+  const double rel = bb > 0 ? std::sqrt(rr / bb) : 0.0;
+  if (info) {
+    info->iters = it;
+    info->converged = rel <= tol;
+    info->true_rel_res = rel;
+    info->n_fine_D = nD;
+    info->n_fine_Ddag = nDd;
+    info->n_coarse = 0;
+    info->t_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (!(rel <= tol)) fail(AMG_ERR_NOCONV, "CGNR did not reach the tolerance");
+  AMG_CATCH
+}
+
+amg_status amg_setup(const amg_gauge* g, const amg_mg_params* p, const void* const* dev_nullvecs, void* stream,
+                     amg_solver** out) {
+  AMG_TRY
+  check_ptr(out, "out");
+  check_ptr(dev_nullvecs, "nullvecs");
+  Solver* S = new_solver(g, p);
+  hipStream_t st = as_stream(stream);
+  try {
+    ensure_work(*S, 1);
+    for (int l = 0; l + 1 < (int)S->lv.size(); ++l) {
+      check_ptr(dev_nullvecs[l], "nullvecs[l]");
+      upload_vectors(*S, l, dev_nullvecs[l], S->lv[l].nv_max, st);
+      build_transfer(*S, l, st);
+    }
+    HIPC(hipStreamSynchronize(st));
+  } catch (...) {
+    delete S;
+    throw;
+  }
+  *out = S;
+  AMG_CATCH
+}
+
+amg_status amg_setup_adaptive(const amg_gauge* g, const amg_mg_params* p, const void* const* dev_init, int nu0,
+                              int ncyc, void* stream, amg_solver** out) {
+  AMG_TRY
+  check_ptr(out, "out");
+  check_ptr(dev_init, "init");
+  if (nu0 < 0 || ncyc < 0) fail(AMG_ERR_ARG, "nu0 / ncyc must be >= 0");
+  Solver* S = new_solver(g, p);
+  hipStream_t st = as_stream(stream);
+  try {
+    ensure_work(*S, 1);
+    for (int l = 0; l + 1 < (int)S->lv.size(); ++l) {
+      check_ptr(dev_init[l], "init[l]");
+      adaptive_level(*S, l, dev_init[l], nu0, ncyc, st);
+    }
+    HIPC(hipStreamSynchronize(st));
+  } catch (...) {
+    delete S;
+    throw;
+  }
+  *out = S;
+  AMG_CATCH
+}
+
+amg_status amg_solver_set_mass(amg_solver* S, double mass) {
+  AMG_TRY
+  check_ptr(S, "solver");
+  if (!std::isfinite(mass)) fail(AMG_ERR_ARG, "mass must be finite");
+  const double dm = mass - S->mass;
+  S->mass = mass;
+  if (dm != 0.0) {
+    for (size_t l = 1; l < S->lv.size(); ++l) {
+      Level& L = S->lv[l];
+      launch_diag_shift(L.Y64.as<double2>(), L.M64.as<double2>(), L.V, L.dof, L.ndir(), dm, nullptr);
+      if (S->p.inner_prec == AMG_F32)
+        launch_p_convert(L.Y32.p, P_F32, L.Y64.as<double2>(), L.V * L.ndir() * (long)L.dof * L.dof, nullptr);
+    }
+    HIPC(hipStreamSynchronize(nullptr));
+  }
+  AMG_CATCH
+}
+
+amg_status amg_solver_destroy(amg_solver* S) {
+  AMG_TRY
+  delete S;
+  AMG_CATCH
+}
+
+amg_status amg_solve(amg_solver* S, const void* dev_chi, void* dev_psi, int nrhs, double tol, int max_iter,
+                     amg_solve_info* info, void* stream) {
+  AMG_TRY
+  check_ptr(S, "solver");
+  check_ptr(dev_chi, "chi");
+  check_ptr(dev_psi, "psi");
+  if (nrhs < 1 || nrhs > RHS_MAX) fail(AMG_ERR_ARG, "bad nrhs");
+  if (!(tol > 0.0) || max_iter < 0) fail(AMG_ERR_ARG, "bad tol / max_iter");
+  hipStream_t st = as_stream(stream);
+  const auto t0 = std::chrono::steady_clock::now();
+  ensure_work(*S, nrhs);
+  const long long d0 = S->nD, dd0 = S->nDd, c0 = S->nC;
+  to_internal<double>(*S, 0, (const double2*)dev_chi, S->ob.as<double2>(), nrhs, st);
+  OuterResult R = fgcr_outer(*S, S->ob.as<double2>(), S->ox.as<double2>(), nrhs, tol, max_iter, st);
+  to_canonical<double>(*S, 0, S->ox.as<double2>(), (double2*)dev_psi, nrhs, st);
+  HIPC(hipStreamSynchronize(st));
+  const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  bool all = true;
+  for (int i = 0; i < nrhs; ++i) {
+    const bool c = R.rel[i] <= tol;
+    all = all && c;
+    if (info) {
+      info[i].iters = R.iters;
+      info[i].converged = c;
+      info[i].true_rel_res = R.rel[i];
+      info[i].n_fine_D = S->nD - d0;
+      info[i].n_fine_Ddag = S->nDd - dd0;
+      info[i].n_coarse = S->nC - c0;
+      info[i].t_ms = ms;
+    }
+  }
+  if (!all) fail(AMG_ERR_NOCONV, "FGCR did not reach the tolerance");
+  AMG_CATCH
+}
+
+amg_status amg_get_nullvecs(const amg_solver* S, int level, void* dev_out, void* stream) {
+  AMG_TRY
+  check_ptr(S, "solver");
+  check_ptr(dev_out, "out");
+  if (level < 0 || level + 1 >= (int)S->lv.size()) fail(AMG_ERR_ARG, "bad level");
+  const Level& L = S->lv[level];
+  to_canonical<double>(*S, level, L.vecs.as<double2>(), (double2*)dev_out, L.nv, as_stream(stream));
+  AMG_CATCH
+}
+
+amg_status amg_get_coarse_op(const amg_solver* S, int level, void* dev_out, void* stream) {
+  AMG_TRY
+  check_ptr(S, "solver");
+  check_ptr(dev_out, "out");
+  if (level < 1 || level >= (int)S->lv.size()) fail(AMG_ERR_ARG, "bad level");
+  const Level& L = S->lv[level];
+  // internal blocks are column-major; the ABI exports row-major [t][t']
+  launch_block_transpose((double2*)dev_out, L.Y64.as<double2>(), L.V * L.ndir(), L.dof, as_stream(stream));
+  AMG_CATCH
+}
+
+amg_status amg_level_apply(const amg_solver* Sc, int level, int dagger, int prec, const void* dev_in, void* dev_out,
+                           int nrhs, void* stream) {
+  AMG_TRY
+  check_ptr(Sc, "solver");
+  check_ptr(dev_in, "in");
+  check_ptr(dev_out, "out");
+  if (dev_in == dev_out) fail(AMG_ERR_ARG, "in-place application is not supported");
+  amg_solver* S = const_cast<amg_solver*>(Sc);
+  if (level < 0 || level >= (int)S->lv.size()) fail(AMG_ERR_ARG, "bad level");
+  if (nrhs < 1 || nrhs > RHS_MAX) fail(AMG_ERR_ARG, "bad nrhs");
+  if (prec != AMG_F64 && prec != AMG_F32) fail(AMG_ERR_ARG, "bad precision");
+  if (prec == AMG_F32 && level > 0 && S->p.inner_prec != AMG_F32) fail(AMG_ERR_STATE, "no FP32 coarse operator");
+  hipStream_t st = as_stream(stream);
+  ensure_work(*S, nrhs);
+  Level& L = S->lv[level];
+  if (prec == AMG_F64) {
+    double2* a = S->otmp.as<double2>();
+    double2* c = L.w64[W_P].as<double2>();
+    launch_convert<double, double>(a, (const double2*)dev_in, L.V, L.dof, L.dof, L.lay64.W, nrhs, st);
+    op_apply<double>(*S, level, dagger, EPI_PLAIN, a, c, nullptr, nullptr, nrhs, S->sc.red(0), st);
+    launch_convert<double, double>((double2*)dev_out, c, L.V, L.dof, L.lay64.W, L.dof, nrhs, st);
+  } else {
+    float2* a = L.w32[W_B].as<float2>();
+    float2* c = L.w32[W_P].as<float2>();
+    if (!a) {
+      S->lv[level].w32[W_B].ensure((size_t)L.V * L.dof_max * nrhs * sizeof(float2));
+      S->lv[level].w32[W_P].ensure((size_t)L.V * L.dof_max * nrhs * sizeof(float2));
+      a = L.w32[W_B].as<float2>();
+      c = L.w32[W_P].as<float2>();
+    }
+    launch_convert<float, float>(a, (const float2*)dev_in, L.V, L.dof, L.dof, L.lay32.W, nrhs, st);
+    op_apply<float>(*S, level, dagger, EPI_PLAIN, a, c, nullptr, nullptr, nrhs, S->sc.red(0), st);
+    launch_convert<float, float>((float2*)dev_out, c, L.V, L.dof, L.lay32.W, L.dof, nrhs, st);
+  }
+  AMG_CATCH
+}
+
+amg_status amg_transfer(const amg_solver* Sc, int level, int dir, const void* dev_in, void* dev_out, int nrhs,
+                        void* stream) {
+  AMG_TRY
+  check_ptr(Sc, "solver");
+  check_ptr(dev_in, "in");
+  check_ptr(dev_out, "out");
+  amg_solver* S = const_cast<amg_solver*>(Sc);
+  if (level < 0 || level + 1 >= (int)S->lv.size()) fail(AMG_ERR_ARG, "bad level");
+  if (nrhs < 1 || nrhs > RHS_MAX) fail(AMG_ERR_ARG, "bad nrhs");
+  hipStream_t st = as_stream(stream);
+  ensure_work(*S, nrhs);
+  Level& F = S->lv[level];
+  const TransferGeom tg = tgeom(*S, level, AMG_F64);
+  double2* a = S->otmp.as<double2>();
+  if (level > 0) a = F.w64[W_P].as<double2>();
+  if (dir == 0) {
+    launch_convert<double, double>(a, (const double2*)dev_in, F.V, F.dof, F.dof, F.lay64.W, nrhs, st);
+    launch_restrict<double>((double2*)dev_out, a, F.P64.p, P_F64, tg, nrhs, nullptr, st);
+  } else {
+    launch_prolong<double>(a, (const double2*)dev_in, F.P64.p, P_F64, tg, nrhs, 0, nullptr, st);
+    launch_convert<double, double>((double2*)dev_out, a, F.V, F.dof, F.lay64.W, F.dof, nrhs, st);
+  }
+  AMG_CATCH
+}
+
+amg_status amg_vcycle(amg_solver* S, const void* dev_b, void* dev_x, int nrhs, void* stream) {
+  AMG_TRY
+  check_ptr(S, "solver");
+  check_ptr(dev_b, "b");
+  check_ptr(dev_x, "x");
+  if (nrhs < 1 || nrhs > RHS_MAX) fail(AMG_ERR_ARG, "bad nrhs");
+  hipStream_t st = as_stream(stream);
+  ensure_work(*S, nrhs);
+  to_internal<double>(*S, 0, (const double2*)dev_b, S->ob.as<double2>(), nrhs, st);
+  precondition(*S, S->ob.as<double2>(), S->ox.as<double2>(), nrhs, st);
+  to_canonical<double>(*S, 0, S->ox.as<double2>(), (double2*)dev_x, nrhs, st);
+  AMG_CATCH
+}
+
+amg_status amg_mr(amg_solver* S, int level, int nu, const void* dev_b, void* dev_x, int nrhs, void* stream) {
+  AMG_TRY
+  check_ptr(S, "solver");
+  check_ptr(dev_b, "b");
+  check_ptr(dev_x, "x");
+  if (level < 0 || level >= (int)S->lv.size()) fail(AMG_ERR_ARG, "bad level");
+  if (nrhs < 1 || nrhs > RHS_MAX || nu < 0) fail(AMG_ERR_ARG, "bad nrhs / nu");
+  hipStream_t st = as_stream(stream);
+  ensure_work(*S, nrhs);
+  Level& L = S->lv[level];
+  double2* b = level == 0 ? S->ob.as<double2>() : L.w64[W_B].as<double2>();
+  double2* x = level == 0 ? S->ox.as<double2>() : L.w64[W_X].as<double2>();
+  launch_convert<double, double>(b, (const double2*)dev_b, L.V, L.dof, L.dof, L.lay64.W, nrhs, st);
+  mr_smooth<double>(*S, level, b, x, L.w64[W_R].as<double2>(), L.w64[W_P].as<double2>(), nu, true, true, nrhs, st);
+  launch_convert<double, double>((double2*)dev_x, x, L.V, L.dof, L.lay64.W, L.dof, nrhs, st);
+  AMG_CATCH
+}
+
+amg_status amg_level_info(const amg_solver* S, int level, int* dims4, int* dof, long long* V) {
+  AMG_TRY
+  check_ptr(S, "solver");
+  if (level < 0 || level >= (int)S->lv.size()) fail(AMG_ERR_ARG, "bad level");
+  const Level& L = S->lv[level];
+  if (dims4)
+    for (int mu = 0; mu < 4; ++mu) dims4[mu] = L.dims[mu];
+  if (dof) *dof = L.dof;
+  if (V) *V = L.V;
+  AMG_CATCH
+}
+
+}  // extern "C"

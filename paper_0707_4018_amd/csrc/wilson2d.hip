@@ -1,0 +1,200 @@
+// Two-dimensional U(1) Wilson-Dirac stencil on gfx950.
+//
+//   (D psi)(x) = (2 + m) psi(x)
+//     - 1/2 sum_mu [ (1 - gamma_mu) U_mu(x) psi(x+mu) + (1 + gamma_mu) U_mu(x-mu)^* psi(x-mu) ]
+//
+// (operator defined after Eq. (1) of the paper, diagonal read as d + m;
+// gamma_1 = sigma_1, gamma_2 = sigma_2).  D^dagger swaps the two projectors.
+// Each projector 1 + s gamma_mu (s = +-1) has rank one, so a hop needs one
+// complex product:  mu = 1: h = f0 + s f1, result (h, s h);
+//                   mu = 2: h = f0 - i s f1, result (h, i s h).
+//
+// Internal layouts (one thread per site, grid-stride, 16-byte accesses):
+//   FP64 spinor: two planes [spin][site] of double2;  links [mu][site] double2
+//   FP32 spinor: [site] float4 = (s0, s1);            links [site] float4 = (U_1, U_2)
+// These are Layout{V, 2, W} with W = 1 (FP64) and W = 2 (FP32).
+#include "common.h"
+#include "kernels.h"
+
+namespace amg {
+namespace {
+
+template <typename T> struct Sp2 { cplx<T> a, b; };
+
+__device__ __forceinline__ Sp2<double> ld2(const double2* __restrict__ p, long s, long V) {
+  return {p[s], p[V + s]};
+}
+__device__ __forceinline__ Sp2<float> ld2(const float2* __restrict__ p, long s, long) {
+  const float4 q = reinterpret_cast<const float4*>(p)[s];
+  return {make_float2(q.x, q.y), make_float2(q.z, q.w)};
+}
+__device__ __forceinline__ void st2(double2* __restrict__ p, long s, long V, Sp2<double> v) {
+  p[s] = v.a; p[V + s] = v.b;
+}
+__device__ __forceinline__ void st2(float2* __restrict__ p, long s, long, Sp2<float> v) {
+  reinterpret_cast<float4*>(p)[s] = make_float4(v.a.x, v.a.y, v.b.x, v.b.y);
+}
+// single link U_mu(site)
+__device__ __forceinline__ double2 ldU(const double2* __restrict__ U, long s, long V, int mu) {
+  return U[mu * V + s];
+}
+__device__ __forceinline__ float2 ldU(const float2* __restrict__ U, long s, long, int mu) {
+  return U[2 * s + mu];
+}
+
+// The four hops of site s, accumulated as o -= 1/2 (projected, transported neighbour).
+// SPLIT: route each hop to out0 (inside the block) or to its own output (crossing a face).
+template <typename T, int DAG>
+struct Hops {
+  long V; int L1, L2;
+  __device__ __forceinline__ void neighbours(long s, int& x1, int& x2, long& sp1, long& sm1,
+                                             long& sp2, long& sm2) const {
+    x1 = (int)(s % L1); x2 = (int)(s / L1);
+    sp1 = (x1 == L1 - 1) ? s - (L1 - 1) : s + 1;
+    sm1 = (x1 == 0) ? s + (L1 - 1) : s - 1;
+    sp2 = (x2 == L2 - 1) ? s - (long)(L2 - 1) * L1 : s + L1;
+    sm2 = (x2 == 0) ? s + (long)(L2 - 1) * L1 : s - L1;
+  }
+  // forward hop in mu = 0 with projector 1 + sg gamma_1 on link u, neighbour f
+  static __device__ __forceinline__ Sp2<T> hop1(cplx<T> u, Sp2<T> f, T sg, bool conj_u) {
+    const cplx<T> h = mk<T>(f.a.x + sg * f.b.x, f.a.y + sg * f.b.y);
+    const cplx<T> uh = conj_u ? cjmul<T>(u, h) : cmul<T>(u, h);
+    return {uh, cscale<T>(sg, uh)};
+  }
+  static __device__ __forceinline__ Sp2<T> hop2(cplx<T> u, Sp2<T> f, T sg, bool conj_u) {
+    // h = f0 - i sg f1
+    const cplx<T> h = mk<T>(f.a.x + sg * f.b.y, f.a.y - sg * f.b.x);
+    const cplx<T> uh = conj_u ? cjmul<T>(u, h) : cmul<T>(u, h);
+    return {uh, cscale<T>(sg, ctimesi<T>(uh))};
+  }
+};
+
+template <typename T>
+__device__ __forceinline__ void sub_half(Sp2<T>& o, const Sp2<T>& h) {
+  o.a.x -= (T)0.5 * h.a.x; o.a.y -= (T)0.5 * h.a.y;
+  o.b.x -= (T)0.5 * h.b.x; o.b.y -= (T)0.5 * h.b.y;
+}
+
+template <typename T, int DAG, int EPI>
+__global__ __launch_bounds__(256) void wilson2d_kernel(
+    cplx<T>* __restrict__ out, const cplx<T>* __restrict__ in, const cplx<T>* __restrict__ bvec,
+    cplx<T>* __restrict__ copy_out, const cplx<T>* __restrict__ U, T diag, int L1, int L2,
+    RedArgs red) {
+  const int rhs = blockIdx.y;
+  if (skip_rhs(red.flags, rhs)) return;
+  const long V = (long)L1 * L2;
+  const long ro = (long)rhs * 2 * V;
+  const cplx<T>* __restrict__ pin = in + ro;
+  Hops<T, DAG> H{V, L1, L2};
+  const T sf = DAG ? (T)1 : (T)-1;  // forward projector 1 + sf gamma
+  const T sb = -sf;
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (long s = (long)blockIdx.x * blockDim.x + threadIdx.x; s < V; s += (long)gridDim.x * blockDim.x) {
+    int x1, x2; long sp1, sm1, sp2, sm2;
+    H.neighbours(s, x1, x2, sp1, sm1, sp2, sm2);
+    const Sp2<T> c = ld2(pin, s, V);
+    Sp2<T> o{cscale<T>(diag, c.a), cscale<T>(diag, c.b)};
+    sub_half<T>(o, Hops<T, DAG>::hop1(ldU(U, s, V, 0), ld2(pin, sp1, V), sf, false));
+    sub_half<T>(o, Hops<T, DAG>::hop1(ldU(U, sm1, V, 0), ld2(pin, sm1, V), sb, true));
+    sub_half<T>(o, Hops<T, DAG>::hop2(ldU(U, s, V, 1), ld2(pin, sp2, V), sf, false));
+    sub_half<T>(o, Hops<T, DAG>::hop2(ldU(U, sm2, V, 1), ld2(pin, sm2, V), sb, true));
+    if (EPI == EPI_RESID) {
+      const Sp2<T> bb = ld2(bvec + ro, s, V);
+      o = {csub<T>(bb.a, o.a), csub<T>(bb.b, o.b)};
+    }
+    st2(out + ro, s, V, o);
+    if (copy_out) st2(copy_out + ro, s, V, c);
+    if (EPI == EPI_MRDOT) {
+      acc[0] += (double)o.a.x * c.a.x + (double)o.a.y * c.a.y + (double)o.b.x * c.b.x + (double)o.b.y * c.b.y;
+      acc[1] += (double)o.a.x * c.a.y - (double)o.a.y * c.a.x + (double)o.b.x * c.b.y - (double)o.b.y * c.b.x;
+      acc[2] += (double)o.a.x * o.a.x + (double)o.a.y * o.a.y + (double)o.b.x * o.b.x + (double)o.b.y * o.b.y;
+    } else if (EPI == EPI_NORM) {
+      acc[0] += (double)o.a.x * o.a.x + (double)o.a.y * o.a.y + (double)o.b.x * o.b.x + (double)o.b.y * o.b.y;
+    }
+  }
+  if (EPI == EPI_MRDOT) {
+    double tot[3];
+    if (grid_reduce<3>(acc, red.part, red.ticket, rhs, tot) && threadIdx.x == 0) finalize_mr(tot, red, rhs);
+  } else if (EPI == EPI_NORM) {
+    double a1[1] = {acc[0]}, tot[1];
+    if (grid_reduce<1>(a1, red.part, red.ticket, rhs, tot) && threadIdx.x == 0) red.scal[red.slot + rhs] = tot[0];
+  }
+}
+
+// Split apply for the Galerkin product: out[k] (k = 0..4) for every input
+// field; out[0] = diagonal + hops that stay inside the block, out[1 + dir] =
+// the hop in direction dir (0:+1, 1:-1, 2:+2, 3:-2) when it leaves the block
+// through its face.  FP64, layout W = 1.
+__global__ __launch_bounds__(256) void wilson2d_split_kernel(
+    double2* __restrict__ out, const double2* __restrict__ in, const double2* __restrict__ U,
+    double diag, int L1, int L2, int b1, int b2, int nrhs) {
+  const int rhs = blockIdx.y;
+  const long V = (long)L1 * L2;
+  const long ro = (long)rhs * 2 * V;
+  const long ostride = (long)nrhs * 2 * V;  // between output kinds
+  const double2* __restrict__ pin = in + ro;
+  Hops<double, 0> H{V, L1, L2};
+  for (long s = (long)blockIdx.x * blockDim.x + threadIdx.x; s < V; s += (long)gridDim.x * blockDim.x) {
+    int x1, x2; long sp1, sm1, sp2, sm2;
+    H.neighbours(s, x1, x2, sp1, sm1, sp2, sm2);
+    const Sp2<double> c = ld2(pin, s, V);
+    Sp2<double> o0{cscale<double>(diag, c.a), cscale<double>(diag, c.b)};
+    Sp2<double> hop[4];
+    Sp2<double> z{mk<double>(0, 0), mk<double>(0, 0)};
+    for (int k = 0; k < 4; ++k) hop[k] = z;
+    Sp2<double> t;
+    t = z; sub_half<double>(t, Hops<double, 0>::hop1(ldU(U, s, V, 0), ld2(pin, sp1, V), -1.0, false));
+    if (x1 % b1 == b1 - 1) hop[0] = t; else { o0.a = cadd<double>(o0.a, t.a); o0.b = cadd<double>(o0.b, t.b); }
+    t = z; sub_half<double>(t, Hops<double, 0>::hop1(ldU(U, sm1, V, 0), ld2(pin, sm1, V), 1.0, true));
+    if (x1 % b1 == 0) hop[1] = t; else { o0.a = cadd<double>(o0.a, t.a); o0.b = cadd<double>(o0.b, t.b); }
+    t = z; sub_half<double>(t, Hops<double, 0>::hop2(ldU(U, s, V, 1), ld2(pin, sp2, V), -1.0, false));
+    if (x2 % b2 == b2 - 1) hop[2] = t; else { o0.a = cadd<double>(o0.a, t.a); o0.b = cadd<double>(o0.b, t.b); }
+    t = z; sub_half<double>(t, Hops<double, 0>::hop2(ldU(U, sm2, V, 1), ld2(pin, sm2, V), 1.0, true));
+    if (x2 % b2 == 0) hop[3] = t; else { o0.a = cadd<double>(o0.a, t.a); o0.b = cadd<double>(o0.b, t.b); }
+    st2(out + ro, s, V, o0);
+    for (int k = 0; k < 4; ++k) st2(out + (k + 1) * ostride + ro, s, V, hop[k]);
+  }
+}
+
+}  // namespace
+
+template <typename T>
+void launch_wilson2d(const WilsonArgs<T>& a, int dagger, int epi, hipStream_t st) {
+  const long V = (long)a.L1 * a.L2;
+  long nb = (V + 255) / 256;
+  if (epi == EPI_MRDOT || epi == EPI_NORM) nb = nb < RED_MAX_BLOCKS ? nb : RED_MAX_BLOCKS;
+  dim3 grid((unsigned)nb, (unsigned)a.nrhs);
+  const T diag = (T)(2.0 + a.mass);
+#define AMG_W2(DAG, EPI)                                                                         \
+  hipLaunchKernelGGL((wilson2d_kernel<T, DAG, EPI>), grid, dim3(256), 0, st, a.out, a.in, a.b, \
+                     a.copy_out, a.U, diag, a.L1, a.L2, a.red)
+  if (dagger) {
+    switch (epi) {
+      case EPI_PLAIN: AMG_W2(1, EPI_PLAIN); break;
+      case EPI_MRDOT: AMG_W2(1, EPI_MRDOT); break;
+      case EPI_RESID: AMG_W2(1, EPI_RESID); break;
+      default: AMG_W2(1, EPI_NORM); break;
+    }
+  } else {
+    switch (epi) {
+      case EPI_PLAIN: AMG_W2(0, EPI_PLAIN); break;
+      case EPI_MRDOT: AMG_W2(0, EPI_MRDOT); break;
+      case EPI_RESID: AMG_W2(0, EPI_RESID); break;
+      default: AMG_W2(0, EPI_NORM); break;
+    }
+  }
+#undef AMG_W2
+}
+
+template void launch_wilson2d<double>(const WilsonArgs<double>&, int, int, hipStream_t);
+template void launch_wilson2d<float>(const WilsonArgs<float>&, int, int, hipStream_t);
+
+void launch_wilson2d_split(double2* out, const double2* in, const double2* U, double mass, int L1,
+                           int L2, int b1, int b2, int nrhs, hipStream_t st) {
+  const long V = (long)L1 * L2;
+  dim3 grid((unsigned)((V + 255) / 256), (unsigned)nrhs);
+  hipLaunchKernelGGL(wilson2d_split_kernel, grid, dim3(256), 0, st, out, in, U, 2.0 + mass, L1, L2,
+                     b1, b2, nrhs);
+}
+
+}  // namespace amg

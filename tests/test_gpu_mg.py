@@ -1,0 +1,212 @@
+"""Parity of the multigrid pieces (HIP, through the C ABI) with the oracle.
+
+Same seeded inputs on both sides (the near-null vectors or the adaptive
+setup's random starting vectors are passed to both).  FP64 pieces must agree
+to ~1e-12 (single operations) or ~1e-10 (a V-cycle, which chains dozens of
+reductions); every solve must reach the true FP64 relative residual 1e-10,
+recomputed here with the oracle's D.
+"""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import synth
+from oracle import dirac, mg
+from gpu_util import dev, host, max_rel_err, rel_err, u1_config, vectors, su3_config
+
+pytestmark = pytest.mark.gpu
+
+
+def _params(blocks, nvec, **kw):
+    import paper_0707_4018_amd as amg
+    o = mg.MGParams(blocks=list(blocks), nvec=list(nvec))
+    g = amg.MGParams(blocks=list(blocks), nvec=list(nvec))
+    for k, v in kw.items():
+        setattr(o, k, v)
+        setattr(g, k, v)
+    return o, g
+
+
+def _given(L1, L2, blocks, nvec, m=0.05, seed=0, **kw):
+    """Oracle hierarchy and GPU solver built from the same random vectors."""
+    import paper_0707_4018_amd as amg
+    U = u1_config(L1, L2, seed=seed)
+    A = mg.wilson_stencil(U, m)
+    po, pg = _params(blocks, nvec, **kw)
+    vecs = []
+    V, dof, dims = A.V, 2, (L1, L2)
+    for l, (b, nv) in enumerate(zip(blocks, nvec)):
+        vecs.append(vectors(nv, V, dof, seed * 10 + l))
+        dims = tuple(d // bb for d, bb in zip(dims, b))
+        V, dof = int(np.prod(dims)), 2 * nv
+    H = mg.build_hierarchy(A, vecs, po)
+    g = amg.Gauge(dev(U), m)
+    S = amg.Solver(g, pg, nullvecs=[dev(v) for v in vecs])
+    return U, A, H, g, S
+
+
+@pytest.mark.parametrize("L1,L2,block,nv", [(32, 32, (4, 4), 8), (8, 8, (4, 4), 4), (4, 4, (4, 4), 3),
+                                           (16, 8, (4, 2), 2), (12, 8, (2, 4), 5)])
+def test_coarse_operator_matches_oracle(L1, L2, block, nv):
+    print(f"galerkin {L1}x{L2} block {block} nv {nv}", flush=True)
+    U, A, H, g, S = _given(L1, L2, [block], [nv])
+    Y = host(S.coarse_op(1))
+    Ac = H.ops[1]
+    assert max_rel_err(Y[:, 0], Ac.diag) < 1e-12
+    for d in range(4):
+        assert max_rel_err(Y[:, 1 + d], Ac.hop[d]) < 1e-12
+
+
+def test_three_level_operator_and_transfers():
+    print("three-level 32x32 (4,4)+(2,2)", flush=True)
+    U, A, H, g, S = _given(32, 32, [(4, 4), (2, 2)], [4, 3])
+    Y2 = host(S.coarse_op(2))
+    assert max_rel_err(Y2[:, 0], H.ops[2].diag) < 1e-11
+    for d in range(4):
+        assert max_rel_err(Y2[:, 1 + d], H.ops[2].hop[d]) < 1e-11
+    for lvl in range(2):
+        P = H.Ps[lvl]
+        r = synth.gaussian_field((1, H.ops[lvl].V, H.ops[lvl].dof), synth.rng_for(5, lvl))
+        e = synth.gaussian_field((1, P.Vc, P.nc), synth.rng_for(6, lvl))
+        assert max_rel_err(host(S.restrict(lvl, dev(r)))[0], P.restrict(r[0])) < 1e-12
+        assert max_rel_err(host(S.prolong(lvl, dev(e)))[0], P.prolong(e[0])) < 1e-12
+
+
+def test_coarse_apply_and_mr_match_oracle():
+    import paper_0707_4018_amd as amg
+    import torch
+    U, A, H, g, S = _given(32, 16, [(4, 4)], [8])
+    Ac = H.ops[1]
+    e = synth.gaussian_field((1, Ac.V, Ac.dof), synth.rng_for(7))
+    assert max_rel_err(host(S.level_apply(1, dev(e)))[0], Ac.apply(e[0])) < 1e-12
+    assert max_rel_err(host(S.level_apply(1, dev(e), dagger=True))[0], Ac.apply_dagger(e[0])) < 1e-12
+    b = synth.gaussian_field((1, A.V, 2, 1), synth.rng_for(8))
+    x = host(S.mr(0, 3, dev(b)))
+    xo = mg.mr(A, b[0].reshape(A.V, 2), 3, 0.8)[0]
+    assert max_rel_err(x.reshape(-1), xo.reshape(-1)) < 1e-12
+    xc = host(S.mr(1, 2, dev(e)))
+    xco = mg.mr(Ac, e[0], 2, 0.8)[0]
+    assert max_rel_err(xc.reshape(-1), xco.reshape(-1)) < 1e-12
+    # FP32 coarse operator (rounded from the FP64 Galerkin product)
+    _, pg = _params([(4, 4)], [8], inner_prec=amg.F32)
+    S32 = amg.Solver(g, pg, nullvecs=S._keep)
+    out = host(S32.level_apply(1, dev(e, torch.complex64), prec=amg.F32))[0]
+    assert rel_err(out, Ac.apply(e[0])) < 1e-5
+
+
+@pytest.mark.parametrize("blocks,nvec", [([(4, 4)], [6]), ([(4, 4), (2, 2)], [4, 4])])
+def test_vcycle_matches_oracle(blocks, nvec):
+    print(f"vcycle {blocks} {nvec}", flush=True)
+    U, A, H, g, S = _given(32, 32, blocks, nvec, m=0.02, coarse_tol=0.0, coarse_maxiter=12, coarse_restart=5)
+    b = synth.gaussian_field((1, A.V, 2, 1), synth.rng_for(9))
+    x = host(S.vcycle(dev(b)))[0].reshape(A.V, 2)
+    xo = mg.vcycle(H, 0, b[0].reshape(A.V, 2))
+    assert rel_err(x, xo) < 1e-10
+
+
+def _mcrit(U):
+    ev = np.linalg.eigvals(dirac.dense_D(U, 0.0))
+    return -ev.real.min()
+
+
+def test_adaptive_setup_and_solve_fp64():
+    import paper_0707_4018_amd as amg
+    L = 32
+    U = u1_config(L, L, beta=6.0, sweeps=100, seed=3)
+    m = _mcrit(U) + 0.01
+    A = mg.wilson_stencil(U, m)
+    po, pg = _params([(4, 4)], [8], coarse_tol=0.05, coarse_maxiter=200, coarse_restart=16)
+    init = [vectors(8, A.V, 2, 33)]
+    Ho, vo = mg.adaptive_setup(A, po, init)
+    g = amg.Gauge(dev(U), m)
+    S = amg.Solver(g, pg, init=[dev(v) for v in init])
+    v = host(S.nullvecs(0))
+    assert rel_err(v, vo[0]) < 1e-6
+    b = synth.gaussian_field((1, A.V, 2, 1), synth.rng_for(0))
+    psi, info = S.solve(dev(b), tol=1e-10)
+    psi = host(psi)[0].reshape(A.V, 2)
+    res = mg.norm(b[0].reshape(A.V, 2) - A.apply(psi)) / mg.norm(b)
+    assert info[0].converged and res <= 1e-10 and info[0].true_rel_res <= 1e-10
+    xo, io = mg.mg_solve(Ho, b[0].reshape(A.V, 2), 1e-10)
+    assert abs(info[0].iters - io.iters) <= 2, (info[0].iters, io.iters)
+    xd = spla.spsolve(A.to_sparse().tocsc(), b[0].ravel())
+    assert rel_err(psi.ravel(), xd) < 1e-6
+    # CGNR comparator on the same system
+    psi_c, ic = g.cgnr(dev(b), tol=1e-10)
+    res_c = mg.norm(b[0].reshape(A.V, 2) - A.apply(host(psi_c)[0].reshape(A.V, 2))) / mg.norm(b)
+    assert ic.converged and res_c <= 1e-10
+    assert ic.iters > 5 * info[0].iters
+
+
+def test_mixed_precision_solve():
+    import paper_0707_4018_amd as amg
+    L = 32
+    U = u1_config(L, L, beta=6.0, sweeps=100, seed=4)
+    m = _mcrit(U) + 0.003
+    A = mg.wilson_stencil(U, m)
+    init = [vectors(8, A.V, 2, 44)]
+    g = amg.Gauge(dev(U), m)
+    b = synth.gaussian_field((1, A.V, 2, 1), synth.rng_for(0))
+    xd = spla.spsolve(A.to_sparse().tocsc(), b[0].ravel())
+    for bf16 in (False, True):
+        _, pg = _params([(4, 4)], [8], inner_prec=amg.F32, p_bf16=bf16, coarse_tol=0.05, coarse_maxiter=200)
+        S = amg.Solver(g, pg, init=[dev(v) for v in init])
+        psi, info = S.solve(dev(b), tol=1e-10)
+        psi = host(psi)[0].reshape(A.V, 2)
+        res = mg.norm(b[0].reshape(A.V, 2) - A.apply(psi)) / mg.norm(b)
+        assert info[0].converged and res <= 1e-10
+        assert rel_err(psi.ravel(), xd) < 1e-6
+
+
+def test_set_mass_equals_rebuild():
+    import paper_0707_4018_amd as amg
+    U, A, H, g, S = _given(16, 16, [(4, 4), (2, 2)], [4, 2], m=0.02)
+    S.set_mass(0.15)
+    g2 = amg.Gauge(dev(U), 0.15)
+    S2 = amg.Solver(g2, S.params, nullvecs=S._keep)
+    for lvl in (1, 2):
+        assert max_rel_err(host(S.coarse_op(lvl)), host(S2.coarse_op(lvl))) < 1e-12
+
+
+def test_multi_rhs_solve():
+    U, A, H, g, S = _given(16, 16, [(4, 4)], [4], m=0.05, coarse_tol=1e-3, coarse_maxiter=100)
+    b = synth.gaussian_field((3, A.V, 2, 1), synth.rng_for(10))
+    psi, infos = S.solve(dev(b), tol=1e-10)
+    psi = host(psi)
+    for k in range(3):
+        res = mg.norm(b[k].reshape(A.V, 2) - A.apply(psi[k].reshape(A.V, 2))) / mg.norm(b[k])
+        assert infos[k].converged and res <= 1e-10
+        p1, _ = S.solve(dev(b[k:k + 1]), tol=1e-10)
+        assert rel_err(host(p1)[0], psi[k]) < 1e-8
+
+
+def test_rank_error_on_duplicate_vectors():
+    import paper_0707_4018_amd as amg
+    U = u1_config(8, 8)
+    g = amg.Gauge(dev(U), 0.1)
+    v = vectors(1, 64, 2, 1)
+    _, pg = _params([(4, 4)], [2])
+    with pytest.raises(amg.AMGError) as e:
+        amg.Solver(g, pg, nullvecs=[dev(np.concatenate([v, v]))])
+    assert e.value.status == 6
+
+
+def test_four_dimensional_hierarchy():
+    import paper_0707_4018_amd as amg
+    dims = (4, 4, 4, 4)
+    U = su3_config(dims, seed=2)
+    m = 0.3
+    A = mg.wilson_stencil(U, m)
+    po, pg = _params([(2, 2, 2, 2)], [3], coarse_tol=1e-2, coarse_maxiter=100)
+    vecs = [vectors(3, A.V, 12, 5)]
+    H = mg.build_hierarchy(A, vecs, po)
+    g = amg.Gauge(dev(U), m)
+    S = amg.Solver(g, pg, nullvecs=[dev(v) for v in vecs])
+    Y = host(S.coarse_op(1))
+    assert max_rel_err(Y[:, 0], H.ops[1].diag) < 1e-12
+    for d in range(8):
+        assert max_rel_err(Y[:, 1 + d], H.ops[1].hop[d]) < 1e-12
+    b = synth.gaussian_field((1, A.V, 4, 3), synth.rng_for(11))
+    psi, info = S.solve(dev(b), tol=1e-10)
+    res = mg.norm(b[0].reshape(A.V, 12) - A.apply(host(psi)[0].reshape(A.V, 12))) / mg.norm(b)
+    assert info[0].converged and res <= 1e-10

@@ -1,0 +1,83 @@
+"""Parity of the fine Wilson-Dirac stencil (HIP, through the C ABI) with the oracle.
+
+Tolerances: 1e-12 relative in FP64, 1e-5 relative in FP32 (the inputs are
+rounded to FP32 first, so the FP32 bound covers both input and arithmetic
+rounding of a 9-term complex sum).
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import dirac
+from gpu_util import dev, host, max_rel_err, rel_err, su3_config, u1_config
+
+pytestmark = pytest.mark.gpu
+
+SHAPES_2D = [(32, 32), (8, 6), (34, 18), (256, 256), (4, 4), (130, 2)]
+
+
+@pytest.mark.parametrize("L1,L2", SHAPES_2D)
+@pytest.mark.parametrize("dagger", [0, 1])
+def test_wilson2d_fp64(L1, L2, dagger):
+    import paper_0707_4018_amd as amg
+    print(f"wilson2d fp64 {L1}x{L2} dagger={dagger}", flush=True)
+    U = u1_config(L1, L2)
+    m = -0.07
+    g = amg.Gauge(dev(U), m)
+    nrhs = 3
+    psi = synth.gaussian_field((nrhs, L2 * L1, 2, 1), synth.rng_for(1, L1, L2))
+    out = host(g.apply(dev(psi), dagger=bool(dagger)))
+    for k in range(nrhs):
+        ref = dirac.apply_D(U, psi[k].reshape(L2, L1, 2, 1), m, dagger=bool(dagger)).reshape(-1, 2, 1)
+        assert max_rel_err(out[k], ref) < 1e-12
+
+
+@pytest.mark.parametrize("L1,L2", SHAPES_2D)
+def test_wilson2d_fp32(L1, L2):
+    import paper_0707_4018_amd as amg
+    import torch
+    print(f"wilson2d fp32 {L1}x{L2}", flush=True)
+    U = u1_config(L1, L2, seed=1)
+    g = amg.Gauge(dev(U), 0.1)
+    psi = synth.gaussian_field((1, L2 * L1, 2, 1), synth.rng_for(2, L1, L2))
+    for dagger in (False, True):
+        out = host(g.apply(dev(psi, torch.complex64), dagger=dagger, prec=amg.F32))
+        ref = dirac.apply_D(U, psi[0].reshape(L2, L1, 2, 1), 0.1, dagger=dagger).reshape(1, -1, 2, 1)
+        assert rel_err(out, ref) < 1e-5
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 8), (6, 4, 2, 4), (8, 8, 8, 8)])
+def test_wilson4d(dims):
+    import paper_0707_4018_amd as amg
+    import torch
+    print(f"wilson4d {dims}", flush=True)
+    U = su3_config(dims)
+    V = int(np.prod(dims))
+    m = 0.05
+    g = amg.Gauge(dev(U), m)
+    psi = synth.gaussian_field((2, V, 4, 3), synth.rng_for(3, *dims))
+    lat = tuple(reversed(dims))
+    for dagger in (False, True):
+        out = host(g.apply(dev(psi), dagger=dagger))
+        out32 = host(g.apply(dev(psi, torch.complex64), dagger=dagger, prec=amg.F32))
+        for k in range(2):
+            ref = dirac.apply_D(U, psi[k].reshape(lat + (4, 3)), m, dagger=dagger).reshape(V, 4, 3)
+            assert max_rel_err(out[k], ref) < 1e-12
+            assert rel_err(out32[k], ref) < 1e-5
+
+
+def test_apply_rejects_bad_arguments():
+    import paper_0707_4018_amd as amg
+    import torch
+    from paper_0707_4018_amd import binding as b
+    U = u1_config(8, 8)
+    g = amg.Gauge(dev(U), 0.0)
+    x = torch.zeros((1, 64, 2, 1), dtype=torch.complex128, device="cuda")
+    lib = b.load_library()
+    # in-place application and a bad precision are rejected before any launch
+    assert lib.amg_apply(g.handle, 0, 0, b._ptr(x), b._ptr(x), 1, b._stream()) == 1
+    y = torch.empty_like(x)
+    assert lib.amg_apply(g.handle, 0, 7, b._ptr(x), b._ptr(y), 1, b._stream()) == 1
+    assert lib.amg_apply(g.handle, 0, 0, b._ptr(x), b._ptr(y), 0, b._stream()) == 1
+    with pytest.raises(ValueError):
+        g.apply(torch.zeros((1, 64, 2, 1), dtype=torch.complex64, device="cuda"))
