@@ -1,0 +1,364 @@
+#!/usr/bin/env python3
+"""Benchmark of the adaptive multigrid solve of D(U) psi = chi on MI355X.
+
+Workload (the mixed-precision Schwinger-model configuration): 2d U(1)
+Wilson-Dirac operator on a 256 x 256 periodic lattice, heat-bath ensembles at
+beta in {3, 6, 10} (500 sweeps from a cold start), four masses per ensemble
+at mass gaps m_hat in {1e-1, 1e-2, 3e-3, 1e-3} above the critical mass, a
+Gaussian source.  Solver: 3-level adaptive MG (4x4 then 2x2 blocks, 8
+near-null vectors chirally split into 16 coarse dof per site), FP32 smoother /
+restriction / coarse levels with BF16 prolongator storage, FP64 flexible GCR
+outer iteration to a true relative residual of 1e-10.
+
+One step = for each beta: adaptive setup at the lightest mass, then the four
+solves reusing that setup (the paper reuses the lightest-mass setup for the
+heavier masses).  value = solves per second over the whole step (setup
+included).  The same step with FP64 V-cycles is timed for comparison, the
+fine stencil is timed alone on HBM-sized lattices, and the CPU oracle is
+timed on a bounded sample.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import synth  # noqa: E402
+
+L = 256
+BETAS = [3.0, 6.0, 10.0]
+TOL = 1e-10
+HBM_PEAK_GBS = 8000.0
+WORKLOADS = json.load(open(os.path.join(ROOT, "synth", "workloads.json")))
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload(beta):
+    return WORKLOADS[f"schwinger_256_b{int(beta)}"]
+
+
+def gen_config(beta):
+    """Heat-bath field of one ensemble (runs in a worker process, no GPU)."""
+    W = workload(beta)
+    th = synth.u1_heatbath(W["L1"], W["L2"], beta, W["sweeps"], synth.rng_for(*W["seed"]))
+    plaq = synth.u1_mean_plaquette(th)
+    if abs(plaq - W["plaquette"]) > 1e-12:
+        raise RuntimeError(f"regenerated field differs from the workload table (beta={beta})")
+    return beta, th
+
+
+def init_vectors(nvec=8):
+    v0 = np.stack([synth.gaussian_field((L * L, 2), synth.rng_for(2, 7, 0, k)) for k in range(nvec)])
+    Lc = L // 4
+    v1 = np.stack([synth.gaussian_field((Lc * Lc, 2 * nvec), synth.rng_for(2, 7, 1, k)) for k in range(nvec)])
+    return [v0, v1]
+
+
+def source():
+    return synth.gaussian_field((1, L * L, 2, 1), synth.rng_for(0))
+
+
+# solver parameters shared by the GPU run and the oracle sample
+PARAMS = dict(blocks=[(4, 4), (2, 2)], nvec=[8, 8], nu_pre=2, nu_post=2, omega=0.8,
+              coarse_tol=0.2, coarse_maxiter=100, coarse_restart=16, outer_restart=16,
+              kcycle_tol=0.1, kcycle_maxiter=8)
+
+
+def mg_params(amg, mixed: bool):
+    return amg.MGParams(**PARAMS, inner_prec=amg.F32 if mixed else amg.F64, p_bf16=mixed)
+
+
+class Job:
+    def __init__(self, amg, torch, fields):
+        self.amg, self.torch = amg, torch
+        self.gauges = {}
+        for beta, th in fields.items():
+            U = torch.from_numpy(np.exp(1j * th)[..., None, None].copy()).cuda()
+            self.gauges[beta] = amg.Gauge(U, workload(beta)["masses"][-1])
+        self.init = [torch.from_numpy(v).cuda() for v in init_vectors()]
+        self.chi = torch.from_numpy(source()).cuda()
+        self.results = []
+        self.solvers = {}
+        self.fields = fields
+
+    def step(self, mixed: bool, keep=False, profile=None):
+        """One pass of the whole job; returns (setup_ms, solve_ms, records)."""
+        amg = self.amg
+        setup_ms = solve_ms = 0.0
+        recs = []
+        prof = [0.0, 0]
+        for beta in BETAS:
+            W = workload(beta)
+            g = self.gauges[beta]
+            t0 = time.perf_counter()
+            S = amg.Solver(g, mg_params(amg, mixed), init=self.init, nu0=20, ncyc=2)
+            t1 = time.perf_counter()
+            setup_ms += 1e3 * (t1 - t0)
+            if profile is not None:
+                S.profile(*profile)
+            for gap, m in sorted(zip(W["mass_gaps"], W["masses"]), reverse=True):
+                S.set_mass(m)
+                t2 = time.perf_counter()
+                psi, info = S.solve(self.chi, tol=TOL, max_iter=500)
+                t3 = time.perf_counter()
+                solve_ms += 1e3 * (t3 - t2)
+                recs.append(dict(beta=beta, mass_gap=gap, mass=m, iters=info[0].iters,
+                                 true_rel_res=info[0].true_rel_res, n_fine_D=info[0].n_fine_D,
+                                 n_coarse=info[0].n_coarse, ms=1e3 * (t3 - t2)))
+                if keep:
+                    self.results.append((beta, m, psi.cpu().numpy()))
+            if profile is not None:
+                ms, n = S.profile_read()
+                prof[0] += ms
+                prof[1] += n
+                self.solvers[beta] = S
+        return setup_ms, solve_ms, recs, prof
+
+
+def stencil_bench(amg, torch, th, iters=40):
+    """Fine stencil alone on HBM-sized lattices: the beta=6 U(1) field tiled
+    periodically to 4096^2, and a 32^3 x 64 SU(3) field (4096 seeded Haar
+    matrices tiled over the links, valid SU(3) links; bandwidth does not
+    depend on their distribution).  Timed with HIP events on the stream."""
+    out = {}
+    stream = torch.cuda.current_stream()
+
+    def timed(g, prec, nrhs=1):
+        g.apply_internal(False, prec, nrhs, 3)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        g.apply_internal(False, prec, nrhs, iters)
+        e1.record(stream)
+        e1.synchronize()
+        return 1e3 * e0.elapsed_time(e1) / iters
+
+    Lt = 4096
+    t = synth.tile_u1(th, Lt // L, Lt // L)
+    U = torch.from_numpy(np.exp(1j * t)[..., None, None].copy()).cuda()
+    g = amg.Gauge(U, -0.05)
+    del U
+    V = Lt * Lt
+    for prec, name, bps in ((amg.F64, "f64", 96), (amg.F32, "f32", 48)):
+        us = timed(g, prec)
+        gbs = bps * V / (us * 1e-6) / 1e9
+        out[f"wilson2d_{Lt}x{Lt}_{name}"] = dict(us_per_apply=round(us, 2), bytes_per_site=bps,
+                                                GBps=round(gbs, 1), frac_hbm=round(gbs / HBM_PEAK_GBS, 3))
+    del g
+    dims = (32, 32, 32, 64)
+    V4 = int(np.prod(dims))
+    base = synth.su3_haar((4096,), synth.rng_for(3, 4096))
+    idx = synth.rng_for(3, 1).integers(0, 4096, size=4 * V4)
+    U4 = torch.from_numpy(base[idx].reshape((4,) + tuple(reversed(dims)) + (3, 3))).cuda()
+    g4 = amg.Gauge(U4, 0.0)
+    del U4
+    for prec, name, bps in ((amg.F32, "f32", 480), (amg.F64, "f64", 960)):
+        us = timed(g4, prec)
+        gbs = bps * V4 / (us * 1e-6) / 1e9
+        out[f"wilson4d_32x32x32x64_{name}"] = dict(us_per_apply=round(us, 2), bytes_per_site=bps,
+                                                  GBps=round(gbs, 1), frac_hbm=round(gbs / HBM_PEAK_GBS, 3))
+    del g4
+    return out
+
+
+def cpu_baseline_child(path_in: str, path_out: str):
+    """Runs in a single-threaded subprocess: the oracle (FP64 NumPy/SciPy) on a
+    bounded sample of the job, plus direct solves for the error report."""
+    import scipy.sparse.linalg as spla
+    from oracle import dirac, mg
+    data = np.load(path_in)
+    res = {"errors": []}
+    # errors of the GPU solutions vs the plain definition psi = D^-1 chi (sparse LU)
+    b = source()[0].reshape(L * L, 2)
+    fields = {float(k.split("_")[1]): data[k] for k in data.files if k.startswith("theta_")}
+    for i in range(len(data["betas"])):
+        beta, m = float(data["betas"][i]), float(data["masses"][i])
+        A = mg.wilson_stencil(dirac.u1_field(fields[beta]), m)
+        xd = spla.spsolve(A.to_sparse().tocsc(), b.ravel())
+        psi = data["psi"][i].ravel()
+        res["errors"].append(float(np.linalg.norm(psi - xd) / np.linalg.norm(xd)))
+    # the timed sample: beta = 6 ensemble, lightest mass
+    beta = 6.0
+    W = workload(beta)
+    th = fields.get(beta)
+    if th is None:
+        th = gen_config(beta)[1]
+    A = mg.wilson_stencil(dirac.u1_field(th), W["masses"][-1])
+    p = mg.MGParams(blocks=PARAMS["blocks"], nvec=PARAMS["nvec"], nu_pre=2, nu_post=2, omega=0.8,
+                    coarse_tol=PARAMS["coarse_tol"], coarse_maxiter=PARAMS["coarse_maxiter"],
+                    coarse_restart=PARAMS["coarse_restart"], outer_restart=PARAMS["outer_restart"],
+                    kcycle_tol=PARAMS["kcycle_tol"], kcycle_maxiter=PARAMS["kcycle_maxiter"])
+    init = init_vectors()
+    # (1) adaptive setup unit: the first two near-null vectors of the finest coarsening
+    t0 = time.perf_counter()
+    v1 = mg.relax_homogeneous(A, init[0][0], 20, p.omega)
+    P = mg.build_prolongator(v1[None], A.dims, (4, 4))
+    Ac = mg.galerkin(A, P)
+    H2 = mg.Hierarchy([A, Ac], [P], p)
+    e = init[0][1].copy()
+    for _ in range(2):
+        e = e - mg.vcycle(H2, 0, A.apply(e))
+    t1 = time.perf_counter()
+    res["setup_two_vectors_s"] = t1 - t0
+    # (2) solve unit: outer FGCR iterations of the 3-level K-cycle on a
+    # hierarchy of relaxed random vectors (its construction is not timed)
+    vecs0 = np.stack([mg.relax_homogeneous(A, v, 20, p.omega) for v in init[0]])
+    P0 = mg.build_prolongator(vecs0, A.dims, (4, 4))
+    A1 = mg.galerkin(A, P0)
+    vecs1 = np.stack([mg.relax_homogeneous(A1, v, 20, p.omega) for v in init[1]])
+    H = mg.build_hierarchy(A, [vecs0, vecs1], p)
+    t2 = time.perf_counter()
+    mg.fgcr(H.ops[0], b, lambda r: mg.vcycle(H, 0, r), 1e-30, 2, 16)
+    t3 = time.perf_counter()
+    res["outer_iteration_s"] = (t3 - t2) / 2
+    with open(path_out, "w") as f:
+        json.dump(res, f)
+
+
+def cpu_baseline(job, recs):
+    """Launch the oracle sample in a single-threaded subprocess and scale it to the job."""
+    import subprocess
+    import tempfile
+    tmp = tempfile.mkdtemp(prefix="amg_bench_")
+    pin, pout = os.path.join(tmp, "gpu.npz"), os.path.join(tmp, "cpu.json")
+    np.savez(pin, betas=np.array([r[0] for r in job.results]), masses=np.array([r[1] for r in job.results]),
+             psi=np.stack([r[2] for r in job.results]),
+             **{f"theta_{int(b)}": th for b, th in job.fields.items()})
+    env = dict(os.environ, OMP_NUM_THREADS="1", MKL_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1",
+               HIP_VISIBLE_DEVICES="", CUDA_VISIBLE_DEVICES="")
+    t0 = time.perf_counter()
+    subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-child", pin, pout], check=True, env=env)
+    wall = time.perf_counter() - t0
+    cb = json.load(open(pout))
+    # scale: 16 near-null vectors per ensemble (2 coarsenings x 8), one outer
+    # iteration per GPU outer iteration of the same algorithm
+    setup_s = 8.0 * cb["setup_two_vectors_s"] * len(BETAS)   # 2 vectors measured, 16 needed per ensemble
+    solve_s = sum(r["iters"] for r in recs) * cb["outer_iteration_s"]
+    step_s = setup_s + solve_s
+    value = len(recs) / step_s
+    return {
+        "value": round(value, 6), "unit": "solves/s (1e-10 true FP64 rel. residual, setup included)",
+        "cores": 1, "kind": "oracle",
+        "sample": (f"oracle (FP64 NumPy, 1 thread) on the beta=6 256^2 ensemble at the lightest mass: "
+                   f"adaptive setup of the first 2 near-null vectors ({cb['setup_two_vectors_s']:.1f} s) and "
+                   f"2 outer FGCR iterations of the same 3-level K-cycle ({cb['outer_iteration_s']:.2f} s each); "
+                   f"scaled to the step by 16 vectors per ensemble and the GPU's outer iteration counts; "
+                   f"sample wall time {wall:.0f} s including direct solves for the error report"),
+    }, cb["errors"]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-stencil", action="store_true")
+    ap.add_argument("--betas", type=str, default=None, help="comma-separated subset of the ensembles")
+    args = ap.parse_args()
+    global BETAS
+    if args.betas:
+        BETAS = [float(b) for b in args.betas.split(",")]
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (the multi-GPU "
+                                   "decomposition is described in the design notes, not built)"}))
+        sys.exit(2)
+
+    log("generating gauge ensembles (heat-bath, 3 workers)")
+    with cf.ProcessPoolExecutor(max_workers=len(BETAS)) as ex:
+        fields = dict(ex.map(gen_config, BETAS))
+
+    import torch
+    import paper_0707_4018_amd as amg
+    torch.cuda.set_device(0)
+    job = Job(amg, torch, fields)
+
+    for i in range(args.warmup):
+        log(f"warmup step {i}")
+        job.step(mixed=True)
+    torch.cuda.synchronize()
+    log(f"timing {args.steps} steps")
+    t0 = time.perf_counter()
+    tot_setup = tot_solve = 0.0
+    recs = []
+    for i in range(args.steps):
+        s_ms, v_ms, recs, _ = job.step(mixed=True, keep=(i == args.steps - 1))
+        tot_setup += s_ms
+        tot_solve += v_ms
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = 1e3 * (t1 - t0) / args.steps
+    nsolve = len(BETAS) * 4
+    value = nsolve / (ms_per_step / 1e3)
+
+    out = {
+        "metric": "time-to-solution at 1e-10 rel. residual + stencil GB/s; mixed/learned vs FP64 MG",
+        "value": round(value, 3),
+        "unit": "solves/s (1e-10 true FP64 rel. residual, setup included)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+bf16 V-cycle, f64 outer", "data": "synthetic",
+        "config": {"workload": "schwinger-256x256, beta {3,6,10} x 4 masses, 3-level MG mixed precision",
+                   "lattice": [L, L], "betas": BETAS, "mass_gaps": workload(6.0)["mass_gaps"],
+                   "levels": 3, "blocks": [[4, 4], [2, 2]], "nvec": [8, 8], "tol": TOL},
+        "time_to_solution_ms": round(tot_solve / args.steps / nsolve, 3),
+        "setup_ms_per_ensemble": round(tot_setup / args.steps / len(BETAS), 3),
+        "solves": recs,
+    }
+
+    # dominant kernel (coarsest-level block stencil, 32^2 sites x 16 dof, FP32):
+    # every launch in one more full step bracketed by HIP events on the stream
+    log("kernel timing pass")
+    _, _, _, prof = job.step(mixed=True, profile=(amg.Solver.PROF_COARSE, 2))
+    Vc2 = (L // 8) ** 2
+    bytes_launch = Vc2 * (5 * 16 * 16 * 8) + 3 * Vc2 * 16 * 8   # Y + in, out, copy/rhs vector
+    avg_s = prof[0] / max(prof[1], 1) * 1e-3
+    achieved = bytes_launch / avg_s / 1e9
+    out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                       "kernel": "coarse16_kernel<float> (level-2 block stencil, 1024 sites x 16 dof)",
+                       "bytes_per_launch": bytes_launch, "avg_launch_us": round(avg_s * 1e6, 3),
+                       "launches": prof[1]}
+
+    if not args.no_fp64:
+        log("FP64 MG comparison step")
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        s64, v64, recs64, _ = job.step(mixed=False)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        out["fp64_mg"] = {"ms_per_step": round(1e3 * (t3 - t2), 2),
+                          "time_to_solution_ms": round(v64 / nsolve, 3),
+                          "setup_ms_per_ensemble": round(s64 / len(BETAS), 3),
+                          "iters": [r["iters"] for r in recs64],
+                          "speedup_mixed_vs_fp64": round(1e3 * (t3 - t2) / ms_per_step, 3)}
+    if not args.no_stencil:
+        log("stencil bandwidth")
+        out["stencil"] = stencil_bench(amg, torch, fields[BETAS[-1]])
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle, single-threaded subprocess)")
+        cb, errs = cpu_baseline(job, recs)
+        out["cpu_baseline"] = cb
+        for r, e in zip(out["solves"], errs):
+            r["err_vs_oracle_direct"] = e
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    if len(sys.argv) == 4 and sys.argv[1] == "--cpu-child":
+        cpu_baseline_child(sys.argv[2], sys.argv[3])
+    else:
+        main()

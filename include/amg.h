@@ -77,6 +77,8 @@ typedef struct {
   int outer_restart;    /* fine FGCR restart length (<= 32)                      */
   int inner_prec;       /* AMG_F64: FP64 V-cycle; AMG_F32: FP32 V-cycle          */
   int p_bf16;           /* with AMG_F32: store P in bfloat16 (Galerkin uses the rounded P) */
+  double kcycle_tol;    /* intermediate levels: flexible GCR preconditioned by their own cycle */
+  int kcycle_maxiter;   /*   to kcycle_tol, at most kcycle_maxiter (<= 32) steps; 0: V-cycle */
 } amg_mg_params;
 
 typedef struct {
@@ -185,6 +187,15 @@ amg_status amg_vcycle(amg_solver* s, const void* dev_b, void* dev_x, int nrhs, v
  * x = MR_nu(b), FP64 canonical. */
 amg_status amg_mr(amg_solver* s, int level, int nu, const void* dev_b, void* dev_x,
                   int nrhs, void* stream);
+
+/* ---- kernel timing (HIP events) -------------------------------------------
+ * While enabled, every launch of kernel `kind` on level `level` made by this
+ * solver is bracketed by a pair of HIP events on its stream.  amg_profile_read
+ * synchronises on the last event and returns the summed kernel time and the
+ * number of launches since enabling.  kind: 0 fine Wilson stencil, 1 coarse
+ * block stencil, 2 restriction, 3 prolongation (level = the fine side). */
+amg_status amg_profile_enable(amg_solver* s, int kind, int level, int enable);
+amg_status amg_profile_read(amg_solver* s, double* total_ms, long long* launches);
 
 /* Introspection: lattice extents and dof per site of a level. */
 amg_status amg_level_info(const amg_solver* s, int level, int* dims4, int* dof, long long* V);

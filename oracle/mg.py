@@ -424,6 +424,8 @@ class MGParams:
     coarse_restart: int = 16
     outer_restart: int = 16
     smoother: object = None           # callable(A, b, nu, omega) -> (x, r); MR when None
+    kcycle_tol: float = None          # intermediate levels: GCR to this tolerance (K-cycle); None: V-cycle
+    kcycle_maxiter: int = 8
 
 
 @dataclass
@@ -438,14 +440,15 @@ class Hierarchy:
         return len(self.ops)
 
 
-def gcr_coarse(A: Stencil, b: np.ndarray, tol: float, maxiter: int, restart: int) -> np.ndarray:
-    """Approximate coarsest-level solve: unpreconditioned GCR from x = 0.
+def gcr_coarse(A: Stencil, b: np.ndarray, tol: float, maxiter: int, restart: int, precond=None) -> np.ndarray:
+    """Approximate level solve: GCR from x = 0 (flexible when a preconditioner is given).
 
     The paper solves its coarsest lattice exactly; a lattice too large for
     that is solved approximately here (the outer Krylov method is flexible).
     Iteration it: stop if ||r|| <= tol ||b|| (recursive residual); at the
     start of every restart cycle after the first, r = b - A x and the stored
-    directions are dropped; then z = r, w = A z, w and z are orthogonalised
+    directions are dropped; then z = r (or z = M(r) with a preconditioner M),
+    w = A z, w and z are orthogonalised
     against the stored directions (classical Gram-Schmidt coefficients
     <w_j, w>/<w_j, w_j>), alpha = <w, r>/<w, w>, x += alpha z, r -= alpha w.
     At most maxiter iterations; tol >= 1 returns x = 0.
@@ -461,7 +464,7 @@ def gcr_coarse(A: Stencil, b: np.ndarray, tol: float, maxiter: int, restart: int
         if it % restart == 0 and it > 0:
             r = b - A.apply(x)
             Z, W, WW = [], [], []
-        z = r.copy()
+        z = r.copy() if precond is None else precond(r)
         w = A.apply(z)
         betas = [(vdot(W[j], w) / WW[j]) if WW[j] > 0 else 0.0 for j in range(len(W))]
         for j, beta in enumerate(betas):
@@ -500,7 +503,13 @@ def vcycle(H: Hierarchy, level: int, b: np.ndarray) -> np.ndarray:
     P = H.Ps[level]
     x, r = relax(A, b, p.nu_pre, p.omega)
     rc = P.restrict(r)
-    ec = vcycle(H, level + 1, rc)
+    if p.kcycle_tol is not None and level + 1 < H.nlevels - 1:
+        # K-cycle: the intermediate level is solved by flexible GCR
+        # preconditioned by its own cycle
+        ec = gcr_coarse(H.ops[level + 1], rc, p.kcycle_tol, p.kcycle_maxiter, p.kcycle_maxiter,
+                        precond=lambda rr: vcycle(H, level + 1, rr))
+    else:
+        ec = vcycle(H, level + 1, rc)
     x = x + P.prolong(ec)
     r = b - A.apply(x)
     x = x + relax(A, r, p.nu_post, p.omega)[0]

@@ -14,7 +14,7 @@ import scipy.sparse.linalg as spla
 from .mg import Stencil
 
 
-def leftmost_eigenvalues(A0: Stencil, k: int = 8, shifts=(-0.1,)) -> np.ndarray:
+def leftmost_eigenvalues(A0: Stencil, k: int = 4, shifts=(-0.05,)) -> np.ndarray:
     """Eigenvalues of A0 with the smallest real parts.
 
     Dense for up to 4096 unknowns; beyond that ARPACK on (A0 - s)^-1 (sparse
@@ -31,7 +31,8 @@ def leftmost_eigenvalues(A0: Stencil, k: int = 8, shifts=(-0.1,)) -> np.ndarray:
     for s in shifts:
         lu = spla.splu((M - s * sp.identity(N, format="csc")).tocsc())
         op = spla.LinearOperator(M.shape, matvec=lu.solve, dtype=np.complex128)
-        mu = spla.eigs(op, k=k, which="LM", return_eigenvectors=False, tol=1e-9)
+        mu = spla.eigs(op, k=k, which="LM", return_eigenvectors=False, tol=1e-6,
+                       ncv=max(4 * k, 40), maxiter=100000)
         pool.append(1.0 / mu + s)
     ev = np.concatenate(pool)
     return ev[np.argsort(ev.real)][:k]

@@ -40,6 +40,7 @@ class _Params(C.Structure):
         ("nu_pre", C.c_int), ("nu_post", C.c_int), ("omega", C.c_double),
         ("coarse_tol", C.c_double), ("coarse_maxiter", C.c_int), ("coarse_restart", C.c_int),
         ("outer_restart", C.c_int), ("inner_prec", C.c_int), ("p_bf16", C.c_int),
+        ("kcycle_tol", C.c_double), ("kcycle_maxiter", C.c_int),
     ]
 
 
@@ -76,6 +77,8 @@ _SIGS = {
     "amg_mr": (C.c_int, [_P, C.c_int, C.c_int, _P, _P, C.c_int, _P]),
     "amg_level_info": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                  C.POINTER(C.c_longlong)]),
+    "amg_profile_enable": (C.c_int, [_P, C.c_int, C.c_int, C.c_int]),
+    "amg_profile_read": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_longlong)]),
 }
 
 
@@ -131,6 +134,8 @@ class MGParams:
     outer_restart: int = 16
     inner_prec: int = F64
     p_bf16: bool = False
+    kcycle_tol: float = 0.1
+    kcycle_maxiter: int = 0
 
     def to_c(self) -> _Params:
         p = _Params()
@@ -143,6 +148,7 @@ class MGParams:
         p.nu_pre, p.nu_post, p.omega = self.nu_pre, self.nu_post, self.omega
         p.coarse_tol, p.coarse_maxiter, p.coarse_restart = self.coarse_tol, self.coarse_maxiter, self.coarse_restart
         p.outer_restart, p.inner_prec, p.p_bf16 = self.outer_restart, self.inner_prec, int(self.p_bf16)
+        p.kcycle_tol, p.kcycle_maxiter = self.kcycle_tol, self.kcycle_maxiter
         return p
 
 
@@ -321,6 +327,19 @@ class Solver:
         out = torch.empty((nv, V, dof), dtype=torch.complex128, device="cuda")
         _check(load_library().amg_get_nullvecs(self._h, level, _ptr(out), _stream()), "amg_get_nullvecs")
         return out
+
+    PROF_FINE, PROF_COARSE, PROF_RESTRICT, PROF_PROLONG = 0, 1, 2, 3
+
+    def profile(self, kind: int, level: int, enable: bool = True):
+        """Time every launch of kernel `kind` on `level` with HIP events."""
+        _check(load_library().amg_profile_enable(self._h, kind, level, int(enable)), "amg_profile_enable")
+
+    def profile_read(self):
+        """(summed kernel milliseconds, launches) since profile(); synchronises."""
+        ms = C.c_double()
+        n = C.c_longlong()
+        _check(load_library().amg_profile_read(self._h, C.byref(ms), C.byref(n)), "amg_profile_read")
+        return ms.value, n.value
 
     def __del__(self):
         try:

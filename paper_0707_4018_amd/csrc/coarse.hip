@@ -89,6 +89,85 @@ __global__ __launch_bounds__(256) void coarse_kernel(CoarseArgs<T> a) {
   }
 }
 
+// Wave-per-site variant for N_c = 16 (the 2d hierarchy).  The 5 blocks of a
+// site (80 columns of 16 rows, contiguous) are streamed with each lane
+// loading 16 bytes: R = 16 / sizeof(complex T) rows of one column per lane,
+// LPC = 16 / R lanes per column, CPI = 64 / LPC columns per instruction.
+// Partial row sums are then reduced across the lanes that share the rows.
+template <typename T, int DAG, int EPI>
+__global__ __launch_bounds__(256) void coarse16_kernel(CoarseArgs<T> a) {
+  constexpr int NC = 16;
+  constexpr int R = (sizeof(T) == 4) ? 2 : 1;
+  constexpr int LPC = NC / R;
+  constexpr int CPI = 64 / LPC;
+  const int rhs = blockIdx.y;
+  if (skip_rhs(a.red.flags, rhs)) return;
+  const int nd = a.g.nd;
+  const int ndir = 2 * nd + 1;
+  const int ncols = ndir * NC;
+  const long V = a.g.V;
+  const long ro = (long)rhs * V * NC;
+  const cplx<T>* __restrict__ pin = a.in + ro;
+  const int lane = threadIdx.x & 63;
+  const int cg = lane / LPC, rg = lane - cg * LPC;
+  const int wave = threadIdx.x >> 6;
+  double acc3[3] = {0.0, 0.0, 0.0};
+  for (long site = (long)blockIdx.x * 4 + wave; site < V; site += (long)gridDim.x * 4) {
+    int x[4];
+    coords(site, a.g.dims, nd, x);
+    long nbs[9];
+    nbs[0] = site;
+    for (int k = 1; k < ndir; ++k) nbs[k] = neighbour(site, x, a.g.dims, nd, k - 1);
+    cplx<T> acc[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) acc[i] = mk<T>(0, 0);
+    const cplx<T>* __restrict__ Ys = a.Y + site * (long)ndir * NC * NC;
+    for (int gc = cg; gc < ncols; gc += CPI) {
+      const int k = gc / NC, col = gc - k * NC;
+      cplx<T> e = pin[nbs[k] * NC + col];
+      if (DAG && col >= NC / 2) e = mk<T>(-e.x, -e.y);
+      const cplx<T>* y = Ys + (long)gc * NC + rg * R;
+#pragma unroll
+      for (int i = 0; i < R; ++i) cfma<T>(acc[i], y[i], e);
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+#pragma unroll
+      for (int o = LPC; o < 64; o <<= 1) {
+        acc[i].x += __shfl_xor(acc[i].x, o, 64);
+        acc[i].y += __shfl_xor(acc[i].y, o, 64);
+      }
+    }
+    if (cg == 0) {
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        const int row = rg * R + i;
+        cplx<T> v = acc[i];
+        if (DAG && row >= NC / 2) v = mk<T>(-v.x, -v.y);
+        const long idx = ro + site * NC + row;
+        const cplx<T> c = a.in[idx];
+        if (EPI == EPI_RESID) v = csub<T>(a.b[idx], v);
+        a.out[idx] = v;
+        if (a.copy_out) a.copy_out[idx] = c;
+        if (EPI == EPI_MRDOT) {
+          acc3[0] += (double)v.x * c.x + (double)v.y * c.y;
+          acc3[1] += (double)v.x * c.y - (double)v.y * c.x;
+          acc3[2] += (double)v.x * v.x + (double)v.y * v.y;
+        } else if (EPI == EPI_NORM) {
+          acc3[0] += (double)v.x * v.x + (double)v.y * v.y;
+        }
+      }
+    }
+  }
+  if (EPI == EPI_MRDOT) {
+    double tot[3];
+    if (grid_reduce<3>(acc3, a.red.part, a.red.ticket, rhs, tot) && threadIdx.x == 0) finalize_mr(tot, a.red, rhs);
+  } else if (EPI == EPI_NORM) {
+    double a1[1] = {acc3[0]}, tot[1];
+    if (grid_reduce<1>(a1, a.red.part, a.red.ticket, rhs, tot) && threadIdx.x == 0) a.red.scal[a.red.slot + rhs] = tot[0];
+  }
+}
+
 // Split apply (FP64) of a coarse operator for the next Galerkin product:
 // out[0] = diagonal + hops inside the next block, out[1 + dir] = the hop in
 // direction dir when it leaves the block through its face.
@@ -339,7 +418,22 @@ void launch_coarse(const CoarseArgs<T>& a, int dagger, int epi, hipStream_t st) 
     default: AMG_C(NC, DAG, EPI_NORM); break;   \
   }
   if (a.g.nc == 16) {
-    if (dagger) { AMG_C_EPI(16, 1) } else { AMG_C_EPI(16, 0) }
+    long nb = (a.g.V + 3) / 4;
+    const long cap = red ? RED_MAX_BLOCKS : (1L << 20);
+    if (nb > cap) nb = cap;
+    dim3 g16((unsigned)nb, (unsigned)a.nrhs);
+#define AMG_C16(DAG, EPI) hipLaunchKernelGGL((coarse16_kernel<T, DAG, EPI>), g16, dim3(256), 0, st, a)
+    switch (epi * 2 + (dagger ? 1 : 0)) {
+      case EPI_PLAIN * 2: AMG_C16(0, EPI_PLAIN); break;
+      case EPI_PLAIN * 2 + 1: AMG_C16(1, EPI_PLAIN); break;
+      case EPI_MRDOT * 2: AMG_C16(0, EPI_MRDOT); break;
+      case EPI_MRDOT * 2 + 1: AMG_C16(1, EPI_MRDOT); break;
+      case EPI_RESID * 2: AMG_C16(0, EPI_RESID); break;
+      case EPI_RESID * 2 + 1: AMG_C16(1, EPI_RESID); break;
+      case EPI_NORM * 2: AMG_C16(0, EPI_NORM); break;
+      default: AMG_C16(1, EPI_NORM); break;
+    }
+#undef AMG_C16
   } else if (a.g.nc == 48) {
     if (dagger) { AMG_C_EPI(48, 1) } else { AMG_C_EPI(48, 0) }
   } else {

@@ -142,6 +142,13 @@ template <typename T>
 void launch_scale_inv_norm(cplx<T>* v, const double* nn, long n, int nrhs, hipStream_t st);
 void launch_diag_shift(double2* Y, const double2* M, long V, int nc, int ndir, double dm, hipStream_t st);
 void launch_links4d_pack(double2* U64, float2* U32, const double2* canon, long V, hipStream_t st);
+// whole coarsest-level GCR (N_c = 16) in one cooperative launch
+template <typename T>
+hipError_t launch_gcr16_persistent(const cplx<T>* Y, const CoarseGeom& g, const cplx<T>* b, cplx<T>* x, cplx<T>* r,
+                                   cplx<T>* Zb, cplx<T>* Wb, long dstride, int m, int maxiter, double tol2, int nrhs,
+                                   int nblk, double* part, unsigned* bar, int* err, int* iters, hipStream_t st,
+                                   bool cooperative);
+int gcr16_partials_per_block();
 // CG on the normal equations
 void launch_cg_update(double2* x, double2* r, const double2* p, const double2* q, long n, int nrhs,
                       RedArgs red, int gamma_slot, int qq_slot, int rr_slot, hipStream_t st);

@@ -5,9 +5,11 @@
 // residual norm per outer iteration.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -94,6 +96,15 @@ struct Scratch {
     r.flags = fl;
     return r;
   }
+  // true when flags[off .. off+n) are all set (synchronises the stream)
+  bool all_flags(int off, int n, hipStream_t st) {
+    int* h = reinterpret_cast<int*>(host + RHS_MAX * 2);
+    HIPC(hipMemcpyAsync(h, flags.as<int>() + off, sizeof(int) * n, hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    for (int i = 0; i < n; ++i)
+      if (!h[i]) return false;
+    return true;
+  }
   // copy n scalars from slot to the pinned mirror and wait for them
   const double* fetch(int slot, int n, hipStream_t st) {
     HIPC(hipMemcpyAsync(host, scal.as<double>() + slot, sizeof(double) * n, hipMemcpyDeviceToHost, st));
@@ -161,7 +172,7 @@ void wilson_apply(const amg_gauge& g, double mass, int dagger, int epi, const cp
 // ---------------------------------------------------------------------------
 namespace {
 
-enum { W_B = 0, W_X, W_R, W_P, W_COUNT };
+enum { W_B = 0, W_X, W_R, W_P, W_GR, W_COUNT };
 
 struct Level {
   bool fine = false;
@@ -224,11 +235,54 @@ struct amg_solver {
   // setup temporaries
   Buf tE, tF, tS, tR, tzero;
   long long nD = 0, nDd = 0, nC = 0;
+  // persistent coarsest solve: barrier counters, timeout flag, iteration counts
+  Buf pbar, perr, piters;
+  bool persistent = false;  // measured slower than the launch sequence (grid barriers are costly)
+  int pcoarse_max_blocks = 64;
+  bool pcoarse_coop = true;
+  // kernel timing
+  struct Prof {
+    bool on = false;
+    int kind = -1, level = -1;
+    std::vector<hipEvent_t> ev;  // start/stop pairs, reused
+    size_t used = 0;
+    hipStream_t last = nullptr;
+  } prof;
+  ~amg_solver() {
+    for (auto e : prof.ev) (void)hipEventDestroy(e);
+  }
 };
 
 namespace {
 
 using Solver = amg_solver;
+
+enum { PK_FINE = 0, PK_COARSE = 1, PK_RESTRICT = 2, PK_PROLONG = 3 };
+
+// event pair around one launch when the profiler watches (kind, level)
+struct ProfScope {
+  Solver& S;
+  bool active;
+  hipStream_t st;
+  ProfScope(Solver& s, int kind, int level, hipStream_t stream)
+      : S(s), active(s.prof.on && s.prof.kind == kind && s.prof.level == level), st(stream) {
+    if (!active) return;
+    auto& P = S.prof;
+    while (P.ev.size() < P.used + 2) {
+      hipEvent_t e;
+      HIPC(hipEventCreate(&e));
+      P.ev.push_back(e);
+    }
+    HIPC(hipEventRecord(P.ev[P.used], st));
+  }
+  ~ProfScope() {
+    if (!active) return;
+    auto& P = S.prof;
+    (void)hipEventRecord(P.ev[P.used + 1], st);
+    P.used += 2;
+    P.last = st;
+  }
+};
 
 TransferGeom tgeom(const Solver& S, int l, int prec) {
   const Level& f = S.lv[l];
@@ -264,6 +318,7 @@ template <typename T>
 void op_apply(Solver& S, int l, int dagger, int epi, const cplx<T>* in, cplx<T>* out, const cplx<T>* b,
               cplx<T>* copy_out, int nrhs, RedArgs red, hipStream_t st) {
   Level& L = S.lv[l];
+  ProfScope ps(S, L.fine ? PK_FINE : PK_COARSE, l, st);
   if (L.fine) {
     wilson_apply<T>(*S.g, S.mass, dagger, epi, in, out, b, copy_out, nrhs, red, st);
     (dagger ? S.nDd : S.nD) += 1;
@@ -303,7 +358,7 @@ void ensure_work(Solver& S, int nrhs) {
   const int nl = (int)S.lv.size();
   for (int l = 0; l < nl; ++l) {
     // during adaptive setup every level may serve as the coarsest one
-    alloc_level_work(S.lv[l], nrhs, S.p.coarse_restart, l > 0, f32);
+    alloc_level_work(S.lv[l], nrhs, std::max(S.p.coarse_restart, S.p.kcycle_maxiter), l > 0, f32);
   }
   if (S.o_nrhs < nrhs) {
     const size_t n = (size_t)S.lv[0].V * S.lv[0].dof * nrhs;
@@ -341,36 +396,72 @@ void mr_smooth(Solver& S, int l, const cplx<T>* b, cplx<T>* x, cplx<T>* r, cplx<
   }
 }
 
-// ---- coarsest solve: GCR with restarts, stopping per rhs on the recursive
-// residual |r| <= coarse_tol |b| (device flags; later launches become no-ops)
+constexpr int kCoarseCheck = 8;  // unpreconditioned GCR iterations between flag checks
+
 template <typename T>
-void coarse_gcr(Solver& S, int l, const cplx<T>* b, cplx<T>* x, int nrhs, hipStream_t st) {
+void vcycle(Solver& S, int l, int lstop, const cplx<T>* b, cplx<T>* x, int nrhs, hipStream_t st);
+
+// ---- GCR on level l with restarts, stopping per rhs on the recursive
+// residual |r| <= tol |b| (device flags; later launches become no-ops).
+// precond = false: the coarsest-level solve (z = r);
+// precond = true:  a K-cycle level, z = the cycle of level l down to lstop.
+template <typename T>
+void level_gcr(Solver& S, int l, int lstop, const cplx<T>* b, cplx<T>* x, int nrhs, double tol, int maxiter,
+               int m, bool precond, hipStream_t st) {
   Level& L = S.lv[l];
   const long n = L.per_rhs();
   const long dstride = n * nrhs;
   Buf* w = L.w<T>();
-  cplx<T>* r = w[W_R].as<cplx<T>>();
+  cplx<T>* r = w[W_GR].as<cplx<T>>();
   cplx<T>* Zb = L.template Zd<T>().template as<cplx<T>>();
   cplx<T>* Wb = L.template Wd<T>().template as<cplx<T>>();
   int* flags = S.sc.flags.as<int>() + L.flag_off;
-  const int m = S.p.coarse_restart;
-  const double tol2 = S.p.coarse_tol * S.p.coarse_tol;
+  const double tol2 = tol * tol;
+  const int check = precond ? 1 : kCoarseCheck;
+  if (!precond && S.persistent && L.dof == 16 && !L.fine) {
+    // the whole solve in one cooperative launch
+    long nb = (L.V + 15) / 16;
+    nb = std::max(8L, std::min((long)S.pcoarse_max_blocks, nb));
+    HIPC(hipMemsetAsync(S.pbar.p, 0, sizeof(unsigned) * nrhs, st));
+    {
+      ProfScope ps(S, PK_COARSE, l, st);
+      HIPC(launch_gcr16_persistent<T>(L.Y<T>(), L.cgeom(), b, x, r, Zb, Wb, dstride, m, maxiter, tol2, nrhs,
+                                      (int)nb, S.sc.part.as<double>(), S.pbar.as<unsigned>(), S.perr.as<int>(),
+                                      S.piters.as<int>(), st, S.pcoarse_coop));
+    }
+    S.nC += maxiter;  // upper bound of coarse applications (exact count is per rhs on the device)
+    return;
+  }
   HIPC(hipMemsetAsync(x, 0, sizeof(cplx<T>) * dstride, st));
   HIPC(hipMemcpyAsync(r, b, sizeof(cplx<T>) * dstride, hipMemcpyDeviceToDevice, st));
   launch_norm2<T>(b, n, nrhs, S.sc.red(L.gs.bb), st);
   launch_set_flags<T>(flags, S.sc.scal.as<double>(), L.gs.bb, L.gs.bb, tol2 >= 1.0 ? 1.0 : 0.0, nrhs, st);
-  for (int it = 0; it < S.p.coarse_maxiter; ++it) {
+  for (int it = 0; it < maxiter; ++it) {
     const int k = it % m;
     if (k == 0 && it > 0)
       op_apply<T>(S, l, 0, EPI_RESID, x, r, b, nullptr, nrhs, S.sc.red(0, flags), st);
     cplx<T>* Wk = Wb + (long)k * dstride;
     cplx<T>* Zk = Zb + (long)k * dstride;
-    op_apply<T>(S, l, 0, EPI_PLAIN, r, Wk, nullptr, Zk, nrhs, S.sc.red(0, flags), st);
+    if (precond) {
+      vcycle<T>(S, l, lstop, r, Zk, nrhs, st);
+      op_apply<T>(S, l, 0, EPI_PLAIN, Zk, Wk, nullptr, nullptr, nrhs, S.sc.red(0, flags), st);
+    } else {
+      op_apply<T>(S, l, 0, EPI_PLAIN, r, Wk, nullptr, Zk, nrhs, S.sc.red(0, flags), st);
+    }
     launch_gcr_mdot<T>(Wb, dstride, Wk, k, n, nrhs, S.sc.red(0, flags), L.gs.beta, L.gs.ww, st);
     launch_gcr_maxpy<T>(Wk, Zk, Wb, Zb, dstride, r, k, n, nrhs, S.sc.red(0, flags), L.gs.beta, L.gs.ww, L.gs.alpha,
                         st);
     launch_gcr_update<T>(x, r, Zk, Wk, n, nrhs, S.sc.red(0, flags), L.gs.alpha, L.gs.rr, L.gs.bb, tol2, flags, st);
+    // Every rhs that met the tolerance turns the remaining launches into
+    // no-ops; look at the flags now and then and stop issuing them.  This
+    // changes no arithmetic, only how many empty launches are made.
+    if ((it + 1) % check == 0 && it + 1 < maxiter && S.sc.all_flags(L.flag_off, nrhs, st)) break;
   }
+}
+
+template <typename T>
+void coarse_gcr(Solver& S, int l, const cplx<T>* b, cplx<T>* x, int nrhs, hipStream_t st) {
+  level_gcr<T>(S, l, l, b, x, nrhs, S.p.coarse_tol, S.p.coarse_maxiter, S.p.coarse_restart, false, st);
 }
 
 // ---- V-cycle (five steps listed before Eq. (3), applied to D) ---------------
@@ -394,11 +485,20 @@ void vcycle(Solver& S, int l, int lstop, const cplx<T>* b, cplx<T>* x, int nrhs,
   // 2. restrict the residual
   cplx<T>* bc = wc[W_B].as<cplx<T>>();
   cplx<T>* xc = wc[W_X].as<cplx<T>>();
-  launch_restrict<T>(bc, r, P, pk, tg, nrhs, nullptr, st);
-  // 3. coarse-level cycle
-  vcycle<T>(S, l + 1, lstop, bc, xc, nrhs, st);
+  {
+    ProfScope ps(S, PK_RESTRICT, l, st);
+    launch_restrict<T>(bc, r, P, pk, tg, nrhs, nullptr, st);
+  }
+  // 3. coarse-level cycle; an intermediate level is a K-cycle when enabled
+  if (S.p.kcycle_maxiter > 0 && l + 1 < lstop)
+    level_gcr<T>(S, l + 1, lstop, bc, xc, nrhs, S.p.kcycle_tol, S.p.kcycle_maxiter, S.p.kcycle_maxiter, true, st);
+  else
+    vcycle<T>(S, l + 1, lstop, bc, xc, nrhs, st);
   // 4. coarse-grid correction
-  launch_prolong<T>(x, xc, P, pk, tg, nrhs, 1, nullptr, st);
+  {
+    ProfScope ps(S, PK_PROLONG, l, st);
+    launch_prolong<T>(x, xc, P, pk, tg, nrhs, 1, nullptr, st);
+  }
   // 5. post-relax on the new residual
   op_apply<T>(S, l, 0, EPI_RESID, x, r, b, nullptr, nrhs, S.sc.red(0), st);
   mr_smooth<T>(S, l, r, x, r, p, S.p.nu_post, false, false, nrhs, st);
@@ -503,6 +603,8 @@ void check_params(const amg_gauge* g, const amg_mg_params* p) {
   if (p->coarse_maxiter < 1 || p->coarse_restart < 1 || p->coarse_restart > GCR_KMAX) fail(AMG_ERR_ARG, "bad coarse GCR limits");
   if (p->outer_restart < 1 || p->outer_restart > GCR_KMAX) fail(AMG_ERR_ARG, "outer_restart must be 1..32");
   if (p->inner_prec != AMG_F64 && p->inner_prec != AMG_F32) fail(AMG_ERR_ARG, "bad inner_prec");
+  if (p->kcycle_maxiter < 0 || p->kcycle_maxiter > GCR_KMAX) fail(AMG_ERR_ARG, "kcycle_maxiter must be 0..32");
+  if (p->kcycle_maxiter > 0 && !(p->kcycle_tol >= 0.0 && std::isfinite(p->kcycle_tol))) fail(AMG_ERR_ARG, "bad kcycle_tol");
   int dims[4];
   for (int mu = 0; mu < 4; ++mu) dims[mu] = g->dims[mu];
   int dof = g->dof;
@@ -565,6 +667,13 @@ Solver* new_solver(const amg_gauge* g, const amg_mg_params* p) {
   for (size_t l = 0; l < S->lv.size(); ++l) S->lv[l].flag_off = RHS_MAX * (int)l;
   S->flags_base = RHS_MAX * (int)S->lv.size();
   S->sc.init(off, nflags);
+  S->pbar.ensure(sizeof(unsigned) * RHS_MAX);
+  S->perr.ensure(sizeof(int) * 4);
+  S->piters.ensure(sizeof(int) * RHS_MAX);
+  HIPC(hipMemset(S->perr.p, 0, sizeof(int) * 4));
+  if (const char* e = std::getenv("AMG_PERSISTENT_COARSE")) S->persistent = std::atoi(e) != 0;
+  if (const char* e = std::getenv("AMG_PCOARSE_BLOCKS")) S->pcoarse_max_blocks = std::max(1, std::min(128, std::atoi(e)));
+  if (const char* e = std::getenv("AMG_PCOARSE_COOP")) S->pcoarse_coop = std::atoi(e) != 0;
   return S;
 }
 
@@ -703,6 +812,16 @@ OuterResult fgcr_outer(Solver& S, const double2* b, double2* x, int nrhs, double
   return res;
 }
 
+// A persistent coarse solve whose grid barrier timed out has left the flag set.
+void check_persistent(Solver& S) {
+  int e = 0;
+  HIPC(hipMemcpy(&e, S.perr.p, sizeof(int), hipMemcpyDeviceToHost));
+  if (e) {
+    HIPC(hipMemset(S.perr.p, 0, sizeof(int)));
+    fail(AMG_ERR_HIP, "a grid barrier of the persistent coarsest solve timed out");
+  }
+}
+
 void check_ptr(const void* p, const char* what) {
   if (!p) fail(AMG_ERR_ARG, std::string("NULL ") + what);
 }
@@ -763,6 +882,8 @@ void amg_default_params(amg_mg_params* p) {
   p->outer_restart = 16;
   p->inner_prec = AMG_F64;
   p->p_bf16 = 0;
+  p->kcycle_tol = 0.1;
+  p->kcycle_maxiter = 0;
 }
 
 amg_status amg_gauge_create(const amg_lattice* lat, const void* dev_links, double mass, void* stream,
@@ -1023,6 +1144,7 @@ amg_status amg_solve(amg_solver* S, const void* dev_chi, void* dev_psi, int nrhs
   OuterResult R = fgcr_outer(*S, S->ob.as<double2>(), S->ox.as<double2>(), nrhs, tol, max_iter, st);
   to_canonical<double>(*S, 0, S->ox.as<double2>(), (double2*)dev_psi, nrhs, st);
   HIPC(hipStreamSynchronize(st));
+  check_persistent(*S);
   const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   bool all = true;
   for (int i = 0; i < nrhs; ++i) {
@@ -1154,6 +1276,33 @@ amg_status amg_mr(amg_solver* S, int level, int nu, const void* dev_b, void* dev
   launch_convert<double, double>(b, (const double2*)dev_b, L.V, L.dof, L.dof, L.lay64.W, nrhs, st);
   mr_smooth<double>(*S, level, b, x, L.w64[W_R].as<double2>(), L.w64[W_P].as<double2>(), nu, true, true, nrhs, st);
   launch_convert<double, double>((double2*)dev_x, x, L.V, L.dof, L.lay64.W, L.dof, nrhs, st);
+  AMG_CATCH
+}
+
+amg_status amg_profile_enable(amg_solver* S, int kind, int level, int enable) {
+  AMG_TRY
+  check_ptr(S, "solver");
+  if (kind < 0 || kind > 3 || level < 0 || level >= (int)S->lv.size()) fail(AMG_ERR_ARG, "bad kind / level");
+  S->prof.on = enable != 0;
+  S->prof.kind = kind;
+  S->prof.level = level;
+  S->prof.used = 0;
+  AMG_CATCH
+}
+
+amg_status amg_profile_read(amg_solver* S, double* total_ms, long long* launches) {
+  AMG_TRY
+  check_ptr(S, "solver");
+  auto& P = S->prof;
+  double tot = 0.0;
+  if (P.used) HIPC(hipEventSynchronize(P.ev[P.used - 1]));
+  for (size_t i = 0; i + 1 < P.used; i += 2) {
+    float ms = 0.f;
+    HIPC(hipEventElapsedTime(&ms, P.ev[i], P.ev[i + 1]));
+    tot += ms;
+  }
+  if (total_ms) *total_ms = tot;
+  if (launches) *launches = (long long)(P.used / 2);
   AMG_CATCH
 }
 

@@ -24,6 +24,8 @@ def _params(blocks, nvec, **kw):
     for k, v in kw.items():
         setattr(o, k, v)
         setattr(g, k, v)
+    if o.kcycle_tol is None:          # plain V-cycle on both sides
+        g.kcycle_tol, g.kcycle_maxiter = 0.1, 0
     return o, g
 
 
@@ -94,10 +96,14 @@ def test_coarse_apply_and_mr_match_oracle():
     assert rel_err(out, Ac.apply(e[0])) < 1e-5
 
 
-@pytest.mark.parametrize("blocks,nvec", [([(4, 4)], [6]), ([(4, 4), (2, 2)], [4, 4])])
-def test_vcycle_matches_oracle(blocks, nvec):
-    print(f"vcycle {blocks} {nvec}", flush=True)
-    U, A, H, g, S = _given(32, 32, blocks, nvec, m=0.02, coarse_tol=0.0, coarse_maxiter=12, coarse_restart=5)
+@pytest.mark.parametrize("blocks,nvec,kc", [([(4, 4)], [6], 0), ([(4, 4), (2, 2)], [4, 4], 0),
+                                            ([(4, 4), (2, 2)], [4, 4], 3), ([(4, 4)], [8], 0),
+                                            ([(4, 4), (2, 2)], [4, 8], 3)])
+def test_vcycle_matches_oracle(blocks, nvec, kc):
+    print(f"vcycle {blocks} {nvec} kcycle {kc}", flush=True)
+    U, A, H, g, S = _given(32, 32, blocks, nvec, m=0.02, coarse_tol=0.0, coarse_maxiter=12, coarse_restart=5,
+                           kcycle_tol=0.0 if kc else None, kcycle_maxiter=kc if kc else 8)
+    assert (S.params.kcycle_maxiter > 0) == bool(kc)
     b = synth.gaussian_field((1, A.V, 2, 1), synth.rng_for(9))
     x = host(S.vcycle(dev(b)))[0].reshape(A.V, 2)
     xo = mg.vcycle(H, 0, b[0].reshape(A.V, 2))
