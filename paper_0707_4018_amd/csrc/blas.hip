@@ -163,6 +163,42 @@ __global__ __launch_bounds__(256) void gcr_update_kernel(cplx<T>* __restrict__ x
   }
 }
 
+// GCR step, part 2: w' = w - sum_j beta_j W_j, z' = zsrc - sum_j beta_j Z_j
+// (stored as direction k), x += alpha z', r -= alpha w', <r, r> and flags.
+template <typename T>
+__global__ __launch_bounds__(256) void gcr_update2_kernel(cplx<T>* __restrict__ x, cplx<T>* __restrict__ r,
+                                                          const cplx<T>* zsrc, cplx<T>* Wb, cplx<T>* Zb, long dstride,
+                                                          int k, long n, RedArgs red, int beta_slot, int alpha_slot,
+                                                          int rr_slot, int bb_slot, double tol2, int* set_flags) {
+  const int rhs = blockIdx.y;
+  if (skip_rhs(red.flags, rhs)) return;
+  const long ro = (long)rhs * n;
+  const double* beta = red.scal + beta_slot + (long)rhs * GCR_KMAX * 2;
+  const cplx<T> al = mk<T>((T)red.scal[alpha_slot + 2 * rhs], (T)red.scal[alpha_slot + 2 * rhs + 1]);
+  cplx<T>* Wk = Wb + (long)k * dstride + ro;
+  cplx<T>* Zk = Zb + (long)k * dstride + ro;
+  double acc[1] = {0.0};
+  GRID_STRIDE(i, n) {
+    cplx<T> wi = Wk[i], zi = zsrc[ro + i];
+    for (int j = 0; j < k; ++j) {
+      const cplx<T> b = mk<T>((T)beta[2 * j], (T)beta[2 * j + 1]);
+      wi = csub<T>(wi, cmul<T>(b, Wb[(long)j * dstride + ro + i]));
+      zi = csub<T>(zi, cmul<T>(b, Zb[(long)j * dstride + ro + i]));
+    }
+    Wk[i] = wi;
+    Zk[i] = zi;
+    x[ro + i] = cadd<T>(x[ro + i], cmul<T>(al, zi));
+    const cplx<T> ri = csub<T>(r[ro + i], cmul<T>(al, wi));
+    r[ro + i] = ri;
+    acc[0] += (double)ri.x * ri.x + (double)ri.y * ri.y;
+  }
+  double tot[1];
+  if (grid_reduce<1>(acc, red.part, red.ticket, rhs, tot) && threadIdx.x == 0) {
+    red.scal[rr_slot + rhs] = tot[0];
+    if (set_flags) set_flags[rhs] = (tot[0] <= tol2 * red.scal[bb_slot + rhs]) ? 1 : 0;
+  }
+}
+
 __global__ void set_flags_kernel(int* flags, const double* scal, int rr_slot, int bb_slot, double tol2, int nrhs) {
   const int rhs = threadIdx.x;
   if (rhs < nrhs) flags[rhs] = (scal[rr_slot + rhs] <= tol2 * scal[bb_slot + rhs]) ? 1 : 0;
@@ -279,6 +315,19 @@ void launch_gcr_update(cplx<T>* x, cplx<T>* r, const cplx<T>* z, const cplx<T>* 
 }
 template void launch_gcr_update<double>(double2*, double2*, const double2*, const double2*, long, int, RedArgs, int, int, int, double, int*, hipStream_t);
 template void launch_gcr_update<float>(float2*, float2*, const float2*, const float2*, long, int, RedArgs, int, int, int, double, int*, hipStream_t);
+
+template <typename T>
+void launch_gcr_update2(cplx<T>* x, cplx<T>* r, const cplx<T>* zsrc, cplx<T>* Wb, cplx<T>* Zb, long dstride, int k,
+                        long n, int nrhs, RedArgs red, int beta_slot, int alpha_slot, int rr_slot, int bb_slot,
+                        double tol2, int* set_flags, hipStream_t st) {
+  dim3 grid(nblocks(n, RED_MAX_BLOCKS), (unsigned)nrhs);
+  hipLaunchKernelGGL((gcr_update2_kernel<T>), grid, dim3(256), 0, st, x, r, zsrc, Wb, Zb, dstride, k, n, red,
+                     beta_slot, alpha_slot, rr_slot, bb_slot, tol2, set_flags);
+}
+template void launch_gcr_update2<double>(double2*, double2*, const double2*, double2*, double2*, long, int, long, int,
+                                         RedArgs, int, int, int, int, double, int*, hipStream_t);
+template void launch_gcr_update2<float>(float2*, float2*, const float2*, float2*, float2*, long, int, long, int,
+                                        RedArgs, int, int, int, int, double, int*, hipStream_t);
 
 template <typename T>
 void launch_set_flags(int* flags, const double* scal, int rr_slot, int bb_slot, double tol2, int nrhs, hipStream_t st) {

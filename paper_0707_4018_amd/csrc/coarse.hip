@@ -89,62 +89,84 @@ __global__ __launch_bounds__(256) void coarse_kernel(CoarseArgs<T> a) {
   }
 }
 
-// Wave-per-site variant for N_c = 16 (the 2d hierarchy).  The 5 blocks of a
-// site (80 columns of 16 rows, contiguous) are streamed with each lane
-// loading 16 bytes: R = 16 / sizeof(complex T) rows of one column per lane,
-// LPC = 16 / R lanes per column, CPI = 64 / LPC columns per instruction.
-// Partial row sums are then reduced across the lanes that share the rows.
+// Wave-per-site variant for N_c = 16 (the 2d hierarchy).  The blocks of a
+// site (16 columns of 16 rows per direction, contiguous) are streamed with
+// each lane loading 16 bytes: R = 16 / sizeof(complex T) rows of one column
+// per lane, LPC = 16 / R lanes per column, CPI = 64 / LPC columns per load.
+// All loads of one direction are issued before its multiply-adds; partial
+// row sums are then reduced across the lanes that share the rows, leaving
+// the 16 results in lanes 0 .. LPC-1.
+template <typename T> struct C16 {
+  static constexpr int NC = 16;
+  static constexpr int R = (sizeof(T) == 4) ? 2 : 1;
+  static constexpr int LPC = NC / R;
+  static constexpr int CPI = 64 / LPC;
+  static constexpr int NQ = NC / CPI;  // loads per lane per direction
+};
+
+template <typename T, int DAG>
+__device__ __forceinline__ void site_apply16(const cplx<T>* __restrict__ Y, const cplx<T>* __restrict__ pin, long site,
+                                             const CoarseGeom& g, int cg, int rg, cplx<T> (&acc)[C16<T>::R]) {
+  using K = C16<T>;
+  int x[4];
+  coords(site, g.dims, g.nd, x);
+  const int ndir = 2 * g.nd + 1;
+#pragma unroll
+  for (int i = 0; i < K::R; ++i) acc[i] = mk<T>(0, 0);
+  const cplx<T>* __restrict__ Ys = Y + site * (long)ndir * K::NC * K::NC;
+  for (int k = 0; k < ndir; ++k) {
+    const long nb = (k == 0) ? site : neighbour(site, x, g.dims, g.nd, k - 1);
+    const cplx<T>* __restrict__ e = pin + nb * K::NC;
+    const cplx<T>* __restrict__ yk = Ys + (long)k * K::NC * K::NC + rg * K::R;
+    cplx<T> ev[K::NQ], yv[K::NQ][K::R];
+#pragma unroll
+    for (int q = 0; q < K::NQ; ++q) {
+      const int col = cg + K::CPI * q;
+      ev[q] = e[col];
+#pragma unroll
+      for (int i = 0; i < K::R; ++i) yv[q][i] = yk[col * K::NC + i];
+    }
+#pragma unroll
+    for (int q = 0; q < K::NQ; ++q) {
+      const int col = cg + K::CPI * q;
+      cplx<T> v = ev[q];
+      if (DAG && col >= K::NC / 2) v = mk<T>(-v.x, -v.y);
+#pragma unroll
+      for (int i = 0; i < K::R; ++i) cfma<T>(acc[i], yv[q][i], v);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < K::R; ++i) {
+#pragma unroll
+    for (int o = K::LPC; o < 64; o <<= 1) {
+      acc[i].x += __shfl_xor(acc[i].x, o, 64);
+      acc[i].y += __shfl_xor(acc[i].y, o, 64);
+    }
+  }
+}
+
 template <typename T, int DAG, int EPI>
 __global__ __launch_bounds__(256) void coarse16_kernel(CoarseArgs<T> a) {
-  constexpr int NC = 16;
-  constexpr int R = (sizeof(T) == 4) ? 2 : 1;
-  constexpr int LPC = NC / R;
-  constexpr int CPI = 64 / LPC;
+  using K = C16<T>;
   const int rhs = blockIdx.y;
   if (skip_rhs(a.red.flags, rhs)) return;
-  const int nd = a.g.nd;
-  const int ndir = 2 * nd + 1;
-  const int ncols = ndir * NC;
   const long V = a.g.V;
-  const long ro = (long)rhs * V * NC;
+  const long ro = (long)rhs * V * K::NC;
   const cplx<T>* __restrict__ pin = a.in + ro;
   const int lane = threadIdx.x & 63;
-  const int cg = lane / LPC, rg = lane - cg * LPC;
+  const int cg = lane / K::LPC, rg = lane - cg * K::LPC;
   const int wave = threadIdx.x >> 6;
   double acc3[3] = {0.0, 0.0, 0.0};
   for (long site = (long)blockIdx.x * 4 + wave; site < V; site += (long)gridDim.x * 4) {
-    int x[4];
-    coords(site, a.g.dims, nd, x);
-    long nbs[9];
-    nbs[0] = site;
-    for (int k = 1; k < ndir; ++k) nbs[k] = neighbour(site, x, a.g.dims, nd, k - 1);
-    cplx<T> acc[R];
-#pragma unroll
-    for (int i = 0; i < R; ++i) acc[i] = mk<T>(0, 0);
-    const cplx<T>* __restrict__ Ys = a.Y + site * (long)ndir * NC * NC;
-    for (int gc = cg; gc < ncols; gc += CPI) {
-      const int k = gc / NC, col = gc - k * NC;
-      cplx<T> e = pin[nbs[k] * NC + col];
-      if (DAG && col >= NC / 2) e = mk<T>(-e.x, -e.y);
-      const cplx<T>* y = Ys + (long)gc * NC + rg * R;
-#pragma unroll
-      for (int i = 0; i < R; ++i) cfma<T>(acc[i], y[i], e);
-    }
-#pragma unroll
-    for (int i = 0; i < R; ++i) {
-#pragma unroll
-      for (int o = LPC; o < 64; o <<= 1) {
-        acc[i].x += __shfl_xor(acc[i].x, o, 64);
-        acc[i].y += __shfl_xor(acc[i].y, o, 64);
-      }
-    }
+    cplx<T> acc[K::R];
+    site_apply16<T, DAG>(a.Y, pin, site, a.g, cg, rg, acc);
     if (cg == 0) {
 #pragma unroll
-      for (int i = 0; i < R; ++i) {
-        const int row = rg * R + i;
+      for (int i = 0; i < K::R; ++i) {
+        const int row = rg * K::R + i;
         cplx<T> v = acc[i];
-        if (DAG && row >= NC / 2) v = mk<T>(-v.x, -v.y);
-        const long idx = ro + site * NC + row;
+        if (DAG && row >= K::NC / 2) v = mk<T>(-v.x, -v.y);
+        const long idx = ro + site * K::NC + row;
         const cplx<T> c = a.in[idx];
         if (EPI == EPI_RESID) v = csub<T>(a.b[idx], v);
         a.out[idx] = v;
@@ -165,6 +187,120 @@ __global__ __launch_bounds__(256) void coarse16_kernel(CoarseArgs<T> a) {
   } else if (EPI == EPI_NORM) {
     double a1[1] = {acc3[0]}, tot[1];
     if (grid_reduce<1>(a1, a.red.part, a.red.ticket, rhs, tot) && threadIdx.x == 0) a.red.scal[a.red.slot + rhs] = tot[0];
+  }
+}
+
+// GCR step, part 1 (N_c = 16): w = A z for every site, stored raw, with the
+// sums c_j = <W_j, w> (j < k), <w, w> and <w, r> accumulated on the way.  The
+// last block forms beta_j = c_j / <W_j, W_j>, the norm of the orthogonalised
+// direction <w', w'> = <w, w> - sum_j |c_j|^2 / <W_j, W_j> (the stored W_j
+// are mutually orthogonal) and alpha = <w', r> / <w', w'> with
+// <w', r> = <w, r> (the residual is orthogonal to every stored W_j).
+// Algebraically this is the GCR step; it needs one reduction instead of two.
+constexpr int G16_NQ = 2 * GCR_KMAX + 2;
+template <typename T>
+__global__ __launch_bounds__(256) void gcr16_apply_dots_kernel(CoarseArgs<T> a, const cplx<T>* __restrict__ r,
+                                                               const cplx<T>* __restrict__ Wb, long dstride, int k,
+                                                               int beta_slot, int ww_slot, int alpha_slot) {
+  using K = C16<T>;
+  __shared__ double sh[4 * K::LPC * G16_NQ];
+  __shared__ double blk_part[G16_NQ];
+  __shared__ int is_last;
+  const int rhs = blockIdx.y;
+  if (skip_rhs(a.red.flags, rhs)) return;
+  const long V = a.g.V;
+  const long ro = (long)rhs * V * K::NC;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int cg = lane / K::LPC, rg = lane - cg * K::LPC;
+  const int nq = 2 * k + 2;
+  for (int q = threadIdx.x; q < 4 * K::LPC * G16_NQ; q += blockDim.x) sh[q] = 0.0;
+  __syncthreads();
+  double* mine = sh + (wave * K::LPC + rg) * G16_NQ;  // this lane's accumulators (cg == 0 lanes)
+  for (long site = (long)blockIdx.x * 4 + wave; site < V; site += (long)gridDim.x * 4) {
+    cplx<T> acc[K::R];
+    site_apply16<T, 0>(a.Y, a.in + ro, site, a.g, cg, rg, acc);
+    if (cg == 0) {
+      double ww = 0.0, wrr = 0.0, wri = 0.0;
+#pragma unroll
+      for (int i = 0; i < K::R; ++i) {
+        const long idx = ro + site * K::NC + rg * K::R + i;
+        const cplx<T> w = acc[i];
+        a.out[idx] = w;
+        const cplx<T> rv = r[idx];
+        ww += (double)w.x * w.x + (double)w.y * w.y;
+        wrr += (double)w.x * rv.x + (double)w.y * rv.y;
+        wri += (double)w.x * rv.y - (double)w.y * rv.x;
+      }
+      mine[2 * k] += ww;
+      mine[2 * k + 1] += 0.0;
+      for (int j = 0; j < k; ++j) {
+        const cplx<T>* Wj = Wb + (long)j * dstride + ro + site * K::NC + rg * K::R;
+        double cr = 0.0, ci = 0.0;
+#pragma unroll
+        for (int i = 0; i < K::R; ++i) {
+          const cplx<T> q = Wj[i], w = acc[i];
+          cr += (double)q.x * w.x + (double)q.y * w.y;
+          ci += (double)q.x * w.y - (double)q.y * w.x;
+        }
+        mine[2 * j] += cr;
+        mine[2 * j + 1] += ci;
+      }
+      // <w, r> in the spare slots after the dots
+      mine[2 * k + 1] += wrr;
+      mine[G16_NQ - 1] += wri;
+    }
+  }
+  __syncthreads();
+  const int nblk = gridDim.x;
+  for (int q = threadIdx.x; q < G16_NQ; q += blockDim.x) {
+    if (q < nq || q == G16_NQ - 1) {
+      double s = 0.0;
+      for (int l = 0; l < 4 * K::LPC; ++l) s += sh[l * G16_NQ + q];
+      a.red.part[((long)rhs * G16_NQ + q) * nblk + blockIdx.x] = s;
+    }
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    is_last = (atomicAdd(&a.red.ticket[rhs], 1u) == (unsigned)(nblk - 1));
+  }
+  __syncthreads();
+  if (!is_last) return;
+  __threadfence();
+  // every thread sums a stride of the blocks for each quantity, then the
+  // waves are combined: loads stay independent and the order fixed
+  __shared__ double wsum[4][G16_NQ];
+  for (int q = 0; q < G16_NQ; ++q) {
+    if (!(q < nq || q == G16_NQ - 1)) continue;
+    double s = 0.0;
+    for (int bk = threadIdx.x; bk < nblk; bk += blockDim.x)
+      s += __hip_atomic_load(&a.red.part[((long)rhs * G16_NQ + q) * nblk + bk], __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) wsum[wave][q] = s;
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < G16_NQ; q += blockDim.x)
+    blk_part[q] = (q < nq || q == G16_NQ - 1) ? (wsum[0][q] + wsum[1][q]) + (wsum[2][q] + wsum[3][q]) : 0.0;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double* scal = a.red.scal;
+    double wwp = blk_part[2 * k];
+    for (int j = 0; j < k; ++j) {
+      const double wwj = scal[ww_slot + rhs * GCR_KMAX + j];
+      const double s = wwj > 0.0 ? 1.0 / wwj : 0.0;
+      const double cr = blk_part[2 * j], ci = blk_part[2 * j + 1];
+      scal[beta_slot + (rhs * GCR_KMAX + j) * 2] = cr * s;
+      scal[beta_slot + (rhs * GCR_KMAX + j) * 2 + 1] = ci * s;
+      wwp -= (cr * cr + ci * ci) * s;
+    }
+    scal[ww_slot + rhs * GCR_KMAX + k] = wwp;
+    const double s = wwp > 0.0 ? 1.0 / wwp : 0.0;
+    scal[alpha_slot + 2 * rhs] = blk_part[2 * k + 1] * s;
+    scal[alpha_slot + 2 * rhs + 1] = blk_part[G16_NQ - 1] * s;
+    __hip_atomic_store(&a.red.ticket[rhs], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -444,6 +580,20 @@ void launch_coarse(const CoarseArgs<T>& a, int dagger, int epi, hipStream_t st) 
 }
 template void launch_coarse<double>(const CoarseArgs<double>&, int, int, hipStream_t);
 template void launch_coarse<float>(const CoarseArgs<float>&, int, int, hipStream_t);
+
+template <typename T>
+void launch_gcr16_apply_dots(const CoarseArgs<T>& a, const cplx<T>* r, const cplx<T>* Wb, long dstride, int k,
+                             int beta_slot, int ww_slot, int alpha_slot, hipStream_t st) {
+  long nb = (a.g.V + 3) / 4;
+  if (nb > RED_MAX_BLOCKS) nb = RED_MAX_BLOCKS;
+  dim3 grid((unsigned)nb, (unsigned)a.nrhs);
+  hipLaunchKernelGGL((gcr16_apply_dots_kernel<T>), grid, dim3(256), 0, st, a, r, Wb, dstride, k, beta_slot, ww_slot,
+                     alpha_slot);
+}
+template void launch_gcr16_apply_dots<double>(const CoarseArgs<double>&, const double2*, const double2*, long, int,
+                                              int, int, int, hipStream_t);
+template void launch_gcr16_apply_dots<float>(const CoarseArgs<float>&, const float2*, const float2*, long, int, int,
+                                             int, int, hipStream_t);
 
 void launch_coarse_split(double2* out, const double2* in, const double2* Y, const CoarseGeom& g, const int* blk,
                          int nrhs, hipStream_t st) {

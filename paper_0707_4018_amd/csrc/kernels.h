@@ -75,6 +75,14 @@ struct CoarseArgs {
   RedArgs red;
 };
 template <typename T> void launch_coarse(const CoarseArgs<T>& a, int dagger, int epi, hipStream_t st);
+// fused GCR step for N_c = 16 levels: part 1 (apply + all sums) and part 2 (updates)
+template <typename T>
+void launch_gcr16_apply_dots(const CoarseArgs<T>& a, const cplx<T>* r, const cplx<T>* Wb, long dstride, int k,
+                             int beta_slot, int ww_slot, int alpha_slot, hipStream_t st);
+template <typename T>
+void launch_gcr_update2(cplx<T>* x, cplx<T>* r, const cplx<T>* zsrc, cplx<T>* Wb, cplx<T>* Zb, long dstride, int k,
+                        long n, int nrhs, RedArgs red, int beta_slot, int alpha_slot, int rr_slot, int bb_slot,
+                        double tol2, int* set_flags, hipStream_t st);
 void launch_coarse_split(double2* out, const double2* in, const double2* Y, const CoarseGeom& g,
                          const int* blk, int nrhs, hipStream_t st);
 void launch_coarse_massmat(double2* out, const double2* in, const double2* M, const CoarseGeom& g,

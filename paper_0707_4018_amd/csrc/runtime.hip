@@ -73,7 +73,7 @@ struct Scratch {
   double* host = nullptr;  // pinned mirror of a few scalars
   int nslots = 0;
   void init(int nscal, int nflags) {
-    part.ensure(sizeof(double) * (size_t)RHS_MAX * 2 * GCR_KMAX * RED_MAX_BLOCKS);
+    part.ensure(sizeof(double) * (size_t)RHS_MAX * (2 * GCR_KMAX + 4) * RED_MAX_BLOCKS);
     ticket.ensure(sizeof(unsigned) * RHS_MAX);
     HIPC(hipMemset(ticket.p, 0, sizeof(unsigned) * RHS_MAX));
     scal.ensure(sizeof(double) * nscal);
@@ -240,6 +240,7 @@ struct amg_solver {
   bool persistent = false;  // measured slower than the launch sequence (grid barriers are costly)
   int pcoarse_max_blocks = 64;
   bool pcoarse_coop = true;
+  bool fused_gcr = false;  // measured slower than the separate kernels at the 2d coarse sizes
   // kernel timing
   struct Prof {
     bool on = false;
@@ -442,6 +443,25 @@ void level_gcr(Solver& S, int l, int lstop, const cplx<T>* b, cplx<T>* x, int nr
       op_apply<T>(S, l, 0, EPI_RESID, x, r, b, nullptr, nrhs, S.sc.red(0, flags), st);
     cplx<T>* Wk = Wb + (long)k * dstride;
     cplx<T>* Zk = Zb + (long)k * dstride;
+    if (!L.fine && L.dof == 16 && S.fused_gcr) {
+      // two launches per step: apply + all sums, then the updates
+      const cplx<T>* z = r;
+      if (precond) {
+        vcycle<T>(S, l, lstop, r, Zk, nrhs, st);
+        z = Zk;
+      }
+      {
+        ProfScope ps(S, PK_COARSE, l, st);
+        CoarseArgs<T> ca;
+        ca.out = Wk; ca.in = z; ca.Y = L.Y<T>(); ca.g = L.cgeom(); ca.nrhs = nrhs; ca.red = S.sc.red(0, flags);
+        launch_gcr16_apply_dots<T>(ca, r, Wb, dstride, k, L.gs.beta, L.gs.ww, L.gs.alpha, st);
+        S.nC += 1;
+      }
+      launch_gcr_update2<T>(x, r, z, Wb, Zb, dstride, k, n, nrhs, S.sc.red(0, flags), L.gs.beta, L.gs.alpha, L.gs.rr,
+                            L.gs.bb, tol2, flags, st);
+      if ((it + 1) % check == 0 && it + 1 < maxiter && S.sc.all_flags(L.flag_off, nrhs, st)) break;
+      continue;
+    }
     if (precond) {
       vcycle<T>(S, l, lstop, r, Zk, nrhs, st);
       op_apply<T>(S, l, 0, EPI_PLAIN, Zk, Wk, nullptr, nullptr, nrhs, S.sc.red(0, flags), st);
@@ -674,6 +694,7 @@ Solver* new_solver(const amg_gauge* g, const amg_mg_params* p) {
   if (const char* e = std::getenv("AMG_PERSISTENT_COARSE")) S->persistent = std::atoi(e) != 0;
   if (const char* e = std::getenv("AMG_PCOARSE_BLOCKS")) S->pcoarse_max_blocks = std::max(1, std::min(128, std::atoi(e)));
   if (const char* e = std::getenv("AMG_PCOARSE_COOP")) S->pcoarse_coop = std::atoi(e) != 0;
+  if (const char* e = std::getenv("AMG_FUSED_GCR")) S->fused_gcr = std::atoi(e) != 0;
   return S;
 }
 
