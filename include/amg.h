@@ -188,6 +188,31 @@ amg_status amg_vcycle(amg_solver* s, const void* dev_b, void* dev_x, int nrhs, v
 amg_status amg_mr(amg_solver* s, int level, int nu, const void* dev_b, void* dev_x,
                   int nrhs, void* stream);
 
+/* ---- batched solves ---------------------------------------------------------
+ * Many independent solves (different gauge fields, lattice sizes, masses)
+ * advanced together: every stage of the outer iteration is one launch over
+ * all instances (instance = grid z), and the stages of each outer-iteration
+ * step are captured once into a HIP graph and replayed.  Right-hand sides
+ * that have converged are masked on the device. */
+typedef struct amg_batch amg_batch;
+
+/* Group n solvers (two-dimensional, same hierarchy depth, dof per level and
+ * solver parameters); instance i solves nrhs[i] right-hand sides.  With
+ * autotune != 0 the grid size of the reducing kernels is chosen by timing
+ * one batched outer step per candidate.  The solvers must outlive the batch
+ * and must not be used concurrently with it. */
+amg_status amg_batch_create(amg_solver* const* solvers, const int* nrhs, int n, int autotune, void* stream,
+                            amg_batch** out);
+/* Solve all instances to |chi - D psi| <= tol |chi| (true FP64 residual per
+ * right-hand side).  dev_chi[i], dev_psi[i]: nrhs[i] canonical complex128
+ * fields of instance i.  info: sum(nrhs) entries, instance-major.  Returns
+ * AMG_ERR_NOCONV if any right-hand side misses tol.  Synchronous. */
+amg_status amg_batch_solve(amg_batch* b, const void* const* dev_chi, void* const* dev_psi, double tol,
+                           int max_iter, amg_solve_info* info, void* stream);
+/* The autotuned reduction grid cap and the number of batched launches per outer step. */
+amg_status amg_batch_info(const amg_batch* b, int* red_cap, int* stages_per_iteration);
+amg_status amg_batch_destroy(amg_batch* b);
+
 /* ---- kernel timing (HIP events) -------------------------------------------
  * While enabled, every launch of kernel `kind` on level `level` made by this
  * solver is bracketed by a pair of HIP events on its stream.  amg_profile_read

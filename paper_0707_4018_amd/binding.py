@@ -78,6 +78,10 @@ _SIGS = {
     "amg_level_info": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                  C.POINTER(C.c_longlong)]),
     "amg_profile_enable": (C.c_int, [_P, C.c_int, C.c_int, C.c_int]),
+    "amg_batch_create": (C.c_int, [C.POINTER(_P), C.POINTER(C.c_int), C.c_int, C.c_int, _P, C.POINTER(_P)]),
+    "amg_batch_solve": (C.c_int, [_P, C.POINTER(_P), C.POINTER(_P), C.c_double, C.c_int, C.POINTER(_Info), _P]),
+    "amg_batch_info": (C.c_int, [_P, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "amg_batch_destroy": (C.c_int, [_P]),
     "amg_profile_read": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_longlong)]),
 }
 
@@ -345,6 +349,48 @@ class Solver:
         try:
             if getattr(self, "_h", None):
                 load_library().amg_solver_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+
+class Batch:
+    """Independent solvers advanced together, one launch per stage over all of them."""
+
+    def __init__(self, solvers, nrhs, autotune: bool = True):
+        lib = load_library()
+        self.solvers = list(solvers)
+        self.nrhs = [int(k) for k in nrhs]
+        n = len(self.solvers)
+        hs = (C.c_void_p * n)(*[s._h.value for s in self.solvers])
+        nr = (C.c_int * n)(*self.nrhs)
+        h = C.c_void_p()
+        _check(lib.amg_batch_create(hs, nr, n, int(autotune), _stream(), C.byref(h)), "amg_batch_create")
+        self._h = h
+
+    def info(self):
+        cap, stages = C.c_int(), C.c_int()
+        _check(load_library().amg_batch_info(self._h, C.byref(cap), C.byref(stages)), "amg_batch_info")
+        return {"red_block_cap": cap.value, "launches_per_outer_step": stages.value}
+
+    def solve(self, chis, tol: float = 1e-10, max_iter: int = 1000, raise_noconv: bool = True):
+        """chis[i]: (nrhs[i], V_i, 2, 1) complex128 on the GPU; returns (psis, infos per rhs)."""
+        lib = load_library()
+        xs = [c.contiguous() for c in chis]
+        psis = [torch.empty_like(c) for c in xs]
+        n = len(xs)
+        cp = (C.c_void_p * n)(*[_ptr(c).value for c in xs])
+        pp = (C.c_void_p * n)(*[_ptr(p).value for p in psis])
+        infos = (_Info * sum(self.nrhs))()
+        st = lib.amg_batch_solve(self._h, cp, pp, float(tol), int(max_iter), infos, _stream())
+        if st != 0 and (raise_noconv or st != 7):
+            _check(st, "amg_batch_solve")
+        return psis, [SolveInfo.from_c(i) for i in infos]
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None):
+                load_library().amg_batch_destroy(self._h)
                 self._h = None
         except Exception:
             pass

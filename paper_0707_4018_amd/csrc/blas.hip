@@ -5,6 +5,9 @@
 // consumers), so a solver step needs no host round trip.
 #include "common.h"
 #include "kernels.h"
+#include "dispatch.h"
+
+#include <cstring>
 
 namespace amg {
 namespace {
@@ -19,16 +22,38 @@ inline unsigned nblocks(long n, long cap) {
 #define GRID_STRIDE(i, n) for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (long)gridDim.x * blockDim.x)
 
 template <typename Tin, typename Tout>
-__global__ void convert_kernel(cplx<Tout>* __restrict__ out, const cplx<Tin>* __restrict__ in, Layout li, Layout lo) {
-  const int rhs = blockIdx.y;
-  const long n = li.per_rhs();
-  const long ro = (long)rhs * n;
+struct CvArgs {
+  cplx<Tout>* out;
+  const cplx<Tin>* in;
+  Layout li, lo;
+  int nrhs;
+};
+template <typename Tin, typename Tout>
+__global__ void convert_kernel(CvArgs<Tin, Tout> a0, const CvArgs<Tin, Tout>* batch) {
+  AMG_ARGS(CvArgs<Tin, Tout>)
+  const long n = a.li.per_rhs();
+  const long ro = (long)blockIdx.y * n;
   GRID_STRIDE(i, n) {
-    const int c = (int)(i / li.V);
-    const long s = i - (long)c * li.V;
-    const cplx<Tin> z = in[ro + li.off(s, c)];
-    out[ro + lo.off(s, c)] = mk<Tout>((Tout)z.x, (Tout)z.y);
+    const int c = (int)(i / a.li.V);
+    const long s = i - (long)c * a.li.V;
+    const cplx<Tin> z = a.in[ro + a.li.off(s, c)];
+    a.out[ro + a.lo.off(s, c)] = mk<Tout>((Tout)z.x, (Tout)z.y);
   }
+}
+
+// dst = src (src == nullptr: dst = 0), n complex per rhs
+template <typename T>
+struct FillArgs {
+  cplx<T>* dst;
+  const cplx<T>* src;
+  long n;
+  int nrhs;
+};
+template <typename T>
+__global__ void fill_kernel(FillArgs<T> a0, const FillArgs<T>* batch) {
+  AMG_ARGS(FillArgs<T>)
+  const long ro = (long)blockIdx.y * a.n;
+  GRID_STRIDE(i, a.n) a.dst[ro + i] = a.src ? a.src[ro + i] : mk<T>(0, 0);
 }
 
 __global__ void p_to_f32_kernel(float2* __restrict__ out, const double2* __restrict__ in, long n) {
@@ -45,163 +70,222 @@ __global__ void p_roundtrip_bf16_kernel(double2* __restrict__ P, long n) {
 }
 
 template <typename T>
-__global__ void mr_update_kernel(cplx<T>* __restrict__ x, cplx<T>* __restrict__ r_out, const cplx<T>* __restrict__ r_in,
-                                 const cplx<T>* __restrict__ p, const double* __restrict__ alpha, long n, int first,
-                                 int update_r, const int* flags) {
+struct MrArgs {
+  cplx<T>* x;
+  cplx<T>* r_out;
+  const cplx<T>* r_in;
+  const cplx<T>* p;
+  const double* alpha;
+  long n;
+  int first, update_r;
+  const int* flags;
+  int nrhs;
+};
+template <typename T>
+__global__ void mr_update_kernel(MrArgs<T> a0, const MrArgs<T>* batch) {
+  AMG_ARGS(MrArgs<T>)
   const int rhs = blockIdx.y;
-  if (skip_rhs(flags, rhs)) return;
-  const cplx<T> a = mk<T>((T)alpha[2 * rhs], (T)alpha[2 * rhs + 1]);
-  const long ro = (long)rhs * n;
-  GRID_STRIDE(i, n) {
-    const cplx<T> r = r_in[ro + i];
-    const cplx<T> ar = cmul<T>(a, r);
-    x[ro + i] = first ? ar : cadd<T>(x[ro + i], ar);
-    if (update_r) r_out[ro + i] = csub<T>(r, cmul<T>(a, p[ro + i]));
+  if (skip_rhs(a.flags, rhs)) return;
+  const cplx<T> al = mk<T>((T)a.alpha[2 * rhs], (T)a.alpha[2 * rhs + 1]);
+  const long ro = (long)rhs * a.n;
+  GRID_STRIDE(i, a.n) {
+    const cplx<T> r = a.r_in[ro + i];
+    const cplx<T> ar = cmul<T>(al, r);
+    a.x[ro + i] = a.first ? ar : cadd<T>(a.x[ro + i], ar);
+    if (a.update_r) a.r_out[ro + i] = csub<T>(r, cmul<T>(al, a.p[ro + i]));
   }
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void norm2_kernel(const cplx<T>* __restrict__ v, long n, RedArgs red) {
+struct NormArgs {
+  const cplx<T>* v;
+  long n;
+  RedArgs red;
+  int nrhs;
+};
+template <typename T>
+__global__ __launch_bounds__(256) void norm2_kernel(NormArgs<T> a0, const NormArgs<T>* batch) {
+  AMG_ARGS(NormArgs<T>)
   const int rhs = blockIdx.y;
-  if (skip_rhs(red.flags, rhs)) return;
-  const long ro = (long)rhs * n;
+  if (skip_rhs(a.red.flags, rhs)) return;
+  const long ro = (long)rhs * a.n;
   double acc[1] = {0.0};
-  GRID_STRIDE(i, n) { const cplx<T> z = v[ro + i]; acc[0] += (double)z.x * z.x + (double)z.y * z.y; }
+  GRID_STRIDE(i, a.n) { const cplx<T> z = a.v[ro + i]; acc[0] += (double)z.x * z.x + (double)z.y * z.y; }
   double tot[1];
-  if (grid_reduce<1>(acc, red.part, red.ticket, rhs, tot) && threadIdx.x == 0) red.scal[red.slot + rhs] = tot[0];
+  if (grid_reduce<1>(acc, a.red.part, a.red.ticket, rhs, tot) && threadIdx.x == 0) a.red.scal[a.red.slot + rhs] = tot[0];
 }
+
+// arguments shared by the GCR step kernels; directions W_j = Wb + j * dstride
+template <typename T>
+struct GcrArgs {
+  cplx<T>* x;
+  cplx<T>* r;
+  cplx<T>* w;        // current direction (W_k)
+  cplx<T>* z;        // current preconditioned direction (Z_k)
+  const cplx<T>* zsrc;
+  cplx<T>* Wb;
+  cplx<T>* Zb;
+  long dstride, n;
+  int k;
+  RedArgs red;
+  int beta_slot, ww_slot, alpha_slot, rr_slot, bb_slot;
+  double tol2;
+  int* set_flags;
+  int nrhs;
+};
 
 // beta_j = <W_j, w> / <W_j, W_j>, j < k  (classical Gram-Schmidt coefficients)
 template <typename T, int KM>
-__global__ __launch_bounds__(256) void gcr_mdot_kernel(const cplx<T>* __restrict__ Wb, long dstride,
-                                                       const cplx<T>* __restrict__ w, int k, long n, RedArgs red,
-                                                       int beta_slot, int ww_slot) {
+__global__ __launch_bounds__(256) void gcr_mdot_kernel(GcrArgs<T> a0, const GcrArgs<T>* batch) {
+  AMG_ARGS(GcrArgs<T>)
   const int rhs = blockIdx.y;
-  if (skip_rhs(red.flags, rhs)) return;
-  const long ro = (long)rhs * n;
+  if (skip_rhs(a.red.flags, rhs)) return;
+  const long ro = (long)rhs * a.n;
+  const int k = a.k;
   double acc[2 * KM];
 #pragma unroll
   for (int j = 0; j < 2 * KM; ++j) acc[j] = 0.0;
-  GRID_STRIDE(i, n) {
-    const cplx<T> wi = w[ro + i];
+  GRID_STRIDE(i, a.n) {
+    const cplx<T> wi = a.w[ro + i];
 #pragma unroll
     for (int j = 0; j < KM; ++j) {
       if (j < k) {
-        const cplx<T> q = Wb[(long)j * dstride + ro + i];
+        const cplx<T> q = a.Wb[(long)j * a.dstride + ro + i];
         acc[2 * j] += (double)q.x * wi.x + (double)q.y * wi.y;
         acc[2 * j + 1] += (double)q.x * wi.y - (double)q.y * wi.x;
       }
     }
   }
   double tot[2 * KM];
-  if (grid_reduce<2 * KM>(acc, red.part, red.ticket, rhs, tot) && threadIdx.x == 0) {
+  if (grid_reduce<2 * KM>(acc, a.red.part, a.red.ticket, rhs, tot) && threadIdx.x == 0) {
     for (int j = 0; j < k; ++j) {
-      const double ww = red.scal[ww_slot + rhs * GCR_KMAX + j];
+      const double ww = a.red.scal[a.ww_slot + rhs * GCR_KMAX + j];
       const double s = ww > 0.0 ? 1.0 / ww : 0.0;
-      red.scal[beta_slot + (rhs * GCR_KMAX + j) * 2] = tot[2 * j] * s;
-      red.scal[beta_slot + (rhs * GCR_KMAX + j) * 2 + 1] = tot[2 * j + 1] * s;
+      a.red.scal[a.beta_slot + (rhs * GCR_KMAX + j) * 2] = tot[2 * j] * s;
+      a.red.scal[a.beta_slot + (rhs * GCR_KMAX + j) * 2 + 1] = tot[2 * j + 1] * s;
     }
   }
 }
 
 // w -= sum_j beta_j W_j ; z -= sum_j beta_j Z_j ; then <w,w> and alpha = <w,r>/<w,w>
 template <typename T>
-__global__ __launch_bounds__(256) void gcr_maxpy_kernel(cplx<T>* __restrict__ w, cplx<T>* __restrict__ z,
-                                                        const cplx<T>* __restrict__ Wb, const cplx<T>* __restrict__ Zb,
-                                                        long dstride, const cplx<T>* __restrict__ r, int k, long n,
-                                                        RedArgs red, int beta_slot, int ww_slot, int alpha_slot) {
+__global__ __launch_bounds__(256) void gcr_maxpy_kernel(GcrArgs<T> a0, const GcrArgs<T>* batch) {
+  AMG_ARGS(GcrArgs<T>)
   const int rhs = blockIdx.y;
-  if (skip_rhs(red.flags, rhs)) return;
-  const long ro = (long)rhs * n;
-  const double* beta = red.scal + beta_slot + (long)rhs * GCR_KMAX * 2;
+  if (skip_rhs(a.red.flags, rhs)) return;
+  const long ro = (long)rhs * a.n;
+  const int k = a.k;
+  const double* beta = a.red.scal + a.beta_slot + (long)rhs * GCR_KMAX * 2;
   double acc[3] = {0.0, 0.0, 0.0};
-  GRID_STRIDE(i, n) {
-    cplx<T> wi = w[ro + i];
-    cplx<T> zi = z[ro + i];
+  GRID_STRIDE(i, a.n) {
+    cplx<T> wi = a.w[ro + i];
+    cplx<T> zi = a.z[ro + i];
     for (int j = 0; j < k; ++j) {
       const cplx<T> b = mk<T>((T)beta[2 * j], (T)beta[2 * j + 1]);
-      wi = csub<T>(wi, cmul<T>(b, Wb[(long)j * dstride + ro + i]));
-      zi = csub<T>(zi, cmul<T>(b, Zb[(long)j * dstride + ro + i]));
+      wi = csub<T>(wi, cmul<T>(b, a.Wb[(long)j * a.dstride + ro + i]));
+      zi = csub<T>(zi, cmul<T>(b, a.Zb[(long)j * a.dstride + ro + i]));
     }
-    if (k > 0) { w[ro + i] = wi; z[ro + i] = zi; }
-    const cplx<T> ri = r[ro + i];
+    if (k > 0) { a.w[ro + i] = wi; a.z[ro + i] = zi; }
+    const cplx<T> ri = a.r[ro + i];
     acc[0] += (double)wi.x * wi.x + (double)wi.y * wi.y;
     acc[1] += (double)wi.x * ri.x + (double)wi.y * ri.y;
     acc[2] += (double)wi.x * ri.y - (double)wi.y * ri.x;
   }
   double tot[3];
-  if (grid_reduce<3>(acc, red.part, red.ticket, rhs, tot) && threadIdx.x == 0) {
+  if (grid_reduce<3>(acc, a.red.part, a.red.ticket, rhs, tot) && threadIdx.x == 0) {
     const double ww = tot[0];
-    red.scal[ww_slot + rhs * GCR_KMAX + k] = ww;
+    a.red.scal[a.ww_slot + rhs * GCR_KMAX + k] = ww;
     const double s = ww > 0.0 ? 1.0 / ww : 0.0;
-    red.scal[alpha_slot + 2 * rhs] = tot[1] * s;
-    red.scal[alpha_slot + 2 * rhs + 1] = tot[2] * s;
+    a.red.scal[a.alpha_slot + 2 * rhs] = tot[1] * s;
+    a.red.scal[a.alpha_slot + 2 * rhs + 1] = tot[2] * s;
   }
 }
 
 // x += alpha z ; r -= alpha w ; rr = <r,r> ; optionally flag rr <= tol2 * bb
 template <typename T>
-__global__ __launch_bounds__(256) void gcr_update_kernel(cplx<T>* __restrict__ x, cplx<T>* __restrict__ r,
-                                                         const cplx<T>* __restrict__ z, const cplx<T>* __restrict__ w,
-                                                         long n, RedArgs red, int alpha_slot, int rr_slot, int bb_slot,
-                                                         double tol2, int* set_flags) {
+__global__ __launch_bounds__(256) void gcr_update_kernel(GcrArgs<T> a0, const GcrArgs<T>* batch) {
+  AMG_ARGS(GcrArgs<T>)
   const int rhs = blockIdx.y;
-  if (skip_rhs(red.flags, rhs)) return;
-  const long ro = (long)rhs * n;
-  const cplx<T> a = mk<T>((T)red.scal[alpha_slot + 2 * rhs], (T)red.scal[alpha_slot + 2 * rhs + 1]);
+  if (skip_rhs(a.red.flags, rhs)) return;
+  const long ro = (long)rhs * a.n;
+  const cplx<T> al = mk<T>((T)a.red.scal[a.alpha_slot + 2 * rhs], (T)a.red.scal[a.alpha_slot + 2 * rhs + 1]);
   double acc[1] = {0.0};
-  GRID_STRIDE(i, n) {
-    x[ro + i] = cadd<T>(x[ro + i], cmul<T>(a, z[ro + i]));
-    const cplx<T> ri = csub<T>(r[ro + i], cmul<T>(a, w[ro + i]));
-    r[ro + i] = ri;
+  GRID_STRIDE(i, a.n) {
+    a.x[ro + i] = cadd<T>(a.x[ro + i], cmul<T>(al, a.z[ro + i]));
+    const cplx<T> ri = csub<T>(a.r[ro + i], cmul<T>(al, a.w[ro + i]));
+    a.r[ro + i] = ri;
     acc[0] += (double)ri.x * ri.x + (double)ri.y * ri.y;
   }
   double tot[1];
-  if (grid_reduce<1>(acc, red.part, red.ticket, rhs, tot) && threadIdx.x == 0) {
-    red.scal[rr_slot + rhs] = tot[0];
-    if (set_flags) set_flags[rhs] = (tot[0] <= tol2 * red.scal[bb_slot + rhs]) ? 1 : 0;
+  if (grid_reduce<1>(acc, a.red.part, a.red.ticket, rhs, tot) && threadIdx.x == 0) {
+    a.red.scal[a.rr_slot + rhs] = tot[0];
+    if (a.set_flags) a.set_flags[rhs] = (tot[0] <= a.tol2 * a.red.scal[a.bb_slot + rhs]) ? 1 : 0;
   }
 }
 
-// GCR step, part 2: w' = w - sum_j beta_j W_j, z' = zsrc - sum_j beta_j Z_j
-// (stored as direction k), x += alpha z', r -= alpha w', <r, r> and flags.
+// GCR step, part 2 of the fused variant: w' = w - sum_j beta_j W_j,
+// z' = zsrc - sum_j beta_j Z_j (stored as direction k), x += alpha z',
+// r -= alpha w', <r, r> and flags.
 template <typename T>
-__global__ __launch_bounds__(256) void gcr_update2_kernel(cplx<T>* __restrict__ x, cplx<T>* __restrict__ r,
-                                                          const cplx<T>* zsrc, cplx<T>* Wb, cplx<T>* Zb, long dstride,
-                                                          int k, long n, RedArgs red, int beta_slot, int alpha_slot,
-                                                          int rr_slot, int bb_slot, double tol2, int* set_flags) {
+__global__ __launch_bounds__(256) void gcr_update2_kernel(GcrArgs<T> a0, const GcrArgs<T>* batch) {
+  AMG_ARGS(GcrArgs<T>)
   const int rhs = blockIdx.y;
-  if (skip_rhs(red.flags, rhs)) return;
-  const long ro = (long)rhs * n;
-  const double* beta = red.scal + beta_slot + (long)rhs * GCR_KMAX * 2;
-  const cplx<T> al = mk<T>((T)red.scal[alpha_slot + 2 * rhs], (T)red.scal[alpha_slot + 2 * rhs + 1]);
-  cplx<T>* Wk = Wb + (long)k * dstride + ro;
-  cplx<T>* Zk = Zb + (long)k * dstride + ro;
+  if (skip_rhs(a.red.flags, rhs)) return;
+  const long ro = (long)rhs * a.n;
+  const int k = a.k;
+  const double* beta = a.red.scal + a.beta_slot + (long)rhs * GCR_KMAX * 2;
+  const cplx<T> al = mk<T>((T)a.red.scal[a.alpha_slot + 2 * rhs], (T)a.red.scal[a.alpha_slot + 2 * rhs + 1]);
+  cplx<T>* Wk = a.Wb + (long)k * a.dstride + ro;
+  cplx<T>* Zk = a.Zb + (long)k * a.dstride + ro;
   double acc[1] = {0.0};
-  GRID_STRIDE(i, n) {
-    cplx<T> wi = Wk[i], zi = zsrc[ro + i];
+  GRID_STRIDE(i, a.n) {
+    cplx<T> wi = Wk[i], zi = a.zsrc[ro + i];
     for (int j = 0; j < k; ++j) {
       const cplx<T> b = mk<T>((T)beta[2 * j], (T)beta[2 * j + 1]);
-      wi = csub<T>(wi, cmul<T>(b, Wb[(long)j * dstride + ro + i]));
-      zi = csub<T>(zi, cmul<T>(b, Zb[(long)j * dstride + ro + i]));
+      wi = csub<T>(wi, cmul<T>(b, a.Wb[(long)j * a.dstride + ro + i]));
+      zi = csub<T>(zi, cmul<T>(b, a.Zb[(long)j * a.dstride + ro + i]));
     }
     Wk[i] = wi;
     Zk[i] = zi;
-    x[ro + i] = cadd<T>(x[ro + i], cmul<T>(al, zi));
-    const cplx<T> ri = csub<T>(r[ro + i], cmul<T>(al, wi));
-    r[ro + i] = ri;
+    a.x[ro + i] = cadd<T>(a.x[ro + i], cmul<T>(al, zi));
+    const cplx<T> ri = csub<T>(a.r[ro + i], cmul<T>(al, wi));
+    a.r[ro + i] = ri;
     acc[0] += (double)ri.x * ri.x + (double)ri.y * ri.y;
   }
   double tot[1];
-  if (grid_reduce<1>(acc, red.part, red.ticket, rhs, tot) && threadIdx.x == 0) {
-    red.scal[rr_slot + rhs] = tot[0];
-    if (set_flags) set_flags[rhs] = (tot[0] <= tol2 * red.scal[bb_slot + rhs]) ? 1 : 0;
+  if (grid_reduce<1>(acc, a.red.part, a.red.ticket, rhs, tot) && threadIdx.x == 0) {
+    a.red.scal[a.rr_slot + rhs] = tot[0];
+    if (a.set_flags) a.set_flags[rhs] = (tot[0] <= a.tol2 * a.red.scal[a.bb_slot + rhs]) ? 1 : 0;
   }
 }
 
-__global__ void set_flags_kernel(int* flags, const double* scal, int rr_slot, int bb_slot, double tol2, int nrhs) {
+// flags[rhs] = inherit[rhs] || scal[rr] <= tol2 * scal[bb]   (one block, thread per rhs)
+struct FlagArgs {
+  int* flags;
+  const int* inherit;
+  const double* scal;
+  int rr_slot, bb_slot;
+  double tol2;
+  int nrhs;
+};
+__global__ void set_flags_kernel(FlagArgs a0, const FlagArgs* batch) {
+  const FlagArgs& a = (batch != nullptr) ? batch[blockIdx.z] : a0;
   const int rhs = threadIdx.x;
-  if (rhs < nrhs) flags[rhs] = (scal[rr_slot + rhs] <= tol2 * scal[bb_slot + rhs]) ? 1 : 0;
+  if (rhs < a.nrhs)
+    a.flags[rhs] = ((a.inherit && a.inherit[rhs]) || a.scal[a.rr_slot + rhs] <= a.tol2 * a.scal[a.bb_slot + rhs]) ? 1 : 0;
+}
+
+// out[rhs] = scal[slot + rhs] (collects scalars of many instances in one array)
+struct GatherArgs {
+  double* out;
+  const double* scal;
+  int slot;
+  int nrhs;
+};
+__global__ void gather_kernel(GatherArgs a0, const GatherArgs* batch) {
+  const GatherArgs& a = (batch != nullptr) ? batch[blockIdx.z] : a0;
+  const int rhs = threadIdx.x;
+  if (rhs < a.nrhs) a.out[rhs] = a.scal[a.slot + rhs];
 }
 
 __global__ __launch_bounds__(256) void cg_update_kernel(double2* __restrict__ x, double2* __restrict__ r,
@@ -242,14 +326,21 @@ __global__ void cg_pupdate_kernel(double2* __restrict__ p, const double2* __rest
 
 template <typename Tin, typename Tout>
 void launch_convert(cplx<Tout>* out, const cplx<Tin>* in, long V, int dof, int Win, int Wout, int nrhs, hipStream_t st) {
-  Layout li{V, dof, Win}, lo{V, dof, Wout};
-  dim3 grid(nblocks(V * dof, 1L << 20), (unsigned)nrhs);
-  hipLaunchKernelGGL((convert_kernel<Tin, Tout>), grid, dim3(256), 0, st, out, in, li, lo);
+  CvArgs<Tin, Tout> a{out, in, Layout{V, dof, Win}, Layout{V, dof, Wout}, nrhs};
+  dispatch(convert_kernel<Tin, Tout>, a, dim3(nblocks(V * dof, 1L << 20), (unsigned)nrhs), dim3(256), st);
 }
 template void launch_convert<double, double>(double2*, const double2*, long, int, int, int, int, hipStream_t);
 template void launch_convert<double, float>(float2*, const double2*, long, int, int, int, int, hipStream_t);
 template void launch_convert<float, double>(double2*, const float2*, long, int, int, int, int, hipStream_t);
 template void launch_convert<float, float>(float2*, const float2*, long, int, int, int, int, hipStream_t);
+
+template <typename T>
+void launch_fill(cplx<T>* dst, const cplx<T>* src, long n, int nrhs, hipStream_t st) {
+  FillArgs<T> a{dst, src, n, nrhs};
+  dispatch(fill_kernel<T>, a, dim3(nblocks(n, 1L << 20), (unsigned)nrhs), dim3(256), st);
+}
+template void launch_fill<double>(double2*, const double2*, long, int, hipStream_t);
+template void launch_fill<float>(float2*, const float2*, long, int, hipStream_t);
 
 void launch_p_convert(void* out, int pkind, const double2* in, long n, hipStream_t st) {
   if (pkind == P_F32)
@@ -265,33 +356,42 @@ void launch_p_roundtrip_bf16(double2* P, long n, hipStream_t st) {
 template <typename T>
 void launch_mr_update(cplx<T>* x, cplx<T>* r_out, const cplx<T>* r_in, const cplx<T>* p, const double* alpha, long n,
                       int nrhs, int first, int update_r, const int* flags, hipStream_t st) {
-  dim3 grid(nblocks(n, 1L << 20), (unsigned)nrhs);
-  hipLaunchKernelGGL((mr_update_kernel<T>), grid, dim3(256), 0, st, x, r_out, r_in, p, alpha, n, first, update_r, flags);
+  MrArgs<T> a{x, r_out, r_in, p, alpha, n, first, update_r, flags, nrhs};
+  dispatch(mr_update_kernel<T>, a, dim3(nblocks(n, 1L << 20), (unsigned)nrhs), dim3(256), st);
 }
 template void launch_mr_update<double>(double2*, double2*, const double2*, const double2*, const double*, long, int, int, int, const int*, hipStream_t);
 template void launch_mr_update<float>(float2*, float2*, const float2*, const float2*, const double*, long, int, int, int, const int*, hipStream_t);
 
 template <typename T>
 void launch_norm2(const cplx<T>* v, long n, int nrhs, RedArgs red, hipStream_t st) {
-  dim3 grid(nblocks(n, RED_MAX_BLOCKS), (unsigned)nrhs);
-  hipLaunchKernelGGL((norm2_kernel<T>), grid, dim3(256), 0, st, v, n, red);
+  NormArgs<T> a{v, n, red, nrhs};
+  dispatch(norm2_kernel<T>, a, dim3(nblocks(n, red_block_cap()), (unsigned)nrhs), dim3(256), st);
 }
 template void launch_norm2<double>(const double2*, long, int, RedArgs, hipStream_t);
 template void launch_norm2<float>(const float2*, long, int, RedArgs, hipStream_t);
 
 template <typename T>
+static GcrArgs<T> gcr_args(long n, int nrhs, RedArgs red) {
+  GcrArgs<T> a;
+  std::memset(&a, 0, sizeof(a));
+  a.n = n;
+  a.nrhs = nrhs;
+  a.red = red;
+  return a;
+}
+
+template <typename T>
 void launch_gcr_mdot(const cplx<T>* Wb, long dstride, const cplx<T>* w, int k, long n, int nrhs, RedArgs red,
                      int beta_slot, int ww_slot, hipStream_t st) {
   if (k <= 0) return;
-  dim3 grid(nblocks(n, RED_MAX_BLOCKS), (unsigned)nrhs);
-  if (k <= 4)
-    hipLaunchKernelGGL((gcr_mdot_kernel<T, 4>), grid, dim3(256), 0, st, Wb, dstride, w, k, n, red, beta_slot, ww_slot);
-  else if (k <= 8)
-    hipLaunchKernelGGL((gcr_mdot_kernel<T, 8>), grid, dim3(256), 0, st, Wb, dstride, w, k, n, red, beta_slot, ww_slot);
-  else if (k <= 16)
-    hipLaunchKernelGGL((gcr_mdot_kernel<T, 16>), grid, dim3(256), 0, st, Wb, dstride, w, k, n, red, beta_slot, ww_slot);
-  else
-    hipLaunchKernelGGL((gcr_mdot_kernel<T, 32>), grid, dim3(256), 0, st, Wb, dstride, w, k, n, red, beta_slot, ww_slot);
+  GcrArgs<T> a = gcr_args<T>(n, nrhs, red);
+  a.Wb = const_cast<cplx<T>*>(Wb); a.dstride = dstride; a.w = const_cast<cplx<T>*>(w); a.k = k;
+  a.beta_slot = beta_slot; a.ww_slot = ww_slot;
+  dim3 grid(nblocks(n, red_block_cap()), (unsigned)nrhs);
+  if (k <= 4) dispatch(gcr_mdot_kernel<T, 4>, a, grid, dim3(256), st);
+  else if (k <= 8) dispatch(gcr_mdot_kernel<T, 8>, a, grid, dim3(256), st);
+  else if (k <= 16) dispatch(gcr_mdot_kernel<T, 16>, a, grid, dim3(256), st);
+  else dispatch(gcr_mdot_kernel<T, 32>, a, grid, dim3(256), st);
 }
 template void launch_gcr_mdot<double>(const double2*, long, const double2*, int, long, int, RedArgs, int, int, hipStream_t);
 template void launch_gcr_mdot<float>(const float2*, long, const float2*, int, long, int, RedArgs, int, int, hipStream_t);
@@ -299,9 +399,11 @@ template void launch_gcr_mdot<float>(const float2*, long, const float2*, int, lo
 template <typename T>
 void launch_gcr_maxpy(cplx<T>* w, cplx<T>* z, const cplx<T>* Wb, const cplx<T>* Zb, long dstride, const cplx<T>* r, int k,
                       long n, int nrhs, RedArgs red, int beta_slot, int ww_slot, int alpha_slot, hipStream_t st) {
-  dim3 grid(nblocks(n, RED_MAX_BLOCKS), (unsigned)nrhs);
-  hipLaunchKernelGGL((gcr_maxpy_kernel<T>), grid, dim3(256), 0, st, w, z, Wb, Zb, dstride, r, k, n, red, beta_slot,
-                     ww_slot, alpha_slot);
+  GcrArgs<T> a = gcr_args<T>(n, nrhs, red);
+  a.w = w; a.z = z; a.Wb = const_cast<cplx<T>*>(Wb); a.Zb = const_cast<cplx<T>*>(Zb); a.dstride = dstride;
+  a.r = const_cast<cplx<T>*>(r); a.k = k;
+  a.beta_slot = beta_slot; a.ww_slot = ww_slot; a.alpha_slot = alpha_slot;
+  dispatch(gcr_maxpy_kernel<T>, a, dim3(nblocks(n, red_block_cap()), (unsigned)nrhs), dim3(256), st);
 }
 template void launch_gcr_maxpy<double>(double2*, double2*, const double2*, const double2*, long, const double2*, int, long, int, RedArgs, int, int, int, hipStream_t);
 template void launch_gcr_maxpy<float>(float2*, float2*, const float2*, const float2*, long, const float2*, int, long, int, RedArgs, int, int, int, hipStream_t);
@@ -309,9 +411,10 @@ template void launch_gcr_maxpy<float>(float2*, float2*, const float2*, const flo
 template <typename T>
 void launch_gcr_update(cplx<T>* x, cplx<T>* r, const cplx<T>* z, const cplx<T>* w, long n, int nrhs, RedArgs red,
                        int alpha_slot, int rr_slot, int bb_slot, double tol2, int* set_flags, hipStream_t st) {
-  dim3 grid(nblocks(n, RED_MAX_BLOCKS), (unsigned)nrhs);
-  hipLaunchKernelGGL((gcr_update_kernel<T>), grid, dim3(256), 0, st, x, r, z, w, n, red, alpha_slot, rr_slot, bb_slot,
-                     tol2, set_flags);
+  GcrArgs<T> a = gcr_args<T>(n, nrhs, red);
+  a.x = x; a.r = r; a.z = const_cast<cplx<T>*>(z); a.w = const_cast<cplx<T>*>(w);
+  a.alpha_slot = alpha_slot; a.rr_slot = rr_slot; a.bb_slot = bb_slot; a.tol2 = tol2; a.set_flags = set_flags;
+  dispatch(gcr_update_kernel<T>, a, dim3(nblocks(n, red_block_cap()), (unsigned)nrhs), dim3(256), st);
 }
 template void launch_gcr_update<double>(double2*, double2*, const double2*, const double2*, long, int, RedArgs, int, int, int, double, int*, hipStream_t);
 template void launch_gcr_update<float>(float2*, float2*, const float2*, const float2*, long, int, RedArgs, int, int, int, double, int*, hipStream_t);
@@ -320,25 +423,31 @@ template <typename T>
 void launch_gcr_update2(cplx<T>* x, cplx<T>* r, const cplx<T>* zsrc, cplx<T>* Wb, cplx<T>* Zb, long dstride, int k,
                         long n, int nrhs, RedArgs red, int beta_slot, int alpha_slot, int rr_slot, int bb_slot,
                         double tol2, int* set_flags, hipStream_t st) {
-  dim3 grid(nblocks(n, RED_MAX_BLOCKS), (unsigned)nrhs);
-  hipLaunchKernelGGL((gcr_update2_kernel<T>), grid, dim3(256), 0, st, x, r, zsrc, Wb, Zb, dstride, k, n, red,
-                     beta_slot, alpha_slot, rr_slot, bb_slot, tol2, set_flags);
+  GcrArgs<T> a = gcr_args<T>(n, nrhs, red);
+  a.x = x; a.r = r; a.zsrc = zsrc; a.Wb = Wb; a.Zb = Zb; a.dstride = dstride; a.k = k;
+  a.beta_slot = beta_slot; a.alpha_slot = alpha_slot; a.rr_slot = rr_slot; a.bb_slot = bb_slot; a.tol2 = tol2;
+  a.set_flags = set_flags;
+  dispatch(gcr_update2_kernel<T>, a, dim3(nblocks(n, red_block_cap()), (unsigned)nrhs), dim3(256), st);
 }
 template void launch_gcr_update2<double>(double2*, double2*, const double2*, double2*, double2*, long, int, long, int,
                                          RedArgs, int, int, int, int, double, int*, hipStream_t);
 template void launch_gcr_update2<float>(float2*, float2*, const float2*, float2*, float2*, long, int, long, int,
                                         RedArgs, int, int, int, int, double, int*, hipStream_t);
 
-template <typename T>
-void launch_set_flags(int* flags, const double* scal, int rr_slot, int bb_slot, double tol2, int nrhs, hipStream_t st) {
-  hipLaunchKernelGGL(set_flags_kernel, dim3(1), dim3(64), 0, st, flags, scal, rr_slot, bb_slot, tol2, nrhs);
+void launch_set_flags(int* flags, const int* inherit, const double* scal, int rr_slot, int bb_slot, double tol2,
+                      int nrhs, hipStream_t st) {
+  FlagArgs a{flags, inherit, scal, rr_slot, bb_slot, tol2, nrhs};
+  dispatch(set_flags_kernel, a, dim3(1), dim3(64), st);
 }
-template void launch_set_flags<double>(int*, const double*, int, int, double, int, hipStream_t);
-template void launch_set_flags<float>(int*, const double*, int, int, double, int, hipStream_t);
+
+void launch_gather(double* out, const double* scal, int slot, int nrhs, hipStream_t st) {
+  GatherArgs a{out, scal, slot, nrhs};
+  dispatch(gather_kernel, a, dim3(1), dim3(64), st);
+}
 
 void launch_cg_update(double2* x, double2* r, const double2* p, const double2* q, long n, int nrhs, RedArgs red,
                       int gamma_slot, int qq_slot, int rr_slot, hipStream_t st) {
-  dim3 grid(nblocks(n, RED_MAX_BLOCKS), (unsigned)nrhs);
+  dim3 grid(nblocks(n, red_block_cap()), (unsigned)nrhs);
   hipLaunchKernelGGL(cg_update_kernel, grid, dim3(256), 0, st, x, r, p, q, n, red, gamma_slot, qq_slot, rr_slot);
 }
 

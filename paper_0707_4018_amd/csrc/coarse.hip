@@ -11,6 +11,7 @@
 // because P commutes with gamma_5.
 #include "common.h"
 #include "kernels.h"
+#include "dispatch.h"
 
 namespace amg {
 namespace {
@@ -31,7 +32,8 @@ __device__ __forceinline__ long neighbour(long site, const int* x, const int* di
 }
 
 template <typename T, int NC, int DAG, int EPI>
-__global__ __launch_bounds__(256) void coarse_kernel(CoarseArgs<T> a) {
+__global__ __launch_bounds__(256) void coarse_kernel(CoarseArgs<T> a0, const CoarseArgs<T>* batch) {
+  AMG_ARGS(CoarseArgs<T>)
   const int rhs = blockIdx.y;
   if (skip_rhs(a.red.flags, rhs)) return;
   const int nc = NC > 0 ? NC : a.g.nc;
@@ -146,7 +148,8 @@ __device__ __forceinline__ void site_apply16(const cplx<T>* __restrict__ Y, cons
 }
 
 template <typename T, int DAG, int EPI>
-__global__ __launch_bounds__(256) void coarse16_kernel(CoarseArgs<T> a) {
+__global__ __launch_bounds__(256) void coarse16_kernel(CoarseArgs<T> a0, const CoarseArgs<T>* batch) {
+  AMG_ARGS(CoarseArgs<T>)
   using K = C16<T>;
   const int rhs = blockIdx.y;
   if (skip_rhs(a.red.flags, rhs)) return;
@@ -199,9 +202,23 @@ __global__ __launch_bounds__(256) void coarse16_kernel(CoarseArgs<T> a) {
 // Algebraically this is the GCR step; it needs one reduction instead of two.
 constexpr int G16_NQ = 2 * GCR_KMAX + 2;
 template <typename T>
-__global__ __launch_bounds__(256) void gcr16_apply_dots_kernel(CoarseArgs<T> a, const cplx<T>* __restrict__ r,
-                                                               const cplx<T>* __restrict__ Wb, long dstride, int k,
-                                                               int beta_slot, int ww_slot, int alpha_slot) {
+struct G16Args {
+  CoarseArgs<T> c;
+  const cplx<T>* r;
+  const cplx<T>* Wb;
+  long dstride;
+  int k, beta_slot, ww_slot, alpha_slot;
+  int nrhs;
+};
+template <typename T>
+__global__ __launch_bounds__(256) void gcr16_apply_dots_kernel(G16Args<T> a0, const G16Args<T>* batch) {
+  const G16Args<T>& ga = (batch != nullptr) ? batch[blockIdx.z] : a0;
+  if ((int)blockIdx.y >= ga.nrhs) return;
+  const CoarseArgs<T>& a = ga.c;
+  const cplx<T>* __restrict__ r = ga.r;
+  const cplx<T>* __restrict__ Wb = ga.Wb;
+  const long dstride = ga.dstride;
+  const int k = ga.k, beta_slot = ga.beta_slot, ww_slot = ga.ww_slot, alpha_slot = ga.alpha_slot;
   using K = C16<T>;
   __shared__ double sh[4 * K::LPC * G16_NQ];
   __shared__ double blk_part[G16_NQ];
@@ -393,10 +410,25 @@ struct BlockIdx {
 };
 
 template <typename T, typename PT>
-__global__ __launch_bounds__(256) void restrict_kernel(cplx<T>* __restrict__ out, const cplx<T>* __restrict__ in,
-                                                       const PT* __restrict__ P, TransferGeom g, const int* flags) {
+struct TrArgs {
+  cplx<T>* out;
+  const cplx<T>* in;
+  const PT* P;
+  TransferGeom g;
+  const int* flags;
+  int accumulate;
+  int nrhs;
+};
+
+template <typename T, typename PT>
+__global__ __launch_bounds__(256) void restrict_kernel(TrArgs<T, PT> a0, const TrArgs<T, PT>* batch) {
+  AMG_ARGS(TrArgs<T, PT>)
+  const TransferGeom& g = a.g;
+  cplx<T>* __restrict__ out = a.out;
+  const cplx<T>* __restrict__ in = a.in;
+  const PT* __restrict__ P = a.P;
   const int rhs = blockIdx.y;
-  if (skip_rhs(flags, rhs)) return;
+  if (skip_rhs(a.flags, rhs)) return;
   const int nc = 2 * g.nv, hd = g.dof / 2;
   const long total = g.Vc * nc;
   const long rof = (long)rhs * g.lf.per_rhs();
@@ -419,11 +451,15 @@ __global__ __launch_bounds__(256) void restrict_kernel(cplx<T>* __restrict__ out
 }
 
 template <typename T, typename PT>
-__global__ __launch_bounds__(256) void prolong_kernel(cplx<T>* __restrict__ out, const cplx<T>* __restrict__ in,
-                                                      const PT* __restrict__ P, TransferGeom g, int accumulate,
-                                                      const int* flags) {
+__global__ __launch_bounds__(256) void prolong_kernel(TrArgs<T, PT> a0, const TrArgs<T, PT>* batch) {
+  AMG_ARGS(TrArgs<T, PT>)
+  const TransferGeom& g = a.g;
+  cplx<T>* __restrict__ out = a.out;
+  const cplx<T>* __restrict__ in = a.in;
+  const PT* __restrict__ P = a.P;
+  const int accumulate = a.accumulate;
   const int rhs = blockIdx.y;
-  if (skip_rhs(flags, rhs)) return;
+  if (skip_rhs(a.flags, rhs)) return;
   const int nc = 2 * g.nv, hd = g.dof / 2;
   const long total = g.Vf * g.dof;
   const long rof = (long)rhs * g.lf.per_rhs();
@@ -544,8 +580,8 @@ template <typename T>
 void launch_coarse(const CoarseArgs<T>& a, int dagger, int epi, hipStream_t st) {
   const long total = a.g.V * a.g.nc;
   const bool red = (epi == EPI_MRDOT || epi == EPI_NORM);
-  dim3 grid(nblocks(total, red ? RED_MAX_BLOCKS : (1L << 20)), (unsigned)a.nrhs);
-#define AMG_C(NC, DAG, EPI) hipLaunchKernelGGL((coarse_kernel<T, NC, DAG, EPI>), grid, dim3(256), 0, st, a)
+  dim3 grid(nblocks(total, red ? (long)red_block_cap() : (1L << 20)), (unsigned)a.nrhs);
+#define AMG_C(NC, DAG, EPI) dispatch(coarse_kernel<T, NC, DAG, EPI>, a, grid, dim3(256), st)
 #define AMG_C_EPI(NC, DAG)                      \
   switch (epi) {                                \
     case EPI_PLAIN: AMG_C(NC, DAG, EPI_PLAIN); break; \
@@ -555,10 +591,10 @@ void launch_coarse(const CoarseArgs<T>& a, int dagger, int epi, hipStream_t st) 
   }
   if (a.g.nc == 16) {
     long nb = (a.g.V + 3) / 4;
-    const long cap = red ? RED_MAX_BLOCKS : (1L << 20);
+    const long cap = red ? (long)red_block_cap() : (1L << 20);
     if (nb > cap) nb = cap;
     dim3 g16((unsigned)nb, (unsigned)a.nrhs);
-#define AMG_C16(DAG, EPI) hipLaunchKernelGGL((coarse16_kernel<T, DAG, EPI>), g16, dim3(256), 0, st, a)
+#define AMG_C16(DAG, EPI) dispatch(coarse16_kernel<T, DAG, EPI>, a, g16, dim3(256), st)
     switch (epi * 2 + (dagger ? 1 : 0)) {
       case EPI_PLAIN * 2: AMG_C16(0, EPI_PLAIN); break;
       case EPI_PLAIN * 2 + 1: AMG_C16(1, EPI_PLAIN); break;
@@ -585,10 +621,10 @@ template <typename T>
 void launch_gcr16_apply_dots(const CoarseArgs<T>& a, const cplx<T>* r, const cplx<T>* Wb, long dstride, int k,
                              int beta_slot, int ww_slot, int alpha_slot, hipStream_t st) {
   long nb = (a.g.V + 3) / 4;
-  if (nb > RED_MAX_BLOCKS) nb = RED_MAX_BLOCKS;
+  if (nb > red_block_cap()) nb = red_block_cap();
   dim3 grid((unsigned)nb, (unsigned)a.nrhs);
-  hipLaunchKernelGGL((gcr16_apply_dots_kernel<T>), grid, dim3(256), 0, st, a, r, Wb, dstride, k, beta_slot, ww_slot,
-                     alpha_slot);
+  G16Args<T> ga{a, r, Wb, dstride, k, beta_slot, ww_slot, alpha_slot, a.nrhs};
+  dispatch(gcr16_apply_dots_kernel<T>, ga, grid, dim3(256), st);
 }
 template void launch_gcr16_apply_dots<double>(const CoarseArgs<double>&, const double2*, const double2*, long, int,
                                               int, int, int, hipStream_t);
@@ -613,11 +649,11 @@ void launch_restrict(cplx<T>* out, const cplx<T>* in, const void* P, int pkind, 
                      const int* flags, hipStream_t st) {
   dim3 grid(nblocks(g.Vc * 2 * g.nv), (unsigned)nrhs);
   if (pkind == P_F64)
-    hipLaunchKernelGGL((restrict_kernel<T, double2>), grid, dim3(256), 0, st, out, in, (const double2*)P, g, flags);
+    dispatch(restrict_kernel<T, double2>, TrArgs<T, double2>{out, in, (const double2*)P, g, flags, 0, nrhs}, grid, dim3(256), st);
   else if (pkind == P_F32)
-    hipLaunchKernelGGL((restrict_kernel<T, float2>), grid, dim3(256), 0, st, out, in, (const float2*)P, g, flags);
+    dispatch(restrict_kernel<T, float2>, TrArgs<T, float2>{out, in, (const float2*)P, g, flags, 0, nrhs}, grid, dim3(256), st);
   else
-    hipLaunchKernelGGL((restrict_kernel<T, bf16x2>), grid, dim3(256), 0, st, out, in, (const bf16x2*)P, g, flags);
+    dispatch(restrict_kernel<T, bf16x2>, TrArgs<T, bf16x2>{out, in, (const bf16x2*)P, g, flags, 0, nrhs}, grid, dim3(256), st);
 }
 template void launch_restrict<double>(double2*, const double2*, const void*, int, const TransferGeom&, int, const int*, hipStream_t);
 template void launch_restrict<float>(float2*, const float2*, const void*, int, const TransferGeom&, int, const int*, hipStream_t);
@@ -627,11 +663,11 @@ void launch_prolong(cplx<T>* out, const cplx<T>* in, const void* P, int pkind, c
                     int accumulate, const int* flags, hipStream_t st) {
   dim3 grid(nblocks(g.Vf * g.dof), (unsigned)nrhs);
   if (pkind == P_F64)
-    hipLaunchKernelGGL((prolong_kernel<T, double2>), grid, dim3(256), 0, st, out, in, (const double2*)P, g, accumulate, flags);
+    dispatch(prolong_kernel<T, double2>, TrArgs<T, double2>{out, in, (const double2*)P, g, flags, accumulate, nrhs}, grid, dim3(256), st);
   else if (pkind == P_F32)
-    hipLaunchKernelGGL((prolong_kernel<T, float2>), grid, dim3(256), 0, st, out, in, (const float2*)P, g, accumulate, flags);
+    dispatch(prolong_kernel<T, float2>, TrArgs<T, float2>{out, in, (const float2*)P, g, flags, accumulate, nrhs}, grid, dim3(256), st);
   else
-    hipLaunchKernelGGL((prolong_kernel<T, bf16x2>), grid, dim3(256), 0, st, out, in, (const bf16x2*)P, g, accumulate, flags);
+    dispatch(prolong_kernel<T, bf16x2>, TrArgs<T, bf16x2>{out, in, (const bf16x2*)P, g, flags, accumulate, nrhs}, grid, dim3(256), st);
 }
 template void launch_prolong<double>(double2*, const double2*, const void*, int, const TransferGeom&, int, int, const int*, hipStream_t);
 template void launch_prolong<float>(float2*, const float2*, const void*, int, const TransferGeom&, int, int, const int*, hipStream_t);

@@ -1,0 +1,53 @@
+// Kernel dispatch with an optional recorder.
+//
+// Every solve-path kernel takes its arguments as one trivially copyable
+// struct `a0` plus an optional device array `batch` of such structs.  A plain
+// launch passes batch = nullptr and runs one problem instance; a batched
+// launch runs many instances in one grid, instance = blockIdx.z reading its
+// own struct from `batch`.
+//
+// dispatch() launches immediately, or — while a Recorder is installed on the
+// calling thread — appends (kernel, argument bytes, grid, block) to it
+// instead.  The batch layer records the same solve sequence once per
+// instance and merges the recordings stage by stage into batched launches.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <vector>
+
+namespace amg {
+
+struct RecordedLaunch {
+  const void* fn = nullptr;
+  std::vector<char> args;
+  dim3 grid, block;
+};
+
+struct Recorder {
+  std::vector<RecordedLaunch> ops;
+};
+
+Recorder*& current_recorder();
+
+template <class A>
+inline void dispatch(void (*fn)(A, const A*), const A& a, dim3 grid, dim3 block, hipStream_t st) {
+  if (Recorder* rec = current_recorder()) {
+    RecordedLaunch r;
+    r.fn = reinterpret_cast<const void*>(fn);
+    r.args.resize(sizeof(A));
+    std::memcpy(r.args.data(), &a, sizeof(A));
+    r.grid = grid;
+    r.block = block;
+    rec->ops.push_back(std::move(r));
+    return;
+  }
+  hipLaunchKernelGGL(fn, grid, block, 0, st, a, static_cast<const A*>(nullptr));
+}
+
+// pick this block's argument struct; blocks past the instance's rhs count exit
+#define AMG_ARGS(...)                                                  \
+  const __VA_ARGS__& a = (batch != nullptr) ? batch[blockIdx.z] : a0;   \
+  if ((int)blockIdx.y >= a.nrhs) return;
+
+}  // namespace amg

@@ -15,7 +15,11 @@ enum Epi {
   EPI_NORM = 3    // out = A in; scal[slot + rhs] = <out, out>
 };
 
-constexpr int RED_MAX_BLOCKS = 1024;   // grid cap of kernels that reduce
+constexpr int RED_MAX_BLOCKS = 1024;   // largest grid of kernels that reduce
+// grid cap used when launching reducing kernels (<= RED_MAX_BLOCKS); a launch
+// shape chosen by the batch autotuner, 1024 by default
+int red_block_cap();
+void set_red_block_cap(int cap);
 constexpr int GCR_KMAX = 32;           // longest GCR restart cycle
 
 // Reduction plumbing handed to every kernel that reduces or can skip rhs.
@@ -141,9 +145,14 @@ template <typename T>
 void launch_gcr_update(cplx<T>* x, cplx<T>* r, const cplx<T>* z, const cplx<T>* w, long n, int nrhs,
                        RedArgs red, int alpha_slot, int rr_slot, int bb_slot, double tol2, int* set_flags,
                        hipStream_t st);
+// flags[rhs] = inherit[rhs] || scal[rr + rhs] <= tol2 * scal[bb + rhs]
+void launch_set_flags(int* flags, const int* inherit, const double* scal, int rr_slot, int bb_slot, double tol2,
+                      int nrhs, hipStream_t st);
+// out[rhs] = scal[slot + rhs]
+void launch_gather(double* out, const double* scal, int slot, int nrhs, hipStream_t st);
+// dst = src (src == nullptr: zero), n complex per rhs
 template <typename T>
-void launch_set_flags(int* flags, const double* scal, int rr_slot, int bb_slot, double tol2, int nrhs,
-                      hipStream_t st);
+void launch_fill(cplx<T>* dst, const cplx<T>* src, long n, int nrhs, hipStream_t st);
 template <typename T>
 void launch_axpy(cplx<T>* y, const cplx<T>* x, double are, double aim, long n, int nrhs, hipStream_t st);
 template <typename T>

@@ -16,8 +16,21 @@
 
 #include "amg.h"
 #include "kernels.h"
+#include "dispatch.h"
 
 using namespace amg;
+
+namespace amg {
+Recorder*& current_recorder() {
+  thread_local Recorder* rec = nullptr;
+  return rec;
+}
+namespace {
+thread_local int g_red_cap = RED_MAX_BLOCKS;
+}
+int red_block_cap() { return g_red_cap; }
+void set_red_block_cap(int cap) { g_red_cap = std::max(16, std::min(RED_MAX_BLOCKS, cap)); }
+}  // namespace amg
 
 namespace {
 
@@ -235,6 +248,8 @@ struct amg_solver {
   // setup temporaries
   Buf tE, tF, tS, tR, tzero;
   long long nD = 0, nDd = 0, nC = 0;
+  // per-rhs mask of right-hand sides that are done (batched solves); nullptr otherwise
+  int* outer_flags = nullptr;
   // persistent coarsest solve: barrier counters, timeout flag, iteration counts
   Buf pbar, perr, piters;
   bool persistent = false;  // measured slower than the launch sequence (grid barriers are costly)
@@ -266,7 +281,8 @@ struct ProfScope {
   bool active;
   hipStream_t st;
   ProfScope(Solver& s, int kind, int level, hipStream_t stream)
-      : S(s), active(s.prof.on && s.prof.kind == kind && s.prof.level == level), st(stream) {
+      : S(s), active(s.prof.on && s.prof.kind == kind && s.prof.level == level && current_recorder() == nullptr),
+        st(stream) {
     if (!active) return;
     auto& P = S.prof;
     while (P.ev.size() < P.used + 2) {
@@ -383,17 +399,17 @@ void mr_smooth(Solver& S, int l, const cplx<T>* b, cplx<T>* x, cplx<T>* r, cplx<
   const long n = L.per_rhs();
   if (nu == 0) {
     if (first) {
-      HIPC(hipMemsetAsync(x, 0, sizeof(cplx<T>) * n * nrhs, st));
-      if (need_r && r != b) HIPC(hipMemcpyAsync(r, b, sizeof(cplx<T>) * n * nrhs, hipMemcpyDeviceToDevice, st));
+      launch_fill<T>(x, nullptr, n, nrhs, st);
+      if (need_r && r != b) launch_fill<T>(r, b, n, nrhs, st);
     }
     return;
   }
   for (int i = 0; i < nu; ++i) {
     const cplx<T>* rin = (i == 0) ? b : r;
-    op_apply<T>(S, l, 0, EPI_MRDOT, rin, p, nullptr, nullptr, nrhs, S.sc.red(L.mr_slot, nullptr, S.p.omega), st);
+    op_apply<T>(S, l, 0, EPI_MRDOT, rin, p, nullptr, nullptr, nrhs, S.sc.red(L.mr_slot, S.outer_flags, S.p.omega), st);
     const bool upd = (i < nu - 1) || need_r;
     launch_mr_update<T>(x, r, rin, p, S.sc.scal.as<double>() + L.mr_slot, n, nrhs, first && i == 0, upd ? 1 : 0,
-                        nullptr, st);
+                        S.outer_flags, st);
   }
 }
 
@@ -419,7 +435,8 @@ void level_gcr(Solver& S, int l, int lstop, const cplx<T>* b, cplx<T>* x, int nr
   int* flags = S.sc.flags.as<int>() + L.flag_off;
   const double tol2 = tol * tol;
   const int check = precond ? 1 : kCoarseCheck;
-  if (!precond && S.persistent && L.dof == 16 && !L.fine) {
+  const bool recording = current_recorder() != nullptr;
+  if (!precond && S.persistent && !recording && L.dof == 16 && !L.fine) {
     // the whole solve in one cooperative launch
     long nb = (L.V + 15) / 16;
     nb = std::max(8L, std::min((long)S.pcoarse_max_blocks, nb));
@@ -433,10 +450,10 @@ void level_gcr(Solver& S, int l, int lstop, const cplx<T>* b, cplx<T>* x, int nr
     S.nC += maxiter;  // upper bound of coarse applications (exact count is per rhs on the device)
     return;
   }
-  HIPC(hipMemsetAsync(x, 0, sizeof(cplx<T>) * dstride, st));
-  HIPC(hipMemcpyAsync(r, b, sizeof(cplx<T>) * dstride, hipMemcpyDeviceToDevice, st));
+  launch_fill<T>(x, nullptr, n, nrhs, st);
+  launch_fill<T>(r, b, n, nrhs, st);
   launch_norm2<T>(b, n, nrhs, S.sc.red(L.gs.bb), st);
-  launch_set_flags<T>(flags, S.sc.scal.as<double>(), L.gs.bb, L.gs.bb, tol2 >= 1.0 ? 1.0 : 0.0, nrhs, st);
+  launch_set_flags(flags, S.outer_flags, S.sc.scal.as<double>(), L.gs.bb, L.gs.bb, tol2 >= 1.0 ? 1.0 : 0.0, nrhs, st);
   for (int it = 0; it < maxiter; ++it) {
     const int k = it % m;
     if (k == 0 && it > 0)
@@ -459,7 +476,7 @@ void level_gcr(Solver& S, int l, int lstop, const cplx<T>* b, cplx<T>* x, int nr
       }
       launch_gcr_update2<T>(x, r, z, Wb, Zb, dstride, k, n, nrhs, S.sc.red(0, flags), L.gs.beta, L.gs.alpha, L.gs.rr,
                             L.gs.bb, tol2, flags, st);
-      if ((it + 1) % check == 0 && it + 1 < maxiter && S.sc.all_flags(L.flag_off, nrhs, st)) break;
+      if (!recording && (it + 1) % check == 0 && it + 1 < maxiter && S.sc.all_flags(L.flag_off, nrhs, st)) break;
       continue;
     }
     if (precond) {
@@ -475,7 +492,7 @@ void level_gcr(Solver& S, int l, int lstop, const cplx<T>* b, cplx<T>* x, int nr
     // Every rhs that met the tolerance turns the remaining launches into
     // no-ops; look at the flags now and then and stop issuing them.  This
     // changes no arithmetic, only how many empty launches are made.
-    if ((it + 1) % check == 0 && it + 1 < maxiter && S.sc.all_flags(L.flag_off, nrhs, st)) break;
+    if (!recording && (it + 1) % check == 0 && it + 1 < maxiter && S.sc.all_flags(L.flag_off, nrhs, st)) break;
   }
 }
 
@@ -507,7 +524,7 @@ void vcycle(Solver& S, int l, int lstop, const cplx<T>* b, cplx<T>* x, int nrhs,
   cplx<T>* xc = wc[W_X].as<cplx<T>>();
   {
     ProfScope ps(S, PK_RESTRICT, l, st);
-    launch_restrict<T>(bc, r, P, pk, tg, nrhs, nullptr, st);
+    launch_restrict<T>(bc, r, P, pk, tg, nrhs, S.outer_flags, st);
   }
   // 3. coarse-level cycle; an intermediate level is a K-cycle when enabled
   if (S.p.kcycle_maxiter > 0 && l + 1 < lstop)
@@ -517,10 +534,10 @@ void vcycle(Solver& S, int l, int lstop, const cplx<T>* b, cplx<T>* x, int nrhs,
   // 4. coarse-grid correction
   {
     ProfScope ps(S, PK_PROLONG, l, st);
-    launch_prolong<T>(x, xc, P, pk, tg, nrhs, 1, nullptr, st);
+    launch_prolong<T>(x, xc, P, pk, tg, nrhs, 1, S.outer_flags, st);
   }
   // 5. post-relax on the new residual
-  op_apply<T>(S, l, 0, EPI_RESID, x, r, b, nullptr, nrhs, S.sc.red(0), st);
+  op_apply<T>(S, l, 0, EPI_RESID, x, r, b, nullptr, nrhs, S.sc.red(0, S.outer_flags), st);
   mr_smooth<T>(S, l, r, x, r, p, S.p.nu_post, false, false, nrhs, st);
 }
 
@@ -776,8 +793,8 @@ OuterResult fgcr_outer(Solver& S, const double2* b, double2* x, int nrhs, double
   double2* Wb = S.oW.as<double2>();
   const int m = S.p.outer_restart;
   const GcrSlots& gs = S.og;
-  HIPC(hipMemsetAsync(x, 0, sizeof(double2) * dstride, st));
-  HIPC(hipMemcpyAsync(r, b, sizeof(double2) * dstride, hipMemcpyDeviceToDevice, st));
+  launch_fill<double>(x, nullptr, n, nrhs, st);
+  launch_fill<double>(r, b, n, nrhs, st);
   launch_norm2<double>(b, n, nrhs, S.sc.red(gs.bb), st);
   launch_norm2<double>(r, n, nrhs, S.sc.red(gs.rr), st);
   std::vector<double> bb(nrhs), rr(nrhs);
@@ -848,6 +865,262 @@ void check_ptr(const void* p, const char* what) {
 }
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+}  // namespace
+
+// ===========================================================================
+// Batched solves: many independent solvers, one launch per stage.
+//
+// The solve of each instance is recorded (the same host code as a single
+// solve, with host-side checks off and every copy / clear done by kernels),
+// the recordings are merged stage by stage into batched launches (argument
+// structs in a device array, instance = blockIdx.z), and each segment of the
+// outer iteration is captured once into a HIP graph.  Right-hand sides that
+// have converged are masked on the device by their instance's outer flags.
+// ===========================================================================
+struct amg_batch {
+  std::vector<Solver*> S;
+  std::vector<int> nrhs;
+  int n = 0, m = 0, red_cap = RED_MAX_BLOCKS;
+  hipStream_t st = nullptr;
+  Buf args_dev, flags_dev, gath_dev;
+  double* gath_host = nullptr;
+  int* flags_host = nullptr;
+  struct Op {
+    const void* fn;
+    dim3 grid, block;
+    size_t off;
+    std::vector<char> a0;
+  };
+  struct Seg {
+    std::vector<Op> ops;
+    hipGraphExec_t exec = nullptr;
+  };
+  Seg init, truer;
+  std::vector<Seg> iters;
+  std::vector<char> img;
+  ~amg_batch() {
+    auto drop = [](Seg& g) {
+      if (g.exec) (void)hipGraphExecDestroy(g.exec);
+      g.exec = nullptr;
+    };
+    drop(init);
+    drop(truer);
+    for (auto& g : iters) drop(g);
+    if (gath_host) (void)hipHostFree(gath_host);
+    if (flags_host) (void)hipHostFree(flags_host);
+    if (st) (void)hipStreamDestroy(st);
+    for (Solver* s : S) s->outer_flags = nullptr;
+  }
+};
+
+namespace {
+
+using Batch = amg_batch;
+
+// record fn(S_i, i) for every instance and merge the launches stage by stage
+template <class F>
+void batch_record(Batch& B, Batch::Seg& seg, F fn) {
+  std::vector<Recorder> recs(B.n);
+  for (int i = 0; i < B.n; ++i) {
+    current_recorder() = &recs[i];
+    try {
+      fn(*B.S[i], i);
+    } catch (...) {
+      current_recorder() = nullptr;
+      throw;
+    }
+    current_recorder() = nullptr;
+  }
+  const size_t nops = recs[0].ops.size();
+  for (int i = 1; i < B.n; ++i)
+    if (recs[i].ops.size() != nops) fail(AMG_ERR_STATE, "batched instances record different launch sequences");
+  seg.ops.clear();
+  for (size_t j = 0; j < nops; ++j) {
+    Batch::Op op;
+    const RecordedLaunch& r0 = recs[0].ops[j];
+    op.fn = r0.fn;
+    op.block = r0.block;
+    op.grid = dim3(1, 1, (unsigned)B.n);
+    const size_t asz = r0.args.size();
+    size_t off = (B.img.size() + 255) & ~size_t(255);
+    B.img.resize(off + asz * B.n);
+    for (int i = 0; i < B.n; ++i) {
+      const RecordedLaunch& r = recs[i].ops[j];
+      if (r.fn != op.fn || r.args.size() != asz || r.block.x != op.block.x)
+        fail(AMG_ERR_STATE, "batched instances record different kernels at one stage");
+      op.grid.x = std::max(op.grid.x, r.grid.x);
+      op.grid.y = std::max(op.grid.y, r.grid.y);
+      std::memcpy(B.img.data() + off + asz * i, r.args.data(), asz);
+    }
+    op.off = off;
+    op.a0 = r0.args;
+    seg.ops.push_back(std::move(op));
+  }
+}
+
+void batch_capture(Batch& B, Batch::Seg& seg) {
+  hipGraph_t g = nullptr;
+  HIPC(hipStreamBeginCapture(B.st, hipStreamCaptureModeThreadLocal));
+  for (auto& op : seg.ops) {
+    void* dptr = static_cast<char*>(B.args_dev.p) + op.off;
+    void* kargs[2] = {op.a0.data(), &dptr};
+    const hipError_t e = hipLaunchKernel(op.fn, op.grid, op.block, kargs, 0, B.st);
+    if (e != hipSuccess) {
+      hipGraph_t dummy = nullptr;
+      (void)hipStreamEndCapture(B.st, &dummy);
+      if (dummy) (void)hipGraphDestroy(dummy);
+      hip_check(e, "hipLaunchKernel (capture)");
+    }
+  }
+  HIPC(hipStreamEndCapture(B.st, &g));
+  const hipError_t e = hipGraphInstantiate(&seg.exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  hip_check(e, "hipGraphInstantiate");
+}
+
+// segments of the batched outer FGCR (fine level, FP64); gathered scalars:
+// rr of instance i at gath[i * RHS_MAX], bb at gath[(n + i) * RHS_MAX]
+void batch_build(Batch& B) {
+  B.img.clear();
+  B.iters.assign(B.m, Batch::Seg());
+  double* gath = B.gath_dev.as<double>();
+  auto rr_out = [&](int i) { return gath + (long)i * RHS_MAX; };
+  auto bb_out = [&](int i) { return gath + (long)(B.n + i) * RHS_MAX; };
+  batch_record(B, B.init, [&](Solver& S, int i) {
+    const long n = S.lv[0].per_rhs();
+    const int nr = B.nrhs[i];
+    double2* b = S.ob.as<double2>();
+    launch_fill<double>(S.ox.as<double2>(), nullptr, n, nr, B.st);
+    launch_fill<double>(S.orr.as<double2>(), b, n, nr, B.st);
+    launch_norm2<double>(b, n, nr, S.sc.red(S.og.bb), B.st);
+    launch_norm2<double>(S.orr.as<double2>(), n, nr, S.sc.red(S.og.rr), B.st);
+    launch_gather(bb_out(i), S.sc.scal.as<double>(), S.og.bb, nr, B.st);
+    launch_gather(rr_out(i), S.sc.scal.as<double>(), S.og.rr, nr, B.st);
+  });
+  for (int k = 0; k < B.m; ++k)
+    batch_record(B, B.iters[k], [&](Solver& S, int i) {
+      const long n = S.lv[0].per_rhs();
+      const int nr = B.nrhs[i];
+      const long dstride = n * nr;
+      double2* r = S.orr.as<double2>();
+      double2* x = S.ox.as<double2>();
+      double2* Zb = S.oZ.as<double2>();
+      double2* Wb = S.oW.as<double2>();
+      double2* Zk = Zb + (long)k * dstride;
+      double2* Wk = Wb + (long)k * dstride;
+      const GcrSlots& gs = S.og;
+      precondition(S, r, Zk, nr, B.st);
+      op_apply<double>(S, 0, 0, EPI_PLAIN, Zk, Wk, nullptr, nullptr, nr, S.sc.red(0, S.outer_flags), B.st);
+      launch_gcr_mdot<double>(Wb, dstride, Wk, k, n, nr, S.sc.red(0, S.outer_flags), gs.beta, gs.ww, B.st);
+      launch_gcr_maxpy<double>(Wk, Zk, Wb, Zb, dstride, r, k, n, nr, S.sc.red(0, S.outer_flags), gs.beta, gs.ww,
+                               gs.alpha, B.st);
+      launch_gcr_update<double>(x, r, Zk, Wk, n, nr, S.sc.red(0, S.outer_flags), gs.alpha, gs.rr, gs.bb, 0.0, nullptr,
+                                B.st);
+      launch_gather(rr_out(i), S.sc.scal.as<double>(), gs.rr, nr, B.st);
+    });
+  batch_record(B, B.truer, [&](Solver& S, int i) {
+    const long n = S.lv[0].per_rhs();
+    const int nr = B.nrhs[i];
+    op_apply<double>(S, 0, 0, EPI_RESID, S.ox.as<double2>(), S.orr.as<double2>(), S.ob.as<double2>(), nullptr, nr,
+                     S.sc.red(0), B.st);
+    launch_norm2<double>(S.orr.as<double2>(), n, nr, S.sc.red(S.og.rr), B.st);
+    launch_gather(rr_out(i), S.sc.scal.as<double>(), S.og.rr, nr, B.st);
+  });
+  B.args_dev.ensure(std::max<size_t>(B.img.size(), 256));
+  HIPC(hipMemcpy(B.args_dev.p, B.img.data(), B.img.size(), hipMemcpyHostToDevice));
+  batch_capture(B, B.init);
+  for (auto& g : B.iters) batch_capture(B, g);
+  batch_capture(B, B.truer);
+}
+
+void batch_replay(Batch& B, Batch::Seg& seg) { HIPC(hipGraphLaunch(seg.exec, B.st)); }
+
+void batch_fetch(Batch& B) {
+  HIPC(hipMemcpyAsync(B.gath_host, B.gath_dev.p, sizeof(double) * 2 * B.n * RHS_MAX, hipMemcpyDeviceToHost, B.st));
+  HIPC(hipStreamSynchronize(B.st));
+}
+
+void batch_put_flags(Batch& B) {
+  HIPC(hipMemcpyAsync(B.flags_dev.p, B.flags_host, sizeof(int) * B.n * RHS_MAX, hipMemcpyHostToDevice, B.st));
+}
+
+struct BatchResult {
+  std::vector<int> iters;
+  std::vector<double> rel;
+  std::vector<int> done;
+  int outer = 0;
+};
+
+BatchResult batch_run(Batch& B, double tol, int maxiter) {
+  const int n = B.n;
+  std::vector<int> base(n + 1, 0);
+  for (int i = 0; i < n; ++i) base[i + 1] = base[i] + B.nrhs[i];
+  const int tot = base[n];
+  BatchResult R;
+  R.iters.assign(tot, 0);
+  R.rel.assign(tot, 0.0);
+  std::vector<int> state(tot, 0);  // 0 active, 1 candidate (recursive residual below tol), 2 done
+  std::vector<double> bb(tot);
+  auto rr = [&](int i, int j) { return B.gath_host[(long)i * RHS_MAX + j]; };
+  std::memset(B.flags_host, 0, sizeof(int) * n * RHS_MAX);
+  batch_put_flags(B);
+  batch_replay(B, B.init);
+  batch_fetch(B);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < B.nrhs[i]; ++j) bb[base[i] + j] = B.gath_host[(long)(n + i) * RHS_MAX + j];
+  int k = 0, it = 0;
+  for (;;) {
+    int active = 0, cand = 0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < B.nrhs[i]; ++j) {
+        const int q = base[i] + j;
+        if (state[q] == 0 && rr(i, j) <= tol * tol * bb[q]) state[q] = 1;
+        if (state[q] == 0) ++active;
+        if (state[q] == 1) ++cand;
+      }
+    if ((cand > 0 && active == 0) || k == B.m || (it >= maxiter && cand > 0)) {
+      // true residual of every rhs; candidates that pass are done, and the
+      // iteration restarts from the true residuals
+      batch_replay(B, B.truer);
+      batch_fetch(B);
+      active = 0;
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < B.nrhs[i]; ++j) {
+          const int q = base[i] + j;
+          R.rel[q] = bb[q] > 0 ? std::sqrt(rr(i, j) / bb[q]) : 0.0;
+          if (state[q] == 1) {
+            if (rr(i, j) <= tol * tol * bb[q]) { state[q] = 2; R.iters[q] = it; }
+            else state[q] = 0;
+          }
+          if (state[q] == 0) ++active;
+        }
+      k = 0;
+    }
+    if (active == 0 || it >= maxiter) break;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < B.nrhs[i]; ++j) B.flags_host[(long)i * RHS_MAX + j] = state[base[i] + j] != 0;
+    batch_put_flags(B);
+    batch_replay(B, B.iters[k]);
+    batch_fetch(B);
+    ++k;
+    ++it;
+  }
+  if (std::any_of(state.begin(), state.end(), [](int v) { return v == 0; })) {
+    batch_replay(B, B.truer);
+    batch_fetch(B);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < B.nrhs[i]; ++j) {
+        const int q = base[i] + j;
+        R.rel[q] = bb[q] > 0 ? std::sqrt(rr(i, j) / bb[q]) : 0.0;
+        if (state[q] != 2) R.iters[q] = it;
+      }
+  }
+  R.done.resize(tot);
+  for (int q = 0; q < tot; ++q) R.done[q] = (state[q] == 2) || (R.rel[q] <= tol);
+  R.outer = it;
+  return R;
+}
 
 }  // namespace
 
@@ -1336,6 +1609,142 @@ amg_status amg_level_info(const amg_solver* S, int level, int* dims4, int* dof, 
     for (int mu = 0; mu < 4; ++mu) dims4[mu] = L.dims[mu];
   if (dof) *dof = L.dof;
   if (V) *V = L.V;
+  AMG_CATCH
+}
+
+amg_status amg_batch_create(amg_solver* const* solvers, const int* nrhs, int n, int autotune, void* stream,
+                            amg_batch** out) {
+  AMG_TRY
+  check_ptr(solvers, "solvers");
+  check_ptr(nrhs, "nrhs");
+  check_ptr(out, "out");
+  if (n < 1 || n > 4096) fail(AMG_ERR_ARG, "batch size must be 1..4096");
+  Batch* B = new Batch();
+  try {
+    B->n = n;
+    HIPC(hipStreamCreateWithFlags(&B->st, hipStreamNonBlocking));
+    HIPC(hipStreamSynchronize(as_stream(stream)));
+    const Solver* s0 = solvers[0];
+    check_ptr(s0, "solvers[0]");
+    for (int i = 0; i < n; ++i) {
+      Solver* S = solvers[i];
+      check_ptr(S, "solvers[i]");
+      if (S->g->nd != 2) fail(AMG_ERR_ARG, "batched solves support the 2d operator");
+      if (S->lv.size() != s0->lv.size() || S->p.inner_prec != s0->p.inner_prec || S->p.p_bf16 != s0->p.p_bf16 ||
+          S->p.nu_pre != s0->p.nu_pre || S->p.nu_post != s0->p.nu_post || S->p.outer_restart != s0->p.outer_restart ||
+          S->p.coarse_maxiter != s0->p.coarse_maxiter || S->p.coarse_restart != s0->p.coarse_restart ||
+          S->p.kcycle_maxiter != s0->p.kcycle_maxiter)
+        fail(AMG_ERR_ARG, "batched solvers must share the hierarchy depth and solver parameters");
+      for (size_t l = 0; l < S->lv.size(); ++l)
+        if (S->lv[l].dof != s0->lv[l].dof) fail(AMG_ERR_ARG, "batched solvers must share the dof per level");
+      if (nrhs[i] < 1 || nrhs[i] > RHS_MAX) fail(AMG_ERR_ARG, "bad nrhs");
+      for (int j = 0; j < i; ++j)
+        if (solvers[j] == S) fail(AMG_ERR_ARG, "a solver appears twice in the batch");
+      B->S.push_back(S);
+      B->nrhs.push_back(nrhs[i]);
+      ensure_work(*S, nrhs[i]);
+    }
+    B->m = s0->p.outer_restart;
+    B->flags_dev.ensure(sizeof(int) * n * RHS_MAX);
+    HIPC(hipMemset(B->flags_dev.p, 0, sizeof(int) * n * RHS_MAX));
+    B->gath_dev.ensure(sizeof(double) * 2 * n * RHS_MAX);
+    HIPC(hipHostMalloc((void**)&B->gath_host, sizeof(double) * 2 * n * RHS_MAX, hipHostMallocDefault));
+    HIPC(hipHostMalloc((void**)&B->flags_host, sizeof(int) * n * RHS_MAX, hipHostMallocDefault));
+    for (int i = 0; i < n; ++i) B->S[i]->outer_flags = B->flags_dev.as<int>() + (long)i * RHS_MAX;
+    const int saved = red_block_cap();
+    if (autotune) {
+      // autotune the grid of the reducing kernels: time one outer iteration
+      // (the first direction) for every candidate on a unit source
+      for (int i = 0; i < n; ++i) {
+        Solver& S = *B->S[i];
+        const long cnt = S.lv[0].per_rhs() * B->nrhs[i];
+        std::vector<double2> ones(cnt, make_double2(1.0, 0.0));
+        HIPC(hipMemcpy(S.ob.p, ones.data(), sizeof(double2) * cnt, hipMemcpyHostToDevice));
+      }
+      float best = 1e30f;
+      int best_cap = RED_MAX_BLOCKS;
+      hipEvent_t e0, e1;
+      HIPC(hipEventCreate(&e0));
+      HIPC(hipEventCreate(&e1));
+      for (int cap : {128, 256, 512, 1024}) {
+        set_red_block_cap(cap);
+        batch_build(*B);
+        batch_replay(*B, B->init);
+        batch_replay(*B, B->iters[0]);
+        HIPC(hipEventRecord(e0, B->st));
+        for (int rep = 0; rep < 3; ++rep) batch_replay(*B, B->iters[0]);
+        HIPC(hipEventRecord(e1, B->st));
+        HIPC(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPC(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) { best = ms; best_cap = cap; }
+        auto drop = [](Batch::Seg& g) { if (g.exec) (void)hipGraphExecDestroy(g.exec); g.exec = nullptr; };
+        drop(B->init);
+        drop(B->truer);
+        for (auto& g : B->iters) drop(g);
+      }
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      B->red_cap = best_cap;
+    }
+    set_red_block_cap(B->red_cap);
+    batch_build(*B);
+    set_red_block_cap(saved);
+    for (int i = 0; i < n; ++i) B->S[i]->outer_flags = nullptr;
+    HIPC(hipStreamSynchronize(B->st));
+  } catch (...) {
+    delete B;
+    throw;
+  }
+  *out = B;
+  AMG_CATCH
+}
+
+amg_status amg_batch_solve(amg_batch* B, const void* const* dev_chi, void* const* dev_psi, double tol, int max_iter,
+                           amg_solve_info* info, void* stream) {
+  AMG_TRY
+  check_ptr(B, "batch");
+  check_ptr(dev_chi, "chi");
+  check_ptr(dev_psi, "psi");
+  if (!(tol > 0.0) || max_iter < 0) fail(AMG_ERR_ARG, "bad tol / max_iter");
+  const auto t0 = std::chrono::steady_clock::now();
+  HIPC(hipStreamSynchronize(as_stream(stream)));
+  for (int i = 0; i < B->n; ++i) {
+    check_ptr(dev_chi[i], "chi[i]");
+    check_ptr(dev_psi[i], "psi[i]");
+    to_internal<double>(*B->S[i], 0, (const double2*)dev_chi[i], B->S[i]->ob.as<double2>(), B->nrhs[i], B->st);
+  }
+  BatchResult R = batch_run(*B, tol, max_iter);
+  for (int i = 0; i < B->n; ++i)
+    to_canonical<double>(*B->S[i], 0, B->S[i]->ox.as<double2>(), (double2*)dev_psi[i], B->nrhs[i], B->st);
+  HIPC(hipStreamSynchronize(B->st));
+  const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  bool all = true;
+  for (size_t q = 0; q < R.rel.size(); ++q) {
+    all = all && R.done[q];
+    if (info) {
+      info[q].iters = R.iters[q];
+      info[q].converged = R.done[q];
+      info[q].true_rel_res = R.rel[q];
+      info[q].n_fine_D = info[q].n_fine_Ddag = info[q].n_coarse = 0;
+      info[q].t_ms = ms;
+    }
+  }
+  if (!all) fail(AMG_ERR_NOCONV, "batched FGCR did not reach the tolerance for every right-hand side");
+  AMG_CATCH
+}
+
+amg_status amg_batch_info(const amg_batch* B, int* red_cap, int* stages_per_iteration) {
+  AMG_TRY
+  check_ptr(B, "batch");
+  if (red_cap) *red_cap = B->red_cap;
+  if (stages_per_iteration) *stages_per_iteration = B->iters.empty() ? 0 : (int)B->iters[0].ops.size();
+  AMG_CATCH
+}
+
+amg_status amg_batch_destroy(amg_batch* B) {
+  AMG_TRY
+  delete B;
   AMG_CATCH
 }
 

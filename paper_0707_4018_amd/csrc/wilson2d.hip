@@ -15,6 +15,7 @@
 // These are Layout{V, 2, W} with W = 1 (FP64) and W = 2 (FP32).
 #include "common.h"
 #include "kernels.h"
+#include "dispatch.h"
 
 namespace amg {
 namespace {
@@ -76,15 +77,20 @@ __device__ __forceinline__ void sub_half(Sp2<T>& o, const Sp2<T>& h) {
 }
 
 template <typename T, int DAG, int EPI>
-__global__ __launch_bounds__(256) void wilson2d_kernel(
-    cplx<T>* __restrict__ out, const cplx<T>* __restrict__ in, const cplx<T>* __restrict__ bvec,
-    cplx<T>* __restrict__ copy_out, const cplx<T>* __restrict__ U, T diag, int L1, int L2,
-    RedArgs red) {
+__global__ __launch_bounds__(256) void wilson2d_kernel(WilsonArgs<T> a0, const WilsonArgs<T>* batch) {
+  AMG_ARGS(WilsonArgs<T>)
   const int rhs = blockIdx.y;
+  const RedArgs& red = a.red;
   if (skip_rhs(red.flags, rhs)) return;
+  const int L1 = a.L1, L2 = a.L2;
   const long V = (long)L1 * L2;
   const long ro = (long)rhs * 2 * V;
-  const cplx<T>* __restrict__ pin = in + ro;
+  const cplx<T>* __restrict__ pin = a.in + ro;
+  const cplx<T>* __restrict__ U = a.U;
+  const cplx<T>* __restrict__ bvec = a.b;
+  cplx<T>* __restrict__ out = a.out;
+  cplx<T>* __restrict__ copy_out = a.copy_out;
+  const T diag = (T)(2.0 + a.mass);
   Hops<T, DAG> H{V, L1, L2};
   const T sf = DAG ? (T)1 : (T)-1;  // forward projector 1 + sf gamma
   const T sb = -sf;
@@ -162,12 +168,9 @@ template <typename T>
 void launch_wilson2d(const WilsonArgs<T>& a, int dagger, int epi, hipStream_t st) {
   const long V = (long)a.L1 * a.L2;
   long nb = (V + 255) / 256;
-  if (epi == EPI_MRDOT || epi == EPI_NORM) nb = nb < RED_MAX_BLOCKS ? nb : RED_MAX_BLOCKS;
+  if (epi == EPI_MRDOT || epi == EPI_NORM) nb = nb < red_block_cap() ? nb : red_block_cap();
   dim3 grid((unsigned)nb, (unsigned)a.nrhs);
-  const T diag = (T)(2.0 + a.mass);
-#define AMG_W2(DAG, EPI)                                                                         \
-  hipLaunchKernelGGL((wilson2d_kernel<T, DAG, EPI>), grid, dim3(256), 0, st, a.out, a.in, a.b, \
-                     a.copy_out, a.U, diag, a.L1, a.L2, a.red)
+#define AMG_W2(DAG, EPI) dispatch(wilson2d_kernel<T, DAG, EPI>, a, grid, dim3(256), st)
   if (dagger) {
     switch (epi) {
       case EPI_PLAIN: AMG_W2(1, EPI_PLAIN); break;

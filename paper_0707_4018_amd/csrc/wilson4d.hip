@@ -19,6 +19,7 @@
 //   links: 36 planes [mu*9 + a*3 + b][site] (double2 / float2)
 #include "common.h"
 #include "kernels.h"
+#include "dispatch.h"
 
 namespace amg {
 namespace {
@@ -152,15 +153,28 @@ __device__ __forceinline__ void all_hops(Spinor<T>& o, const cplx<T>* __restrict
 #undef AMG_HOP4
 }
 
+Geo4 geo(const int* d);
+
 template <typename T, int DAG, int EPI>
-__global__ __launch_bounds__(256) void wilson4d_kernel(cplx<T>* __restrict__ out, const cplx<T>* __restrict__ in,
-                                                       const cplx<T>* __restrict__ bvec, cplx<T>* __restrict__ copy_out,
-                                                       const cplx<T>* __restrict__ U, T diag, Geo4 G, long V,
-                                                       RedArgs red) {
+__global__ __launch_bounds__(256) void wilson4d_kernel(WilsonArgs<T> a0, const WilsonArgs<T>* batch) {
+  AMG_ARGS(WilsonArgs<T>)
   const int rhs = blockIdx.y;
+  const RedArgs& red = a.red;
   if (skip_rhs(red.flags, rhs)) return;
+  const int d4[4] = {a.L1, a.L2, a.L3, a.L4};
+  Geo4 G;
+  {
+    long st = 1;
+    for (int mu = 0; mu < 4; ++mu) { G.L[mu] = d4[mu]; G.st[mu] = st; st *= d4[mu]; }
+  }
+  const long V = (long)a.L1 * a.L2 * a.L3 * a.L4;
   const long ro = (long)rhs * 12 * V;
-  const cplx<T>* __restrict__ pin = in + ro;
+  const cplx<T>* __restrict__ pin = a.in + ro;
+  const cplx<T>* __restrict__ U = a.U;
+  const cplx<T>* __restrict__ bvec = a.b;
+  cplx<T>* __restrict__ out = a.out;
+  cplx<T>* __restrict__ copy_out = a.copy_out;
+  const T diag = (T)(4.0 + a.mass);
   double acc[3] = {0.0, 0.0, 0.0};
   for (long s = (long)blockIdx.x * blockDim.x + threadIdx.x; s < V; s += (long)gridDim.x * blockDim.x) {
     long fw[4], bw[4];
@@ -288,15 +302,11 @@ Geo4 geo(const int* d) {
 
 template <typename T>
 void launch_wilson4d(const WilsonArgs<T>& a, int dagger, int epi, hipStream_t st) {
-  const int d[4] = {a.L1, a.L2, a.L3, a.L4};
-  const Geo4 G = geo(d);
   const long V = (long)a.L1 * a.L2 * a.L3 * a.L4;
   long nb = (V + 255) / 256;
-  if (epi == EPI_MRDOT || epi == EPI_NORM) nb = nb < RED_MAX_BLOCKS ? nb : RED_MAX_BLOCKS;
+  if (epi == EPI_MRDOT || epi == EPI_NORM) nb = nb < red_block_cap() ? nb : red_block_cap();
   dim3 grid((unsigned)nb, (unsigned)a.nrhs);
-  const T diag = (T)(4.0 + a.mass);
-#define AMG_W4(DAG, EPI) \
-  hipLaunchKernelGGL((wilson4d_kernel<T, DAG, EPI>), grid, dim3(256), 0, st, a.out, a.in, a.b, a.copy_out, a.U, diag, G, V, a.red)
+#define AMG_W4(DAG, EPI) dispatch(wilson4d_kernel<T, DAG, EPI>, a, grid, dim3(256), st)
   if (dagger) {
     switch (epi) {
       case EPI_PLAIN: AMG_W4(1, EPI_PLAIN); break;
