@@ -36,6 +36,7 @@ import synth  # noqa: E402
 
 L = 256
 BETAS = [3.0, 6.0, 10.0]
+BETAS_ALL = list(BETAS)
 TOL = 1e-10
 HBM_PEAK_GBS = 8000.0
 WORKLOADS = json.load(open(os.path.join(ROOT, "synth", "workloads.json")))
@@ -125,6 +126,93 @@ class Job:
                 prof[1] += n
                 self.solvers[beta] = S
         return setup_ms, solve_ms, recs, prof
+
+
+# ---------------------------------------------------------------------------
+# batched workload: 64 independent solves of uneven lattice sizes
+# ---------------------------------------------------------------------------
+NBATCH = 64
+BATCH_SWEEPS = 50
+
+
+def _mcrit_interp(beta):
+    """m_crit interpolated (linear in 1/beta) between the three 256^2 ensembles."""
+    bs = np.array(BETAS_ALL)
+    mc = np.array([workload(b)["m_crit"] for b in BETAS_ALL])
+    return float(np.interp(1.0 / beta, (1.0 / bs)[::-1], mc[::-1]))
+
+
+def batch_instance(i):
+    """Seeded instance i: lattice L x L (L = 16 round(exp(U(ln 64, ln 512)) / 16)),
+    beta ~ U[3, 10], mass m_crit(beta) + 0.02, nrhs ~ U{1..8}."""
+    rng = synth.rng_for(4, i)
+    L = int(16 * round(np.exp(rng.uniform(np.log(64), np.log(512))) / 16))
+    beta = float(rng.uniform(3.0, 10.0))
+    nrhs = int(rng.integers(1, 9))
+    return L, beta, nrhs
+
+
+def gen_batch_config(i):
+    L, beta, nrhs = batch_instance(i)
+    th = synth.u1_heatbath(L, L, beta, BATCH_SWEEPS, synth.rng_for(4, i, 1))
+    return i, th
+
+
+def batch_bench(amg, torch, bfields, mixed=True):
+    insts = [batch_instance(i) for i in range(NBATCH)]
+    params = amg.MGParams(blocks=[(4, 4), (4, 4)], nvec=[8, 8], nu_pre=2, nu_post=2, omega=0.8, coarse_tol=0.2,
+                          coarse_maxiter=100, coarse_restart=16, outer_restart=16, kcycle_tol=0.1, kcycle_maxiter=8,
+                          inner_prec=amg.F32 if mixed else amg.F64, p_bf16=mixed)
+    solvers, chis = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i, (L, beta, nrhs) in enumerate(insts):
+        U = torch.from_numpy(np.exp(1j * bfields[i])[..., None, None].copy()).cuda()
+        g = amg.Gauge(U, _mcrit_interp(beta) + 0.02)
+        init = [np.stack([synth.gaussian_field((L * L, 2), synth.rng_for(4, 7, i, 0, k)) for k in range(8)]),
+                np.stack([synth.gaussian_field(((L // 4) ** 2, 16), synth.rng_for(4, 7, i, 1, k)) for k in range(8)])]
+        solvers.append(amg.Solver(g, params, init=[torch.from_numpy(v).cuda() for v in init], nu0=20, ncyc=2))
+        chis.append(torch.from_numpy(synth.gaussian_field((nrhs, L * L, 2, 1), synth.rng_for(4, 9, i))).cuda())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    nsol = sum(n for _, _, n in insts)
+    # sequential loop of the same library, one instance after the other
+    seq_iters = []
+    for S, c in zip(solvers, chis):
+        S.solve(c, tol=TOL, max_iter=500)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for S, c in zip(solvers, chis):
+        _, info = S.solve(c, tol=TOL, max_iter=500)
+        seq_iters.append(info[0].iters)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    B = amg.Batch(solvers, [n for _, _, n in insts], autotune=True)
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    B.solve(chis, tol=TOL, max_iter=500)
+    torch.cuda.synchronize()
+    t5 = time.perf_counter()
+    psis, infos = B.solve(chis, tol=TOL, max_iter=500)
+    torch.cuda.synchronize()
+    t6 = time.perf_counter()
+    worst = max(i.true_rel_res for i in infos)
+    return {
+        "workload": f"{NBATCH} independent 2d U(1) solves, L in [64, 512] (log-uniform, multiples of 16), "
+                    f"beta ~ U[3, 10], m = m_crit(beta) + 0.02, 1-8 Gaussian rhs each ({nsol} rhs, "
+                    f"{sum(L * L for L, _, _ in insts)} fine sites); 3-level MG 4x4 then 4x4 blocks, mixed precision",
+        "rhs_total": nsol,
+        "batched_solves_per_s": round(nsol / (t6 - t5), 2),
+        "sequential_solves_per_s": round(nsol / (t3 - t2), 2),
+        "speedup_batched_vs_sequential": round((t3 - t2) / (t6 - t5), 3),
+        "batched_ms": round(1e3 * (t6 - t5), 1), "sequential_ms": round(1e3 * (t3 - t2), 1),
+        "setup_ms_all_instances": round(1e3 * (t1 - t0), 1),
+        "batch_create_ms_incl_autotune": round(1e3 * (t4 - t3), 1),
+        "autotuned": B.info(),
+        "outer_iterations_max": max(i.iters for i in infos),
+        "worst_true_rel_res": worst,
+        "all_converged": all(i.converged for i in infos),
+    }
 
 
 def stencil_bench(amg, torch, th, iters=40):
@@ -267,6 +355,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-stencil", action="store_true")
     ap.add_argument("--betas", type=str, default=None, help="comma-separated subset of the ensembles")
+    ap.add_argument("--no-batch", action="store_true")
     args = ap.parse_args()
     global BETAS
     if args.betas:
@@ -276,9 +365,12 @@ def main():
                                    "decomposition is described in the design notes, not built)"}))
         sys.exit(2)
 
-    log("generating gauge ensembles (heat-bath, 3 workers)")
-    with cf.ProcessPoolExecutor(max_workers=len(BETAS)) as ex:
-        fields = dict(ex.map(gen_config, BETAS))
+    log("generating gauge ensembles (heat-bath, worker processes)")
+    with cf.ProcessPoolExecutor(max_workers=16) as ex:
+        fut = {b: ex.submit(gen_config, b) for b in BETAS}
+        bfut = [] if args.no_batch else [ex.submit(gen_batch_config, i) for i in range(NBATCH)]
+        fields = dict(f.result() for f in fut.values())
+        bfields = dict(f.result() for f in bfut)
 
     import torch
     import paper_0707_4018_amd as amg
@@ -345,6 +437,9 @@ def main():
                           "setup_ms_per_ensemble": round(s64 / len(BETAS), 3),
                           "iters": [r["iters"] for r in recs64],
                           "speedup_mixed_vs_fp64": round(1e3 * (t3 - t2) / ms_per_step, 3)}
+    if not args.no_batch:
+        log("batched workload")
+        out["batched"] = batch_bench(amg, torch, bfields)
     if not args.no_stencil:
         log("stencil bandwidth")
         out["stencil"] = stencil_bench(amg, torch, fields[BETAS[-1]])
