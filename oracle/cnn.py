@@ -146,9 +146,11 @@ def projection_loss(pred: np.ndarray, target: np.ndarray, dims, block=(4, 4), ep
 
     For every block S_j and chirality s (spin component s in two dimensions),
     with V_p the block-restricted predicted vectors (columns) and t_k the
-    target ones: L_js = sum_k ||(1 - Pi) t_k||^2 / ||t_k||^2 with
-    Pi = V_p (V_p^dag V_p + eps 1)^-1 V_p^dag.  The loss is the mean over
-    (blocks, chiralities, target vectors).  The span, not the basis, is what
+    target ones: L_js = sum_k (1 - t_k^dag Pi t_k / ||t_k||^2) with
+    Pi = V_p (V_p^dag V_p + eps 1)^-1 V_p^dag, which at eps = 0 is the
+    squared relative distance ||(1 - Pi) t_k||^2 / ||t_k||^2 of t_k from the
+    predicted span.  The loss is the mean over (blocks, chiralities, target
+    vectors).  The span, not the basis, is what
     the prolongator uses, so the loss is invariant under any invertible mixing
     of the predicted vectors within a block (up to eps).
 

@@ -17,8 +17,19 @@
 #include "amg.h"
 #include "kernels.h"
 #include "dispatch.h"
+#include "hostutil.h"
 
 using namespace amg;
+using namespace amg::host;
+
+namespace amg {
+namespace host {
+std::string& last_error() {
+  thread_local std::string msg;
+  return msg;
+}
+}  // namespace host
+}  // namespace amg
 
 namespace amg {
 Recorder*& current_recorder() {
@@ -33,47 +44,6 @@ void set_red_block_cap(int cap) { g_red_cap = std::max(16, std::min(RED_MAX_BLOC
 }  // namespace amg
 
 namespace {
-
-thread_local std::string g_last_error;
-
-struct Fail {
-  amg_status s;
-  std::string msg;
-};
-
-[[noreturn]] void fail(amg_status s, const std::string& m) { throw Fail{s, m}; }
-
-void hip_check(hipError_t e, const char* what) {
-  if (e != hipSuccess) fail(AMG_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
-}
-#define HIPC(x) hip_check((x), #x)
-
-// Owned device allocation.
-struct Buf {
-  void* p = nullptr;
-  size_t bytes = 0;
-  Buf() = default;
-  Buf(const Buf&) = delete;
-  Buf& operator=(const Buf&) = delete;
-  Buf(Buf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
-  ~Buf() { release(); }
-  void release() {
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    bytes = 0;
-  }
-  void ensure(size_t n) {
-    if (n <= bytes && p) return;
-    release();
-    if (n == 0) n = 16;
-    if (hipMalloc(&p, n) != hipSuccess) {
-      p = nullptr;
-      fail(AMG_ERR_NOMEM, "hipMalloc of " + std::to_string(n) + " bytes failed");
-    }
-    bytes = n;
-  }
-  template <typename T> T* as() const { return reinterpret_cast<T*>(p); }
-};
 
 template <typename T> struct Pick;
 template <> struct Pick<double> { static constexpr int prec = AMG_F64; };
@@ -763,6 +733,33 @@ void adaptive_level(Solver& S, int l, const void* dev_init, int nu0, int ncyc, h
   }
 }
 
+// ---- convergence factor of the method as a stationary iteration ----------------
+// e <- e - M(D e) from e0 (canonical); returns (|e_n| / |e_0|)^(1/n).
+void precondition(Solver& S, const double2* r, double2* z, int nrhs, hipStream_t st);
+
+double mg_convergence(Solver& S, const double2* e0, int iters, hipStream_t st) {
+  ensure_work(S, 1);
+  Level& F = S.lv[0];
+  const long n = F.per_rhs();
+  double2* e = S.ox.as<double2>();
+  double2* t = S.ob.as<double2>();
+  double2* z = S.otmp.as<double2>();
+  const int slot = S.og.rr;
+  to_internal<double>(S, 0, e0, e, 1, st);
+  launch_norm2<double>(e, n, 1, S.sc.red(slot), st);
+  const double n0 = S.sc.fetch(slot, 1, st)[0];
+  if (!(n0 > 0.0) || !std::isfinite(n0)) fail(AMG_ERR_ARG, "starting error must be finite and nonzero");
+  for (int i = 0; i < iters; ++i) {
+    op_apply<double>(S, 0, 0, EPI_PLAIN, e, t, nullptr, nullptr, 1, S.sc.red(0), st);
+    precondition(S, t, z, 1, st);
+    launch_axpy<double>(e, z, -1.0, 0.0, n, 1, st);
+  }
+  launch_norm2<double>(e, n, 1, S.sc.red(slot), st);
+  const double n1 = S.sc.fetch(slot, 1, st)[0];
+  if (!std::isfinite(n1)) fail(AMG_ERR_NAN, "non-finite error in the convergence test");
+  return std::pow(std::sqrt(n1 / n0), 1.0 / iters);
+}
+
 // ---- outer FGCR (fine level, FP64) ------------------------------------------
 struct OuterResult {
   int iters = 0;
@@ -1127,18 +1124,7 @@ BatchResult batch_run(Batch& B, double tol, int maxiter) {
 // ===========================================================================
 // C ABI
 // ===========================================================================
-#define AMG_TRY try {
-#define AMG_CATCH                                              \
-  }                                                            \
-  catch (const Fail& f) {                                      \
-    g_last_error = f.msg;                                      \
-    return f.s;                                                \
-  }                                                            \
-  catch (const std::exception& e) {                            \
-    g_last_error = e.what();                                   \
-    return AMG_ERR_HIP;                                        \
-  }                                                            \
-  return AMG_OK;
+
 
 extern "C" {
 
@@ -1157,7 +1143,7 @@ const char* amg_status_str(amg_status s) {
   return "unknown status";
 }
 
-const char* amg_last_error(void) { return g_last_error.c_str(); }
+const char* amg_last_error(void) { return last_error().c_str(); }
 
 void amg_default_params(amg_mg_params* p) {
   if (!p) return;
@@ -1398,6 +1384,32 @@ amg_status amg_setup_adaptive(const amg_gauge* g, const amg_mg_params* p, const 
   AMG_CATCH
 }
 
+amg_status amg_setup_adaptive_levels(const amg_gauge* g, const amg_mg_params* p, const void* const* dev_init,
+                                     const int* nu0, const int* ncyc, void* stream, amg_solver** out) {
+  AMG_TRY
+  check_ptr(out, "out");
+  check_ptr(dev_init, "init");
+  check_ptr(nu0, "nu0");
+  check_ptr(ncyc, "ncyc");
+  Solver* S = new_solver(g, p);
+  hipStream_t st = as_stream(stream);
+  try {
+    ensure_work(*S, 1);
+    for (int l = 0; l + 1 < (int)S->lv.size(); ++l) {
+      check_ptr(dev_init[l], "init[l]");
+      if (nu0[l] < 0 || ncyc[l] < 0) fail(AMG_ERR_ARG, "nu0 / ncyc must be >= 0");
+      adaptive_level(*S, l, dev_init[l], nu0[l], ncyc[l], st);
+    }
+    HIPC(hipStreamSynchronize(st));
+  } catch (...) {
+    (void)hipStreamSynchronize(st);
+    delete S;
+    throw;
+  }
+  *out = S;
+  AMG_CATCH
+}
+
 amg_status amg_solver_set_mass(amg_solver* S, double mass) {
   AMG_TRY
   check_ptr(S, "solver");
@@ -1609,6 +1621,79 @@ amg_status amg_level_info(const amg_solver* S, int level, int* dims4, int* dof, 
     for (int mu = 0; mu < 4; ++mu) dims4[mu] = L.dims[mu];
   if (dof) *dof = L.dof;
   if (V) *V = L.V;
+  AMG_CATCH
+}
+
+amg_status amg_mg_convergence(amg_solver* S, const void* dev_e0, int iters, double* rho, void* stream) {
+  AMG_TRY
+  check_ptr(S, "solver");
+  check_ptr(dev_e0, "e0");
+  check_ptr(rho, "rho");
+  if (iters < 1 || iters > 1000) fail(AMG_ERR_ARG, "iters must be 1..1000");
+  *rho = mg_convergence(*S, (const double2*)dev_e0, iters, as_stream(stream));
+  AMG_CATCH
+}
+
+amg_status amg_setup_learned(const amg_gauge* g, const amg_mg_params* p, amg_cnn* net, const void* const* dev_init,
+                             int nu0_ref, int ncyc_ref, double rho_max, int nu0, int ncyc, void* stream,
+                             amg_solver** out, int* fell_back, double* rho) {
+  AMG_TRY
+  check_ptr(g, "gauge");
+  check_ptr(p, "params");
+  check_ptr(net, "network");
+  check_ptr(dev_init, "init");
+  check_ptr(out, "out");
+  if (g->nd != 2) fail(AMG_ERR_ARG, "the learned setup is two-dimensional (U(1)) only");
+  if (p->nvec[0] < 1 || p->nvec[0] > 8) fail(AMG_ERR_ARG, "the network proposes 8 vectors; nvec[0] must be <= 8");
+  if (nu0_ref < 0 || ncyc_ref < 0 || nu0 < 0 || ncyc < 0) fail(AMG_ERR_ARG, "nu0 / ncyc must be >= 0");
+  if (!(rho_max > 0.0)) fail(AMG_ERR_ARG, "rho_max must be positive");
+  for (int l = 0; l + 1 < p->nlevels; ++l) check_ptr(dev_init[l], "init[l]");
+  hipStream_t st = as_stream(stream);
+  Buf prop;
+  prop.ensure((size_t)8 * g->V * 2 * sizeof(double2));
+  const amg_status ps = amg_cnn_propose(net, g->U64.p, g->dims[0], g->dims[1], prop.p, stream);
+  if (ps != AMG_OK) fail(ps, "amg_cnn_propose: " + last_error());
+  auto build = [&](bool learned) {
+    Solver* S = new_solver(g, p);
+    try {
+      ensure_work(*S, 1);
+      for (int l = 0; l + 1 < (int)S->lv.size(); ++l) {
+        if (learned && l == 0) adaptive_level(*S, 0, prop.p, nu0_ref, ncyc_ref, st);
+        else adaptive_level(*S, l, dev_init[l], nu0, ncyc, st);
+      }
+      HIPC(hipStreamSynchronize(st));
+    } catch (...) {
+      (void)hipStreamSynchronize(st);
+      delete S;
+      throw;
+    }
+    return S;
+  };
+  Solver* S = nullptr;
+  double r = 0.0;
+  int fb = 0;
+  try {
+    S = build(true);
+    r = mg_convergence(*S, (const double2*)dev_init[0], 3, st);
+    if (!(r <= rho_max)) fb = 1;
+  } catch (const Fail& f) {
+    if (f.s != AMG_ERR_RANK && f.s != AMG_ERR_NAN) throw;
+    fb = 1;
+  }
+  if (fb) {
+    delete S;
+    S = nullptr;
+    S = build(false);
+    try {
+      r = mg_convergence(*S, (const double2*)dev_init[0], 3, st);
+    } catch (...) {
+      delete S;
+      throw;
+    }
+  }
+  if (fell_back) *fell_back = fb;
+  if (rho) *rho = r;
+  *out = S;
   AMG_CATCH
 }
 
