@@ -145,6 +145,11 @@ amg_status amg_setup_adaptive(const amg_gauge* g, const amg_mg_params* p,
                               const void* const* dev_init, int nu0, int ncyc,
                               void* stream, amg_solver** out);
 
+/* As amg_setup_adaptive with per-coarsening counts nu0[l], ncyc[l]. */
+amg_status amg_setup_adaptive_levels(const amg_gauge* g, const amg_mg_params* p,
+                                     const void* const* dev_init, const int* nu0, const int* ncyc,
+                                     void* stream, amg_solver** out);
+
 /* Reuse the setup at another fine mass: every level's diagonal shifts by
  * (mass - current) P^dag ... P 1 P ... P (exact, also for a rounded P). */
 amg_status amg_solver_set_mass(amg_solver* s, double mass);
@@ -224,6 +229,91 @@ amg_status amg_profile_read(amg_solver* s, double* total_ms, long long* launches
 
 /* Introspection: lattice extents and dof per site of a level. */
 amg_status amg_level_info(const amg_solver* s, int level, int* dims4, int* dof, long long* V);
+
+/* Convergence factor of the multigrid method as a stationary iteration,
+ * e <- e - M(D e) with M one V-cycle (the test of the adaptive construction,
+ * text after Eq. (5): a random error either decays quickly or survives).
+ * Starts from the canonical complex128 fine field dev_e0 (not modified),
+ * runs `iters` >= 1 iterations and returns
+ * rho = (|e_iters| / |e_0|)^(1/iters).  Synchronous. */
+amg_status amg_mg_convergence(amg_solver* s, const void* dev_e0, int iters, double* rho, void* stream);
+
+/* ---- learned setup (two-dimensional U(1) only) -------------------------------
+ * A local convolutional network proposes the initial near-null vectors of
+ * the finest coarsening, which the adaptive procedure (Eq. (4) and the text
+ * after Eq. (5)) then refines.  The network is not part of the paper; it is
+ * trained on near-null vectors that the adaptive setup itself produced.
+ *
+ * Network: four 3x3 convolutions with periodic padding, channels
+ * 4 -> 64 -> 64 -> 64 -> 32, tanh after the first three.  Input per site:
+ * (cos, sin) of both link angles after a block-local tree gauge fixing
+ * (4x4 blocks; the x_1 links along every block row and the x_2 links along
+ * the first block column are set to 1 by g = exp(i phi), phi = 0 at the
+ * block origin).  Output channel 4k + 2s + c is component c (re, im) of spin
+ * s of proposal k = 0..7 in the fixed gauge; proposals are returned in the
+ * original gauge, v = g^dag v'.
+ *
+ * Parameters (amg_cnn_num_params() floats, 94,688): for each layer the
+ * weights W[c_out][c_in][3][3] (y(i,j) += W[o][c][di][dj] x(i+di-1, j+dj-1),
+ * i = x_2 row, j = x_1 column) then the biases b[c_out].  FP32 master copy
+ * with Adam moments; activations and the compute copy of the weights in
+ * bfloat16 (bf16 != 0) or FP32, accumulation in FP32.
+ *
+ * Loss (mean over configurations, 4x4 blocks, spin s and targets k): with V
+ * the 16 x 8 block restriction of the predictions of spin s and t_k the
+ * normalised block restriction of target k, 1 - t_k^dag V (V^dag V + 1e-3)^-1 V^dag t_k,
+ * i.e. how much of each target lies outside the predicted block span (the
+ * prolongator of Eq. (5) only depends on that span).  Evaluated in FP64.
+ *
+ * Links: dev_links[b] is one configuration in the canonical gauge layout,
+ * [B][2][L2*L1] complex128 of unit modulus.  Targets: dev_vecs[b][8][L2*L1][2]
+ * complex128 canonical (what amg_get_nullvecs returns for level 0).  L1, L2
+ * multiples of 16.  Calls with gradients or training synchronise `stream`. */
+typedef struct amg_cnn amg_cnn;
+long long amg_cnn_num_params(void);
+amg_status amg_cnn_create(const float* host_params, int bf16, amg_cnn** out);
+amg_status amg_cnn_destroy(amg_cnn* n);
+amg_status amg_cnn_get_params(const amg_cnn* n, float* host_out);
+amg_status amg_cnn_set_params(amg_cnn* n, const float* host_params);
+/* Network output for B configurations, dev_out[B][32][L2][L1] float32. */
+amg_status amg_cnn_forward(amg_cnn* n, const void* dev_links, int B, int L1, int L2, float* dev_out, void* stream);
+/* Mean loss and (host_grads != NULL) its gradient, amg_cnn_num_params() floats
+ * in parameter order; parameters unchanged. */
+amg_status amg_cnn_loss_grad(amg_cnn* n, const void* dev_links, const void* dev_vecs, int B, int L1, int L2,
+                             double* loss, float* host_grads, void* stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the mean loss of the
+ * batch; returns the loss before the step.  AMG_ERR_NAN leaves the
+ * parameters unchanged. */
+amg_status amg_cnn_train_step(amg_cnn* n, const void* dev_links, const void* dev_vecs, int B, int L1, int L2,
+                              float lr, double* loss, void* stream);
+/* 8 proposals for one configuration, dev_vecs_out[8][L2*L1][2] complex128. */
+amg_status amg_cnn_propose(amg_cnn* n, const void* dev_links, int L1, int L2, void* dev_vecs_out, void* stream);
+
+/* Setup from given starting vectors for the finest coarsening (e.g. the
+ * network's proposals).  Level 0: vectors 0..n_start-1 are the first n_start
+ * canonical complex128 fields of dev_start0 ([n][V][dof]), each relaxed by
+ * nu_ref MR steps on D v = 0 (Eq. (4)); vectors n_start..nvec[0]-1 come from
+ * one adaptive iteration each (text after Eq. (5)): dev_init[0][k - n_start]
+ * after ncyc_ref sweeps of the two-level error propagation e <- e - V(D e)
+ * built from the vectors before it.  Deeper coarsenings l >= 1: adaptive
+ * setup from dev_init[l] with (nu0, ncyc).  1 <= n_start <= nvec[0].
+ * Synchronous. */
+amg_status amg_setup_refined(const amg_gauge* g, const amg_mg_params* p, const void* dev_start0,
+                             int n_start, int nu_ref, int ncyc_ref, const void* const* dev_init,
+                             int nu0, int ncyc, void* stream, amg_solver** out);
+
+/* Learned setup: amg_setup_refined from the network's proposals for g's
+ * links (n_start <= 8 of them).  If that fails (dependent vectors, non-finite
+ * values) or, with rho_iters > 0, the convergence factor of the resulting
+ * method measured from dev_init[0][0] over rho_iters iterations
+ * (amg_mg_convergence) exceeds rho_max, the plain adaptive setup from
+ * dev_init with (nu0, ncyc) is built instead and *fell_back is set to 1.
+ * *rho gets the factor of the returned hierarchy (-1 when not measured).
+ * Synchronous. */
+amg_status amg_setup_learned(const amg_gauge* g, const amg_mg_params* p, amg_cnn* net,
+                             const void* const* dev_init, int n_start, int nu_ref, int ncyc_ref,
+                             double rho_max, int rho_iters, int nu0, int ncyc, void* stream,
+                             amg_solver** out, int* fell_back, double* rho);
 
 #ifdef __cplusplus
 }

@@ -9,5 +9,5 @@ Method: Brannick, Brower, Clark, Osborn, Rebbi, "Adaptive Multigrid Algorithm
 for Lattice QCD", arXiv:0707.4018.
 """
 from .binding import (  # noqa: F401
-    AMGError, Batch, Gauge, MGParams, Solver, SolveInfo, F32, F64, lib_path, load_library,
+    AMGError, Batch, Cnn, Gauge, MGParams, Solver, SolveInfo, F32, F64, lib_path, load_library,
 )

@@ -83,6 +83,24 @@ _SIGS = {
     "amg_batch_info": (C.c_int, [_P, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "amg_batch_destroy": (C.c_int, [_P]),
     "amg_profile_read": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_longlong)]),
+    "amg_setup_adaptive_levels": (C.c_int, [_P, C.POINTER(_Params), C.POINTER(_P), C.POINTER(C.c_int),
+                                            C.POINTER(C.c_int), _P, C.POINTER(_P)]),
+    "amg_setup_refined": (C.c_int, [_P, C.POINTER(_Params), _P, C.c_int, C.c_int, C.c_int, C.POINTER(_P), C.c_int,
+                                    C.c_int, _P, C.POINTER(_P)]),
+    "amg_mg_convergence": (C.c_int, [_P, _P, C.c_int, C.POINTER(C.c_double), _P]),
+    "amg_cnn_num_params": (C.c_longlong, []),
+    "amg_cnn_create": (C.c_int, [C.POINTER(C.c_float), C.c_int, C.POINTER(_P)]),
+    "amg_cnn_destroy": (C.c_int, [_P]),
+    "amg_cnn_get_params": (C.c_int, [_P, C.POINTER(C.c_float)]),
+    "amg_cnn_set_params": (C.c_int, [_P, C.POINTER(C.c_float)]),
+    "amg_cnn_forward": (C.c_int, [_P, _P, C.c_int, C.c_int, C.c_int, _P, _P]),
+    "amg_cnn_loss_grad": (C.c_int, [_P, _P, _P, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double),
+                                    C.POINTER(C.c_float), _P]),
+    "amg_cnn_train_step": (C.c_int, [_P, _P, _P, C.c_int, C.c_int, C.c_int, C.c_float, C.POINTER(C.c_double), _P]),
+    "amg_cnn_propose": (C.c_int, [_P, _P, C.c_int, C.c_int, _P, _P]),
+    "amg_setup_learned": (C.c_int, [_P, C.POINTER(_Params), _P, C.POINTER(_P), C.c_int, C.c_int, C.c_int,
+                                    C.c_double, C.c_int, C.c_int, C.c_int, _P, C.POINTER(_P), C.POINTER(C.c_int),
+                                    C.POINTER(C.c_double)]),
 }
 
 
@@ -239,7 +257,9 @@ class Gauge:
 class Solver:
     """Multigrid hierarchy + FGCR solver bound to a Gauge."""
 
-    def __init__(self, gauge: Gauge, params: MGParams, nullvecs=None, init=None, nu0: int = 20, ncyc: int = 2):
+    def __init__(self, gauge: Gauge, params: MGParams, nullvecs=None, init=None, nu0=20, ncyc=2):
+        """Setup from given near-null vectors, or adaptive from random `init`
+        (nu0 / ncyc: one count for every level or a list per level)."""
         lib = load_library()
         self.gauge = gauge
         self.params = params
@@ -253,8 +273,16 @@ class Solver:
         elif init is not None:
             vs = [v.contiguous() for v in init]
             arr = (C.c_void_p * len(vs))(*[_ptr(v).value for v in vs])
-            _check(lib.amg_setup_adaptive(gauge.handle, C.byref(self._p), arr, int(nu0), int(ncyc), _stream(),
-                                          C.byref(h)), "amg_setup_adaptive")
+            if isinstance(nu0, (list, tuple)) or isinstance(ncyc, (list, tuple)):
+                nl = len(vs)
+                n0 = list(nu0) if isinstance(nu0, (list, tuple)) else [nu0] * nl
+                nc = list(ncyc) if isinstance(ncyc, (list, tuple)) else [ncyc] * nl
+                _check(lib.amg_setup_adaptive_levels(gauge.handle, C.byref(self._p), arr, (C.c_int * nl)(*n0),
+                                                     (C.c_int * nl)(*nc), _stream(), C.byref(h)),
+                       "amg_setup_adaptive_levels")
+            else:
+                _check(lib.amg_setup_adaptive(gauge.handle, C.byref(self._p), arr, int(nu0), int(ncyc), _stream(),
+                                              C.byref(h)), "amg_setup_adaptive")
             self._keep = vs
         else:
             raise ValueError("give nullvecs (setup) or init (adaptive setup)")
@@ -332,6 +360,62 @@ class Solver:
         _check(load_library().amg_get_nullvecs(self._h, level, _ptr(out), _stream()), "amg_get_nullvecs")
         return out
 
+    @classmethod
+    def _bare(cls, gauge: Gauge, params: MGParams):
+        self = cls.__new__(cls)
+        self.gauge = gauge
+        self.params = params
+        self._p = params.to_c()
+        self.mass = gauge.mass
+        return self
+
+    @classmethod
+    def refined(cls, gauge: Gauge, params: MGParams, start, n_start=None, nu_ref: int = 0, ncyc_ref: int = 2,
+                init=None, nu0: int = 20, ncyc: int = 2):
+        """Level 0 from the first n_start vectors of `start` (each relaxed by
+        nu_ref MR steps) plus nvec[0] - n_start adaptive iterations from
+        init[0]; deeper levels adaptive from init[l]."""
+        self = cls._bare(gauge, params)
+        st0 = start.contiguous()
+        n_start = params.nvec[0] if n_start is None else int(n_start)
+        vs = [v.contiguous() for v in (init or [st0])]
+        arr = (C.c_void_p * len(vs))(*[_ptr(v).value for v in vs])
+        h = C.c_void_p()
+        _check(load_library().amg_setup_refined(gauge.handle, C.byref(self._p), _ptr(st0), n_start, int(nu_ref),
+                                                 int(ncyc_ref), arr, int(nu0), int(ncyc), _stream(), C.byref(h)),
+               "amg_setup_refined")
+        self._keep = vs + [st0]
+        self._h = h
+        return self
+
+    @classmethod
+    def learned(cls, gauge: Gauge, params: MGParams, net: "Cnn", init, n_start=None, nu_ref: int = 0,
+                ncyc_ref: int = 2, rho_max: float = 0.5, rho_iters: int = 0, nu0: int = 20, ncyc: int = 2):
+        """amg_setup_learned: the network's proposals (n_start of them) plus
+        adaptive iterations for the rest, falling back to the plain adaptive
+        setup from `init`.  Returns (solver, fell_back, rho)."""
+        self = cls._bare(gauge, params)
+        n_start = params.nvec[0] if n_start is None else int(n_start)
+        vs = [v.contiguous() for v in init]
+        arr = (C.c_void_p * len(vs))(*[_ptr(v).value for v in vs])
+        h = C.c_void_p()
+        fb = C.c_int()
+        rho = C.c_double()
+        _check(load_library().amg_setup_learned(gauge.handle, C.byref(self._p), net.handle, arr, n_start,
+                                                 int(nu_ref), int(ncyc_ref), float(rho_max), int(rho_iters),
+                                                 int(nu0), int(ncyc), _stream(), C.byref(h), C.byref(fb),
+                                                 C.byref(rho)), "amg_setup_learned")
+        self._keep = vs
+        self._h = h
+        return self, bool(fb.value), rho.value
+
+    def convergence(self, e0: torch.Tensor, iters: int = 3) -> float:
+        """Convergence factor of e <- e - V(D e) from the fine field e0."""
+        rho = C.c_double()
+        _check(load_library().amg_mg_convergence(self._h, _ptr(e0.contiguous()), int(iters), C.byref(rho),
+                                                  _stream()), "amg_mg_convergence")
+        return rho.value
+
     PROF_FINE, PROF_COARSE, PROF_RESTRICT, PROF_PROLONG = 0, 1, 2, 3
 
     def profile(self, kind: int, level: int, enable: bool = True):
@@ -391,6 +475,98 @@ class Batch:
         try:
             if getattr(self, "_h", None):
                 load_library().amg_batch_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+
+def _fptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+class Cnn:
+    """The near-null-vector proposal network (two-dimensional U(1)).
+
+    Parameters travel as one flat float32 vector: per layer W[c_out][c_in][3][3]
+    then b[c_out].  Links: (B, 2, V) or (2, V) complex128 on the GPU; target
+    vectors (B, 8, V, 2) complex128 (level-0 near-null vectors)."""
+
+    CHANNELS = (4, 64, 64, 64, 32)
+
+    def __init__(self, params, bf16: bool = True):
+        import numpy as np
+        lib = load_library()
+        flat = np.ascontiguousarray(np.asarray(params, dtype=np.float32).ravel())
+        if flat.size != self.num_params():
+            raise ValueError(f"expected {self.num_params()} parameters, got {flat.size}")
+        h = C.c_void_p()
+        _check(lib.amg_cnn_create(_fptr(flat), int(bf16), C.byref(h)), "amg_cnn_create")
+        self._h = h
+        self.bf16 = bool(bf16)
+
+    @staticmethod
+    def num_params() -> int:
+        return int(load_library().amg_cnn_num_params())
+
+    @property
+    def handle(self):
+        return self._h
+
+    def params(self):
+        import numpy as np
+        out = np.empty(self.num_params(), dtype=np.float32)
+        _check(load_library().amg_cnn_get_params(self._h, _fptr(out)), "amg_cnn_get_params")
+        return out
+
+    def set_params(self, params):
+        import numpy as np
+        flat = np.ascontiguousarray(np.asarray(params, dtype=np.float32).ravel())
+        if flat.size != self.num_params():
+            raise ValueError("wrong parameter count")
+        _check(load_library().amg_cnn_set_params(self._h, _fptr(flat)), "amg_cnn_set_params")
+
+    @staticmethod
+    def _shape(links: torch.Tensor, L1: int, L2: int):
+        B = links.shape[0] if links.dim() == 3 else 1
+        if links.shape[-1] != L1 * L2 or links.shape[-2] != 2:
+            raise ValueError("links must be (B, 2, L1*L2)")
+        return B
+
+    def forward(self, links: torch.Tensor, L1: int, L2: int) -> torch.Tensor:
+        B = self._shape(links, L1, L2)
+        out = torch.empty((B, 32, L2, L1), dtype=torch.float32, device="cuda")
+        _check(load_library().amg_cnn_forward(self._h, _ptr(links.contiguous()), B, L1, L2,
+                                               _ptr(out, torch.float32), _stream()), "amg_cnn_forward")
+        return out
+
+    def loss_grad(self, links: torch.Tensor, vecs: torch.Tensor, L1: int, L2: int, grads: bool = True):
+        import numpy as np
+        B = self._shape(links, L1, L2)
+        loss = C.c_double()
+        g = np.empty(self.num_params(), dtype=np.float32) if grads else None
+        _check(load_library().amg_cnn_loss_grad(self._h, _ptr(links.contiguous()), _ptr(vecs.contiguous()), B, L1,
+                                                 L2, C.byref(loss), _fptr(g) if grads else None, _stream()),
+               "amg_cnn_loss_grad")
+        return loss.value, g
+
+    def train_step(self, links: torch.Tensor, vecs: torch.Tensor, L1: int, L2: int, lr: float) -> float:
+        B = self._shape(links, L1, L2)
+        loss = C.c_double()
+        _check(load_library().amg_cnn_train_step(self._h, _ptr(links.contiguous()), _ptr(vecs.contiguous()), B, L1,
+                                                  L2, float(lr), C.byref(loss), _stream()), "amg_cnn_train_step")
+        return loss.value
+
+    def propose(self, links: torch.Tensor, L1: int, L2: int) -> torch.Tensor:
+        self._shape(links, L1, L2)
+        out = torch.empty((8, L1 * L2, 2), dtype=torch.complex128, device="cuda")
+        _check(load_library().amg_cnn_propose(self._h, _ptr(links.contiguous()), L1, L2, _ptr(out), _stream()),
+               "amg_cnn_propose")
+        return out
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None):
+                load_library().amg_cnn_destroy(self._h)
                 self._h = None
         except Exception:
             pass

@@ -705,21 +705,20 @@ void relax_homogeneous(Solver& S, int l, double2* v, int nu0, hipStream_t st) {
   }
 }
 
-void adaptive_level(Solver& S, int l, const void* dev_init, int nu0, int ncyc, hipStream_t st) {
+// Vectors k0.. of level l each get ncyc sweeps of the two-level error
+// propagation e <- e - V(A_l e), V built from the vectors before them, and
+// are normalised; finally P_l and A_{l+1} are built from all of them (the
+// adaptive procedure after Eq. (5)).  Vectors before k0 are used as given.
+void adaptive_sweeps(Solver& S, int l, int ncyc, int k0, hipStream_t st) {
   Level& L = S.lv[l];
   const int nv = L.nv_max;
   const long n = L.per_rhs();
-  upload_vectors(S, l, dev_init, nv, st);
-  S.tzero.ensure(n * sizeof(double2));
-  HIPC(hipMemsetAsync(S.tzero.p, 0, n * sizeof(double2), st));
   double2* vecs = L.vecs.as<double2>();
-  relax_homogeneous(S, l, vecs, nu0, st);
   double2* t = L.w64[W_B].as<double2>();  // A e
   double2* zc = S.otmp.as<double2>();
-  for (int k = 1; k <= nv; ++k) {
+  for (int k = k0; k < nv; ++k) {
     L.nv = k;
     build_transfer(S, l, st);
-    if (k == nv) break;
     double2* e = vecs + (long)k * n;
     for (int c = 0; c < ncyc; ++c) {
       op_apply<double>(S, l, 0, EPI_PLAIN, e, t, nullptr, nullptr, 1, S.sc.red(0), st);
@@ -731,6 +730,42 @@ void adaptive_level(Solver& S, int l, const void* dev_init, int nu0, int ncyc, h
     launch_norm2<double>(e, n, 1, S.sc.red(L.gs.rr), st);
     launch_scale_inv_norm<double>(e, S.sc.scal.as<double>() + L.gs.rr, n, 1, st);
   }
+  L.nv = nv;
+  build_transfer(S, l, st);
+}
+
+void zero_scratch(Solver& S, int l, hipStream_t st) {
+  const long n = S.lv[l].per_rhs();
+  S.tzero.ensure(n * sizeof(double2));
+  HIPC(hipMemsetAsync(S.tzero.p, 0, n * sizeof(double2), st));
+}
+
+// Adaptive setup of coarsening l from random vectors: the first relaxed by
+// nu0 MR steps on A_l v = 0 (Eq. (4)), the others by the sweeps above.
+void adaptive_level(Solver& S, int l, const void* dev_init, int nu0, int ncyc, hipStream_t st) {
+  Level& L = S.lv[l];
+  upload_vectors(S, l, dev_init, L.nv_max, st);
+  zero_scratch(S, l, st);
+  relax_homogeneous(S, l, L.vecs.as<double2>(), nu0, st);
+  adaptive_sweeps(S, l, ncyc, 1, st);
+}
+
+// Coarsening l from n_start given vectors (proposals), each relaxed by nu MR
+// steps on A_l v = 0; the remaining nvec - n_start vectors are built by the
+// adaptive procedure (ncyc sweeps each) from the first random vectors of
+// dev_rand.
+void refined_level(Solver& S, int l, const void* dev_start, int n_start, int nu, const void* dev_rand, int ncyc,
+                   hipStream_t st) {
+  Level& L = S.lv[l];
+  const long n = L.per_rhs();
+  upload_vectors(S, l, dev_start, n_start, st);
+  if (n_start < L.nv_max)
+    to_internal<double>(S, l, (const double2*)dev_rand, L.vecs.as<double2>() + (long)n_start * n, L.nv_max - n_start,
+                        st);
+  zero_scratch(S, l, st);
+  if (nu > 0)
+    for (int k = 0; k < n_start; ++k) relax_homogeneous(S, l, L.vecs.as<double2>() + (long)k * n, nu, st);
+  adaptive_sweeps(S, l, ncyc, n_start, st);
 }
 
 // ---- convergence factor of the method as a stationary iteration ----------------
@@ -1634,59 +1669,97 @@ amg_status amg_mg_convergence(amg_solver* S, const void* dev_e0, int iters, doub
   AMG_CATCH
 }
 
-amg_status amg_setup_learned(const amg_gauge* g, const amg_mg_params* p, amg_cnn* net, const void* const* dev_init,
-                             int nu0_ref, int ncyc_ref, double rho_max, int nu0, int ncyc, void* stream,
-                             amg_solver** out, int* fell_back, double* rho) {
-  AMG_TRY
+namespace {
+
+// Level 0 from given starting vectors, refined; deeper levels adaptive.
+Solver* build_refined(const amg_gauge* g, const amg_mg_params* p, const void* start0, int n_start, int nu_ref,
+                      int ncyc_ref, const void* const* dev_init, int nu0, int ncyc, hipStream_t st) {
+  Solver* S = new_solver(g, p);
+  try {
+    ensure_work(*S, 1);
+    for (int l = 0; l + 1 < (int)S->lv.size(); ++l) {
+      if (l == 0) refined_level(*S, 0, start0, n_start, nu_ref, dev_init[0], ncyc_ref, st);
+      else adaptive_level(*S, l, dev_init[l], nu0, ncyc, st);
+    }
+    HIPC(hipStreamSynchronize(st));
+  } catch (...) {
+    (void)hipStreamSynchronize(st);
+    delete S;
+    throw;
+  }
+  return S;
+}
+
+void check_refine_args(const amg_gauge* g, const amg_mg_params* p, const void* const* dev_init, int n_start,
+                       int nu_ref, int ncyc_ref, int nu0, int ncyc, amg_solver** out) {
   check_ptr(g, "gauge");
   check_ptr(p, "params");
-  check_ptr(net, "network");
   check_ptr(dev_init, "init");
   check_ptr(out, "out");
+  if (nu_ref < 0 || ncyc_ref < 0 || nu0 < 0 || ncyc < 0) fail(AMG_ERR_ARG, "nu / ncyc must be >= 0");
+  if (p->nlevels < 2 || p->nlevels > 4) fail(AMG_ERR_ARG, "nlevels must be 2..4");
+  if (n_start < 1 || n_start > p->nvec[0]) fail(AMG_ERR_ARG, "n_start must be 1..nvec[0]");
+  if (n_start < p->nvec[0]) check_ptr(dev_init[0], "init[0]");
+  for (int l = 1; l + 1 < p->nlevels; ++l) check_ptr(dev_init[l], "init[l]");
+}
+
+}  // namespace
+
+amg_status amg_setup_refined(const amg_gauge* g, const amg_mg_params* p, const void* dev_start0, int n_start,
+                             int nu_ref, int ncyc_ref, const void* const* dev_init, int nu0, int ncyc, void* stream,
+                             amg_solver** out) {
+  AMG_TRY
+  check_refine_args(g, p, dev_init, n_start, nu_ref, ncyc_ref, nu0, ncyc, out);
+  check_ptr(dev_start0, "start vectors");
+  *out = build_refined(g, p, dev_start0, n_start, nu_ref, ncyc_ref, dev_init, nu0, ncyc, as_stream(stream));
+  AMG_CATCH
+}
+
+amg_status amg_setup_learned(const amg_gauge* g, const amg_mg_params* p, amg_cnn* net, const void* const* dev_init,
+                             int n_start, int nu_ref, int ncyc_ref, double rho_max, int rho_iters, int nu0, int ncyc,
+                             void* stream, amg_solver** out, int* fell_back, double* rho) {
+  AMG_TRY
+  check_refine_args(g, p, dev_init, n_start, nu_ref, ncyc_ref, nu0, ncyc, out);
+  check_ptr(net, "network");
+  check_ptr(dev_init[0], "init[0]");
   if (g->nd != 2) fail(AMG_ERR_ARG, "the learned setup is two-dimensional (U(1)) only");
-  if (p->nvec[0] < 1 || p->nvec[0] > 8) fail(AMG_ERR_ARG, "the network proposes 8 vectors; nvec[0] must be <= 8");
-  if (nu0_ref < 0 || ncyc_ref < 0 || nu0 < 0 || ncyc < 0) fail(AMG_ERR_ARG, "nu0 / ncyc must be >= 0");
-  if (!(rho_max > 0.0)) fail(AMG_ERR_ARG, "rho_max must be positive");
-  for (int l = 0; l + 1 < p->nlevels; ++l) check_ptr(dev_init[l], "init[l]");
+  if (n_start > 8) fail(AMG_ERR_ARG, "the network proposes 8 vectors");
+  if (rho_iters < 0 || rho_iters > 1000) fail(AMG_ERR_ARG, "rho_iters must be 0..1000");
+  if (rho_iters > 0 && !(rho_max > 0.0)) fail(AMG_ERR_ARG, "rho_max must be positive");
   hipStream_t st = as_stream(stream);
-  Buf prop;
-  prop.ensure((size_t)8 * g->V * 2 * sizeof(double2));
-  const amg_status ps = amg_cnn_propose(net, g->U64.p, g->dims[0], g->dims[1], prop.p, stream);
-  if (ps != AMG_OK) fail(ps, "amg_cnn_propose: " + last_error());
-  auto build = [&](bool learned) {
-    Solver* S = new_solver(g, p);
-    try {
-      ensure_work(*S, 1);
-      for (int l = 0; l + 1 < (int)S->lv.size(); ++l) {
-        if (learned && l == 0) adaptive_level(*S, 0, prop.p, nu0_ref, ncyc_ref, st);
-        else adaptive_level(*S, l, dev_init[l], nu0, ncyc, st);
-      }
-      HIPC(hipStreamSynchronize(st));
-    } catch (...) {
-      (void)hipStreamSynchronize(st);
-      delete S;
-      throw;
-    }
-    return S;
-  };
   Solver* S = nullptr;
-  double r = 0.0;
+  double r = -1.0;
   int fb = 0;
-  try {
-    S = build(true);
-    r = mg_convergence(*S, (const double2*)dev_init[0], 3, st);
-    if (!(r <= rho_max)) fb = 1;
-  } catch (const Fail& f) {
-    if (f.s != AMG_ERR_RANK && f.s != AMG_ERR_NAN) throw;
-    fb = 1;
+  {
+    Buf prop;
+    prop.ensure((size_t)8 * g->V * 2 * sizeof(double2));
+    const amg_status ps = amg_cnn_propose(net, g->U64.p, g->dims[0], g->dims[1], prop.p, stream);
+    if (ps != AMG_OK) fail(ps, "amg_cnn_propose: " + last_error());
+    try {
+      S = build_refined(g, p, prop.p, n_start, nu_ref, ncyc_ref, dev_init, nu0, ncyc, st);
+      if (rho_iters > 0) {
+        r = mg_convergence(*S, (const double2*)dev_init[0], rho_iters, st);
+        if (!(r <= rho_max)) fb = 1;
+      }
+    } catch (const Fail& f) {
+      if (f.s != AMG_ERR_RANK && f.s != AMG_ERR_NAN) {
+        delete S;
+        throw;
+      }
+      fb = 1;
+    }
   }
   if (fb) {
     delete S;
     S = nullptr;
-    S = build(false);
+    S = new_solver(g, p);
     try {
-      r = mg_convergence(*S, (const double2*)dev_init[0], 3, st);
+      ensure_work(*S, 1);
+      for (int l = 0; l + 1 < (int)S->lv.size(); ++l) adaptive_level(*S, l, dev_init[l], nu0, ncyc, st);
+      HIPC(hipStreamSynchronize(st));
+      if (rho_iters > 0) r = mg_convergence(*S, (const double2*)dev_init[0], rho_iters, st);
     } catch (...) {
+      (void)hipStreamSynchronize(st);
       delete S;
       throw;
     }
