@@ -215,6 +215,95 @@ def batch_bench(amg, torch, bfields, mixed=True):
     }
 
 
+# ---------------------------------------------------------------------------
+# learned setup: held-out configurations at 256^2 and 512^2
+# ---------------------------------------------------------------------------
+LEARNED_WEIGHTS = os.path.join(ROOT, "paper_0707_4018_amd", "weights", "cnn_u1_128.npz")
+LEARNED_NAMES = [f"heldout_{L}_b{b}" for L in (256, 512) for b in (3, 10, 6)]
+
+
+def gen_learned_config(name):
+    """Held-out configuration of the learned-setup evaluation (recipe of its training set)."""
+    W = WORKLOADS[name]
+    th = synth.u1_heatbath(W["L1"], W["L2"], W["beta"], W["sweeps"], synth.rng_for(*W["seed"]))
+    if abs(synth.u1_mean_plaquette(th) - W["plaquette"]) > 1e-12:
+        raise RuntimeError(f"regenerated field differs from the workload table ({name})")
+    return name, th
+
+
+def learned_bench(amg, torch, lfields, mixed=True):
+    """Setup time + FGCR iterations to 1e-10 at mass gap 1e-3 (m_crit of each configuration from the
+    workload table) for setups of the same 3-level solver:
+    A  plain adaptive setup (nu0 = 20, ncyc = 2 on both coarsenings);
+    B  the network's 8 proposals for level 0, then one adaptive iteration in the paper's sense (the
+       V-cycle applied to a random error, two iterations; plain setup as fallback if it does not
+       converge at rate <= 0.6); level 1 adaptive as in A;
+    B7 7 proposals + 1 vector from the adaptive procedure (4 sweeps), same test;
+    C  random vectors through the same path as B (no network);
+    D  random vectors relaxed by 20 MR steps each (relaxation only, level 1 as in A)."""
+    from paper_0707_4018_amd import learned
+    net = learned.load(LEARNED_WEIGHTS, bf16=True)
+    with np.load(LEARNED_WEIGHTS, allow_pickle=False) as z:
+        meta = {k: z[k].tolist() for k in ("n_train", "L", "epochs", "val_loss", "val_loss_init", "target_nu0",
+                                          "target_ncyc") if k in z}
+    params = mg_params(amg, mixed)
+    rows = []
+    for name in LEARNED_NAMES:
+        if name not in lfields:
+            continue
+        W = WORKLOADS[name]
+        L, beta, idx = W["L1"], W["beta"], W["idx"]
+        m = W["masses"][-1]
+        U = torch.from_numpy(np.exp(1j * lfields[name])[..., None, None].copy()).cuda()
+        g = amg.Gauge(U, m)
+        Lc = L // 4
+        init = [torch.from_numpy(np.stack([synth.gaussian_field((L * L, 2), synth.rng_for(5, 1, idx, 0, k))
+                                           for k in range(8)])).cuda(),
+                torch.from_numpy(np.stack([synth.gaussian_field((Lc * Lc, 16), synth.rng_for(5, 1, idx, 1, k))
+                                           for k in range(8)])).cuda()]
+        chi = torch.from_numpy(synth.gaussian_field((1, L * L, 2, 1), synth.rng_for(5, 3, idx))).cuda()
+        setups = {
+            "A_adaptive": (lambda: (amg.Solver(g, params, init=init, nu0=20, ncyc=2), None), 300),
+            "B_learned": (lambda: amg.Solver.learned(g, params, net, init, rho_iters=2, rho_max=0.6)[:2], 300),
+            "B7_learned_plus_adaptive": (lambda: amg.Solver.learned(g, params, net, init, n_start=7, ncyc_ref=4,
+                                                                     rho_iters=2, rho_max=0.6)[:2], 300),
+            "C_random_same_path": (lambda: (amg.Solver.refined(g, params, init[0], nu_ref=0, init=init), None), 60),
+            "D_random_relax20": (lambda: (amg.Solver.refined(g, params, init[0], nu_ref=20, init=init), None), 300),
+        }
+        row = {"L": L, "beta": beta, "idx": idx, "mass_gap": W["mass_gaps"][-1], "mass": m}
+        for key, (mk, maxit) in setups.items():
+            S, fb = mk()                       # warm (allocations), then timed
+            del S
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            S, fb = mk()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            _, info = S.solve(chi, tol=TOL, max_iter=maxit, raise_noconv=False)
+            t2 = time.perf_counter()
+            row[key] = {"setup_ms": round(1e3 * (t1 - t0), 2), "iters": info[0].iters,
+                        "solve_ms": round(1e3 * (t2 - t1), 2), "total_ms": round(1e3 * (t2 - t0), 2),
+                        "converged": bool(info[0].converged), "true_rel_res": info[0].true_rel_res}
+            if fb is not None:
+                row[key]["fell_back"] = bool(fb)
+            del S
+        rows.append(row)
+        log(f"learned L={L} beta={beta}: " + ", ".join(f"{k} {v['setup_ms']}+{v['solve_ms']} ms/{v['iters']} it"
+                                                     for k, v in row.items() if isinstance(v, dict)))
+
+    keys = [k for k in rows[0] if isinstance(rows[0][k], dict)]
+    summary = {k: {f: round(float(np.mean([r[k][f] for r in rows])), 3) for f in ("setup_ms", "iters", "total_ms")}
+               for k in keys}
+    for k in keys:
+        summary[k]["converged"] = sum(int(r[k]["converged"]) for r in rows)
+    return {"workload": "held-out U(1) configurations 256^2 and 512^2 (100 sweeps), beta {3,6,10}, mass gap 1e-3, "
+                        "3-level mixed-precision MG, FGCR to 1e-10",
+            "network": meta, "fallbacks": sum(int(r["B_learned"].get("fell_back", False)) for r in rows),
+            "summary": summary,
+            "speedup_total_B_vs_A": round(summary["A_adaptive"]["total_ms"] / summary["B_learned"]["total_ms"], 3),
+            "instances": rows}
+
+
 def stencil_bench(amg, torch, th, iters=40):
     """Fine stencil alone on HBM-sized lattices: the beta=6 U(1) field tiled
     periodically to 4096^2, and a 32^3 x 64 SU(3) field (4096 seeded Haar
@@ -356,6 +445,7 @@ def main():
     ap.add_argument("--no-stencil", action="store_true")
     ap.add_argument("--betas", type=str, default=None, help="comma-separated subset of the ensembles")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
     args = ap.parse_args()
     global BETAS
     if args.betas:
@@ -369,8 +459,11 @@ def main():
     with cf.ProcessPoolExecutor(max_workers=16) as ex:
         fut = {b: ex.submit(gen_config, b) for b in BETAS}
         bfut = [] if args.no_batch else [ex.submit(gen_batch_config, i) for i in range(NBATCH)]
+        use_learned = not args.no_learned and os.path.exists(LEARNED_WEIGHTS)
+        lfut = [ex.submit(gen_learned_config, n) for n in LEARNED_NAMES if n in WORKLOADS] if use_learned else []
         fields = dict(f.result() for f in fut.values())
         bfields = dict(f.result() for f in bfut)
+        lfields = dict(f.result() for f in lfut)
 
     import torch
     import paper_0707_4018_amd as amg
@@ -440,6 +533,9 @@ def main():
     if not args.no_batch:
         log("batched workload")
         out["batched"] = batch_bench(amg, torch, bfields)
+    if lfields:
+        log("learned setup")
+        out["learned"] = learned_bench(amg, torch, lfields)
     if not args.no_stencil:
         log("stencil bandwidth")
         out["stencil"] = stencil_bench(amg, torch, fields[BETAS[-1]])

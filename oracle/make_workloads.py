@@ -1,6 +1,6 @@
 """Write the synthetic workload table (masses) used by tests and the benchmark.
 
-Run: python -m oracle.make_workloads   (writes synth/workloads.json)
+Run: python -m oracle.make_workloads [names...] [-jN]   (writes synth/workloads.json)
 
 For every workload lattice this generates the gauge field with the seeded
 heat-bath, computes m_crit from the spectrum of D(0) with the oracle, and
@@ -26,32 +26,52 @@ WORKLOADS = [
     ("schwinger_256_b3", 2, 256, 3.0, 0, 500, [1e-1, 1e-2, 3e-3, 1e-3]),
     ("schwinger_256_b6", 2, 256, 6.0, 0, 500, [1e-1, 1e-2, 3e-3, 1e-3]),
     ("schwinger_256_b10", 2, 256, 10.0, 0, 500, [1e-1, 1e-2, 3e-3, 1e-3]),
+    # held-out configurations of the learned setup (same recipe as its training set)
+    ("heldout_256_b3", 5, 256, 3.0, 10000, 100, [1e-2, 1e-3]),
+    ("heldout_256_b6", 5, 256, 6.0, 10001, 100, [1e-2, 1e-3]),
+    ("heldout_256_b10", 5, 256, 10.0, 10002, 100, [1e-2, 1e-3]),
+    ("heldout_512_b3", 5, 512, 3.0, 10003, 100, [1e-2, 1e-3]),
+    ("heldout_512_b6", 5, 512, 6.0, 10004, 100, [1e-2, 1e-3]),
+    ("heldout_512_b10", 5, 512, 10.0, 10005, 100, [1e-2, 1e-3]),
 ]
 
 
-def main(names=None):
+def entry(w):
+    name, cfg, L, beta, idx, sweeps, gaps = w
+    t0 = time.time()
+    seed = [cfg, int(round(100 * beta)), L, L, idx]
+    th = synth.u1_heatbath(L, L, beta, sweeps, synth.rng_for(*seed))
+    A0 = mg.wilson_stencil(dirac.u1_field(th), 0.0)
+    mcrit, lam = spectrum.critical_mass(A0)
+    e = {
+        "cfg": cfg, "L1": L, "L2": L, "beta": beta, "idx": idx, "sweeps": sweeps,
+        "seed": seed, "m_crit": mcrit, "leftmost_eigenvalue_m0": [lam.real, lam.imag],
+        "mass_gaps": gaps, "masses": [mcrit + g for g in gaps],
+        "plaquette": synth.u1_mean_plaquette(th), "Q": round(synth.u1_topological_charge(th)),
+    }
+    print(name, e, f"{time.time() - t0:.1f}s", flush=True)
+    return name, e
+
+
+def main(names=None, workers=1):
     table = {}
     if os.path.exists(OUT):
         with open(OUT) as f:
             table = json.load(f)
-    for name, cfg, L, beta, idx, sweeps, gaps in WORKLOADS:
-        if names and name not in names:
-            continue
-        t0 = time.time()
-        seed = [cfg, int(round(100 * beta)), L, L, idx]
-        th = synth.u1_heatbath(L, L, beta, sweeps, synth.rng_for(*seed))
-        A0 = mg.wilson_stencil(dirac.u1_field(th), 0.0)
-        mcrit, lam = spectrum.critical_mass(A0)
-        table[name] = {
-            "cfg": cfg, "L1": L, "L2": L, "beta": beta, "idx": idx, "sweeps": sweeps,
-            "seed": seed, "m_crit": mcrit, "leftmost_eigenvalue_m0": [lam.real, lam.imag],
-            "mass_gaps": gaps, "masses": [mcrit + g for g in gaps],
-            "plaquette": synth.u1_mean_plaquette(th), "Q": round(synth.u1_topological_charge(th)),
-        }
-        print(name, table[name], f"{time.time() - t0:.1f}s", flush=True)
-        with open(OUT, "w") as f:
-            json.dump(table, f, indent=1)
+    todo = [w for w in WORKLOADS if not names or w[0] in names]
+    if workers > 1:
+        import concurrent.futures as cf
+        with cf.ProcessPoolExecutor(max_workers=workers) as ex:
+            done = list(ex.map(entry, todo))
+    else:
+        done = [entry(w) for w in todo]
+    for name, e in done:
+        table[name] = e
+    with open(OUT, "w") as f:
+        json.dump(table, f, indent=1)
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:] or None)
+    args = [a for a in sys.argv[1:] if not a.startswith("-j")]
+    jobs = [int(a[2:]) for a in sys.argv[1:] if a.startswith("-j")]
+    main(args or None, jobs[0] if jobs else 1)

@@ -79,6 +79,9 @@ struct CoarseArgs {
   RedArgs red;
 };
 template <typename T> void launch_coarse(const CoarseArgs<T>& a, int dagger, int epi, hipStream_t st);
+// many right-hand sides per launch on MFMA (FP32; N_c = 16 or 48; plain or residual epilogue)
+bool coarse_mrhs_supported(int nc, int epi);
+void launch_coarse_mrhs(const CoarseArgs<float>& a, int dagger, int epi, hipStream_t st);
 // fused GCR step for N_c = 16 levels: part 1 (apply + all sums) and part 2 (updates)
 template <typename T>
 void launch_gcr16_apply_dots(const CoarseArgs<T>& a, const cplx<T>* r, const cplx<T>* Wb, long dstride, int k,

@@ -12,6 +12,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "amg.h"
@@ -226,6 +227,9 @@ struct amg_solver {
   int pcoarse_max_blocks = 64;
   bool pcoarse_coop = true;
   bool fused_gcr = false;  // measured slower than the separate kernels at the 2d coarse sizes
+  // FP32 coarse applies with at least this many right-hand sides use the
+  // MFMA multi-rhs kernel (plain / residual epilogues, N_c = 16 or 48)
+  int mrhs_min = 2;
   // kernel timing
   struct Prof {
     bool on = false;
@@ -316,7 +320,10 @@ void op_apply(Solver& S, int l, int dagger, int epi, const cplx<T>* in, cplx<T>*
     a.g = L.cgeom();
     a.nrhs = nrhs;
     a.red = red;
-    launch_coarse<T>(a, dagger, epi, st);
+    if (std::is_same<T, float>::value && nrhs >= S.mrhs_min && coarse_mrhs_supported(L.dof, epi))
+      launch_coarse_mrhs(reinterpret_cast<const CoarseArgs<float>&>(a), dagger, epi, st);
+    else
+      launch_coarse<T>(a, dagger, epi, st);
     S.nC += 1;
   }
 }
@@ -682,6 +689,7 @@ Solver* new_solver(const amg_gauge* g, const amg_mg_params* p) {
   if (const char* e = std::getenv("AMG_PCOARSE_BLOCKS")) S->pcoarse_max_blocks = std::max(1, std::min(128, std::atoi(e)));
   if (const char* e = std::getenv("AMG_PCOARSE_COOP")) S->pcoarse_coop = std::atoi(e) != 0;
   if (const char* e = std::getenv("AMG_FUSED_GCR")) S->fused_gcr = std::atoi(e) != 0;
+  if (const char* e = std::getenv("AMG_MRHS_MIN")) S->mrhs_min = std::max(1, std::atoi(e));
   return S;
 }
 
@@ -1809,6 +1817,15 @@ amg_status amg_batch_create(amg_solver* const* solvers, const int* nrhs, int n, 
     HIPC(hipHostMalloc((void**)&B->gath_host, sizeof(double) * 2 * n * RHS_MAX, hipHostMallocDefault));
     HIPC(hipHostMalloc((void**)&B->flags_host, sizeof(int) * n * RHS_MAX, hipHostMallocDefault));
     for (int i = 0; i < n; ++i) B->S[i]->outer_flags = B->flags_dev.as<int>() + (long)i * RHS_MAX;
+    // one kernel choice for every instance at a stage: the multi-rhs coarse
+    // kernel for all of them (any nrhs) unless disabled
+    int batch_mrhs = 1;
+    if (const char* e = std::getenv("AMG_BATCH_MRHS")) batch_mrhs = std::atoi(e) != 0 ? 1 : (1 << 30);
+    std::vector<int> saved_mrhs(n);
+    for (int i = 0; i < n; ++i) {
+      saved_mrhs[i] = B->S[i]->mrhs_min;
+      B->S[i]->mrhs_min = batch_mrhs;
+    }
     const int saved = red_block_cap();
     if (autotune) {
       // autotune the grid of the reducing kernels: time one outer iteration
@@ -1848,7 +1865,10 @@ amg_status amg_batch_create(amg_solver* const* solvers, const int* nrhs, int n, 
     set_red_block_cap(B->red_cap);
     batch_build(*B);
     set_red_block_cap(saved);
-    for (int i = 0; i < n; ++i) B->S[i]->outer_flags = nullptr;
+    for (int i = 0; i < n; ++i) {
+      B->S[i]->outer_flags = nullptr;
+      B->S[i]->mrhs_min = saved_mrhs[i];
+    }
     HIPC(hipStreamSynchronize(B->st));
   } catch (...) {
     delete B;
