@@ -77,6 +77,10 @@ PARAMS = dict(blocks=[(4, 4), (2, 2)], nvec=[8, 8], nu_pre=2, nu_post=2, omega=0
               kcycle_tol=0.1, kcycle_maxiter=8)
 
 
+# adaptive setup: nu0 MR steps on the first vector, ncyc error-propagation sweeps per further vector
+SETUP_NU0, SETUP_NCYC = 20, 4
+
+
 def mg_params(amg, mixed: bool):
     return amg.MGParams(**PARAMS, inner_prec=amg.F32 if mixed else amg.F64, p_bf16=mixed)
 
@@ -104,7 +108,7 @@ class Job:
             W = workload(beta)
             g = self.gauges[beta]
             t0 = time.perf_counter()
-            S = amg.Solver(g, mg_params(amg, mixed), init=self.init, nu0=20, ncyc=2)
+            S = amg.Solver(g, mg_params(amg, mixed), init=self.init, nu0=SETUP_NU0, ncyc=SETUP_NCYC)
             t1 = time.perf_counter()
             setup_ms += 1e3 * (t1 - t0)
             if profile is not None:
@@ -171,7 +175,8 @@ def batch_bench(amg, torch, bfields, mixed=True):
         g = amg.Gauge(U, _mcrit_interp(beta) + 0.02)
         init = [np.stack([synth.gaussian_field((L * L, 2), synth.rng_for(4, 7, i, 0, k)) for k in range(8)]),
                 np.stack([synth.gaussian_field(((L // 4) ** 2, 16), synth.rng_for(4, 7, i, 1, k)) for k in range(8)])]
-        solvers.append(amg.Solver(g, params, init=[torch.from_numpy(v).cuda() for v in init], nu0=20, ncyc=2))
+        solvers.append(amg.Solver(g, params, init=[torch.from_numpy(v).cuda() for v in init], nu0=SETUP_NU0,
+                                  ncyc=SETUP_NCYC))
         chis.append(torch.from_numpy(synth.gaussian_field((nrhs, L * L, 2, 1), synth.rng_for(4, 9, i))).cuda())
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -233,14 +238,16 @@ def gen_learned_config(name):
 
 def learned_bench(amg, torch, lfields, mixed=True):
     """Setup time + FGCR iterations to 1e-10 at mass gap 1e-3 (m_crit of each configuration from the
-    workload table) for setups of the same 3-level solver:
-    A  plain adaptive setup (nu0 = 20, ncyc = 2 on both coarsenings);
-    B  the network's 8 proposals for level 0, then one adaptive iteration in the paper's sense (the
-       V-cycle applied to a random error, two iterations; plain setup as fallback if it does not
-       converge at rate <= 0.6); level 1 adaptive as in A;
-    B7 7 proposals + 1 vector from the adaptive procedure (4 sweeps), same test;
-    C  random vectors through the same path as B (no network);
-    D  random vectors relaxed by 20 MR steps each (relaxation only, level 1 as in A)."""
+    workload table) for setups of the same 3-level solver (level 1 always the adaptive setup with
+    nu0 = 20, ncyc = 4):
+    A   plain adaptive setup of level 0 (nu0 = 20, ncyc = 4), the fallback of B;
+    B   the learned setup: 7 network proposals + 1 vector from one adaptive iteration (4 sweeps of
+        the two-level error propagation on a random vector), then the V-cycle test on a random
+        error (2 iterations; plain setup if the rate exceeds 0.6);
+    B8  the 8 raw proposals, no adaptive iteration (fails near-critical on 3 levels: the exceptional
+        low mode is outside the proposals' span);
+    C   random vectors through the same path as B (no network);
+    D   random vectors relaxed by 20 MR steps each (relaxation only)."""
     from paper_0707_4018_amd import learned
     net = learned.load(LEARNED_WEIGHTS, bf16=True)
     with np.load(LEARNED_WEIGHTS, allow_pickle=False) as z:
@@ -263,12 +270,15 @@ def learned_bench(amg, torch, lfields, mixed=True):
                                            for k in range(8)])).cuda()]
         chi = torch.from_numpy(synth.gaussian_field((1, L * L, 2, 1), synth.rng_for(5, 3, idx))).cuda()
         setups = {
-            "A_adaptive": (lambda: (amg.Solver(g, params, init=init, nu0=20, ncyc=2), None), 300),
-            "B_learned": (lambda: amg.Solver.learned(g, params, net, init, rho_iters=2, rho_max=0.6)[:2], 300),
-            "B7_learned_plus_adaptive": (lambda: amg.Solver.learned(g, params, net, init, n_start=7, ncyc_ref=4,
-                                                                     rho_iters=2, rho_max=0.6)[:2], 300),
-            "C_random_same_path": (lambda: (amg.Solver.refined(g, params, init[0], nu_ref=0, init=init), None), 60),
-            "D_random_relax20": (lambda: (amg.Solver.refined(g, params, init[0], nu_ref=20, init=init), None), 300),
+            "A_adaptive": (lambda: (amg.Solver(g, params, init=init, nu0=20, ncyc=4), None), 300),
+            "B_learned": (lambda: amg.Solver.learned(g, params, net, init, n_start=7, ncyc_ref=4, rho_iters=2,
+                                                     rho_max=0.6, nu0=20, ncyc=4)[:2], 300),
+            "B8_raw_proposals": (lambda: amg.Solver.learned(g, params, net, init, n_start=8, nu0=20, ncyc=4)[:2],
+                                 100),
+            "C_random_same_path": (lambda: (amg.Solver.refined(g, params, init[0][1:], n_start=7, ncyc_ref=4,
+                                                               init=init, nu0=20, ncyc=4), None), 100),
+            "D_random_relax20": (lambda: (amg.Solver.refined(g, params, init[0], nu_ref=20, init=init, nu0=20,
+                                                             ncyc=4), None), 300),
         }
         row = {"L": L, "beta": beta, "idx": idx, "mass_gap": W["mass_gaps"][-1], "mass": m}
         for key, (mk, maxit) in setups.items():
@@ -302,6 +312,95 @@ def learned_bench(amg, torch, lfields, mixed=True):
             "summary": summary,
             "speedup_total_B_vs_A": round(summary["A_adaptive"]["total_ms"] / summary["B_learned"]["total_ms"], 3),
             "instances": rows}
+
+
+# ---------------------------------------------------------------------------
+# four-dimensional SU(3) workload: 32^3 x 64, 12 point sources solved together
+# ---------------------------------------------------------------------------
+W4_NAME = "wilson4d_8x8x8x16"
+W4_DIMS = (32, 32, 32, 64)
+
+
+def gen_4d_base():
+    """Smeared SU(3) base field (worker process); tiled to W4_DIMS on the host later."""
+    W = WORKLOADS[W4_NAME]
+    U = synth.su3_haar((4,) + tuple(reversed(W["dims"])), synth.rng_for(*W["seed"]))
+    U = synth.su3_stout_smear(U, W["stout_rho"], W["stout_steps"])
+    if abs(synth.su3_mean_plaquette(U) - W["plaquette"]) > 1e-12:
+        raise RuntimeError("regenerated 4d base field differs from the workload table")
+    return U
+
+
+def wilson4d_bench(amg, torch, U0):
+    """12 point sources (one per spin-colour component at the origin) solved together by
+    2-level MG (4^4 blocks, 24 near-null vectors -> 48 coarse dof) with FP32 smoother and
+    coarse level (BF16 P), FP64 FGCR outer iteration, to a true relative residual of 1e-10;
+    the same solve with FP64 inner levels, the 12 sources one at a time, and CGNR on one
+    source for reference."""
+    W = WORKLOADS[W4_NAME]
+    tile = tuple(d // b for d, b in zip(W4_DIMS, W["dims"]))
+    V = int(np.prod(W4_DIMS))
+    m = W["masses"][0]
+    U = torch.from_numpy(np.tile(U0, (1,) + tuple(reversed(tile)) + (1, 1))).cuda()
+    g = amg.Gauge(U, m)
+    del U
+    nrhs = 12
+    chi = torch.zeros((nrhs, V, 4, 3), dtype=torch.complex128, device="cuda")
+    for j in range(nrhs):
+        chi[j, 0, j // 3, j % 3] = 1.0
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(4096)
+    shape = (24, V, 12)
+    init = [torch.complex(torch.randn(shape, generator=gen, device="cuda", dtype=torch.float64),
+                          torch.randn(shape, generator=gen, device="cuda", dtype=torch.float64)) / np.sqrt(2.0)]
+    out = {"workload": f"4d SU(3) Wilson-Dirac {'x'.join(map(str, W4_DIMS))}, stout-smeared Haar links tiled from "
+                       f"{'x'.join(map(str, W['dims']))} (plaquette {W['plaquette']:.3f}), mass gap {W['mass_gaps'][0]}, "
+                       "12 point sources",
+           "mass": m, "levels": 2, "blocks": [4, 4, 4, 4], "nvec": 24}
+    res = {}
+    for tag, prec in (("mixed", amg.F32), ("fp64", amg.F64)):
+        p = amg.MGParams(blocks=[(4, 4, 4, 4)], nvec=[24], nu_pre=2, nu_post=2, omega=0.8, coarse_tol=0.1,
+                         coarse_maxiter=100, coarse_restart=16, outer_restart=8, inner_prec=prec,
+                         p_bf16=(prec == amg.F32))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S = amg.Solver.refined(g, p, init[0], nu_ref=W4_RELAX)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        psi, info = S.solve(chi, tol=TOL, max_iter=200)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        res[tag] = {"setup_s": round(t1 - t0, 3), "solve_12rhs_s": round(t2 - t1, 3),
+                    "iters": [i.iters for i in info], "max_true_rel_res": max(i.true_rel_res for i in info),
+                    "n_coarse": info[0].n_coarse, "n_fine_D": info[0].n_fine_D}
+        log(f"4d {tag}: setup {t1 - t0:.2f} s, 12-rhs solve {t2 - t1:.3f} s, iters {res[tag]['iters'][:3]}...")
+        if tag == "mixed":
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            its = []
+            for j in range(nrhs):
+                _, i1 = S.solve(chi[j:j + 1], tol=TOL, max_iter=200)
+                its.append(i1[0].iters)
+            torch.cuda.synchronize()
+            res[tag]["solve_1rhs_x12_s"] = round(time.perf_counter() - t3, 3)
+            res[tag]["iters_1rhs"] = its
+        del S, psi
+        torch.cuda.empty_cache()
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    _, ic = g.cgnr(chi[:1], tol=TOL, max_iter=20000)
+    torch.cuda.synchronize()
+    res["cgnr_1rhs"] = {"s": round(time.perf_counter() - t4, 3), "iters": ic.iters, "converged": ic.converged,
+                        "true_rel_res": ic.true_rel_res}
+    out.update(res)
+    out["speedup_12rhs_vs_sequential"] = round(res["mixed"]["solve_1rhs_x12_s"] / res["mixed"]["solve_12rhs_s"], 3)
+    out["speedup_mixed_vs_fp64"] = round(res["fp64"]["solve_12rhs_s"] / res["mixed"]["solve_12rhs_s"], 3)
+    del g, init, chi
+    torch.cuda.empty_cache()
+    return out
+
+
+W4_RELAX = 20
 
 
 def stencil_bench(amg, torch, th, iters=40):
@@ -379,12 +478,12 @@ def cpu_baseline_child(path_in: str, path_out: str):
     init = init_vectors()
     # (1) adaptive setup unit: the first two near-null vectors of the finest coarsening
     t0 = time.perf_counter()
-    v1 = mg.relax_homogeneous(A, init[0][0], 20, p.omega)
+    v1 = mg.relax_homogeneous(A, init[0][0], SETUP_NU0, p.omega)
     P = mg.build_prolongator(v1[None], A.dims, (4, 4))
     Ac = mg.galerkin(A, P)
     H2 = mg.Hierarchy([A, Ac], [P], p)
     e = init[0][1].copy()
-    for _ in range(2):
+    for _ in range(SETUP_NCYC):
         e = e - mg.vcycle(H2, 0, A.apply(e))
     t1 = time.perf_counter()
     res["setup_two_vectors_s"] = t1 - t0
@@ -428,7 +527,8 @@ def cpu_baseline(job, recs):
         "value": round(value, 6), "unit": "solves/s (1e-10 true FP64 rel. residual, setup included)",
         "cores": 1, "kind": "oracle",
         "sample": (f"oracle (FP64 NumPy, 1 thread) on the beta=6 256^2 ensemble at the lightest mass: "
-                   f"adaptive setup of the first 2 near-null vectors ({cb['setup_two_vectors_s']:.1f} s) and "
+                   f"adaptive setup of the first 2 near-null vectors (nu0 = {SETUP_NU0}, {SETUP_NCYC} sweeps; "
+                   f"{cb['setup_two_vectors_s']:.1f} s) and "
                    f"2 outer FGCR iterations of the same 3-level K-cycle ({cb['outer_iteration_s']:.2f} s each); "
                    f"scaled to the step by 16 vectors per ensemble and the GPU's outer iteration counts; "
                    f"sample wall time {wall:.0f} s including direct solves for the error report"),
@@ -446,6 +546,7 @@ def main():
     ap.add_argument("--betas", type=str, default=None, help="comma-separated subset of the ensembles")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-4d", action="store_true")
     args = ap.parse_args()
     global BETAS
     if args.betas:
@@ -459,11 +560,13 @@ def main():
     with cf.ProcessPoolExecutor(max_workers=16) as ex:
         fut = {b: ex.submit(gen_config, b) for b in BETAS}
         bfut = [] if args.no_batch else [ex.submit(gen_batch_config, i) for i in range(NBATCH)]
+        f4 = ex.submit(gen_4d_base) if (not args.no_4d and W4_NAME in WORKLOADS) else None
         use_learned = not args.no_learned and os.path.exists(LEARNED_WEIGHTS)
         lfut = [ex.submit(gen_learned_config, n) for n in LEARNED_NAMES if n in WORKLOADS] if use_learned else []
         fields = dict(f.result() for f in fut.values())
         bfields = dict(f.result() for f in bfut)
         lfields = dict(f.result() for f in lfut)
+        U4 = f4.result() if f4 is not None else None
 
     import torch
     import paper_0707_4018_amd as amg
@@ -533,6 +636,10 @@ def main():
     if not args.no_batch:
         log("batched workload")
         out["batched"] = batch_bench(amg, torch, bfields)
+    if U4 is not None:
+        log("4d multi-rhs workload")
+        out["wilson4d"] = wilson4d_bench(amg, torch, U4)
+        del U4
     if lfields:
         log("learned setup")
         out["learned"] = learned_bench(amg, torch, lfields)
