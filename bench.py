@@ -412,7 +412,7 @@ def stencil_bench(amg, torch, th, iters=40):
     stream = torch.cuda.current_stream()
 
     def timed(g, prec, nrhs=1):
-        g.apply_internal(False, prec, nrhs, 3)
+        g.apply_internal(False, prec, nrhs, 30)      # also brings the clocks up
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         g.apply_internal(False, prec, nrhs, iters)
@@ -547,6 +547,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-4d", action="store_true")
+    ap.add_argument("--only-stencil", action="store_true",
+                    help="time the fine stencils alone (for profiling runs) and print their JSON")
     args = ap.parse_args()
     global BETAS
     if args.betas:
@@ -556,6 +558,19 @@ def main():
                                    "decomposition is described in the design notes, not built)"}))
         sys.exit(2)
 
+    if args.only_stencil:
+        th = gen_config(BETAS[-1])[1]
+        import torch
+        import paper_0707_4018_amd as amg
+        torch.cuda.set_device(0)
+        # a plain 256 MiB device copy: the reference that HBM byte counters are scaled by
+        x = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
+        print(json.dumps({"stencil": stencil_bench(amg, torch, th)}))
+        return
     log("generating gauge ensembles (heat-bath, worker processes)")
     with cf.ProcessPoolExecutor(max_workers=16) as ex:
         fut = {b: ex.submit(gen_config, b) for b in BETAS}

@@ -35,6 +35,20 @@ __device__ __forceinline__ void st2(double2* __restrict__ p, long s, long V, Sp2
 __device__ __forceinline__ void st2(float2* __restrict__ p, long s, long, Sp2<float> v) {
   reinterpret_cast<float4*>(p)[s] = make_float4(v.a.x, v.a.y, v.b.x, v.b.y);
 }
+// streaming (non-temporal) stores for lattices far larger than the caches:
+// the result is not read again by this kernel and would only evict the
+// neighbour spinors that the other waves still need
+typedef double v2d __attribute__((ext_vector_type(2)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void st2_nt(double2* __restrict__ p, long s, long V, Sp2<double> v) {
+  const v2d a = {v.a.x, v.a.y}, b = {v.b.x, v.b.y};
+  __builtin_nontemporal_store(a, reinterpret_cast<v2d*>(p) + s);
+  __builtin_nontemporal_store(b, reinterpret_cast<v2d*>(p) + V + s);
+}
+__device__ __forceinline__ void st2_nt(float2* __restrict__ p, long s, long, Sp2<float> v) {
+  const v4f a = {v.a.x, v.a.y, v.b.x, v.b.y};
+  __builtin_nontemporal_store(a, reinterpret_cast<v4f*>(p) + s);
+}
 // single link U_mu(site)
 __device__ __forceinline__ double2 ldU(const double2* __restrict__ U, long s, long V, int mu) {
   return U[mu * V + s];
@@ -76,7 +90,7 @@ __device__ __forceinline__ void sub_half(Sp2<T>& o, const Sp2<T>& h) {
   o.b.x -= (T)0.5 * h.b.x; o.b.y -= (T)0.5 * h.b.y;
 }
 
-template <typename T, int DAG, int EPI>
+template <typename T, int DAG, int EPI, bool NT>
 __global__ __launch_bounds__(256) void wilson2d_kernel(WilsonArgs<T> a0, const WilsonArgs<T>* batch) {
   AMG_ARGS(WilsonArgs<T>)
   const int rhs = blockIdx.y;
@@ -108,8 +122,13 @@ __global__ __launch_bounds__(256) void wilson2d_kernel(WilsonArgs<T> a0, const W
       const Sp2<T> bb = ld2(bvec + ro, s, V);
       o = {csub<T>(bb.a, o.a), csub<T>(bb.b, o.b)};
     }
-    st2(out + ro, s, V, o);
-    if (copy_out) st2(copy_out + ro, s, V, c);
+    if (NT) {
+      st2_nt(out + ro, s, V, o);
+      if (copy_out) st2_nt(copy_out + ro, s, V, c);
+    } else {
+      st2(out + ro, s, V, o);
+      if (copy_out) st2(copy_out + ro, s, V, c);
+    }
     if (EPI == EPI_MRDOT) {
       acc[0] += (double)o.a.x * c.a.x + (double)o.a.y * c.a.y + (double)o.b.x * c.b.x + (double)o.b.y * c.b.y;
       acc[1] += (double)o.a.x * c.a.y - (double)o.a.y * c.a.x + (double)o.b.x * c.b.y - (double)o.b.y * c.b.x;
@@ -164,13 +183,18 @@ __global__ __launch_bounds__(256) void wilson2d_split_kernel(
 
 }  // namespace
 
+// lattices from this many sites on stream their results past the caches
+constexpr long kStreamSites = 1L << 20;
+
 template <typename T>
 void launch_wilson2d(const WilsonArgs<T>& a, int dagger, int epi, hipStream_t st) {
   const long V = (long)a.L1 * a.L2;
   long nb = (V + 255) / 256;
   if (epi == EPI_MRDOT || epi == EPI_NORM) nb = nb < red_block_cap() ? nb : red_block_cap();
   dim3 grid((unsigned)nb, (unsigned)a.nrhs);
-#define AMG_W2(DAG, EPI) dispatch(wilson2d_kernel<T, DAG, EPI>, a, grid, dim3(256), st)
+#define AMG_W2N(DAG, EPI, NT) dispatch(wilson2d_kernel<T, DAG, EPI, NT>, a, grid, dim3(256), st)
+#define AMG_W2(DAG, EPI) if (nt) { AMG_W2N(DAG, EPI, true); } else { AMG_W2N(DAG, EPI, false); }
+  const bool nt = V >= kStreamSites;
   if (dagger) {
     switch (epi) {
       case EPI_PLAIN: AMG_W2(1, EPI_PLAIN); break;
@@ -186,6 +210,7 @@ void launch_wilson2d(const WilsonArgs<T>& a, int dagger, int epi, hipStream_t st
       default: AMG_W2(0, EPI_NORM); break;
     }
   }
+#undef AMG_W2N
 #undef AMG_W2
 }
 

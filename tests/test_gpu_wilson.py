@@ -46,7 +46,7 @@ def test_wilson2d_fp32(L1, L2):
         assert rel_err(out, ref) < 1e-5
 
 
-@pytest.mark.parametrize("dims", [(4, 4, 4, 8), (6, 4, 2, 4), (8, 8, 8, 8)])
+@pytest.mark.parametrize("dims", [(4, 4, 4, 8), (6, 4, 2, 4), (8, 8, 8, 8), (4, 4, 2, 12), (2, 2, 4, 2), (4, 2, 2, 20)])
 def test_wilson4d(dims):
     import paper_0707_4018_amd as amg
     import torch
@@ -81,3 +81,24 @@ def test_apply_rejects_bad_arguments():
     assert lib.amg_apply(g.handle, 0, 0, b._ptr(x), b._ptr(y), 0, b._stream()) == 1
     with pytest.raises(ValueError):
         g.apply(torch.zeros((1, 64, 2, 1), dtype=torch.complex64, device="cuda"))
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_wilson2d_streaming_store_size(prec):
+    """A lattice of 2^20 sites takes the kernels' streaming-store path."""
+    import paper_0707_4018_amd as amg
+    import torch
+    L1 = L2 = 1024
+    print(f"wilson2d {prec} {L1}x{L2} (streaming stores)", flush=True)
+    th = synth.u1_heatbath(64, 64, 6.0, 20, synth.rng_for(90, 600, 64, 64, 7))
+    U = np.exp(1j * synth.tile_u1(th, L1 // 64, L2 // 64))[..., None, None]
+    g = amg.Gauge(dev(U), 0.03)
+    psi = synth.gaussian_field((1, L2 * L1, 2, 1), synth.rng_for(4, L1, L2))
+    dt = torch.complex128 if prec == "f64" else torch.complex64
+    for dagger in (False, True):
+        out = host(g.apply(dev(psi, dt), dagger=dagger, prec=amg.F64 if prec == "f64" else amg.F32))
+        ref = dirac.apply_D(U, psi[0].reshape(L2, L1, 2, 1), 0.03, dagger=dagger).reshape(1, -1, 2, 1)
+        if prec == "f64":
+            assert max_rel_err(out, ref) < 1e-12
+        else:
+            assert rel_err(out, ref) < 1e-5
