@@ -3,6 +3,9 @@
 // precision / layout conversions.  All coefficients stay on the device
 // (written by the last block of the producing reduction, read by the
 // consumers), so a solver step needs no host round trip.
+#include <algorithm>
+#include <cstdlib>
+
 #include "common.h"
 #include "kernels.h"
 #include "dispatch.h"
@@ -15,6 +18,24 @@ namespace {
 inline unsigned nblocks(long n, long cap) {
   long b = (n + 255) / 256;
   if (b > cap) b = cap;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+// grid of a reducing kernel: ept elements per thread (more blocks keep more
+// loads in flight, fewer leave fewer partial sums for the last block), at
+// most the reduction cap
+inline int red_ept() {
+  static int e = [] {
+    const char* v = std::getenv("AMG_RED_EPT");
+    return v ? std::max(1, std::atoi(v)) : 1;
+  }();
+  return e;
+}
+inline unsigned red_blocks(long n) {
+  const long per = 256L * red_ept();
+  long b = (n + per - 1) / per;
+  if (b > red_block_cap()) b = red_block_cap();
   if (b < 1) b = 1;
   return (unsigned)b;
 }
@@ -147,13 +168,16 @@ __global__ __launch_bounds__(256) void gcr_mdot_kernel(GcrArgs<T> a0, const GcrA
   for (int j = 0; j < 2 * KM; ++j) acc[j] = 0.0;
   GRID_STRIDE(i, a.n) {
     const cplx<T> wi = a.w[ro + i];
+    // every load is issued (clamped to a stored direction), the surplus ones
+    // are masked: no branch between the loads, so they are all in flight
+    cplx<T> q[KM];
+#pragma unroll
+    for (int j = 0; j < KM; ++j) q[j] = a.Wb[(long)(j < k ? j : k - 1) * a.dstride + ro + i];
 #pragma unroll
     for (int j = 0; j < KM; ++j) {
-      if (j < k) {
-        const cplx<T> q = a.Wb[(long)j * a.dstride + ro + i];
-        acc[2 * j] += (double)q.x * wi.x + (double)q.y * wi.y;
-        acc[2 * j + 1] += (double)q.x * wi.y - (double)q.y * wi.x;
-      }
+      const double m = j < k ? 1.0 : 0.0;
+      acc[2 * j] += m * ((double)q[j].x * wi.x + (double)q[j].y * wi.y);
+      acc[2 * j + 1] += m * ((double)q[j].x * wi.y - (double)q[j].y * wi.x);
     }
   }
   double tot[2 * KM];
@@ -168,7 +192,7 @@ __global__ __launch_bounds__(256) void gcr_mdot_kernel(GcrArgs<T> a0, const GcrA
 }
 
 // w -= sum_j beta_j W_j ; z -= sum_j beta_j Z_j ; then <w,w> and alpha = <w,r>/<w,w>
-template <typename T>
+template <typename T, int KM>
 __global__ __launch_bounds__(256) void gcr_maxpy_kernel(GcrArgs<T> a0, const GcrArgs<T>* batch) {
   AMG_ARGS(GcrArgs<T>)
   const int rhs = blockIdx.y;
@@ -176,14 +200,27 @@ __global__ __launch_bounds__(256) void gcr_maxpy_kernel(GcrArgs<T> a0, const Gcr
   const long ro = (long)rhs * a.n;
   const int k = a.k;
   const double* beta = a.red.scal + a.beta_slot + (long)rhs * GCR_KMAX * 2;
+  cplx<T> b[KM];
+#pragma unroll
+  for (int j = 0; j < KM; ++j)
+    b[j] = j < k ? mk<T>((T)beta[2 * j], (T)beta[2 * j + 1]) : mk<T>(0, 0);
   double acc[3] = {0.0, 0.0, 0.0};
   GRID_STRIDE(i, a.n) {
     cplx<T> wi = a.w[ro + i];
     cplx<T> zi = a.z[ro + i];
-    for (int j = 0; j < k; ++j) {
-      const cplx<T> b = mk<T>((T)beta[2 * j], (T)beta[2 * j + 1]);
-      wi = csub<T>(wi, cmul<T>(b, a.Wb[(long)j * a.dstride + ro + i]));
-      zi = csub<T>(zi, cmul<T>(b, a.Zb[(long)j * a.dstride + ro + i]));
+    if (k > 0) {
+      cplx<T> wq[KM], zq[KM];
+#pragma unroll
+      for (int j = 0; j < KM; ++j) {
+        const long off = (long)(j < k ? j : k - 1) * a.dstride + ro + i;
+        wq[j] = a.Wb[off];
+        zq[j] = a.Zb[off];
+      }
+#pragma unroll
+      for (int j = 0; j < KM; ++j) {
+        wi = csub<T>(wi, cmul<T>(b[j], wq[j]));
+        zi = csub<T>(zi, cmul<T>(b[j], zq[j]));
+      }
     }
     if (k > 0) { a.w[ro + i] = wi; a.z[ro + i] = zi; }
     const cplx<T> ri = a.r[ro + i];
@@ -365,7 +402,7 @@ template void launch_mr_update<float>(float2*, float2*, const float2*, const flo
 template <typename T>
 void launch_norm2(const cplx<T>* v, long n, int nrhs, RedArgs red, hipStream_t st) {
   NormArgs<T> a{v, n, red, nrhs};
-  dispatch(norm2_kernel<T>, a, dim3(nblocks(n, red_block_cap()), (unsigned)nrhs), dim3(256), st);
+  dispatch(norm2_kernel<T>, a, dim3(red_blocks(n), (unsigned)nrhs), dim3(256), st);
 }
 template void launch_norm2<double>(const double2*, long, int, RedArgs, hipStream_t);
 template void launch_norm2<float>(const float2*, long, int, RedArgs, hipStream_t);
@@ -387,8 +424,9 @@ void launch_gcr_mdot(const cplx<T>* Wb, long dstride, const cplx<T>* w, int k, l
   GcrArgs<T> a = gcr_args<T>(n, nrhs, red);
   a.Wb = const_cast<cplx<T>*>(Wb); a.dstride = dstride; a.w = const_cast<cplx<T>*>(w); a.k = k;
   a.beta_slot = beta_slot; a.ww_slot = ww_slot;
-  dim3 grid(nblocks(n, red_block_cap()), (unsigned)nrhs);
-  if (k <= 4) dispatch(gcr_mdot_kernel<T, 4>, a, grid, dim3(256), st);
+  dim3 grid(red_blocks(n), (unsigned)nrhs);
+  if (k <= 2) dispatch(gcr_mdot_kernel<T, 2>, a, grid, dim3(256), st);
+  else if (k <= 4) dispatch(gcr_mdot_kernel<T, 4>, a, grid, dim3(256), st);
   else if (k <= 8) dispatch(gcr_mdot_kernel<T, 8>, a, grid, dim3(256), st);
   else if (k <= 16) dispatch(gcr_mdot_kernel<T, 16>, a, grid, dim3(256), st);
   else dispatch(gcr_mdot_kernel<T, 32>, a, grid, dim3(256), st);
@@ -403,7 +441,13 @@ void launch_gcr_maxpy(cplx<T>* w, cplx<T>* z, const cplx<T>* Wb, const cplx<T>* 
   a.w = w; a.z = z; a.Wb = const_cast<cplx<T>*>(Wb); a.Zb = const_cast<cplx<T>*>(Zb); a.dstride = dstride;
   a.r = const_cast<cplx<T>*>(r); a.k = k;
   a.beta_slot = beta_slot; a.ww_slot = ww_slot; a.alpha_slot = alpha_slot;
-  dispatch(gcr_maxpy_kernel<T>, a, dim3(nblocks(n, red_block_cap()), (unsigned)nrhs), dim3(256), st);
+  const dim3 grid(red_blocks(n), (unsigned)nrhs);
+  if (k <= 1) dispatch(gcr_maxpy_kernel<T, 1>, a, grid, dim3(256), st);
+  else if (k <= 2) dispatch(gcr_maxpy_kernel<T, 2>, a, grid, dim3(256), st);
+  else if (k <= 4) dispatch(gcr_maxpy_kernel<T, 4>, a, grid, dim3(256), st);
+  else if (k <= 8) dispatch(gcr_maxpy_kernel<T, 8>, a, grid, dim3(256), st);
+  else if (k <= 16) dispatch(gcr_maxpy_kernel<T, 16>, a, grid, dim3(256), st);
+  else dispatch(gcr_maxpy_kernel<T, 32>, a, grid, dim3(256), st);
 }
 template void launch_gcr_maxpy<double>(double2*, double2*, const double2*, const double2*, long, const double2*, int, long, int, RedArgs, int, int, int, hipStream_t);
 template void launch_gcr_maxpy<float>(float2*, float2*, const float2*, const float2*, long, const float2*, int, long, int, RedArgs, int, int, int, hipStream_t);
@@ -414,7 +458,7 @@ void launch_gcr_update(cplx<T>* x, cplx<T>* r, const cplx<T>* z, const cplx<T>* 
   GcrArgs<T> a = gcr_args<T>(n, nrhs, red);
   a.x = x; a.r = r; a.z = const_cast<cplx<T>*>(z); a.w = const_cast<cplx<T>*>(w);
   a.alpha_slot = alpha_slot; a.rr_slot = rr_slot; a.bb_slot = bb_slot; a.tol2 = tol2; a.set_flags = set_flags;
-  dispatch(gcr_update_kernel<T>, a, dim3(nblocks(n, red_block_cap()), (unsigned)nrhs), dim3(256), st);
+  dispatch(gcr_update_kernel<T>, a, dim3(red_blocks(n), (unsigned)nrhs), dim3(256), st);
 }
 template void launch_gcr_update<double>(double2*, double2*, const double2*, const double2*, long, int, RedArgs, int, int, int, double, int*, hipStream_t);
 template void launch_gcr_update<float>(float2*, float2*, const float2*, const float2*, long, int, RedArgs, int, int, int, double, int*, hipStream_t);
@@ -427,7 +471,7 @@ void launch_gcr_update2(cplx<T>* x, cplx<T>* r, const cplx<T>* zsrc, cplx<T>* Wb
   a.x = x; a.r = r; a.zsrc = zsrc; a.Wb = Wb; a.Zb = Zb; a.dstride = dstride; a.k = k;
   a.beta_slot = beta_slot; a.alpha_slot = alpha_slot; a.rr_slot = rr_slot; a.bb_slot = bb_slot; a.tol2 = tol2;
   a.set_flags = set_flags;
-  dispatch(gcr_update2_kernel<T>, a, dim3(nblocks(n, red_block_cap()), (unsigned)nrhs), dim3(256), st);
+  dispatch(gcr_update2_kernel<T>, a, dim3(red_blocks(n), (unsigned)nrhs), dim3(256), st);
 }
 template void launch_gcr_update2<double>(double2*, double2*, const double2*, double2*, double2*, long, int, long, int,
                                          RedArgs, int, int, int, int, double, int*, hipStream_t);
@@ -447,7 +491,7 @@ void launch_gather(double* out, const double* scal, int slot, int nrhs, hipStrea
 
 void launch_cg_update(double2* x, double2* r, const double2* p, const double2* q, long n, int nrhs, RedArgs red,
                       int gamma_slot, int qq_slot, int rr_slot, hipStream_t st) {
-  dim3 grid(nblocks(n, red_block_cap()), (unsigned)nrhs);
+  dim3 grid(red_blocks(n), (unsigned)nrhs);
   hipLaunchKernelGGL(cg_update_kernel, grid, dim3(256), 0, st, x, r, p, q, n, red, gamma_slot, qq_slot, rr_slot);
 }
 

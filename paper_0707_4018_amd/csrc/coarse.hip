@@ -106,35 +106,72 @@ template <typename T> struct C16 {
   static constexpr int NQ = NC / CPI;  // loads per lane per direction
 };
 
-template <typename T, int DAG>
+// ND = 2: the five directions are known at compile time, so the loads of all
+// of them are issued before the first multiply-add (one memory round trip per
+// site instead of five: the 2d coarse levels are small and latency-bound).
+// ND = 0: any dimension, one direction at a time.
+template <typename T, int DAG, int ND>
 __device__ __forceinline__ void site_apply16(const cplx<T>* __restrict__ Y, const cplx<T>* __restrict__ pin, long site,
                                              const CoarseGeom& g, int cg, int rg, cplx<T> (&acc)[C16<T>::R]) {
   using K = C16<T>;
-  int x[4];
-  coords(site, g.dims, g.nd, x);
-  const int ndir = 2 * g.nd + 1;
 #pragma unroll
   for (int i = 0; i < K::R; ++i) acc[i] = mk<T>(0, 0);
-  const cplx<T>* __restrict__ Ys = Y + site * (long)ndir * K::NC * K::NC;
-  for (int k = 0; k < ndir; ++k) {
-    const long nb = (k == 0) ? site : neighbour(site, x, g.dims, g.nd, k - 1);
-    const cplx<T>* __restrict__ e = pin + nb * K::NC;
-    const cplx<T>* __restrict__ yk = Ys + (long)k * K::NC * K::NC + rg * K::R;
-    cplx<T> ev[K::NQ], yv[K::NQ][K::R];
+  if (ND == 2) {
+    constexpr int NDIR = 5;
+    const int L1 = g.dims[0], L2 = g.dims[1];
+    const int x1 = (int)(site % L1), x2 = (int)(site / L1);
+    long nbs[NDIR];
+    nbs[0] = site;
+    nbs[1] = (x1 == L1 - 1) ? site - (L1 - 1) : site + 1;
+    nbs[2] = (x1 == 0) ? site + (L1 - 1) : site - 1;
+    nbs[3] = (x2 == L2 - 1) ? site - (long)(L2 - 1) * L1 : site + L1;
+    nbs[4] = (x2 == 0) ? site + (long)(L2 - 1) * L1 : site - L1;
+    const cplx<T>* __restrict__ Ys = Y + site * (long)NDIR * K::NC * K::NC + rg * K::R;
+    cplx<T> ev[NDIR][K::NQ], yv[NDIR][K::NQ][K::R];
 #pragma unroll
-    for (int q = 0; q < K::NQ; ++q) {
-      const int col = cg + K::CPI * q;
-      ev[q] = e[col];
+    for (int k = 0; k < NDIR; ++k)
 #pragma unroll
-      for (int i = 0; i < K::R; ++i) yv[q][i] = yk[col * K::NC + i];
-    }
+      for (int q = 0; q < K::NQ; ++q) {
+        const int col = cg + K::CPI * q;
+        ev[k][q] = pin[nbs[k] * K::NC + col];
 #pragma unroll
-    for (int q = 0; q < K::NQ; ++q) {
-      const int col = cg + K::CPI * q;
-      cplx<T> v = ev[q];
-      if (DAG && col >= K::NC / 2) v = mk<T>(-v.x, -v.y);
+        for (int i = 0; i < K::R; ++i) yv[k][q][i] = Ys[(long)k * K::NC * K::NC + col * K::NC + i];
+      }
 #pragma unroll
-      for (int i = 0; i < K::R; ++i) cfma<T>(acc[i], yv[q][i], v);
+    for (int k = 0; k < NDIR; ++k)
+#pragma unroll
+      for (int q = 0; q < K::NQ; ++q) {
+        const int col = cg + K::CPI * q;
+        cplx<T> v = ev[k][q];
+        if (DAG && col >= K::NC / 2) v = mk<T>(-v.x, -v.y);
+#pragma unroll
+        for (int i = 0; i < K::R; ++i) cfma<T>(acc[i], yv[k][q][i], v);
+      }
+  } else {
+    int x[4];
+    coords(site, g.dims, g.nd, x);
+    const int ndir = 2 * g.nd + 1;
+    const cplx<T>* __restrict__ Ys = Y + site * (long)ndir * K::NC * K::NC;
+    for (int k = 0; k < ndir; ++k) {
+      const long nb = (k == 0) ? site : neighbour(site, x, g.dims, g.nd, k - 1);
+      const cplx<T>* __restrict__ e = pin + nb * K::NC;
+      const cplx<T>* __restrict__ yk = Ys + (long)k * K::NC * K::NC + rg * K::R;
+      cplx<T> ev[K::NQ], yv[K::NQ][K::R];
+#pragma unroll
+      for (int q = 0; q < K::NQ; ++q) {
+        const int col = cg + K::CPI * q;
+        ev[q] = e[col];
+#pragma unroll
+        for (int i = 0; i < K::R; ++i) yv[q][i] = yk[col * K::NC + i];
+      }
+#pragma unroll
+      for (int q = 0; q < K::NQ; ++q) {
+        const int col = cg + K::CPI * q;
+        cplx<T> v = ev[q];
+        if (DAG && col >= K::NC / 2) v = mk<T>(-v.x, -v.y);
+#pragma unroll
+        for (int i = 0; i < K::R; ++i) cfma<T>(acc[i], yv[q][i], v);
+      }
     }
   }
 #pragma unroll
@@ -147,7 +184,7 @@ __device__ __forceinline__ void site_apply16(const cplx<T>* __restrict__ Y, cons
   }
 }
 
-template <typename T, int DAG, int EPI>
+template <typename T, int DAG, int EPI, int ND>
 __global__ __launch_bounds__(256) void coarse16_kernel(CoarseArgs<T> a0, const CoarseArgs<T>* batch) {
   AMG_ARGS(CoarseArgs<T>)
   using K = C16<T>;
@@ -162,7 +199,7 @@ __global__ __launch_bounds__(256) void coarse16_kernel(CoarseArgs<T> a0, const C
   double acc3[3] = {0.0, 0.0, 0.0};
   for (long site = (long)blockIdx.x * 4 + wave; site < V; site += (long)gridDim.x * 4) {
     cplx<T> acc[K::R];
-    site_apply16<T, DAG>(a.Y, pin, site, a.g, cg, rg, acc);
+    site_apply16<T, DAG, ND>(a.Y, pin, site, a.g, cg, rg, acc);
     if (cg == 0) {
 #pragma unroll
       for (int i = 0; i < K::R; ++i) {
@@ -235,7 +272,8 @@ __global__ __launch_bounds__(256) void gcr16_apply_dots_kernel(G16Args<T> a0, co
   double* mine = sh + (wave * K::LPC + rg) * G16_NQ;  // this lane's accumulators (cg == 0 lanes)
   for (long site = (long)blockIdx.x * 4 + wave; site < V; site += (long)gridDim.x * 4) {
     cplx<T> acc[K::R];
-    site_apply16<T, 0>(a.Y, a.in + ro, site, a.g, cg, rg, acc);
+    if (a.g.nd == 2) site_apply16<T, 0, 2>(a.Y, a.in + ro, site, a.g, cg, rg, acc);
+    else site_apply16<T, 0, 0>(a.Y, a.in + ro, site, a.g, cg, rg, acc);
     if (cg == 0) {
       double ww = 0.0, wrr = 0.0, wri = 0.0;
 #pragma unroll
@@ -594,7 +632,8 @@ void launch_coarse(const CoarseArgs<T>& a, int dagger, int epi, hipStream_t st) 
     const long cap = red ? (long)red_block_cap() : (1L << 20);
     if (nb > cap) nb = cap;
     dim3 g16((unsigned)nb, (unsigned)a.nrhs);
-#define AMG_C16(DAG, EPI) dispatch(coarse16_kernel<T, DAG, EPI>, a, g16, dim3(256), st)
+#define AMG_C16N(DAG, EPI, ND) dispatch(coarse16_kernel<T, DAG, EPI, ND>, a, g16, dim3(256), st)
+#define AMG_C16(DAG, EPI) if (a.g.nd == 2) { AMG_C16N(DAG, EPI, 2); } else { AMG_C16N(DAG, EPI, 0); }
     switch (epi * 2 + (dagger ? 1 : 0)) {
       case EPI_PLAIN * 2: AMG_C16(0, EPI_PLAIN); break;
       case EPI_PLAIN * 2 + 1: AMG_C16(1, EPI_PLAIN); break;
@@ -606,6 +645,7 @@ void launch_coarse(const CoarseArgs<T>& a, int dagger, int epi, hipStream_t st) 
       default: AMG_C16(1, EPI_NORM); break;
     }
 #undef AMG_C16
+#undef AMG_C16N
   } else if (a.g.nc == 48) {
     if (dagger) { AMG_C_EPI(48, 1) } else { AMG_C_EPI(48, 0) }
   } else {

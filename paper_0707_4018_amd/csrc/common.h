@@ -125,15 +125,16 @@ __device__ bool grid_reduce(double (&v)[NV], double* part, unsigned* ticket, int
   }
   __syncthreads();
   if (!is_last) return false;
+  // acquire: every block released its partials (fence) before taking a
+  // ticket, and this fence invalidates the local caches, so plain loads see
+  // them; plain loads can all be in flight at once, unlike coherent ones
   __threadfence();
   double s[NV];
 #pragma unroll
-  for (int k = 0; k < NV; ++k) {
-    double a = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += blockDim.x)
-      a += __hip_atomic_load(&part[((long)rhs * NV + k) * nblk + b], __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
-    s[k] = a;
+  for (int k = 0; k < NV; ++k) s[k] = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) s[k] += part[((long)rhs * NV + k) * nblk + b];
   }
   block_sum<NV>(s, sh);
 #pragma unroll
