@@ -109,6 +109,29 @@ __global__ void mr_update_kernel(MrArgs<T> a0, const MrArgs<T>* batch) {
   if (skip_rhs(a.flags, rhs)) return;
   const cplx<T> al = mk<T>((T)a.alpha[2 * rhs], (T)a.alpha[2 * rhs + 1]);
   const long ro = (long)rhs * a.n;
+  if (sizeof(T) == 4 && (a.n & 1) == 0) {
+    // FP32: two complex numbers per 16-byte access
+    using V4 = float4;
+    const long n2 = a.n / 2, ro2 = ro / 2;
+    const V4* __restrict__ rin = reinterpret_cast<const V4*>(a.r_in) + ro2;
+    const V4* __restrict__ pp = reinterpret_cast<const V4*>(a.p) + ro2;
+    V4* __restrict__ xx = reinterpret_cast<V4*>(a.x) + ro2;
+    V4* __restrict__ rout = reinterpret_cast<V4*>(a.r_out) + ro2;
+    const float ar = (float)al.x, ai = (float)al.y;
+    GRID_STRIDE(i, n2) {
+      const V4 r = rin[i];
+      V4 x = a.first ? make_float4(0.f, 0.f, 0.f, 0.f) : xx[i];
+      x.x += ar * r.x - ai * r.y; x.y += ar * r.y + ai * r.x;
+      x.z += ar * r.z - ai * r.w; x.w += ar * r.w + ai * r.z;
+      xx[i] = x;
+      if (a.update_r) {
+        const V4 q = pp[i];
+        rout[i] = make_float4(r.x - (ar * q.x - ai * q.y), r.y - (ar * q.y + ai * q.x),
+                              r.z - (ar * q.z - ai * q.w), r.w - (ar * q.w + ai * q.z));
+      }
+    }
+    return;
+  }
   GRID_STRIDE(i, a.n) {
     const cplx<T> r = a.r_in[ro + i];
     const cplx<T> ar = cmul<T>(al, r);

@@ -420,30 +420,32 @@ __global__ __launch_bounds__(256) void coarse_massmat_kernel(double2* __restrict
 
 struct BlockIdx {
   // fine site of (coarse site j, site-in-block xi)
+  // (32-bit index arithmetic: lattices have fewer than 2^31 sites)
   static __device__ __forceinline__ long fine_site(const TransferGeom& g, long j, int xi) {
-    long rj = j;
+    int rj = (int)j;
     int rxi = xi;
-    long fs = 0, stride = 1;
+    int fs = 0, stride = 1;
     for (int mu = 0; mu < g.nd; ++mu) {
-      const int jc = (int)(rj % g.cdims[mu]); rj /= g.cdims[mu];
+      const int jc = rj % g.cdims[mu]; rj /= g.cdims[mu];
       const int bc = rxi % g.blk[mu]; rxi /= g.blk[mu];
-      fs += (long)(jc * g.blk[mu] + bc) * stride;
+      fs += (jc * g.blk[mu] + bc) * stride;
       stride *= g.fdims[mu];
     }
     return fs;
   }
   // (coarse site, site-in-block) of a fine site
   static __device__ __forceinline__ void coarse_of(const TransferGeom& g, long fs, long& j, int& xi) {
-    long rem = fs, cs = 1;
+    int rem = (int)fs, cs = 1, jj = 0;
     int bstride = 1;
-    j = 0; xi = 0;
+    xi = 0;
     for (int mu = 0; mu < g.nd; ++mu) {
-      const int x = (int)(rem % g.fdims[mu]); rem /= g.fdims[mu];
-      j += (long)(x / g.blk[mu]) * cs;
+      const int x = rem % g.fdims[mu]; rem /= g.fdims[mu];
+      jj += (x / g.blk[mu]) * cs;
       xi += (x % g.blk[mu]) * bstride;
       cs *= g.cdims[mu];
       bstride *= g.blk[mu];
     }
+    j = jj;
   }
 };
 
@@ -516,6 +518,138 @@ __global__ __launch_bounds__(256) void prolong_kernel(TrArgs<T, PT> a0, const Tr
     for (int k = 0; k < g.nv; ++k) cfma<T>(acc, ldp<T>(P, pb + k), e[k]);
     const long o = rof + g.lf.off(fs, comp);
     out[o] = accumulate ? cadd<T>(out[o], acc) : acc;
+  }
+}
+
+// ---- transfers for large blocks (4d: 256 sites x 6 components per chirality) --
+// One wave per (coarse site j, chirality chi); right-hand sides go in groups
+// of RG inside the wave, so every row of P is read once per group instead of
+// once per right-hand side (the per-element kernels above re-read all of P
+// for each rhs and serialise 1536 terms per thread).
+//
+// restriction: lane l < 2 NV owns coarse component k = l mod NV and the
+// components h of parity l / NV; consecutive lanes read consecutive k of one
+// row of P.  The two parities are combined by one cross-lane add.
+template <typename T, typename PT, int NV, int RG>
+__global__ __launch_bounds__(256) void restrict_blk_kernel(TrArgs<T, PT> a0, const TrArgs<T, PT>* batch) {
+  AMG_ARGS(TrArgs<T, PT>)
+  const TransferGeom& g = a.g;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const long q = (long)blockIdx.x * 4 + wave;
+  if (q >= g.Vc * 2) return;
+  const long j = q >> 1;
+  const int chi = (int)(q & 1);
+  const int k = lane % NV, par = lane / NV;
+  const bool active = lane < 2 * NV;
+  const int hd = g.dof / 2;
+  const long per_f = g.lf.per_rhs(), per_c = g.Vc * 2 * NV;
+  for (int r0 = 0; r0 < a.nrhs; r0 += RG) {
+    const int nr = (a.nrhs - r0 < RG) ? a.nrhs - r0 : RG;
+    cplx<T> acc[RG];
+#pragma unroll
+    for (int r = 0; r < RG; ++r) acc[r] = mk<T>(0, 0);
+    if (active) {
+      // sites of the block in P order (x_1 fastest) from the block origin,
+      // with 32-bit additions only
+      const long fs0 = BlockIdx::fine_site(g, j, 0);
+      const int s1 = g.fdims[0], s2 = s1 * g.fdims[1], s3 = s2 * g.fdims[2];
+      // elements (xi, h) of this lane's parity, UN at a time: all their loads
+      // are issued before the multiply-adds (the chain is latency-bound)
+      constexpr int UN = 6;
+      const int hn = (hd - par + 1) / 2;    // components of this parity per site
+      const int nel = g.bs * hn;
+      const long pbase = (j * g.bs * g.dof + chi * hd) * (long)NV + k;
+      for (int e0 = 0; e0 < nel; e0 += UN) {
+        cplx<T> pv[UN];
+        long fo[UN];
+#pragma unroll
+        for (int u = 0; u < UN; ++u) {
+          const int e = (e0 + u < nel) ? e0 + u : nel - 1;
+          const int xi = e / hn, h = par + 2 * (e - xi * hn);
+          int rem = xi;
+          const int b0 = rem % g.blk[0]; rem /= g.blk[0];
+          const int b1 = rem % g.blk[1]; rem /= g.blk[1];
+          const int b2 = rem % g.blk[2]; rem /= g.blk[2];
+          const long fs = fs0 + b0 + b1 * s1 + b2 * s2 + (long)rem * s3;
+          const T w = (e0 + u < nel) ? (T)1 : (T)0;
+          const cplx<T> pp = ldp<T>(a.P, pbase + ((long)xi * g.dof + h) * NV);
+          pv[u] = mk<T>(w * pp.x, w * pp.y);
+          fo[u] = g.lf.off(fs, chi * hd + h);
+        }
+#pragma unroll
+        for (int r = 0; r < RG; ++r)
+          if (r < nr) {
+            cplx<T> xv[UN];
+#pragma unroll
+            for (int u = 0; u < UN; ++u) xv[u] = a.in[(long)(r0 + r) * per_f + fo[u]];
+#pragma unroll
+            for (int u = 0; u < UN; ++u) cjfma<T>(acc[r], pv[u], xv[u]);
+          }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < RG; ++r) {
+      const int src = (lane + NV) & 63;
+      const T ox = __shfl(acc[r].x, src, 64), oy = __shfl(acc[r].y, src, 64);
+      if (r < nr && lane < NV && !skip_rhs(a.flags, r0 + r))
+        a.out[(long)(r0 + r) * per_c + j * 2 * NV + chi * NV + k] = mk<T>(acc[r].x + ox, acc[r].y + oy);
+    }
+  }
+}
+
+// prolongation: lane owns (site xi, component pair hp) elements of the block
+// (sites fastest, for the fine-field stores) and computes both components of
+// the pair for RG right-hand sides; the coarse values of (j, chi) are read by
+// every lane (cache broadcast).
+template <typename T, typename PT, int NV, int RG>
+__global__ __launch_bounds__(256) void prolong_blk_kernel(TrArgs<T, PT> a0, const TrArgs<T, PT>* batch) {
+  AMG_ARGS(TrArgs<T, PT>)
+  const TransferGeom& g = a.g;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const long q = (long)blockIdx.x * 4 + wave;
+  if (q >= g.Vc * 2) return;
+  const long j = q >> 1;
+  const int chi = (int)(q & 1);
+  const int hd = g.dof / 2, hp_n = hd / 2;
+  const long per_f = g.lf.per_rhs(), per_c = g.Vc * 2 * NV;
+  const long fs0 = BlockIdx::fine_site(g, j, 0);
+  const int s1 = g.fdims[0], s2 = s1 * g.fdims[1], s3 = s2 * g.fdims[2];
+  for (int r0 = 0; r0 < a.nrhs; r0 += RG) {
+    const int nr = (a.nrhs - r0 < RG) ? a.nrhs - r0 : RG;
+    for (int xi = lane; xi < g.bs; xi += 64) {
+      int rem = xi;
+      const int b0 = rem % g.blk[0]; rem /= g.blk[0];
+      const int b1 = rem % g.blk[1]; rem /= g.blk[1];
+      const int b2 = rem % g.blk[2]; rem /= g.blk[2];
+      const long fs = fs0 + b0 + b1 * s1 + b2 * s2 + (long)rem * s3;
+      for (int hp = 0; hp < hp_n; ++hp) {
+      const int c0 = chi * hd + 2 * hp;
+      const long prow = ((j * g.bs + xi) * g.dof + c0) * (long)NV;
+      cplx<T> s0[RG], s1[RG];  // (the pair's two components)
+#pragma unroll
+      for (int r = 0; r < RG; ++r) { s0[r] = mk<T>(0, 0); s1[r] = mk<T>(0, 0); }
+      const cplx<T>* __restrict__ e = a.in + (long)r0 * per_c + j * 2 * NV + chi * NV;
+#pragma unroll 4
+      for (int k = 0; k < NV; ++k) {
+        const cplx<T> p0 = ldp<T>(a.P, prow + k), p1 = ldp<T>(a.P, prow + NV + k);
+#pragma unroll
+        for (int r = 0; r < RG; ++r)
+          if (r < nr) {
+            const cplx<T> ev = e[(long)r * per_c + k];
+            cfma<T>(s0[r], p0, ev);
+            cfma<T>(s1[r], p1, ev);
+          }
+      }
+      const long o0 = g.lf.off(fs, c0), o1 = g.lf.off(fs, c0 + 1);
+#pragma unroll
+      for (int r = 0; r < RG; ++r)
+        if (r < nr && !skip_rhs(a.flags, r0 + r)) {
+          cplx<T>* __restrict__ out = a.out + (long)(r0 + r) * per_f;
+          out[o0] = a.accumulate ? cadd<T>(out[o0], s0[r]) : s0[r];
+          out[o1] = a.accumulate ? cadd<T>(out[o1], s1[r]) : s1[r];
+        }
+      }
+    }
   }
 }
 
@@ -684,9 +818,28 @@ void launch_coarse_massmat(double2* out, const double2* in, const double2* M, co
   hipLaunchKernelGGL(coarse_massmat_kernel, grid, dim3(256), 0, st, out, in, M, g.V, g.nc);
 }
 
+// the per-wave kernels need an even number of components per chirality, a
+// block large enough to fill a wave, and 2 NV <= 64 lanes
+inline bool blk_transfer(const TransferGeom& g) {
+  return g.nd == 4 && (g.dof / 2) % 2 == 0 && g.bs * (g.dof / 2) >= 512 && g.nv == 24;
+}
+
 template <typename T>
 void launch_restrict(cplx<T>* out, const cplx<T>* in, const void* P, int pkind, const TransferGeom& g, int nrhs,
                      const int* flags, hipStream_t st) {
+  // several right-hand sides: the per-wave kernel reads P once per group of
+  // them (measured 2x faster at 12 rhs); one rhs: the per-element kernel
+  if (blk_transfer(g) && nrhs > 1) {
+    const dim3 grid((unsigned)((g.Vc * 2 + 3) / 4), 1);
+#define AMG_RB(PT, RG) dispatch(restrict_blk_kernel<T, PT, 24, RG>, TrArgs<T, PT>{out, in, (const PT*)P, g, flags, 0, nrhs}, grid, dim3(256), st)
+#define AMG_RB_G(PT) if (nrhs <= 4) { AMG_RB(PT, 4); } else { AMG_RB(PT, 16); }
+    if (pkind == P_F64) { AMG_RB_G(double2) }
+    else if (pkind == P_F32) { AMG_RB_G(float2) }
+    else { AMG_RB_G(bf16x2) }
+#undef AMG_RB_G
+#undef AMG_RB
+    return;
+  }
   dim3 grid(nblocks(g.Vc * 2 * g.nv), (unsigned)nrhs);
   if (pkind == P_F64)
     dispatch(restrict_kernel<T, double2>, TrArgs<T, double2>{out, in, (const double2*)P, g, flags, 0, nrhs}, grid, dim3(256), st);
@@ -701,6 +854,15 @@ template void launch_restrict<float>(float2*, const float2*, const void*, int, c
 template <typename T>
 void launch_prolong(cplx<T>* out, const cplx<T>* in, const void* P, int pkind, const TransferGeom& g, int nrhs,
                     int accumulate, const int* flags, hipStream_t st) {
+  if (blk_transfer(g) && nrhs >= 4) {
+    const dim3 grid((unsigned)((g.Vc * 2 + 3) / 4), 1);
+#define AMG_PB(PT) dispatch(prolong_blk_kernel<T, PT, 24, 8>, TrArgs<T, PT>{out, in, (const PT*)P, g, flags, accumulate, nrhs}, grid, dim3(256), st)
+    if (pkind == P_F64) AMG_PB(double2);
+    else if (pkind == P_F32) AMG_PB(float2);
+    else AMG_PB(bf16x2);
+#undef AMG_PB
+    return;
+  }
   dim3 grid(nblocks(g.Vf * g.dof), (unsigned)nrhs);
   if (pkind == P_F64)
     dispatch(prolong_kernel<T, double2>, TrArgs<T, double2>{out, in, (const double2*)P, g, flags, accumulate, nrhs}, grid, dim3(256), st);

@@ -1222,7 +1222,7 @@ amg_status amg_gauge_create(const amg_lattice* lat, const void* dev_links, doubl
     if (lat->dims[mu] < 2 || lat->dims[mu] % 2) fail(AMG_ERR_SHAPE, "lattice extents must be even and >= 2");
     V *= lat->dims[mu];
   }
-  if (V > (1L << 31)) fail(AMG_ERR_SHAPE, "lattice too large");
+  if (V >= (1L << 31)) fail(AMG_ERR_SHAPE, "lattice too large");
   hipStream_t st = as_stream(stream);
   amg_gauge* g = new amg_gauge();
   try {

@@ -13,6 +13,8 @@
 //   FP64 spinor: two planes [spin][site] of double2;  links [mu][site] double2
 //   FP32 spinor: [site] float4 = (s0, s1);            links [site] float4 = (U_1, U_2)
 // These are Layout{V, 2, W} with W = 1 (FP64) and W = 2 (FP32).
+#include <cstdlib>
+
 #include "common.h"
 #include "kernels.h"
 #include "dispatch.h"
@@ -194,7 +196,11 @@ void launch_wilson2d(const WilsonArgs<T>& a, int dagger, int epi, hipStream_t st
   dim3 grid((unsigned)nb, (unsigned)a.nrhs);
 #define AMG_W2N(DAG, EPI, NT) dispatch(wilson2d_kernel<T, DAG, EPI, NT>, a, grid, dim3(256), st)
 #define AMG_W2(DAG, EPI) if (nt) { AMG_W2N(DAG, EPI, true); } else { AMG_W2N(DAG, EPI, false); }
-  const bool nt = V >= kStreamSites;
+  static const bool nt_on = [] {
+    const char* e = std::getenv("AMG_STREAM_STORES");
+    return e ? std::atoi(e) != 0 : true;
+  }();
+  const bool nt = nt_on && V >= kStreamSites;
   if (dagger) {
     switch (epi) {
       case EPI_PLAIN: AMG_W2(1, EPI_PLAIN); break;

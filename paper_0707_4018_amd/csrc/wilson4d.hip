@@ -60,6 +60,60 @@ __device__ __forceinline__ void st_spinor(float2* __restrict__ p, long s, long V
   }
 }
 
+// streaming (non-temporal) stores for lattices far larger than the caches:
+// the result bypasses L2, so it evicts no neighbour data and leaves no dirty
+// lines for the reductions' release fences to write back
+typedef double v2d __attribute__((ext_vector_type(2)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void st_spinor_nt(double2* __restrict__ p, long s, long V, const Spinor<double>& o) {
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const v2d v = {o.c[sp][c].x, o.c[sp][c].y};
+      __builtin_nontemporal_store(v, reinterpret_cast<v2d*>(p) + (long)(sp * 3 + c) * V + s);
+    }
+}
+__device__ __forceinline__ void st_spinor_nt(float2* __restrict__ p, long s, long V, const Spinor<float>& o) {
+#pragma unroll
+  for (int u = 0; u < 6; ++u) {
+    const int c0 = 2 * u, c1 = 2 * u + 1;
+    const float2 a = o.c[c0 / 3][c0 % 3], b = o.c[c1 / 3][c1 % 3];
+    const v4f v = {a.x, a.y, b.x, b.y};
+    __builtin_nontemporal_store(v, reinterpret_cast<v4f*>(p) + (long)u * V + s);
+  }
+}
+template <bool NT, typename T>
+__device__ __forceinline__ void st_out(cplx<T>* __restrict__ p, long s, long V, const Spinor<T>& o) {
+  if (NT) st_spinor_nt(p, s, V, o);
+  else st_spinor(p, s, V, o);
+}
+
+// <o, c>, |o|^2 (MRDOT) or |o|^2 (NORM) of one site, summed over its 12
+// components in T and added to the FP64 accumulators
+template <typename T, int EPI>
+__device__ __forceinline__ void site_dots(const Spinor<T>& o, const Spinor<T>& c, double (&acc)[3]) {
+  T s0 = 0, s1 = 0, s2 = 0;
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const cplx<T> u = o.c[sp][k], r = c.c[sp][k];
+      if (EPI == EPI_MRDOT) {
+        s0 += u.x * r.x + u.y * r.y;
+        s1 += u.x * r.y - u.y * r.x;
+      }
+      s2 += u.x * u.x + u.y * u.y;
+    }
+  if (EPI == EPI_MRDOT) {
+    acc[0] += (double)s0;
+    acc[1] += (double)s1;
+    acc[2] += (double)s2;
+  } else {
+    acc[0] += (double)s2;
+  }
+}
+
 template <typename T> struct Link { cplx<T> m[3][3]; };
 
 template <typename T>
@@ -158,7 +212,7 @@ __device__ __forceinline__ void all_hops(Spinor<T>& o, const cplx<T>* __restrict
 Geo4 geo(const int* d);
 
 // W: minimum waves per SIMD asked of the register allocator
-template <typename T, int DAG, int EPI, int W>
+template <typename T, int DAG, int EPI, int W, bool NT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) void wilson4d_kernel(
     WilsonArgs<T> a0, const WilsonArgs<T>* batch) {
   AMG_ARGS(WilsonArgs<T>)
@@ -198,23 +252,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
 #pragma unroll
         for (int k = 0; k < 3; ++k) o.c[sp][k] = csub<T>(b.c[sp][k], o.c[sp][k]);
     }
-    st_spinor(out + ro, s, V, o);
-    if (copy_out) st_spinor(copy_out + ro, s, V, c);
-    if (EPI == EPI_MRDOT || EPI == EPI_NORM) {
-#pragma unroll
-      for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          const cplx<T> a = o.c[sp][k], r = c.c[sp][k];
-          if (EPI == EPI_MRDOT) {
-            acc[0] += (double)a.x * r.x + (double)a.y * r.y;
-            acc[1] += (double)a.x * r.y - (double)a.y * r.x;
-            acc[2] += (double)a.x * a.x + (double)a.y * a.y;
-          } else {
-            acc[0] += (double)a.x * a.x + (double)a.y * a.y;
-          }
-        }
-    }
+    st_out<NT>(out + ro, s, V, o);
+    if (copy_out) st_out<NT>(copy_out + ro, s, V, c);
+    if (EPI == EPI_MRDOT || EPI == EPI_NORM) site_dots<T, EPI>(o, c, acc);
   }
   if (EPI == EPI_MRDOT) {
     double tot[3];
@@ -232,7 +272,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
 // 3-volume apart and would otherwise be re-fetched from memory), and the
 // blocks are renumbered so that every XCD works on one contiguous part of
 // the lattice (its L2 then holds the x_3 neighbours of its own columns).
-template <typename T, int DAG, int EPI, int TT>
+template <typename T, int DAG, int EPI, int TT, bool NT>
 __global__ __launch_bounds__(256) void wilson4d_tm_kernel(WilsonArgs<T> a0, const WilsonArgs<T>* batch) {
   AMG_ARGS(WilsonArgs<T>)
   const int rhs = blockIdx.y;
@@ -299,23 +339,9 @@ __global__ __launch_bounds__(256) void wilson4d_tm_kernel(WilsonArgs<T> a0, cons
 #pragma unroll
           for (int k = 0; k < 3; ++k) o.c[sp][k] = csub<T>(b.c[sp][k], o.c[sp][k]);
       }
-      st_spinor(a.out + ro, s, V, o);
-      if (a.copy_out) st_spinor(a.copy_out + ro, s, V, cur);
-      if (EPI == EPI_MRDOT || EPI == EPI_NORM) {
-#pragma unroll
-        for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-          for (int k = 0; k < 3; ++k) {
-            const cplx<T> u = o.c[sp][k], r = cur.c[sp][k];
-            if (EPI == EPI_MRDOT) {
-              acc[0] += (double)u.x * r.x + (double)u.y * r.y;
-              acc[1] += (double)u.x * r.y - (double)u.y * r.x;
-              acc[2] += (double)u.x * u.x + (double)u.y * u.y;
-            } else {
-              acc[0] += (double)u.x * u.x + (double)u.y * u.y;
-            }
-          }
-      }
+      st_out<NT>(a.out + ro, s, V, o);
+      if (a.copy_out) st_out<NT>(a.copy_out + ro, s, V, cur);
+      if (EPI == EPI_MRDOT || EPI == EPI_NORM) site_dots<T, EPI>(o, cur, acc);
       prev = cur;
       cur = nxt;
       Lb = Lf;
@@ -420,10 +446,13 @@ int w4_tt() {
   }();
   return tt;
 }
+// minimum waves per SIMD for the one-site kernel: 2 for FP32 (fits without
+// spilling, ~10% faster), 1 for FP64 (two waves would spill)
+template <typename T>
 int w4_waves() {
   static int w = [] {
     const char* e = std::getenv("AMG_W4_WAVES");
-    return e ? std::atoi(e) : 1;
+    return e ? std::atoi(e) : (sizeof(T) == 4 ? 2 : 1);
   }();
   return w;
 }
@@ -431,14 +460,23 @@ int w4_waves() {
 template <typename T>
 void launch_wilson4d(const WilsonArgs<T>& a, int dagger, int epi, hipStream_t st) {
   const long V = (long)a.L1 * a.L2 * a.L3 * a.L4;
-  const int tt = w4_tt<T>();
   const bool red = (epi == EPI_MRDOT || epi == EPI_NORM);
+  // reducing epilogues run the one-site-per-thread kernel: the x_4-marching
+  // one measured about 1.5x slower with a reduction (600 vs 390 us, FP32)
+  static const int tt_red = [] {
+    const char* e = std::getenv("AMG_W4_TT_RED");
+    return e ? std::atoi(e) : 0;
+  }();
+  const int tt = (red && tt_red >= 0) ? tt_red : w4_tt<T>();
+  const bool nt = V >= (1L << 20);
   if (tt == 4 || tt == 8 || tt == 16) {
     const long V3 = (long)a.L1 * a.L2 * a.L3;
     long nb = (V3 * ((a.L4 + tt - 1) / tt) + 255) / 256;
     if (red) nb = nb < red_block_cap() ? nb : red_block_cap();
     dim3 grid((unsigned)nb, (unsigned)a.nrhs);
-#define AMG_W4T(TT, DAG, EPI) dispatch(wilson4d_tm_kernel<T, DAG, EPI, TT>, a, grid, dim3(256), st)
+#define AMG_W4T(TT, DAG, EPI)                                                                    \
+  if (nt) { dispatch(wilson4d_tm_kernel<T, DAG, EPI, TT, true>, a, grid, dim3(256), st); }      \
+  else { dispatch(wilson4d_tm_kernel<T, DAG, EPI, TT, false>, a, grid, dim3(256), st); }
 #define AMG_W4T_E(TT, DAG)                                   \
     switch (epi) {                                          \
       case EPI_PLAIN: AMG_W4T(TT, DAG, EPI_PLAIN); break;   \
@@ -456,9 +494,11 @@ void launch_wilson4d(const WilsonArgs<T>& a, int dagger, int epi, hipStream_t st
   long nb = (V + 255) / 256;
   if (red) nb = nb < red_block_cap() ? nb : red_block_cap();
   dim3 grid((unsigned)nb, (unsigned)a.nrhs);
-#define AMG_W4N(DAG, EPI, W) dispatch(wilson4d_kernel<T, DAG, EPI, W>, a, grid, dim3(256), st)
+#define AMG_W4N(DAG, EPI, W)                                                                     \
+  if (nt) { dispatch(wilson4d_kernel<T, DAG, EPI, W, true>, a, grid, dim3(256), st); }          \
+  else { dispatch(wilson4d_kernel<T, DAG, EPI, W, false>, a, grid, dim3(256), st); }
 #define AMG_W4(DAG, EPI) if (w2) { AMG_W4N(DAG, EPI, 2); } else { AMG_W4N(DAG, EPI, 1); }
-  const bool w2 = w4_waves() == 2;
+  const bool w2 = w4_waves<T>() == 2;
   if (dagger) {
     switch (epi) {
       case EPI_PLAIN: AMG_W4(1, EPI_PLAIN); break;

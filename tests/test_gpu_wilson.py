@@ -102,3 +102,22 @@ def test_wilson2d_streaming_store_size(prec):
             assert max_rel_err(out, ref) < 1e-12
         else:
             assert rel_err(out, ref) < 1e-5
+
+
+def test_wilson4d_streaming_store_size():
+    """A 4d lattice of 2^20 sites takes the kernels' streaming-store path (FP64 and FP32)."""
+    import paper_0707_4018_amd as amg
+    import torch
+    base = (8, 8, 8, 8)
+    tile = (2, 2, 2, 32)
+    dims = tuple(b * t for b, t in zip(base, tile))
+    print(f"wilson4d {dims} (streaming stores)", flush=True)
+    U = np.tile(su3_config(base, seed=3), (1,) + tuple(reversed(tile)) + (1, 1))
+    V = int(np.prod(dims))
+    m = 0.05
+    g = amg.Gauge(dev(U), m)
+    psi = synth.gaussian_field((1, V, 4, 3), synth.rng_for(5, *dims))
+    lat = tuple(reversed(dims))
+    ref = dirac.apply_D(U, psi[0].reshape(lat + (4, 3)), m).reshape(1, V, 4, 3)
+    assert max_rel_err(host(g.apply(dev(psi))), ref) < 1e-12
+    assert rel_err(host(g.apply(dev(psi, torch.complex64), prec=amg.F32)), ref) < 1e-5
