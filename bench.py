@@ -39,6 +39,9 @@ BETAS = [3.0, 6.0, 10.0]
 BETAS_ALL = list(BETAS)
 TOL = 1e-10
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per launch of the roofline kernel from rocprofv3 counters (FETCH_SIZE x 2,
+# calibrated on a 256 MiB device copy, + WRITE_SIZE), taken on the current kernel
+ROOF_TRAFFIC = 43522560   # 42502.5 KiB: FETCH 20930.4 KiB x 2 + WRITE 641.7 KiB
 WORKLOADS = json.load(open(os.path.join(ROOT, "synth", "workloads.json")))
 
 
@@ -651,17 +654,19 @@ def main():
         "solves": recs,
     }
 
-    # dominant kernel (coarsest-level block stencil, 32^2 sites x 16 dof, FP32):
-    # every launch in one more full step bracketed by HIP events on the stream
+    # roofline kernel: the level-1 block stencil with the MR epilogue (64^2 sites x 16 dof,
+    # FP32), the longest-running apply of the solve (the shorter GCR kernels of the
+    # coarsest level are latency-bound); every launch in one more full step is bracketed
+    # by HIP events on the solver's stream
     log("kernel timing pass")
-    _, _, _, prof = job.step(mixed=True, profile=(amg.Solver.PROF_COARSE, 2))
-    Vc2 = (L // 8) ** 2
-    bytes_launch = Vc2 * (5 * 16 * 16 * 8) + 3 * Vc2 * 16 * 8   # Y + in, out, copy/rhs vector
+    _, _, _, prof = job.step(mixed=True, profile=(amg.Solver.PROF_COARSE_MR, 1))
+    Vc1 = (L // 4) ** 2
+    bytes_launch = Vc1 * (5 * 16 * 16 * 8) + 2 * Vc1 * 16 * 8   # Y once + in + out
     avg_s = prof[0] / max(prof[1], 1) * 1e-3
     achieved = bytes_launch / avg_s / 1e9
     out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                       "kernel": "coarse16_kernel<float> (level-2 block stencil, 1024 sites x 16 dof)",
+                       "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": ROOF_TRAFFIC,
+                       "kernel": "coarse16_kernel<float, MR epilogue> (level-1 block stencil, 4096 sites x 16 dof)",
                        "bytes_per_launch": bytes_launch, "avg_launch_us": round(avg_s * 1e6, 3),
                        "launches": prof[1]}
 

@@ -223,7 +223,8 @@ amg_status amg_batch_destroy(amg_batch* b);
  * solver is bracketed by a pair of HIP events on its stream.  amg_profile_read
  * synchronises on the last event and returns the summed kernel time and the
  * number of launches since enabling.  kind: 0 fine Wilson stencil, 1 coarse
- * block stencil, 2 restriction, 3 prolongation (level = the fine side). */
+ * block stencil, 2 restriction, 3 prolongation (level = the fine side),
+ * 4 coarse block stencil with the MR epilogue only. */
 amg_status amg_profile_enable(amg_solver* s, int kind, int level, int enable);
 amg_status amg_profile_read(amg_solver* s, double* total_ms, long long* launches);
 

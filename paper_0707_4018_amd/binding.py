@@ -416,7 +416,7 @@ class Solver:
                                                   _stream()), "amg_mg_convergence")
         return rho.value
 
-    PROF_FINE, PROF_COARSE, PROF_RESTRICT, PROF_PROLONG = 0, 1, 2, 3
+    PROF_FINE, PROF_COARSE, PROF_RESTRICT, PROF_PROLONG, PROF_COARSE_MR = 0, 1, 2, 3, 4
 
     def profile(self, kind: int, level: int, enable: bool = True):
         """Time every launch of kernel `kind` on `level` with HIP events."""

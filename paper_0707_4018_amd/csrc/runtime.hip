@@ -247,7 +247,7 @@ namespace {
 
 using Solver = amg_solver;
 
-enum { PK_FINE = 0, PK_COARSE = 1, PK_RESTRICT = 2, PK_PROLONG = 3 };
+enum { PK_FINE = 0, PK_COARSE = 1, PK_RESTRICT = 2, PK_PROLONG = 3, PK_COARSE_MR = 4 };
 
 // event pair around one launch when the profiler watches (kind, level)
 struct ProfScope {
@@ -309,7 +309,7 @@ template <typename T>
 void op_apply(Solver& S, int l, int dagger, int epi, const cplx<T>* in, cplx<T>* out, const cplx<T>* b,
               cplx<T>* copy_out, int nrhs, RedArgs red, hipStream_t st) {
   Level& L = S.lv[l];
-  ProfScope ps(S, L.fine ? PK_FINE : PK_COARSE, l, st);
+  ProfScope ps(S, L.fine ? PK_FINE : (epi == EPI_MRDOT && S.prof.kind == PK_COARSE_MR ? PK_COARSE_MR : PK_COARSE), l, st);
   if (L.fine) {
     wilson_apply<T>(*S.g, S.mass, dagger, epi, in, out, b, copy_out, nrhs, red, st);
     (dagger ? S.nDd : S.nD) += 1;
@@ -1631,7 +1631,7 @@ amg_status amg_mr(amg_solver* S, int level, int nu, const void* dev_b, void* dev
 amg_status amg_profile_enable(amg_solver* S, int kind, int level, int enable) {
   AMG_TRY
   check_ptr(S, "solver");
-  if (kind < 0 || kind > 3 || level < 0 || level >= (int)S->lv.size()) fail(AMG_ERR_ARG, "bad kind / level");
+  if (kind < 0 || kind > 4 || level < 0 || level >= (int)S->lv.size()) fail(AMG_ERR_ARG, "bad kind / level");
   S->prof.on = enable != 0;
   S->prof.kind = kind;
   S->prof.level = level;
