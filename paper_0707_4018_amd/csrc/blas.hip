@@ -52,13 +52,15 @@ struct CvArgs {
 template <typename Tin, typename Tout>
 __global__ void convert_kernel(CvArgs<Tin, Tout> a0, const CvArgs<Tin, Tout>* batch) {
   AMG_ARGS(CvArgs<Tin, Tout>)
+  const auto pin = gl(a.in);
+  const auto pout = gl(a.out);
   const long n = a.li.per_rhs();
   const long ro = (long)blockIdx.y * n;
   GRID_STRIDE(i, n) {
     const int c = (int)(i / a.li.V);
     const long s = i - (long)c * a.li.V;
-    const cplx<Tin> z = a.in[ro + a.li.off(s, c)];
-    a.out[ro + a.lo.off(s, c)] = mk<Tout>((Tout)z.x, (Tout)z.y);
+    const cplx<Tin> z = pin[ro + a.li.off(s, c)];
+    pout[ro + a.lo.off(s, c)] = mk<Tout>((Tout)z.x, (Tout)z.y);
   }
 }
 
@@ -73,8 +75,14 @@ struct FillArgs {
 template <typename T>
 __global__ void fill_kernel(FillArgs<T> a0, const FillArgs<T>* batch) {
   AMG_ARGS(FillArgs<T>)
+  const auto dst = gl(a.dst);
+  const auto src = gl(a.src);
   const long ro = (long)blockIdx.y * a.n;
-  GRID_STRIDE(i, a.n) a.dst[ro + i] = a.src ? a.src[ro + i] : mk<T>(0, 0);
+  GRID_STRIDE(i, a.n) {
+    cplx<T> v = mk<T>(0, 0);
+    if (a.src) v = src[ro + i];
+    dst[ro + i] = v;
+  }
 }
 
 __global__ void p_to_f32_kernel(float2* __restrict__ out, const double2* __restrict__ in, long n) {
@@ -107,16 +115,16 @@ __global__ void mr_update_kernel(MrArgs<T> a0, const MrArgs<T>* batch) {
   AMG_ARGS(MrArgs<T>)
   const int rhs = blockIdx.y;
   if (skip_rhs(a.flags, rhs)) return;
-  const cplx<T> al = mk<T>((T)a.alpha[2 * rhs], (T)a.alpha[2 * rhs + 1]);
+  const cplx<T> al = mk<T>((T)gl(a.alpha)[2 * rhs], (T)gl(a.alpha)[2 * rhs + 1]);
   const long ro = (long)rhs * a.n;
   if (sizeof(T) == 4 && (a.n & 1) == 0) {
     // FP32: two complex numbers per 16-byte access
     using V4 = float4;
     const long n2 = a.n / 2, ro2 = ro / 2;
-    const V4* __restrict__ rin = reinterpret_cast<const V4*>(a.r_in) + ro2;
-    const V4* __restrict__ pp = reinterpret_cast<const V4*>(a.p) + ro2;
-    V4* __restrict__ xx = reinterpret_cast<V4*>(a.x) + ro2;
-    V4* __restrict__ rout = reinterpret_cast<V4*>(a.r_out) + ro2;
+    gptr<const V4> __restrict__ rin = (gptr<const V4>)a.r_in + ro2;
+    gptr<const V4> __restrict__ pp = (gptr<const V4>)a.p + ro2;
+    gptr<V4> __restrict__ xx = (gptr<V4>)a.x + ro2;
+    gptr<V4> __restrict__ rout = (gptr<V4>)a.r_out + ro2;
     const float ar = (float)al.x, ai = (float)al.y;
     GRID_STRIDE(i, n2) {
       const V4 r = rin[i];
@@ -132,11 +140,14 @@ __global__ void mr_update_kernel(MrArgs<T> a0, const MrArgs<T>* batch) {
     }
     return;
   }
+  const auto r_in = gl(a.r_in);
+  const auto x = gl(a.x), r_out = gl(a.r_out);
+  const auto p = gl(a.p);
   GRID_STRIDE(i, a.n) {
-    const cplx<T> r = a.r_in[ro + i];
+    const cplx<T> r = r_in[ro + i];
     const cplx<T> ar = cmul<T>(al, r);
-    a.x[ro + i] = a.first ? ar : cadd<T>(a.x[ro + i], ar);
-    if (a.update_r) a.r_out[ro + i] = csub<T>(r, cmul<T>(al, a.p[ro + i]));
+    x[ro + i] = a.first ? ar : cadd<T>(x[ro + i], ar);
+    if (a.update_r) r_out[ro + i] = csub<T>(r, cmul<T>(al, p[ro + i]));
   }
 }
 
@@ -150,13 +161,15 @@ struct NormArgs {
 template <typename T>
 __global__ __launch_bounds__(256) void norm2_kernel(NormArgs<T> a0, const NormArgs<T>* batch) {
   AMG_ARGS(NormArgs<T>)
+  const auto v = gl(a.v);
+  const auto scal = gl(a.red.scal);
   const int rhs = blockIdx.y;
   if (skip_rhs(a.red.flags, rhs)) return;
   const long ro = (long)rhs * a.n;
   double acc[1] = {0.0};
-  GRID_STRIDE(i, a.n) { const cplx<T> z = a.v[ro + i]; acc[0] += (double)z.x * z.x + (double)z.y * z.y; }
+  GRID_STRIDE(i, a.n) { const cplx<T> z = v[ro + i]; acc[0] += (double)z.x * z.x + (double)z.y * z.y; }
   double tot[1];
-  if (grid_reduce<1>(acc, a.red.part, a.red.ticket, rhs, tot) && threadIdx.x == 0) a.red.scal[a.red.slot + rhs] = tot[0];
+  if (grid_reduce<1>(acc, a.red.part, a.red.ticket, rhs, tot) && threadIdx.x == 0) scal[a.red.slot + rhs] = tot[0];
 }
 
 // arguments shared by the GCR step kernels; directions W_j = Wb + j * dstride
@@ -182,6 +195,8 @@ struct GcrArgs {
 template <typename T, int KM>
 __global__ __launch_bounds__(256) void gcr_mdot_kernel(GcrArgs<T> a0, const GcrArgs<T>* batch) {
   AMG_ARGS(GcrArgs<T>)
+  const auto w = gl(a.w), Wb = gl(a.Wb);
+  const auto scal = gl(a.red.scal);
   const int rhs = blockIdx.y;
   if (skip_rhs(a.red.flags, rhs)) return;
   const long ro = (long)rhs * a.n;
@@ -190,12 +205,12 @@ __global__ __launch_bounds__(256) void gcr_mdot_kernel(GcrArgs<T> a0, const GcrA
 #pragma unroll
   for (int j = 0; j < 2 * KM; ++j) acc[j] = 0.0;
   GRID_STRIDE(i, a.n) {
-    const cplx<T> wi = a.w[ro + i];
+    const cplx<T> wi = w[ro + i];
     // every load is issued (clamped to a stored direction), the surplus ones
     // are masked: no branch between the loads, so they are all in flight
     cplx<T> q[KM];
 #pragma unroll
-    for (int j = 0; j < KM; ++j) q[j] = a.Wb[(long)(j < k ? j : k - 1) * a.dstride + ro + i];
+    for (int j = 0; j < KM; ++j) q[j] = Wb[(long)(j < k ? j : k - 1) * a.dstride + ro + i];
 #pragma unroll
     for (int j = 0; j < KM; ++j) {
       const double m = j < k ? 1.0 : 0.0;
@@ -206,10 +221,10 @@ __global__ __launch_bounds__(256) void gcr_mdot_kernel(GcrArgs<T> a0, const GcrA
   double tot[2 * KM];
   if (grid_reduce<2 * KM>(acc, a.red.part, a.red.ticket, rhs, tot) && threadIdx.x == 0) {
     for (int j = 0; j < k; ++j) {
-      const double ww = a.red.scal[a.ww_slot + rhs * GCR_KMAX + j];
+      const double ww = scal[a.ww_slot + rhs * GCR_KMAX + j];
       const double s = ww > 0.0 ? 1.0 / ww : 0.0;
-      a.red.scal[a.beta_slot + (rhs * GCR_KMAX + j) * 2] = tot[2 * j] * s;
-      a.red.scal[a.beta_slot + (rhs * GCR_KMAX + j) * 2 + 1] = tot[2 * j + 1] * s;
+      scal[a.beta_slot + (rhs * GCR_KMAX + j) * 2] = tot[2 * j] * s;
+      scal[a.beta_slot + (rhs * GCR_KMAX + j) * 2 + 1] = tot[2 * j + 1] * s;
     }
   }
 }
@@ -218,26 +233,29 @@ __global__ __launch_bounds__(256) void gcr_mdot_kernel(GcrArgs<T> a0, const GcrA
 template <typename T, int KM>
 __global__ __launch_bounds__(256) void gcr_maxpy_kernel(GcrArgs<T> a0, const GcrArgs<T>* batch) {
   AMG_ARGS(GcrArgs<T>)
+  const auto w = gl(a.w), z = gl(a.z), Wb = gl(a.Wb), Zb = gl(a.Zb);
+  const auto r = gl(a.r);
+  const auto scal = gl(a.red.scal);
   const int rhs = blockIdx.y;
   if (skip_rhs(a.red.flags, rhs)) return;
   const long ro = (long)rhs * a.n;
   const int k = a.k;
-  const double* beta = a.red.scal + a.beta_slot + (long)rhs * GCR_KMAX * 2;
+  const auto beta = scal + a.beta_slot + (long)rhs * GCR_KMAX * 2;
   cplx<T> b[KM];
 #pragma unroll
   for (int j = 0; j < KM; ++j)
     b[j] = j < k ? mk<T>((T)beta[2 * j], (T)beta[2 * j + 1]) : mk<T>(0, 0);
   double acc[3] = {0.0, 0.0, 0.0};
   GRID_STRIDE(i, a.n) {
-    cplx<T> wi = a.w[ro + i];
-    cplx<T> zi = a.z[ro + i];
+    cplx<T> wi = w[ro + i];
+    cplx<T> zi = z[ro + i];
     if (k > 0) {
       cplx<T> wq[KM], zq[KM];
 #pragma unroll
       for (int j = 0; j < KM; ++j) {
         const long off = (long)(j < k ? j : k - 1) * a.dstride + ro + i;
-        wq[j] = a.Wb[off];
-        zq[j] = a.Zb[off];
+        wq[j] = Wb[off];
+        zq[j] = Zb[off];
       }
 #pragma unroll
       for (int j = 0; j < KM; ++j) {
@@ -245,8 +263,8 @@ __global__ __launch_bounds__(256) void gcr_maxpy_kernel(GcrArgs<T> a0, const Gcr
         zi = csub<T>(zi, cmul<T>(b[j], zq[j]));
       }
     }
-    if (k > 0) { a.w[ro + i] = wi; a.z[ro + i] = zi; }
-    const cplx<T> ri = a.r[ro + i];
+    if (k > 0) { w[ro + i] = wi; z[ro + i] = zi; }
+    const cplx<T> ri = r[ro + i];
     acc[0] += (double)wi.x * wi.x + (double)wi.y * wi.y;
     acc[1] += (double)wi.x * ri.x + (double)wi.y * ri.y;
     acc[2] += (double)wi.x * ri.y - (double)wi.y * ri.x;
@@ -254,10 +272,10 @@ __global__ __launch_bounds__(256) void gcr_maxpy_kernel(GcrArgs<T> a0, const Gcr
   double tot[3];
   if (grid_reduce<3>(acc, a.red.part, a.red.ticket, rhs, tot) && threadIdx.x == 0) {
     const double ww = tot[0];
-    a.red.scal[a.ww_slot + rhs * GCR_KMAX + k] = ww;
+    scal[a.ww_slot + rhs * GCR_KMAX + k] = ww;
     const double s = ww > 0.0 ? 1.0 / ww : 0.0;
-    a.red.scal[a.alpha_slot + 2 * rhs] = tot[1] * s;
-    a.red.scal[a.alpha_slot + 2 * rhs + 1] = tot[2] * s;
+    scal[a.alpha_slot + 2 * rhs] = tot[1] * s;
+    scal[a.alpha_slot + 2 * rhs + 1] = tot[2] * s;
   }
 }
 
@@ -265,21 +283,23 @@ __global__ __launch_bounds__(256) void gcr_maxpy_kernel(GcrArgs<T> a0, const Gcr
 template <typename T>
 __global__ __launch_bounds__(256) void gcr_update_kernel(GcrArgs<T> a0, const GcrArgs<T>* batch) {
   AMG_ARGS(GcrArgs<T>)
+  const auto x = gl(a.x), z = gl(a.z), r = gl(a.r), w = gl(a.w);
+  const auto scal = gl(a.red.scal);
   const int rhs = blockIdx.y;
   if (skip_rhs(a.red.flags, rhs)) return;
   const long ro = (long)rhs * a.n;
-  const cplx<T> al = mk<T>((T)a.red.scal[a.alpha_slot + 2 * rhs], (T)a.red.scal[a.alpha_slot + 2 * rhs + 1]);
+  const cplx<T> al = mk<T>((T)scal[a.alpha_slot + 2 * rhs], (T)scal[a.alpha_slot + 2 * rhs + 1]);
   double acc[1] = {0.0};
   GRID_STRIDE(i, a.n) {
-    a.x[ro + i] = cadd<T>(a.x[ro + i], cmul<T>(al, a.z[ro + i]));
-    const cplx<T> ri = csub<T>(a.r[ro + i], cmul<T>(al, a.w[ro + i]));
-    a.r[ro + i] = ri;
+    x[ro + i] = cadd<T>(x[ro + i], cmul<T>(al, z[ro + i]));
+    const cplx<T> ri = csub<T>(r[ro + i], cmul<T>(al, w[ro + i]));
+    r[ro + i] = ri;
     acc[0] += (double)ri.x * ri.x + (double)ri.y * ri.y;
   }
   double tot[1];
   if (grid_reduce<1>(acc, a.red.part, a.red.ticket, rhs, tot) && threadIdx.x == 0) {
-    a.red.scal[a.rr_slot + rhs] = tot[0];
-    if (a.set_flags) a.set_flags[rhs] = (tot[0] <= a.tol2 * a.red.scal[a.bb_slot + rhs]) ? 1 : 0;
+    scal[a.rr_slot + rhs] = tot[0];
+    if (a.set_flags) gl(a.set_flags)[rhs] = (tot[0] <= a.tol2 * scal[a.bb_slot + rhs]) ? 1 : 0;
   }
 }
 
@@ -289,33 +309,36 @@ __global__ __launch_bounds__(256) void gcr_update_kernel(GcrArgs<T> a0, const Gc
 template <typename T>
 __global__ __launch_bounds__(256) void gcr_update2_kernel(GcrArgs<T> a0, const GcrArgs<T>* batch) {
   AMG_ARGS(GcrArgs<T>)
+  const auto x = gl(a.x), r = gl(a.r), Wb = gl(a.Wb), Zb = gl(a.Zb);
+  const auto zsrc = gl(a.zsrc);
+  const auto scal = gl(a.red.scal);
   const int rhs = blockIdx.y;
   if (skip_rhs(a.red.flags, rhs)) return;
   const long ro = (long)rhs * a.n;
   const int k = a.k;
-  const double* beta = a.red.scal + a.beta_slot + (long)rhs * GCR_KMAX * 2;
-  const cplx<T> al = mk<T>((T)a.red.scal[a.alpha_slot + 2 * rhs], (T)a.red.scal[a.alpha_slot + 2 * rhs + 1]);
-  cplx<T>* Wk = a.Wb + (long)k * a.dstride + ro;
-  cplx<T>* Zk = a.Zb + (long)k * a.dstride + ro;
+  const auto beta = scal + a.beta_slot + (long)rhs * GCR_KMAX * 2;
+  const cplx<T> al = mk<T>((T)scal[a.alpha_slot + 2 * rhs], (T)scal[a.alpha_slot + 2 * rhs + 1]);
+  const auto Wk = Wb + (long)k * a.dstride + ro;
+  const auto Zk = Zb + (long)k * a.dstride + ro;
   double acc[1] = {0.0};
   GRID_STRIDE(i, a.n) {
-    cplx<T> wi = Wk[i], zi = a.zsrc[ro + i];
+    cplx<T> wi = Wk[i], zi = zsrc[ro + i];
     for (int j = 0; j < k; ++j) {
       const cplx<T> b = mk<T>((T)beta[2 * j], (T)beta[2 * j + 1]);
-      wi = csub<T>(wi, cmul<T>(b, a.Wb[(long)j * a.dstride + ro + i]));
-      zi = csub<T>(zi, cmul<T>(b, a.Zb[(long)j * a.dstride + ro + i]));
+      wi = csub<T>(wi, cmul<T>(b, Wb[(long)j * a.dstride + ro + i]));
+      zi = csub<T>(zi, cmul<T>(b, Zb[(long)j * a.dstride + ro + i]));
     }
     Wk[i] = wi;
     Zk[i] = zi;
-    a.x[ro + i] = cadd<T>(a.x[ro + i], cmul<T>(al, zi));
-    const cplx<T> ri = csub<T>(a.r[ro + i], cmul<T>(al, wi));
-    a.r[ro + i] = ri;
+    x[ro + i] = cadd<T>(x[ro + i], cmul<T>(al, zi));
+    const cplx<T> ri = csub<T>(r[ro + i], cmul<T>(al, wi));
+    r[ro + i] = ri;
     acc[0] += (double)ri.x * ri.x + (double)ri.y * ri.y;
   }
   double tot[1];
   if (grid_reduce<1>(acc, a.red.part, a.red.ticket, rhs, tot) && threadIdx.x == 0) {
-    a.red.scal[a.rr_slot + rhs] = tot[0];
-    if (a.set_flags) a.set_flags[rhs] = (tot[0] <= a.tol2 * a.red.scal[a.bb_slot + rhs]) ? 1 : 0;
+    scal[a.rr_slot + rhs] = tot[0];
+    if (a.set_flags) gl(a.set_flags)[rhs] = (tot[0] <= a.tol2 * scal[a.bb_slot + rhs]) ? 1 : 0;
   }
 }
 
@@ -329,7 +352,7 @@ struct FlagArgs {
   int nrhs;
 };
 __global__ void set_flags_kernel(FlagArgs a0, const FlagArgs* batch) {
-  const FlagArgs& a = (batch != nullptr) ? batch[blockIdx.z] : a0;
+  AMG_PICK(a, FlagArgs)
   const int rhs = threadIdx.x;
   if (rhs < a.nrhs)
     a.flags[rhs] = ((a.inherit && a.inherit[rhs]) || a.scal[a.rr_slot + rhs] <= a.tol2 * a.scal[a.bb_slot + rhs]) ? 1 : 0;
@@ -343,7 +366,7 @@ struct GatherArgs {
   int nrhs;
 };
 __global__ void gather_kernel(GatherArgs a0, const GatherArgs* batch) {
-  const GatherArgs& a = (batch != nullptr) ? batch[blockIdx.z] : a0;
+  AMG_PICK(a, GatherArgs)
   const int rhs = threadIdx.x;
   if (rhs < a.nrhs) a.out[rhs] = a.scal[a.slot + rhs];
 }

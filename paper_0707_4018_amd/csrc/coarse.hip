@@ -16,19 +16,26 @@
 namespace amg {
 namespace {
 
-__device__ __forceinline__ void coords(long site, const int* dims, int nd, int* x) {
+__device__ __forceinline__ void coords(long site, const int (&dims)[4], int nd, int (&x)[4]) {
   long rem = site;
-  for (int mu = 0; mu < nd; ++mu) { x[mu] = (int)(rem % dims[mu]); rem /= dims[mu]; }
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+    x[mu] = 0;
+    if (mu < nd) { x[mu] = (int)(rem % dims[mu]); rem /= dims[mu]; }
+  }
 }
 
-__device__ __forceinline__ long neighbour(long site, const int* x, const int* dims, int nd, int dir) {
+__device__ __forceinline__ long neighbour(long site, const int (&x)[4], const int (&dims)[4], int nd, int dir) {
   // dir = 2 mu (+mu) or 2 mu + 1 (-mu)
   const int mu = dir >> 1;
   long stride = 1;
-  for (int nu = 0; nu < mu; ++nu) stride *= dims[nu];
-  const int L = dims[mu];
-  if ((dir & 1) == 0) return (x[mu] == L - 1) ? site - (long)(L - 1) * stride : site + stride;
-  return (x[mu] == 0) ? site + (long)(L - 1) * stride : site - stride;
+#pragma unroll
+  for (int nu = 0; nu < 3; ++nu)
+    if (nu < mu) stride *= dims[nu];
+  const int L = at4(dims, mu);
+  const int xm = at4(x, mu);
+  if ((dir & 1) == 0) return (xm == L - 1) ? site - (long)(L - 1) * stride : site + stride;
+  return (xm == 0) ? site + (long)(L - 1) * stride : site - stride;
 }
 
 template <typename T, int NC, int DAG, int EPI>
@@ -111,7 +118,7 @@ template <typename T> struct C16 {
 // site instead of five: the 2d coarse levels are small and latency-bound).
 // ND = 0: any dimension, one direction at a time.
 template <typename T, int DAG, int ND>
-__device__ __forceinline__ void site_apply16(const cplx<T>* __restrict__ Y, const cplx<T>* __restrict__ pin, long site,
+__device__ __forceinline__ void site_apply16(gptr<const cplx<T>> __restrict__ Y, gptr<const cplx<T>> __restrict__ pin, long site,
                                              const CoarseGeom& g, int cg, int rg, cplx<T> (&acc)[C16<T>::R]) {
   using K = C16<T>;
 #pragma unroll
@@ -126,7 +133,7 @@ __device__ __forceinline__ void site_apply16(const cplx<T>* __restrict__ Y, cons
     nbs[2] = (x1 == 0) ? site + (L1 - 1) : site - 1;
     nbs[3] = (x2 == L2 - 1) ? site - (long)(L2 - 1) * L1 : site + L1;
     nbs[4] = (x2 == 0) ? site + (long)(L2 - 1) * L1 : site - L1;
-    const cplx<T>* __restrict__ Ys = Y + site * (long)NDIR * K::NC * K::NC + rg * K::R;
+    gptr<const cplx<T>> __restrict__ Ys = Y + site * (long)NDIR * K::NC * K::NC + rg * K::R;
     cplx<T> ev[NDIR][K::NQ], yv[NDIR][K::NQ][K::R];
 #pragma unroll
     for (int k = 0; k < NDIR; ++k)
@@ -151,11 +158,11 @@ __device__ __forceinline__ void site_apply16(const cplx<T>* __restrict__ Y, cons
     int x[4];
     coords(site, g.dims, g.nd, x);
     const int ndir = 2 * g.nd + 1;
-    const cplx<T>* __restrict__ Ys = Y + site * (long)ndir * K::NC * K::NC;
+    gptr<const cplx<T>> __restrict__ Ys = Y + site * (long)ndir * K::NC * K::NC;
     for (int k = 0; k < ndir; ++k) {
       const long nb = (k == 0) ? site : neighbour(site, x, g.dims, g.nd, k - 1);
-      const cplx<T>* __restrict__ e = pin + nb * K::NC;
-      const cplx<T>* __restrict__ yk = Ys + (long)k * K::NC * K::NC + rg * K::R;
+      gptr<const cplx<T>> __restrict__ e = pin + nb * K::NC;
+      gptr<const cplx<T>> __restrict__ yk = Ys + (long)k * K::NC * K::NC + rg * K::R;
       cplx<T> ev[K::NQ], yv[K::NQ][K::R];
 #pragma unroll
       for (int q = 0; q < K::NQ; ++q) {
@@ -192,28 +199,40 @@ __global__ __launch_bounds__(256) void coarse16_kernel(CoarseArgs<T> a0, const C
   if (skip_rhs(a.red.flags, rhs)) return;
   const long V = a.g.V;
   const long ro = (long)rhs * V * K::NC;
-  const cplx<T>* __restrict__ pin = a.in + ro;
+  gptr<const cplx<T>> __restrict__ pin = gl(a.in) + ro;
+  gptr<const cplx<T>> __restrict__ pb = gl(a.b) + ro;
+  gptr<cplx<T>> __restrict__ pout = gl(a.out) + ro;
+  gptr<cplx<T>> __restrict__ pcopy = gl(a.copy_out) + ro;
+  const bool copy = a.copy_out != nullptr;
   const int lane = threadIdx.x & 63;
   const int cg = lane / K::LPC, rg = lane - cg * K::LPC;
   const int wave = threadIdx.x >> 6;
   double acc3[3] = {0.0, 0.0, 0.0};
   for (long site = (long)blockIdx.x * 4 + wave; site < V; site += (long)gridDim.x * 4) {
+    // this lane's rows of the input (MR sums, copy) and of b, loaded with the stencil's operands
+    const long o = site * K::NC + rg * K::R;
+    cplx<T> c[K::R], bv[K::R];
+#pragma unroll
+    for (int i = 0; i < K::R; ++i) {
+      c[i] = mk<T>(0, 0);
+      bv[i] = mk<T>(0, 0);
+      if (cg == 0 && (EPI == EPI_MRDOT || copy)) c[i] = pin[o + i];
+      if (cg == 0 && EPI == EPI_RESID) bv[i] = pb[o + i];
+    }
     cplx<T> acc[K::R];
-    site_apply16<T, DAG, ND>(a.Y, pin, site, a.g, cg, rg, acc);
+    site_apply16<T, DAG, ND>(gl(a.Y), pin, site, a.g, cg, rg, acc);
     if (cg == 0) {
 #pragma unroll
       for (int i = 0; i < K::R; ++i) {
         const int row = rg * K::R + i;
         cplx<T> v = acc[i];
         if (DAG && row >= K::NC / 2) v = mk<T>(-v.x, -v.y);
-        const long idx = ro + site * K::NC + row;
-        const cplx<T> c = a.in[idx];
-        if (EPI == EPI_RESID) v = csub<T>(a.b[idx], v);
-        a.out[idx] = v;
-        if (a.copy_out) a.copy_out[idx] = c;
+        if (EPI == EPI_RESID) v = csub<T>(bv[i], v);
+        pout[o + i] = v;
+        if (copy) pcopy[o + i] = c[i];
         if (EPI == EPI_MRDOT) {
-          acc3[0] += (double)v.x * c.x + (double)v.y * c.y;
-          acc3[1] += (double)v.x * c.y - (double)v.y * c.x;
+          acc3[0] += (double)v.x * c[i].x + (double)v.y * c[i].y;
+          acc3[1] += (double)v.x * c[i].y - (double)v.y * c[i].x;
           acc3[2] += (double)v.x * v.x + (double)v.y * v.y;
         } else if (EPI == EPI_NORM) {
           acc3[0] += (double)v.x * v.x + (double)v.y * v.y;
@@ -249,7 +268,7 @@ struct G16Args {
 };
 template <typename T>
 __global__ __launch_bounds__(256) void gcr16_apply_dots_kernel(G16Args<T> a0, const G16Args<T>* batch) {
-  const G16Args<T>& ga = (batch != nullptr) ? batch[blockIdx.z] : a0;
+  AMG_PICK(ga, G16Args<T>)
   if ((int)blockIdx.y >= ga.nrhs) return;
   const CoarseArgs<T>& a = ga.c;
   const cplx<T>* __restrict__ r = ga.r;
@@ -272,8 +291,8 @@ __global__ __launch_bounds__(256) void gcr16_apply_dots_kernel(G16Args<T> a0, co
   double* mine = sh + (wave * K::LPC + rg) * G16_NQ;  // this lane's accumulators (cg == 0 lanes)
   for (long site = (long)blockIdx.x * 4 + wave; site < V; site += (long)gridDim.x * 4) {
     cplx<T> acc[K::R];
-    if (a.g.nd == 2) site_apply16<T, 0, 2>(a.Y, a.in + ro, site, a.g, cg, rg, acc);
-    else site_apply16<T, 0, 0>(a.Y, a.in + ro, site, a.g, cg, rg, acc);
+    if (a.g.nd == 2) site_apply16<T, 0, 2>(gl(a.Y), gl(a.in) + ro, site, a.g, cg, rg, acc);
+    else site_apply16<T, 0, 0>(gl(a.Y), gl(a.in) + ro, site, a.g, cg, rg, acc);
     if (cg == 0) {
       double ww = 0.0, wrr = 0.0, wri = 0.0;
 #pragma unroll
@@ -311,18 +330,19 @@ __global__ __launch_bounds__(256) void gcr16_apply_dots_kernel(G16Args<T> a0, co
     if (q < nq || q == G16_NQ - 1) {
       double s = 0.0;
       for (int l = 0; l < 4 * K::LPC; ++l) s += sh[l * G16_NQ + q];
-      a.red.part[((long)rhs * G16_NQ + q) * nblk + blockIdx.x] = s;
+      __hip_atomic_store(&a.red.part[((long)rhs * G16_NQ + q) * nblk + blockIdx.x], s, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
     }
   }
-  __threadfence();
+  // partials published as in grid_reduce: agent-scope atomic stores, complete
+  // before the ticket is taken, read back with agent-scope atomic loads
+  wait_stores_complete();
   __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    is_last = (atomicAdd(&a.red.ticket[rhs], 1u) == (unsigned)(nblk - 1));
-  }
+  if (threadIdx.x == 0)
+    is_last = (__hip_atomic_fetch_add(&a.red.ticket[rhs], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+               (unsigned)(nblk - 1));
   __syncthreads();
   if (!is_last) return;
-  __threadfence();
   // every thread sums a stride of the blocks for each quantity, then the
   // waves are combined: loads stay independent and the order fixed
   __shared__ double wsum[4][G16_NQ];
@@ -386,8 +406,8 @@ __global__ __launch_bounds__(256) void coarse_split_kernel(double2* __restrict__
       bool cross = false;
       if (k > 0) {
         const int mu = (k - 1) >> 1;
-        const int face = ((k - 1) & 1) ? 0 : blk[mu] - 1;
-        cross = (x[mu] % blk[mu]) == face;
+        const int face = ((k - 1) & 1) ? 0 : at4(blk, mu) - 1;
+        cross = (at4(x, mu) % at4(blk, mu)) == face;
       }
       if (cross) {
         out[(long)k * kstride + ro + i] = acc;
@@ -425,11 +445,14 @@ struct BlockIdx {
     int rj = (int)j;
     int rxi = xi;
     int fs = 0, stride = 1;
-    for (int mu = 0; mu < g.nd; ++mu) {
-      const int jc = rj % g.cdims[mu]; rj /= g.cdims[mu];
-      const int bc = rxi % g.blk[mu]; rxi /= g.blk[mu];
-      fs += (jc * g.blk[mu] + bc) * stride;
-      stride *= g.fdims[mu];
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+      if (mu < g.nd) {
+        const int jc = rj % g.cdims[mu]; rj /= g.cdims[mu];
+        const int bc = rxi % g.blk[mu]; rxi /= g.blk[mu];
+        fs += (jc * g.blk[mu] + bc) * stride;
+        stride *= g.fdims[mu];
+      }
     }
     return fs;
   }
@@ -438,12 +461,15 @@ struct BlockIdx {
     int rem = (int)fs, cs = 1, jj = 0;
     int bstride = 1;
     xi = 0;
-    for (int mu = 0; mu < g.nd; ++mu) {
-      const int x = rem % g.fdims[mu]; rem /= g.fdims[mu];
-      jj += (x / g.blk[mu]) * cs;
-      xi += (x % g.blk[mu]) * bstride;
-      cs *= g.cdims[mu];
-      bstride *= g.blk[mu];
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+      if (mu < g.nd) {
+        const int x = rem % g.fdims[mu]; rem /= g.fdims[mu];
+        jj += (x / g.blk[mu]) * cs;
+        xi += (x % g.blk[mu]) * bstride;
+        cs *= g.cdims[mu];
+        bstride *= g.blk[mu];
+      }
     }
     j = jj;
   }
@@ -464,9 +490,9 @@ template <typename T, typename PT>
 __global__ __launch_bounds__(256) void restrict_kernel(TrArgs<T, PT> a0, const TrArgs<T, PT>* batch) {
   AMG_ARGS(TrArgs<T, PT>)
   const TransferGeom& g = a.g;
-  cplx<T>* __restrict__ out = a.out;
-  const cplx<T>* __restrict__ in = a.in;
-  const PT* __restrict__ P = a.P;
+  gptr<cplx<T>> __restrict__ out = gl(a.out);
+  gptr<const cplx<T>> __restrict__ in = gl(a.in);
+  gptr<const PT> __restrict__ P = gl(a.P);
   const int rhs = blockIdx.y;
   if (skip_rhs(a.flags, rhs)) return;
   const int nc = 2 * g.nv, hd = g.dof / 2;
@@ -494,9 +520,9 @@ template <typename T, typename PT>
 __global__ __launch_bounds__(256) void prolong_kernel(TrArgs<T, PT> a0, const TrArgs<T, PT>* batch) {
   AMG_ARGS(TrArgs<T, PT>)
   const TransferGeom& g = a.g;
-  cplx<T>* __restrict__ out = a.out;
-  const cplx<T>* __restrict__ in = a.in;
-  const PT* __restrict__ P = a.P;
+  gptr<cplx<T>> __restrict__ out = gl(a.out);
+  gptr<const cplx<T>> __restrict__ in = gl(a.in);
+  gptr<const PT> __restrict__ P = gl(a.P);
   const int accumulate = a.accumulate;
   const int rhs = blockIdx.y;
   if (skip_rhs(a.flags, rhs)) return;
@@ -513,7 +539,7 @@ __global__ __launch_bounds__(256) void prolong_kernel(TrArgs<T, PT> a0, const Tr
     BlockIdx::coarse_of(g, fs, j, xi);
     const int chi = comp / hd;
     const long pb = ((j * g.bs + xi) * g.dof + comp) * (long)g.nv;
-    const cplx<T>* e = in + roc + j * nc + chi * g.nv;
+    gptr<const cplx<T>> e = in + roc + j * nc + chi * g.nv;
     cplx<T> acc = mk<T>(0, 0);
     for (int k = 0; k < g.nv; ++k) cfma<T>(acc, ldp<T>(P, pb + k), e[k]);
     const long o = rof + g.lf.off(fs, comp);
@@ -572,7 +598,7 @@ __global__ __launch_bounds__(256) void restrict_blk_kernel(TrArgs<T, PT> a0, con
           const int b2 = rem % g.blk[2]; rem /= g.blk[2];
           const long fs = fs0 + b0 + b1 * s1 + b2 * s2 + (long)rem * s3;
           const T w = (e0 + u < nel) ? (T)1 : (T)0;
-          const cplx<T> pp = ldp<T>(a.P, pbase + ((long)xi * g.dof + h) * NV);
+          const cplx<T> pp = ldp<T>(gl(a.P), pbase + ((long)xi * g.dof + h) * NV);
           pv[u] = mk<T>(w * pp.x, w * pp.y);
           fo[u] = g.lf.off(fs, chi * hd + h);
         }
@@ -581,7 +607,7 @@ __global__ __launch_bounds__(256) void restrict_blk_kernel(TrArgs<T, PT> a0, con
           if (r < nr) {
             cplx<T> xv[UN];
 #pragma unroll
-            for (int u = 0; u < UN; ++u) xv[u] = a.in[(long)(r0 + r) * per_f + fo[u]];
+            for (int u = 0; u < UN; ++u) xv[u] = gl(a.in)[(long)(r0 + r) * per_f + fo[u]];
 #pragma unroll
             for (int u = 0; u < UN; ++u) cjfma<T>(acc[r], pv[u], xv[u]);
           }
@@ -592,7 +618,7 @@ __global__ __launch_bounds__(256) void restrict_blk_kernel(TrArgs<T, PT> a0, con
       const int src = (lane + NV) & 63;
       const T ox = __shfl(acc[r].x, src, 64), oy = __shfl(acc[r].y, src, 64);
       if (r < nr && lane < NV && !skip_rhs(a.flags, r0 + r))
-        a.out[(long)(r0 + r) * per_c + j * 2 * NV + chi * NV + k] = mk<T>(acc[r].x + ox, acc[r].y + oy);
+        gl(a.out)[(long)(r0 + r) * per_c + j * 2 * NV + chi * NV + k] = mk<T>(acc[r].x + ox, acc[r].y + oy);
     }
   }
 }
@@ -628,10 +654,10 @@ __global__ __launch_bounds__(256) void prolong_blk_kernel(TrArgs<T, PT> a0, cons
       cplx<T> s0[RG], s1[RG];  // (the pair's two components)
 #pragma unroll
       for (int r = 0; r < RG; ++r) { s0[r] = mk<T>(0, 0); s1[r] = mk<T>(0, 0); }
-      const cplx<T>* __restrict__ e = a.in + (long)r0 * per_c + j * 2 * NV + chi * NV;
+      gptr<const cplx<T>> __restrict__ e = gl(a.in) + (long)r0 * per_c + j * 2 * NV + chi * NV;
 #pragma unroll 4
       for (int k = 0; k < NV; ++k) {
-        const cplx<T> p0 = ldp<T>(a.P, prow + k), p1 = ldp<T>(a.P, prow + NV + k);
+        const cplx<T> p0 = ldp<T>(gl(a.P), prow + k), p1 = ldp<T>(gl(a.P), prow + NV + k);
 #pragma unroll
         for (int r = 0; r < RG; ++r)
           if (r < nr) {
@@ -644,19 +670,13 @@ __global__ __launch_bounds__(256) void prolong_blk_kernel(TrArgs<T, PT> a0, cons
 #pragma unroll
       for (int r = 0; r < RG; ++r)
         if (r < nr && !skip_rhs(a.flags, r0 + r)) {
-          cplx<T>* __restrict__ out = a.out + (long)(r0 + r) * per_f;
+          gptr<cplx<T>> __restrict__ out = gl(a.out) + (long)(r0 + r) * per_f;
           out[o0] = a.accumulate ? cadd<T>(out[o0], s0[r]) : s0[r];
           out[o1] = a.accumulate ? cadd<T>(out[o1], s1[r]) : s1[r];
         }
       }
     }
   }
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
 }
 
 // One wave per (coarse site j, chirality chi): gather the block vectors into

@@ -34,8 +34,10 @@ __device__ __forceinline__ long mr_neighbour(long site, const CoarseGeom& g, int
   // dir = 2 mu (+mu) or 2 mu + 1 (-mu), periodic
   const int mu = dir >> 1;
   long stride = 1;
-  for (int nu = 0; nu < mu; ++nu) stride *= g.dims[nu];
-  const int L = g.dims[mu];
+#pragma unroll
+  for (int nu = 0; nu < 3; ++nu)
+    if (nu < mu) stride *= g.dims[nu];
+  const int L = at4(g.dims, mu);
   const int x = (int)((site / stride) % L);
   if ((dir & 1) == 0) return (x == L - 1) ? site - (long)(L - 1) * stride : site + stride;
   return (x == 0) ? site + (long)(L - 1) * stride : site - stride;
@@ -67,13 +69,13 @@ __global__ __launch_bounds__(NC / 16 * 64) void coarse_mrhs_kernel(CoarseArgs<fl
           const int rhs = r0 + rr;
           float2 v = make_float2(0.f, 0.f);
           if (rhs < a.nrhs && !skip_rhs(a.red.flags, rhs)) {
-            v = a.in[rhs * rstride + nb * NC + col];
+            v = gl(a.in)[rhs * rstride + nb * NC + col];
             if (DAG && col >= NC / 2) v = make_float2(-v.x, -v.y);
           }
           xs[col][rr] = v;
         }
         __syncthreads();
-        const float2* __restrict__ Yk = a.Y + ((site * ndir + k) * NC) * (long)NC;
+        gptr<const float2> __restrict__ Yk = gl(a.Y) + ((site * ndir + k) * NC) * (long)NC;
         float2 y[NC / 4];
 #pragma unroll
         for (int s = 0; s < NC / 4; ++s) y[s] = Yk[(long)(4 * s + kq) * NC + row];
@@ -94,8 +96,11 @@ __global__ __launch_bounds__(NC / 16 * 64) void coarse_mrhs_kernel(CoarseArgs<fl
           float2 v = make_float2(accr[e], acci[e]);
           if (DAG && orow >= NC / 2) v = make_float2(-v.x, -v.y);
           const long idx = rhs * rstride + site * NC + orow;
-          if (EPI == EPI_RESID) v = make_float2(a.b[idx].x - v.x, a.b[idx].y - v.y);
-          a.out[idx] = v;
+          if (EPI == EPI_RESID) {
+            const float2 bv = gl(a.b)[idx];
+            v = make_float2(bv.x - v.x, bv.y - v.y);
+          }
+          gl(a.out)[idx] = v;
         }
       }
     }
@@ -104,7 +109,7 @@ __global__ __launch_bounds__(NC / 16 * 64) void coarse_mrhs_kernel(CoarseArgs<fl
         const int rhs = e / NC, col = e - rhs * NC;
         if (skip_rhs(a.red.flags, rhs)) continue;
         const long idx = rhs * rstride + site * NC + col;
-        a.copy_out[idx] = a.in[idx];
+        gl(a.copy_out)[idx] = gl(a.in)[idx];
       }
     }
   }

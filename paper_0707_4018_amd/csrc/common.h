@@ -5,6 +5,29 @@
 
 namespace amg {
 
+// Global-memory views of pointers.  A pointer read out of an argument struct
+// is generic, and the compiler then emits flat instructions for it (which
+// also count against the scalar/LDS wait counter, so a wait for an argument
+// or an LDS value waits for every load in flight).  Kernels access their
+// fields through these views instead.
+// (The host pass only type-checks device code: there the views are plain.)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define AMG_GLOBAL __attribute__((address_space(1)))
+#else
+#define AMG_GLOBAL
+#endif
+template <typename T> using gptr = AMG_GLOBAL T*;
+template <typename T> __device__ __forceinline__ gptr<const T> gl(const T* p) { return (gptr<const T>)p; }
+template <typename T> __device__ __forceinline__ gptr<T> gl(T* p) { return (gptr<T>)p; }
+
+// Element i (0 <= i < 4) of a four-entry array, by selects.  Argument
+// structs are copied into registers at kernel entry; an array member indexed
+// by a run-time value would keep the whole copy in scratch memory, so loops
+// over dimensions run to 4 with a guard and read arrays through this.
+template <typename T> __device__ __forceinline__ T at4(const T (&a)[4], int i) {
+  return i == 0 ? a[0] : (i == 1 ? a[1] : (i == 2 ? a[2] : a[3]));
+}
+
 // ---------------------------------------------------------------------------
 // complex arithmetic on float2 / double2
 // ---------------------------------------------------------------------------
@@ -56,9 +79,11 @@ __host__ __device__ __forceinline__ float bf2f(uint16_t h) {
 }
 
 // load an element of P in any storage and return it in compute precision T
-template <typename T> __device__ __forceinline__ cplx<T> ldp(const double2* p, long i) { const double2 z = p[i]; return mk<T>((T)z.x, (T)z.y); }
-template <typename T> __device__ __forceinline__ cplx<T> ldp(const float2* p, long i) { const float2 z = p[i]; return mk<T>((T)z.x, (T)z.y); }
-template <typename T> __device__ __forceinline__ cplx<T> ldp(const bf16x2* p, long i) { const bf16x2 z = p[i]; return mk<T>((T)bf2f(z.x), (T)bf2f(z.y)); }
+template <typename T> __device__ __forceinline__ cplx<T> pval(double2 z) { return mk<T>((T)z.x, (T)z.y); }
+template <typename T> __device__ __forceinline__ cplx<T> pval(float2 z) { return mk<T>((T)z.x, (T)z.y); }
+template <typename T> __device__ __forceinline__ cplx<T> pval(bf16x2 z) { return mk<T>((T)bf2f(z.x), (T)bf2f(z.y)); }
+// element i of P (any storage kind, generic or global pointer) in precision T
+template <typename T, typename Ptr> __device__ __forceinline__ cplx<T> ldp(Ptr p, long i) { return pval<T>(p[i]); }
 
 // ---------------------------------------------------------------------------
 // Field layout.  A level field of V sites with `dof` complex components per
@@ -88,14 +113,36 @@ struct Layout {
 constexpr int RED_THREADS = 256;
 constexpr int RED_WAVES = RED_THREADS / 64;
 
+// Sum over the 64 lanes of a wave with DPP row operations (no trip through
+// the LDS crossbar, unlike shuffles): shift-right by 1, 2, 4, 8 within each
+// row of 16 lanes leaves the row's sum in its lane 15; broadcasting lane 15
+// into the next row, then lane 31 into rows 2 and 3, leaves the total in lane
+// 63, which is read into every lane.  Lanes whose DPP source lies outside the
+// row add zero.  The order of the additions is fixed.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_f64<0x111, 0xf>(v);  // row_shr:1
+  v += dpp_f64<0x112, 0xf>(v);  // row_shr:2
+  v += dpp_f64<0x114, 0xf>(v);  // row_shr:4
+  v += dpp_f64<0x118, 0xf>(v);  // row_shr:8
+  v += dpp_f64<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_f64<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
+}
+
 template <int NV>
 __device__ __forceinline__ void block_sum(double (&v)[NV], double (*sh)[RED_WAVES]) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
-    double s = v[k];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+    const double s = wave_sum(v[k]);
     if (lane == 0) sh[k][wave] = s;
   }
   __syncthreads();
@@ -109,6 +156,24 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double (*sh)[RED_WAVE
   __syncthreads();
 }
 
+// Publication without a release fence: on this chip each XCD has its own L2,
+// and an agent-scope release fence (__threadfence) writes back the whole L2
+// of the XCD — for a launch of ~1000 blocks that alone costs tens of
+// microseconds.  Only the partial sums have to cross XCDs inside the launch
+// (everything else is read by later launches), so each block stores its
+// partials with agent-scope atomic stores (written through to the memory
+// side), waits until those stores are complete, and only then takes a ticket;
+// the last block reads the partials with agent-scope atomic loads, which do
+// not hit stale lines of its own L2.  The loads come after the ticket that
+// proves every store complete.
+// Wait until this thread's earlier memory operations are complete (the
+// compiler may not move memory operations across it either).
+__device__ __forceinline__ void wait_stores_complete() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 template <int NV>
 __device__ bool grid_reduce(double (&v)[NV], double* part, unsigned* ticket, int rhs,
                             double (&tot)[NV]) {
@@ -118,23 +183,22 @@ __device__ bool grid_reduce(double (&v)[NV], double* part, unsigned* ticket, int
   block_sum<NV>(v, sh);
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int k = 0; k < NV; ++k) part[((long)rhs * NV + k) * nblk + blockIdx.x] = v[k];
-    __threadfence();
-    const unsigned t = atomicAdd(&ticket[rhs], 1u);
+    for (int k = 0; k < NV; ++k)
+      __hip_atomic_store(&part[((long)rhs * NV + k) * nblk + blockIdx.x], v[k], __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    wait_stores_complete();
+    const unsigned t = __hip_atomic_fetch_add(&ticket[rhs], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     is_last = (t == (unsigned)(nblk - 1));
   }
   __syncthreads();
   if (!is_last) return false;
-  // acquire: every block released its partials (fence) before taking a
-  // ticket, and this fence invalidates the local caches, so plain loads see
-  // them; plain loads can all be in flight at once, unlike coherent ones
-  __threadfence();
   double s[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) s[k] = 0.0;
   for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
 #pragma unroll
-    for (int k = 0; k < NV; ++k) s[k] += part[((long)rhs * NV + k) * nblk + b];
+    for (int k = 0; k < NV; ++k)
+      s[k] += __hip_atomic_load(&part[((long)rhs * NV + k) * nblk + b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   block_sum<NV>(s, sh);
 #pragma unroll
@@ -147,7 +211,7 @@ __device__ bool grid_reduce(double (&v)[NV], double* part, unsigned* ticket, int
 // Scalars and flags of a solver live in one device array of doubles.
 // A right-hand side whose `skip` flag is non-zero is left untouched.
 __device__ __forceinline__ bool skip_rhs(const int* flags, int rhs) {
-  return flags != nullptr && flags[rhs] != 0;
+  return flags != nullptr && gl(flags)[rhs] != 0;
 }
 
 }  // namespace amg

@@ -45,9 +45,21 @@ inline void dispatch(void (*fn)(A, const A*), const A& a, dim3 grid, dim3 block,
   hipLaunchKernelGGL(fn, grid, block, 0, st, a, static_cast<const A*>(nullptr));
 }
 
-// pick this block's argument struct; blocks past the instance's rhs count exit
-#define AMG_ARGS(...)                                                  \
-  const __VA_ARGS__& a = (batch != nullptr) ? batch[blockIdx.z] : a0;   \
+// Pick this block's argument struct; blocks past the instance's rhs count
+// exit.  The struct is copied field by field from the kernel arguments or
+// from the batch table (the copy is split into scalars): a reference that
+// could point at either would be a generic pointer, which turns every
+// pointer loaded from it into a flat address and every memory access of the
+// kernel into a flat instruction (whose waits also wait for scalar loads).
+#define AMG_PICK(NAME, ...)                  \
+  __VA_ARGS__ NAME;                          \
+  if (batch != nullptr) {                    \
+    NAME = batch[blockIdx.z];                \
+  } else {                                   \
+    NAME = a0;                               \
+  }
+#define AMG_ARGS(...)      \
+  AMG_PICK(a, __VA_ARGS__) \
   if ((int)blockIdx.y >= a.nrhs) return;
 
 }  // namespace amg

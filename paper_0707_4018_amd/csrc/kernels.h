@@ -35,8 +35,9 @@ struct RedArgs {
 __device__ __forceinline__ void finalize_mr(const double* tot, const RedArgs& r, int rhs) {
   const double pp = tot[2];
   const double s = pp > 0.0 ? r.omega / pp : 0.0;
-  r.scal[r.slot + 2 * rhs] = s * tot[0];
-  r.scal[r.slot + 2 * rhs + 1] = s * tot[1];
+  gptr<double> scal = gl(r.scal);
+  scal[r.slot + 2 * rhs] = s * tot[0];
+  scal[r.slot + 2 * rhs + 1] = s * tot[1];
 }
 
 template <typename T>

@@ -24,38 +24,38 @@ namespace {
 
 template <typename T> struct Sp2 { cplx<T> a, b; };
 
-__device__ __forceinline__ Sp2<double> ld2(const double2* __restrict__ p, long s, long V) {
+__device__ __forceinline__ Sp2<double> ld2(gptr<const double2> __restrict__ p, long s, long V) {
   return {p[s], p[V + s]};
 }
-__device__ __forceinline__ Sp2<float> ld2(const float2* __restrict__ p, long s, long) {
-  const float4 q = reinterpret_cast<const float4*>(p)[s];
+__device__ __forceinline__ Sp2<float> ld2(gptr<const float2> __restrict__ p, long s, long) {
+  const float4 q = ((gptr<const float4>)p)[s];
   return {make_float2(q.x, q.y), make_float2(q.z, q.w)};
 }
-__device__ __forceinline__ void st2(double2* __restrict__ p, long s, long V, Sp2<double> v) {
+__device__ __forceinline__ void st2(gptr<double2> __restrict__ p, long s, long V, Sp2<double> v) {
   p[s] = v.a; p[V + s] = v.b;
 }
-__device__ __forceinline__ void st2(float2* __restrict__ p, long s, long, Sp2<float> v) {
-  reinterpret_cast<float4*>(p)[s] = make_float4(v.a.x, v.a.y, v.b.x, v.b.y);
+__device__ __forceinline__ void st2(gptr<float2> __restrict__ p, long s, long, Sp2<float> v) {
+  ((gptr<float4>)p)[s] = make_float4(v.a.x, v.a.y, v.b.x, v.b.y);
 }
 // streaming (non-temporal) stores for lattices far larger than the caches:
 // the result is not read again by this kernel and would only evict the
 // neighbour spinors that the other waves still need
 typedef double v2d __attribute__((ext_vector_type(2)));
 typedef float v4f __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ void st2_nt(double2* __restrict__ p, long s, long V, Sp2<double> v) {
+__device__ __forceinline__ void st2_nt(gptr<double2> __restrict__ p, long s, long V, Sp2<double> v) {
   const v2d a = {v.a.x, v.a.y}, b = {v.b.x, v.b.y};
-  __builtin_nontemporal_store(a, reinterpret_cast<v2d*>(p) + s);
-  __builtin_nontemporal_store(b, reinterpret_cast<v2d*>(p) + V + s);
+  __builtin_nontemporal_store(a, (gptr<v2d>)p + s);
+  __builtin_nontemporal_store(b, (gptr<v2d>)p + V + s);
 }
-__device__ __forceinline__ void st2_nt(float2* __restrict__ p, long s, long, Sp2<float> v) {
+__device__ __forceinline__ void st2_nt(gptr<float2> __restrict__ p, long s, long, Sp2<float> v) {
   const v4f a = {v.a.x, v.a.y, v.b.x, v.b.y};
-  __builtin_nontemporal_store(a, reinterpret_cast<v4f*>(p) + s);
+  __builtin_nontemporal_store(a, (gptr<v4f>)p + s);
 }
 // single link U_mu(site)
-__device__ __forceinline__ double2 ldU(const double2* __restrict__ U, long s, long V, int mu) {
+__device__ __forceinline__ double2 ldU(gptr<const double2> __restrict__ U, long s, long V, int mu) {
   return U[mu * V + s];
 }
-__device__ __forceinline__ float2 ldU(const float2* __restrict__ U, long s, long, int mu) {
+__device__ __forceinline__ float2 ldU(gptr<const float2> __restrict__ U, long s, long, int mu) {
   return U[2 * s + mu];
 }
 
@@ -101,11 +101,11 @@ __global__ __launch_bounds__(256) void wilson2d_kernel(WilsonArgs<T> a0, const W
   const int L1 = a.L1, L2 = a.L2;
   const long V = (long)L1 * L2;
   const long ro = (long)rhs * 2 * V;
-  const cplx<T>* __restrict__ pin = a.in + ro;
-  const cplx<T>* __restrict__ U = a.U;
-  const cplx<T>* __restrict__ bvec = a.b;
-  cplx<T>* __restrict__ out = a.out;
-  cplx<T>* __restrict__ copy_out = a.copy_out;
+  gptr<const cplx<T>> __restrict__ pin = gl(a.in) + ro;
+  gptr<const cplx<T>> __restrict__ U = gl(a.U);
+  gptr<const cplx<T>> __restrict__ bvec = gl(a.b);
+  gptr<cplx<T>> __restrict__ out = gl(a.out);
+  gptr<cplx<T>> __restrict__ copy_out = gl(a.copy_out);
   const T diag = (T)(2.0 + a.mass);
   Hops<T, DAG> H{V, L1, L2};
   const T sf = DAG ? (T)1 : (T)-1;  // forward projector 1 + sf gamma
@@ -153,13 +153,15 @@ __global__ __launch_bounds__(256) void wilson2d_kernel(WilsonArgs<T> a0, const W
 // the hop in direction dir (0:+1, 1:-1, 2:+2, 3:-2) when it leaves the block
 // through its face.  FP64, layout W = 1.
 __global__ __launch_bounds__(256) void wilson2d_split_kernel(
-    double2* __restrict__ out, const double2* __restrict__ in, const double2* __restrict__ U,
+    double2* __restrict__ out_, const double2* __restrict__ in, const double2* __restrict__ U_,
     double diag, int L1, int L2, int b1, int b2, int nrhs) {
   const int rhs = blockIdx.y;
   const long V = (long)L1 * L2;
   const long ro = (long)rhs * 2 * V;
   const long ostride = (long)nrhs * 2 * V;  // between output kinds
-  const double2* __restrict__ pin = in + ro;
+  gptr<const double2> __restrict__ pin = gl(in) + ro;
+  gptr<const double2> __restrict__ U = gl(U_);
+  gptr<double2> __restrict__ out = gl(out_);
   Hops<double, 0> H{V, L1, L2};
   for (long s = (long)blockIdx.x * blockDim.x + threadIdx.x; s < V; s += (long)gridDim.x * blockDim.x) {
     int x1, x2; long sp1, sm1, sp2, sm2;

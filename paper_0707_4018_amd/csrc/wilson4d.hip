@@ -28,14 +28,14 @@ namespace {
 
 template <typename T> struct Spinor { cplx<T> c[4][3]; };
 
-__device__ __forceinline__ void ld_spinor(const double2* __restrict__ p, long s, long V, Spinor<double>& o) {
+__device__ __forceinline__ void ld_spinor(gptr<const double2> __restrict__ p, long s, long V, Spinor<double>& o) {
 #pragma unroll
   for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
     for (int c = 0; c < 3; ++c) o.c[sp][c] = p[(long)(sp * 3 + c) * V + s];
 }
-__device__ __forceinline__ void ld_spinor(const float2* __restrict__ p, long s, long V, Spinor<float>& o) {
-  const float4* q = reinterpret_cast<const float4*>(p);
+__device__ __forceinline__ void ld_spinor(gptr<const float2> __restrict__ p, long s, long V, Spinor<float>& o) {
+  gptr<const float4> q = (gptr<const float4>)p;
 #pragma unroll
   for (int u = 0; u < 6; ++u) {
     const float4 v = q[(long)u * V + s];
@@ -44,14 +44,14 @@ __device__ __forceinline__ void ld_spinor(const float2* __restrict__ p, long s, 
     o.c[c1 / 3][c1 % 3] = make_float2(v.z, v.w);
   }
 }
-__device__ __forceinline__ void st_spinor(double2* __restrict__ p, long s, long V, const Spinor<double>& o) {
+__device__ __forceinline__ void st_spinor(gptr<double2> __restrict__ p, long s, long V, const Spinor<double>& o) {
 #pragma unroll
   for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
     for (int c = 0; c < 3; ++c) p[(long)(sp * 3 + c) * V + s] = o.c[sp][c];
 }
-__device__ __forceinline__ void st_spinor(float2* __restrict__ p, long s, long V, const Spinor<float>& o) {
-  float4* q = reinterpret_cast<float4*>(p);
+__device__ __forceinline__ void st_spinor(gptr<float2> __restrict__ p, long s, long V, const Spinor<float>& o) {
+  gptr<float4> q = (gptr<float4>)p;
 #pragma unroll
   for (int u = 0; u < 6; ++u) {
     const int c0 = 2 * u, c1 = 2 * u + 1;
@@ -65,26 +65,26 @@ __device__ __forceinline__ void st_spinor(float2* __restrict__ p, long s, long V
 // lines for the reductions' release fences to write back
 typedef double v2d __attribute__((ext_vector_type(2)));
 typedef float v4f __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ void st_spinor_nt(double2* __restrict__ p, long s, long V, const Spinor<double>& o) {
+__device__ __forceinline__ void st_spinor_nt(gptr<double2> __restrict__ p, long s, long V, const Spinor<double>& o) {
 #pragma unroll
   for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const v2d v = {o.c[sp][c].x, o.c[sp][c].y};
-      __builtin_nontemporal_store(v, reinterpret_cast<v2d*>(p) + (long)(sp * 3 + c) * V + s);
+      __builtin_nontemporal_store(v, (gptr<v2d>)p + (long)(sp * 3 + c) * V + s);
     }
 }
-__device__ __forceinline__ void st_spinor_nt(float2* __restrict__ p, long s, long V, const Spinor<float>& o) {
+__device__ __forceinline__ void st_spinor_nt(gptr<float2> __restrict__ p, long s, long V, const Spinor<float>& o) {
 #pragma unroll
   for (int u = 0; u < 6; ++u) {
     const int c0 = 2 * u, c1 = 2 * u + 1;
     const float2 a = o.c[c0 / 3][c0 % 3], b = o.c[c1 / 3][c1 % 3];
     const v4f v = {a.x, a.y, b.x, b.y};
-    __builtin_nontemporal_store(v, reinterpret_cast<v4f*>(p) + (long)u * V + s);
+    __builtin_nontemporal_store(v, (gptr<v4f>)p + (long)u * V + s);
   }
 }
 template <bool NT, typename T>
-__device__ __forceinline__ void st_out(cplx<T>* __restrict__ p, long s, long V, const Spinor<T>& o) {
+__device__ __forceinline__ void st_out(gptr<cplx<T>> __restrict__ p, long s, long V, const Spinor<T>& o) {
   if (NT) st_spinor_nt(p, s, V, o);
   else st_spinor(p, s, V, o);
 }
@@ -117,7 +117,7 @@ __device__ __forceinline__ void site_dots(const Spinor<T>& o, const Spinor<T>& c
 template <typename T> struct Link { cplx<T> m[3][3]; };
 
 template <typename T>
-__device__ __forceinline__ void ld_link(const cplx<T>* __restrict__ U, long s, long V, int mu, Link<T>& L) {
+__device__ __forceinline__ void ld_link(gptr<const cplx<T>> __restrict__ U, long s, long V, int mu, Link<T>& L) {
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
@@ -197,7 +197,7 @@ struct Geo4 {
 };
 
 template <typename T, int DAG>
-__device__ __forceinline__ void all_hops(Spinor<T>& o, const cplx<T>* __restrict__ pin, const cplx<T>* __restrict__ U,
+__device__ __forceinline__ void all_hops(Spinor<T>& o, gptr<const cplx<T>> __restrict__ pin, gptr<const cplx<T>> __restrict__ U,
                                          long s, long V, const long* fw, const long* bw) {
   const T sf = DAG ? (T)1 : (T)-1, sb = -sf;
   Spinor<T> p;
@@ -227,11 +227,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
   }
   const long V = (long)a.L1 * a.L2 * a.L3 * a.L4;
   const long ro = (long)rhs * 12 * V;
-  const cplx<T>* __restrict__ pin = a.in + ro;
-  const cplx<T>* __restrict__ U = a.U;
-  const cplx<T>* __restrict__ bvec = a.b;
-  cplx<T>* __restrict__ out = a.out;
-  cplx<T>* __restrict__ copy_out = a.copy_out;
+  gptr<const cplx<T>> __restrict__ pin = gl(a.in) + ro;
+  gptr<const cplx<T>> __restrict__ U = gl(a.U);
+  gptr<const cplx<T>> __restrict__ bvec = gl(a.b);
+  gptr<cplx<T>> __restrict__ out = gl(a.out);
+  gptr<cplx<T>> __restrict__ copy_out = gl(a.copy_out);
   const T diag = (T)(4.0 + a.mass);
   double acc[3] = {0.0, 0.0, 0.0};
   for (long s = (long)blockIdx.x * blockDim.x + threadIdx.x; s < V; s += (long)gridDim.x * blockDim.x) {
@@ -282,8 +282,8 @@ __global__ __launch_bounds__(256) void wilson4d_tm_kernel(WilsonArgs<T> a0, cons
   const long V3 = (long)L1 * L2 * L3;
   const long V = V3 * L4;
   const long ro = (long)rhs * 12 * V;
-  const cplx<T>* __restrict__ pin = a.in + ro;
-  const cplx<T>* __restrict__ U = a.U;
+  gptr<const cplx<T>> __restrict__ pin = gl(a.in) + ro;
+  gptr<const cplx<T>> __restrict__ U = gl(a.U);
   const T diag = (T)(4.0 + a.mass);
   const T sf = DAG ? (T)1 : (T)-1, sb = -sf;
   const int nslab = (L4 + TT - 1) / TT;
@@ -333,14 +333,14 @@ __global__ __launch_bounds__(256) void wilson4d_tm_kernel(WilsonArgs<T> a0, cons
       hop<T, 3, true>(o, prev, Lb, sb);
       if (EPI == EPI_RESID) {
         Spinor<T> b;
-        ld_spinor(a.b + ro, s, V, b);
+        ld_spinor(gl(a.b) + ro, s, V, b);
 #pragma unroll
         for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
           for (int k = 0; k < 3; ++k) o.c[sp][k] = csub<T>(b.c[sp][k], o.c[sp][k]);
       }
-      st_out<NT>(a.out + ro, s, V, o);
-      if (a.copy_out) st_out<NT>(a.copy_out + ro, s, V, cur);
+      st_out<NT>(gl(a.out) + ro, s, V, o);
+      if (a.copy_out) st_out<NT>(gl(a.copy_out) + ro, s, V, cur);
       if (EPI == EPI_MRDOT || EPI == EPI_NORM) site_dots<T, EPI>(o, cur, acc);
       prev = cur;
       cur = nxt;
@@ -358,14 +358,16 @@ __global__ __launch_bounds__(256) void wilson4d_tm_kernel(WilsonArgs<T> a0, cons
 
 // Split apply for the Galerkin product (FP64): out[0] = diagonal + hops inside
 // the block, out[1 + dir] = hop in direction dir leaving the block.
-__global__ __launch_bounds__(256) void wilson4d_split_kernel(double2* __restrict__ out, const double2* __restrict__ in,
-                                                             const double2* __restrict__ U, double diag, Geo4 G, long V,
+__global__ __launch_bounds__(256) void wilson4d_split_kernel(double2* __restrict__ out_, const double2* __restrict__ in,
+                                                             const double2* __restrict__ U_, double diag, Geo4 G, long V,
                                                              int b0, int b1, int b2, int b3, int nrhs) {
   const int rhs = blockIdx.y;
   const long ro = (long)rhs * 12 * V;
   const long ks = (long)nrhs * 12 * V;
   const int blk[4] = {b0, b1, b2, b3};
-  const double2* __restrict__ pin = in + ro;
+  gptr<const double2> __restrict__ pin = gl(in) + ro;
+  gptr<const double2> __restrict__ U = gl(U_);
+  gptr<double2> __restrict__ out = gl(out_);
   for (long s = (long)blockIdx.x * blockDim.x + threadIdx.x; s < V; s += (long)gridDim.x * blockDim.x) {
     long fw[4], bw[4];
     int x[4];
