@@ -220,7 +220,9 @@ amg_status amg_batch_destroy(amg_batch* b);
 
 /* ---- kernel timing (HIP events) -------------------------------------------
  * While enabled, every launch of kernel `kind` on level `level` made by this
- * solver is bracketed by a pair of HIP events on its stream.  amg_profile_read
+ * solver is timed by a pair of HIP events that the launch itself stamps at
+ * the start and end of the kernel's execution (hipExtLaunchKernelGGL), on
+ * its stream.  amg_profile_read
  * synchronises on the last event and returns the summed kernel time and the
  * number of launches since enabling.  kind: 0 fine Wilson stencil, 1 coarse
  * block stencil, 2 restriction, 3 prolongation (level = the fine side),

@@ -371,6 +371,61 @@ __global__ void gather_kernel(GatherArgs a0, const GatherArgs* batch) {
   if (rhs < a.nrhs) a.out[rhs] = a.scal[a.slot + rhs];
 }
 
+// GCR step with one reduction for the orthogonalisation: the sums
+// c_j = <W_j, w> (j < k), <w, w> and <w, r> in one pass; the last block forms
+// beta_j = c_j / <W_j, W_j>, the norm of the orthogonalised direction
+// <w', w'> = <w, w> - sum_j |c_j|^2 / <W_j, W_j> (the stored W_j are mutually
+// orthogonal) and alpha = <w', r> / <w', w'> with <w', r> = <w, r> (r is
+// orthogonal to every stored W_j).  gcr_update2 then applies the step.
+template <typename T, int KM>
+__global__ __launch_bounds__(256) void gcr_dots_kernel(GcrArgs<T> a0, const GcrArgs<T>* batch) {
+  AMG_ARGS(GcrArgs<T>)
+  const auto w = gl(a.w), Wb = gl(a.Wb), r = gl(a.r);
+  const auto scal = gl(a.red.scal);
+  const int rhs = blockIdx.y;
+  if (skip_rhs(a.red.flags, rhs)) return;
+  const long ro = (long)rhs * a.n;
+  const int k = a.k;
+  constexpr int NV = 2 * KM + 3;
+  double acc[NV];
+#pragma unroll
+  for (int j = 0; j < NV; ++j) acc[j] = 0.0;
+  GRID_STRIDE(i, a.n) {
+    const cplx<T> wi = w[ro + i], ri = r[ro + i];
+    if (KM > 0) {
+      // clamped loads (no branch between them), surplus terms masked
+      cplx<T> q[KM > 0 ? KM : 1];
+#pragma unroll
+      for (int j = 0; j < KM; ++j) q[j] = Wb[(long)(j < k ? j : k - 1) * a.dstride + ro + i];
+#pragma unroll
+      for (int j = 0; j < KM; ++j) {
+        const double m = j < k ? 1.0 : 0.0;
+        acc[2 * j] += m * ((double)q[j].x * wi.x + (double)q[j].y * wi.y);
+        acc[2 * j + 1] += m * ((double)q[j].x * wi.y - (double)q[j].y * wi.x);
+      }
+    }
+    acc[2 * KM] += (double)wi.x * wi.x + (double)wi.y * wi.y;
+    acc[2 * KM + 1] += (double)wi.x * ri.x + (double)wi.y * ri.y;
+    acc[2 * KM + 2] += (double)wi.x * ri.y - (double)wi.y * ri.x;
+  }
+  double tot[NV];
+  if (grid_reduce<NV>(acc, a.red.part, a.red.ticket, rhs, tot) && threadIdx.x == 0) {
+    double wwp = tot[2 * KM];
+    for (int j = 0; j < k; ++j) {
+      const double wwj = scal[a.ww_slot + rhs * GCR_KMAX + j];
+      const double s = wwj > 0.0 ? 1.0 / wwj : 0.0;
+      const double cr = tot[2 * j], ci = tot[2 * j + 1];
+      scal[a.beta_slot + (rhs * GCR_KMAX + j) * 2] = cr * s;
+      scal[a.beta_slot + (rhs * GCR_KMAX + j) * 2 + 1] = ci * s;
+      wwp -= (cr * cr + ci * ci) * s;
+    }
+    scal[a.ww_slot + rhs * GCR_KMAX + k] = wwp;
+    const double s = wwp > 0.0 ? 1.0 / wwp : 0.0;
+    scal[a.alpha_slot + 2 * rhs] = tot[2 * KM + 1] * s;
+    scal[a.alpha_slot + 2 * rhs + 1] = tot[2 * KM + 2] * s;
+  }
+}
+
 __global__ __launch_bounds__(256) void cg_update_kernel(double2* __restrict__ x, double2* __restrict__ r,
                                                         const double2* __restrict__ p, const double2* __restrict__ q,
                                                         long n, RedArgs red, int gamma_slot, int qq_slot, int rr_slot) {
@@ -497,6 +552,26 @@ void launch_gcr_maxpy(cplx<T>* w, cplx<T>* z, const cplx<T>* Wb, const cplx<T>* 
 }
 template void launch_gcr_maxpy<double>(double2*, double2*, const double2*, const double2*, long, const double2*, int, long, int, RedArgs, int, int, int, hipStream_t);
 template void launch_gcr_maxpy<float>(float2*, float2*, const float2*, const float2*, long, const float2*, int, long, int, RedArgs, int, int, int, hipStream_t);
+
+template <typename T>
+void launch_gcr_dots(const cplx<T>* Wb, long dstride, const cplx<T>* w, const cplx<T>* r, int k, long n, int nrhs,
+                     RedArgs red, int beta_slot, int ww_slot, int alpha_slot, hipStream_t st) {
+  GcrArgs<T> a = gcr_args<T>(n, nrhs, red);
+  a.Wb = const_cast<cplx<T>*>(Wb); a.dstride = dstride; a.w = const_cast<cplx<T>*>(w);
+  a.r = const_cast<cplx<T>*>(r); a.k = k;
+  a.beta_slot = beta_slot; a.ww_slot = ww_slot; a.alpha_slot = alpha_slot;
+  const dim3 grid(red_blocks(n), (unsigned)nrhs);
+  if (k <= 0) dispatch(gcr_dots_kernel<T, 0>, a, grid, dim3(256), st);
+  else if (k <= 2) dispatch(gcr_dots_kernel<T, 2>, a, grid, dim3(256), st);
+  else if (k <= 4) dispatch(gcr_dots_kernel<T, 4>, a, grid, dim3(256), st);
+  else if (k <= 8) dispatch(gcr_dots_kernel<T, 8>, a, grid, dim3(256), st);
+  else if (k <= 16) dispatch(gcr_dots_kernel<T, 16>, a, grid, dim3(256), st);
+  else dispatch(gcr_dots_kernel<T, 32>, a, grid, dim3(256), st);
+}
+template void launch_gcr_dots<double>(const double2*, long, const double2*, const double2*, int, long, int, RedArgs,
+                                      int, int, int, hipStream_t);
+template void launch_gcr_dots<float>(const float2*, long, const float2*, const float2*, int, long, int, RedArgs, int,
+                                     int, int, hipStream_t);
 
 template <typename T>
 void launch_gcr_update(cplx<T>* x, cplx<T>* r, const cplx<T>* z, const cplx<T>* w, long n, int nrhs, RedArgs red,

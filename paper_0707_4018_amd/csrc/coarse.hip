@@ -339,8 +339,7 @@ __global__ __launch_bounds__(256) void gcr16_apply_dots_kernel(G16Args<T> a0, co
   wait_stores_complete();
   __syncthreads();
   if (threadIdx.x == 0)
-    is_last = (__hip_atomic_fetch_add(&a.red.ticket[rhs], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
-               (unsigned)(nblk - 1));
+    is_last = last_block(a.red.ticket, rhs);
   __syncthreads();
   if (!is_last) return;
   // every thread sums a stride of the blocks for each quantity, then the
@@ -375,7 +374,6 @@ __global__ __launch_bounds__(256) void gcr16_apply_dots_kernel(G16Args<T> a0, co
     const double s = wwp > 0.0 ? 1.0 / wwp : 0.0;
     scal[alpha_slot + 2 * rhs] = blk_part[2 * k + 1] * s;
     scal[alpha_slot + 2 * rhs + 1] = blk_part[G16_NQ - 1] * s;
-    __hip_atomic_store(&a.red.ticket[rhs], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 

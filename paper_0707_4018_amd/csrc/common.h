@@ -106,7 +106,7 @@ struct Layout {
 // ---------------------------------------------------------------------------
 // Deterministic block + grid reductions of NV doubles per right-hand side.
 // Every block writes its partial sums to part[(rhs*NV + k)*nblk + block]; the
-// last block to arrive (atomic ticket per rhs) sums the partials in block
+// last block to arrive (atomic tickets per rhs) sums the partials in block
 // order and returns true with the totals in `tot` (valid in all threads).
 // The sum order is fixed, so results do not depend on scheduling.
 // ---------------------------------------------------------------------------
@@ -174,6 +174,31 @@ __device__ __forceinline__ void wait_stores_complete() {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
+// Arrival counters, two levels: blocks take a ticket of their group of
+// RED_GROUP blocks, the last of each group a ticket of the launch, so no
+// counter sees more than RED_GROUP atomics (~1000 atomics on one address
+// serialise for microseconds).  Each counter has a 64-byte line of its own.
+constexpr int RED_GROUP = 32;
+constexpr int TICKET_PAD = 16;
+constexpr int RED_BLOCKS_LIMIT = 1024;
+constexpr int TICKETS_PER_RHS = (1 + RED_BLOCKS_LIMIT / RED_GROUP) * TICKET_PAD;
+
+__device__ __forceinline__ bool take_ticket(unsigned* t, unsigned n) {
+  if (__hip_atomic_fetch_add(t, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != n - 1) return false;
+  __hip_atomic_store(t, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);  // all n arrived: reset for the next launch
+  return true;
+}
+// Called by one thread per block after its partials are complete; true in
+// the block that arrives last in the launch (for right-hand side rhs).
+__device__ __forceinline__ bool last_block(unsigned* ticket, int rhs) {
+  unsigned* tk = ticket + (long)rhs * TICKETS_PER_RHS;
+  const int nblk = gridDim.x, grp = blockIdx.x / RED_GROUP;
+  const int ngrp = (nblk + RED_GROUP - 1) / RED_GROUP;
+  const int gsize = (nblk - grp * RED_GROUP < RED_GROUP) ? nblk - grp * RED_GROUP : RED_GROUP;
+  if (!take_ticket(tk + (1 + grp) * TICKET_PAD, (unsigned)gsize)) return false;
+  return ngrp == 1 || take_ticket(tk, (unsigned)ngrp);
+}
+
 template <int NV>
 __device__ bool grid_reduce(double (&v)[NV], double* part, unsigned* ticket, int rhs,
                             double (&tot)[NV]) {
@@ -187,8 +212,7 @@ __device__ bool grid_reduce(double (&v)[NV], double* part, unsigned* ticket, int
       __hip_atomic_store(&part[((long)rhs * NV + k) * nblk + blockIdx.x], v[k], __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
     wait_stores_complete();
-    const unsigned t = __hip_atomic_fetch_add(&ticket[rhs], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    is_last = (t == (unsigned)(nblk - 1));
+    is_last = last_block(ticket, rhs);
   }
   __syncthreads();
   if (!is_last) return false;
@@ -203,8 +227,6 @@ __device__ bool grid_reduce(double (&v)[NV], double* part, unsigned* ticket, int
   block_sum<NV>(s, sh);
 #pragma unroll
   for (int k = 0; k < NV; ++k) tot[k] = s[k];
-  if (threadIdx.x == 0)
-    __hip_atomic_store(&ticket[rhs], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return true;
 }
 

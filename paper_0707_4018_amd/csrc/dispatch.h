@@ -11,6 +11,7 @@
 // instead.  The batch layer records the same solve sequence once per
 // instance and merges the recordings stage by stage into batched launches.
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -30,6 +31,15 @@ struct Recorder {
 
 Recorder*& current_recorder();
 
+// Kernel timing: an event pair armed for the next launch on this thread.  The
+// launch stamps the pair itself (start and end of the kernel's execution),
+// so the interval excludes the dispatch gap that events recorded on the
+// stream around a launch would include.
+struct LaunchTiming {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+LaunchTiming& pending_timing();
+
 template <class A>
 inline void dispatch(void (*fn)(A, const A*), const A& a, dim3 grid, dim3 block, hipStream_t st) {
   if (Recorder* rec = current_recorder()) {
@@ -40,6 +50,12 @@ inline void dispatch(void (*fn)(A, const A*), const A& a, dim3 grid, dim3 block,
     r.grid = grid;
     r.block = block;
     rec->ops.push_back(std::move(r));
+    return;
+  }
+  LaunchTiming& t = pending_timing();
+  if (t.start != nullptr) {
+    hipExtLaunchKernelGGL(fn, grid, block, 0, st, t.start, t.stop, 0, a, static_cast<const A*>(nullptr));
+    t = LaunchTiming{};
     return;
   }
   hipLaunchKernelGGL(fn, grid, block, 0, st, a, static_cast<const A*>(nullptr));

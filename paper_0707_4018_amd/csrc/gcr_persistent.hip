@@ -1,14 +1,26 @@
-// Persistent coarsest-level solve for the 2d hierarchy (N_c = 16): the whole
-// restarted GCR of the coarsest level (see level_gcr in the runtime for the
-// iteration it reproduces) runs in one cooperative launch.  Phases are
-// separated by grid barriers; every block reduces the partial sums of all
-// blocks in the same fixed order, so control decisions (convergence, restart)
-// are identical in every block and deterministic.
+// Persistent coarsest-level solve (N_c = 16): the whole restarted GCR of the
+// coarsest level (the iteration level_gcr in the runtime issues as separate
+// launches, reproduced step for step) runs in one cooperative launch.
+// Phases are separated by grid barriers; every block reduces the partial
+// sums of all blocks in the same fixed order, so control decisions
+// (convergence, restart) are identical in every block and deterministic.
+//
+// Ownership: wave w of block b owns the sites b*4 + w + t*(4*nblk) in every
+// phase, and the lanes of its first column group own their rows.  Only the
+// stencil reads data of other blocks (the neighbours' entries of r, and of x
+// at a restart); those two vectors are written and read with agent-scope
+// atomic accesses (written through to the memory side, not served from a
+// stale line of another XCD's L2), everything else is private to its owner.
+// That makes the barrier cheap: every thread waits until its stores are
+// complete, then the block arrives — no release fence (which on this chip
+// writes back the whole L2 of the XCD).
 //
 // Barrier: monotonic arrival counter per right-hand side, zeroed before the
 // launch.  Waiting is bounded: after ~2^24 polls, or once any block has
 // recorded a timeout, a block records the timeout and proceeds, so every
 // wave reaches the end of the kernel; the host turns the flag into an error.
+#include <cstring>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -19,17 +31,37 @@ constexpr int PG_THREADS = 256;
 constexpr int PG_WAVES = PG_THREADS / 64;
 constexpr int PG_NQ = 2 * GCR_KMAX + 3;  // partial sums per block
 
-struct PgCtl {
-  unsigned epoch;
-};
+// agent-coherent accesses of r and x
+__device__ __forceinline__ float2 ld_coh(const float2* p) {
+  const unsigned long long u = __hip_atomic_load(reinterpret_cast<unsigned long long*>(const_cast<float2*>(p)),
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  float2 v;
+  memcpy(&v, &u, sizeof(v));
+  return v;
+}
+__device__ __forceinline__ double2 ld_coh(const double2* p) {
+  double* q = reinterpret_cast<double*>(const_cast<double2*>(p));
+  return make_double2(__hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                      __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+__device__ __forceinline__ void st_coh(float2* p, float2 v) {
+  unsigned long long u;
+  memcpy(&u, &v, sizeof(u));
+  __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_coh(double2* p, double2 v) {
+  double* q = reinterpret_cast<double*>(p);
+  __hip_atomic_store(q, v.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(q + 1, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
-__device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned nblk, PgCtl& c, int* err) {
-  __syncthreads();  // the block's stores are complete before thread 0 releases them
-  c.epoch += 1;
+__device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned nblk, unsigned& epoch, int* err) {
+  wait_stores_complete();  // this thread's stores (r, x, partial sums) are complete
+  __syncthreads();
+  epoch += 1;
   if (threadIdx.x == 0) {
-    __threadfence();
-    atomicAdd(bar, 1u);
-    const unsigned target = c.epoch * nblk;
+    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned target = epoch * nblk;
     unsigned spins = 0;
     while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
       __builtin_amdgcn_s_sleep(1);
@@ -38,19 +70,8 @@ __device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned nblk, PgCtl
         break;
       }
     }
-    __threadfence();
   }
   __syncthreads();
-}
-
-__device__ __forceinline__ int nbr_coarse(long site, const int* x, const int* dims, int nd, int dir, long* out) {
-  const int mu = dir >> 1;
-  long stride = 1;
-  for (int nu = 0; nu < mu; ++nu) stride *= dims[nu];
-  const int L = dims[mu];
-  if ((dir & 1) == 0) *out = (x[mu] == L - 1) ? site - (long)(L - 1) * stride : site + stride;
-  else *out = (x[mu] == 0) ? site + (long)(L - 1) * stride : site - stride;
-  return 0;
 }
 
 template <typename T>
@@ -71,34 +92,57 @@ struct PgArgs {
   int* iters;     // [nrhs]
 };
 
-// One wave computes (A v)(site) for the 16 rows of `site` (N_c = 16); the
-// result ends in lanes lane < LPC, rows lane*R .. lane*R + R - 1.
-template <typename T>
-__device__ __forceinline__ void wave_apply16(const PgArgs<T>& a, const cplx<T>* __restrict__ v, long site,
-                                             cplx<T> (&acc)[(sizeof(T) == 4) ? 2 : 1]) {
+// (A v)(site) for the 16 rows of `site` by one wave (NDIR = 2 nd + 1 blocks
+// of the stencil); v is read with agent-coherent loads.  The result ends in
+// the lanes of column group 0: lane rg holds rows rg*R .. rg*R + R - 1.
+template <typename T, int NDIR>
+__device__ __forceinline__ void pg_apply(gptr<const cplx<T>> Y, const CoarseGeom& g, const cplx<T>* v, long site,
+                                         int cg, int rg, cplx<T> (&acc)[(sizeof(T) == 4) ? 2 : 1]) {
   constexpr int NC = 16;
   constexpr int R = (sizeof(T) == 4) ? 2 : 1;
   constexpr int LPC = NC / R;
   constexpr int CPI = 64 / LPC;
-  const int lane = threadIdx.x & 63;
-  const int cg = lane / LPC, rg = lane - cg * LPC;
-  const int nd = a.g.nd, ndir = 2 * nd + 1;
+  constexpr int NQ = NC / CPI;
+  constexpr int ND = (NDIR - 1) / 2;
   int xc[4];
-  long rem = site;
-  for (int mu = 0; mu < nd; ++mu) { xc[mu] = (int)(rem % a.g.dims[mu]); rem /= a.g.dims[mu]; }
-  long nbs[9];
+  long stride[4];
+  {
+    long rem = site, st = 1;
+#pragma unroll
+    for (int mu = 0; mu < ND; ++mu) {
+      xc[mu] = (int)(rem % g.dims[mu]);
+      rem /= g.dims[mu];
+      stride[mu] = st;
+      st *= g.dims[mu];
+    }
+  }
+  long nbs[NDIR];
   nbs[0] = site;
-  for (int k = 1; k < ndir; ++k) nbr_coarse(site, xc, a.g.dims, nd, k - 1, &nbs[k]);
+#pragma unroll
+  for (int mu = 0; mu < ND; ++mu) {
+    const int L = g.dims[mu];
+    nbs[1 + 2 * mu] = (xc[mu] == L - 1) ? site - (long)(L - 1) * stride[mu] : site + stride[mu];
+    nbs[2 + 2 * mu] = (xc[mu] == 0) ? site + (long)(L - 1) * stride[mu] : site - stride[mu];
+  }
+  gptr<const cplx<T>> Ys = Y + site * (long)NDIR * NC * NC + rg * R;
+  cplx<T> ev[NDIR][NQ], yv[NDIR][NQ][R];
+#pragma unroll
+  for (int k = 0; k < NDIR; ++k)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int col = cg + CPI * q;
+      ev[k][q] = ld_coh(v + nbs[k] * NC + col);
+#pragma unroll
+      for (int i = 0; i < R; ++i) yv[k][q][i] = Ys[(long)k * NC * NC + col * NC + i];
+    }
 #pragma unroll
   for (int i = 0; i < R; ++i) acc[i] = mk<T>(0, 0);
-  const cplx<T>* __restrict__ Ys = a.Y + site * (long)ndir * NC * NC;
-  for (int gc = cg; gc < ndir * NC; gc += CPI) {
-    const int k = gc / NC, col = gc - k * NC;
-    const cplx<T> e = v[nbs[k] * NC + col];
-    const cplx<T>* y = Ys + (long)gc * NC + rg * R;
 #pragma unroll
-    for (int i = 0; i < R; ++i) cfma<T>(acc[i], y[i], e);
-  }
+  for (int k = 0; k < NDIR; ++k)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+      for (int i = 0; i < R; ++i) cfma<T>(acc[i], yv[k][q][i], ev[k][q]);
 #pragma unroll
   for (int i = 0; i < R; ++i) {
 #pragma unroll
@@ -109,56 +153,12 @@ __device__ __forceinline__ void wave_apply16(const PgArgs<T>& a, const cplx<T>* 
   }
 }
 
-// Block partial sums of nq values held per thread in LDS scratch, then the
-// grid reduction after the barrier: every block sums all partials in order.
-// Partials alternate between two buffers (publish counter parity): a block
-// cannot publish twice before every block has read the first publication,
-// because a grid barrier separates consecutive publications.
-template <int NQMAX>
-struct Reducer {
-  double* sh;  // [PG_WAVES][NQMAX] in LDS
-  double* part0;  // this rhs's two partial buffers, each [nblk][PG_NQ]
-  long half;
-  unsigned pub = 0;
-  __device__ void clear(int nq) {
-    for (int q = threadIdx.x; q < PG_WAVES * NQMAX; q += blockDim.x) sh[q] = 0.0;
-    __syncthreads();
-  }
-  // add a per-lane value to the wave's slot q (wave reduction, lane 0 adds)
-  __device__ void add(int q, double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    if ((threadIdx.x & 63) == 0) sh[(threadIdx.x >> 6) * NQMAX + q] += v;
-  }
-  __device__ void publish(int blk, int nq) {
-    __syncthreads();
-    double* part = part0 + (pub & 1u) * half;
-    for (int q = threadIdx.x; q < nq; q += blockDim.x) {
-      double s = 0.0;
-      for (int w = 0; w < PG_WAVES; ++w) s += sh[w * NQMAX + q];
-      part[(long)blk * PG_NQ + q] = s;
-    }
-  }
-  // after the barrier: totals of all blocks into tot[0..nq) (LDS), fixed order
-  __device__ void total(int nblk, int nq, double* tot) {
-    const double* part = part0 + (pub & 1u) * half;
-    pub += 1;
-    for (int q = threadIdx.x; q < nq; q += blockDim.x) {
-      double s = 0.0;
-      for (int bk = 0; bk < nblk; ++bk)
-        s += __hip_atomic_load(&part[(long)bk * PG_NQ + q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      tot[q] = s;
-    }
-    __syncthreads();
-  }
-};
-
-template <typename T>
+template <typename T, int NDIR>
 __global__ __launch_bounds__(PG_THREADS) void gcr16_persistent_kernel(PgArgs<T> a) {
   constexpr int NC = 16;
   constexpr int R = (sizeof(T) == 4) ? 2 : 1;
   constexpr int LPC = NC / R;
-  __shared__ double sh_red[PG_WAVES * PG_NQ];
+  __shared__ double sh[PG_WAVES][PG_NQ];  // per-wave partial sums
   __shared__ double tot[PG_NQ];
   __shared__ double wwh[GCR_KMAX];
   __shared__ double coef[2 * GCR_KMAX + 2];
@@ -168,32 +168,66 @@ __global__ __launch_bounds__(PG_THREADS) void gcr16_persistent_kernel(PgArgs<T> 
   const long V = a.g.V;
   const long n = V * NC;
   const long ro = (long)rhs * n;
-  const cplx<T>* __restrict__ b = a.b + ro;
-  cplx<T>* __restrict__ x = a.x + ro;
-  cplx<T>* __restrict__ r = a.r + ro;
+  gptr<const cplx<T>> b = gl(a.b) + ro;
+  cplx<T>* x = a.x + ro;  // agent-coherent accesses only
+  cplx<T>* r = a.r + ro;  // agent-coherent accesses only
+  gptr<const cplx<T>> Y = gl(a.Y);
   unsigned* bar = a.bar + rhs;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int cg = lane / LPC, rg = lane - cg * LPC;
-  Reducer<PG_NQ> red{sh_red, a.part + (long)rhs * 2 * nblk * PG_NQ, (long)nblk * PG_NQ};
-  PgCtl ctl{0};
-  const long tstride = (long)nblk * PG_THREADS;
-  const long t0 = (long)blk * PG_THREADS + threadIdx.x;
+  const bool own = cg == 0;
+  const long s0 = (long)blk * PG_WAVES + wave, sstride = (long)nblk * PG_WAVES;
+  double* part0 = a.part + (long)rhs * 2 * nblk * PG_NQ;
+  const long half = (long)nblk * PG_NQ;
+  unsigned pub = 0, epoch = 0;
+
+  auto clear = [&]() {
+    for (int q = threadIdx.x; q < PG_WAVES * PG_NQ; q += PG_THREADS) (&sh[0][0])[q] = 0.0;
+    __syncthreads();
+  };
+  // add a value of every lane to the wave's slot q (whole wave active)
+  auto wave_add = [&](int q, double v) {
+    v = wave_sum(v);
+    if (lane == 0) sh[wave][q] += v;
+  };
+  // block partials -> published -> barrier -> totals of all blocks in tot[0..nq)
+  auto reduce = [&](int nq) {
+    __syncthreads();
+    double* part = part0 + (pub & 1u) * half;
+    for (int q = threadIdx.x; q < nq; q += PG_THREADS) {
+      double s = 0.0;
+#pragma unroll
+      for (int w = 0; w < PG_WAVES; ++w) s += sh[w][q];
+      __hip_atomic_store(&part[(long)blk * PG_NQ + q], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    grid_barrier(bar, nblk, epoch, a.err);
+    for (int q = threadIdx.x; q < nq; q += PG_THREADS) {
+      double s = 0.0;
+#pragma unroll 8
+      for (unsigned bk = 0; bk < nblk; ++bk)
+        s += __hip_atomic_load(&part[(long)bk * PG_NQ + q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      tot[q] = s;
+    }
+    pub += 1;
+    __syncthreads();
+  };
 
   // x = 0, r = b, bb = <b, b>
-  red.clear(1);
-  {
+  clear();
+  for (long site = s0; site < V; site += sstride) {
     double s = 0.0;
-    for (long i = t0; i < n; i += tstride) {
-      const cplx<T> v = b[i];
-      x[i] = mk<T>(0, 0);
-      r[i] = v;
-      s += (double)v.x * v.x + (double)v.y * v.y;
-    }
-    red.add(0, s);
+    if (own)
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        const long idx = site * NC + rg * R + i;
+        const cplx<T> v = b[idx];
+        st_coh(x + idx, mk<T>(0, 0));
+        st_coh(r + idx, v);
+        s += (double)v.x * v.x + (double)v.y * v.y;
+      }
+    wave_add(0, s);
   }
-  red.publish(blk, 1);
-  grid_barrier(bar, nblk, ctl, a.err);
-  red.total(nblk, 1, tot);
+  reduce(1);
   const double bb = tot[0];
   bool done = (a.tol2 >= 1.0) ? true : (bb == 0.0);
   int it = 0;
@@ -201,81 +235,79 @@ __global__ __launch_bounds__(PG_THREADS) void gcr16_persistent_kernel(PgArgs<T> 
     const int k = it % a.m;
     if (k == 0 && it > 0) {
       // restart: r = b - A x
-      for (long site = (long)blk * PG_WAVES + wave; site < V; site += (long)nblk * PG_WAVES) {
+      for (long site = s0; site < V; site += sstride) {
         cplx<T> acc[R];
-        wave_apply16<T>(a, x, site, acc);
-        if (cg == 0)
+        pg_apply<T, NDIR>(Y, a.g, x, site, cg, rg, acc);
+        if (own)
 #pragma unroll
           for (int i = 0; i < R; ++i) {
             const long idx = site * NC + rg * R + i;
-            r[idx] = csub<T>(b[idx], acc[i]);
+            st_coh(r + idx, csub<T>(b[idx], acc[i]));
           }
       }
-      grid_barrier(bar, nblk, ctl, a.err);
+      grid_barrier(bar, nblk, epoch, a.err);
     }
-    cplx<T>* __restrict__ Wk = a.Wb + (long)k * a.dstride + ro;
-    cplx<T>* __restrict__ Zk = a.Zb + (long)k * a.dstride + ro;
-    // phase B: w = A r, z = r, dots <W_j, w> (j < k)
-    const int nq1 = 2 * k;
-    red.clear(nq1 + 1);
-    for (long site = (long)blk * PG_WAVES + wave; site < V; site += (long)nblk * PG_WAVES) {
+    gptr<cplx<T>> Wk = gl(a.Wb) + (long)k * a.dstride + ro;
+    gptr<cplx<T>> Zk = gl(a.Zb) + (long)k * a.dstride + ro;
+    // w = A r (stored as W_k), z = r (Z_k), dots <W_j, w> (j < k)
+    clear();
+    for (long site = s0; site < V; site += sstride) {
       cplx<T> acc[R];
-      wave_apply16<T>(a, r, site, acc);
-      for (int j = 0; j < k; ++j) {
-        double dr = 0.0, di = 0.0;
-        if (cg == 0) {
-          const cplx<T>* Wj = a.Wb + (long)j * a.dstride + ro;
-#pragma unroll
-          for (int i = 0; i < R; ++i) {
-            const cplx<T> q = Wj[site * NC + rg * R + i];
-            dr += (double)q.x * acc[i].x + (double)q.y * acc[i].y;
-            di += (double)q.x * acc[i].y - (double)q.y * acc[i].x;
-          }
-        }
-        red.add(2 * j, dr);
-        red.add(2 * j + 1, di);
-      }
-      if (cg == 0)
+      pg_apply<T, NDIR>(Y, a.g, r, site, cg, rg, acc);
+      if (own)
 #pragma unroll
         for (int i = 0; i < R; ++i) {
           const long idx = site * NC + rg * R + i;
           Wk[idx] = acc[i];
-          Zk[idx] = r[idx];
+          Zk[idx] = ld_coh(r + idx);
         }
+      for (int j = 0; j < k; ++j) {
+        double dr = 0.0, di = 0.0;
+        if (own) {
+          gptr<const cplx<T>> Wj = gl(a.Wb) + (long)j * a.dstride + ro + site * NC + rg * R;
+#pragma unroll
+          for (int i = 0; i < R; ++i) {
+            const cplx<T> q = Wj[i];
+            dr += (double)q.x * acc[i].x + (double)q.y * acc[i].y;
+            di += (double)q.x * acc[i].y - (double)q.y * acc[i].x;
+          }
+        }
+        wave_add(2 * j, dr);
+        wave_add(2 * j + 1, di);
+      }
     }
-    red.publish(blk, nq1);
-    grid_barrier(bar, nblk, ctl, a.err);
-    red.total(nblk, nq1, tot);
-    for (int j = threadIdx.x; j < k; j += blockDim.x) {
+    reduce(2 * k);
+    for (int j = threadIdx.x; j < k; j += PG_THREADS) {
       const double s = wwh[j] > 0.0 ? 1.0 / wwh[j] : 0.0;
       coef[2 * j] = tot[2 * j] * s;
       coef[2 * j + 1] = tot[2 * j + 1] * s;
     }
     __syncthreads();
-    // phase C: w -= sum beta_j W_j, z -= sum beta_j Z_j; <w,w>, <w,r>
-    red.clear(3);
-    {
-      double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-      for (long i = t0; i < n; i += tstride) {
-        cplx<T> wi = Wk[i], zi = Zk[i];
-        for (int j = 0; j < k; ++j) {
-          const cplx<T> bj = mk<T>((T)coef[2 * j], (T)coef[2 * j + 1]);
-          wi = csub<T>(wi, cmul<T>(bj, a.Wb[(long)j * a.dstride + ro + i]));
-          zi = csub<T>(zi, cmul<T>(bj, a.Zb[(long)j * a.dstride + ro + i]));
+    // w -= sum beta_j W_j, z -= sum beta_j Z_j; <w,w>, <w,r>
+    clear();
+    for (long site = s0; site < V; site += sstride) {
+      double s0w = 0.0, s1 = 0.0, s2 = 0.0;
+      if (own)
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          const long idx = site * NC + rg * R + i;
+          cplx<T> wi = Wk[idx], zi = Zk[idx];
+          for (int j = 0; j < k; ++j) {
+            const cplx<T> bj = mk<T>((T)coef[2 * j], (T)coef[2 * j + 1]);
+            wi = csub<T>(wi, cmul<T>(bj, gl(a.Wb)[(long)j * a.dstride + ro + idx]));
+            zi = csub<T>(zi, cmul<T>(bj, gl(a.Zb)[(long)j * a.dstride + ro + idx]));
+          }
+          if (k > 0) { Wk[idx] = wi; Zk[idx] = zi; }
+          const cplx<T> ri = ld_coh(r + idx);
+          s0w += (double)wi.x * wi.x + (double)wi.y * wi.y;
+          s1 += (double)wi.x * ri.x + (double)wi.y * ri.y;
+          s2 += (double)wi.x * ri.y - (double)wi.y * ri.x;
         }
-        if (k > 0) { Wk[i] = wi; Zk[i] = zi; }
-        const cplx<T> ri = r[i];
-        s0 += (double)wi.x * wi.x + (double)wi.y * wi.y;
-        s1 += (double)wi.x * ri.x + (double)wi.y * ri.y;
-        s2 += (double)wi.x * ri.y - (double)wi.y * ri.x;
-      }
-      red.add(0, s0);
-      red.add(1, s1);
-      red.add(2, s2);
+      wave_add(0, s0w);
+      wave_add(1, s1);
+      wave_add(2, s2);
     }
-    red.publish(blk, 3);
-    grid_barrier(bar, nblk, ctl, a.err);
-    red.total(nblk, 3, tot);
+    reduce(3);
     if (threadIdx.x == 0) {
       const double ww = tot[0];
       wwh[k] = ww;
@@ -284,22 +316,25 @@ __global__ __launch_bounds__(PG_THREADS) void gcr16_persistent_kernel(PgArgs<T> 
       coef[2 * GCR_KMAX + 1] = tot[2] * s;
     }
     __syncthreads();
-    // phase D: x += alpha z, r -= alpha w, rr
-    red.clear(1);
+    // x += alpha z, r -= alpha w, <r, r>
+    clear();
     {
       const cplx<T> al = mk<T>((T)coef[2 * GCR_KMAX], (T)coef[2 * GCR_KMAX + 1]);
-      double s = 0.0;
-      for (long i = t0; i < n; i += tstride) {
-        x[i] = cadd<T>(x[i], cmul<T>(al, Zk[i]));
-        const cplx<T> ri = csub<T>(r[i], cmul<T>(al, Wk[i]));
-        r[i] = ri;
-        s += (double)ri.x * ri.x + (double)ri.y * ri.y;
+      for (long site = s0; site < V; site += sstride) {
+        double s = 0.0;
+        if (own)
+#pragma unroll
+          for (int i = 0; i < R; ++i) {
+            const long idx = site * NC + rg * R + i;
+            st_coh(x + idx, cadd<T>(ld_coh(x + idx), cmul<T>(al, Zk[idx])));
+            const cplx<T> ri = csub<T>(ld_coh(r + idx), cmul<T>(al, Wk[idx]));
+            st_coh(r + idx, ri);
+            s += (double)ri.x * ri.x + (double)ri.y * ri.y;
+          }
+        wave_add(0, s);
       }
-      red.add(0, s);
     }
-    red.publish(blk, 1);
-    grid_barrier(bar, nblk, ctl, a.err);
-    red.total(nblk, 1, tot);
+    reduce(1);
     done = tot[0] <= a.tol2 * bb;
   }
   if (blk == 0 && threadIdx.x == 0) a.iters[rhs] = it;
@@ -313,15 +348,19 @@ hipError_t launch_gcr16_persistent(const cplx<T>* Y, const CoarseGeom& g, const 
                                    int nblk, double* part, unsigned* bar, int* err, int* iters, hipStream_t st,
                                    bool cooperative) {
   PgArgs<T> a{Y, g, b, x, r, Zb, Wb, dstride, m, maxiter, tol2, part, bar, err, iters};
+  if (g.nd != 2 && g.nd != 4) return hipErrorInvalidValue;
+  const void* fn = (g.nd == 2) ? (const void*)gcr16_persistent_kernel<T, 5> : (const void*)gcr16_persistent_kernel<T, 9>;
   if (cooperative) {
     void* args[] = {&a};
-    return hipLaunchCooperativeKernel((const void*)gcr16_persistent_kernel<T>, dim3((unsigned)nblk, (unsigned)nrhs),
-                                      dim3(PG_THREADS), args, 0, st);
+    return hipLaunchCooperativeKernel(fn, dim3((unsigned)nblk, (unsigned)nrhs), dim3(PG_THREADS), args, 0, st);
   }
-  // plain launch: the grid is far below one block per compute unit, and the
+  // plain launch: the grid is at most one block per compute unit, and the
   // bounded barrier wait ends the kernel with an error flag should a block
   // ever not be resident
-  hipLaunchKernelGGL(gcr16_persistent_kernel<T>, dim3((unsigned)nblk, (unsigned)nrhs), dim3(PG_THREADS), 0, st, a);
+  if (g.nd == 2)
+    hipLaunchKernelGGL((gcr16_persistent_kernel<T, 5>), dim3((unsigned)nblk, (unsigned)nrhs), dim3(PG_THREADS), 0, st, a);
+  else
+    hipLaunchKernelGGL((gcr16_persistent_kernel<T, 9>), dim3((unsigned)nblk, (unsigned)nrhs), dim3(PG_THREADS), 0, st, a);
   return hipGetLastError();
 }
 template hipError_t launch_gcr16_persistent<double>(const double2*, const CoarseGeom&, const double2*, double2*,

@@ -16,6 +16,7 @@ enum Epi {
 };
 
 constexpr int RED_MAX_BLOCKS = 1024;   // largest grid of kernels that reduce
+static_assert(RED_MAX_BLOCKS <= RED_BLOCKS_LIMIT, "ticket layout covers at most RED_BLOCKS_LIMIT blocks");
 // grid cap used when launching reducing kernels (<= RED_MAX_BLOCKS); a launch
 // shape chosen by the batch autotuner, 1024 by default
 int red_block_cap();
@@ -25,7 +26,7 @@ constexpr int GCR_KMAX = 32;           // longest GCR restart cycle
 // Reduction plumbing handed to every kernel that reduces or can skip rhs.
 struct RedArgs {
   double* part = nullptr;      // partial sums scratch
-  unsigned* ticket = nullptr;  // per-rhs arrival counters (zero between launches)
+  unsigned* ticket = nullptr;  // per-rhs arrival counters, TICKETS_PER_RHS each (zero between launches)
   double* scal = nullptr;      // solver scalars
   int slot = 0;                // where this reduction writes in scal
   double omega = 1.0;          // MR under-relaxation (EPI_MRDOT)
@@ -138,6 +139,10 @@ void launch_mr_update(cplx<T>* x, cplx<T>* r_out, const cplx<T>* r_in, const cpl
 template <typename T>
 void launch_norm2(const cplx<T>* v, long n, int nrhs, RedArgs red, hipStream_t st);
 // GCR building blocks; directions stored contiguously: W_j = Wb + j * dstride
+// one-reduction GCR orthogonalisation: betas, <w',w'> and alpha (then launch_gcr_update2)
+template <typename T>
+void launch_gcr_dots(const cplx<T>* Wb, long dstride, const cplx<T>* w, const cplx<T>* r, int k, long n, int nrhs,
+                     RedArgs red, int beta_slot, int ww_slot, int alpha_slot, hipStream_t st);
 template <typename T>
 void launch_gcr_mdot(const cplx<T>* Wb, long dstride, const cplx<T>* w, int k, long n, int nrhs,
                      RedArgs red, int beta_slot, int ww_slot, hipStream_t st);

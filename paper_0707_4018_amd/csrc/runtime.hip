@@ -37,6 +37,10 @@ Recorder*& current_recorder() {
   thread_local Recorder* rec = nullptr;
   return rec;
 }
+LaunchTiming& pending_timing() {
+  thread_local LaunchTiming t;
+  return t;
+}
 namespace {
 thread_local int g_red_cap = RED_MAX_BLOCKS;
 }
@@ -58,8 +62,8 @@ struct Scratch {
   int nslots = 0;
   void init(int nscal, int nflags) {
     part.ensure(sizeof(double) * (size_t)RHS_MAX * (2 * GCR_KMAX + 4) * RED_MAX_BLOCKS);
-    ticket.ensure(sizeof(unsigned) * RHS_MAX);
-    HIPC(hipMemset(ticket.p, 0, sizeof(unsigned) * RHS_MAX));
+    ticket.ensure(sizeof(unsigned) * RHS_MAX * TICKETS_PER_RHS);
+    HIPC(hipMemset(ticket.p, 0, sizeof(unsigned) * RHS_MAX * TICKETS_PER_RHS));
     scal.ensure(sizeof(double) * nscal);
     HIPC(hipMemset(scal.p, 0, sizeof(double) * nscal));
     flags.ensure(sizeof(int) * nflags);
@@ -227,6 +231,9 @@ struct amg_solver {
   int pcoarse_max_blocks = 64;
   bool pcoarse_coop = true;
   bool fused_gcr = false;  // measured slower than the separate kernels at the 2d coarse sizes
+  // GCR step as apply + one reduction for the orthogonalisation + update
+  // (three launches) instead of apply + dots + orthogonalise + update
+  bool gcr_dots = true;
   // FP32 coarse applies with at least this many right-hand sides use the
   // MFMA multi-rhs kernel (plain / residual epilogues, N_c = 16 or 48)
   int mrhs_min = 2;
@@ -264,12 +271,18 @@ struct ProfScope {
       HIPC(hipEventCreate(&e));
       P.ev.push_back(e);
     }
-    HIPC(hipEventRecord(P.ev[P.used], st));
+    // the scope's (first) kernel launch stamps the pair
+    pending_timing() = LaunchTiming{P.ev[P.used], P.ev[P.used + 1]};
   }
   ~ProfScope() {
     if (!active) return;
     auto& P = S.prof;
-    (void)hipEventRecord(P.ev[P.used + 1], st);
+    LaunchTiming& t = pending_timing();
+    if (t.start != nullptr) {  // nothing was launched: an empty interval
+      (void)hipEventRecord(t.start, st);
+      (void)hipEventRecord(t.stop, st);
+      t = LaunchTiming{};
+    }
     P.used += 2;
     P.last = st;
   }
@@ -413,7 +426,7 @@ void level_gcr(Solver& S, int l, int lstop, const cplx<T>* b, cplx<T>* x, int nr
   const double tol2 = tol * tol;
   const int check = precond ? 1 : kCoarseCheck;
   const bool recording = current_recorder() != nullptr;
-  if (!precond && S.persistent && !recording && L.dof == 16 && !L.fine) {
+  if (!precond && S.persistent && !recording && L.dof == 16 && !L.fine && (L.nd == 2 || L.nd == 4)) {
     // the whole solve in one cooperative launch
     long nb = (L.V + 15) / 16;
     nb = std::max(8L, std::min((long)S.pcoarse_max_blocks, nb));
@@ -451,6 +464,20 @@ void level_gcr(Solver& S, int l, int lstop, const cplx<T>* b, cplx<T>* x, int nr
         launch_gcr16_apply_dots<T>(ca, r, Wb, dstride, k, L.gs.beta, L.gs.ww, L.gs.alpha, st);
         S.nC += 1;
       }
+      launch_gcr_update2<T>(x, r, z, Wb, Zb, dstride, k, n, nrhs, S.sc.red(0, flags), L.gs.beta, L.gs.alpha, L.gs.rr,
+                            L.gs.bb, tol2, flags, st);
+      if (!recording && (it + 1) % check == 0 && it + 1 < maxiter && S.sc.all_flags(L.flag_off, nrhs, st)) break;
+      continue;
+    }
+    if (S.gcr_dots) {
+      // three launches per step: apply, all sums, updates
+      const cplx<T>* z = r;
+      if (precond) {
+        vcycle<T>(S, l, lstop, r, Zk, nrhs, st);
+        z = Zk;
+      }
+      op_apply<T>(S, l, 0, EPI_PLAIN, z, Wk, nullptr, nullptr, nrhs, S.sc.red(0, flags), st);
+      launch_gcr_dots<T>(Wb, dstride, Wk, r, k, n, nrhs, S.sc.red(0, flags), L.gs.beta, L.gs.ww, L.gs.alpha, st);
       launch_gcr_update2<T>(x, r, z, Wb, Zb, dstride, k, n, nrhs, S.sc.red(0, flags), L.gs.beta, L.gs.alpha, L.gs.rr,
                             L.gs.bb, tol2, flags, st);
       if (!recording && (it + 1) % check == 0 && it + 1 < maxiter && S.sc.all_flags(L.flag_off, nrhs, st)) break;
@@ -686,9 +713,10 @@ Solver* new_solver(const amg_gauge* g, const amg_mg_params* p) {
   S->piters.ensure(sizeof(int) * RHS_MAX);
   HIPC(hipMemset(S->perr.p, 0, sizeof(int) * 4));
   if (const char* e = std::getenv("AMG_PERSISTENT_COARSE")) S->persistent = std::atoi(e) != 0;
-  if (const char* e = std::getenv("AMG_PCOARSE_BLOCKS")) S->pcoarse_max_blocks = std::max(1, std::min(128, std::atoi(e)));
+  if (const char* e = std::getenv("AMG_PCOARSE_BLOCKS")) S->pcoarse_max_blocks = std::max(1, std::min(256, std::atoi(e)));
   if (const char* e = std::getenv("AMG_PCOARSE_COOP")) S->pcoarse_coop = std::atoi(e) != 0;
   if (const char* e = std::getenv("AMG_FUSED_GCR")) S->fused_gcr = std::atoi(e) != 0;
+  if (const char* e = std::getenv("AMG_GCR_DOTS")) S->gcr_dots = std::atoi(e) != 0;
   if (const char* e = std::getenv("AMG_MRHS_MIN")) S->mrhs_min = std::max(1, std::atoi(e));
   return S;
 }
