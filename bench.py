@@ -41,7 +41,8 @@ TOL = 1e-10
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the roofline kernel from rocprofv3 counters (FETCH_SIZE x 2,
 # calibrated on a 256 MiB device copy, + WRITE_SIZE), taken on the current kernel
-ROOF_TRAFFIC = 43522560   # 42502.5 KiB: FETCH 20930.4 KiB x 2 + WRITE 641.7 KiB
+# (None: the kernel changed since the counters were taken)
+ROOF_TRAFFIC = None
 WORKLOADS = json.load(open(os.path.join(ROOT, "synth", "workloads.json")))
 
 
@@ -656,8 +657,8 @@ def main():
 
     # roofline kernel: the level-1 block stencil with the MR epilogue (64^2 sites x 16 dof,
     # FP32), the longest-running apply of the solve (the shorter GCR kernels of the
-    # coarsest level are latency-bound); every launch in one more full step is bracketed
-    # by HIP events on the solver's stream
+    # coarsest level are latency-bound); every launch in one more full step is timed by
+    # a pair of HIP events that the launch stamps at the kernel's start and end
     log("kernel timing pass")
     _, _, _, prof = job.step(mixed=True, profile=(amg.Solver.PROF_COARSE_MR, 1))
     Vc1 = (L // 4) ** 2

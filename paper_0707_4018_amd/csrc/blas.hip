@@ -306,7 +306,8 @@ __global__ __launch_bounds__(256) void gcr_update_kernel(GcrArgs<T> a0, const Gc
 // GCR step, part 2 of the fused variant: w' = w - sum_j beta_j W_j,
 // z' = zsrc - sum_j beta_j Z_j (stored as direction k), x += alpha z',
 // r -= alpha w', <r, r> and flags.
-template <typename T>
+// RED = false: no <r, r> (the next step's dots kernel takes it).
+template <typename T, int KM, bool RED>
 __global__ __launch_bounds__(256) void gcr_update2_kernel(GcrArgs<T> a0, const GcrArgs<T>* batch) {
   AMG_ARGS(GcrArgs<T>)
   const auto x = gl(a.x), r = gl(a.r), Wb = gl(a.Wb), Zb = gl(a.Zb);
@@ -320,21 +321,36 @@ __global__ __launch_bounds__(256) void gcr_update2_kernel(GcrArgs<T> a0, const G
   const cplx<T> al = mk<T>((T)scal[a.alpha_slot + 2 * rhs], (T)scal[a.alpha_slot + 2 * rhs + 1]);
   const auto Wk = Wb + (long)k * a.dstride + ro;
   const auto Zk = Zb + (long)k * a.dstride + ro;
+  // coefficients in registers (zero past k); every direction load is issued
+  // (clamped to a stored one), so they are all in flight at once
+  cplx<T> bj[KM > 0 ? KM : 1];
+#pragma unroll
+  for (int j = 0; j < KM; ++j) bj[j] = j < k ? mk<T>((T)beta[2 * j], (T)beta[2 * j + 1]) : mk<T>(0, 0);
   double acc[1] = {0.0};
   GRID_STRIDE(i, a.n) {
     cplx<T> wi = Wk[i], zi = zsrc[ro + i];
-    for (int j = 0; j < k; ++j) {
-      const cplx<T> b = mk<T>((T)beta[2 * j], (T)beta[2 * j + 1]);
-      wi = csub<T>(wi, cmul<T>(b, Wb[(long)j * a.dstride + ro + i]));
-      zi = csub<T>(zi, cmul<T>(b, Zb[(long)j * a.dstride + ro + i]));
+    if (KM > 0) {
+      cplx<T> wq[KM > 0 ? KM : 1], zq[KM > 0 ? KM : 1];
+#pragma unroll
+      for (int j = 0; j < KM; ++j) {
+        const long off = (long)(j < k ? j : k - 1) * a.dstride + ro + i;
+        wq[j] = Wb[off];
+        zq[j] = Zb[off];
+      }
+#pragma unroll
+      for (int j = 0; j < KM; ++j) {
+        wi = csub<T>(wi, cmul<T>(bj[j], wq[j]));
+        zi = csub<T>(zi, cmul<T>(bj[j], zq[j]));
+      }
     }
     Wk[i] = wi;
     Zk[i] = zi;
     x[ro + i] = cadd<T>(x[ro + i], cmul<T>(al, zi));
     const cplx<T> ri = csub<T>(r[ro + i], cmul<T>(al, wi));
     r[ro + i] = ri;
-    acc[0] += (double)ri.x * ri.x + (double)ri.y * ri.y;
+    if (RED) acc[0] += (double)ri.x * ri.x + (double)ri.y * ri.y;
   }
+  if (!RED) return;
   double tot[1];
   if (grid_reduce<1>(acc, a.red.part, a.red.ticket, rhs, tot) && threadIdx.x == 0) {
     scal[a.rr_slot + rhs] = tot[0];
@@ -377,7 +393,10 @@ __global__ void gather_kernel(GatherArgs a0, const GatherArgs* batch) {
 // <w', w'> = <w, w> - sum_j |c_j|^2 / <W_j, W_j> (the stored W_j are mutually
 // orthogonal) and alpha = <w', r> / <w', w'> with <w', r> = <w, r> (r is
 // orthogonal to every stored W_j).  gcr_update2 then applies the step.
-template <typename T, int KM>
+// RR: also <r, r> of the current residual (the previous step's result) into
+// the rr slot, and the convergence flag rr <= tol2 * bb — the stopping test
+// of the previous step, taken here so that the update needs no reduction.
+template <typename T, int KM, bool RR>
 __global__ __launch_bounds__(256) void gcr_dots_kernel(GcrArgs<T> a0, const GcrArgs<T>* batch) {
   AMG_ARGS(GcrArgs<T>)
   const auto w = gl(a.w), Wb = gl(a.Wb), r = gl(a.r);
@@ -386,7 +405,14 @@ __global__ __launch_bounds__(256) void gcr_dots_kernel(GcrArgs<T> a0, const GcrA
   if (skip_rhs(a.red.flags, rhs)) return;
   const long ro = (long)rhs * a.n;
   const int k = a.k;
-  constexpr int NV = 2 * KM + 3;
+  constexpr int NV = 2 * KM + 3 + (RR ? 1 : 0);
+  // the scalars the last block needs, loaded now (their latency overlaps the sums)
+  double wwj[KM > 0 ? KM : 1], bbv = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int j = 0; j < KM; ++j) wwj[j] = scal[a.ww_slot + rhs * GCR_KMAX + (j < k ? j : 0)];
+    if (RR) bbv = scal[a.bb_slot + rhs];
+  }
   double acc[NV];
 #pragma unroll
   for (int j = 0; j < NV; ++j) acc[j] = 0.0;
@@ -407,17 +433,23 @@ __global__ __launch_bounds__(256) void gcr_dots_kernel(GcrArgs<T> a0, const GcrA
     acc[2 * KM] += (double)wi.x * wi.x + (double)wi.y * wi.y;
     acc[2 * KM + 1] += (double)wi.x * ri.x + (double)wi.y * ri.y;
     acc[2 * KM + 2] += (double)wi.x * ri.y - (double)wi.y * ri.x;
+    if (RR) acc[NV - 1] += (double)ri.x * ri.x + (double)ri.y * ri.y;
   }
   double tot[NV];
   if (grid_reduce<NV>(acc, a.red.part, a.red.ticket, rhs, tot) && threadIdx.x == 0) {
     double wwp = tot[2 * KM];
-    for (int j = 0; j < k; ++j) {
-      const double wwj = scal[a.ww_slot + rhs * GCR_KMAX + j];
-      const double s = wwj > 0.0 ? 1.0 / wwj : 0.0;
+#pragma unroll
+    for (int j = 0; j < KM; ++j) {
+      if (j >= k) break;
+      const double s = wwj[j] > 0.0 ? 1.0 / wwj[j] : 0.0;
       const double cr = tot[2 * j], ci = tot[2 * j + 1];
       scal[a.beta_slot + (rhs * GCR_KMAX + j) * 2] = cr * s;
       scal[a.beta_slot + (rhs * GCR_KMAX + j) * 2 + 1] = ci * s;
       wwp -= (cr * cr + ci * ci) * s;
+    }
+    if (RR) {
+      scal[a.rr_slot + rhs] = tot[NV - 1];
+      if (a.set_flags) gl(a.set_flags)[rhs] = (tot[NV - 1] <= a.tol2 * bbv) ? 1 : 0;
     }
     scal[a.ww_slot + rhs * GCR_KMAX + k] = wwp;
     const double s = wwp > 0.0 ? 1.0 / wwp : 0.0;
@@ -555,23 +587,32 @@ template void launch_gcr_maxpy<float>(float2*, float2*, const float2*, const flo
 
 template <typename T>
 void launch_gcr_dots(const cplx<T>* Wb, long dstride, const cplx<T>* w, const cplx<T>* r, int k, long n, int nrhs,
-                     RedArgs red, int beta_slot, int ww_slot, int alpha_slot, hipStream_t st) {
+                     RedArgs red, int beta_slot, int ww_slot, int alpha_slot, int rr_slot, int bb_slot, double tol2,
+                     int* set_flags, hipStream_t st) {
   GcrArgs<T> a = gcr_args<T>(n, nrhs, red);
   a.Wb = const_cast<cplx<T>*>(Wb); a.dstride = dstride; a.w = const_cast<cplx<T>*>(w);
   a.r = const_cast<cplx<T>*>(r); a.k = k;
   a.beta_slot = beta_slot; a.ww_slot = ww_slot; a.alpha_slot = alpha_slot;
+  a.rr_slot = rr_slot; a.bb_slot = bb_slot; a.tol2 = tol2; a.set_flags = set_flags;
   const dim3 grid(red_blocks(n), (unsigned)nrhs);
-  if (k <= 0) dispatch(gcr_dots_kernel<T, 0>, a, grid, dim3(256), st);
-  else if (k <= 2) dispatch(gcr_dots_kernel<T, 2>, a, grid, dim3(256), st);
-  else if (k <= 4) dispatch(gcr_dots_kernel<T, 4>, a, grid, dim3(256), st);
-  else if (k <= 8) dispatch(gcr_dots_kernel<T, 8>, a, grid, dim3(256), st);
-  else if (k <= 16) dispatch(gcr_dots_kernel<T, 16>, a, grid, dim3(256), st);
-  else dispatch(gcr_dots_kernel<T, 32>, a, grid, dim3(256), st);
+#define AMG_DOTS(RR)                                                                    \
+  if (k <= 0) dispatch(gcr_dots_kernel<T, 0, RR>, a, grid, dim3(256), st);             \
+  else if (k <= 2) dispatch(gcr_dots_kernel<T, 2, RR>, a, grid, dim3(256), st);        \
+  else if (k <= 4) dispatch(gcr_dots_kernel<T, 4, RR>, a, grid, dim3(256), st);        \
+  else if (k <= 8) dispatch(gcr_dots_kernel<T, 8, RR>, a, grid, dim3(256), st);        \
+  else if (k <= 16) dispatch(gcr_dots_kernel<T, 16, RR>, a, grid, dim3(256), st);      \
+  else dispatch(gcr_dots_kernel<T, 32, RR>, a, grid, dim3(256), st);
+  if (rr_slot >= 0) {
+    AMG_DOTS(true)
+  } else {
+    AMG_DOTS(false)
+  }
+#undef AMG_DOTS
 }
 template void launch_gcr_dots<double>(const double2*, long, const double2*, const double2*, int, long, int, RedArgs,
-                                      int, int, int, hipStream_t);
+                                      int, int, int, int, int, double, int*, hipStream_t);
 template void launch_gcr_dots<float>(const float2*, long, const float2*, const float2*, int, long, int, RedArgs, int,
-                                     int, int, hipStream_t);
+                                     int, int, int, int, double, int*, hipStream_t);
 
 template <typename T>
 void launch_gcr_update(cplx<T>* x, cplx<T>* r, const cplx<T>* z, const cplx<T>* w, long n, int nrhs, RedArgs red,
@@ -592,7 +633,20 @@ void launch_gcr_update2(cplx<T>* x, cplx<T>* r, const cplx<T>* zsrc, cplx<T>* Wb
   a.x = x; a.r = r; a.zsrc = zsrc; a.Wb = Wb; a.Zb = Zb; a.dstride = dstride; a.k = k;
   a.beta_slot = beta_slot; a.alpha_slot = alpha_slot; a.rr_slot = rr_slot; a.bb_slot = bb_slot; a.tol2 = tol2;
   a.set_flags = set_flags;
-  dispatch(gcr_update2_kernel<T>, a, dim3(red_blocks(n), (unsigned)nrhs), dim3(256), st);
+  const dim3 grid(red_blocks(n), (unsigned)nrhs);
+#define AMG_UPD2(RED)                                                                   \
+  if (k <= 0) dispatch(gcr_update2_kernel<T, 0, RED>, a, grid, dim3(256), st);         \
+  else if (k <= 2) dispatch(gcr_update2_kernel<T, 2, RED>, a, grid, dim3(256), st);    \
+  else if (k <= 4) dispatch(gcr_update2_kernel<T, 4, RED>, a, grid, dim3(256), st);    \
+  else if (k <= 8) dispatch(gcr_update2_kernel<T, 8, RED>, a, grid, dim3(256), st);    \
+  else if (k <= 16) dispatch(gcr_update2_kernel<T, 16, RED>, a, grid, dim3(256), st);  \
+  else dispatch(gcr_update2_kernel<T, 32, RED>, a, grid, dim3(256), st);
+  if (rr_slot >= 0) {
+    AMG_UPD2(true)
+  } else {
+    AMG_UPD2(false)
+  }
+#undef AMG_UPD2
 }
 template void launch_gcr_update2<double>(double2*, double2*, const double2*, double2*, double2*, long, int, long, int,
                                          RedArgs, int, int, int, int, double, int*, hipStream_t);

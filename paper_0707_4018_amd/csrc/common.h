@@ -106,9 +106,9 @@ struct Layout {
 // ---------------------------------------------------------------------------
 // Deterministic block + grid reductions of NV doubles per right-hand side.
 // Every block writes its partial sums to part[(rhs*NV + k)*nblk + block]; the
-// last block to arrive (atomic tickets per rhs) sums the partials in block
-// order and returns true with the totals in `tot` (valid in all threads).
-// The sum order is fixed, so results do not depend on scheduling.
+// last block to arrive (atomic tickets per rhs) sums the partials in a fixed
+// order and returns true with the totals in `tot` (valid in all threads), so
+// results do not depend on scheduling.
 // ---------------------------------------------------------------------------
 constexpr int RED_THREADS = 256;
 constexpr int RED_WAVES = RED_THREADS / 64;
@@ -137,25 +137,6 @@ __device__ __forceinline__ double wave_sum(double v) {
   return __hiloint2double(hi, lo);
 }
 
-template <int NV>
-__device__ __forceinline__ void block_sum(double (&v)[NV], double (*sh)[RED_WAVES]) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-  for (int k = 0; k < NV; ++k) {
-    const double s = wave_sum(v[k]);
-    if (lane == 0) sh[k][wave] = s;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < NV; ++k) {
-    double s = 0.0;
-#pragma unroll
-    for (int w = 0; w < RED_WAVES; ++w) s += sh[k][w];
-    v[k] = s;
-  }
-  __syncthreads();
-}
-
 // Publication without a release fence: on this chip each XCD has its own L2,
 // and an agent-scope release fence (__threadfence) writes back the whole L2
 // of the XCD — for a launch of ~1000 blocks that alone costs tens of
@@ -174,10 +155,13 @@ __device__ __forceinline__ void wait_stores_complete() {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
-// Arrival counters, two levels: blocks take a ticket of their group of
-// RED_GROUP blocks, the last of each group a ticket of the launch, so no
-// counter sees more than RED_GROUP atomics (~1000 atomics on one address
-// serialise for microseconds).  Each counter has a 64-byte line of its own.
+// Arrival counters: a launch of up to RED_ONE_LEVEL blocks takes tickets of
+// one counter (one atomic round trip); a larger one takes two levels — a
+// ticket of the block's group of RED_GROUP blocks, then the last of each group
+// a ticket of the launch — so no counter sees more than RED_GROUP atomics
+// (~1000 atomics on one address serialise for ~8 us).  Each counter has a
+// 64-byte line of its own.
+constexpr int RED_ONE_LEVEL = 64;
 constexpr int RED_GROUP = 32;
 constexpr int TICKET_PAD = 16;
 constexpr int RED_BLOCKS_LIMIT = 1024;
@@ -192,41 +176,65 @@ __device__ __forceinline__ bool take_ticket(unsigned* t, unsigned n) {
 // the block that arrives last in the launch (for right-hand side rhs).
 __device__ __forceinline__ bool last_block(unsigned* ticket, int rhs) {
   unsigned* tk = ticket + (long)rhs * TICKETS_PER_RHS;
-  const int nblk = gridDim.x, grp = blockIdx.x / RED_GROUP;
+  const int nblk = gridDim.x;
+  if (nblk <= RED_ONE_LEVEL) return take_ticket(tk, (unsigned)nblk);
+  const int grp = blockIdx.x / RED_GROUP;
   const int ngrp = (nblk + RED_GROUP - 1) / RED_GROUP;
   const int gsize = (nblk - grp * RED_GROUP < RED_GROUP) ? nblk - grp * RED_GROUP : RED_GROUP;
   if (!take_ticket(tk + (1 + grp) * TICKET_PAD, (unsigned)gsize)) return false;
-  return ngrp == 1 || take_ticket(tk, (unsigned)ngrp);
+  return take_ticket(tk, (unsigned)ngrp);
 }
 
 template <int NV>
 __device__ bool grid_reduce(double (&v)[NV], double* part, unsigned* ticket, int rhs,
                             double (&tot)[NV]) {
+  static_assert(NV <= RED_THREADS, "one thread per quantity at least");
   __shared__ double sh[NV][RED_WAVES];
   __shared__ int is_last;
   const int nblk = gridDim.x;
-  block_sum<NV>(v, sh);
-  if (threadIdx.x == 0) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-    for (int k = 0; k < NV; ++k)
-      __hip_atomic_store(&part[((long)rhs * NV + k) * nblk + blockIdx.x], v[k], __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
-    wait_stores_complete();
-    is_last = last_block(ticket, rhs);
+  for (int k = 0; k < NV; ++k) {
+    const double s = wave_sum(v[k]);
+    if (lane == 0) sh[k][wave] = s;
   }
   __syncthreads();
-  if (!is_last) return false;
-  double s[NV];
+  // thread q publishes the block's sum of quantity q
+  if (threadIdx.x < NV) {
+    double s = 0.0;
 #pragma unroll
-  for (int k = 0; k < NV; ++k) s[k] = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
-#pragma unroll
-    for (int k = 0; k < NV; ++k)
-      s[k] += __hip_atomic_load(&part[((long)rhs * NV + k) * nblk + b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int w = 0; w < RED_WAVES; ++w) s += sh[threadIdx.x][w];
+    __hip_atomic_store(&part[((long)rhs * NV + threadIdx.x) * nblk + blockIdx.x], s, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    wait_stores_complete();
   }
-  block_sum<NV>(s, sh);
+  __syncthreads();
+  if (threadIdx.x == 0) is_last = last_block(ticket, rhs);
+  __syncthreads();
+  if (!is_last) return false;
+  // thread t sums quantity q = t mod NV over every G-th block from
+  // g = t / NV (G = blockDim / NV groups: few loads per thread, all
+  // independent), then one wave per quantity adds the G group sums
+  __shared__ double shg[RED_THREADS];
+  constexpr int G = RED_THREADS / NV;
+  const int q = threadIdx.x % NV, g = threadIdx.x / NV;
+  if (g < G) {
+    const double* pq = part + ((long)rhs * NV + q) * nblk;
+    double s = 0.0;
+    for (int b = g; b < nblk; b += G) s += __hip_atomic_load(pq + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    shg[g * NV + q] = s;
+  }
+  __syncthreads();
+  __shared__ double shtot[NV];
+  for (int qq = wave; qq < NV; qq += RED_WAVES) {  // one wave per quantity
+    double s = 0.0;
+    for (int gg = lane; gg < G; gg += 64) s += shg[gg * NV + qq];
+    s = wave_sum(s);
+    if (lane == 0) shtot[qq] = s;
+  }
+  __syncthreads();
 #pragma unroll
-  for (int k = 0; k < NV; ++k) tot[k] = s[k];
+  for (int k = 0; k < NV; ++k) tot[k] = shtot[k];
   return true;
 }
 

@@ -88,6 +88,7 @@ void launch_coarse_mrhs(const CoarseArgs<float>& a, int dagger, int epi, hipStre
 template <typename T>
 void launch_gcr16_apply_dots(const CoarseArgs<T>& a, const cplx<T>* r, const cplx<T>* Wb, long dstride, int k,
                              int beta_slot, int ww_slot, int alpha_slot, hipStream_t st);
+// (rr_slot < 0: no <r, r> reduction and no flag)
 template <typename T>
 void launch_gcr_update2(cplx<T>* x, cplx<T>* r, const cplx<T>* zsrc, cplx<T>* Wb, cplx<T>* Zb, long dstride, int k,
                         long n, int nrhs, RedArgs red, int beta_slot, int alpha_slot, int rr_slot, int bb_slot,
@@ -139,10 +140,12 @@ void launch_mr_update(cplx<T>* x, cplx<T>* r_out, const cplx<T>* r_in, const cpl
 template <typename T>
 void launch_norm2(const cplx<T>* v, long n, int nrhs, RedArgs red, hipStream_t st);
 // GCR building blocks; directions stored contiguously: W_j = Wb + j * dstride
-// one-reduction GCR orthogonalisation: betas, <w',w'> and alpha (then launch_gcr_update2)
+// one-reduction GCR orthogonalisation: betas, <w',w'> and alpha (then launch_gcr_update2);
+// rr_slot >= 0: also <r, r> of the current residual and the flag rr <= tol2 * bb
 template <typename T>
 void launch_gcr_dots(const cplx<T>* Wb, long dstride, const cplx<T>* w, const cplx<T>* r, int k, long n, int nrhs,
-                     RedArgs red, int beta_slot, int ww_slot, int alpha_slot, hipStream_t st);
+                     RedArgs red, int beta_slot, int ww_slot, int alpha_slot, int rr_slot, int bb_slot, double tol2,
+                     int* set_flags, hipStream_t st);
 template <typename T>
 void launch_gcr_mdot(const cplx<T>* Wb, long dstride, const cplx<T>* w, int k, long n, int nrhs,
                      RedArgs red, int beta_slot, int ww_slot, hipStream_t st);

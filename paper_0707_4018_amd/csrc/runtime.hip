@@ -444,10 +444,21 @@ void level_gcr(Solver& S, int l, int lstop, const cplx<T>* b, cplx<T>* x, int nr
   launch_fill<T>(r, b, n, nrhs, st);
   launch_norm2<T>(b, n, nrhs, S.sc.red(L.gs.bb), st);
   launch_set_flags(flags, S.outer_flags, S.sc.scal.as<double>(), L.gs.bb, L.gs.bb, tol2 >= 1.0 ? 1.0 : 0.0, nrhs, st);
+  // Coarsest level in the three-launch form: the residual norm and stopping
+  // flag of each step are taken by the next step's sums kernel, so the
+  // update needs no reduction; before a restart the recursive residual is
+  // checked explicitly.  The stopping decisions are those of the
+  // step-by-step form.
+  const bool lag = S.gcr_dots && !precond && !(!L.fine && L.dof == 16 && S.fused_gcr);
   for (int it = 0; it < maxiter; ++it) {
     const int k = it % m;
-    if (k == 0 && it > 0)
+    if (k == 0 && it > 0) {
+      if (lag) {
+        launch_norm2<T>(r, n, nrhs, S.sc.red(L.gs.rr, flags), st);
+        launch_set_flags(flags, S.outer_flags, S.sc.scal.as<double>(), L.gs.rr, L.gs.bb, tol2, nrhs, st);
+      }
       op_apply<T>(S, l, 0, EPI_RESID, x, r, b, nullptr, nrhs, S.sc.red(0, flags), st);
+    }
     cplx<T>* Wk = Wb + (long)k * dstride;
     cplx<T>* Zk = Zb + (long)k * dstride;
     if (!L.fine && L.dof == 16 && S.fused_gcr) {
@@ -477,9 +488,11 @@ void level_gcr(Solver& S, int l, int lstop, const cplx<T>* b, cplx<T>* x, int nr
         z = Zk;
       }
       op_apply<T>(S, l, 0, EPI_PLAIN, z, Wk, nullptr, nullptr, nrhs, S.sc.red(0, flags), st);
-      launch_gcr_dots<T>(Wb, dstride, Wk, r, k, n, nrhs, S.sc.red(0, flags), L.gs.beta, L.gs.ww, L.gs.alpha, st);
-      launch_gcr_update2<T>(x, r, z, Wb, Zb, dstride, k, n, nrhs, S.sc.red(0, flags), L.gs.beta, L.gs.alpha, L.gs.rr,
-                            L.gs.bb, tol2, flags, st);
+      const bool check_here = lag && !(k == 0 && it > 0);
+      launch_gcr_dots<T>(Wb, dstride, Wk, r, k, n, nrhs, S.sc.red(0, flags), L.gs.beta, L.gs.ww, L.gs.alpha,
+                         check_here ? L.gs.rr : -1, L.gs.bb, tol2, flags, st);
+      launch_gcr_update2<T>(x, r, z, Wb, Zb, dstride, k, n, nrhs, S.sc.red(0, flags), L.gs.beta, L.gs.alpha,
+                            lag ? -1 : L.gs.rr, L.gs.bb, tol2, flags, st);
       if (!recording && (it + 1) % check == 0 && it + 1 < maxiter && S.sc.all_flags(L.flag_off, nrhs, st)) break;
       continue;
     }
