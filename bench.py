@@ -77,7 +77,7 @@ def source():
 
 # solver parameters shared by the GPU run and the oracle sample
 PARAMS = dict(blocks=[(4, 4), (2, 2)], nvec=[8, 8], nu_pre=2, nu_post=2, omega=0.8,
-              coarse_tol=0.2, coarse_maxiter=100, coarse_restart=16, outer_restart=16,
+              coarse_tol=0.2, coarse_maxiter=100, coarse_restart=10, outer_restart=16,
               kcycle_tol=0.1, kcycle_maxiter=8)
 
 
@@ -169,7 +169,7 @@ def gen_batch_config(i):
 def batch_bench(amg, torch, bfields, mixed=True):
     insts = [batch_instance(i) for i in range(NBATCH)]
     params = amg.MGParams(blocks=[(4, 4), (4, 4)], nvec=[8, 8], nu_pre=2, nu_post=2, omega=0.8, coarse_tol=0.2,
-                          coarse_maxiter=100, coarse_restart=16, outer_restart=16, kcycle_tol=0.1, kcycle_maxiter=8,
+                          coarse_maxiter=100, coarse_restart=10, outer_restart=16, kcycle_tol=0.1, kcycle_maxiter=8,
                           inner_prec=amg.F32 if mixed else amg.F64, p_bf16=mixed)
     solvers, chis = [], []
     torch.cuda.synchronize()

@@ -219,7 +219,7 @@ __global__ __launch_bounds__(256) void gcr_mdot_kernel(GcrArgs<T> a0, const GcrA
     }
   }
   double tot[2 * KM];
-  if (grid_reduce<2 * KM>(acc, a.red.part, a.red.ticket, rhs, tot) && threadIdx.x == 0) {
+  if (grid_reduce<2 * KM>(acc, a.red.part, a.red.ticket, rhs, tot, 2 * k, 2 * KM) && threadIdx.x == 0) {
     for (int j = 0; j < k; ++j) {
       const double ww = scal[a.ww_slot + rhs * GCR_KMAX + j];
       const double s = ww > 0.0 ? 1.0 / ww : 0.0;
@@ -436,7 +436,8 @@ __global__ __launch_bounds__(256) void gcr_dots_kernel(GcrArgs<T> a0, const GcrA
     if (RR) acc[NV - 1] += (double)ri.x * ri.x + (double)ri.y * ri.y;
   }
   double tot[NV];
-  if (grid_reduce<NV>(acc, a.red.part, a.red.ticket, rhs, tot) && threadIdx.x == 0) {
+  // slots of directions j >= k are zero
+  if (grid_reduce<NV>(acc, a.red.part, a.red.ticket, rhs, tot, 2 * k, 2 * KM) && threadIdx.x == 0) {
     double wwp = tot[2 * KM];
 #pragma unroll
     for (int j = 0; j < KM; ++j) {
@@ -599,7 +600,10 @@ void launch_gcr_dots(const cplx<T>* Wb, long dstride, const cplx<T>* w, const cp
   if (k <= 0) dispatch(gcr_dots_kernel<T, 0, RR>, a, grid, dim3(256), st);             \
   else if (k <= 2) dispatch(gcr_dots_kernel<T, 2, RR>, a, grid, dim3(256), st);        \
   else if (k <= 4) dispatch(gcr_dots_kernel<T, 4, RR>, a, grid, dim3(256), st);        \
+  else if (k <= 6) dispatch(gcr_dots_kernel<T, 6, RR>, a, grid, dim3(256), st);        \
   else if (k <= 8) dispatch(gcr_dots_kernel<T, 8, RR>, a, grid, dim3(256), st);        \
+  else if (k <= 10) dispatch(gcr_dots_kernel<T, 10, RR>, a, grid, dim3(256), st);      \
+  else if (k <= 12) dispatch(gcr_dots_kernel<T, 12, RR>, a, grid, dim3(256), st);      \
   else if (k <= 16) dispatch(gcr_dots_kernel<T, 16, RR>, a, grid, dim3(256), st);      \
   else dispatch(gcr_dots_kernel<T, 32, RR>, a, grid, dim3(256), st);
   if (rr_slot >= 0) {
@@ -638,7 +642,10 @@ void launch_gcr_update2(cplx<T>* x, cplx<T>* r, const cplx<T>* zsrc, cplx<T>* Wb
   if (k <= 0) dispatch(gcr_update2_kernel<T, 0, RED>, a, grid, dim3(256), st);         \
   else if (k <= 2) dispatch(gcr_update2_kernel<T, 2, RED>, a, grid, dim3(256), st);    \
   else if (k <= 4) dispatch(gcr_update2_kernel<T, 4, RED>, a, grid, dim3(256), st);    \
+  else if (k <= 6) dispatch(gcr_update2_kernel<T, 6, RED>, a, grid, dim3(256), st);    \
   else if (k <= 8) dispatch(gcr_update2_kernel<T, 8, RED>, a, grid, dim3(256), st);    \
+  else if (k <= 10) dispatch(gcr_update2_kernel<T, 10, RED>, a, grid, dim3(256), st);  \
+  else if (k <= 12) dispatch(gcr_update2_kernel<T, 12, RED>, a, grid, dim3(256), st);  \
   else if (k <= 16) dispatch(gcr_update2_kernel<T, 16, RED>, a, grid, dim3(256), st);  \
   else dispatch(gcr_update2_kernel<T, 32, RED>, a, grid, dim3(256), st);
   if (rr_slot >= 0) {

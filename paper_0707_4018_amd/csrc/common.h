@@ -185,9 +185,12 @@ __device__ __forceinline__ bool last_block(unsigned* ticket, int rhs) {
   return take_ticket(tk, (unsigned)ngrp);
 }
 
+// Quantities z0 <= q < z1 are known to be zero in every block (unused slots
+// of a template-sized set): they are neither summed nor published, and their
+// totals are zero.
 template <int NV>
 __device__ bool grid_reduce(double (&v)[NV], double* part, unsigned* ticket, int rhs,
-                            double (&tot)[NV]) {
+                            double (&tot)[NV], int z0 = NV, int z1 = NV) {
   static_assert(NV <= RED_THREADS, "one thread per quantity at least");
   __shared__ double sh[NV][RED_WAVES];
   __shared__ int is_last;
@@ -195,12 +198,13 @@ __device__ bool grid_reduce(double (&v)[NV], double* part, unsigned* ticket, int
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
+    if (k >= z0 && k < z1) continue;  // uniform
     const double s = wave_sum(v[k]);
     if (lane == 0) sh[k][wave] = s;
   }
   __syncthreads();
   // thread q publishes the block's sum of quantity q
-  if (threadIdx.x < NV) {
+  if (threadIdx.x < NV && !(threadIdx.x >= z0 && threadIdx.x < z1)) {
     double s = 0.0;
 #pragma unroll
     for (int w = 0; w < RED_WAVES; ++w) s += sh[threadIdx.x][w];
@@ -218,15 +222,28 @@ __device__ bool grid_reduce(double (&v)[NV], double* part, unsigned* ticket, int
   __shared__ double shg[RED_THREADS];
   constexpr int G = RED_THREADS / NV;
   const int q = threadIdx.x % NV, g = threadIdx.x / NV;
-  if (g < G) {
-    const double* pq = part + ((long)rhs * NV + q) * nblk;
+  if (g < G && !(q >= z0 && q < z1)) {
     double s = 0.0;
-    for (int b = g; b < nblk; b += G) s += __hip_atomic_load(pq + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    double* pq = part + ((long)rhs * NV + q) * nblk;
+    for (int b0 = g; b0 < nblk; b0 += 16 * G) {
+      double v[16];  // up to 16 loads in flight, then the adds in block order
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int b = b0 + u * G;
+        v[u] = (b < nblk) ? __hip_atomic_load(pq + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) s += v[u];
+    }
     shg[g * NV + q] = s;
   }
   __syncthreads();
   __shared__ double shtot[NV];
   for (int qq = wave; qq < NV; qq += RED_WAVES) {  // one wave per quantity
+    if (qq >= z0 && qq < z1) {
+      if (lane == 0) shtot[qq] = 0.0;
+      continue;
+    }
     double s = 0.0;
     for (int gg = lane; gg < G; gg += 64) s += shg[gg * NV + qq];
     s = wave_sum(s);
