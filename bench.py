@@ -41,8 +41,8 @@ TOL = 1e-10
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the roofline kernel from rocprofv3 counters (FETCH_SIZE x 2,
 # calibrated on a 256 MiB device copy, + WRITE_SIZE), taken on the current kernel
-# (None: the kernel changed since the counters were taken)
-ROOF_TRAFFIC = None
+# (None whenever the kernel changes, until the counters are taken again)
+ROOF_TRAFFIC = 43560653   # 42539.7 KiB: FETCH 20948.8 KiB x 2 + WRITE 642.1 KiB
 WORKLOADS = json.load(open(os.path.join(ROOT, "synth", "workloads.json")))
 
 
