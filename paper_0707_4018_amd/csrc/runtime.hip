@@ -582,7 +582,12 @@ void build_transfer(Solver& S, int l, hipStream_t st) {
   C.lay32 = C.lay64;
   const TransferGeom tg = tgeom(S, l, AMG_F64);
   const long psz = (long)F.V * F.dof * nv;  // P entries
-  F.P64.ensure(psz * sizeof(double2));
+  // buffers are sized for the final number of vectors on first use: the
+  // adaptive setup rebuilds the transfer once per added vector, and growing
+  // a buffer (hipFree + hipMalloc) synchronises the device every time
+  const int nvm = std::max(nv, F.nv_max);
+  const long psz_max = (long)F.V * F.dof * nvm;
+  F.P64.ensure(psz_max * sizeof(double2));
   int* err = S.sc.flags.as<int>() + S.flags_base;  // scratch flag
   HIPC(hipMemsetAsync(err, 0, sizeof(int), st));
   launch_orthonormalise(F.P64.as<double2>(), F.vecs.as<double2>(), tg, err, st);
@@ -593,27 +598,33 @@ void build_transfer(Solver& S, int l, hipStream_t st) {
   if (S.p.inner_prec == AMG_F32) {
     if (S.p.p_bf16) {
       launch_p_roundtrip_bf16(F.P64.as<double2>(), psz, st);
-      F.Pbf.ensure(psz * sizeof(bf16x2));
+      F.Pbf.ensure(psz_max * sizeof(bf16x2));
       launch_p_convert(F.Pbf.p, P_BF16, F.P64.as<double2>(), psz, st);
     } else {
-      F.P32.ensure(psz * sizeof(float2));
+      F.P32.ensure(psz_max * sizeof(float2));
       launch_p_convert(F.P32.p, P_F32, F.P64.as<double2>(), psz, st);
     }
   }
   // Galerkin product column by column: E = unit coarse fields, F = P E,
   // S = split(A F), R = P^dag S, scattered into Y.  Mass matrix likewise.
   const int nc = C.dof, ndir = F.ndir();
+  const int ncm = 2 * nvm;
   const long ysz = C.V * ndir * (long)nc * nc;
-  C.Y64.ensure(ysz * sizeof(double2));
-  C.M64.ensure(C.V * (long)nc * nc * sizeof(double2));
+  C.Y64.ensure(C.V * ndir * (long)ncm * ncm * sizeof(double2));
+  C.M64.ensure(C.V * (long)ncm * ncm * sizeof(double2));
   const long fper = F.per_rhs();
-  int chunk = nc;
   const long budget = 1L << 31;  // bytes for the split outputs
-  while (chunk > 1 && (long)chunk * ndir * fper * 16 > budget) chunk = (chunk + 1) / 2;
-  S.tE.ensure((size_t)chunk * C.V * nc * sizeof(double2));
-  S.tF.ensure((size_t)chunk * fper * sizeof(double2));
-  S.tS.ensure((size_t)chunk * ndir * fper * sizeof(double2));
-  S.tR.ensure((size_t)chunk * ndir * C.V * nc * sizeof(double2));
+  auto chunk_of = [&](int c) {
+    int ch = c;
+    while (ch > 1 && (long)ch * ndir * fper * 16 > budget) ch = (ch + 1) / 2;
+    return ch;
+  };
+  const int chunk = chunk_of(nc);
+  const size_t chm = (size_t)std::max(chunk, chunk_of(ncm));
+  S.tE.ensure(chm * C.V * ncm * sizeof(double2));
+  S.tF.ensure(chm * fper * sizeof(double2));
+  S.tS.ensure(chm * ndir * fper * sizeof(double2));
+  S.tR.ensure(chm * ndir * C.V * ncm * sizeof(double2));
   double2* E = S.tE.as<double2>();
   double2* Fv = S.tF.as<double2>();
   double2* Sv = S.tS.as<double2>();
@@ -643,7 +654,7 @@ void build_transfer(Solver& S, int l, hipStream_t st) {
     launch_galerkin_scatter(C.M64.as<double2>(), Rv, C.V, nc, 1, t0, ch, st);
   }
   if (S.p.inner_prec == AMG_F32) {
-    C.Y32.ensure(ysz * sizeof(float2));
+    C.Y32.ensure(C.V * ndir * (long)ncm * ncm * sizeof(float2));
     launch_p_convert(C.Y32.p, P_F32, C.Y64.as<double2>(), ysz, st);
   }
 }
