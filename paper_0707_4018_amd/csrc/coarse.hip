@@ -9,6 +9,8 @@
 // that the threads of one site (one per row) read consecutive addresses.
 // D_hat^dagger = Gamma_5 D_hat Gamma_5 with Gamma_5 = diag(+1_{N_v}, -1_{N_v})
 // because P commutes with gamma_5.
+#include <type_traits>
+
 #include "common.h"
 #include "kernels.h"
 #include "dispatch.h"
@@ -49,7 +51,8 @@ __global__ __launch_bounds__(256) void coarse_kernel(CoarseArgs<T> a0, const Coa
   const long V = a.g.V;
   const long total = V * nc;
   const long ro = (long)rhs * total;
-  const cplx<T>* __restrict__ pin = a.in + ro;
+  gptr<const cplx<T>> __restrict__ pin = gl(a.in) + ro;
+  gptr<const cplx<T>> __restrict__ Y = gl(a.Y);
   double acc3[3] = {0.0, 0.0, 0.0};
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
     const long site = i / nc;
@@ -59,16 +62,24 @@ __global__ __launch_bounds__(256) void coarse_kernel(CoarseArgs<T> a0, const Coa
     cplx<T> acc = mk<T>(0, 0);
     for (int k = 0; k < ndir; ++k) {
       const long nb = (k == 0) ? site : neighbour(site, x, a.g.dims, nd, k - 1);
-      const cplx<T>* __restrict__ Yk = a.Y + ((site * ndir + k) * nc) * (long)nc + row;
-      const cplx<T>* __restrict__ e = pin + nb * nc;
-      if (NC > 0) {
-#pragma unroll 8
-        for (int col = 0; col < nc; ++col) {
-          cplx<T> v = e[col];
-          if (DAG && col >= nc / 2) v = mk<T>(-v.x, -v.y);
-          cfma<T>(acc, Yk[(long)col * nc], v);
+      gptr<const cplx<T>> __restrict__ Yk = Y + ((site * ndir + k) * nc) * (long)nc + row;
+      gptr<const cplx<T>> __restrict__ e = pin + nb * nc;
+      if (NC > 0 && NC <= 16) {
+        // all loads of the direction in flight at once
+        cplx<T> ev[NC > 0 && NC <= 16 ? NC : 1], yv[NC > 0 && NC <= 16 ? NC : 1];
+#pragma unroll
+        for (int col = 0; col < NC; ++col) {
+          ev[col] = e[col];
+          yv[col] = Yk[(long)col * NC];
+        }
+#pragma unroll
+        for (int col = 0; col < NC; ++col) {
+          cplx<T> v = ev[col];
+          if (DAG && col >= NC / 2) v = mk<T>(-v.x, -v.y);
+          cfma<T>(acc, yv[col], v);
         }
       } else {
+#pragma unroll 4
         for (int col = 0; col < nc; ++col) {
           cplx<T> v = e[col];
           if (DAG && col >= nc / 2) v = mk<T>(-v.x, -v.y);
@@ -78,9 +89,9 @@ __global__ __launch_bounds__(256) void coarse_kernel(CoarseArgs<T> a0, const Coa
     }
     if (DAG && row >= nc / 2) acc = mk<T>(-acc.x, -acc.y);
     const cplx<T> c = pin[i];
-    if (EPI == EPI_RESID) acc = csub<T>(a.b[ro + i], acc);
-    a.out[ro + i] = acc;
-    if (a.copy_out) a.copy_out[ro + i] = c;
+    if (EPI == EPI_RESID) acc = csub<T>(gl(a.b)[ro + i], acc);
+    gl(a.out)[ro + i] = acc;
+    if (a.copy_out) gl(a.copy_out)[ro + i] = c;
     if (EPI == EPI_MRDOT) {
       acc3[0] += (double)acc.x * c.x + (double)acc.y * c.y;
       acc3[1] += (double)acc.x * c.y - (double)acc.y * c.x;
@@ -800,6 +811,21 @@ void launch_coarse(const CoarseArgs<T>& a, int dagger, int epi, hipStream_t st) 
 #undef AMG_C16N
   } else if (a.g.nc == 48) {
     if (dagger) { AMG_C_EPI(48, 1) } else { AMG_C_EPI(48, 0) }
+  } else if (std::is_same<T, double>::value && !dagger && (epi == EPI_PLAIN || epi == EPI_RESID) &&
+             a.g.nc >= 2 && a.g.nc <= 14 && a.g.nc % 2 == 0) {
+    // the partial hierarchies of the adaptive setup (2 .. 14 coarse dof, FP64)
+#define AMG_CP(NC) \
+  if (epi == EPI_RESID) { AMG_C(NC, 0, EPI_RESID); } else { AMG_C(NC, 0, EPI_PLAIN); }
+    switch (a.g.nc) {
+      case 2: AMG_CP(2) break;
+      case 4: AMG_CP(4) break;
+      case 6: AMG_CP(6) break;
+      case 8: AMG_CP(8) break;
+      case 10: AMG_CP(10) break;
+      case 12: AMG_CP(12) break;
+      default: AMG_CP(14) break;
+    }
+#undef AMG_CP
   } else {
     if (dagger) { AMG_C_EPI(0, 1) } else { AMG_C_EPI(0, 0) }
   }
