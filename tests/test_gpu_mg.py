@@ -271,3 +271,22 @@ def test_four_dimensional_transfers_match_oracle(nrhs):
     for i in range(nrhs):
         assert max_rel_err(rc[i], P.restrict(r[i].reshape(A.V, 12))) < 1e-12
         assert max_rel_err(pe[i].reshape(A.V, 12), P.prolong(e[i])) < 1e-12
+
+
+@pytest.mark.parametrize("L1,L2", [(128, 128), (132, 128), (160, 160), (512, 512)])
+def test_mr_reductions_across_grid_sizes(L1, L2):
+    """MR on the fine level needs <p, r> and <p, p> over the whole lattice in
+    every step: 64 blocks (one ticket level), 66 and 100 blocks (two levels,
+    ragged last group) and the 1024-block cap; bitwise reproducible."""
+    import paper_0707_4018_amd as amg
+    print(f"fine MR reductions {L1}x{L2}", flush=True)
+    U = u1_config(L1, L2, sweeps=10)
+    A = mg.wilson_stencil(U, 0.05)
+    g = amg.Gauge(dev(U), 0.05)
+    S = amg.Solver(g, amg.MGParams(blocks=[(4, 4)], nvec=[4]), nullvecs=[dev(vectors(4, A.V, 2, 11))])
+    b = synth.gaussian_field((1, A.V, 2, 1), synth.rng_for(12, L1, L2))
+    x1 = host(S.mr(0, 3, dev(b)))
+    x2 = host(S.mr(0, 3, dev(b)))
+    assert np.array_equal(x1, x2)
+    xo = mg.mr(A, b[0].reshape(A.V, 2), 3, 0.8)[0]
+    assert max_rel_err(x1.reshape(-1), xo.reshape(-1)) < 1e-12
