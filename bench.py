@@ -42,7 +42,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the roofline kernel from rocprofv3 counters (FETCH_SIZE x 2,
 # calibrated on a 256 MiB device copy, + WRITE_SIZE), taken on the current kernel
 # (None whenever the kernel changes, until the counters are taken again)
-ROOF_TRAFFIC = 43560653   # 42539.7 KiB: FETCH 20948.8 KiB x 2 + WRITE 642.1 KiB
+ROOF_TRAFFIC = None
 WORKLOADS = json.load(open(os.path.join(ROOT, "synth", "workloads.json")))
 
 
@@ -655,8 +655,9 @@ def main():
         "solves": recs,
     }
 
-    # roofline kernel: the level-1 block stencil with the MR epilogue (64^2 sites x 16 dof,
-    # FP32), the longest-running apply of the solve (the shorter GCR kernels of the
+    # roofline kernel: the level-1 block stencil of the MR smoother (64^2 sites x 16 dof,
+    # FP32; per-block sums of <p, r>, <p, p> in its epilogue, which the update kernel
+    # combines), the longest-running apply of the solve (the shorter GCR kernels of the
     # coarsest level are latency-bound); every launch in one more full step is timed by
     # a pair of HIP events that the launch stamps at the kernel's start and end
     log("kernel timing pass")
@@ -667,7 +668,8 @@ def main():
     achieved = bytes_launch / avg_s / 1e9
     out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": ROOF_TRAFFIC,
-                       "kernel": "coarse16_kernel<float, MR epilogue> (level-1 block stencil, 4096 sites x 16 dof)",
+                       "kernel": "coarse16_kernel<float, MR partial-sum epilogue> (level-1 block stencil, "
+                                 "4096 sites x 16 dof)",
                        "bytes_per_launch": bytes_launch, "avg_launch_us": round(avg_s * 1e6, 3),
                        "launches": prof[1]}
 

@@ -104,18 +104,30 @@ struct MrArgs {
   cplx<T>* r_out;
   const cplx<T>* r_in;
   const cplx<T>* p;
-  const double* alpha;
+  const double* alpha;  // [2 rhs] (re, im), or nullptr: from the partial sums below
   long n;
   int first, update_r;
   const int* flags;
   int nrhs;
+  const double* part;   // per-block <p, r> (re, im), <p, p> of the stencil launch (EPI_MRPART)
+  int nblk;             // its number of blocks
+  double omega;
 };
 template <typename T>
 __global__ void mr_update_kernel(MrArgs<T> a0, const MrArgs<T>* batch) {
   AMG_ARGS(MrArgs<T>)
   const int rhs = blockIdx.y;
   if (skip_rhs(a.flags, rhs)) return;
-  const cplx<T> al = mk<T>((T)gl(a.alpha)[2 * rhs], (T)gl(a.alpha)[2 * rhs + 1]);
+  cplx<T> al;
+  if (a.alpha != nullptr) {
+    al = mk<T>((T)gl(a.alpha)[2 * rhs], (T)gl(a.alpha)[2 * rhs + 1]);
+  } else {
+    // alpha = omega <p, r> / <p, p> from the stencil's per-block sums
+    double tot[3];
+    sum_partials<3>(a.part, a.nblk, rhs, tot);
+    const double s = tot[2] > 0.0 ? a.omega / tot[2] : 0.0;
+    al = mk<T>((T)(s * tot[0]), (T)(s * tot[1]));
+  }
   const long ro = (long)rhs * a.n;
   if (sizeof(T) == 4 && (a.n & 1) == 0) {
     // FP32: two complex numbers per 16-byte access
@@ -526,12 +538,15 @@ void launch_p_roundtrip_bf16(double2* P, long n, hipStream_t st) {
 
 template <typename T>
 void launch_mr_update(cplx<T>* x, cplx<T>* r_out, const cplx<T>* r_in, const cplx<T>* p, const double* alpha, long n,
-                      int nrhs, int first, int update_r, const int* flags, hipStream_t st) {
-  MrArgs<T> a{x, r_out, r_in, p, alpha, n, first, update_r, flags, nrhs};
+                      int nrhs, int first, int update_r, const int* flags, hipStream_t st, const double* part,
+                      int nblk, double omega) {
+  MrArgs<T> a{x, r_out, r_in, p, alpha, n, first, update_r, flags, nrhs, part, nblk, omega};
   dispatch(mr_update_kernel<T>, a, dim3(nblocks(n, 1L << 20), (unsigned)nrhs), dim3(256), st);
 }
-template void launch_mr_update<double>(double2*, double2*, const double2*, const double2*, const double*, long, int, int, int, const int*, hipStream_t);
-template void launch_mr_update<float>(float2*, float2*, const float2*, const float2*, const double*, long, int, int, int, const int*, hipStream_t);
+template void launch_mr_update<double>(double2*, double2*, const double2*, const double2*, const double*, long, int, int,
+                                       int, const int*, hipStream_t, const double*, int, double);
+template void launch_mr_update<float>(float2*, float2*, const float2*, const float2*, const double*, long, int, int,
+                                      int, const int*, hipStream_t, const double*, int, double);
 
 template <typename T>
 void launch_norm2(const cplx<T>* v, long n, int nrhs, RedArgs red, hipStream_t st) {

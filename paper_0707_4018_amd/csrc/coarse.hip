@@ -227,7 +227,7 @@ __global__ __launch_bounds__(256) void coarse16_kernel(CoarseArgs<T> a0, const C
     for (int i = 0; i < K::R; ++i) {
       c[i] = mk<T>(0, 0);
       bv[i] = mk<T>(0, 0);
-      if (cg == 0 && (EPI == EPI_MRDOT || copy)) c[i] = pin[o + i];
+      if (cg == 0 && (EPI == EPI_MRDOT || EPI == EPI_MRPART || copy)) c[i] = pin[o + i];
       if (cg == 0 && EPI == EPI_RESID) bv[i] = pb[o + i];
     }
     cplx<T> acc[K::R];
@@ -241,7 +241,7 @@ __global__ __launch_bounds__(256) void coarse16_kernel(CoarseArgs<T> a0, const C
         if (EPI == EPI_RESID) v = csub<T>(bv[i], v);
         pout[o + i] = v;
         if (copy) pcopy[o + i] = c[i];
-        if (EPI == EPI_MRDOT) {
+        if (EPI == EPI_MRDOT || EPI == EPI_MRPART) {
           acc3[0] += (double)v.x * c[i].x + (double)v.y * c[i].y;
           acc3[1] += (double)v.x * c[i].y - (double)v.y * c[i].x;
           acc3[2] += (double)v.x * v.x + (double)v.y * v.y;
@@ -251,6 +251,7 @@ __global__ __launch_bounds__(256) void coarse16_kernel(CoarseArgs<T> a0, const C
       }
     }
   }
+  if (EPI == EPI_MRPART) block_partials<3>(acc3, a.red.part, rhs);
   if (EPI == EPI_MRDOT) {
     double tot[3];
     if (grid_reduce<3>(acc3, a.red.part, a.red.ticket, rhs, tot) && threadIdx.x == 0) finalize_mr(tot, a.red, rhs);
@@ -870,6 +871,12 @@ inline unsigned nblocks(long n, long cap = 1L << 20) {
 
 }  // namespace
 
+int coarse16_red_blocks(long V) {
+  long nb = (V + 3) / 4;
+  if (nb > red_block_cap()) nb = red_block_cap();
+  return (int)nb;
+}
+
 template <typename T>
 void launch_coarse(const CoarseArgs<T>& a, int dagger, int epi, hipStream_t st) {
   const long total = a.g.V * a.g.nc;
@@ -885,7 +892,7 @@ void launch_coarse(const CoarseArgs<T>& a, int dagger, int epi, hipStream_t st) 
   }
   if (a.g.nc == 16) {
     long nb = (a.g.V + 3) / 4;
-    const long cap = red ? (long)red_block_cap() : (1L << 20);
+    const long cap = (red || epi == EPI_MRPART) ? (long)red_block_cap() : (1L << 20);
     if (nb > cap) nb = cap;
     dim3 g16((unsigned)nb, (unsigned)a.nrhs);
 #define AMG_C16N(DAG, EPI, ND) dispatch(coarse16_kernel<T, DAG, EPI, ND>, a, g16, dim3(256), st)
@@ -898,7 +905,9 @@ void launch_coarse(const CoarseArgs<T>& a, int dagger, int epi, hipStream_t st) 
       case EPI_RESID * 2: AMG_C16(0, EPI_RESID); break;
       case EPI_RESID * 2 + 1: AMG_C16(1, EPI_RESID); break;
       case EPI_NORM * 2: AMG_C16(0, EPI_NORM); break;
-      default: AMG_C16(1, EPI_NORM); break;
+      case EPI_NORM * 2 + 1: AMG_C16(1, EPI_NORM); break;
+      case EPI_MRPART * 2: AMG_C16(0, EPI_MRPART); break;
+      default: AMG_C16(1, EPI_MRPART); break;
     }
 #undef AMG_C16
 #undef AMG_C16N

@@ -255,6 +255,69 @@ __device__ bool grid_reduce(double (&v)[NV], double* part, unsigned* ticket, int
   return true;
 }
 
+// Largest grid whose per-block partial sums sum_partials accepts.
+constexpr int RED_MAX_PART_BLOCKS = 1024;
+
+// Per-block sums only: thread q < NV stores the block's sum of quantity q to
+// part[(rhs NV + q) gridDim.x + block] with a plain store; the kernel that
+// consumes them runs after this launch, which makes them visible.
+template <int NV>
+__device__ void block_partials(double (&v)[NV], double* part, int rhs) {
+  __shared__ double sh[NV][RED_WAVES];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const double s = wave_sum(v[k]);
+    if (lane == 0) sh[k][wave] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < RED_WAVES; ++w) s += sh[threadIdx.x][w];
+    gl(part)[((long)rhs * NV + threadIdx.x) * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+// Totals of the NV partial sums of nblk blocks written by block_partials
+// (every block of the consuming kernel computes them, in the same fixed
+// order, so all get identical values).  Returns them in every thread.
+template <int NV>
+__device__ void sum_partials(const double* part, int nblk, int rhs, double (&tot)[NV]) {
+  __shared__ double sh[NV][RED_WAVES];
+  __shared__ double shtot[NV];
+  constexpr int U = (RED_MAX_PART_BLOCKS + RED_THREADS - 1) / RED_THREADS;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  gptr<const double> p = gl(part);
+  // all of this thread's loads first, then the adds in block order
+  double v[NV][U];
+#pragma unroll
+  for (int k = 0; k < NV; ++k)
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int b = threadIdx.x + u * RED_THREADS;
+      v[k][u] = (b < nblk) ? p[((long)rhs * NV + k) * nblk + b] : 0.0;
+    }
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double s = 0.0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) s += v[k][u];
+    s = wave_sum(s);
+    if (lane == 0) sh[k][wave] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < RED_WAVES; ++w) s += sh[threadIdx.x][w];
+    shtot[threadIdx.x] = s;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) tot[k] = shtot[k];
+}
+
 // Scalars and flags of a solver live in one device array of doubles.
 // A right-hand side whose `skip` flag is non-zero is left untouched.
 __device__ __forceinline__ bool skip_rhs(const int* flags, int rhs) {

@@ -12,7 +12,8 @@ enum Epi {
   EPI_PLAIN = 0,  // out = A in
   EPI_MRDOT = 1,  // out = A in; alpha = omega <out, in> / <out, out>  -> scal[slot + 2 rhs]
   EPI_RESID = 2,  // out = b - A in
-  EPI_NORM = 3    // out = A in; scal[slot + rhs] = <out, out>
+  EPI_NORM = 3,   // out = A in; scal[slot + rhs] = <out, out>
+  EPI_MRPART = 4  // out = A in; this block's <out, in> (re, im), <out, out> -> part[(3 rhs + q) nblk + block]
 };
 
 constexpr int RED_MAX_BLOCKS = 1024;   // largest grid of kernels that reduce
@@ -81,6 +82,8 @@ struct CoarseArgs {
   RedArgs red;
 };
 template <typename T> void launch_coarse(const CoarseArgs<T>& a, int dagger, int epi, hipStream_t st);
+// blocks of the N_c = 16 stencil launched with a reducing epilogue (partial sums per block)
+int coarse16_red_blocks(long V);
 // many right-hand sides per launch on MFMA (FP32; N_c = 16 or 48; plain or residual epilogue)
 bool coarse_mrhs_supported(int nc, int epi);
 void launch_coarse_mrhs(const CoarseArgs<float>& a, int dagger, int epi, hipStream_t st);
@@ -136,7 +139,7 @@ void launch_p_roundtrip_bf16(double2* P, long n, hipStream_t st);
 template <typename T>
 void launch_mr_update(cplx<T>* x, cplx<T>* r_out, const cplx<T>* r_in, const cplx<T>* p,
                       const double* alpha, long n, int nrhs, int first, int update_r, const int* flags,
-                      hipStream_t st);
+                      hipStream_t st, const double* part = nullptr, int nblk = 0, double omega = 1.0);
 template <typename T>
 void launch_norm2(const cplx<T>* v, long n, int nrhs, RedArgs red, hipStream_t st);
 // GCR building blocks; directions stored contiguously: W_j = Wb + j * dstride

@@ -322,7 +322,8 @@ template <typename T>
 void op_apply(Solver& S, int l, int dagger, int epi, const cplx<T>* in, cplx<T>* out, const cplx<T>* b,
               cplx<T>* copy_out, int nrhs, RedArgs red, hipStream_t st) {
   Level& L = S.lv[l];
-  ProfScope ps(S, L.fine ? PK_FINE : (epi == EPI_MRDOT && S.prof.kind == PK_COARSE_MR ? PK_COARSE_MR : PK_COARSE), l, st);
+  const bool mr_epi = epi == EPI_MRDOT || epi == EPI_MRPART;
+  ProfScope ps(S, L.fine ? PK_FINE : (mr_epi && S.prof.kind == PK_COARSE_MR ? PK_COARSE_MR : PK_COARSE), l, st);
   if (L.fine) {
     wilson_apply<T>(*S.g, S.mass, dagger, epi, in, out, b, copy_out, nrhs, red, st);
     (dagger ? S.nDd : S.nD) += 1;
@@ -394,10 +395,22 @@ void mr_smooth(Solver& S, int l, const cplx<T>* b, cplx<T>* x, cplx<T>* r, cplx<
     }
     return;
   }
+  // N_c = 16 coarse levels: the stencil leaves per-block sums and the update
+  // kernel forms alpha from them (no cross-block reduction in the stencil).
+  // Not while recording for a batch: merged launches change the stencil's
+  // grid, which the update kernel must know.
+  const bool part = !L.fine && L.dof == 16 && current_recorder() == nullptr &&
+                    coarse16_red_blocks(L.V) <= RED_MAX_PART_BLOCKS;
   for (int i = 0; i < nu; ++i) {
     const cplx<T>* rin = (i == 0) ? b : r;
-    op_apply<T>(S, l, 0, EPI_MRDOT, rin, p, nullptr, nullptr, nrhs, S.sc.red(L.mr_slot, S.outer_flags, S.p.omega), st);
     const bool upd = (i < nu - 1) || need_r;
+    if (part) {
+      op_apply<T>(S, l, 0, EPI_MRPART, rin, p, nullptr, nullptr, nrhs, S.sc.red(0, S.outer_flags), st);
+      launch_mr_update<T>(x, r, rin, p, nullptr, n, nrhs, first && i == 0, upd ? 1 : 0, S.outer_flags, st,
+                          S.sc.part.as<double>(), coarse16_red_blocks(L.V), S.p.omega);
+      continue;
+    }
+    op_apply<T>(S, l, 0, EPI_MRDOT, rin, p, nullptr, nullptr, nrhs, S.sc.red(L.mr_slot, S.outer_flags, S.p.omega), st);
     launch_mr_update<T>(x, r, rin, p, S.sc.scal.as<double>() + L.mr_slot, n, nrhs, first && i == 0, upd ? 1 : 0,
                         S.outer_flags, st);
   }
