@@ -665,16 +665,22 @@ __global__ __launch_bounds__(256) void prolong_blk_kernel(TrArgs<T, PT> a0, cons
 #pragma unroll
       for (int r = 0; r < RG; ++r) { s0[r] = mk<T>(0, 0); s1[r] = mk<T>(0, 0); }
       gptr<const cplx<T>> __restrict__ e = gl(a.in) + (long)r0 * per_c + j * 2 * NV + chi * NV;
-#pragma unroll 4
-      for (int k = 0; k < NV; ++k) {
-        const cplx<T> p0 = ldp<T>(gl(a.P), prow + k), p1 = ldp<T>(gl(a.P), prow + NV + k);
+      // the pair's P rows 16 bytes at a time (rows start 16-byte aligned: NV
+      // entries of 4, 8 or 16 bytes with NV a multiple of 4)
+      constexpr int QN = 16 / (int)sizeof(PT);
+      for (int k0 = 0; k0 < NV; k0 += QN) {
+        cplx<T> p0[QN], p1[QN];
+        ldp16<T, PT>(gl(a.P) + prow + k0, p0);
+        ldp16<T, PT>(gl(a.P) + prow + NV + k0, p1);
 #pragma unroll
-        for (int r = 0; r < RG; ++r)
-          if (r < nr) {
-            const cplx<T> ev = e[(long)r * per_c + k];
-            cfma<T>(s0[r], p0, ev);
-            cfma<T>(s1[r], p1, ev);
-          }
+        for (int qq = 0; qq < QN; ++qq)
+#pragma unroll
+          for (int r = 0; r < RG; ++r)
+            if (r < nr) {
+              const cplx<T> ev = e[(long)r * per_c + k0 + qq];
+              cfma<T>(s0[r], p0[qq], ev);
+              cfma<T>(s1[r], p1[qq], ev);
+            }
       }
       const long o0 = g.lf.off(fs, c0), o1 = g.lf.off(fs, c0 + 1);
 #pragma unroll
@@ -1002,10 +1008,12 @@ void launch_prolong(cplx<T>* out, const cplx<T>* in, const void* P, int pkind, c
                     int accumulate, const int* flags, hipStream_t st) {
   if (blk_transfer(g) && nrhs >= 4) {
     const dim3 grid((unsigned)((g.Vc * 2 + 3) / 4), 1);
-#define AMG_PB(PT) dispatch(prolong_blk_kernel<T, PT, 24, 8>, TrArgs<T, PT>{out, in, (const PT*)P, g, flags, accumulate, nrhs}, grid, dim3(256), st)
-    if (pkind == P_F64) AMG_PB(double2);
-    else if (pkind == P_F32) AMG_PB(float2);
-    else AMG_PB(bf16x2);
+#define AMG_PB(PT, RG) dispatch(prolong_blk_kernel<T, PT, 24, RG>, TrArgs<T, PT>{out, in, (const PT*)P, g, flags, accumulate, nrhs}, grid, dim3(256), st)
+#define AMG_PB_RG(PT) if (nrhs > 8) { AMG_PB(PT, 16); } else { AMG_PB(PT, 8); }
+    if (pkind == P_F64) { AMG_PB_RG(double2) }
+    else if (pkind == P_F32) { AMG_PB_RG(float2) }
+    else { AMG_PB_RG(bf16x2) }
+#undef AMG_PB_RG
 #undef AMG_PB
     return;
   }

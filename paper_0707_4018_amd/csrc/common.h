@@ -84,6 +84,15 @@ template <typename T> __device__ __forceinline__ cplx<T> pval(float2 z) { return
 template <typename T> __device__ __forceinline__ cplx<T> pval(bf16x2 z) { return mk<T>((T)bf2f(z.x), (T)bf2f(z.y)); }
 // element i of P (any storage kind, generic or global pointer) in precision T
 template <typename T, typename Ptr> __device__ __forceinline__ cplx<T> ldp(Ptr p, long i) { return pval<T>(p[i]); }
+// 16 bytes of P (4 BF16, 2 FP32 or 1 FP64 complex entries) from a 16-byte aligned address
+template <typename T, typename PT, typename Ptr>
+__device__ __forceinline__ void ldp16(Ptr p, cplx<T> (&out)[16 / sizeof(PT)]) {
+  const uint4 v = *reinterpret_cast<const AMG_GLOBAL uint4*>(p);
+  PT t[16 / sizeof(PT)];
+  __builtin_memcpy(t, &v, 16);
+#pragma unroll
+  for (int n = 0; n < (int)(16 / sizeof(PT)); ++n) out[n] = pval<T>(t[n]);
+}
 
 // ---------------------------------------------------------------------------
 // Field layout.  A level field of V sites with `dof` complex components per
