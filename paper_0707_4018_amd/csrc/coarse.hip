@@ -579,49 +579,70 @@ __global__ __launch_bounds__(256) void restrict_blk_kernel(TrArgs<T, PT> a0, con
   const bool active = lane < 2 * NV;
   const int hd = g.dof / 2;
   const long per_f = g.lf.per_rhs(), per_c = g.Vc * 2 * NV;
+  // the fine values of a batch, loaded once by the whole wave: [parity][u][r]
+  constexpr int UN = 6;
+  __shared__ cplx<T> xs[4][2][UN][RG];
+  const long fs0 = BlockIdx::fine_site(g, j, 0);
+  const int s1 = g.fdims[0], s2 = s1 * g.fdims[1], s3 = s2 * g.fdims[2];
+  const int nel0 = g.bs * ((hd + 1) / 2), nel1 = g.bs * (hd / 2);  // elements per parity
+  // fine field offset of element e of parity p (sites of the block in P order)
+  auto fine_off = [&](int p, int e) -> long {
+    const int hn = p ? hd / 2 : (hd + 1) / 2;
+    const int xi = e / hn, h = p + 2 * (e - xi * hn);
+    int rem = xi;
+    const int b0 = rem % g.blk[0]; rem /= g.blk[0];
+    const int b1 = rem % g.blk[1]; rem /= g.blk[1];
+    const int b2 = rem % g.blk[2]; rem /= g.blk[2];
+    const long fs = fs0 + b0 + b1 * s1 + b2 * s2 + (long)rem * s3;
+    return g.lf.off(fs, chi * hd + h);
+  };
+  const int pc = active ? par : 0;
+  const int hn = pc ? hd / 2 : (hd + 1) / 2;  // components of this lane's parity per site
+  const int nel = pc ? nel1 : nel0;
+  const long pbase = (j * g.bs * g.dof + chi * hd) * (long)NV + k;
   for (int r0 = 0; r0 < a.nrhs; r0 += RG) {
     const int nr = (a.nrhs - r0 < RG) ? a.nrhs - r0 : RG;
     cplx<T> acc[RG];
 #pragma unroll
     for (int r = 0; r < RG; ++r) acc[r] = mk<T>(0, 0);
-    if (active) {
-      // sites of the block in P order (x_1 fastest) from the block origin,
-      // with 32-bit additions only
-      const long fs0 = BlockIdx::fine_site(g, j, 0);
-      const int s1 = g.fdims[0], s2 = s1 * g.fdims[1], s3 = s2 * g.fdims[2];
-      // elements (xi, h) of this lane's parity, UN at a time: all their loads
-      // are issued before the multiply-adds (the chain is latency-bound)
-      constexpr int UN = 6;
-      const int hn = (hd - par + 1) / 2;    // components of this parity per site
-      const int nel = g.bs * hn;
-      const long pbase = (j * g.bs * g.dof + chi * hd) * (long)NV + k;
-      for (int e0 = 0; e0 < nel; e0 += UN) {
+    for (int e0 = 0; e0 < nel0; e0 += UN) {
+      // every lane loads distinct fine values of the batch into LDS
+      constexpr int NT = (2 * UN * RG + 63) / 64;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int v = lane + 64 * t;
+        if (v < 2 * UN * RG) {
+          const int p = v / (UN * RG), rest = v - p * (UN * RG);
+          const int u = rest / RG, r = rest - u * RG;
+          const int e = e0 + u;
+          cplx<T> x = mk<T>(0, 0);
+          if (r < nr && e < (p ? nel1 : nel0)) x = gl(a.in)[(long)(r0 + r) * per_f + fine_off(p, e)];
+          xs[wave][p][u][r] = x;
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (active) {
         cplx<T> pv[UN];
-        long fo[UN];
 #pragma unroll
         for (int u = 0; u < UN; ++u) {
           const int e = (e0 + u < nel) ? e0 + u : nel - 1;
           const int xi = e / hn, h = par + 2 * (e - xi * hn);
-          int rem = xi;
-          const int b0 = rem % g.blk[0]; rem /= g.blk[0];
-          const int b1 = rem % g.blk[1]; rem /= g.blk[1];
-          const int b2 = rem % g.blk[2]; rem /= g.blk[2];
-          const long fs = fs0 + b0 + b1 * s1 + b2 * s2 + (long)rem * s3;
           const T w = (e0 + u < nel) ? (T)1 : (T)0;
           const cplx<T> pp = ldp<T>(gl(a.P), pbase + ((long)xi * g.dof + h) * NV);
           pv[u] = mk<T>(w * pp.x, w * pp.y);
-          fo[u] = g.lf.off(fs, chi * hd + h);
         }
 #pragma unroll
         for (int r = 0; r < RG; ++r)
-          if (r < nr) {
-            cplx<T> xv[UN];
+          if (r < nr)
 #pragma unroll
-            for (int u = 0; u < UN; ++u) xv[u] = gl(a.in)[(long)(r0 + r) * per_f + fo[u]];
-#pragma unroll
-            for (int u = 0; u < UN; ++u) cjfma<T>(acc[r], pv[u], xv[u]);
-          }
+            for (int u = 0; u < UN; ++u) cjfma<T>(acc[r], pv[u], xs[wave][par][u][r]);
       }
+      // the next batch overwrites xs only after every lane has read this one
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 #pragma unroll
     for (int r = 0; r < RG; ++r) {
