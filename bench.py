@@ -78,7 +78,7 @@ def source():
 # solver parameters shared by the GPU run and the oracle sample
 PARAMS = dict(blocks=[(4, 4), (2, 2)], nvec=[8, 8], nu_pre=2, nu_post=2, omega=0.8,
               coarse_tol=0.2, coarse_maxiter=100, coarse_restart=10, outer_restart=16,
-              kcycle_tol=0.1, kcycle_maxiter=8)
+              kcycle_tol=0.2, kcycle_maxiter=8)
 
 
 # adaptive setup: nu0 MR steps on the first vector, ncyc error-propagation sweeps per further vector
