@@ -42,7 +42,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the roofline kernel from rocprofv3 counters (FETCH_SIZE x 2,
 # calibrated on a 256 MiB device copy, + WRITE_SIZE), taken on the current kernel
 # (None whenever the kernel changes, until the counters are taken again)
-ROOF_TRAFFIC = 43451597   # 42433.2 KiB: FETCH 20912.6 KiB x 2 + WRITE 608.0 KiB
+ROOF_TRAFFIC = 43442176   # 42424.0 KiB: FETCH 20908.0 KiB x 2 + WRITE 608.0 KiB
 WORKLOADS = json.load(open(os.path.join(ROOT, "synth", "workloads.json")))
 
 
