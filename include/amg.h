@@ -189,8 +189,10 @@ amg_status amg_transfer(const amg_solver* s, int level, int dir, const void* dev
 amg_status amg_vcycle(amg_solver* s, const void* dev_b, void* dev_x, int nrhs, void* stream);
 
 /* nu MR steps (omega from the params) on level `level` from x = 0:
- * x = MR_nu(b), FP64 canonical. */
-amg_status amg_mr(amg_solver* s, int level, int nu, const void* dev_b, void* dev_x,
+ * x = MR_nu(b) in precision prec, b and x canonical fields of that
+ * precision (complex128 / complex64), nrhs of them.  AMG_F32 needs a solver
+ * built with inner_prec = AMG_F32 (else AMG_ERR_STATE). */
+amg_status amg_mr(amg_solver* s, int level, int prec, int nu, const void* dev_b, void* dev_x,
                   int nrhs, void* stream);
 
 /* ---- batched solves ---------------------------------------------------------

@@ -74,7 +74,7 @@ _SIGS = {
     "amg_level_apply": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, _P, _P, C.c_int, _P]),
     "amg_transfer": (C.c_int, [_P, C.c_int, C.c_int, _P, _P, C.c_int, _P]),
     "amg_vcycle": (C.c_int, [_P, _P, _P, C.c_int, _P]),
-    "amg_mr": (C.c_int, [_P, C.c_int, C.c_int, _P, _P, C.c_int, _P]),
+    "amg_mr": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, _P, _P, C.c_int, _P]),
     "amg_level_info": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                  C.POINTER(C.c_longlong)]),
     "amg_profile_enable": (C.c_int, [_P, C.c_int, C.c_int, C.c_int]),
@@ -318,10 +318,11 @@ class Solver:
         _check(load_library().amg_vcycle(self._h, _ptr(x), _ptr(out), nrhs, _stream()), "amg_vcycle")
         return out
 
-    def mr(self, level: int, nu: int, b: torch.Tensor, nrhs: int = 1) -> torch.Tensor:
+    def mr(self, level: int, nu: int, b: torch.Tensor, nrhs: int = 1, prec: int = F64) -> torch.Tensor:
+        dt = torch.complex128 if prec == F64 else torch.complex64
         x = b.contiguous()
         out = torch.empty_like(x)
-        _check(load_library().amg_mr(self._h, level, nu, _ptr(x), _ptr(out), nrhs, _stream()), "amg_mr")
+        _check(load_library().amg_mr(self._h, level, prec, nu, _ptr(x, dt), _ptr(out, dt), nrhs, _stream()), "amg_mr")
         return out
 
     def level_apply(self, level: int, x: torch.Tensor, dagger: bool = False, prec: int = F64, nrhs: int = 1):

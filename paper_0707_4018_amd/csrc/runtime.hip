@@ -1675,21 +1675,32 @@ amg_status amg_vcycle(amg_solver* S, const void* dev_b, void* dev_x, int nrhs, v
   AMG_CATCH
 }
 
-amg_status amg_mr(amg_solver* S, int level, int nu, const void* dev_b, void* dev_x, int nrhs, void* stream) {
+amg_status amg_mr(amg_solver* S, int level, int prec, int nu, const void* dev_b, void* dev_x, int nrhs,
+                  void* stream) {
   AMG_TRY
   check_ptr(S, "solver");
   check_ptr(dev_b, "b");
   check_ptr(dev_x, "x");
   if (level < 0 || level >= (int)S->lv.size()) fail(AMG_ERR_ARG, "bad level");
   if (nrhs < 1 || nrhs > RHS_MAX || nu < 0) fail(AMG_ERR_ARG, "bad nrhs / nu");
+  if (prec != AMG_F64 && prec != AMG_F32) fail(AMG_ERR_ARG, "bad precision");
+  if (prec == AMG_F32 && S->p.inner_prec != AMG_F32) fail(AMG_ERR_STATE, "no FP32 operators");
   hipStream_t st = as_stream(stream);
   ensure_work(*S, nrhs);
   Level& L = S->lv[level];
-  double2* b = level == 0 ? S->ob.as<double2>() : L.w64[W_B].as<double2>();
-  double2* x = level == 0 ? S->ox.as<double2>() : L.w64[W_X].as<double2>();
-  launch_convert<double, double>(b, (const double2*)dev_b, L.V, L.dof, L.dof, L.lay64.W, nrhs, st);
-  mr_smooth<double>(*S, level, b, x, L.w64[W_R].as<double2>(), L.w64[W_P].as<double2>(), nu, true, true, nrhs, st);
-  launch_convert<double, double>((double2*)dev_x, x, L.V, L.dof, L.lay64.W, L.dof, nrhs, st);
+  if (prec == AMG_F64) {
+    double2* b = level == 0 ? S->ob.as<double2>() : L.w64[W_B].as<double2>();
+    double2* x = level == 0 ? S->ox.as<double2>() : L.w64[W_X].as<double2>();
+    launch_convert<double, double>(b, (const double2*)dev_b, L.V, L.dof, L.dof, L.lay64.W, nrhs, st);
+    mr_smooth<double>(*S, level, b, x, L.w64[W_R].as<double2>(), L.w64[W_P].as<double2>(), nu, true, true, nrhs, st);
+    launch_convert<double, double>((double2*)dev_x, x, L.V, L.dof, L.lay64.W, L.dof, nrhs, st);
+  } else {
+    float2* b = L.w32[W_B].as<float2>();
+    float2* x = L.w32[W_X].as<float2>();
+    launch_convert<float, float>(b, (const float2*)dev_b, L.V, L.dof, L.dof, L.lay32.W, nrhs, st);
+    mr_smooth<float>(*S, level, b, x, L.w32[W_R].as<float2>(), L.w32[W_P].as<float2>(), nu, true, true, nrhs, st);
+    launch_convert<float, float>((float2*)dev_x, x, L.V, L.dof, L.lay32.W, L.dof, nrhs, st);
+  }
   AMG_CATCH
 }
 

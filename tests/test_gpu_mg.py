@@ -290,3 +290,26 @@ def test_mr_reductions_across_grid_sizes(L1, L2):
     assert np.array_equal(x1, x2)
     xo = mg.mr(A, b[0].reshape(A.V, 2), 3, 0.8)[0]
     assert max_rel_err(x1.reshape(-1), xo.reshape(-1)) < 1e-12
+
+
+@pytest.mark.parametrize("nrhs", [1, 3, 5, 12])
+def test_four_dimensional_fp32_mr_multi_rhs(nrhs):
+    """FP32 MR on the 4d fine level (stencil with the MR sums in its epilogue,
+    one launch over all right-hand sides) against the FP64 oracle MR, and
+    against the same MR run one rhs at a time."""
+    import torch
+    import paper_0707_4018_amd as amg
+    print(f"4d fp32 MR nrhs={nrhs}", flush=True)
+    dims = (8, 4, 4, 8)
+    U = su3_config(dims, seed=9, smear=2)
+    m = 0.1
+    A = mg.wilson_stencil(U, m)
+    _, pg = _params([(4, 4, 4, 4)], [6], inner_prec=amg.F32)
+    S = amg.Solver(amg.Gauge(dev(U), m), pg, nullvecs=[dev(vectors(6, A.V, 12, 23))])
+    b = synth.gaussian_field((nrhs, A.V, 4, 3), synth.rng_for(15, nrhs))
+    x = host(S.mr(0, 3, dev(b, torch.complex64), nrhs=nrhs, prec=amg.F32))
+    for r in range(nrhs):
+        xo = mg.mr(A, b[r].reshape(A.V, 12), 3, 0.8)[0]
+        assert rel_err(x[r].reshape(-1), xo.reshape(-1)) < 1e-5, r
+        x1 = host(S.mr(0, 3, dev(b[r:r + 1], torch.complex64), prec=amg.F32))
+        assert rel_err(x[r].reshape(-1), x1.reshape(-1)) < 1e-6, r
