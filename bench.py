@@ -437,7 +437,7 @@ W4_RELAX = 20
 
 
 def stencil_bench(amg, torch, th, iters=40):
-    """Fine stencil alone on HBM-sized lattices: the beta=6 U(1) field tiled
+    """Fine stencil alone on HBM-sized lattices: the beta=10 U(1) field tiled
     periodically to 4096^2, and a 32^3 x 64 SU(3) field (4096 seeded Haar
     matrices tiled over the links, valid SU(3) links; bandwidth does not
     depend on their distribution).  Timed with HIP events on the stream."""

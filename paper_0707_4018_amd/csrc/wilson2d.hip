@@ -148,6 +148,118 @@ __global__ __launch_bounds__(256) void wilson2d_kernel(WilsonArgs<T> a0, const W
   }
 }
 
+// ---- x_2-marching form for lattices far larger than the caches -------------
+// A wave owns 64 consecutive x_1 sites of a strip of kStripRows rows and
+// marches along x_2: the x_2 neighbours and the backward x_2 link come from
+// the previous row's registers, the x_1 neighbours and the backward x_1 link
+// from the adjacent lanes (cross-lane permutes; lanes 0 and 63 load the one
+// value outside the wave).  Every spinor and link is then read from HBM once
+// (plus the two rows above and below the strip), so the loads, like the
+// stores, stream past the caches.  Non-reducing epilogues only.
+__device__ __forceinline__ Sp2<double> ld2_nt(gptr<const double2> __restrict__ p, long s, long V) {
+  const v2d a = __builtin_nontemporal_load((gptr<const v2d>)p + s);
+  const v2d b = __builtin_nontemporal_load((gptr<const v2d>)p + V + s);
+  return {make_double2(a.x, a.y), make_double2(b.x, b.y)};
+}
+__device__ __forceinline__ Sp2<float> ld2_nt(gptr<const float2> __restrict__ p, long s, long) {
+  const v4f q = __builtin_nontemporal_load((gptr<const v4f>)p + s);
+  return {make_float2(q.x, q.y), make_float2(q.z, q.w)};
+}
+// both links of site s: (U_1(s), U_2(s))
+__device__ __forceinline__ void ldU12_nt(gptr<const double2> __restrict__ U, long s, long V, double2& u1,
+                                         double2& u2) {
+  const v2d a = __builtin_nontemporal_load((gptr<const v2d>)U + s);
+  const v2d b = __builtin_nontemporal_load((gptr<const v2d>)U + V + s);
+  u1 = make_double2(a.x, a.y);
+  u2 = make_double2(b.x, b.y);
+}
+__device__ __forceinline__ void ldU12_nt(gptr<const float2> __restrict__ U, long s, long, float2& u1, float2& u2) {
+  const v4f q = __builtin_nontemporal_load((gptr<const v4f>)U + s);
+  u1 = make_float2(q.x, q.y);
+  u2 = make_float2(q.z, q.w);
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> lane_from(cplx<T> v, int src) {
+  return mk<T>(__shfl(v.x, src), __shfl(v.y, src));
+}
+template <typename T>
+__device__ __forceinline__ Sp2<T> lane_from(const Sp2<T>& v, int src) {
+  return {lane_from<T>(v.a, src), lane_from<T>(v.b, src)};
+}
+
+template <typename T, int DAG, int EPI, int ROWS>
+__global__ __launch_bounds__(256) void wilson2d_strip_kernel(WilsonArgs<T> a0, const WilsonArgs<T>* batch) {
+  static_assert(EPI == EPI_PLAIN || EPI == EPI_RESID, "non-reducing epilogues only");
+  AMG_ARGS(WilsonArgs<T>)
+  const int rhs = blockIdx.y;
+  if (skip_rhs(a.red.flags, rhs)) return;
+  const int L1 = a.L1, L2 = a.L2;
+  const long V = (long)L1 * L2;
+  const long ro = (long)rhs * 2 * V;
+  const int lane = threadIdx.x & 63;
+  const int nx = L1 >> 6;                                  // tiles along x_1
+  const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);    // one per wave
+  const int tx = tile % nx, ty = tile / nx;
+  if (ty * ROWS >= L2) return;                       // whole wave (no barriers below)
+  gptr<const cplx<T>> __restrict__ pin = gl(a.in) + ro;
+  gptr<const cplx<T>> __restrict__ U = gl(a.U);
+  gptr<const cplx<T>> __restrict__ bvec = gl(a.b) + ro;
+  gptr<cplx<T>> __restrict__ out = gl(a.out) + ro;
+  gptr<cplx<T>> __restrict__ copy_out = gl(a.copy_out) + ro;
+  const bool copy = a.copy_out != nullptr;
+  const T diag = (T)(2.0 + a.mass);
+  const T sf = DAG ? (T)1 : (T)-1;  // forward projector 1 + sf gamma
+  const T sb = -sf;
+  const int x1 = tx * 64 + lane;
+  const int x1m = (x1 == 0) ? L1 - 1 : x1 - 1;
+  const int x1p = (x1 == L1 - 1) ? 0 : x1 + 1;
+  const int left = (lane + 63) & 63, right = (lane + 1) & 63;
+  const int y0 = ty * ROWS, yl = y0 + ROWS - 1;
+  // The rows a strip shares with its neighbours (the row below it, its first
+  // and last rows, the row above it) and the links of its last row are read
+  // at the start, through the caches: adjacent strips start at about the same
+  // time on the same XCD, so the second reader of a shared row finds it in L2.
+  // The rows in between stream.
+  const long sm0 = (long)((y0 == 0) ? L2 - 1 : y0 - 1) * L1 + x1;
+  const long sl = (long)yl * L1 + x1;
+  const long sh = (long)((yl == L2 - 1) ? 0 : yl + 1) * L1 + x1;
+  Sp2<T> cm = ld2(pin, sm0, V);
+  cplx<T> u2m = ldU(U, sm0, V, 1);
+  Sp2<T> cc = ld2(pin, (long)y0 * L1 + x1, V);
+  const Sp2<T> c_last = ld2(pin, sl, V), c_above = ld2(pin, sh, V);
+  const cplx<T> u1_last = ldU(U, sl, V, 0), u2_last = ldU(U, sl, V, 1);
+#pragma unroll (ROWS <= 4 ? ROWS : 2)
+  for (int t = 0; t < ROWS; ++t) {
+    const int y = y0 + t;
+    const long s = (long)y * L1 + x1;
+    const long sn = s + L1;  // used for t <= ROWS - 3 only: y + 1 < yl, no wrap
+    const Sp2<T> cn = (t == ROWS - 1) ? c_above : (t == ROWS - 2) ? c_last : ld2_nt(pin, sn, V);
+    cplx<T> u1 = u1_last, u2 = u2_last;
+    if (t < ROWS - 1) ldU12_nt(U, s, V, u1, u2);
+    Sp2<T> cl = lane_from<T>(cc, left), cr = lane_from<T>(cc, right);
+    cplx<T> u1l = lane_from<T>(u1, left);
+    if (lane == 0) {
+      cl = ld2(pin, (long)y * L1 + x1m, V);
+      u1l = ldU(U, (long)y * L1 + x1m, V, 0);
+    }
+    if (lane == 63) cr = ld2(pin, (long)y * L1 + x1p, V);
+    Sp2<T> o{cscale<T>(diag, cc.a), cscale<T>(diag, cc.b)};
+    sub_half<T>(o, Hops<T, DAG>::hop1(u1, cr, sf, false));
+    sub_half<T>(o, Hops<T, DAG>::hop1(u1l, cl, sb, true));
+    sub_half<T>(o, Hops<T, DAG>::hop2(u2, cn, sf, false));
+    sub_half<T>(o, Hops<T, DAG>::hop2(u2m, cm, sb, true));
+    if (EPI == EPI_RESID) {
+      const Sp2<T> bb = ld2_nt(bvec, s, V);
+      o = {csub<T>(bb.a, o.a), csub<T>(bb.b, o.b)};
+    }
+    st2_nt(out, s, V, o);
+    if (copy) st2_nt(copy_out, s, V, cc);
+    cm = cc;
+    cc = cn;
+    u2m = u2;
+  }
+}
+
 // Split apply for the Galerkin product: out[k] (k = 0..4) for every input
 // field; out[0] = diagonal + hops that stay inside the block, out[1 + dir] =
 // the hop in direction dir (0:+1, 1:-1, 2:+2, 3:-2) when it leaves the block
@@ -203,6 +315,35 @@ void launch_wilson2d(const WilsonArgs<T>& a, int dagger, int epi, hipStream_t st
     return e ? std::atoi(e) != 0 : true;
   }();
   const bool nt = nt_on && V >= kStreamSites;
+  // rows per strip of the x_2-marching kernel (0: one site per thread);
+  // measured best at 4096^2: 4 in FP64 (72 % of 8 TB/s), 2 in FP32 (77 %)
+  static const int strip_rows = [] {
+    const char* e = std::getenv("AMG_W2_STRIP");
+    return e ? std::atoi(e) : (sizeof(T) == 8 ? 4 : 2);
+  }();
+  // (not while recording for a batch: every instance must record the same kernels)
+  if ((strip_rows == 2 || strip_rows == 4 || strip_rows == 8 || strip_rows == 16) && nt &&
+      current_recorder() == nullptr && (epi == EPI_PLAIN || epi == EPI_RESID) && a.L1 % 64 == 0 &&
+      a.L2 % strip_rows == 0) {
+    const long tiles = (long)(a.L1 / 64) * (a.L2 / strip_rows);
+    const dim3 gs((unsigned)((tiles + 3) / 4), (unsigned)a.nrhs);
+#define AMG_W2S(DAG, EPI, R) dispatch(wilson2d_strip_kernel<T, DAG, EPI, R>, a, gs, dim3(256), st)
+#define AMG_W2SR(DAG, EPI)                                     \
+    switch (strip_rows) {                                      \
+      case 2: AMG_W2S(DAG, EPI, 2); break;                     \
+      case 4: AMG_W2S(DAG, EPI, 4); break;                     \
+      case 8: AMG_W2S(DAG, EPI, 8); break;                     \
+      default: AMG_W2S(DAG, EPI, 16); break;                   \
+    }
+    if (epi == EPI_RESID) {
+      if (dagger) { AMG_W2SR(1, EPI_RESID) } else { AMG_W2SR(0, EPI_RESID) }
+    } else {
+      if (dagger) { AMG_W2SR(1, EPI_PLAIN) } else { AMG_W2SR(0, EPI_PLAIN) }
+    }
+#undef AMG_W2SR
+#undef AMG_W2S
+    return;
+  }
   if (dagger) {
     switch (epi) {
       case EPI_PLAIN: AMG_W2(1, EPI_PLAIN); break;

@@ -313,3 +313,24 @@ def test_four_dimensional_fp32_mr_multi_rhs(nrhs):
         assert rel_err(x[r].reshape(-1), xo.reshape(-1)) < 1e-5, r
         x1 = host(S.mr(0, 3, dev(b[r:r + 1], torch.complex64), prec=amg.F32))
         assert rel_err(x[r].reshape(-1), x1.reshape(-1)) < 1e-6, r
+
+
+def test_large_lattice_mixed_solve():
+    """A 1024^2 mixed-precision adaptive solve.  At this size the fine-level
+    residual of the V-cycle (FP32), the outer FGCR residual (FP64) and the
+    setup's error propagation (FP64) run the x_2-marching stencil with the
+    residual epilogue; the true residual is recomputed with the oracle's D."""
+    import paper_0707_4018_amd as amg
+    L = 1024
+    print(f"mixed solve {L}x{L}", flush=True)
+    th = synth.u1_heatbath(8, 8, 6.0, 20, synth.rng_for(90, 600, 8, 8, 11))
+    U = np.exp(1j * synth.tile_u1(th, L // 8, L // 8))[..., None, None]
+    m = 0.1
+    A = mg.wilson_stencil(U, m)
+    g = amg.Gauge(dev(U), m)
+    _, pg = _params([(4, 4)], [8], inner_prec=amg.F32, p_bf16=True, coarse_tol=0.1, coarse_maxiter=100)
+    S = amg.Solver(g, pg, init=[dev(vectors(8, A.V, 2, 46))])
+    b = synth.gaussian_field((1, A.V, 2, 1), synth.rng_for(16, L))
+    psi, info = S.solve(dev(b), tol=1e-10)
+    res = mg.norm(b[0].reshape(A.V, 2) - A.apply(host(psi)[0].reshape(A.V, 2))) / mg.norm(b)
+    assert info[0].converged and res <= 1e-10
