@@ -24,7 +24,8 @@
  *   (chirality major), complex128.
  * - Ownership: the caller owns every dev_* buffer and must keep inputs alive
  *   until `stream` has passed the call.  Handles own their internal device
- *   memory (hipMalloc) and free it in amg_destroy_*.
+ *   memory (hipMalloc, or the routines given to amg_set_allocator) and free
+ *   it in amg_*_destroy.
  * - Errors: every call returns amg_status; nothing throws across the ABI.
  *   Arguments are validated on the host before any launch.  A thread-local
  *   message with details is available from amg_last_error().
@@ -94,6 +95,22 @@ typedef struct {
 /* ---- errors ------------------------------------------------------------ */
 const char* amg_status_str(amg_status s);
 const char* amg_last_error(void);   /* thread-local detail of the last failure */
+
+/* ---- device memory -------------------------------------------------------
+ * Library plumbing (no passage of the paper defines it).  From this call on,
+ * the internal device buffers of every handle (gauge copies, hierarchies,
+ * work vectors, batches, networks) are taken from alloc(bytes, stream, ctx),
+ * which returns a device pointer or NULL (the call that needed the memory
+ * then fails with AMG_ERR_NOMEM), and handed back to release(ptr, stream,
+ * ctx); stream is NULL (the buffers are used on whatever stream a call
+ * names).  A buffer goes back to the routines that allocated it, also after
+ * a later amg_set_allocator; before handing one back the library waits for
+ * the device to finish its queued work, so a caching allocator may give the
+ * block out again at once.  alloc = release = NULL restores hipMalloc /
+ * hipFree; exactly one of them NULL is AMG_ERR_ARG.  Process-wide; do not
+ * call it while another thread creates or grows handles. */
+amg_status amg_set_allocator(void* (*alloc)(size_t bytes, void* stream, void* ctx),
+                             void (*release)(void* ptr, void* stream, void* ctx), void* ctx);
 
 /* ---- gauge field and the fine operator --------------------------------- */
 

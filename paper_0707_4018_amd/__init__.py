@@ -10,4 +10,5 @@ for Lattice QCD", arXiv:0707.4018.
 """
 from .binding import (  # noqa: F401
     AMGError, Batch, Cnn, Gauge, MGParams, Solver, SolveInfo, F32, F64, lib_path, load_library,
+    use_torch_allocator,
 )

@@ -53,7 +53,10 @@ class _Info(C.Structure):
 
 
 _P = C.c_void_p
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+_RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
 _SIGS = {
+    "amg_set_allocator": (C.c_int, [_ALLOC_FN, _RELEASE_FN, _P]),
     "amg_status_str": (C.c_char_p, [C.c_int]),
     "amg_last_error": (C.c_char_p, []),
     "amg_default_params": (None, [C.POINTER(_Params)]),
@@ -126,6 +129,34 @@ def _check(status: int, where: str):
     if status != 0:
         lib = load_library()
         raise AMGError(status, where, f"{lib.amg_status_str(status).decode()}: {lib.amg_last_error().decode()}")
+
+
+def _torch_alloc(nbytes, stream, ctx):
+    try:
+        return torch.cuda.caching_allocator_alloc(int(nbytes))
+    except Exception:  # out of memory: the library reports AMG_ERR_NOMEM
+        return None
+
+
+def _torch_release(ptr, stream, ctx):
+    torch.cuda.caching_allocator_delete(ptr)
+
+
+# kept for the life of the process: buffers taken from torch are released
+# through these even after the default allocator is restored
+_TORCH_ALLOC = _ALLOC_FN(_torch_alloc)
+_TORCH_RELEASE = _RELEASE_FN(_torch_release)
+
+
+def use_torch_allocator(enable: bool = True) -> None:
+    """amg_set_allocator: take the handles' internal device buffers from torch's
+    caching allocator (enable) or from hipMalloc again (disable).  Handles
+    created while enabled should be destroyed before the interpreter exits."""
+    lib = load_library()
+    if enable:
+        _check(lib.amg_set_allocator(_TORCH_ALLOC, _TORCH_RELEASE, None), "amg_set_allocator")
+    else:
+        _check(lib.amg_set_allocator(_ALLOC_FN(), _RELEASE_FN(), None), "amg_set_allocator")
 
 
 def _stream():

@@ -1599,6 +1599,17 @@ amg_status amg_get_coarse_op(const amg_solver* S, int level, void* dev_out, void
   AMG_CATCH
 }
 
+amg_status amg_set_allocator(void* (*alloc)(size_t, void*, void*), void (*release)(void*, void*, void*),
+                             void* ctx) {
+  AMG_TRY
+  if ((alloc == nullptr) != (release == nullptr)) fail(AMG_ERR_ARG, "give both alloc and release, or neither");
+  Allocator& a = allocator();
+  a.alloc = alloc;
+  a.release = release;
+  a.ctx = alloc ? ctx : nullptr;
+  AMG_CATCH
+}
+
 amg_status amg_level_apply(const amg_solver* Sc, int level, int dagger, int prec, const void* dev_in, void* dev_out,
                            int nrhs, void* stream) {
   AMG_TRY
