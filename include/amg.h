@@ -175,8 +175,9 @@ amg_status amg_solver_destroy(amg_solver* s);
 /* Solve D psi = chi for nrhs canonical complex128 fields by FP64 flexible GCR
  * preconditioned by one V-cycle per iteration, to |chi - D psi| <= tol |chi|
  * (true FP64 residual).  info: array of nrhs.  Returns AMG_ERR_NOCONV if any
- * right-hand side misses tol within max_iter (psi holds the last iterate).
- * Synchronises `stream` once per outer iteration. */
+ * right-hand side misses tol within max_iter (psi holds the last iterate),
+ * AMG_ERR_NAN (before any iteration, psi unwritten) if a right-hand side has
+ * a non-finite entry.  Synchronises `stream` once per outer iteration. */
 amg_status amg_solve(amg_solver* s, const void* dev_chi, void* dev_psi, int nrhs,
                      double tol, int max_iter, amg_solve_info* info, void* stream);
 
@@ -230,7 +231,8 @@ amg_status amg_batch_create(amg_solver* const* solvers, const int* nrhs, int n, 
 /* Solve all instances to |chi - D psi| <= tol |chi| (true FP64 residual per
  * right-hand side).  dev_chi[i], dev_psi[i]: nrhs[i] canonical complex128
  * fields of instance i.  info: sum(nrhs) entries, instance-major.  Returns
- * AMG_ERR_NOCONV if any right-hand side misses tol.  Synchronous. */
+ * AMG_ERR_NOCONV if any right-hand side misses tol, AMG_ERR_NAN (before any
+ * iteration) if one has a non-finite entry.  Synchronous. */
 amg_status amg_batch_solve(amg_batch* b, const void* const* dev_chi, void* const* dev_psi, double tol,
                            int max_iter, amg_solve_info* info, void* stream);
 /* The autotuned reduction grid cap and the number of batched launches per outer step. */

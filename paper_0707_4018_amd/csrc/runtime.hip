@@ -907,6 +907,8 @@ OuterResult fgcr_outer(Solver& S, const double2* b, double2* x, int nrhs, double
     const double* h = S.sc.fetch(gs.bb, nrhs, st);
     for (int i = 0; i < nrhs; ++i) bb[i] = h[i];
   }
+  for (int i = 0; i < nrhs; ++i)
+    if (!std::isfinite(bb[i])) fail(AMG_ERR_NAN, "right-hand side " + std::to_string(i) + " has non-finite entries");
   OuterResult res;
   int k = 0;
   auto read_rr = [&]() {
@@ -1173,7 +1175,12 @@ BatchResult batch_run(Batch& B, double tol, int maxiter) {
   batch_replay(B, B.init);
   batch_fetch(B);
   for (int i = 0; i < n; ++i)
-    for (int j = 0; j < B.nrhs[i]; ++j) bb[base[i] + j] = B.gath_host[(long)(n + i) * RHS_MAX + j];
+    for (int j = 0; j < B.nrhs[i]; ++j) {
+      bb[base[i] + j] = B.gath_host[(long)(n + i) * RHS_MAX + j];
+      if (!std::isfinite(bb[base[i] + j]))
+        fail(AMG_ERR_NAN, "instance " + std::to_string(i) + ", right-hand side " + std::to_string(j) +
+                              " has non-finite entries");
+    }
   int k = 0, it = 0;
   for (;;) {
     int active = 0, cand = 0;

@@ -334,3 +334,22 @@ def test_large_lattice_mixed_solve():
     psi, info = S.solve(dev(b), tol=1e-10)
     res = mg.norm(b[0].reshape(A.V, 2) - A.apply(host(psi)[0].reshape(A.V, 2))) / mg.norm(b)
     assert info[0].converged and res <= 1e-10
+
+
+def test_non_finite_rhs_is_rejected():
+    """A right-hand side with a NaN or an infinite entry: AMG_ERR_NAN before any
+    iteration; the solver then solves a clean system as before."""
+    import paper_0707_4018_amd as amg
+    print("non-finite rhs", flush=True)
+    U, A, H, g, S = _given(16, 16, [(4, 4)], [4])
+    b = synth.gaussian_field((3, A.V, 2, 1), synth.rng_for(18))
+    x_ref, _ = S.solve(dev(b), tol=1e-10)
+    for bad in (np.nan, np.inf):
+        bb = b.copy()
+        bb[1, 7, 0, 0] = bad
+        with pytest.raises(amg.AMGError) as e:
+            S.solve(dev(bb), tol=1e-10)
+        assert e.value.status == 3
+    x, info = S.solve(dev(b), tol=1e-10)
+    assert all(i.converged for i in info)
+    assert np.array_equal(host(x), host(x_ref))
