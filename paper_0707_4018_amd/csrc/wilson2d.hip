@@ -149,13 +149,13 @@ __global__ __launch_bounds__(256) void wilson2d_kernel(WilsonArgs<T> a0, const W
 }
 
 // ---- x_2-marching form for lattices far larger than the caches -------------
-// A wave owns 64 consecutive x_1 sites of a strip of kStripRows rows and
-// marches along x_2: the x_2 neighbours and the backward x_2 link come from
-// the previous row's registers, the x_1 neighbours and the backward x_1 link
+// A wave owns 64 consecutive x_1 sites of a strip of ROWS rows and marches
+// along x_2: the x_2 neighbours and the backward x_2 link come from the
+// previous row's registers, the x_1 neighbours and the backward x_1 link
 // from the adjacent lanes (cross-lane permutes; lanes 0 and 63 load the one
 // value outside the wave).  Every spinor and link is then read from HBM once
-// (plus the two rows above and below the strip), so the loads, like the
-// stores, stream past the caches.  Non-reducing epilogues only.
+// (the rows shared with the strips above and below through L2), so the
+// loads, like the stores, stream past the caches.  All four epilogues.
 __device__ __forceinline__ Sp2<double> ld2_nt(gptr<const double2> __restrict__ p, long s, long V) {
   const v2d a = __builtin_nontemporal_load((gptr<const v2d>)p + s);
   const v2d b = __builtin_nontemporal_load((gptr<const v2d>)p + V + s);
@@ -189,18 +189,16 @@ __device__ __forceinline__ Sp2<T> lane_from(const Sp2<T>& v, int src) {
 
 template <typename T, int DAG, int EPI, int ROWS>
 __global__ __launch_bounds__(256) void wilson2d_strip_kernel(WilsonArgs<T> a0, const WilsonArgs<T>* batch) {
-  static_assert(EPI == EPI_PLAIN || EPI == EPI_RESID, "non-reducing epilogues only");
   AMG_ARGS(WilsonArgs<T>)
   const int rhs = blockIdx.y;
-  if (skip_rhs(a.red.flags, rhs)) return;
+  const RedArgs& red = a.red;
+  if (skip_rhs(red.flags, rhs)) return;  // every block of this rhs: no reduction is started
   const int L1 = a.L1, L2 = a.L2;
   const long V = (long)L1 * L2;
   const long ro = (long)rhs * 2 * V;
   const int lane = threadIdx.x & 63;
   const int nx = L1 >> 6;                                  // tiles along x_1
-  const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);    // one per wave
-  const int tx = tile % nx, ty = tile / nx;
-  if (ty * ROWS >= L2) return;                       // whole wave (no barriers below)
+  const long tiles = (long)nx * (L2 / ROWS);
   gptr<const cplx<T>> __restrict__ pin = gl(a.in) + ro;
   gptr<const cplx<T>> __restrict__ U = gl(a.U);
   gptr<const cplx<T>> __restrict__ bvec = gl(a.b) + ro;
@@ -210,53 +208,80 @@ __global__ __launch_bounds__(256) void wilson2d_strip_kernel(WilsonArgs<T> a0, c
   const T diag = (T)(2.0 + a.mass);
   const T sf = DAG ? (T)1 : (T)-1;  // forward projector 1 + sf gamma
   const T sb = -sf;
-  const int x1 = tx * 64 + lane;
-  const int x1m = (x1 == 0) ? L1 - 1 : x1 - 1;
-  const int x1p = (x1 == L1 - 1) ? 0 : x1 + 1;
   const int left = (lane + 63) & 63, right = (lane + 1) & 63;
-  const int y0 = ty * ROWS, yl = y0 + ROWS - 1;
-  // The rows a strip shares with its neighbours (the row below it, its first
-  // and last rows, the row above it) and the links of its last row are read
-  // at the start, through the caches: adjacent strips start at about the same
-  // time on the same XCD, so the second reader of a shared row finds it in L2.
-  // The rows in between stream.
-  const long sm0 = (long)((y0 == 0) ? L2 - 1 : y0 - 1) * L1 + x1;
-  const long sl = (long)yl * L1 + x1;
-  const long sh = (long)((yl == L2 - 1) ? 0 : yl + 1) * L1 + x1;
-  Sp2<T> cm = ld2(pin, sm0, V);
-  cplx<T> u2m = ldU(U, sm0, V, 1);
-  Sp2<T> cc = ld2(pin, (long)y0 * L1 + x1, V);
-  const Sp2<T> c_last = ld2(pin, sl, V), c_above = ld2(pin, sh, V);
-  const cplx<T> u1_last = ldU(U, sl, V, 0), u2_last = ldU(U, sl, V, 1);
+  double acc[3] = {0.0, 0.0, 0.0};
+  auto strip = [&](int tile) {
+    const int tx = tile % nx, ty = tile / nx;
+    const int x1 = tx * 64 + lane;
+    const int x1m = (x1 == 0) ? L1 - 1 : x1 - 1;
+    const int x1p = (x1 == L1 - 1) ? 0 : x1 + 1;
+    const int y0 = ty * ROWS, yl = y0 + ROWS - 1;
+    // The rows a strip shares with its neighbours (the row below it, its
+    // first and last rows, the row above it) and the links of its last row
+    // are read at the start, through the caches: adjacent strips start at
+    // about the same time on the same XCD, so the second reader of a shared
+    // row finds it in L2.  The rows in between stream.
+    const long sm0 = (long)((y0 == 0) ? L2 - 1 : y0 - 1) * L1 + x1;
+    const long sl = (long)yl * L1 + x1;
+    const long sh = (long)((yl == L2 - 1) ? 0 : yl + 1) * L1 + x1;
+    Sp2<T> cm = ld2(pin, sm0, V);
+    cplx<T> u2m = ldU(U, sm0, V, 1);
+    Sp2<T> cc = ld2(pin, (long)y0 * L1 + x1, V);
+    const Sp2<T> c_last = ld2(pin, sl, V), c_above = ld2(pin, sh, V);
+    const cplx<T> u1_last = ldU(U, sl, V, 0), u2_last = ldU(U, sl, V, 1);
 #pragma unroll (ROWS <= 4 ? ROWS : 2)
-  for (int t = 0; t < ROWS; ++t) {
-    const int y = y0 + t;
-    const long s = (long)y * L1 + x1;
-    const long sn = s + L1;  // used for t <= ROWS - 3 only: y + 1 < yl, no wrap
-    const Sp2<T> cn = (t == ROWS - 1) ? c_above : (t == ROWS - 2) ? c_last : ld2_nt(pin, sn, V);
-    cplx<T> u1 = u1_last, u2 = u2_last;
-    if (t < ROWS - 1) ldU12_nt(U, s, V, u1, u2);
-    Sp2<T> cl = lane_from<T>(cc, left), cr = lane_from<T>(cc, right);
-    cplx<T> u1l = lane_from<T>(u1, left);
-    if (lane == 0) {
-      cl = ld2(pin, (long)y * L1 + x1m, V);
-      u1l = ldU(U, (long)y * L1 + x1m, V, 0);
+    for (int t = 0; t < ROWS; ++t) {
+      const int y = y0 + t;
+      const long s = (long)y * L1 + x1;
+      const long sn = s + L1;  // used for t <= ROWS - 3 only: y + 1 < yl, no wrap
+      const Sp2<T> cn = (t == ROWS - 1) ? c_above : (t == ROWS - 2) ? c_last : ld2_nt(pin, sn, V);
+      cplx<T> u1 = u1_last, u2 = u2_last;
+      if (t < ROWS - 1) ldU12_nt(U, s, V, u1, u2);
+      Sp2<T> cl = lane_from<T>(cc, left), cr = lane_from<T>(cc, right);
+      cplx<T> u1l = lane_from<T>(u1, left);
+      if (lane == 0) {
+        cl = ld2(pin, (long)y * L1 + x1m, V);
+        u1l = ldU(U, (long)y * L1 + x1m, V, 0);
+      }
+      if (lane == 63) cr = ld2(pin, (long)y * L1 + x1p, V);
+      Sp2<T> o{cscale<T>(diag, cc.a), cscale<T>(diag, cc.b)};
+      sub_half<T>(o, Hops<T, DAG>::hop1(u1, cr, sf, false));
+      sub_half<T>(o, Hops<T, DAG>::hop1(u1l, cl, sb, true));
+      sub_half<T>(o, Hops<T, DAG>::hop2(u2, cn, sf, false));
+      sub_half<T>(o, Hops<T, DAG>::hop2(u2m, cm, sb, true));
+      if (EPI == EPI_RESID) {
+        const Sp2<T> bb = ld2_nt(bvec, s, V);
+        o = {csub<T>(bb.a, o.a), csub<T>(bb.b, o.b)};
+      }
+      st2_nt(out, s, V, o);
+      if (copy) st2_nt(copy_out, s, V, cc);
+      if (EPI == EPI_MRDOT) {
+        acc[0] += (double)o.a.x * cc.a.x + (double)o.a.y * cc.a.y + (double)o.b.x * cc.b.x + (double)o.b.y * cc.b.y;
+        acc[1] += (double)o.a.x * cc.a.y - (double)o.a.y * cc.a.x + (double)o.b.x * cc.b.y - (double)o.b.y * cc.b.x;
+        acc[2] += (double)o.a.x * o.a.x + (double)o.a.y * o.a.y + (double)o.b.x * o.b.x + (double)o.b.y * o.b.y;
+      } else if (EPI == EPI_NORM) {
+        acc[0] += (double)o.a.x * o.a.x + (double)o.a.y * o.a.y + (double)o.b.x * o.b.x + (double)o.b.y * o.b.y;
+      }
+      cm = cc;
+      cc = cn;
+      u2m = u2;
     }
-    if (lane == 63) cr = ld2(pin, (long)y * L1 + x1p, V);
-    Sp2<T> o{cscale<T>(diag, cc.a), cscale<T>(diag, cc.b)};
-    sub_half<T>(o, Hops<T, DAG>::hop1(u1, cr, sf, false));
-    sub_half<T>(o, Hops<T, DAG>::hop1(u1l, cl, sb, true));
-    sub_half<T>(o, Hops<T, DAG>::hop2(u2, cn, sf, false));
-    sub_half<T>(o, Hops<T, DAG>::hop2(u2m, cm, sb, true));
-    if (EPI == EPI_RESID) {
-      const Sp2<T> bb = ld2_nt(bvec, s, V);
-      o = {csub<T>(bb.a, o.a), csub<T>(bb.b, o.b)};
-    }
-    st2_nt(out, s, V, o);
-    if (copy) st2_nt(copy_out, s, V, cc);
-    cm = cc;
-    cc = cn;
-    u2m = u2;
+  };
+  // one tile per wave: the waves of a pass cover consecutive tiles, so
+  // adjacent strips run at the same time
+  const int tile0 = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (EPI == EPI_PLAIN || EPI == EPI_RESID) {  // a wave for every tile, no reduction
+    if (tile0 < tiles) strip(tile0);
+    return;
+  }
+  // reducing epilogues: capped grid, tile stride
+  for (long tile = tile0; tile < tiles; tile += (long)gridDim.x * 4) strip((int)tile);
+  if (EPI == EPI_MRDOT) {
+    double tot[3];
+    if (grid_reduce<3>(acc, red.part, red.ticket, rhs, tot) && threadIdx.x == 0) finalize_mr(tot, red, rhs);
+  } else if (EPI == EPI_NORM) {
+    double a1[1] = {acc[0]}, tot[1];
+    if (grid_reduce<1>(a1, red.part, red.ticket, rhs, tot) && threadIdx.x == 0) red.scal[red.slot + rhs] = tot[0];
   }
 }
 
@@ -323,10 +348,11 @@ void launch_wilson2d(const WilsonArgs<T>& a, int dagger, int epi, hipStream_t st
   }();
   // (not while recording for a batch: every instance must record the same kernels)
   if ((strip_rows == 2 || strip_rows == 4 || strip_rows == 8 || strip_rows == 16) && nt &&
-      current_recorder() == nullptr && (epi == EPI_PLAIN || epi == EPI_RESID) && a.L1 % 64 == 0 &&
-      a.L2 % strip_rows == 0) {
+      current_recorder() == nullptr && a.L1 % 64 == 0 && a.L2 % strip_rows == 0) {
     const long tiles = (long)(a.L1 / 64) * (a.L2 / strip_rows);
-    const dim3 gs((unsigned)((tiles + 3) / 4), (unsigned)a.nrhs);
+    long nbs = (tiles + 3) / 4;
+    if (epi == EPI_MRDOT || epi == EPI_NORM) nbs = nbs < red_block_cap() ? nbs : red_block_cap();
+    const dim3 gs((unsigned)nbs, (unsigned)a.nrhs);
 #define AMG_W2S(DAG, EPI, R) dispatch(wilson2d_strip_kernel<T, DAG, EPI, R>, a, gs, dim3(256), st)
 #define AMG_W2SR(DAG, EPI)                                     \
     switch (strip_rows) {                                      \
@@ -335,11 +361,14 @@ void launch_wilson2d(const WilsonArgs<T>& a, int dagger, int epi, hipStream_t st
       case 8: AMG_W2S(DAG, EPI, 8); break;                     \
       default: AMG_W2S(DAG, EPI, 16); break;                   \
     }
-    if (epi == EPI_RESID) {
-      if (dagger) { AMG_W2SR(1, EPI_RESID) } else { AMG_W2SR(0, EPI_RESID) }
-    } else {
-      if (dagger) { AMG_W2SR(1, EPI_PLAIN) } else { AMG_W2SR(0, EPI_PLAIN) }
+#define AMG_W2SE(EPI) if (dagger) { AMG_W2SR(1, EPI) } else { AMG_W2SR(0, EPI) }
+    switch (epi) {
+      case EPI_PLAIN: AMG_W2SE(EPI_PLAIN) break;
+      case EPI_RESID: AMG_W2SE(EPI_RESID) break;
+      case EPI_MRDOT: AMG_W2SE(EPI_MRDOT) break;
+      default: AMG_W2SE(EPI_NORM) break;
     }
+#undef AMG_W2SE
 #undef AMG_W2SR
 #undef AMG_W2S
     return;

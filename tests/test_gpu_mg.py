@@ -353,3 +353,28 @@ def test_non_finite_rhs_is_rejected():
     x, info = S.solve(dev(b), tol=1e-10)
     assert all(i.converged for i in info)
     assert np.array_equal(host(x), host(x_ref))
+
+
+@pytest.mark.parametrize("L1,L2", [(1024, 1024), (1024, 1032)])
+def test_mr_on_streaming_size_lattices(L1, L2):
+    """MR on a fine lattice of 2^20 sites and more: the stencil with the MR sums
+    marches along x_2 (1024^2, tile-strided capped grid) or runs one site per
+    thread (1024 x 1032); FP64 and FP32 against the oracle's MR, bitwise
+    reproducible."""
+    import torch
+    import paper_0707_4018_amd as amg
+    print(f"fine MR {L1}x{L2}", flush=True)
+    th = synth.u1_heatbath(8, 8, 6.0, 20, synth.rng_for(90, 600, 8, 8, 13))
+    U = np.exp(1j * synth.tile_u1(th, L1 // 8, L2 // 8))[..., None, None]
+    m = 0.05
+    A = mg.wilson_stencil(U, m)
+    g = amg.Gauge(dev(U), m)
+    _, pg = _params([(4, 4)], [4], inner_prec=amg.F32)
+    S = amg.Solver(g, pg, nullvecs=[dev(vectors(4, A.V, 2, 47))])
+    b = synth.gaussian_field((1, A.V, 2, 1), synth.rng_for(19, L1, L2))
+    xo = mg.mr(A, b[0].reshape(A.V, 2), 3, 0.8)[0]
+    x1 = host(S.mr(0, 3, dev(b)))
+    assert np.array_equal(x1, host(S.mr(0, 3, dev(b))))
+    assert max_rel_err(x1.reshape(-1), xo.reshape(-1)) < 1e-12
+    x32 = host(S.mr(0, 3, dev(b, torch.complex64), prec=amg.F32))
+    assert rel_err(x32.reshape(-1), xo.reshape(-1)) < 1e-5
