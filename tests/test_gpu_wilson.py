@@ -84,17 +84,20 @@ def test_apply_rejects_bad_arguments():
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-@pytest.mark.parametrize("L1,L2", [(1024, 1024), (64, 16384), (4096, 256), (1040, 1024), (1024, 1032)])
+@pytest.mark.parametrize("L1,L2", [(1024, 1024), (64, 16384), (4096, 256), (262144, 4), (1040, 1024), (1024, 1032)])
 def test_wilson2d_streaming_store_size(prec, L1, L2):
     """Lattices from 2^20 sites: streaming stores; with L1 a multiple of 64 and
     L2 of 16 the x_2-marching kernel (a single 64-site tile across x_1 at
     L1 = 64, so the periodic x_1 neighbours of lanes 0 and 63 lie in the same
-    wave), otherwise the one-site-per-thread kernel.  Two right-hand sides."""
+    wave; at L2 = 4 one strip spans x_2 in FP64, so the rows below and above
+    it are its own last and first rows), otherwise the one-site-per-thread
+    kernel.  Two right-hand sides."""
     import paper_0707_4018_amd as amg
     import torch
     print(f"wilson2d {prec} {L1}x{L2} (streaming stores)", flush=True)
-    th = synth.u1_heatbath(8, 8, 6.0, 20, synth.rng_for(90, 600, 8, 8, 7))
-    U = np.exp(1j * synth.tile_u1(th, L1 // 8, L2 // 8))[..., None, None]
+    b2 = min(8, L2)
+    th = synth.u1_heatbath(8, b2, 6.0, 20, synth.rng_for(90, 600, 8, b2, 7))
+    U = np.exp(1j * synth.tile_u1(th, L1 // 8, L2 // b2))[..., None, None]
     g = amg.Gauge(dev(U), 0.03)
     psi = synth.gaussian_field((2, L2 * L1, 2, 1), synth.rng_for(4, L1, L2))
     dt = torch.complex128 if prec == "f64" else torch.complex64
