@@ -463,11 +463,12 @@ template <typename T>
 void launch_wilson4d(const WilsonArgs<T>& a, int dagger, int epi, hipStream_t st) {
   const long V = (long)a.L1 * a.L2 * a.L3 * a.L4;
   const bool red = (epi == EPI_MRDOT || epi == EPI_NORM);
-  // reducing epilogues run the one-site-per-thread kernel: the x_4-marching
-  // one measured about 1.5x slower with a reduction (600 vs 390 us, FP32)
+  // reducing epilogues: FP32 marches 16 sites along x_4 (the 12-rhs MR
+  // smoother at 32^3 x 64: solve 9.54 -> 9.09 s against one site per
+  // thread), FP64 runs one site per thread (its marching form is slower)
   static const int tt_red = [] {
     const char* e = std::getenv("AMG_W4_TT_RED");
-    return e ? std::atoi(e) : 0;
+    return e ? std::atoi(e) : (sizeof(T) == 4 ? 16 : 0);
   }();
   const int tt = (red && tt_red >= 0) ? tt_red : w4_tt<T>();
   const bool nt = V >= (1L << 20);
