@@ -363,7 +363,7 @@ def estimate_mcrit(amg, torch, g, V, iters=12):
 
 def wilson4d_bench(amg, torch, U0):
     """12 point sources (one per spin-colour component at the origin) solved together by
-    2-level MG (4^4 blocks, 24 near-null vectors -> 48 coarse dof, 4 + 4 MR steps) with FP32
+    2-level MG (4^4 blocks, 24 near-null vectors -> 48 coarse dof, W4_NU + W4_NU MR steps) with FP32
     smoother and coarse level (BF16 P), FP64 FGCR outer iteration, to a true relative residual
     of 1e-10; two of the sources one at a time, and CGNR on one source, for reference."""
     tile = tuple(d // b for d, b in zip(W4_DIMS, W4_BASE))
