@@ -671,8 +671,23 @@ __global__ __launch_bounds__(256) void prolong_blk_kernel(TrArgs<T, PT> a0, cons
   const long per_f = g.lf.per_rhs(), per_c = g.Vc * 2 * NV;
   const long fs0 = BlockIdx::fine_site(g, j, 0);
   const int s1 = g.fdims[0], s2 = s1 * g.fdims[1], s3 = s2 * g.fdims[2];
+  // this wave's coarse values [rhs][k] (the same for all its lanes), staged
+  // once per group of right-hand sides and read as LDS broadcasts
+  __shared__ cplx<T> es[4][RG][NV];
   for (int r0 = 0; r0 < a.nrhs; r0 += RG) {
     const int nr = (a.nrhs - r0 < RG) ? a.nrhs - r0 : RG;
+    {
+      gptr<const cplx<T>> __restrict__ e = gl(a.in) + (long)r0 * per_c + j * 2 * NV + chi * NV;
+      for (int v = lane; v < RG * NV; v += 64) {
+        const int r = v / NV, k = v - r * NV;
+        cplx<T> ev = mk<T>(0, 0);
+        if (r < nr) ev = e[(long)r * per_c + k];
+        es[wave][r][k] = ev;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
     for (int xi = lane; xi < g.bs; xi += 64) {
       int rem = xi;
       const int b0 = rem % g.blk[0]; rem /= g.blk[0];
@@ -685,7 +700,6 @@ __global__ __launch_bounds__(256) void prolong_blk_kernel(TrArgs<T, PT> a0, cons
       cplx<T> s0[RG], s1[RG];  // (the pair's two components)
 #pragma unroll
       for (int r = 0; r < RG; ++r) { s0[r] = mk<T>(0, 0); s1[r] = mk<T>(0, 0); }
-      gptr<const cplx<T>> __restrict__ e = gl(a.in) + (long)r0 * per_c + j * 2 * NV + chi * NV;
       // the pair's P rows 16 bytes at a time (rows start 16-byte aligned: NV
       // entries of 4, 8 or 16 bytes with NV a multiple of 4)
       constexpr int QN = 16 / (int)sizeof(PT);
@@ -698,7 +712,7 @@ __global__ __launch_bounds__(256) void prolong_blk_kernel(TrArgs<T, PT> a0, cons
 #pragma unroll
           for (int r = 0; r < RG; ++r)
             if (r < nr) {
-              const cplx<T> ev = e[(long)r * per_c + k0 + qq];
+              const cplx<T> ev = es[wave][r][k0 + qq];
               cfma<T>(s0[r], p0[qq], ev);
               cfma<T>(s1[r], p1[qq], ev);
             }
@@ -713,6 +727,10 @@ __global__ __launch_bounds__(256) void prolong_blk_kernel(TrArgs<T, PT> a0, cons
         }
       }
     }
+    // the next group overwrites es only after every lane has read this one
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
 

@@ -249,7 +249,7 @@ def test_multi_rhs_coarse_apply_matches_oracle(case, nrhs):
             assert rel_err(out[r], ref) < 2e-5, (dag, r)
 
 
-@pytest.mark.parametrize("nrhs", [1, 3, 17])
+@pytest.mark.parametrize("nrhs", [1, 3, 5, 12, 17])
 def test_four_dimensional_transfers_match_oracle(nrhs):
     """Restriction / prolongation with 4^4 blocks and 24 vectors (the per-wave kernels with
     right-hand sides grouped inside the wave) against the oracle, rhs by rhs; the coarse
