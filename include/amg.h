@@ -50,7 +50,8 @@ typedef enum {
   AMG_ERR_HIP = 5,     /* a HIP runtime call failed                          */
   AMG_ERR_RANK = 6,    /* block near-null vectors are linearly dependent     */
   AMG_ERR_NOCONV = 7,  /* solver hit max_iter; psi holds the best iterate    */
-  AMG_ERR_STATE = 8    /* call not valid for this handle's state             */
+  AMG_ERR_STATE = 8,   /* call not valid for this handle's state             */
+  AMG_ERR_SINGULAR = 9 /* the coarsest operator of an exact solve is singular */
 } amg_status;
 
 typedef enum { AMG_F64 = 0, AMG_F32 = 1 } amg_prec;  /* complex<double>, complex<float> */
@@ -80,7 +81,18 @@ typedef struct {
   int p_bf16;           /* with AMG_F32: store P in bfloat16 (Galerkin uses the rounded P) */
   double kcycle_tol;    /* intermediate levels: flexible GCR preconditioned by their own cycle */
   int kcycle_maxiter;   /*   to kcycle_tol, at most kcycle_maxiter (<= 32) steps; 0: V-cycle */
+  int coarse_dense_max; /* a coarsest level of at most this many unknowns (V * dof, <= AMG_DENSE_MAX)
+                         * is solved exactly: the recursion of the V-cycle ends in a direct solve
+                         * (the five-step list before Eq. (3)).  The dense matrix of its Galerkin
+                         * operator is inverted at setup (and after a mass change) by Gauss-Jordan
+                         * elimination with partial pivoting in FP64 (AMG_ERR_SINGULAR if a pivot
+                         * is zero); each coarsest solve is then one dense matrix-vector product
+                         * (FP32 copy of the inverse for the FP32 cycle).  Larger coarsest levels
+                         * use GCR (coarse_tol, coarse_maxiter, coarse_restart).  Default 4096.
+                         * Batched solves (amg_batch_create) use GCR on every instance. */
 } amg_mg_params;
+
+#define AMG_DENSE_MAX 8192
 
 typedef struct {
   int iters;                 /* outer FGCR (or CG) iterations                  */
@@ -198,9 +210,20 @@ amg_status amg_level_apply(const amg_solver* s, int level, int dagger, int prec,
                            const void* dev_in, void* dev_out, int nrhs, void* stream);
 
 /* Restriction r_hat = P^dag r (dir = 0) or prolongation e = P e_hat (dir = 1)
- * between level `level` and level+1, FP64 canonical, nrhs fields. */
-amg_status amg_transfer(const amg_solver* s, int level, int dir, const void* dev_in,
+ * between level `level` and level+1 (the transfers of the five-step V-cycle
+ * before Eq. (3), P built as in Eq. (5)), nrhs canonical fields.
+ * prec = AMG_F64: FP64 P and complex128 fields; AMG_F32: the P that the FP32
+ * cycle uses (FP32, or bfloat16 with p_bf16) and complex64 fields,
+ * accumulation in FP32 (AMG_ERR_STATE for a solver with inner_prec = AMG_F64). */
+amg_status amg_transfer(const amg_solver* s, int level, int dir, int prec, const void* dev_in,
                         void* dev_out, int nrhs, void* stream);
+
+/* The prolongator of coarsening `level` as stored (Eq. (5) with the chirally
+ * split, block-orthonormalised vectors): dev_out[V_l][dof_l][2 nvec_l]
+ * complex128, row (site, component), column t = chi*N_v + k, zero where the
+ * component's chirality is not chi.  prec = AMG_F64: the FP64 P; AMG_F32:
+ * the FP32 cycle's copy (FP32 or bfloat16 values, widened exactly). */
+amg_status amg_get_prolongator(const amg_solver* s, int level, int prec, void* dev_out, void* stream);
 
 /* One V-cycle x = V(b) from the finest level, in the solver's inner
  * precision; b and x canonical complex128, nrhs fields. */

@@ -1,12 +1,19 @@
-"""Write the synthetic workload table (masses) used by tests and the benchmark.
+"""Write (or check) the synthetic workload table (masses) used by tests and the benchmark.
 
-Run: python -m oracle.make_workloads [names...] [-jN]   (writes synth/workloads.json)
+Run: python -m oracle.make_workloads [names...] [-jN]          (writes synth/workloads.json)
+     python -m oracle.make_workloads --check [names...] [-jN]  (recomputes, compares, writes nothing)
 
-For every workload lattice this generates the gauge field with the seeded
-heat-bath, computes m_crit from the spectrum of D(0) with the oracle, and
-stores m_crit with the field's plaquette and topological charge, so that a
-consumer can regenerate the field and check it is the same one.
+Test infrastructure: this script calls only the oracle and the seeded input
+generators.  For every workload lattice it generates the gauge field with the
+seeded heat-bath, computes m_crit from the spectrum of D(m = 0) with the
+oracle (m_crit = -min Re lambda, numerical-test section), and stores m_crit
+with the field's plaquette and topological charge, so that a consumer can
+regenerate the field and check it is the same one.
 Seeds: gauge field rng_for(cfg, round(100 beta), L1, L2, idx).
+
+--check recomputes the listed entries and compares them with the stored
+table: plaquette and charge exactly (same seeded generator, same
+arithmetic), m_crit to the eigensolver tolerance (CHECK_MCRIT_TOL).
 """
 from __future__ import annotations
 
@@ -19,6 +26,10 @@ import synth
 from oracle import dirac, mg, spectrum
 
 OUT = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "synth", "workloads.json")
+
+# ARPACK is run to tol 1e-6 on the shift-inverted operator; the eigenvalues
+# of D near the shift then carry an absolute error far below this bound.
+CHECK_MCRIT_TOL = 1e-8
 
 # (name, cfg, L, beta, idx, sweeps, mass gaps)
 WORKLOADS = [
@@ -35,25 +46,78 @@ WORKLOADS = [
     ("heldout_512_b10", 5, 512, 10.0, 10005, 100, [1e-2, 1e-3]),
 ]
 
-def main(names=None, workers=1):
+
+def entry(w):
+    """(name, table entry) of one 2d U(1) workload."""
+    name, cfg, L, beta, idx, sweeps, gaps = w
+    t0 = time.time()
+    seed = [cfg, int(round(100 * beta)), L, L, idx]
+    th = synth.u1_heatbath(L, L, beta, sweeps, synth.rng_for(*seed))
+    A0 = mg.wilson_stencil(dirac.u1_field(th), 0.0)
+    mcrit, lam = spectrum.critical_mass(A0)
+    e = {
+        "cfg": cfg, "L1": L, "L2": L, "beta": beta, "idx": idx, "sweeps": sweeps,
+        "seed": seed, "m_crit": mcrit, "leftmost_eigenvalue_m0": [lam.real, lam.imag],
+        "mass_gaps": gaps, "masses": [mcrit + g for g in gaps],
+        "plaquette": synth.u1_mean_plaquette(th), "Q": round(synth.u1_topological_charge(th)),
+    }
+    print(name, f"m_crit {mcrit:.12f} plaquette {e['plaquette']!r} Q {e['Q']} ({time.time() - t0:.1f} s)",
+          flush=True)
+    return name, e
+
+
+def compare(stored: dict, new: dict) -> list[str]:
+    """Differences between a stored entry and a recomputed one (empty: identical)."""
+    bad = []
+    for k in ("cfg", "L1", "L2", "beta", "idx", "sweeps", "seed", "mass_gaps", "Q"):
+        if stored.get(k) != new[k]:
+            bad.append(f"{k}: stored {stored.get(k)!r} new {new[k]!r}")
+    if stored.get("plaquette") != new["plaquette"]:
+        bad.append(f"plaquette: stored {stored.get('plaquette')!r} new {new['plaquette']!r}")
+    dm = abs(stored["m_crit"] - new["m_crit"])
+    if not dm <= CHECK_MCRIT_TOL:
+        bad.append(f"m_crit: stored {stored['m_crit']!r} new {new['m_crit']!r} (|diff| {dm:.2e})")
+    for a, b in zip(stored["masses"], new["masses"]):
+        if not abs(a - b) <= CHECK_MCRIT_TOL:
+            bad.append(f"mass: stored {a!r} new {b!r}")
+    return bad
+
+
+def _run(todo, workers):
+    if workers > 1:
+        import concurrent.futures as cf
+        with cf.ProcessPoolExecutor(max_workers=workers) as ex:
+            return list(ex.map(entry, todo))
+    return [entry(w) for w in todo]
+
+
+def main(names=None, workers=1, check=False) -> int:
     table = {}
     if os.path.exists(OUT):
         with open(OUT) as f:
             table = json.load(f)
     todo = [w for w in WORKLOADS if not names or w[0] in names]
-    if workers > 1:
-        import concurrent.futures as cf
-        with cf.ProcessPoolExecutor(max_workers=workers) as ex:
-            done = list(ex.map(entry, todo))
-    else:
-        done = [entry(w) for w in todo]
+    done = _run(todo, workers)
+    if check:
+        nbad = 0
+        for name, e in done:
+            bad = compare(table[name], e) if name in table else ["not in the stored table"]
+            print(f"{name}: {'identical' if not bad else 'DIFFERS'}"
+                  f" (|dm_crit| {abs(table.get(name, e)['m_crit'] - e['m_crit']):.2e})", flush=True)
+            for b in bad:
+                print("   ", b)
+            nbad += bool(bad)
+        return 1 if nbad else 0
     for name, e in done:
         table[name] = e
     with open(OUT, "w") as f:
         json.dump(table, f, indent=1)
+    return 0
 
 
 if __name__ == "__main__":
-    args = [a for a in sys.argv[1:] if not a.startswith("-j")]
-    jobs = [int(a[2:]) for a in sys.argv[1:] if a.startswith("-j")]
-    main(args or None, jobs[0] if jobs else 1)
+    argv = sys.argv[1:]
+    check = "--check" in argv
+    args = [a for a in argv if not a.startswith("-")]
+    jobs = [int(a[2:]) for a in argv if a.startswith("-j")]
+    sys.exit(main(args or None, jobs[0] if jobs else 1, check))

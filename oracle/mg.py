@@ -25,6 +25,7 @@ from __future__ import annotations
 from dataclasses import dataclass, field
 
 import numpy as np
+import scipy.linalg as sla
 import scipy.sparse as sp
 
 from .lattice import gammas, site_coords, site_index
@@ -65,6 +66,7 @@ class Stencil:
     hop: np.ndarray             # (2 nd, V, dof, dof)
     napply: int = 0             # number of single-vector applications (cost counter)
     nbr: np.ndarray = field(default=None, repr=False)
+    _lu: tuple = field(default=None, repr=False)   # dense LU factors (coarsest-level solves)
 
     def __post_init__(self):
         if self.nbr is None:
@@ -419,7 +421,8 @@ class MGParams:
     nu_pre: int = 2
     nu_post: int = 2
     omega: float = 0.8
-    coarse_tol: float = 0.1           # coarsest-level GCR relative tolerance
+    coarse_dense_max: int = 4096      # coarsest level solved exactly (dense LU) up to this many unknowns
+    coarse_tol: float = 0.1           # coarsest-level GCR relative tolerance (larger coarsest levels)
     coarse_maxiter: int = 64
     coarse_restart: int = 16
     outer_restart: int = 16
@@ -443,20 +446,21 @@ class Hierarchy:
 def gcr_coarse(A: Stencil, b: np.ndarray, tol: float, maxiter: int, restart: int, precond=None) -> np.ndarray:
     """Approximate level solve: GCR from x = 0 (flexible when a preconditioner is given).
 
-    The paper solves its coarsest lattice exactly; a lattice too large for
-    that is solved approximately here (the outer Krylov method is flexible).
-    Iteration it: stop if ||r|| <= tol ||b|| (recursive residual); at the
-    start of every restart cycle after the first, r = b - A x and the stored
-    directions are dropped; then z = r (or z = M(r) with a preconditioner M),
-    w = A z, w and z are orthogonalised
+    Used for a coarsest level too large for the exact solve, and with a
+    preconditioner M for the K-cycle's intermediate levels.  GCR minimises
+    the residual over the span of the search directions; iteration it:
+    stop if ||r|| <= tol ||b|| (recursive residual; checked before the first
+    step too, so x = 0 is returned when tol >= 1); at the start of every
+    restart cycle after the first, r = b - A x and the stored directions are
+    dropped; then z = r (or z = M(r)), w = A z, w and z are orthogonalised
     against the stored directions (classical Gram-Schmidt coefficients
     <w_j, w>/<w_j, w_j>), alpha = <w, r>/<w, w>, x += alpha z, r -= alpha w.
-    At most maxiter iterations; tol >= 1 returns x = 0.
+    At most maxiter iterations.
     """
     x = np.zeros_like(b, dtype=np.complex128)
     r = b.astype(np.complex128).copy()
     bb = vdot(b, b).real
-    done = True if tol >= 1.0 else bb == 0.0
+    done = vdot(r, r).real <= tol * tol * bb
     Z, W, WW = [], [], []
     for it in range(maxiter):
         if done:
@@ -479,8 +483,21 @@ def gcr_coarse(A: Stencil, b: np.ndarray, tol: float, maxiter: int, restart: int
     return x
 
 
+def dense_solve(A: Stencil, b: np.ndarray) -> np.ndarray:
+    """x = A^-1 b by LU with partial pivoting of the dense matrix of A (the
+    factors are kept on the operator for later solves)."""
+    if getattr(A, "_lu", None) is None:
+        A._lu = sla.lu_factor(A.to_sparse().toarray())
+    return sla.lu_solve(A._lu, b.reshape(-1)).reshape(b.shape)
+
+
 def coarsest_solve(A: Stencil, b: np.ndarray, p: MGParams) -> np.ndarray:
-    """Solve on the coarsest level: GCR to coarse_tol (see gcr_coarse)."""
+    """Solve on the coarsest level.  The paper solves its coarsest lattice
+    exactly; that is done here whenever it has at most coarse_dense_max
+    unknowns.  A larger coarsest level is solved approximately by GCR to
+    coarse_tol (see gcr_coarse; the outer Krylov method is flexible)."""
+    if A.V * A.dof <= p.coarse_dense_max:
+        return dense_solve(A, b)
     return gcr_coarse(A, b, p.coarse_tol, p.coarse_maxiter, p.coarse_restart)
 
 

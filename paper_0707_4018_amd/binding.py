@@ -40,7 +40,7 @@ class _Params(C.Structure):
         ("nu_pre", C.c_int), ("nu_post", C.c_int), ("omega", C.c_double),
         ("coarse_tol", C.c_double), ("coarse_maxiter", C.c_int), ("coarse_restart", C.c_int),
         ("outer_restart", C.c_int), ("inner_prec", C.c_int), ("p_bf16", C.c_int),
-        ("kcycle_tol", C.c_double), ("kcycle_maxiter", C.c_int),
+        ("kcycle_tol", C.c_double), ("kcycle_maxiter", C.c_int), ("coarse_dense_max", C.c_int),
     ]
 
 
@@ -75,7 +75,8 @@ _SIGS = {
     "amg_get_nullvecs": (C.c_int, [_P, C.c_int, _P, _P]),
     "amg_get_coarse_op": (C.c_int, [_P, C.c_int, _P, _P]),
     "amg_level_apply": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, _P, _P, C.c_int, _P]),
-    "amg_transfer": (C.c_int, [_P, C.c_int, C.c_int, _P, _P, C.c_int, _P]),
+    "amg_transfer": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, _P, _P, C.c_int, _P]),
+    "amg_get_prolongator": (C.c_int, [_P, C.c_int, C.c_int, _P, _P]),
     "amg_vcycle": (C.c_int, [_P, _P, _P, C.c_int, _P]),
     "amg_mr": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, _P, _P, C.c_int, _P]),
     "amg_level_info": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
@@ -189,6 +190,7 @@ class MGParams:
     p_bf16: bool = False
     kcycle_tol: float = 0.1
     kcycle_maxiter: int = 0
+    coarse_dense_max: int = 4096
 
     def to_c(self) -> _Params:
         p = _Params()
@@ -202,6 +204,7 @@ class MGParams:
         p.coarse_tol, p.coarse_maxiter, p.coarse_restart = self.coarse_tol, self.coarse_maxiter, self.coarse_restart
         p.outer_restart, p.inner_prec, p.p_bf16 = self.outer_restart, self.inner_prec, int(self.p_bf16)
         p.kcycle_tol, p.kcycle_maxiter = self.kcycle_tol, self.kcycle_maxiter
+        p.coarse_dense_max = self.coarse_dense_max
         return p
 
 
@@ -364,18 +367,28 @@ class Solver:
                                               _stream()), "amg_level_apply")
         return out
 
-    def restrict(self, level: int, r: torch.Tensor, nrhs: int = 1) -> torch.Tensor:
+    def restrict(self, level: int, r: torch.Tensor, nrhs: int = 1, prec: int = F64) -> torch.Tensor:
+        dt = torch.complex128 if prec == F64 else torch.complex64
         dims, dof, V = self.level_info(level + 1)
-        out = torch.empty((nrhs, V, dof), dtype=torch.complex128, device=r.device)
-        _check(load_library().amg_transfer(self._h, level, 0, _ptr(r.contiguous()), _ptr(out), nrhs, _stream()),
-               "amg_transfer")
+        out = torch.empty((nrhs, V, dof), dtype=dt, device=r.device)
+        _check(load_library().amg_transfer(self._h, level, 0, prec, _ptr(r.contiguous(), dt), _ptr(out, dt), nrhs,
+                                           _stream()), "amg_transfer")
         return out
 
-    def prolong(self, level: int, e: torch.Tensor, nrhs: int = 1) -> torch.Tensor:
+    def prolong(self, level: int, e: torch.Tensor, nrhs: int = 1, prec: int = F64) -> torch.Tensor:
+        dt = torch.complex128 if prec == F64 else torch.complex64
         dims, dof, V = self.level_info(level)
-        out = torch.empty((nrhs, V, dof), dtype=torch.complex128, device=e.device)
-        _check(load_library().amg_transfer(self._h, level, 1, _ptr(e.contiguous()), _ptr(out), nrhs, _stream()),
-               "amg_transfer")
+        out = torch.empty((nrhs, V, dof), dtype=dt, device=e.device)
+        _check(load_library().amg_transfer(self._h, level, 1, prec, _ptr(e.contiguous(), dt), _ptr(out, dt), nrhs,
+                                           _stream()), "amg_transfer")
+        return out
+
+    def prolongator(self, level: int, prec: int = F64) -> torch.Tensor:
+        """P of coarsening `level` as stored: (V_l, dof_l, 2 nvec_l) complex128."""
+        dims, dof, V = self.level_info(level)
+        nc = 2 * self.params.nvec[level]
+        out = torch.empty((V, dof, nc), dtype=torch.complex128, device="cuda")
+        _check(load_library().amg_get_prolongator(self._h, level, prec, _ptr(out), _stream()), "amg_get_prolongator")
         return out
 
     def coarse_op(self, level: int) -> torch.Tensor:

@@ -1142,4 +1142,39 @@ void launch_block_transpose(double2* out, const double2* in, long nblocks, int n
   if (nb > (1L << 20)) nb = 1L << 20;
   hipLaunchKernelGGL(block_transpose_kernel, dim3((unsigned)nb), dim3(256), 0, st, out, in, nblocks, nc);
 }
+
+namespace {
+// The stored prolongator as the dense rows of P at every fine site:
+// out[fs][comp][t] (t = chi N_v + k) = P(fs)[comp][k] when comp has
+// chirality chi, else 0; values of any storage kind widened to FP64.
+template <typename PT>
+__global__ void p_export_kernel(double2* __restrict__ out, const PT* __restrict__ P, TransferGeom g) {
+  const int nc = 2 * g.nv, hd = g.dof / 2;
+  const long total = g.Vf * g.dof * nc;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
+    const long fs = i / ((long)g.dof * nc);
+    const int rem = (int)(i - fs * g.dof * nc);
+    const int comp = rem / nc, t = rem - comp * nc;
+    long j; int xi;
+    BlockIdx::coarse_of(g, fs, j, xi);
+    double2 v = make_double2(0.0, 0.0);
+    if (comp / hd == t / g.nv) {
+      const cplx<double> z = ldp<double>(gl(P), ((j * g.bs + xi) * g.dof + comp) * (long)g.nv + t % g.nv);
+      v = z;
+    }
+    gl(out)[i] = v;
+  }
+}
+}  // namespace
+
+void launch_p_export(double2* out, const void* P, int pkind, const TransferGeom& g, hipStream_t st) {
+  long nb = (g.Vf * g.dof * 2 * g.nv + 255) / 256;
+  if (nb > (1L << 20)) nb = 1L << 20;
+  if (pkind == P_F64)
+    hipLaunchKernelGGL(p_export_kernel<double2>, dim3((unsigned)nb), dim3(256), 0, st, out, (const double2*)P, g);
+  else if (pkind == P_F32)
+    hipLaunchKernelGGL(p_export_kernel<float2>, dim3((unsigned)nb), dim3(256), 0, st, out, (const float2*)P, g);
+  else
+    hipLaunchKernelGGL(p_export_kernel<bf16x2>, dim3((unsigned)nb), dim3(256), 0, st, out, (const bf16x2*)P, g);
+}
 }  // namespace amg

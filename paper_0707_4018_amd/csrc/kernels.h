@@ -101,6 +101,19 @@ void launch_coarse_split(double2* out, const double2* in, const double2* Y, cons
 void launch_coarse_massmat(double2* out, const double2* in, const double2* M, const CoarseGeom& g,
                            int nrhs, hipStream_t st);
 
+// ---- exact coarsest solve (dense inverse) ----------------------------------------
+// A[N][N] (N = V nc, row-major) = the dense matrix of the block stencil Y
+void launch_dense_assemble(double2* A, const double2* Y, const CoarseGeom& g, hipStream_t st);
+// Gauss-Jordan inversion with partial pivoting of A (overwritten; B: second
+// N x N buffer).  key: N+1 u64, piv / used / pinv: N ints, err: 2 ints
+// (err[0] != 0 afterwards: singular).  Ainv32 may be NULL.
+void launch_gj_invert(double2* A, double2* B, long N, unsigned long long* key, int* piv, int* used, int* pinv,
+                      int* err, double2* Ainv, float2* Ainv32, hipStream_t st);
+// x[rhs] = Ainv b[rhs] (fields of N complex numbers per rhs)
+template <typename T>
+void launch_dense_apply(cplx<T>* x, const cplx<T>* b, const cplx<T>* Ainv, long N, int nrhs, const int* flags,
+                        hipStream_t st);
+
 // ---- transfers ----------------------------------------------------------------
 struct TransferGeom {
   int nd;
@@ -121,6 +134,8 @@ void launch_restrict(cplx<T>* out, const cplx<T>* in, const void* P, int pkind, 
 template <typename T>
 void launch_prolong(cplx<T>* out, const cplx<T>* in, const void* P, int pkind, const TransferGeom& g,
                     int nrhs, int accumulate, const int* flags, hipStream_t st);
+// the stored P (any kind) as dense rows per fine site: out[Vf][dof][2 nv] complex128
+void launch_p_export(double2* out, const void* P, int pkind, const TransferGeom& g, hipStream_t st);
 // block orthonormalisation (FP64): vecs [nv][per_rhs] in layout g.lf -> P [Vc][bs][dof][nv]
 void launch_orthonormalise(double2* P, const double2* vecs, const TransferGeom& g, int* err_flag,
                            hipStream_t st);

@@ -181,6 +181,10 @@ struct Level {
   // work vectors (per precision)
   Buf w64[W_COUNT], w32[W_COUNT];
   Buf Z64, W64, Z32, W32;  // GCR directions (coarsest level)
+  // exact coarsest solve: dense inverse of this level's operator (FP64, and
+  // FP32 for the FP32 cycle), valid while `dense` is set
+  Buf D64, D32;
+  bool dense = false;
   int alloc_nrhs = 0;
   // scalar slots
   int mr_slot = 0;
@@ -222,6 +226,11 @@ struct amg_solver {
   GcrSlots og;
   // setup temporaries
   Buf tE, tF, tS, tR, tzero;
+  // Gauss-Jordan work (two N x N matrices, pivot records)
+  Buf gjA, gjB, gjkey, gjint;
+  // batched solves run the coarsest level by GCR on every instance (one
+  // launch sequence for all of them)
+  bool no_dense = false;
   long long nD = 0, nDd = 0, nC = 0;
   // per-rhs mask of right-hand sides that are done (batched solves); nullptr otherwise
   int* outer_flags = nullptr;
@@ -535,7 +544,12 @@ void coarse_gcr(Solver& S, int l, const cplx<T>* b, cplx<T>* x, int nrhs, hipStr
 template <typename T>
 void vcycle(Solver& S, int l, int lstop, const cplx<T>* b, cplx<T>* x, int nrhs, hipStream_t st) {
   if (l == lstop) {
-    coarse_gcr<T>(S, l, b, x, nrhs, st);
+    Level& L = S.lv[l];
+    if (L.dense && !S.no_dense)
+      launch_dense_apply<T>(x, b, Pick<T>::prec == AMG_F64 ? (const cplx<T>*)L.D64.p : (const cplx<T>*)L.D32.p,
+                            L.V * L.dof, nrhs, S.outer_flags, st);
+    else
+      coarse_gcr<T>(S, l, b, x, nrhs, st);
     return;
   }
   Level& L = S.lv[l];
@@ -585,6 +599,36 @@ void to_canonical(const Solver& S, int l, const cplx<T>* in, double2* canon, int
 }
 
 // ---- setup ------------------------------------------------------------------
+// Dense inverse of the operator of coarse level l when it has at most
+// coarse_dense_max unknowns (the exact coarsest solve); otherwise the level
+// is solved by GCR when it is the coarsest one.
+void build_dense(Solver& S, int l, hipStream_t st) {
+  Level& L = S.lv[l];
+  const long N = L.V * L.dof;
+  L.dense = false;
+  if (L.fine || N > S.p.coarse_dense_max) return;
+  const size_t nn = (size_t)N * N;
+  S.gjA.ensure(nn * sizeof(double2));
+  S.gjB.ensure(nn * sizeof(double2));
+  S.gjkey.ensure((size_t)(N + 2) * sizeof(unsigned long long));
+  S.gjint.ensure((size_t)(3 * N + 8) * sizeof(int));
+  L.D64.ensure(nn * sizeof(double2));
+  const bool f32 = S.p.inner_prec == AMG_F32;
+  if (f32) L.D32.ensure(nn * sizeof(float2));
+  int* piv = S.gjint.as<int>();
+  int* used = piv + N;
+  int* pinv = used + N;
+  int* err = pinv + N;
+  launch_dense_assemble(S.gjA.as<double2>(), L.Y64.as<double2>(), L.cgeom(), st);
+  launch_gj_invert(S.gjA.as<double2>(), S.gjB.as<double2>(), N, S.gjkey.as<unsigned long long>(), piv, used, pinv,
+                   err, L.D64.as<double2>(), f32 ? L.D32.as<float2>() : nullptr, st);
+  int herr = 0;
+  HIPC(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPC(hipStreamSynchronize(st));
+  if (herr) fail(AMG_ERR_SINGULAR, "the operator of level " + std::to_string(l) + " is singular (exact coarsest solve)");
+  L.dense = true;
+}
+
 // Build P_l from the first L.nv raw vectors and A_{l+1} = P_l^dag A_l P_l.
 void build_transfer(Solver& S, int l, hipStream_t st) {
   Level& F = S.lv[l];
@@ -670,6 +714,7 @@ void build_transfer(Solver& S, int l, hipStream_t st) {
     C.Y32.ensure(C.V * ndir * (long)ncm * ncm * sizeof(float2));
     launch_p_convert(C.Y32.p, P_F32, C.Y64.as<double2>(), ysz, st);
   }
+  build_dense(S, l + 1, st);
 }
 
 void check_params(const amg_gauge* g, const amg_mg_params* p) {
@@ -683,6 +728,8 @@ void check_params(const amg_gauge* g, const amg_mg_params* p) {
   if (p->inner_prec != AMG_F64 && p->inner_prec != AMG_F32) fail(AMG_ERR_ARG, "bad inner_prec");
   if (p->kcycle_maxiter < 0 || p->kcycle_maxiter > GCR_KMAX) fail(AMG_ERR_ARG, "kcycle_maxiter must be 0..32");
   if (p->kcycle_maxiter > 0 && !(p->kcycle_tol >= 0.0 && std::isfinite(p->kcycle_tol))) fail(AMG_ERR_ARG, "bad kcycle_tol");
+  if (p->coarse_dense_max < 0 || p->coarse_dense_max > AMG_DENSE_MAX)
+    fail(AMG_ERR_ARG, "coarse_dense_max must be 0.." + std::to_string(AMG_DENSE_MAX));
   int dims[4];
   for (int mu = 0; mu < 4; ++mu) dims[mu] = g->dims[mu];
   int dof = g->dof;
@@ -1017,7 +1064,10 @@ struct amg_batch {
     if (gath_host) (void)hipHostFree(gath_host);
     if (flags_host) (void)hipHostFree(flags_host);
     if (st) (void)hipStreamDestroy(st);
-    for (Solver* s : S) s->outer_flags = nullptr;
+    for (Solver* s : S) {
+      s->outer_flags = nullptr;
+      s->no_dense = false;
+    }
   }
 };
 
@@ -1254,6 +1304,7 @@ const char* amg_status_str(amg_status s) {
     case AMG_ERR_RANK: return "linearly dependent near-null vectors";
     case AMG_ERR_NOCONV: return "not converged";
     case AMG_ERR_STATE: return "invalid state";
+    case AMG_ERR_SINGULAR: return "singular coarsest operator";
   }
   return "unknown status";
 }
@@ -1279,6 +1330,7 @@ void amg_default_params(amg_mg_params* p) {
   p->p_bf16 = 0;
   p->kcycle_tol = 0.1;
   p->kcycle_maxiter = 0;
+  p->coarse_dense_max = 4096;
 }
 
 amg_status amg_gauge_create(const amg_lattice* lat, const void* dev_links, double mass, void* stream,
@@ -1537,6 +1589,7 @@ amg_status amg_solver_set_mass(amg_solver* S, double mass) {
       launch_diag_shift(L.Y64.as<double2>(), L.M64.as<double2>(), L.V, L.dof, L.ndir(), dm, nullptr);
       if (S->p.inner_prec == AMG_F32)
         launch_p_convert(L.Y32.p, P_F32, L.Y64.as<double2>(), L.V * L.ndir() * (long)L.dof * L.dof, nullptr);
+      if (L.dense) build_dense(*S, (int)l, nullptr);
     }
     HIPC(hipStreamSynchronize(nullptr));
   }
@@ -1639,14 +1692,12 @@ amg_status amg_level_apply(const amg_solver* Sc, int level, int dagger, int prec
     op_apply<double>(*S, level, dagger, EPI_PLAIN, a, c, nullptr, nullptr, nrhs, S->sc.red(0), st);
     launch_convert<double, double>((double2*)dev_out, c, L.V, L.dof, L.lay64.W, L.dof, nrhs, st);
   } else {
+    // FP64 solvers have no FP32 work vectors on the fine level: size them
+    // for this call (no-op when they are large enough already)
+    L.w32[W_B].ensure((size_t)L.V * L.dof_max * nrhs * sizeof(float2));
+    L.w32[W_P].ensure((size_t)L.V * L.dof_max * nrhs * sizeof(float2));
     float2* a = L.w32[W_B].as<float2>();
     float2* c = L.w32[W_P].as<float2>();
-    if (!a) {
-      S->lv[level].w32[W_B].ensure((size_t)L.V * L.dof_max * nrhs * sizeof(float2));
-      S->lv[level].w32[W_P].ensure((size_t)L.V * L.dof_max * nrhs * sizeof(float2));
-      a = L.w32[W_B].as<float2>();
-      c = L.w32[W_P].as<float2>();
-    }
     launch_convert<float, float>(a, (const float2*)dev_in, L.V, L.dof, L.dof, L.lay32.W, nrhs, st);
     op_apply<float>(*S, level, dagger, EPI_PLAIN, a, c, nullptr, nullptr, nrhs, S->sc.red(0), st);
     launch_convert<float, float>((float2*)dev_out, c, L.V, L.dof, L.lay32.W, L.dof, nrhs, st);
@@ -1654,8 +1705,8 @@ amg_status amg_level_apply(const amg_solver* Sc, int level, int dagger, int prec
   AMG_CATCH
 }
 
-amg_status amg_transfer(const amg_solver* Sc, int level, int dir, const void* dev_in, void* dev_out, int nrhs,
-                        void* stream) {
+amg_status amg_transfer(const amg_solver* Sc, int level, int dir, int prec, const void* dev_in, void* dev_out,
+                        int nrhs, void* stream) {
   AMG_TRY
   check_ptr(Sc, "solver");
   check_ptr(dev_in, "in");
@@ -1663,19 +1714,51 @@ amg_status amg_transfer(const amg_solver* Sc, int level, int dir, const void* de
   amg_solver* S = const_cast<amg_solver*>(Sc);
   if (level < 0 || level + 1 >= (int)S->lv.size()) fail(AMG_ERR_ARG, "bad level");
   if (nrhs < 1 || nrhs > RHS_MAX) fail(AMG_ERR_ARG, "bad nrhs");
+  if (dir != 0 && dir != 1) fail(AMG_ERR_ARG, "dir must be 0 (restrict) or 1 (prolong)");
+  if (prec != AMG_F64 && prec != AMG_F32) fail(AMG_ERR_ARG, "bad precision");
+  if (prec == AMG_F32 && S->p.inner_prec != AMG_F32) fail(AMG_ERR_STATE, "no FP32 prolongator");
   hipStream_t st = as_stream(stream);
   ensure_work(*S, nrhs);
   Level& F = S->lv[level];
-  const TransferGeom tg = tgeom(*S, level, AMG_F64);
-  double2* a = S->otmp.as<double2>();
-  if (level > 0) a = F.w64[W_P].as<double2>();
-  if (dir == 0) {
-    launch_convert<double, double>(a, (const double2*)dev_in, F.V, F.dof, F.dof, F.lay64.W, nrhs, st);
-    launch_restrict<double>((double2*)dev_out, a, F.P64.p, P_F64, tg, nrhs, nullptr, st);
+  if (prec == AMG_F64) {
+    const TransferGeom tg = tgeom(*S, level, AMG_F64);
+    double2* a = S->otmp.as<double2>();
+    if (level > 0) a = F.w64[W_P].as<double2>();
+    if (dir == 0) {
+      launch_convert<double, double>(a, (const double2*)dev_in, F.V, F.dof, F.dof, F.lay64.W, nrhs, st);
+      launch_restrict<double>((double2*)dev_out, a, F.P64.p, P_F64, tg, nrhs, nullptr, st);
+    } else {
+      launch_prolong<double>(a, (const double2*)dev_in, F.P64.p, P_F64, tg, nrhs, 0, nullptr, st);
+      launch_convert<double, double>((double2*)dev_out, a, F.V, F.dof, F.lay64.W, F.dof, nrhs, st);
+    }
   } else {
-    launch_prolong<double>(a, (const double2*)dev_in, F.P64.p, P_F64, tg, nrhs, 0, nullptr, st);
-    launch_convert<double, double>((double2*)dev_out, a, F.V, F.dof, F.lay64.W, F.dof, nrhs, st);
+    // the FP32 cycle's transfer: P as the cycle stores it (FP32 or bfloat16)
+    const TransferGeom tg = tgeom(*S, level, AMG_F32);
+    int pk;
+    const void* P = Pstore<float>(*S, level, pk);
+    float2* a = F.w32[W_P].as<float2>();
+    if (dir == 0) {
+      launch_convert<float, float>(a, (const float2*)dev_in, F.V, F.dof, F.dof, F.lay32.W, nrhs, st);
+      launch_restrict<float>((float2*)dev_out, a, P, pk, tg, nrhs, nullptr, st);
+    } else {
+      launch_prolong<float>(a, (const float2*)dev_in, P, pk, tg, nrhs, 0, nullptr, st);
+      launch_convert<float, float>((float2*)dev_out, a, F.V, F.dof, F.lay32.W, F.dof, nrhs, st);
+    }
   }
+  AMG_CATCH
+}
+
+amg_status amg_get_prolongator(const amg_solver* Sc, int level, int prec, void* dev_out, void* stream) {
+  AMG_TRY
+  check_ptr(Sc, "solver");
+  check_ptr(dev_out, "out");
+  amg_solver* S = const_cast<amg_solver*>(Sc);
+  if (level < 0 || level + 1 >= (int)S->lv.size()) fail(AMG_ERR_ARG, "bad level");
+  if (prec != AMG_F64 && prec != AMG_F32) fail(AMG_ERR_ARG, "bad precision");
+  if (prec == AMG_F32 && S->p.inner_prec != AMG_F32) fail(AMG_ERR_STATE, "no FP32 prolongator");
+  int pk;
+  const void* P = prec == AMG_F64 ? Pstore<double>(*S, level, pk) : Pstore<float>(*S, level, pk);
+  launch_p_export((double2*)dev_out, P, pk, tgeom(*S, level, prec), as_stream(stream));
   AMG_CATCH
 }
 
@@ -1919,6 +2002,9 @@ amg_status amg_batch_create(amg_solver* const* solvers, const int* nrhs, int n, 
     for (int i = 0; i < n; ++i) {
       saved_mrhs[i] = B->S[i]->mrhs_min;
       B->S[i]->mrhs_min = batch_mrhs;
+      // the coarsest level by GCR on every instance: an exact (dense) solve on
+      // some instances and GCR on others would not merge stage by stage
+      B->S[i]->no_dense = true;
     }
     const int saved = red_block_cap();
     if (autotune) {
@@ -1962,6 +2048,7 @@ amg_status amg_batch_create(amg_solver* const* solvers, const int* nrhs, int n, 
     for (int i = 0; i < n; ++i) {
       B->S[i]->outer_flags = nullptr;
       B->S[i]->mrhs_min = saved_mrhs[i];
+      B->S[i]->no_dense = false;
     }
     HIPC(hipStreamSynchronize(B->st));
   } catch (...) {

@@ -18,8 +18,10 @@ def _instances(sizes, nrhs, mixed, seed=0):
         U = u1_config(L, L, beta=3.0 + i, sweeps=30, seed=seed + i)
         m = 0.02 + 0.01 * i
         A = mg.wilson_stencil(U, m)
+        # coarsest level by GCR (what batched solves run) also in the single solves compared with
         p = amg.MGParams(blocks=[(4, 4), (2, 2)], nvec=[4, 4], coarse_tol=0.1, coarse_maxiter=40,
-                         kcycle_tol=0.1, kcycle_maxiter=4, inner_prec=amg.F32 if mixed else amg.F64, p_bf16=mixed)
+                         kcycle_tol=0.1, kcycle_maxiter=4, inner_prec=amg.F32 if mixed else amg.F64, p_bf16=mixed,
+                         coarse_dense_max=0)
         g = amg.Gauge(dev(U), m)
         V1 = (L // 4) ** 2
         init = [vectors(4, L * L, 2, 100 + i), vectors(4, V1, 8, 200 + i)]
@@ -74,10 +76,10 @@ def test_fused_gcr_step_matches_oracle_vcycle(monkeypatch):
     A = mg.wilson_stencil(U, 0.02)
     vecs = [vectors(4, A.V, 2, 7), vectors(8, 64, 8, 8)]
     po = mg.MGParams(blocks=[(4, 4), (2, 2)], nvec=[4, 8], coarse_tol=0.0, coarse_maxiter=12, coarse_restart=5,
-                     kcycle_tol=0.0, kcycle_maxiter=3)
+                     kcycle_tol=0.0, kcycle_maxiter=3, coarse_dense_max=0)
     H = mg.build_hierarchy(A, vecs, po)
     pg = amg.MGParams(blocks=[(4, 4), (2, 2)], nvec=[4, 8], coarse_tol=0.0, coarse_maxiter=12, coarse_restart=5,
-                      kcycle_tol=0.0, kcycle_maxiter=3)
+                      kcycle_tol=0.0, kcycle_maxiter=3, coarse_dense_max=0)
     S = amg.Solver(amg.Gauge(dev(U), 0.02), pg, nullvecs=[dev(v) for v in vecs])
     b = synth.gaussian_field((1, A.V, 2, 1), synth.rng_for(9))
     x = host(S.vcycle(dev(b)))[0].reshape(A.V, 2)

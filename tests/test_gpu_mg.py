@@ -96,13 +96,16 @@ def test_coarse_apply_and_mr_match_oracle():
     assert rel_err(out, Ac.apply(e[0])) < 1e-5
 
 
+@pytest.mark.parametrize("dense", [4096, 0])
 @pytest.mark.parametrize("blocks,nvec,kc", [([(4, 4)], [6], 0), ([(4, 4), (2, 2)], [4, 4], 0),
                                             ([(4, 4), (2, 2)], [4, 4], 3), ([(4, 4)], [8], 0),
                                             ([(4, 4), (2, 2)], [4, 8], 3)])
-def test_vcycle_matches_oracle(blocks, nvec, kc):
-    print(f"vcycle {blocks} {nvec} kcycle {kc}", flush=True)
+def test_vcycle_matches_oracle(blocks, nvec, kc, dense):
+    """dense = 4096: the coarsest level is solved exactly (dense inverse);
+    dense = 0: by GCR (12 steps, restart 5) on both sides."""
+    print(f"vcycle {blocks} {nvec} kcycle {kc} dense {dense}", flush=True)
     U, A, H, g, S = _given(32, 32, blocks, nvec, m=0.02, coarse_tol=0.0, coarse_maxiter=12, coarse_restart=5,
-                           kcycle_tol=0.0 if kc else None, kcycle_maxiter=kc if kc else 8)
+                           kcycle_tol=0.0 if kc else None, kcycle_maxiter=kc if kc else 8, coarse_dense_max=dense)
     assert (S.params.kcycle_maxiter > 0) == bool(kc)
     b = synth.gaussian_field((1, A.V, 2, 1), synth.rng_for(9))
     x = host(S.vcycle(dev(b)))[0].reshape(A.V, 2)
@@ -378,3 +381,143 @@ def test_mr_on_streaming_size_lattices(L1, L2):
     assert max_rel_err(x1.reshape(-1), xo.reshape(-1)) < 1e-12
     x32 = host(S.mr(0, 3, dev(b, torch.complex64), prec=amg.F32))
     assert rel_err(x32.reshape(-1), xo.reshape(-1)) < 1e-5
+
+
+def _bf16_round(a: np.ndarray) -> np.ndarray:
+    """Round float32 values to bfloat16 (nearest, ties to even), returned widened."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
+    return u.astype(np.uint32).view(np.float32)
+
+
+def _rounded_prolongator(P: "mg.Prolongator", Q: np.ndarray) -> "mg.Prolongator":
+    return mg.Prolongator(P.fine_dims, P.block, P.dof, P.nvec, Q, P.blk)
+
+
+@pytest.mark.parametrize("case,bf16", [("2d", False), ("2d", True), ("4d", False), ("4d", True)])
+def test_fp32_transfers_match_oracle_on_stored_prolongator(case, bf16):
+    """FP32 restriction / prolongation (the kernels of the FP32 cycle, P in FP32
+    or bfloat16) element by element against the oracle's transfers built on
+    the prolongator the library stores; the stored P itself is the oracle's
+    FP64 P rounded (bit-exactly for the bfloat16 rounding of the library's
+    FP64 P)."""
+    import torch
+    import paper_0707_4018_amd as amg
+    print(f"fp32 transfers {case} bf16={bf16}", flush=True)
+    if case == "2d":
+        dims, block, nv, dof = (32, 16), (4, 4), 8, 2
+        U = u1_config(*dims)
+        rhs_list = [1, 3]
+    else:
+        dims, block, nv, dof = (8, 4, 4, 8), (4, 4, 4, 4), 24, 12
+        U = su3_config(dims, seed=10, smear=2)
+        rhs_list = [1, 5, 12]
+    A = mg.wilson_stencil(U, 0.1)
+    vecs = [vectors(nv, A.V, dof, 61)]
+    po, pg = _params([block], [nv], inner_prec=amg.F32, p_bf16=bf16)
+    H = mg.build_hierarchy(A, vecs, po)
+    S = amg.Solver(amg.Gauge(dev(U), 0.1), pg, nullvecs=[dev(v) for v in vecs])
+    P64 = host(S.prolongator(0, amg.F64))
+    P32 = host(S.prolongator(0, amg.F32))
+    if bf16:
+        # with bfloat16 storage the library rounds its FP64 P as well (the
+        # Galerkin operator is built from the P the transfers use): the FP64
+        # copy lies on the bfloat16 grid, within one bfloat16 step of the
+        # oracle's P, and the stored copy holds the same values
+        on_grid = _bf16_round(P64.real.astype(np.float32)) + 1j * _bf16_round(P64.imag.astype(np.float32))
+        assert np.array_equal(P64, on_grid.astype(np.complex128))
+        assert np.abs(P64 - H.Ps[0].Q).max() <= 2.0 ** -8 * np.abs(H.Ps[0].Q).max()
+        assert np.array_equal(P32, P64)
+    else:
+        assert max_rel_err(P64, H.Ps[0].Q) < 1e-12
+        ref = P64.real.astype(np.float32) + 1j * P64.imag.astype(np.float32)
+        assert np.array_equal(P32, ref.astype(np.complex128))
+    Pr = _rounded_prolongator(H.Ps[0], P32)
+    ns, nc = (2, 1) if case == "2d" else (4, 3)
+    for nrhs in rhs_list:
+        r = synth.gaussian_field((nrhs, A.V, ns, nc), synth.rng_for(62, nrhs))
+        e = synth.gaussian_field((nrhs, Pr.Vc, Pr.nc), synth.rng_for(63, nrhs))
+        r32 = r.astype(np.complex64)
+        e32 = e.astype(np.complex64)
+        rc = host(S.restrict(0, dev(r32), nrhs=nrhs, prec=amg.F32))
+        pe = host(S.prolong(0, dev(e32), nrhs=nrhs, prec=amg.F32))
+        for i in range(nrhs):
+            ro = Pr.restrict(r32[i].astype(np.complex128).reshape(A.V, dof))
+            po_ = Pr.prolong(e32[i].astype(np.complex128))
+            assert max_rel_err(rc[i], ro) < 2e-6, (nrhs, i)
+            assert max_rel_err(pe[i].reshape(A.V, dof), po_) < 2e-6, (nrhs, i)
+
+
+class _Wilson4dOp:
+    """The oracle's D (the formula, dirac.apply_D) for fields of shape (V, 12):
+    what mg.mr needs, without the per-site block matrices of a Stencil."""
+
+    def __init__(self, U, m):
+        from oracle import dirac
+        self.U, self.m, self.dirac = U, m, dirac
+        self.lat = U.shape[1:5]
+        self.V = int(np.prod(self.lat))
+
+    def apply(self, f):
+        return self.dirac.apply_D(self.U, f.reshape(self.lat + (4, 3)), self.m).reshape(self.V, 12)
+
+
+@pytest.mark.parametrize("nrhs", [1, 12])
+def test_four_dimensional_fp32_mr_multi_slab(nrhs):
+    """FP32 MR on a 16^3 x 64 fine level: the stencil with the MR sums marches
+    x_4 in four slabs of 16 sites, 64 blocks per rhs renumbered by XCD, with
+    the grid reduction across them; against the oracle's MR on its D."""
+    import torch
+    import paper_0707_4018_amd as amg
+    print(f"4d fp32 MR 16^3x64 nrhs={nrhs}", flush=True)
+    base, tile = (8, 8, 8, 8), (2, 2, 2, 8)
+    dims = tuple(b * t for b, t in zip(base, tile))
+    U = np.tile(su3_config(base, seed=12, smear=2), (1,) + tuple(reversed(tile)) + (1, 1))
+    m = 0.1
+    V = int(np.prod(dims))
+    _, pg = _params([(4, 4, 4, 4)], [2], inner_prec=amg.F32)
+    vv = synth.gaussian_field((2, V, 12), synth.rng_for(64))
+    S = amg.Solver(amg.Gauge(dev(U), m), pg, nullvecs=[dev(vv)])
+    b = synth.gaussian_field((nrhs, V, 4, 3), synth.rng_for(65, nrhs))
+    x = host(S.mr(0, 3, dev(b, torch.complex64), nrhs=nrhs, prec=amg.F32))
+    Aop = _Wilson4dOp(U, m)
+    for r in ([0, nrhs - 1] if nrhs > 1 else [0]):
+        xo = mg.mr(Aop, b[r].reshape(V, 12), 3, 0.8)[0]
+        assert max_rel_err(x[r].reshape(-1), xo.reshape(-1)) < 1e-5, r
+
+
+@pytest.mark.parametrize("dense", [4096, 0])
+def test_three_level_adaptive_vectors_match_oracle(dense):
+    """Adaptive setup on three levels (32^2 -> 8^2 -> 4^2): the vectors of both
+    coarsenings equal the oracle's from the same random starts."""
+    import paper_0707_4018_amd as amg
+    print(f"3-level adaptive vectors dense={dense}", flush=True)
+    U = u1_config(32, 32, beta=6.0, sweeps=60, seed=5)
+    m = 0.03
+    A = mg.wilson_stencil(U, m)
+    po, pg = _params([(4, 4), (2, 2)], [4, 4], coarse_tol=0.05, coarse_maxiter=60, coarse_restart=16,
+                     coarse_dense_max=dense)
+    init = [vectors(4, A.V, 2, 71), vectors(4, 64, 8, 72)]
+    Ho, vo = mg.adaptive_setup(A, po, init, nu0=10, ncyc=2)
+    S = amg.Solver(amg.Gauge(dev(U), m), pg, init=[dev(v) for v in init], nu0=10, ncyc=2)
+    for lvl in range(2):
+        v = host(S.nullvecs(lvl))
+        assert rel_err(v, vo[lvl]) < 1e-7, lvl
+    Y2 = host(S.coarse_op(2))
+    assert max_rel_err(Y2[:, 0], Ho.ops[2].diag) < 1e-7
+
+
+def test_level_apply_fp32_on_fp64_solver_grows_buffers():
+    """FP32 fine-level applies on an FP64 solver, first with one right-hand side
+    and then with four (the FP32 work buffers must grow), against the oracle."""
+    import torch
+    import paper_0707_4018_amd as amg
+    from oracle import dirac
+    print("level_apply fp32 on fp64 solver, nrhs 1 then 4", flush=True)
+    U, A, H, g, S = _given(16, 16, [(4, 4)], [4])
+    for nrhs in (1, 4):
+        psi = synth.gaussian_field((nrhs, A.V, 2, 1), synth.rng_for(66, nrhs))
+        out = host(S.level_apply(0, dev(psi, torch.complex64), prec=amg.F32, nrhs=nrhs))
+        for k in range(nrhs):
+            ref = dirac.apply_D(U, psi[k].reshape(16, 16, 2, 1), 0.05).reshape(-1, 2, 1)
+            assert max_rel_err(out[k], ref) < 1e-5, (nrhs, k)

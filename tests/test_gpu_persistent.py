@@ -17,7 +17,7 @@ def _setup(amg, L, ctol, prec=None):
     V1 = (L // 4) ** 2
     vecs = [vectors(4, A.V, 2, 7), vectors(8, V1, 8, 8)]
     kw = dict(blocks=[(4, 4), (2, 2)], nvec=[4, 8], coarse_tol=ctol, coarse_maxiter=12, coarse_restart=5,
-              kcycle_tol=0.0, kcycle_maxiter=3)
+              kcycle_tol=0.0, kcycle_maxiter=3, coarse_dense_max=0)
     H = mg.build_hierarchy(A, vecs, mg.MGParams(**kw))
     if prec is not None:
         kw["inner_prec"] = prec
