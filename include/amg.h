@@ -142,6 +142,20 @@ amg_status amg_gauge_destroy(amg_gauge* g);
 amg_status amg_apply(const amg_gauge* g, int dagger, int prec, const void* dev_in,
                      void* dev_out, int nrhs, void* stream);
 
+/* As amg_apply, for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the call allocates nothing.  The two layout conversions are staged in a
+ * fixed device array of 64 MiB (each GPU the library runs on holds its own
+ * copy until the process ends) instead of the handle's buffers, so
+ * 2 * V * dof * nrhs complex numbers of precision prec (each half rounded up
+ * to 256 bytes) must fit in 64 MiB, else AMG_ERR_ARG before any launch.  Same
+ * kernels and results as amg_apply.  Every call on one GPU shares that GPU's
+ * array: calls that overlap on one GPU (other streams, other threads) race.
+ * The current device must be the one the gauge handle was created on
+ * (AMG_ERR_STATE). */
+amg_status amg_apply_noalloc(const amg_gauge* g, int dagger, int prec, const void* dev_in,
+                             void* dev_out, int nrhs, void* stream);
+
 /* Apply the fine stencil `iters` times on the handle's internal
  * structure-of-arrays buffers (no layout conversion): the kernel that the
  * solver runs, for bandwidth measurement.  Enqueued on `stream`. */

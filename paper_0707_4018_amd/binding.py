@@ -65,6 +65,7 @@ _SIGS = {
     "amg_gauge_destroy": (C.c_int, [_P]),
     "amg_apply": (C.c_int, [_P, C.c_int, C.c_int, _P, _P, C.c_int, _P]),
     "amg_apply_internal": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, C.c_int, _P]),
+    "amg_apply_noalloc": (C.c_int, [_P, C.c_int, C.c_int, _P, _P, C.c_int, _P]),
     "amg_cgnr_solve": (C.c_int, [_P, _P, _P, C.c_double, C.c_int, C.POINTER(_Info), _P]),
     "amg_setup": (C.c_int, [_P, C.POINTER(_Params), C.POINTER(_P), _P, C.POINTER(_P)]),
     "amg_setup_adaptive": (C.c_int, [_P, C.POINTER(_Params), C.POINTER(_P), C.c_int, C.c_int, _P,
@@ -264,6 +265,13 @@ class Gauge:
         _check(load_library().amg_apply(self._h, int(dagger), prec, _ptr(x, dt), _ptr(out, dt), nrhs, _stream()),
                "amg_apply")
         return out
+
+    def apply_noalloc(self, psi: torch.Tensor, out: torch.Tensor, dagger: bool = False, prec: int = F64) -> None:
+        """amg_apply_noalloc into a caller-provided `out` (no device allocation by the library)."""
+        dt = torch.complex128 if prec == F64 else torch.complex64
+        nrhs = psi.shape[0] if psi.dim() == 4 else 1
+        _check(load_library().amg_apply_noalloc(self._h, int(dagger), prec, _ptr(psi, dt), _ptr(out, dt), nrhs,
+                                                 _stream()), "amg_apply_noalloc")
 
     def apply_internal(self, dagger: bool, prec: int, nrhs: int, iters: int):
         _check(load_library().amg_apply_internal(self._h, int(dagger), prec, nrhs, iters, _stream()),

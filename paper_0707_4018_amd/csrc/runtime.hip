@@ -13,6 +13,7 @@
 #include <cstring>
 #include <string>
 #include <type_traits>
+#include <mutex>
 #include <vector>
 
 #include "amg.h"
@@ -120,6 +121,7 @@ struct GcrSlots {
 // gauge handle
 // ---------------------------------------------------------------------------
 struct amg_gauge {
+  int device = 0;  // HIP device holding the buffers
   int nd = 2;
   int dims[4] = {1, 1, 1, 1};
   long V = 0;
@@ -1357,6 +1359,7 @@ amg_status amg_gauge_create(const amg_lattice* lat, const void* dev_links, doubl
     g->ns = lat->nd == 2 ? 2 : 4;
     g->dof = g->nc * g->ns;
     g->mass = mass;
+    HIPC(hipGetDevice(&g->device));
     if (g->nd == 2) {
       g->U64.ensure((size_t)2 * V * sizeof(double2));
       g->U32.ensure((size_t)2 * V * sizeof(float2));
@@ -1420,6 +1423,76 @@ amg_status amg_apply(const amg_gauge* gc, int dagger, int prec, const void* dev_
                         nrhs, g->sc.red(0), st);
     launch_convert<float, float>((float2*)dev_out, g->tout.as<float2>(), g->V, g->dof, W, g->dof, nrhs, st);
   }
+  AMG_CATCH
+}
+
+}  // extern "C"
+
+// ---- the application of D that allocates nothing ------------------------------
+// Staging of the two layout conversions in a fixed device array instead of
+// the handle's buffers.  Each GPU that runs the library holds its own copy of
+// the array until the process ends; host code reaches it only through the
+// per-device address taken with hipGetSymbolAddress (the array's name is a
+// host-side stand-in, not a device address).
+namespace {
+constexpr size_t kNoallocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) double2 scratch[kNoallocScratchBytes / sizeof(double2)];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// device address of this device's copy of `scratch` (taken once per device,
+// with that device current)
+void* scratch_ptr(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) fail(AMG_ERR_STATE, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    HIPC(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (p == nullptr) fail(AMG_ERR_HIP, "hipGetSymbolAddress returned no address for the scratch array");
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+}  // namespace
+
+extern "C" {
+
+amg_status amg_apply_noalloc(const amg_gauge* g, int dagger, int prec, const void* dev_in, void* dev_out, int nrhs,
+                             void* stream) {
+  AMG_TRY
+  check_ptr(g, "gauge");
+  check_ptr(dev_in, "in");
+  check_ptr(dev_out, "out");
+  if (dev_in == dev_out) fail(AMG_ERR_ARG, "in-place application is not supported");
+  if (nrhs < 1 || nrhs > RHS_MAX) fail(AMG_ERR_ARG, "bad nrhs");
+  if (prec != AMG_F64 && prec != AMG_F32) fail(AMG_ERR_ARG, "bad precision");
+  const size_t es = prec == AMG_F64 ? sizeof(double2) : sizeof(float2);
+  const size_t half = (((size_t)g->V * g->dof * nrhs * es) + 255) & ~size_t(255);
+  if (2 * half > kNoallocScratchBytes)
+    fail(AMG_ERR_ARG, "amg_apply_noalloc: 2 x V x dof x nrhs complex numbers (" + std::to_string(2 * half) +
+                          " bytes) exceed the scratch array of " + std::to_string(kNoallocScratchBytes) + " bytes");
+  int dev = 0;
+  HIPC(hipGetDevice(&dev));
+  if (dev != g->device) fail(AMG_ERR_STATE, "the current device is not the gauge handle's device");
+  char* base = static_cast<char*>(scratch_ptr(dev));
+  hipStream_t st = as_stream(stream);
+  const int W = prec == AMG_F64 ? 1 : 2;
+  if (prec == AMG_F64) {
+    double2* tin = reinterpret_cast<double2*>(base);
+    double2* tout = reinterpret_cast<double2*>(base + half);
+    launch_convert<double, double>(tin, (const double2*)dev_in, g->V, g->dof, g->dof, W, nrhs, st);
+    wilson_apply<double>(*g, g->mass, dagger, EPI_PLAIN, tin, tout, nullptr, nullptr, nrhs, g->sc.red(0), st);
+    launch_convert<double, double>((double2*)dev_out, tout, g->V, g->dof, W, g->dof, nrhs, st);
+  } else {
+    float2* tin = reinterpret_cast<float2*>(base);
+    float2* tout = reinterpret_cast<float2*>(base + half);
+    launch_convert<float, float>(tin, (const float2*)dev_in, g->V, g->dof, g->dof, W, nrhs, st);
+    wilson_apply<float>(*g, g->mass, dagger, EPI_PLAIN, tin, tout, nullptr, nullptr, nrhs, g->sc.red(0), st);
+    launch_convert<float, float>((float2*)dev_out, tout, g->V, g->dof, W, g->dof, nrhs, st);
+  }
+  HIPC(hipGetLastError());
   AMG_CATCH
 }
 
