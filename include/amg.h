@@ -81,8 +81,9 @@ typedef struct {
   int p_bf16;           /* with AMG_F32: store P in bfloat16 (Galerkin uses the rounded P) */
   double kcycle_tol;    /* intermediate levels: flexible GCR preconditioned by their own cycle */
   int kcycle_maxiter;   /*   to kcycle_tol, at most kcycle_maxiter (<= 32) steps; 0: V-cycle */
-  int coarse_dense_max; /* a coarsest level of at most this many unknowns (V * dof, <= AMG_DENSE_MAX)
-                         * is solved exactly: the recursion of the V-cycle ends in a direct solve
+  int coarse_dense_max; /* a coarsest level of at most this many unknowns (V * 2 nvec of the finished
+                         * level, <= AMG_DENSE_MAX; the adaptive setup's partially built levels follow
+                         * the finished level) is solved exactly: the recursion of the V-cycle ends in a direct solve
                          * (the five-step list before Eq. (3)).  The dense matrix of its Galerkin
                          * operator is inverted at setup (and after a mass change) by Gauss-Jordan
                          * elimination with partial pivoting in FP64 (AMG_ERR_SINGULAR if a pivot

@@ -437,6 +437,11 @@ class Hierarchy:
     Ps: list                          # Prolongator per coarsening
     params: MGParams
     mass_mats: list = None            # d(op)/dm per level (per-site blocks)
+    exact: list = None                # per level: solved exactly when it is the coarsest level of a cycle
+
+    def __post_init__(self):
+        if self.exact is None:
+            self.exact = [A.V * A.dof <= self.params.coarse_dense_max for A in self.ops]
 
     @property
     def nlevels(self) -> int:
@@ -491,12 +496,13 @@ def dense_solve(A: Stencil, b: np.ndarray) -> np.ndarray:
     return sla.lu_solve(A._lu, b.reshape(-1)).reshape(b.shape)
 
 
-def coarsest_solve(A: Stencil, b: np.ndarray, p: MGParams) -> np.ndarray:
-    """Solve on the coarsest level.  The paper solves its coarsest lattice
-    exactly; that is done here whenever it has at most coarse_dense_max
-    unknowns.  A larger coarsest level is solved approximately by GCR to
-    coarse_tol (see gcr_coarse; the outer Krylov method is flexible)."""
-    if A.V * A.dof <= p.coarse_dense_max:
+def coarsest_solve(A: Stencil, b: np.ndarray, p: MGParams, exact: bool) -> np.ndarray:
+    """Solve on the coarsest level of a cycle.  The paper solves its coarsest
+    lattice exactly; that is done here for a level marked exact (one of at
+    most coarse_dense_max unknowns when all its near-null vectors are in
+    place).  Other levels are solved approximately by GCR to coarse_tol (see
+    gcr_coarse; the outer Krylov method is flexible)."""
+    if exact:
         return dense_solve(A, b)
     return gcr_coarse(A, b, p.coarse_tol, p.coarse_maxiter, p.coarse_restart)
 
@@ -515,7 +521,7 @@ def vcycle(H: Hierarchy, level: int, b: np.ndarray) -> np.ndarray:
     p = H.params
     A = H.ops[level]
     if level == H.nlevels - 1:
-        return coarsest_solve(A, b, p)
+        return coarsest_solve(A, b, p, H.exact[level])
     relax = mr if p.smoother is None else p.smoother
     P = H.Ps[level]
     x, r = relax(A, b, p.nu_pre, p.omega)
@@ -550,7 +556,7 @@ def with_mass(H: Hierarchy, dm: float) -> Hierarchy:
     """Reuse the setup at another mass (the paper reuses the null vectors of the
     lightest mass for heavier ones): every level shifts by dm times P^dag...P."""
     ops = [A.shifted(dm, M) for A, M in zip(H.ops, H.mass_mats)]
-    return Hierarchy(ops, H.Ps, H.params, H.mass_mats)
+    return Hierarchy(ops, H.Ps, H.params, H.mass_mats, H.exact)
 
 
 def mg_solve(H: Hierarchy, b: np.ndarray, tol: float = 1e-10, maxiter: int = 500):
@@ -576,7 +582,9 @@ def adaptive_setup(A0: Stencil, params: MGParams, init: list, nu0: int = 20, ncy
            from {v_1} and A_{l+1} = P_l^dag A_l P_l;
       (ii) for k = 2..N_v: e = init[l][k-1]; apply ncyc sweeps of the
            two-level error propagation e <- e - V(A_l e) (A_{l+1} solved as
-           the coarsest level); v_k = e/||e||; rebuild P_l and A_{l+1}.
+           the coarsest level: exactly if the finished level, with all N_v
+           vectors, has at most coarse_dense_max unknowns, else by GCR);
+           v_k = e/||e||; rebuild P_l and A_{l+1}.
     With l fixed, the procedure recurses on A_{l+1} (the method is recursive).
     Returns (hierarchy, vecs) with vecs[l] of shape (N_v, V_l, dof_l).
     """
@@ -591,7 +599,8 @@ def adaptive_setup(A0: Stencil, params: MGParams, init: list, nu0: int = 20, ncy
             Ac = galerkin(A, P)
             if k == nv:
                 break
-            H2 = Hierarchy([A, Ac], [P], params)
+            exact_c = Ac.V * 2 * nv <= params.coarse_dense_max
+            H2 = Hierarchy([A, Ac], [P], params, exact=[False, exact_c])
             e = init[lvl][k].astype(np.complex128).copy()
             for _ in range(ncyc):
                 e = e - vcycle(H2, 0, A.apply(e))

@@ -601,14 +601,16 @@ void to_canonical(const Solver& S, int l, const cplx<T>* in, double2* canon, int
 }
 
 // ---- setup ------------------------------------------------------------------
-// Dense inverse of the operator of coarse level l when it has at most
-// coarse_dense_max unknowns (the exact coarsest solve); otherwise the level
-// is solved by GCR when it is the coarsest one.
+// Dense inverse of the operator of coarse level l (the exact coarsest
+// solve) when the finished level, with all its near-null vectors, has at
+// most coarse_dense_max unknowns; the adaptive setup's partial levels follow
+// the finished level's choice.  Otherwise the level is solved by GCR when it
+// is the coarsest one of a cycle.
 void build_dense(Solver& S, int l, hipStream_t st) {
   Level& L = S.lv[l];
   const long N = L.V * L.dof;
   L.dense = false;
-  if (L.fine || N > S.p.coarse_dense_max) return;
+  if (L.fine || L.V * (long)L.dof_max > S.p.coarse_dense_max) return;
   const size_t nn = (size_t)N * N;
   S.gjA.ensure(nn * sizeof(double2));
   S.gjB.ensure(nn * sizeof(double2));

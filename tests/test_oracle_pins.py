@@ -203,20 +203,24 @@ def test_kcycle_one_step_is_minimal_residual_multiple():
 
 
 def test_dense_coarsest_solve_is_exact():
-    """The coarsest solve below the dense limit returns A^-1 b (checked by the
-    residual with the oracle's own operator and against numpy's solve of the
-    sparse triple product P^dag D P)."""
+    """The exact coarsest solve returns A^-1 b (against numpy's solve of the
+    sparse triple product P^dag D P); a hierarchy marks a level exact by its
+    size, and the adaptive setup by the size of the finished level."""
     U = _field(8, 8, seed=6)
     A = mg.wilson_stencil(U, 0.05)
     P = mg.build_prolongator(_vecs(4, A.V, 2, 5), A.dims, (4, 4))
     Ac = mg.galerkin(A, P)
     b = synth.gaussian_field((Ac.V, Ac.dof), synth.rng_for(99, 6))
-    x = mg.coarsest_solve(Ac, b, mg.MGParams(blocks=[(4, 4)], nvec=[4]))
+    x = mg.coarsest_solve(Ac, b, mg.MGParams(blocks=[(4, 4)], nvec=[4]), exact=True)
     Ps = P.to_sparse()
     M = (Ps.conj().T @ A.to_sparse() @ Ps).toarray()
     ref = np.linalg.solve(M, b.ravel())
     assert mg.norm(x.ravel() - ref) < 1e-12 * mg.norm(ref)
-    # above the limit the same call runs GCR to coarse_tol
-    x2 = mg.coarsest_solve(Ac, b, mg.MGParams(blocks=[(4, 4)], nvec=[4], coarse_dense_max=0, coarse_tol=1e-2))
+    # a level not marked exact is solved by GCR to coarse_tol
+    x2 = mg.coarsest_solve(Ac, b, mg.MGParams(blocks=[(4, 4)], nvec=[4], coarse_tol=1e-2), exact=False)
     assert mg.norm(b - Ac.apply(x2)) <= 1e-2 * mg.norm(b)
     assert mg.norm(x2.ravel() - ref) > 1e-9 * mg.norm(ref)
+    p = mg.MGParams(blocks=[(4, 4)], nvec=[4], coarse_dense_max=Ac.V * Ac.dof)
+    assert mg.Hierarchy([A, Ac], [P], p).exact == [False, True]
+    p.coarse_dense_max -= 1
+    assert mg.Hierarchy([A, Ac], [P], p).exact == [False, False]
