@@ -288,6 +288,10 @@ amg_status amg_batch_destroy(amg_batch* b);
  * 4 coarse block stencil with the MR epilogue only. */
 amg_status amg_profile_enable(amg_solver* s, int kind, int level, int enable);
 amg_status amg_profile_read(amg_solver* s, double* total_ms, long long* launches);
+/* kind = -1 and / or level = -1 in amg_profile_enable time every kind / level
+ * (kind 1 then excludes the launches counted as kind 4); this returns the
+ * part of the recorded launches of one (kind, level). */
+amg_status amg_profile_read_kind(amg_solver* s, int kind, int level, double* total_ms, long long* launches);
 
 /* Introspection: lattice extents and dof per site of a level. */
 amg_status amg_level_info(const amg_solver* s, int level, int* dims4, int* dof, long long* V);

@@ -88,6 +88,7 @@ _SIGS = {
     "amg_batch_info": (C.c_int, [_P, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "amg_batch_destroy": (C.c_int, [_P]),
     "amg_profile_read": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_longlong)]),
+    "amg_profile_read_kind": (C.c_int, [_P, C.c_int, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_longlong)]),
     "amg_setup_adaptive_levels": (C.c_int, [_P, C.POINTER(_Params), C.POINTER(_P), C.POINTER(C.c_int),
                                             C.POINTER(C.c_int), _P, C.POINTER(_P)]),
     "amg_setup_refined": (C.c_int, [_P, C.POINTER(_Params), _P, C.c_int, C.c_int, C.c_int, C.POINTER(_P), C.c_int,
@@ -475,11 +476,16 @@ class Solver:
         """Time every launch of kernel `kind` on `level` with HIP events."""
         _check(load_library().amg_profile_enable(self._h, kind, level, int(enable)), "amg_profile_enable")
 
-    def profile_read(self):
-        """(summed kernel milliseconds, launches) since profile(); synchronises."""
+    def profile_read(self, kind: int | None = None, level: int | None = None):
+        """(summed kernel milliseconds, launches) since profile(); synchronises.
+        With kind and level: the part of one (kind, level) of an all-kinds profile."""
         ms = C.c_double()
         n = C.c_longlong()
-        _check(load_library().amg_profile_read(self._h, C.byref(ms), C.byref(n)), "amg_profile_read")
+        if kind is None:
+            _check(load_library().amg_profile_read(self._h, C.byref(ms), C.byref(n)), "amg_profile_read")
+        else:
+            _check(load_library().amg_profile_read_kind(self._h, int(kind), int(level), C.byref(ms), C.byref(n)),
+                   "amg_profile_read_kind")
         return ms.value, n.value
 
     def __del__(self):

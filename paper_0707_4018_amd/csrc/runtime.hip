@@ -251,8 +251,9 @@ struct amg_solver {
   // kernel timing
   struct Prof {
     bool on = false;
-    int kind = -1, level = -1;
+    int kind = -1, level = -1;   // -1: every kind / every level
     std::vector<hipEvent_t> ev;  // start/stop pairs, reused
+    std::vector<int> tag;        // (kind << 8 | level) of each pair
     size_t used = 0;
     hipStream_t last = nullptr;
   } prof;
@@ -273,7 +274,9 @@ struct ProfScope {
   bool active;
   hipStream_t st;
   ProfScope(Solver& s, int kind, int level, hipStream_t stream)
-      : S(s), active(s.prof.on && s.prof.kind == kind && s.prof.level == level && current_recorder() == nullptr),
+      : S(s),
+        active(s.prof.on && (s.prof.kind == kind || s.prof.kind < 0) && (s.prof.level == level || s.prof.level < 0) &&
+               current_recorder() == nullptr),
         st(stream) {
     if (!active) return;
     auto& P = S.prof;
@@ -282,6 +285,8 @@ struct ProfScope {
       HIPC(hipEventCreate(&e));
       P.ev.push_back(e);
     }
+    if (P.tag.size() < P.used / 2 + 1) P.tag.resize(P.used / 2 + 1);
+    P.tag[P.used / 2] = (kind << 8) | level;
     // the scope's (first) kernel launch stamps the pair
     pending_timing() = LaunchTiming{P.ev[P.used], P.ev[P.used + 1]};
   }
@@ -334,7 +339,9 @@ void op_apply(Solver& S, int l, int dagger, int epi, const cplx<T>* in, cplx<T>*
               cplx<T>* copy_out, int nrhs, RedArgs red, hipStream_t st) {
   Level& L = S.lv[l];
   const bool mr_epi = epi == EPI_MRDOT || epi == EPI_MRPART;
-  ProfScope ps(S, L.fine ? PK_FINE : (mr_epi && S.prof.kind == PK_COARSE_MR ? PK_COARSE_MR : PK_COARSE), l, st);
+  ProfScope ps(S, L.fine ? PK_FINE : (mr_epi && (S.prof.kind == PK_COARSE_MR || S.prof.kind < 0) ? PK_COARSE_MR
+                                                                                                   : PK_COARSE),
+               l, st);
   if (L.fine) {
     wilson_apply<T>(*S.g, S.mass, dagger, epi, in, out, b, copy_out, nrhs, red, st);
     (dagger ? S.nDd : S.nD) += 1;
@@ -1883,7 +1890,7 @@ amg_status amg_mr(amg_solver* S, int level, int prec, int nu, const void* dev_b,
 amg_status amg_profile_enable(amg_solver* S, int kind, int level, int enable) {
   AMG_TRY
   check_ptr(S, "solver");
-  if (kind < 0 || kind > 4 || level < 0 || level >= (int)S->lv.size()) fail(AMG_ERR_ARG, "bad kind / level");
+  if (kind < -1 || kind > 4 || level < -1 || level >= (int)S->lv.size()) fail(AMG_ERR_ARG, "bad kind / level");
   S->prof.on = enable != 0;
   S->prof.kind = kind;
   S->prof.level = level;
@@ -1904,6 +1911,25 @@ amg_status amg_profile_read(amg_solver* S, double* total_ms, long long* launches
   }
   if (total_ms) *total_ms = tot;
   if (launches) *launches = (long long)(P.used / 2);
+  AMG_CATCH
+}
+
+amg_status amg_profile_read_kind(amg_solver* S, int kind, int level, double* total_ms, long long* launches) {
+  AMG_TRY
+  check_ptr(S, "solver");
+  auto& P = S->prof;
+  double tot = 0.0;
+  long long n = 0;
+  if (P.used) HIPC(hipEventSynchronize(P.ev[P.used - 1]));
+  for (size_t i = 0; i + 1 < P.used; i += 2) {
+    if (P.tag[i / 2] != ((kind << 8) | level)) continue;
+    float ms = 0.f;
+    HIPC(hipEventElapsedTime(&ms, P.ev[i], P.ev[i + 1]));
+    tot += ms;
+    ++n;
+  }
+  if (total_ms) *total_ms = tot;
+  if (launches) *launches = n;
   AMG_CATCH
 }
 
