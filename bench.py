@@ -735,7 +735,17 @@ def coarse16_bytes(Vc):
 # WRITE_SIZE, each scaled by the counter's reading for a plain copy of known
 # size); keyed by (kind, level) of the headline's profile; None when the kernel
 # has changed since the counters were taken
-ROOF_TRAFFIC = {}
+ROOF_TRAFFIC = {
+    # coarse16_kernel<float> on level 2 (1024 sites, plain epilogue): FETCH 4577.9 KiB x 2 + WRITE 111.9 KiB
+    (1, 2): 9490125,
+}
+# the same for the large-lattice stencils of roofline_hbm (profiles/wilson_stencils_hbm.md)
+STENCIL_TRAFFIC = {
+    "wilson2d_4096x4096_f64_nrhs1": 1741802906,     # FETCH 588345.7 KiB x 2 + WRITE 524288 KiB
+    "wilson2d_4096x4096_f32_nrhs1": 839446733,      # FETCH 278814.1 KiB x 2 + WRITE 262144 KiB
+    "wilson4d_32x32x32x64_f32_nrhs1": 1178906829,   # FETCH 477334.1 KiB x 2 + WRITE 196608 KiB
+    "wilson4d_32x32x32x64_f64_nrhs1": 3992881766,   # FETCH 1753041.3 KiB x 2 + WRITE 393216 KiB
+}
 
 PROF_KINDS = {0: "fine Wilson stencil", 1: "coarse block stencil", 2: "restriction", 3: "prolongation",
               4: "coarse block stencil with the MR sums"}
@@ -756,6 +766,8 @@ def main():
     ap.add_argument("--no-cfg1", action="store_true")
     ap.add_argument("--only-stencil", action="store_true",
                     help="time the fine stencils alone (for profiling runs) and print their JSON")
+    ap.add_argument("--only-4d", action="store_true",
+                    help="run the 4d multi-rhs workload alone (for profiling runs) and print its JSON")
     args = ap.parse_args()
     global BETAS
     if args.betas:
@@ -777,6 +789,13 @@ def main():
         torch.cuda.synchronize()
         del x, y
         print(json.dumps({"stencil": stencil_bench(amg, torch, th)}))
+        return
+    if args.only_4d:
+        U4 = gen_4d_base()
+        import torch
+        import paper_0707_4018_amd as amg
+        torch.cuda.set_device(0)
+        print(json.dumps({"wilson4d": wilson4d_bench(amg, torch, U4)}))
         return
     log("generating gauge ensembles (heat-bath, worker processes)")
     with cf.ProcessPoolExecutor(max_workers=16) as ex:
@@ -890,8 +909,15 @@ def main():
         st = stencil_bench(amg, torch, fields[BETAS[-1]])
         out["stencil"] = st
         out["roofline_hbm"] = {k: {"bound": "hbm", "achieved": v["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                   "frac": v["frac_hbm"], "traffic": None}
+                                   "frac": v["frac_hbm"], "traffic": STENCIL_TRAFFIC.get(k)}
                                for k, v in st.items() if k.endswith("nrhs1")}
+        # the 4d kernels read SU(3) links as two rows (12 of 18 reals): their rate by the
+        # bytes they move, beside the rate by the canonical count above
+        for k, per_site in (("wilson4d_32x32x32x64_f32_nrhs1", 384), ("wilson4d_32x32x32x64_f64_nrhs1", 768)):
+            if k in st:
+                gbs = 2097152 * per_site / (st[k]["us_per_apply"] * 1e-6) / 1e9
+                out["roofline_hbm"][k]["achieved_two_row_links"] = round(gbs, 1)
+                out["roofline_hbm"][k]["frac_two_row_links"] = round(gbs / HBM_PEAK_GBS, 3)
     if oracle is not None:
         log("waiting for the oracle workers")
         res = oracle.collect()

@@ -135,6 +135,13 @@ amg_status amg_set_allocator(void* (*alloc)(size_t bytes, void* stream, void* ct
 amg_status amg_gauge_create(const amg_lattice* lat, const void* dev_links, double mass,
                             void* stream, amg_gauge** out);
 amg_status amg_gauge_set_mass(amg_gauge* g, double mass);
+/* Dimension, extents and link storage of a handle (library plumbing, no
+ * passage of the paper defines it).  links_compressed = 1: every 4d link was
+ * in SU(3) (unitary, unit determinant, to 1e-9) at creation, and the stencil
+ * reads the first two rows of each link and rebuilds the third as the
+ * conjugated cross product of the first two; 0: full 3 x 3 links.  Any
+ * pointer may be NULL. */
+amg_status amg_gauge_info(const amg_gauge* g, int* nd, int* dims4, int* links_compressed);
 amg_status amg_gauge_destroy(amg_gauge* g);
 
 /* dev_out = D dev_in (dagger = 0) or D^dagger dev_in (dagger = 1), nrhs

@@ -62,6 +62,7 @@ _SIGS = {
     "amg_default_params": (None, [C.POINTER(_Params)]),
     "amg_gauge_create": (C.c_int, [C.POINTER(_Lattice), _P, C.c_double, _P, C.POINTER(_P)]),
     "amg_gauge_set_mass": (C.c_int, [_P, C.c_double]),
+    "amg_gauge_info": (C.c_int, [_P, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "amg_gauge_destroy": (C.c_int, [_P]),
     "amg_apply": (C.c_int, [_P, C.c_int, C.c_int, _P, _P, C.c_int, _P]),
     "amg_apply_internal": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, C.c_int, _P]),
@@ -256,6 +257,13 @@ class Gauge:
     def set_mass(self, m: float):
         _check(load_library().amg_gauge_set_mass(self._h, float(m)), "amg_gauge_set_mass")
         self.mass = float(m)
+
+    @property
+    def links_compressed(self) -> bool:
+        """True when the 4d stencil reads two-row (12-real) SU(3) links."""
+        c = C.c_int()
+        _check(load_library().amg_gauge_info(self._h, None, None, C.byref(c)), "amg_gauge_info")
+        return bool(c.value)
 
     def apply(self, psi: torch.Tensor, dagger: bool = False, prec: int = F64) -> torch.Tensor:
         """D psi (or D^dagger psi) for psi of shape (nrhs, V, ns, nc) or (V, ns, nc)."""

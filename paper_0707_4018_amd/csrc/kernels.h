@@ -49,6 +49,10 @@ struct WilsonArgs {
   const cplx<T>* b = nullptr;       // EPI_RESID
   cplx<T>* copy_out = nullptr;      // optional copy of `in`
   const cplx<T>* U = nullptr;       // internal link layout of precision T
+  // 4d only: the SU(3) links as their first two rows (third row rebuilt as
+  // the conjugated cross product), or nullptr: FP32 [mu][3][site] float4
+  // (u00 u01 | u02 u10 | u11 u12), FP64 [mu][6][site] double2
+  const void* Uc = nullptr;
   double mass = 0.0;
   int L1 = 0, L2 = 0, L3 = 1, L4 = 1;
   int nrhs = 1;
@@ -189,6 +193,10 @@ template <typename T>
 void launch_scale_inv_norm(cplx<T>* v, const double* nn, long n, int nrhs, hipStream_t st);
 void launch_diag_shift(double2* Y, const double2* M, long V, int nc, int ndir, double dm, hipStream_t st);
 void launch_links4d_pack(double2* U64, float2* U32, const double2* canon, long V, hipStream_t st);
+// two-row (12-real) copies of SU(3) links in FP64 and FP32; *not_su3 (zero on
+// entry) becomes nonzero if some link is not unitary with unit determinant to 1e-9
+void launch_links4d_compress(double2* Uc64, float4* Uc32, const double2* canon, long V, int* not_su3,
+                             hipStream_t st);
 // whole coarsest-level GCR (N_c = 16) in one cooperative launch
 template <typename T>
 hipError_t launch_gcr16_persistent(const cplx<T>* Y, const CoarseGeom& g, const cplx<T>* b, cplx<T>* x, cplx<T>* r,

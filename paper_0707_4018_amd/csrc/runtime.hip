@@ -128,6 +128,10 @@ struct amg_gauge {
   int nc = 1, ns = 2, dof = 2;
   double mass = 0.0;
   Buf U64, U32;
+  // 4d: two-row copies of the links when every link is in SU(3) (third row
+  // rebuilt in the stencil); empty otherwise
+  Buf Uc64, Uc32;
+  bool compressed = false;
   // internal-layout buffers for amg_apply / amg_apply_internal
   Buf tin, tout;
   Scratch sc;
@@ -147,6 +151,7 @@ void wilson_apply(const amg_gauge& g, double mass, int dagger, int epi, const cp
   WilsonArgs<T> a;
   a.out = out; a.in = in; a.b = b; a.copy_out = copy_out;
   a.U = g.U<T>();
+  if (g.nd == 4 && g.compressed) a.Uc = std::is_same<T, float>::value ? g.Uc32.p : g.Uc64.p;
   a.mass = mass;
   a.L1 = g.dims[0]; a.L2 = g.dims[1]; a.L3 = g.dims[2]; a.L4 = g.dims[3];
   a.nrhs = nrhs;
@@ -1379,6 +1384,29 @@ amg_status amg_gauge_create(const amg_lattice* lat, const void* dev_links, doubl
       g->U64.ensure((size_t)36 * V * sizeof(double2));
       g->U32.ensure((size_t)36 * V * sizeof(float2));
       launch_links4d_pack(g->U64.as<double2>(), g->U32.as<float2>(), (const double2*)dev_links, V, st);
+      // SU(3) links travel as their first two rows (12 reals): a third fewer
+      // link bytes and one 16-byte load per element pair in the stencil
+      static const bool compress = [] {
+        const char* e = std::getenv("AMG_W4_COMPRESS");
+        return e ? std::atoi(e) != 0 : true;
+      }();
+      if (compress) {
+        g->Uc64.ensure((size_t)24 * V * sizeof(double2));
+        g->Uc32.ensure((size_t)12 * V * sizeof(float4));
+        Buf flag;
+        flag.ensure(sizeof(int));
+        HIPC(hipMemsetAsync(flag.p, 0, sizeof(int), st));
+        launch_links4d_compress(g->Uc64.as<double2>(), g->Uc32.as<float4>(), (const double2*)dev_links, V,
+                                flag.as<int>(), st);
+        int not_su3 = 1;
+        HIPC(hipMemcpyAsync(&not_su3, flag.p, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPC(hipStreamSynchronize(st));
+        g->compressed = not_su3 == 0;
+        if (!g->compressed) {
+          g->Uc64.release();
+          g->Uc32.release();
+        }
+      }
     }
     g->sc.init(64, RHS_MAX);
     HIPC(hipStreamSynchronize(st));
@@ -1395,6 +1423,16 @@ amg_status amg_gauge_set_mass(amg_gauge* g, double mass) {
   check_ptr(g, "gauge");
   if (!std::isfinite(mass)) fail(AMG_ERR_ARG, "mass must be finite");
   g->mass = mass;
+  AMG_CATCH
+}
+
+amg_status amg_gauge_info(const amg_gauge* g, int* nd, int* dims4, int* links_compressed) {
+  AMG_TRY
+  check_ptr(g, "gauge");
+  if (nd) *nd = g->nd;
+  if (dims4)
+    for (int mu = 0; mu < 4; ++mu) dims4[mu] = g->dims[mu];
+  if (links_compressed) *links_compressed = g->compressed ? 1 : 0;
   AMG_CATCH
 }
 

@@ -124,6 +124,38 @@ __device__ __forceinline__ void ld_link(gptr<const cplx<T>> __restrict__ U, long
     for (int b = 0; b < 3; ++b) L.m[a][b] = U[(long)(mu * 9 + a * 3 + b) * V + s];
 }
 
+// third row of an SU(3) matrix from the first two: r2 = conj(r0 x r1)
+template <typename T>
+__device__ __forceinline__ void su3_third_row(Link<T>& L) {
+  const cplx<T> a = csub<T>(cmul<T>(L.m[0][1], L.m[1][2]), cmul<T>(L.m[0][2], L.m[1][1]));
+  const cplx<T> b = csub<T>(cmul<T>(L.m[0][2], L.m[1][0]), cmul<T>(L.m[0][0], L.m[1][2]));
+  const cplx<T> c = csub<T>(cmul<T>(L.m[0][0], L.m[1][1]), cmul<T>(L.m[0][1], L.m[1][0]));
+  L.m[2][0] = mk<T>(a.x, -a.y);
+  L.m[2][1] = mk<T>(b.x, -b.y);
+  L.m[2][2] = mk<T>(c.x, -c.y);
+}
+// two-row links: three 16-byte loads (FP32) or six (FP64) per link
+__device__ __forceinline__ void ld_link_c(const void* Uc, long s, long V, int mu, Link<float>& L) {
+  gptr<const float4> q = (gptr<const float4>)Uc + (long)(mu * 3) * V + s;
+  const float4 q0 = q[0], q1 = q[V], q2 = q[2 * V];
+  L.m[0][0] = make_float2(q0.x, q0.y); L.m[0][1] = make_float2(q0.z, q0.w);
+  L.m[0][2] = make_float2(q1.x, q1.y); L.m[1][0] = make_float2(q1.z, q1.w);
+  L.m[1][1] = make_float2(q2.x, q2.y); L.m[1][2] = make_float2(q2.z, q2.w);
+  su3_third_row<float>(L);
+}
+__device__ __forceinline__ void ld_link_c(const void* Uc, long s, long V, int mu, Link<double>& L) {
+  gptr<const double2> q = (gptr<const double2>)Uc + (long)(mu * 6) * V + s;
+#pragma unroll
+  for (int e = 0; e < 6; ++e) L.m[e / 3][e % 3] = q[(long)e * V];
+  su3_third_row<double>(L);
+}
+template <typename T, bool COMP>
+__device__ __forceinline__ void ld_lnk(gptr<const cplx<T>> __restrict__ U, const void* Uc, long s, long V, int mu,
+                                       Link<T>& L) {
+  if (COMP) ld_link_c(Uc, s, V, mu, L);
+  else ld_link<T>(U, s, V, mu, L);
+}
+
 // o += -1/2 * (1 + s gamma_mu) W psi, W = U (DAGU = false) or U^dag (true)
 template <typename T, int MU, bool DAGU>
 __device__ __forceinline__ void hop(Spinor<T>& o, const Spinor<T>& p, const Link<T>& L, T s) {
@@ -196,15 +228,15 @@ struct Geo4 {
   }
 };
 
-template <typename T, int DAG>
+template <typename T, int DAG, bool COMP>
 __device__ __forceinline__ void all_hops(Spinor<T>& o, gptr<const cplx<T>> __restrict__ pin, gptr<const cplx<T>> __restrict__ U,
-                                         long s, long V, const long* fw, const long* bw) {
+                                         const void* Uc, long s, long V, const long* fw, const long* bw) {
   const T sf = DAG ? (T)1 : (T)-1, sb = -sf;
   Spinor<T> p;
   Link<T> L;
 #define AMG_HOP4(MU)                                  \
-  ld_spinor(pin, fw[MU], V, p); ld_link<T>(U, s, V, MU, L);      hop<T, MU, false>(o, p, L, sf); \
-  ld_spinor(pin, bw[MU], V, p); ld_link<T>(U, bw[MU], V, MU, L); hop<T, MU, true>(o, p, L, sb);
+  ld_spinor(pin, fw[MU], V, p); ld_lnk<T, COMP>(U, Uc, s, V, MU, L);      hop<T, MU, false>(o, p, L, sf); \
+  ld_spinor(pin, bw[MU], V, p); ld_lnk<T, COMP>(U, Uc, bw[MU], V, MU, L); hop<T, MU, true>(o, p, L, sb);
   AMG_HOP4(0) AMG_HOP4(1) AMG_HOP4(2) AMG_HOP4(3)
 #undef AMG_HOP4
 }
@@ -212,7 +244,7 @@ __device__ __forceinline__ void all_hops(Spinor<T>& o, gptr<const cplx<T>> __res
 Geo4 geo(const int* d);
 
 // W: minimum waves per SIMD asked of the register allocator
-template <typename T, int DAG, int EPI, int W, bool NT>
+template <typename T, int DAG, int EPI, int W, bool NT, bool COMP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) void wilson4d_kernel(
     WilsonArgs<T> a0, const WilsonArgs<T>* batch) {
   AMG_ARGS(WilsonArgs<T>)
@@ -243,7 +275,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
       for (int k = 0; k < 3; ++k) o.c[sp][k] = cscale<T>(diag, c.c[sp][k]);
-    all_hops<T, DAG>(o, pin, U, s, V, fw, bw);
+    all_hops<T, DAG, COMP>(o, pin, U, a.Uc, s, V, fw, bw);
     if (EPI == EPI_RESID) {
       Spinor<T> b;
       ld_spinor(bvec + ro, s, V, b);
@@ -272,8 +304,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
 // 3-volume apart and would otherwise be re-fetched from memory), and the
 // blocks are renumbered so that every XCD works on one contiguous part of
 // the lattice (its L2 then holds the x_3 neighbours of its own columns).
-template <typename T, int DAG, int EPI, int TT, bool NT>
-__global__ __launch_bounds__(256) void wilson4d_tm_kernel(WilsonArgs<T> a0, const WilsonArgs<T>* batch) {
+// Registers: 233 VGPRs with two-row links (two waves per SIMD); asking the
+// allocator for three or four waves spills and measured 1.4-2.3x slower.
+template <typename T, int DAG, int EPI, int TT, bool NT, bool COMP>
+__global__ __launch_bounds__(256) void wilson4d_tm_kernel(
+    WilsonArgs<T> a0, const WilsonArgs<T>* batch) {
   AMG_ARGS(WilsonArgs<T>)
   const int rhs = blockIdx.y;
   const RedArgs& red = a.red;
@@ -311,22 +346,23 @@ __global__ __launch_bounds__(256) void wilson4d_tm_kernel(WilsonArgs<T> a0, cons
       const long sm = q + (long)((t0 + L4 - 1) % L4) * V3;
       ld_spinor(pin, s0, V, cur);
       ld_spinor(pin, sm, V, prev);
-      ld_link<T>(U, sm, V, 3, Lb);
+      ld_lnk<T, COMP>(U, a.Uc, sm, V, 3, Lb);
     }
     for (int t = t0; t < t1; ++t) {
       const long toff = (long)t * V3;
       const long s = q + toff;
       ld_spinor(pin, q + (long)((t + 1) % L4) * V3, V, nxt);
-      ld_link<T>(U, s, V, 3, Lf);
+      ld_lnk<T, COMP>(U, a.Uc, s, V, 3, Lf);
       Spinor<T> o;
 #pragma unroll
       for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
         for (int k = 0; k < 3; ++k) o.c[sp][k] = cscale<T>(diag, cur.c[sp][k]);
       Link<T> L;
-#define AMG_HOP3(MU)                                                                            \
-  ld_spinor(pin, qf[MU] + toff, V, p); ld_link<T>(U, s, V, MU, L); hop<T, MU, false>(o, p, L, sf); \
-  ld_spinor(pin, qb[MU] + toff, V, p); ld_link<T>(U, qb[MU] + toff, V, MU, L); hop<T, MU, true>(o, p, L, sb);
+#define AMG_HOP3(MU)                                                                                      \
+  ld_spinor(pin, qf[MU] + toff, V, p); ld_lnk<T, COMP>(U, a.Uc, s, V, MU, L); hop<T, MU, false>(o, p, L, sf); \
+  ld_spinor(pin, qb[MU] + toff, V, p); ld_lnk<T, COMP>(U, a.Uc, qb[MU] + toff, V, MU, L);                   \
+  hop<T, MU, true>(o, p, L, sb);
       AMG_HOP3(0) AMG_HOP3(1) AMG_HOP3(2)
 #undef AMG_HOP3
       hop<T, 3, false>(o, nxt, Lf, sf);
@@ -428,6 +464,47 @@ __global__ void links4d_pack_kernel(double2* __restrict__ U64, float2* __restric
   }
 }
 
+// Two-row copies of the links and the SU(3) check (FP64: |U U^dag - 1| and
+// |det U - 1| below 1e-9 for every link, else the flag is raised and the
+// caller keeps the full links).
+__global__ void links4d_compress_kernel(double2* __restrict__ Uc64, float4* __restrict__ Uc32,
+                                        const double2* __restrict__ c, long V, int* __restrict__ not_su3) {
+  const long total = 4 * V;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
+    const int mu = (int)(i / V);
+    const long s = i - (long)mu * V;
+    double2 m[3][3];
+#pragma unroll
+    for (int ab = 0; ab < 9; ++ab) m[ab / 3][ab % 3] = c[i * 9 + ab];
+    double dev = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        double2 acc = make_double2(a == b ? -1.0 : 0.0, 0.0);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {   // (U U^dag)_ab = sum_k U_ak conj(U_bk)
+          acc.x += m[a][k].x * m[b][k].x + m[a][k].y * m[b][k].y;
+          acc.y += m[a][k].y * m[b][k].x - m[a][k].x * m[b][k].y;
+        }
+        dev = fmax(dev, fabs(acc.x) + fabs(acc.y));
+      }
+    const double2 c0 = csub<double>(cmul<double>(m[1][1], m[2][2]), cmul<double>(m[1][2], m[2][1]));
+    const double2 c1 = csub<double>(cmul<double>(m[1][2], m[2][0]), cmul<double>(m[1][0], m[2][2]));
+    const double2 c2 = csub<double>(cmul<double>(m[1][0], m[2][1]), cmul<double>(m[1][1], m[2][0]));
+    double2 det = cmul<double>(m[0][0], c0);
+    det = cadd<double>(det, cmul<double>(m[0][1], c1));
+    det = cadd<double>(det, cmul<double>(m[0][2], c2));
+    dev = fmax(dev, fabs(det.x - 1.0) + fabs(det.y));
+    if (!(dev <= 1e-9)) atomicOr(not_su3, 1);
+#pragma unroll
+    for (int e = 0; e < 6; ++e) Uc64[(long)(mu * 6 + e) * V + s] = m[e / 3][e % 3];
+    Uc32[(long)(mu * 3 + 0) * V + s] = make_float4((float)m[0][0].x, (float)m[0][0].y, (float)m[0][1].x, (float)m[0][1].y);
+    Uc32[(long)(mu * 3 + 1) * V + s] = make_float4((float)m[0][2].x, (float)m[0][2].y, (float)m[1][0].x, (float)m[1][0].y);
+    Uc32[(long)(mu * 3 + 2) * V + s] = make_float4((float)m[1][1].x, (float)m[1][1].y, (float)m[1][2].x, (float)m[1][2].y);
+  }
+}
+
 Geo4 geo(const int* d) {
   Geo4 G;
   long st = 1;
@@ -472,6 +549,7 @@ void launch_wilson4d(const WilsonArgs<T>& a, int dagger, int epi, hipStream_t st
   }();
   const int tt = (red && tt_red >= 0) ? tt_red : w4_tt<T>();
   const bool nt = V >= (1L << 20);
+  const bool comp = a.Uc != nullptr;
   if (tt == 4 || tt == 8 || tt == 16) {
     const long V3 = (long)a.L1 * a.L2 * a.L3;
     long nb = (V3 * ((a.L4 + tt - 1) / tt) + 255) / 256;
@@ -479,7 +557,9 @@ void launch_wilson4d(const WilsonArgs<T>& a, int dagger, int epi, hipStream_t st
     dim3 grid((unsigned)nb, (unsigned)a.nrhs);
 // (streaming stores measured 2x slower in the x_4-marching kernel: 548 vs
 // 276 us at 32^3 x 64; it keeps ordinary stores)
-#define AMG_W4T(TT, DAG, EPI) dispatch(wilson4d_tm_kernel<T, DAG, EPI, TT, false>, a, grid, dim3(256), st)
+#define AMG_W4T(TT, DAG, EPI)                                                                  \
+  if (comp) { dispatch(wilson4d_tm_kernel<T, DAG, EPI, TT, false, true>, a, grid, dim3(256), st); } \
+  else { dispatch(wilson4d_tm_kernel<T, DAG, EPI, TT, false, false>, a, grid, dim3(256), st); }
 #define AMG_W4T_E(TT, DAG)                                   \
     switch (epi) {                                          \
       case EPI_PLAIN: AMG_W4T(TT, DAG, EPI_PLAIN); break;   \
@@ -497,9 +577,14 @@ void launch_wilson4d(const WilsonArgs<T>& a, int dagger, int epi, hipStream_t st
   long nb = (V + 255) / 256;
   if (red) nb = nb < red_block_cap() ? nb : red_block_cap();
   dim3 grid((unsigned)nb, (unsigned)a.nrhs);
-#define AMG_W4N(DAG, EPI, W)                                                                     \
-  if (nt) { dispatch(wilson4d_kernel<T, DAG, EPI, W, true>, a, grid, dim3(256), st); }          \
-  else { dispatch(wilson4d_kernel<T, DAG, EPI, W, false>, a, grid, dim3(256), st); }
+#define AMG_W4N(DAG, EPI, W)                                                                          \
+  if (nt) {                                                                                          \
+    if (comp) { dispatch(wilson4d_kernel<T, DAG, EPI, W, true, true>, a, grid, dim3(256), st); }     \
+    else { dispatch(wilson4d_kernel<T, DAG, EPI, W, true, false>, a, grid, dim3(256), st); }         \
+  } else {                                                                                           \
+    if (comp) { dispatch(wilson4d_kernel<T, DAG, EPI, W, false, true>, a, grid, dim3(256), st); }    \
+    else { dispatch(wilson4d_kernel<T, DAG, EPI, W, false, false>, a, grid, dim3(256), st); }        \
+  }
 #define AMG_W4(DAG, EPI) if (w2) { AMG_W4N(DAG, EPI, 2); } else { AMG_W4N(DAG, EPI, 1); }
   const bool w2 = w4_waves<T>() == 2;
   if (dagger) {
@@ -530,6 +615,13 @@ void launch_wilson4d_split(double2* out, const double2* in, const double2* U, do
   dim3 grid((unsigned)((V + 255) / 256), (unsigned)nrhs);
   hipLaunchKernelGGL(wilson4d_split_kernel, grid, dim3(256), 0, st, out, in, U, 4.0 + mass, G, V, blk[0], blk[1],
                      blk[2], blk[3], nrhs);
+}
+
+void launch_links4d_compress(double2* Uc64, float4* Uc32, const double2* canon, long V, int* not_su3,
+                             hipStream_t st) {
+  long nb = (4 * V + 255) / 256;
+  if (nb > (1L << 20)) nb = 1L << 20;
+  hipLaunchKernelGGL(links4d_compress_kernel, dim3((unsigned)nb), dim3(256), 0, st, Uc64, Uc32, canon, V, not_su3);
 }
 
 void launch_links4d_pack(double2* U64, float2* U32, const double2* canon, long V, hipStream_t st) {

@@ -128,3 +128,24 @@ def test_wilson4d_streaming_store_size():
     ref = dirac.apply_D(U, psi[0].reshape(lat + (4, 3)), m).reshape(1, V, 4, 3)
     assert max_rel_err(host(g.apply(dev(psi))), ref) < 1e-12
     assert max_rel_err(host(g.apply(dev(psi, torch.complex64), prec=amg.F32)), ref) < 1e-5
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 8), (8, 8, 8, 16)])
+def test_wilson4d_non_su3_links_use_full_links(dims):
+    """Links in U(3) but not SU(3) (a phase on every link): the library keeps
+    the full 3 x 3 links (the two-row form needs det U = 1), with the same
+    parity; SU(3) links take the two-row form."""
+    import paper_0707_4018_amd as amg
+    import torch
+    print(f"wilson4d non-SU(3) links {dims}", flush=True)
+    U = su3_config(dims, seed=7)
+    V = int(np.prod(dims))
+    assert amg.Gauge(dev(U), 0.05).links_compressed
+    phase = np.exp(1j * synth.rng_for(8, *dims).uniform(-np.pi, np.pi, size=U.shape[:-2]))
+    Up = U * phase[..., None, None]
+    g = amg.Gauge(dev(Up), 0.05)
+    assert not g.links_compressed
+    psi = synth.gaussian_field((1, V, 4, 3), synth.rng_for(9, *dims))
+    ref = dirac.apply_D(Up, psi[0].reshape(tuple(reversed(dims)) + (4, 3)), 0.05).reshape(V, 4, 3)
+    assert max_rel_err(host(g.apply(dev(psi)))[0], ref) < 1e-12
+    assert max_rel_err(host(g.apply(dev(psi, torch.complex64), prec=amg.F32))[0], ref) < 1e-5
