@@ -7,8 +7,11 @@ its definition, so nothing is blocked or fused:
 * A_0 = D^dagger D (D the Wilson-Dirac operator, definition after Eq. (1));
 * P_l: the M near-null vectors restricted to each block S_j of the level's
   lattice and orthonormalised there (Eq. (5) and the text after it; one
-  coarse degree of freedom per vector, no chiral split), A_{l+1} =
-  P_l^dagger A_l P_l (Eq. (2), Hermitian positive definite);
+  coarse degree of freedom per vector, no chiral split), optionally smoothed
+  by one damped Richardson step, P_l = (1 - omega_l A_l) P_l^tent ("smoothed
+  aggregation", adaptive-method section), with omega_l = f / lambda_l and
+  lambda_l the Rayleigh quotient of A_l after a fixed number of power steps;
+  A_{l+1} = P_l^dagger A_l P_l (Eq. (2), Hermitian positive definite);
 * the smoother: two under-relaxed minimal-residual steps (omega = 0.8) whose
   step lengths are computed once from a given vector and then frozen, so the
   relaxation is a fixed polynomial in A with R = R^dagger (numerical-test
@@ -75,6 +78,25 @@ def block_prolongator(vecs: np.ndarray, dims, block) -> sp.csr_matrix:
                          shape=(V * dof, Vc * M))
 
 
+def power_lmax(A: CountingOp, v0: np.ndarray, kpow: int) -> float:
+    """<p, A p> / <p, p> after kpow steps p <- A p / |A p| from v0: an
+    estimate of A's largest eigenvalue from below."""
+    p = v0.astype(np.complex128) / norm(v0)
+    for _ in range(kpow):
+        q = A.apply(p)
+        p = q / norm(q)
+    return vdot(p, A.apply(p)).real
+
+
+def smoothed_prolongator(A: CountingOp, Pt: sp.spmatrix, f: float, v0: np.ndarray, kpow: int):
+    """(P, omega): P = (1 - omega A) Pt with omega = f / power_lmax(A, v0, kpow);
+    f = 0 returns Pt itself."""
+    if f == 0.0:
+        return Pt.tocsr(), 0.0
+    omega = f / power_lmax(A, v0, kpow)
+    return (Pt - omega * (A.M @ Pt)).tocsr(), omega
+
+
 def frozen_steps(A: CountingOp, b: np.ndarray, omega: float) -> tuple[float, float]:
     """Step lengths tau_i = omega alpha_i of two MR steps on A x = b from x = 0,
     alpha = <A r, r> / <A r, A r> (real for Hermitian A; the real part is
@@ -96,6 +118,7 @@ class NormalHierarchy:
     dims: list                       # lattice extents per level
     taus: list                       # frozen smoother steps per level (all but the coarsest)
     coarse_lu: object = None         # factors of the coarsest operator
+    sa_omegas: list = field(default_factory=list)   # Richardson damping of each P (0: unsmoothed)
 
     @property
     def nlevels(self) -> int:
@@ -131,20 +154,23 @@ def vcycle(H: NormalHierarchy, level: int, b: np.ndarray) -> np.ndarray:
     return x + smooth_add(A, b - A.apply(x), H.taus[level])   # 5. x += R (b - A x)
 
 
-def build(D: sp.spmatrix, dims, vecs: list, blocks: list, smoother_b: list, omega: float = 0.8) -> NormalHierarchy:
+def build(D: sp.spmatrix, dims, vecs: list, blocks: list, smoother_b: list, omega: float = 0.8,
+          sa: float = 0.0, kpow: int = 20) -> NormalHierarchy:
     """Hierarchy from given near-null vectors vecs[l] (M, V_l, dof_l) and the
-    vectors smoother_b[l] the frozen step lengths are computed from."""
+    vectors smoother_b[l] the frozen step lengths (and the power estimate of
+    the smoothing damping, sa = f > 0) are computed from."""
     ops = [CountingOp((D.conj().T @ D).tocsr(), fine_D_per_apply=2)]
-    Ps, ds, taus = [], [tuple(dims)], []
+    Ps, ds, taus, oms = [], [tuple(dims)], [], []
     for l, (v, blk) in enumerate(zip(vecs, blocks)):
-        P = block_prolongator(v, ds[-1], blk)
+        P, om = smoothed_prolongator(ops[-1], block_prolongator(v, ds[-1], blk), sa, smoother_b[l], kpow)
         Ps.append(P)
+        oms.append(om)
         ops.append(CountingOp((P.conj().T @ ops[-1].M @ P).tocsr()))
         ds.append(tuple(L // b for L, b in zip(ds[-1], blk)))
     for l in range(len(ops) - 1):
         taus.append(frozen_steps(ops[l], smoother_b[l], omega))
         ops[l].napply = 0
-    H = NormalHierarchy(ops, Ps, ds, taus)
+    H = NormalHierarchy(ops, Ps, ds, taus, sa_omegas=oms)
     H.coarse_lu = spla.splu(ops[-1].M.tocsc())
     return H
 
@@ -161,14 +187,33 @@ def relax_homogeneous(A: CountingOp, v: np.ndarray, nu: int, omega: float) -> np
     return v
 
 
+class _CGCoarse:
+    """Coarse solve of the set-up cycles by plain CG to a relative residual
+    (used where the coarse level is too large to factor)."""
+
+    def __init__(self, A: CountingOp, tol: float, maxiter: int):
+        self.A, self.tol, self.maxiter = A, tol, maxiter
+
+    def solve(self, b):
+        return pcg(self.A, b, None, self.tol, self.maxiter)[0]
+
+
 def adaptive_setup(D: sp.spmatrix, dims, blocks: list, nvec: list, init: list, smoother_b: list,
-                   nu0: int = 20, ncyc: int = 2, omega: float = 0.8):
+                   nu0=20, ncyc=2, omega: float = 0.8, sa: float = 0.0, kpow: int = 20,
+                   setup_coarse_tol=None, setup_coarse_maxiter: int = 100000):
     """Adaptive construction for A = D^dag D, level by level (text from Eq. (4)
     to the recursion remark after Eq. (5)): vector 1 of coarsening l is
     init[l][0] after nu0 MR relaxations on A_l v = 0; vector k > 1 is
     init[l][k-1] after ncyc sweeps of e <- e - V(A_l e) with the two-level
     cycle of the vectors so far (level l+1 solved exactly), normalised.
+    nu0 and ncyc are numbers or one number per coarsening.  The prolongators
+    of the set-up cycles are smoothed like the final ones (sa).  The coarse
+    level of a set-up cycle is factored (setup_coarse_tol None) or solved by
+    CG to that relative residual.
     Returns (hierarchy, vecs)."""
+    nl = len(blocks)
+    nu0 = list(nu0) if np.ndim(nu0) else [nu0] * nl
+    ncyc = list(ncyc) if np.ndim(ncyc) else [ncyc] * nl
     A0 = (D.conj().T @ D).tocsr()
     ops = [CountingOp(A0, fine_D_per_apply=2)]
     ds = [tuple(dims)]
@@ -177,20 +222,23 @@ def adaptive_setup(D: sp.spmatrix, dims, blocks: list, nvec: list, init: list, s
         A = ops[-1]
         shape = init[l][0].shape                        # (V_l, dof_l)
         taus = frozen_steps(A, smoother_b[l], omega)
-        vecs = [relax_homogeneous(A, init[l][0].reshape(-1), nu0, omega)]
+        vecs = [relax_homogeneous(A, init[l][0].reshape(-1), nu0[l], omega)]
         for k in range(1, nvec[l]):
-            P = block_prolongator(np.stack([v.reshape(shape) for v in vecs]), ds[-1], blk)
+            Pt = block_prolongator(np.stack([v.reshape(shape) for v in vecs]), ds[-1], blk)
+            P, _ = smoothed_prolongator(A, Pt, sa, smoother_b[l], kpow)
             Ac = CountingOp((P.conj().T @ A.M @ P).tocsr())
-            H2 = NormalHierarchy([A, Ac], [P], [ds[-1]], [taus], spla.splu(Ac.M.tocsc()))
+            cs = (spla.splu(Ac.M.tocsc()) if setup_coarse_tol is None
+                  else _CGCoarse(Ac, setup_coarse_tol, setup_coarse_maxiter))
+            H2 = NormalHierarchy([A, Ac], [P], [ds[-1]], [taus], cs)
             e = init[l][k].reshape(-1).astype(np.complex128).copy()
-            for _ in range(ncyc):
+            for _ in range(ncyc[l]):
                 e = e - vcycle(H2, 0, A.apply(e))
             vecs.append(e / norm(e))
         all_vecs.append(np.stack([v.reshape(shape) for v in vecs]))
-        P = block_prolongator(all_vecs[-1], ds[-1], blk)
+        P, _ = smoothed_prolongator(A, block_prolongator(all_vecs[-1], ds[-1], blk), sa, smoother_b[l], kpow)
         ops.append(CountingOp((P.conj().T @ A.M @ P).tocsr()))
         ds.append(tuple(L // b for L, b in zip(ds[-1], blk)))
-    H = build(D, dims, all_vecs, blocks, smoother_b, omega)
+    H = build(D, dims, all_vecs, blocks, smoother_b, omega, sa, kpow)
     return H, all_vecs
 
 
@@ -242,8 +290,8 @@ def mgcg(H: NormalHierarchy, b: np.ndarray, tol: float, maxiter: int = 1000):
 
 
 def with_mass(D_of_mass, H: NormalHierarchy, vecs: list, blocks: list, smoother_b: list, dims,
-              omega: float = 0.8) -> NormalHierarchy:
+              omega: float = 0.8, sa: float = 0.0, kpow: int = 20) -> NormalHierarchy:
     """The hierarchy of the same near-null vectors at another mass: every
     Galerkin product rebuilt from D(m) (A(m) = D(m)^dag D(m) is not a shift of
     A(m0)), the step lengths recomputed."""
-    return build(D_of_mass, dims, vecs, blocks, smoother_b, omega)
+    return build(D_of_mass, dims, vecs, blocks, smoother_b, omega, sa, kpow)

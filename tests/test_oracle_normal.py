@@ -182,3 +182,88 @@ def test_fine_applications_per_mgcg_iteration():
     _, info = normal.mgcg(H, b, 1e-10)
     # + one recomputed residual at the convergence check and one for rel_res
     assert info.converged and A.napply == 5 * info.iters + 2
+
+
+def _hier_sa(L, blocks, nvec, sa, m=0.05, seed=0):
+    D = _D(L, m, seed)
+    dims = [(L, L)]
+    vecs, sb = [], []
+    for l, (b, nv) in enumerate(zip(blocks, nvec)):
+        V = dims[-1][0] * dims[-1][1]
+        dof = 2 if l == 0 else nvec[l - 1]
+        vecs.append(_vecs(nv, V, dof, seed * 10 + l))
+        sb.append(synth.gaussian_field((V * dof,), synth.rng_for(122, seed, l)))
+        dims.append((dims[-1][0] // b[0], dims[-1][1] // b[1]))
+    return D, normal.build(D, (L, L), vecs, blocks, sb, sa=sa), vecs, sb
+
+
+def test_normal_operator_is_a_box_stencil():
+    """D^dag D couples x to x + (a, b) with |a|, |b| <= 1 only (the straight
+    double hop cancels), all nine couplings nonzero."""
+    L = 8
+    D = _D(L, 0.05)
+    A = abs((D.conj().T @ D).toarray()).reshape(L * L, 2, L * L, 2).sum((1, 3))
+    x, y = np.arange(L * L) % L, np.arange(L * L) // L
+    dx = np.minimum((x[:, None] - x[None, :]) % L, (x[None, :] - x[:, None]) % L)
+    dy = np.minimum((y[:, None] - y[None, :]) % L, (y[None, :] - y[:, None]) % L)
+    box = (dx <= 1) & (dy <= 1)
+    assert A[~box].max() < 1e-14 and A[box].min() > 0.0
+
+
+def test_power_estimate_bounds_the_largest_eigenvalue():
+    D = _D(16, 0.05)
+    A = normal.CountingOp((D.conj().T @ D).tocsr())
+    lmax = np.linalg.eigvalsh(A.M.toarray()).max()
+    v0 = synth.gaussian_field((A.n,), synth.rng_for(131))
+    est = [normal.power_lmax(A, v0, k) for k in (0, 5, 20, 80)]
+    assert all(e <= lmax * (1 + 1e-12) for e in est)
+    assert est[0] < est[1] <= est[2] <= est[3] and est[3] > 0.95 * lmax
+
+
+def test_smoothed_prolongator_support_and_coarse_reach():
+    """P = (1 - omega A) P_tent.  With r = 1 the spin projectors of a
+    straight double hop multiply to zero, so D^dag D couples a site only to
+    its 3 x 3 box: a smoothed column of block j lives on the block widened by
+    one site on every side (corners included), and for 4 x 4 blocks the
+    Galerkin operator still couples only neighbouring blocks (diagonal ones
+    included): a 9-point box stencil on the coarse lattice."""
+    L, b = 32, 4
+    D, H, vecs, sb = _hier_sa(L, [(b, b)], [4], sa=4.0 / 3.0)
+    A = H.ops[0]
+    Pt = normal.block_prolongator(vecs[0], (L, L), (b, b))
+    om = H.sa_omegas[0]
+    assert om > 0 and abs(om - (4.0 / 3.0) / normal.power_lmax(A, sb[0], 20)) < 1e-15
+    P = H.Ps[0]
+    assert abs(P - (Pt - om * (A.M @ Pt))).max() < 1e-14
+    x = np.arange(L * L) % L
+    y = np.arange(L * L) // L
+    Lc = L // b
+    for j in (0, 5, Lc * Lc - 1):
+        jx, jy = j % Lc, j // Lc
+        col = np.abs(P[:, j * 4].toarray().reshape(L * L, 2)).sum(1)
+        ox, oy = (x - jx * b) % L, (y - jy * b) % L          # offsets from the block's corner
+        ex = np.where(ox < b, 0, np.minimum(ox - (b - 1), L - ox))
+        ey = np.where(oy < b, 0, np.minimum(oy - (b - 1), L - oy))
+        inside = (ex <= 1) & (ey <= 1)
+        assert col[~inside].max() == 0.0 and col[inside].min() > 0.0
+    C = abs(H.ops[1].M.toarray()).reshape(Lc * Lc, 4, Lc * Lc, 4).sum((1, 3))
+    cx, cy = np.arange(Lc * Lc) % Lc, np.arange(Lc * Lc) // Lc
+    ddx = np.minimum((cx[:, None] - cx[None, :]) % Lc, (cx[None, :] - cx[:, None]) % Lc)
+    ddy = np.minimum((cy[:, None] - cy[None, :]) % Lc, (cy[None, :] - cy[:, None]) % Lc)
+    near = (ddx <= 1) & (ddy <= 1)
+    assert C[~near].max() == 0.0 and C[near].min() > 0.0
+
+
+def test_smoothed_vcycle_equals_operator_formula():
+    """Eq. (3) holds for any P, the smoothed one included."""
+    D, H, _, _ = _hier_sa(8, [(4, 4)], [3], sa=4.0 / 3.0)
+    V = _vcycle_matrix(H)
+    A = H.ops[0].M.toarray()
+    P = H.Ps[0].toarray()
+    Ac = H.ops[1].M.toarray()
+    assert np.abs(Ac - P.conj().T @ A @ P).max() < 1e-12 * np.abs(Ac).max()
+    t0, t1 = H.taus[0]
+    I = np.eye(A.shape[0])
+    R = (t0 + t1) * I - t0 * t1 * A
+    ref = R + R.conj().T - R @ A @ R.conj().T + (I - R @ A) @ P @ np.linalg.inv(Ac) @ P.conj().T @ (I - A @ R.conj().T)
+    assert np.abs(V - ref).max() < 1e-10 * np.abs(ref).max()
