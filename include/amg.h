@@ -388,6 +388,113 @@ amg_status amg_setup_learned(const amg_gauge* g, const amg_mg_params* p, amg_cnn
                              double rho_max, int rho_iters, int nu0, int ncyc, void* stream,
                              amg_solver** out, int* fell_back, double* rho);
 
+/* ---- multigrid for the normal equations A = D^dag D (2d) ----------------
+ * The paper's own variant (numerical-test section): the Galerkin hierarchy
+ * A_{l+1} = P_l^dag A_l P_l (Eq. (2)) of the Hermitian positive definite
+ * A_0 = D^dag D, with one coarse degree of freedom per near-null vector (no
+ * chiral split), P_l the block-orthonormalised vectors (Eq. (5)) optionally
+ * smoothed by one damped Richardson step ("smoothed aggregation", adaptive-
+ * method section), the degree-2 smoother whose two minimal-residual step
+ * lengths are computed once and then frozen (R = R^dag), the V-cycle of the
+ * five steps before Eq. (3) ending in an exact solve, and conjugate gradients
+ * preconditioned by one V-cycle per iteration (MG-CG).
+ * Every coarse operator is a 9-point box stencil of M x M blocks (D^dag D
+ * couples a site to its 3 x 3 box only: for r = 1 the straight double hop
+ * cancels), built by probing with coloured unit vectors: coarse extents must
+ * be >= 3 and have a divisor >= 3 (period of the colouring); with smoothing,
+ * blocks >= 3 (the widened columns then still couple neighbouring blocks
+ * only) and coarse extents with a divisor >= 2.
+ * Field layouts: fine fields [site][2] complex128 (x_1 fastest); coarse
+ * fields [site][M]; near-null vectors [M][V_l][dof_l].  All FP64.
+ * Handles keep a pointer to their gauge (which must outlive them) and run on
+ * its device; calls on one handle must not overlap.  Synchronous. */
+typedef struct amg_normal amg_normal;
+
+typedef struct {
+  int nlevels;            /* 2..4 (levels including the finest)                        */
+  int block[3][2];        /* block extents of coarsening l                              */
+  int nvec[3];            /* M of coarsening l (1..16): coarse dof per site             */
+  double omega;           /* under-relaxation of the frozen MR steps (paper: 0.8)       */
+  double sa_factor;       /* f > 0: P = (1 - f / lambda_l A_l) P_tent, lambda_l the     */
+                          /* Rayleigh quotient of A_l after power_steps power steps     */
+                          /* from the level's smoother vector; 0: unsmoothed P          */
+  int power_steps;        /* default 20                                                  */
+  int coarse_dense_max;   /* the coarsest level (V M unknowns) must not exceed this: its */
+                          /* dense Galerkin matrix is inverted (Gauss-Jordan, partial    */
+                          /* pivoting); <= AMG_DENSE_MAX, default 4096                   */
+  int setup_dense_max;        /* adaptive set-up: a set-up cycle's coarse level of at most */
+                              /* this many unknowns is solved exactly (dense inverse),    */
+  double setup_coarse_tol;    /* a larger one by CG to setup_coarse_tol (at most          */
+  int setup_coarse_maxiter;   /* setup_coarse_maxiter iterations); defaults 1024, 1e-6    */
+} amg_normal_params;
+
+typedef struct {
+  int iters;                 /* CG iterations                                             */
+  int converged;             /* |b - A psi| <= tol |b|, b = D^dag chi, recomputed          */
+  int restarts;              /* CG restarts on a recomputed residual                       */
+  double rel_res_normal;     /* |b - A psi| / |b|, FP64                                   */
+  double rel_res_D;          /* |chi - D psi| / |chi|, FP64                               */
+  long long n_fine_D;        /* fine D applications in the call                            */
+  long long n_fine_Ddag;     /* fine D^dag applications in the call                        */
+  double t_ms;               /* wall time of the call (synchronised)                       */
+} amg_normal_info;
+
+void amg_normal_default_params(amg_normal_params* p);
+
+/* Hierarchy from given near-null vectors: dev_vecs[l] holds the nvec[l]
+ * vectors of coarsening l ([M][V_l][dof_l] complex128), dev_sb[l] one field
+ * of level l ([V_l][dof_l]) from which the frozen step lengths (and the power
+ * estimate of the smoothing damping) are computed.  The mass is g's current
+ * mass.  AMG_ERR_RANK if a block's vectors are linearly dependent,
+ * AMG_ERR_SINGULAR if the coarsest matrix is, AMG_ERR_SHAPE for extents the
+ * probing cannot colour. */
+amg_status amg_normal_setup(const amg_gauge* g, const amg_normal_params* p, const void* const* dev_vecs,
+                            const void* const* dev_sb, void* stream, amg_normal** out);
+
+/* Adaptive hierarchy (text from Eq. (4) to the recursion remark after Eq. (5)),
+ * coarsening by coarsening: vector 0 is dev_init[l][0] after nu0[l] MR steps
+ * (omega) on A_l v = 0; vector k >= 1 is dev_init[l][k] after ncyc[l] sweeps
+ * of e <- e - V(A_l e), V the two-level cycle built from vectors 0..k-1
+ * (coarse level solved exactly up to setup_dense_max unknowns, else by CG),
+ * normalised. */
+amg_status amg_normal_setup_adaptive(const amg_gauge* g, const amg_normal_params* p, const void* const* dev_init,
+                                     const void* const* dev_sb, const int* nu0, const int* ncyc, void* stream,
+                                     amg_normal** out);
+
+/* Rebuild P (smoothing), every Galerkin product, the step lengths and the
+ * coarsest inverse for D(mass) from the same near-null vectors (the set-up
+ * at the lightest mass reused for heavier ones, numerical-test section). */
+amg_status amg_normal_set_mass(amg_normal* S, double mass, void* stream);
+
+/* Solve D^dag D psi = D^dag chi by CG (precond 0) or MG-CG (precond 1) from
+ * psi = 0, until the recursive residual of the normal equations falls below
+ * tol |D^dag chi| and the recomputed one confirms it (else restart from the
+ * recomputed residual).  AMG_ERR_NOCONV after max_iter iterations (psi holds
+ * the last iterate). */
+amg_status amg_normal_solve(amg_normal* S, const void* dev_chi, void* dev_psi, double tol, int max_iter,
+                            int precond, amg_normal_info* info, void* stream);
+
+/* dev_out = V dev_in: one V-cycle of the finest level (fine fields). */
+amg_status amg_normal_vcycle(amg_normal* S, const void* dev_in, void* dev_out, void* stream);
+
+/* dev_out = A_level dev_in (level 0: D^dag D; level >= 1: the box stencil). */
+amg_status amg_normal_level_apply(amg_normal* S, int level, const void* dev_in, void* dev_out, void* stream);
+
+/* Exports (test infrastructure):
+ *   what 0: P of coarsening `level` as the dense matrix [V_l dof_l][V_{l+1} M]
+ *   what 1: A_level (level >= 1) as the dense matrix [V M][V M]
+ *   what 2: the near-null vectors of coarsening `level` ([M][V_l][dof_l])
+ * (row-major complex128, at most 2^28 entries, else AMG_ERR_ARG). */
+amg_status amg_normal_export(amg_normal* S, int level, int what, void* dev_out, void* stream);
+
+/* Level facts: extents, dof per site, the frozen step lengths (tau0, tau1) of
+ * the level's smoother, and (lambda, omega_sa) of its smoothed P (zeros on
+ * the coarsest level or without smoothing).  NULL outputs are skipped. */
+amg_status amg_normal_level_info(const amg_normal* S, int level, int* dims2, int* dof, double* taus2,
+                                 double* lambda_omega2);
+
+amg_status amg_normal_destroy(amg_normal* S);
+
 #ifdef __cplusplus
 }
 #endif

@@ -200,16 +200,16 @@ class _CGCoarse:
 
 def adaptive_setup(D: sp.spmatrix, dims, blocks: list, nvec: list, init: list, smoother_b: list,
                    nu0=20, ncyc=2, omega: float = 0.8, sa: float = 0.0, kpow: int = 20,
-                   setup_coarse_tol=None, setup_coarse_maxiter: int = 100000):
+                   setup_dense_max=None, setup_coarse_tol: float = 1e-6, setup_coarse_maxiter: int = 20000):
     """Adaptive construction for A = D^dag D, level by level (text from Eq. (4)
     to the recursion remark after Eq. (5)): vector 1 of coarsening l is
     init[l][0] after nu0 MR relaxations on A_l v = 0; vector k > 1 is
     init[l][k-1] after ncyc sweeps of e <- e - V(A_l e) with the two-level
-    cycle of the vectors so far (level l+1 solved exactly), normalised.
-    nu0 and ncyc are numbers or one number per coarsening.  The prolongators
-    of the set-up cycles are smoothed like the final ones (sa).  The coarse
-    level of a set-up cycle is factored (setup_coarse_tol None) or solved by
-    CG to that relative residual.
+    cycle of the vectors so far, normalised.  nu0 and ncyc are numbers or one
+    number per coarsening.  The prolongators of the set-up cycles are
+    smoothed like the final ones (sa).  The coarse level of a set-up cycle is
+    solved exactly (factored) when setup_dense_max is None or it has at most
+    setup_dense_max unknowns, else by CG to setup_coarse_tol.
     Returns (hierarchy, vecs)."""
     nl = len(blocks)
     nu0 = list(nu0) if np.ndim(nu0) else [nu0] * nl
@@ -227,8 +227,8 @@ def adaptive_setup(D: sp.spmatrix, dims, blocks: list, nvec: list, init: list, s
             Pt = block_prolongator(np.stack([v.reshape(shape) for v in vecs]), ds[-1], blk)
             P, _ = smoothed_prolongator(A, Pt, sa, smoother_b[l], kpow)
             Ac = CountingOp((P.conj().T @ A.M @ P).tocsr())
-            cs = (spla.splu(Ac.M.tocsc()) if setup_coarse_tol is None
-                  else _CGCoarse(Ac, setup_coarse_tol, setup_coarse_maxiter))
+            exact = setup_dense_max is None or Ac.n <= setup_dense_max
+            cs = spla.splu(Ac.M.tocsc()) if exact else _CGCoarse(Ac, setup_coarse_tol, setup_coarse_maxiter)
             H2 = NormalHierarchy([A, Ac], [P], [ds[-1]], [taus], cs)
             e = init[l][k].reshape(-1).astype(np.complex128).copy()
             for _ in range(ncyc[l]):

@@ -9,6 +9,7 @@ Method: Brannick, Brower, Clark, Osborn, Rebbi, "Adaptive Multigrid Algorithm
 for Lattice QCD", arXiv:0707.4018.
 """
 from .binding import (  # noqa: F401
-    AMGError, Batch, Cnn, Gauge, MGParams, Solver, SolveInfo, F32, F64, lib_path, load_library,
+    AMGError, Batch, Cnn, Gauge, MGParams, NormalInfo, NormalMG, NormalParams, Solver, SolveInfo, F32, F64,
+    lib_path, load_library,
     use_torch_allocator,
 )

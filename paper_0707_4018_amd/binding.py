@@ -52,6 +52,21 @@ class _Info(C.Structure):
     ]
 
 
+class _NParams(C.Structure):
+    _fields_ = [
+        ("nlevels", C.c_int), ("block", (C.c_int * 2) * 3), ("nvec", C.c_int * 3), ("omega", C.c_double),
+        ("sa_factor", C.c_double), ("power_steps", C.c_int), ("coarse_dense_max", C.c_int),
+        ("setup_dense_max", C.c_int), ("setup_coarse_tol", C.c_double), ("setup_coarse_maxiter", C.c_int),
+    ]
+
+
+class _NInfo(C.Structure):
+    _fields_ = [
+        ("iters", C.c_int), ("converged", C.c_int), ("restarts", C.c_int), ("rel_res_normal", C.c_double),
+        ("rel_res_D", C.c_double), ("n_fine_D", C.c_longlong), ("n_fine_Ddag", C.c_longlong), ("t_ms", C.c_double),
+    ]
+
+
 _P = C.c_void_p
 _ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
 _RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
@@ -105,6 +120,18 @@ _SIGS = {
                                     C.POINTER(C.c_float), _P]),
     "amg_cnn_train_step": (C.c_int, [_P, _P, _P, C.c_int, C.c_int, C.c_int, C.c_float, C.POINTER(C.c_double), _P]),
     "amg_cnn_propose": (C.c_int, [_P, _P, C.c_int, C.c_int, _P, _P]),
+    "amg_normal_default_params": (None, [C.POINTER(_NParams)]),
+    "amg_normal_setup": (C.c_int, [_P, C.POINTER(_NParams), C.POINTER(_P), C.POINTER(_P), _P, C.POINTER(_P)]),
+    "amg_normal_setup_adaptive": (C.c_int, [_P, C.POINTER(_NParams), C.POINTER(_P), C.POINTER(_P),
+                                            C.POINTER(C.c_int), C.POINTER(C.c_int), _P, C.POINTER(_P)]),
+    "amg_normal_set_mass": (C.c_int, [_P, C.c_double, _P]),
+    "amg_normal_solve": (C.c_int, [_P, _P, _P, C.c_double, C.c_int, C.c_int, C.POINTER(_NInfo), _P]),
+    "amg_normal_vcycle": (C.c_int, [_P, _P, _P, _P]),
+    "amg_normal_level_apply": (C.c_int, [_P, C.c_int, _P, _P, _P]),
+    "amg_normal_export": (C.c_int, [_P, C.c_int, C.c_int, _P, _P]),
+    "amg_normal_level_info": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                        C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "amg_normal_destroy": (C.c_int, [_P]),
     "amg_setup_learned": (C.c_int, [_P, C.POINTER(_Params), _P, C.POINTER(_P), C.c_int, C.c_int, C.c_int,
                                     C.c_double, C.c_int, C.c_int, C.c_int, _P, C.POINTER(_P), C.POINTER(C.c_int),
                                     C.POINTER(C.c_double)]),
@@ -634,6 +661,142 @@ class Cnn:
         try:
             if getattr(self, "_h", None):
                 load_library().amg_cnn_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+
+@dataclass
+class NormalParams:
+    """Multigrid for the normal equations D^dag D (the paper's own variant):
+    defaults are the paper's (4x4 blocks twice, M = 8, omega = 0.8) and the
+    classical smoothing factor 4/3."""
+    blocks: list = field(default_factory=lambda: [(4, 4), (4, 4)])
+    nvec: list = field(default_factory=lambda: [8, 8])
+    omega: float = 0.8
+    sa_factor: float = 4.0 / 3.0
+    power_steps: int = 20
+    coarse_dense_max: int = 4096
+    setup_dense_max: int = 1024
+    setup_coarse_tol: float = 1e-6
+    setup_coarse_maxiter: int = 20000
+
+    def to_c(self) -> _NParams:
+        p = _NParams()
+        load_library().amg_normal_default_params(C.byref(p))
+        p.nlevels = len(self.blocks) + 1
+        for l, b in enumerate(self.blocks):
+            p.block[l][0], p.block[l][1] = int(b[0]), int(b[1])
+            p.nvec[l] = int(self.nvec[l])
+        p.omega, p.sa_factor, p.power_steps = self.omega, self.sa_factor, self.power_steps
+        p.coarse_dense_max, p.setup_dense_max = self.coarse_dense_max, self.setup_dense_max
+        p.setup_coarse_tol, p.setup_coarse_maxiter = self.setup_coarse_tol, self.setup_coarse_maxiter
+        return p
+
+
+@dataclass
+class NormalInfo:
+    iters: int
+    converged: bool
+    restarts: int
+    rel_res_normal: float
+    rel_res_D: float
+    n_fine_D: int
+    n_fine_Ddag: int
+    t_ms: float
+
+
+class NormalMG:
+    """amg_normal_*: MG on A = D^dag D with the Galerkin hierarchy, the frozen
+    two-step smoother and (MG-)CG, bound to a 2d Gauge."""
+
+    def __init__(self, gauge: Gauge, params: NormalParams, smoother_b, vecs=None, init=None, nu0=20, ncyc=2):
+        """From given near-null vectors `vecs` ([M, V_l, dof_l] per coarsening)
+        or adaptively from `init` (nu0 / ncyc: a count or one per coarsening);
+        smoother_b: one field per coarsening level ([V_l, dof_l])."""
+        lib = load_library()
+        self.gauge = gauge
+        self.params = params
+        self._p = params.to_c()
+        sbs = [v.contiguous() for v in smoother_b]
+        sarr = (C.c_void_p * len(sbs))(*[_ptr(v).value for v in sbs])
+        h = C.c_void_p()
+        if vecs is not None:
+            vs = [v.contiguous() for v in vecs]
+            arr = (C.c_void_p * len(vs))(*[_ptr(v).value for v in vs])
+            _check(lib.amg_normal_setup(gauge.handle, C.byref(self._p), arr, sarr, _stream(), C.byref(h)),
+                   "amg_normal_setup")
+        else:
+            vs = [v.contiguous() for v in init]
+            arr = (C.c_void_p * len(vs))(*[_ptr(v).value for v in vs])
+            nl = len(vs)
+            n0 = list(nu0) if isinstance(nu0, (list, tuple)) else [nu0] * nl
+            nc = list(ncyc) if isinstance(ncyc, (list, tuple)) else [ncyc] * nl
+            _check(lib.amg_normal_setup_adaptive(gauge.handle, C.byref(self._p), arr, sarr, (C.c_int * nl)(*n0),
+                                                 (C.c_int * nl)(*nc), _stream(), C.byref(h)),
+                   "amg_normal_setup_adaptive")
+        self._keep = (vs, sbs)
+        self._h = h
+        self.nlevels = len(params.blocks) + 1
+
+    def set_mass(self, m: float):
+        _check(load_library().amg_normal_set_mass(self._h, float(m), _stream()), "amg_normal_set_mass")
+
+    def solve(self, chi: torch.Tensor, tol: float = 1e-10, max_iter: int = 100000, precond: bool = True):
+        """psi with D^dag D psi = D^dag chi by MG-CG (precond) or CG."""
+        x = chi.contiguous()
+        psi = torch.empty_like(x)
+        info = _NInfo()
+        st = load_library().amg_normal_solve(self._h, _ptr(x), _ptr(psi), float(tol), int(max_iter), int(precond),
+                                             C.byref(info), _stream())
+        if st not in (0, 7):
+            _check(st, "amg_normal_solve")
+        return psi, NormalInfo(info.iters, bool(info.converged), info.restarts, info.rel_res_normal, info.rel_res_D,
+                               info.n_fine_D, info.n_fine_Ddag, info.t_ms)
+
+    def vcycle(self, x: torch.Tensor) -> torch.Tensor:
+        x = x.contiguous()
+        out = torch.empty_like(x)
+        _check(load_library().amg_normal_vcycle(self._h, _ptr(x), _ptr(out), _stream()), "amg_normal_vcycle")
+        return out
+
+    def level_apply(self, level: int, x: torch.Tensor) -> torch.Tensor:
+        x = x.contiguous()
+        out = torch.empty_like(x)
+        _check(load_library().amg_normal_level_apply(self._h, int(level), _ptr(x), _ptr(out), _stream()),
+               "amg_normal_level_apply")
+        return out
+
+    def level_info(self, level: int) -> dict:
+        dims, dof = (C.c_int * 2)(), C.c_int()
+        taus, lo = (C.c_double * 2)(), (C.c_double * 2)()
+        _check(load_library().amg_normal_level_info(self._h, int(level), dims, C.byref(dof), taus, lo),
+               "amg_normal_level_info")
+        return {"dims": (dims[0], dims[1]), "dof": dof.value, "taus": (taus[0], taus[1]),
+                "lambda": lo[0], "sa_omega": lo[1]}
+
+    def export(self, level: int, what: int) -> torch.Tensor:
+        """0: P of coarsening `level` (dense), 1: A_level (dense), 2: the
+        near-null vectors of coarsening `level`."""
+        lib = load_library()
+        if what == 0:
+            f, c = self.level_info(level), self.level_info(level + 1)
+            shape = (f["dims"][0] * f["dims"][1] * f["dof"], c["dims"][0] * c["dims"][1] * c["dof"])
+        elif what == 1:
+            i = self.level_info(level)
+            n = i["dims"][0] * i["dims"][1] * i["dof"]
+            shape = (n, n)
+        else:
+            f, c = self.level_info(level), self.level_info(level + 1)
+            shape = (c["dof"], f["dims"][0] * f["dims"][1], f["dof"])
+        out = torch.empty(shape, dtype=torch.complex128, device="cuda")
+        _check(lib.amg_normal_export(self._h, int(level), int(what), _ptr(out), _stream()), "amg_normal_export")
+        return out
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None):
+                load_library().amg_normal_destroy(self._h)
                 self._h = None
         except Exception:
             pass

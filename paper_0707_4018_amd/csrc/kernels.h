@@ -210,4 +210,42 @@ void launch_cg_update(double2* x, double2* r, const double2* p, const double2* q
 void launch_cg_pupdate(double2* p, const double2* s, long n, int nrhs, const double* scal, int gnew_slot,
                        int gold_slot, hipStream_t st);
 
+// ---- multigrid for the normal equations (2d, unsplit P, 9-point box stencils) ----
+// One coarsening: fine extents f1 x f2 with dof components per site in layout
+// lf, blocks b1 x b2, coarse extents c1 x c2 with M components per site
+// ([site][k]); sa: P smoothed (2 x 2 candidate blocks per fine site).
+struct NGeom {
+  int f1, f2, b1, b2, c1, c2;
+  int dof, M, sa;
+  Layout lf;
+};
+size_t normal_orth_lds(const NGeom& g);
+// tentative P [Vf][dof][M] from vecs (M fields of layout lf, vstride apart); *err |= 1 on rank deficiency
+void launch_normal_orth(double2* Pt, const double2* vecs, const NGeom& g, long vstride, int* err, hipStream_t st);
+void launch_normal_prolong(double2* out, const double2* in, const double2* P, const NGeom& g, int nrhs, int accumulate,
+                           hipStream_t st);
+void launch_normal_restrict(double2* out, const double2* in, const double2* P, const NGeom& g, int nrhs,
+                            hipStream_t st);
+// out = Y in (epi 0) or b - Y in (epi 1) for the box stencil Y[V][9][M][M]
+void launch_box(double2* out, const double2* in, const double2* b, const double2* Y, int L1, int L2, int M, int nrhs,
+                int epi, hipStream_t st);
+void launch_box_dense(double2* A, const double2* Y, int L1, int L2, int M, hipStream_t st);
+void launch_probe(double2* e, int c1, int c2, int M, int p1, int p2, int q0, int nq, hipStream_t st);
+void launch_galerkin_box_scatter(double2* Y, const double2* z, int c1, int c2, int M, int p1, int p2, int q0, int nq,
+                                 hipStream_t st);
+void launch_psa_scatter(double2* P, const double2* y, const NGeom& g, int p1, int p2, int q0, int nq,
+                        hipStream_t st);
+// P as a dense matrix [Vf dof][Vc M] (zeroed before)
+void launch_normal_p_dense(double2* out, const double2* P, const NGeom& g, hipStream_t st);
+// scal[slot .. slot+2] = Re <a, b>, Im <a, b>, <a, a>
+void launch_dot3(const double2* a, const double2* b, long n, RedArgs red, hipStream_t st);
+void launch_mr_step(double2* x, double2* r, const double2* p, const double* scal, int slot, double omega, long n,
+                    hipStream_t st);
+void launch_smooth_step(double2* x, double2* r, const double2* b, const double2* t, double tau, long n, int first,
+                        hipStream_t st);
+void launch_smooth_post(double2* x, const double2* r, const double2* t, double c1, double c2, long n,
+                        hipStream_t st);
+void launch_axpy3(double2* y, const double2* x, const double2* t, double w, long n, hipStream_t st);
+void launch_scale_norm(double2* p, const double2* q, const double* scal, int slot, long n, hipStream_t st);
+
 }  // namespace amg
