@@ -584,6 +584,135 @@ def cfg1_oracle():
 
 
 # ---------------------------------------------------------------------------
+# The paper's own experiment (numerical-test section): CG and MG-CG on
+# D^dag D for 128^2 ensembles at beta 6 and 10 in the sectors Q = 0 and 4,
+# the set-up done once at the lightest mass and reused for the heavier ones;
+# fine D and D^dag applications against the mass gap (the shape of its two
+# figures) and its one printed result (3808 CG vs 26 MG-CG iterations at
+# beta 6, m_hat 0.01, Q 0).  Point source; Gaussian and Z4 sources at one mass.
+# ---------------------------------------------------------------------------
+NORMAL_NAMES = ["paper128_b6_q0", "paper128_b6_q4", "paper128_b10_q0", "paper128_b10_q4"]
+NORMAL_BLOCKS = [(4, 4), (4, 4)]
+NORMAL_NVEC = [8, 8]
+NORMAL_NU0 = [100, 500]
+NORMAL_NCYC = [20, 200]
+NORMAL_TOL = 1e-14
+NORMAL_L = 128
+
+
+def gen_normal_config(name):
+    return name, synth.u1_field_of(WORKLOADS[name])
+
+
+def normal_inputs():
+    dims, init, sb = [(NORMAL_L, NORMAL_L)], [], []
+    for l, (b, nv) in enumerate(zip(NORMAL_BLOCKS, NORMAL_NVEC)):
+        V = dims[-1][0] * dims[-1][1]
+        dof = 2 if l == 0 else NORMAL_NVEC[l - 1]
+        init.append(np.stack([synth.gaussian_field((V, dof), synth.rng_for(160, l, k)) for k in range(nv)]))
+        sb.append(synth.gaussian_field((V, dof), synth.rng_for(161, l)))
+        dims.append((dims[-1][0] // b[0], dims[-1][1] // b[1]))
+    return init, sb
+
+
+def normal_source(kind):
+    V = NORMAL_L * NORMAL_L
+    if kind == "point":
+        chi = np.zeros((V, 2), dtype=np.complex128)
+        chi[0, 0] = 1.0
+        return chi
+    if kind == "gaussian":
+        return synth.gaussian_field((V, 2), synth.rng_for(162))
+    z = synth.rng_for(163).integers(0, 4, size=(V, 2))                # Z4 noise
+    return np.exp(0.5j * np.pi * z)
+
+
+def normal_bench_with_oracle(amg, torch, nfields):
+    """normal_bench, with the oracle's cost per iteration measured beside it
+    in a single-threaded worker process."""
+    import subprocess
+    import tempfile
+    proc = None
+    if "paper128_b6_q0" in nfields:
+        tmp = tempfile.mkdtemp(prefix="amg_bench_normal_")
+        pin, pout = os.path.join(tmp, "theta.npz"), os.path.join(tmp, "normal.json")
+        np.savez(pin, theta=nfields["paper128_b6_q0"])
+        env = dict(os.environ, OMP_NUM_THREADS="1", MKL_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1",
+                   HIP_VISIBLE_DEVICES="", CUDA_VISIBLE_DEVICES="")
+        proc = subprocess.Popen([sys.executable, os.path.abspath(__file__), "--oracle-child", "normal", pin, pout],
+                                env=env)
+    out = normal_bench(amg, torch, nfields)
+    if proc is not None:
+        if proc.wait() != 0:
+            raise RuntimeError("oracle worker (normal equations) failed")
+        o = json.load(open(pout))
+        row = next(r for r in out["ensembles"]["paper128_b6_q0"]["solves"] if r["mass_gap"] == 0.01)
+        out["oracle_beside"] = {
+            "kind": "oracle", "cores": 1, "workload": "paper128_b6_q0, m_hat 0.01, point source",
+            "mgcg_ms_per_iter": round(o["mgcg_ms_per_iter"], 2), "cg_ms_per_iter": round(o["cg_ms_per_iter"], 3),
+            "gpu_mgcg_ms_per_iter": round(row["mgcg_ms"] / max(1, row["mgcg_iters"]), 3),
+            "gpu_cg_ms_per_iter": round(row["cg_ms"] / max(1, row["cg_iters"]), 4),
+            "sample": "10 MG-CG and 200 CG iterations of the oracle on a hierarchy of the same shape "
+                      "(random near-null vectors), FP64 NumPy/SciPy, one thread"}
+    return out
+
+
+def normal_bench(amg, torch, nfields):
+    """Per ensemble: the adaptive set-up at the lightest mass (timed), then
+    for every mass gap the hierarchy rebuilt at that mass and the point
+    source solved by MG-CG and by CG to NORMAL_TOL."""
+    init, sb = normal_inputs()
+    params = amg.NormalParams(blocks=NORMAL_BLOCKS, nvec=NORMAL_NVEC, sa_factor=4.0 / 3.0)
+    point = torch.from_numpy(normal_source("point")).cuda()
+    out = {"ensembles": {}, "tol": NORMAL_TOL, "setup": {"nu0": NORMAL_NU0, "ncyc": NORMAL_NCYC,
+                                                         "blocks": NORMAL_BLOCKS, "nvec": NORMAL_NVEC,
+                                                         "sa_factor": 4.0 / 3.0, "omega": 0.8}}
+    for name, th in nfields.items():
+        W = WORKLOADS[name]
+        m_light = min(W["masses"])
+        g = amg.Gauge(torch.from_numpy(np.exp(1j * th)[..., None, None].copy()).cuda(), m_light)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S = amg.NormalMG(g, params, [torch.from_numpy(v).cuda() for v in sb],
+                         init=[torch.from_numpy(v).cuda() for v in init], nu0=NORMAL_NU0, ncyc=NORMAL_NCYC)
+        torch.cuda.synchronize()
+        setup_ms = 1e3 * (time.perf_counter() - t0)
+        rows = []
+        for gap, m in sorted(zip(W["mass_gaps"], W["masses"]), reverse=True):
+            t1 = time.perf_counter()
+            S.set_mass(m)
+            torch.cuda.synchronize()
+            rebuild_ms = 1e3 * (time.perf_counter() - t1)
+            _, im = S.solve(point, tol=NORMAL_TOL, max_iter=500, precond=True)
+            _, ic = S.solve(point, tol=NORMAL_TOL, max_iter=50000, precond=False)
+            rows.append({
+                "mass_gap": gap, "mass": m, "rebuild_ms": round(rebuild_ms, 2),
+                "mgcg_iters": im.iters, "mgcg_converged": im.converged, "mgcg_rel_res": im.rel_res_normal,
+                "mgcg_ms": round(im.t_ms, 2),
+                "mgcg_fine_D_applications": im.n_fine_D + im.n_fine_Ddag,
+                "mgcg_fine_D_applications_paper_count": 12 * im.iters,
+                "cg_iters": ic.iters, "cg_converged": ic.converged, "cg_rel_res": ic.rel_res_normal,
+                "cg_ms": round(ic.t_ms, 2), "cg_fine_D_applications": ic.n_fine_D + ic.n_fine_Ddag,
+                "iteration_ratio": round(ic.iters / max(1, im.iters), 1),
+                "fine_D_ratio_paper_count": round(2 * ic.iters / max(1, 12 * im.iters), 2),
+            })
+            log(f"  {name} m_hat {gap}: MG-CG {im.iters} it ({im.t_ms:.1f} ms), CG {ic.iters} it ({ic.t_ms:.1f} ms)")
+        ent = {"beta": W["beta"], "Q": W["Q"], "m_crit": W["m_crit"], "setup_ms": round(setup_ms, 1),
+               "solves": rows}
+        if name == "paper128_b6_q0":
+            S.set_mass(W["m_crit"] + 0.01)
+            srcs = {}
+            for kind in ("point", "gaussian", "z4"):
+                chi = torch.from_numpy(normal_source(kind)).cuda()
+                _, i = S.solve(chi, tol=NORMAL_TOL, max_iter=500, precond=True)
+                srcs[kind] = {"mgcg_iters": i.iters, "converged": i.converged, "rel_res": i.rel_res_normal}
+            ent["sources_at_m_hat_0.01"] = srcs
+        out["ensembles"][name] = ent
+        del S, g
+    return out
+
+
+# ---------------------------------------------------------------------------
 # CPU oracle (test infrastructure, never on the product path): timed in
 # single-threaded worker processes on the host while the GPU sections run
 # ---------------------------------------------------------------------------
@@ -625,6 +754,27 @@ def oracle_child(mode: str, path_in: str, path_out: str):
             res["solves"].append({"mass_gap": gap, "iters": info.iters, "true_rel_res": info.true_rel_res,
                                   "s": t3 - t2})
         res["total_s"] = time.perf_counter() - t0
+    elif mode == "normal":
+        # the oracle's MG-CG and CG per iteration on a hierarchy of the
+        # benchmark's shape (random near-null vectors: the cost per iteration
+        # does not depend on them), beta 6, Q 0, m_hat 0.01
+        from oracle import normal
+        with np.load(path_in) as z:
+            th = z["theta"]
+        W = WORKLOADS["paper128_b6_q0"]
+        init, sb = normal_inputs()
+        D = mg.wilson_stencil(dirac.u1_field(th), W["m_crit"] + 0.01).to_sparse()
+        t0 = time.perf_counter()
+        H = normal.build(D, (NORMAL_L, NORMAL_L), init, NORMAL_BLOCKS, [v.ravel() for v in sb], sa=4.0 / 3.0)
+        t1 = time.perf_counter()
+        b = D.conj().T @ normal_source("point").ravel()
+        _, i_mg = normal.mgcg(H, b, 1e-30, maxiter=10)
+        t2 = time.perf_counter()
+        _, i_cg = normal.pcg(H.ops[0], b, None, 1e-30, 200)
+        t3 = time.perf_counter()
+        res["build_s"] = t1 - t0
+        res["mgcg_ms_per_iter"] = 1e3 * (t2 - t1) / max(1, i_mg.iters)
+        res["cg_ms_per_iter"] = 1e3 * (t3 - t2) / max(1, i_cg.iters)
     elif mode == "errors":
         with np.load(path_in) as data:
             b = source()[0].reshape(L * L, 2)
@@ -766,6 +916,9 @@ def main():
     ap.add_argument("--no-cfg1", action="store_true")
     ap.add_argument("--only-stencil", action="store_true",
                     help="time the fine stencils alone (for profiling runs) and print their JSON")
+    ap.add_argument("--no-normal", action="store_true")
+    ap.add_argument("--only-normal", action="store_true",
+                    help="run the normal-equation (MG-CG vs CG) experiment alone and print its JSON")
     ap.add_argument("--only-4d", action="store_true",
                     help="run the 4d multi-rhs workload alone (for profiling runs) and print its JSON")
     args = ap.parse_args()
@@ -790,6 +943,14 @@ def main():
         del x, y
         print(json.dumps({"stencil": stencil_bench(amg, torch, th)}))
         return
+    if args.only_normal:
+        with cf.ProcessPoolExecutor(max_workers=4) as ex:
+            nfields = dict(ex.map(gen_normal_config, [n for n in NORMAL_NAMES if n in WORKLOADS]))
+        import torch
+        import paper_0707_4018_amd as amg
+        torch.cuda.set_device(0)
+        print(json.dumps({"normal_mgcg": normal_bench_with_oracle(amg, torch, nfields)}))
+        return
     if args.only_4d:
         U4 = gen_4d_base()
         import torch
@@ -804,9 +965,12 @@ def main():
         f4 = ex.submit(gen_4d_base) if not args.no_4d else None
         use_learned = not args.no_learned and os.path.exists(LEARNED_WEIGHTS)
         lfut = [ex.submit(gen_learned_config, n) for n in LEARNED_NAMES if n in WORKLOADS] if use_learned else []
+        nfut = ([] if args.no_normal else
+                [ex.submit(gen_normal_config, n) for n in NORMAL_NAMES if n in WORKLOADS])
         fields = dict(f.result() for f in fut.values())
         bfields = dict(f.result() for f in bfut)
         lfields = dict(f.result() for f in lfut)
+        nfields = dict(f.result() for f in nfut)
         U4 = f4.result() if f4 is not None else None
 
     import torch
@@ -901,6 +1065,9 @@ def main():
         log("4d multi-rhs workload")
         out["wilson4d"] = wilson4d_bench(amg, torch, U4)
         del U4
+    if nfields:
+        log("normal equations: MG-CG vs CG (the paper's experiment)")
+        out["normal_mgcg"] = normal_bench_with_oracle(amg, torch, nfields)
     if lfields:
         log("learned setup")
         out["learned"] = learned_bench(amg, torch, lfields)

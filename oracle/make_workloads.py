@@ -47,6 +47,43 @@ WORKLOADS = [
 ]
 
 
+# ensembles of the paper's own test (128^2, beta 6 and 10) in chosen
+# topological sectors: the heat-bath starts from the constant flux of charge
+# Q (cold for Q = 0) and the first seed index whose field still has charge Q
+# is kept (name, L, beta, Q, sweeps, mass gaps)
+WORKLOADS_Q = [
+    ("paper128_b6_q0", 128, 6.0, 0, 500, [1e-1, 3e-2, 1e-2, 3e-3, 1e-3]),
+    ("paper128_b6_q4", 128, 6.0, 4, 500, [1e-1, 3e-2, 1e-2, 3e-3, 1e-3]),
+    ("paper128_b10_q0", 128, 10.0, 0, 500, [1e-1, 3e-2, 1e-2, 3e-3, 1e-3]),
+    ("paper128_b10_q4", 128, 10.0, 4, 500, [1e-1, 3e-2, 1e-2, 3e-3, 1e-3]),
+]
+
+
+def entry_q(w):
+    """(name, entry) of the first seed idx = 0, 1, ... (seed (6, 100 beta, L, L,
+    idx)) whose heat-bath field, started from the flux background of charge Q,
+    has topological charge Q."""
+    name, L, beta, Q, sweeps, gaps = w
+    t0 = time.time()
+    for idx in range(1000):
+        seed = [6, int(round(100 * beta)), L, L, idx]
+        th = synth.u1_heatbath(L, L, beta, sweeps, synth.rng_for(*seed), synth.u1_flux(L, L, Q))
+        if round(synth.u1_topological_charge(th)) == Q:
+            break
+    else:
+        raise RuntimeError(f"no field with Q = {Q} among 1000 seeds")
+    A0 = mg.wilson_stencil(dirac.u1_field(th), 0.0)
+    mcrit, lam = spectrum.critical_mass(A0)
+    e = {
+        "cfg": 6, "L1": L, "L2": L, "beta": beta, "idx": idx, "sweeps": sweeps, "start_flux_Q": Q,
+        "seed": seed, "m_crit": mcrit, "leftmost_eigenvalue_m0": [lam.real, lam.imag],
+        "mass_gaps": gaps, "masses": [mcrit + g for g in gaps],
+        "plaquette": synth.u1_mean_plaquette(th), "Q": round(synth.u1_topological_charge(th)),
+    }
+    print(name, f"idx {idx} m_crit {mcrit:.12f} Q {e['Q']} ({time.time() - t0:.1f} s)", flush=True)
+    return name, e
+
+
 def entry(w):
     """(name, table entry) of one 2d U(1) workload."""
     name, cfg, L, beta, idx, sweeps, gaps = w
@@ -83,12 +120,16 @@ def compare(stored: dict, new: dict) -> list[str]:
     return bad
 
 
+def _one(w):
+    return entry_q(w) if len(w) == 6 else entry(w)
+
+
 def _run(todo, workers):
     if workers > 1:
         import concurrent.futures as cf
         with cf.ProcessPoolExecutor(max_workers=workers) as ex:
-            return list(ex.map(entry, todo))
-    return [entry(w) for w in todo]
+            return list(ex.map(_one, todo))
+    return [_one(w) for w in todo]
 
 
 def main(names=None, workers=1, check=False) -> int:
@@ -96,7 +137,7 @@ def main(names=None, workers=1, check=False) -> int:
     if os.path.exists(OUT):
         with open(OUT) as f:
             table = json.load(f)
-    todo = [w for w in WORKLOADS if not names or w[0] in names]
+    todo = [w for w in WORKLOADS + WORKLOADS_Q if not names or w[0] in names]
     done = _run(todo, workers)
     if check:
         nbad = 0

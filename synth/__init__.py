@@ -65,6 +65,18 @@ def _staple_sum(theta: np.ndarray, mu: int) -> np.ndarray:
     return np.exp(1j * up) + np.exp(1j * down)
 
 
+def u1_flux(L1: int, L2: int, Q: int) -> np.ndarray:
+    """Link angles (2, L2, L1) of a constant magnetic flux 2 pi Q / (L1 L2)
+    through every plaquette: theta_1 = -2 pi Q x2 / (L1 L2) everywhere, and
+    on the last row x2 = L2 - 1 theta_2 = 2 pi Q x1 / L1 closes the flux
+    around the torus.  Total charge Q (a start in the sector Q)."""
+    x2, x1 = np.meshgrid(np.arange(L2), np.arange(L1), indexing="ij")
+    th = np.zeros((2, L2, L1))
+    th[0] = -2.0 * np.pi * Q * x2 / (L1 * L2)
+    th[1][L2 - 1] = 2.0 * np.pi * Q * np.arange(L1) / L1
+    return np.angle(np.exp(1j * th))
+
+
 def u1_heatbath(L1: int, L2: int, beta: float, sweeps: int,
                 rng: np.random.Generator, theta: np.ndarray | None = None) -> np.ndarray:
     """Quenched U(1) heat-bath with the Wilson plaquette action (paper's test section).
@@ -91,6 +103,15 @@ def u1_heatbath(L1: int, L2: int, beta: float, sweeps: int,
                 mean = -np.angle(S[m])
                 th[mu][m] = rng.vonmises(mean, kappa)
     return np.angle(np.exp(1j * th))
+
+
+def u1_field_of(entry: dict) -> np.ndarray:
+    """Link angles of a 2d workload-table entry: the seeded heat-bath from its
+    start (cold, or the constant flux of charge start_flux_Q)."""
+    L1, L2 = entry["L1"], entry["L2"]
+    q = entry.get("start_flux_Q", 0)
+    return u1_heatbath(L1, L2, entry["beta"], entry["sweeps"], rng_for(*entry["seed"]),
+                       u1_flux(L1, L2, q) if q else None)
 
 
 def u1_links(theta: np.ndarray) -> np.ndarray:

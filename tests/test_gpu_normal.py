@@ -227,7 +227,7 @@ def paper128():
     import paper_0707_4018_amd as amg
     wl = json.load(open(os.path.join(ROOT, "synth", "workloads.json")))["paper128_b6_q0"]
     L = 128
-    th = synth.u1_heatbath(L, L, wl["beta"], wl["sweeps"], synth.rng_for(*wl["seed"]))
+    th = synth.u1_field_of(wl)
     assert synth.u1_mean_plaquette(th) == wl["plaquette"]
     U = dirac.u1_field(th)
     mc = wl["m_crit"]

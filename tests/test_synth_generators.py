@@ -87,3 +87,16 @@ def test_su3_haar_and_stout():
     assert p1 > p0 + 0.1
     # Haar: <(1/3) Re tr U_P> = 0 in expectation (small sample, loose bound)
     assert abs(p0) < 0.1
+
+
+@pytest.mark.parametrize("Q", [0, 1, 4, -3])
+def test_flux_background_has_charge_q_and_uniform_flux(Q):
+    """The constant-flux start: every plaquette angle is 2 pi Q / V and the
+    charge is exactly Q; a short heat-bath at beta = 10 from it keeps Q."""
+    L1, L2 = 16, 12
+    th = synth.u1_flux(L1, L2, Q)
+    a = np.angle(np.exp(1j * synth.u1_plaquette_angles(th)))
+    assert np.abs(a - 2 * np.pi * Q / (L1 * L2)).max() < 1e-12
+    assert synth.u1_topological_charge(th) == pytest.approx(Q, abs=1e-9)
+    th2 = synth.u1_heatbath(L1, L2, 10.0, 5, synth.rng_for(9, Q + 10), th)
+    assert round(synth.u1_topological_charge(th2)) == Q
