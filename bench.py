@@ -627,13 +627,13 @@ def normal_source(kind):
     return np.exp(0.5j * np.pi * z)
 
 
-def normal_bench_with_oracle(amg, torch, nfields):
+def normal_bench_with_oracle(amg, torch, nfields, oracle=True):
     """normal_bench, with the oracle's cost per iteration measured beside it
     in a single-threaded worker process."""
     import subprocess
     import tempfile
     proc = None
-    if "paper128_b6_q0" in nfields:
+    if oracle and "paper128_b6_q0" in nfields:
         tmp = tempfile.mkdtemp(prefix="amg_bench_normal_")
         pin, pout = os.path.join(tmp, "theta.npz"), os.path.join(tmp, "normal.json")
         np.savez(pin, theta=nfields["paper128_b6_q0"])
@@ -917,12 +917,16 @@ def main():
     ap.add_argument("--only-stencil", action="store_true",
                     help="time the fine stencils alone (for profiling runs) and print their JSON")
     ap.add_argument("--no-normal", action="store_true")
+    ap.add_argument("--normal-names", type=str, default=None,
+                    help="comma-separated subset of the normal-equation ensembles")
     ap.add_argument("--only-normal", action="store_true",
                     help="run the normal-equation (MG-CG vs CG) experiment alone and print its JSON")
     ap.add_argument("--only-4d", action="store_true",
                     help="run the 4d multi-rhs workload alone (for profiling runs) and print its JSON")
     args = ap.parse_args()
-    global BETAS
+    global BETAS, NORMAL_NAMES
+    if args.normal_names:
+        NORMAL_NAMES = args.normal_names.split(",")
     if args.betas:
         BETAS = [float(b) for b in args.betas.split(",")]
     if args.gpus != 1:
@@ -949,7 +953,8 @@ def main():
         import torch
         import paper_0707_4018_amd as amg
         torch.cuda.set_device(0)
-        print(json.dumps({"normal_mgcg": normal_bench_with_oracle(amg, torch, nfields)}))
+        print(json.dumps({"normal_mgcg": normal_bench_with_oracle(amg, torch, nfields,
+                                                                   oracle=not args.no_cpu_baseline)}))
         return
     if args.only_4d:
         U4 = gen_4d_base()
@@ -1067,7 +1072,7 @@ def main():
         del U4
     if nfields:
         log("normal equations: MG-CG vs CG (the paper's experiment)")
-        out["normal_mgcg"] = normal_bench_with_oracle(amg, torch, nfields)
+        out["normal_mgcg"] = normal_bench_with_oracle(amg, torch, nfields, oracle=not args.no_cpu_baseline)
     if lfields:
         log("learned setup")
         out["learned"] = learned_bench(amg, torch, lfields)

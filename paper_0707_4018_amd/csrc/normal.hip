@@ -30,6 +30,8 @@ inline unsigned nblk(long n, long cap = 1L << 16) {
   return (unsigned)(b < cap ? b : cap);
 }
 
+constexpr int NRM_MMAX = 16;  // largest number of vectors per coarsening
+
 __device__ __forceinline__ int wrapc(int x, int L) { return x < 0 ? x + L : (x >= L ? x - L : x); }
 
 // Coarse coordinate of slot a (0: lower, 1: upper candidate) of fine
@@ -159,41 +161,49 @@ __global__ __launch_bounds__(256) void prolong_kernel(double2* __restrict__ out,
   }
 }
 
-// out (coarse, [J][k]) = P^dag in (fine, layout lf); one thread per (J, k)
+// out (coarse, [J][k]) = P^dag in (fine, layout lf).  One wave per coarse
+// site J: the rows (site, component) of J's support (the block, widened by
+// one site for the smoothed P) are spread over the lanes, each lane keeps the
+// M partial sums, and M wave sums finish them.
 __global__ __launch_bounds__(256) void restrict_kernel(double2* __restrict__ out, const double2* __restrict__ in,
                                                        const double2* __restrict__ P, NGeom g) {
   const int rhs = blockIdx.y;
   const int NS = g.sa ? 4 : 1, M = g.M, w = g.sa ? 1 : 0;
   const long Vf = (long)g.f1 * g.f2, Vc = (long)g.c1 * g.c2;
+  const long J = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (J >= Vc) return;  // uniform per wave
   gptr<double2> o = gl(out) + (long)rhs * Vc * M;
   gptr<const double2> f = gl(in) + (long)rhs * Vf * g.dof;
   gptr<const double2> p = gl(P);
-  GRID_STRIDE(i, Vc * M) {
-    const long J = i / M;
-    const int k = (int)(i % M);
-    const int J1 = (int)(J % g.c1), J2 = (int)(J / g.c1);
-    double2 acc = make_double2(0.0, 0.0);
-    for (int u2 = -w; u2 < g.b2 + w; ++u2) {
-      const int x2 = wrapc(J2 * g.b2 + u2, g.f2);
-      int q2 = 0;
-      if (g.sa) {
-        bool v;
-        q2 = slot_coord(x2, g.b2, g.c2, 1, 1, v) == J2 ? 1 : 0;
-      }
-      for (int u1 = -w; u1 < g.b1 + w; ++u1) {
-        const int x1 = wrapc(J1 * g.b1 + u1, g.f1);
-        int q1 = 0;
-        if (g.sa) {
-          bool v;
-          q1 = slot_coord(x1, g.b1, g.c1, 1, 1, v) == J1 ? 1 : 0;
-        }
-        const long s = (long)x2 * g.f1 + x1;
-        const int q = q1 + 2 * q2;
-        for (int d = 0; d < g.dof; ++d)
-          cjfma<double>(acc, p[((s * g.dof + d) * NS + q) * (long)M + k], f[g.lf.off(s, d)]);
-      }
+  const int J1 = (int)(J % g.c1), J2 = (int)(J / g.c1);
+  const int e1 = g.b1 + 2 * w, e2 = g.b2 + 2 * w;
+  const int rows = e1 * e2 * g.dof;
+  double2 acc[NRM_MMAX];
+#pragma unroll
+  for (int k = 0; k < NRM_MMAX; ++k) acc[k] = make_double2(0.0, 0.0);
+  for (int row = lane; row < rows; row += 64) {
+    const int d = row % g.dof;
+    const int u = row / g.dof;
+    const int x1 = wrapc(J1 * g.b1 + u % e1 - w, g.f1), x2 = wrapc(J2 * g.b2 + u / e1 - w, g.f2);
+    int q = 0;
+    if (g.sa) {
+      bool v;
+      q = (slot_coord(x1, g.b1, g.c1, 1, 1, v) == J1 ? 1 : 0) + 2 * (slot_coord(x2, g.b2, g.c2, 1, 1, v) == J2 ? 1 : 0);
     }
-    o[J * M + k] = acc;
+    const long s = (long)x2 * g.f1 + x1;
+    const double2 fv = f[g.lf.off(s, d)];
+    gptr<const double2> pr = p + ((s * g.dof + d) * NS + q) * (long)M;
+#pragma unroll
+    for (int k = 0; k < NRM_MMAX; ++k)
+      if (k < M) cjfma<double>(acc[k], pr[k], fv);
+  }
+#pragma unroll
+  for (int k = 0; k < NRM_MMAX; ++k) {
+    if (k < M) {
+      const double re = wave_sum(acc[k].x), im = wave_sum(acc[k].y);
+      if (lane == 0) o[J * M + k] = make_double2(re, im);
+    }
   }
 }
 
@@ -230,6 +240,51 @@ __global__ __launch_bounds__(256) void box_kernel(double2* __restrict__ out, con
       acc.y = bv.y - acc.y;
     }
     o[i] = acc;
+  }
+}
+
+// The same for M <= 8 with one wave per site: lane l = c M + r (l < M^2)
+// takes column c of row r in all nine directions (each direction's block is
+// one contiguous read of M^2 entries), and the M partial sums of a row are
+// added through LDS.
+__global__ __launch_bounds__(256) void box_wave_kernel(double2* __restrict__ out, const double2* __restrict__ in,
+                                                       const double2* __restrict__ b, const double2* __restrict__ Y,
+                                                       int L1, int L2, int M, int epi) {
+  __shared__ double2 part[4][64];
+  const int rhs = blockIdx.y;
+  const long V = (long)L1 * L2, n = V * M;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const long j = (long)blockIdx.x * 4 + wv;
+  const bool site = j < V;
+  const int c = lane / M, r = lane - c * M;
+  double2 acc = make_double2(0.0, 0.0);
+  if (site && lane < M * M) {
+    gptr<const double2> x = gl(in) + rhs * n;
+    gptr<const double2> y = gl(Y) + j * 9 * (long)M * M + lane;
+    const int j1 = (int)(j % L1), j2 = (int)(j / L1);
+#pragma unroll
+    for (int dir = 0; dir < 9; ++dir) {
+      const int d1 = dir % 3 - 1, d2 = dir / 3 - 1;
+      const long nb = (long)wrapc(j2 + d2, L2) * L1 + wrapc(j1 + d1, L1);
+      cfma<double>(acc, y[(long)dir * M * M], x[nb * M + c]);
+    }
+  }
+  part[wv][lane] = acc;
+  __syncthreads();
+  if (site && lane < M) {
+    double2 sum = make_double2(0.0, 0.0);
+    for (int cc = 0; cc < M; ++cc) {
+      const double2 t = part[wv][cc * M + lane];
+      sum.x += t.x;
+      sum.y += t.y;
+    }
+    const long i = j * M + lane;
+    if (epi == 1) {
+      const double2 bv = gl(b)[rhs * n + i];
+      sum.x = bv.x - sum.x;
+      sum.y = bv.y - sum.y;
+    }
+    gl(out)[rhs * n + i] = sum;
   }
 }
 
@@ -437,12 +492,19 @@ void launch_normal_prolong(double2* out, const double2* in, const double2* P, co
 
 void launch_normal_restrict(double2* out, const double2* in, const double2* P, const NGeom& g, int nrhs,
                             hipStream_t st) {
-  hipLaunchKernelGGL(restrict_kernel, dim3(nblk((long)g.c1 * g.c2 * g.M), (unsigned)nrhs), dim3(256), 0, st, out, in,
-                     P, g);
+  const long Vc = (long)g.c1 * g.c2;
+  hipLaunchKernelGGL(restrict_kernel, dim3((unsigned)((Vc + 3) / 4), (unsigned)nrhs), dim3(256), 0, st, out, in, P,
+                     g);
 }
 
 void launch_box(double2* out, const double2* in, const double2* b, const double2* Y, int L1, int L2, int M, int nrhs,
                 int epi, hipStream_t st) {
+  if (M <= 8) {
+    const long V = (long)L1 * L2;
+    hipLaunchKernelGGL(box_wave_kernel, dim3((unsigned)((V + 3) / 4), (unsigned)nrhs), dim3(256), 0, st, out, in, b,
+                       Y, L1, L2, M, epi);
+    return;
+  }
   hipLaunchKernelGGL(box_kernel, dim3(nblk((long)L1 * L2 * M), (unsigned)nrhs), dim3(256), 0, st, out, in, b, Y, L1,
                      L2, M, epi);
 }
