@@ -22,6 +22,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "amg.h"
@@ -271,6 +272,182 @@ __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(const TS* __restrict
   }
 }
 
+// ---- the same convolutions on the matrix cores (bfloat16 storage mode) -----------
+// Implicit GEMM on v_mfma_f32_16x16x16_bf16 (bf16 operands, FP32 accumulation):
+// Y[o][p] = sum_kk A[o][kk] B[kk][p] with kk = tap * Cin + c, tap-major, so
+// the four K values a lane supplies are four consecutive channels of one tap.
+// Operand layout of the 16x16x16 instruction: lane l gives A[l % 16][4 (l/16) .. +3]
+// and B[4 (l/16) .. +3][l % 16] and receives D[4 (l/16) + r][l % 16], r < 4.
+typedef short mf_v4s __attribute__((ext_vector_type(4)));
+typedef float mf_v4f __attribute__((ext_vector_type(4)));
+constexpr int MT = 8;      // pixel tile MT x MT
+constexpr int MOC = 32;    // output channels per block (two waves of 16)
+constexpr int MCMAX = 64;  // largest channel count
+
+__device__ __forceinline__ uint16_t to_bf(float v) { return f2bf(v); }
+__device__ __forceinline__ float ldf(const float* p, long i) { return p[i]; }
+__device__ __forceinline__ float ldf(const bf16s* p, long i) { return bf2f(p[i].v); }
+
+// Forward (FLIP = false): y[o] = act(bias[o] + sum_{c,tap} W[o][c][tap] x[c][p + d_tap]).
+// Data gradient (FLIP): y[c] = (1 - a^2) sum_{o,tap} W[o][c][8 - tap] dy[o][p + d_tap]
+// ("Cin" = forward Cout).  Block: an 8 x 8 pixel tile and 32 output channels;
+// wave w takes channels 16 (w & 1) .. +15 and pixel rows 4 (w >> 1) .. +3 (two
+// 16-pixel MFMA columns).  The input tile with its one-site halo and the
+// block's weights sit in LDS channel-fastest, so each operand is one 8-byte
+// read.  Cin a multiple of 4 (<= 64), Cout of 16, H and W of 8.
+template <typename TI, typename TO, bool FLIP, bool ACT>
+__global__ __launch_bounds__(256) void conv3x3_mfma_kernel(const TI* __restrict__ x, const bf16s* __restrict__ Wt,
+                                                           const float* __restrict__ bias, TO* __restrict__ y,
+                                                           const bf16s* __restrict__ actv, int Cin, int Cout, int H,
+                                                           int W) {
+  __shared__ __align__(16) uint16_t xs[(MT + 2) * (MT + 2) * MCMAX];
+  __shared__ __align__(16) uint16_t ws[MOC * 9 * MCMAX];
+  const int b = blockIdx.z;
+  const int ntx = W / MT;
+  const int tx0 = (blockIdx.x % ntx) * MT, ty0 = (blockIdx.x / ntx) * MT;
+  const int o0 = blockIdx.y * MOC;
+  const int t = threadIdx.x;
+  const long HW = (long)H * W;
+  for (int idx = t; idx < Cin * (MT + 2) * (MT + 2); idx += 256) {
+    const int c = idx / ((MT + 2) * (MT + 2)), pos = idx - c * (MT + 2) * (MT + 2);
+    const int yy = pos / (MT + 2), xx = pos - yy * (MT + 2);
+    const int gy = (ty0 + yy - 1 + H) % H, gx = (tx0 + xx - 1 + W) % W;
+    xs[pos * Cin + c] = to_bf(ldf(x, ((long)b * Cin + c) * HW + (long)gy * W + gx));
+  }
+  for (int idx = t; idx < MOC * Cin * 9; idx += 256) {
+    const int ol = idx / (Cin * 9), r = idx - ol * Cin * 9;
+    const int c = r / 9, k = r - c * 9;
+    uint16_t v = 0;
+    if (o0 + ol < Cout)
+      v = FLIP ? Wt[((long)c * Cout + o0 + ol) * 9 + (8 - k)].v : Wt[((long)(o0 + ol) * Cin + c) * 9 + k].v;
+    ws[(ol * 9 + k) * Cin + c] = v;
+  }
+  __syncthreads();
+  const int wv = t >> 6, lane = t & 63;
+  const int og = wv & 1, ph = wv >> 1;
+  const int lr = lane & 15, lg = lane >> 4;
+  mf_v4f acc[2];
+  acc[0] = mf_v4f{0.f, 0.f, 0.f, 0.f};
+  acc[1] = acc[0];
+  for (int tap = 0; tap < 9; ++tap) {
+    const int ty = tap / 3, tx = tap - ty * 3;
+    for (int c0 = 0; c0 < Cin; c0 += 16) {
+      const int c = c0 + 4 * lg;
+      mf_v4s a = mf_v4s{0, 0, 0, 0}, bb[2] = {mf_v4s{0, 0, 0, 0}, mf_v4s{0, 0, 0, 0}};
+      if (c < Cin) {
+        a = *reinterpret_cast<const mf_v4s*>(&ws[((og * 16 + lr) * 9 + tap) * Cin + c]);
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) {
+          const int pp = ph * 32 + nt * 16 + lr;
+          const int py = pp / MT, px = pp - py * MT;
+          bb[nt] = *reinterpret_cast<const mf_v4s*>(&xs[((py + ty) * (MT + 2) + px + tx) * Cin + c]);
+        }
+      }
+      acc[0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb[0], acc[0], 0, 0, 0);
+      acc[1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb[1], acc[1], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int nt = 0; nt < 2; ++nt) {
+    const int pp = ph * 32 + nt * 16 + lr;
+    const int py = pp / MT, px = pp - py * MT;
+    const long pix = (long)(ty0 + py) * W + tx0 + px;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int o = o0 + og * 16 + 4 * lg + r;
+      if (o >= Cout) continue;
+      float v = acc[nt][r];
+      const long i = ((long)b * Cout + o) * HW + pix;
+      if (!FLIP && bias) v += bias[o];
+      if (ACT) {
+        if (FLIP) {
+          const float av = bf2f(actv[i].v);
+          v *= 1.f - av * av;
+        } else {
+          v = tanhf(v);
+        }
+      }
+      st(y, i, v);
+    }
+  }
+}
+
+// dW[o][c][tap] += sum_{b,p} dy[b][o][p] x[b][c][p + d_tap], db[o] += sum dy[b][o][p]:
+// M = o, N = c, K = pixels.  One wave per (16 output, 16 input channels) for
+// all nine taps, over a run of 8 x 8 pixel tiles; dy (FP32, rounded to bf16)
+// and x staged in LDS pixel-fastest; partial sums added to the FP32 gradient
+// with atomics.
+constexpr int MWG_TILES = 16;
+template <typename TS>
+__global__ __launch_bounds__(64) void conv3x3_wgrad_mfma_kernel(const TS* __restrict__ x, const float* __restrict__ dy,
+                                                                float* __restrict__ dW, float* __restrict__ db,
+                                                                int Cin, int Cout, int H, int W, int B) {
+  __shared__ __align__(16) uint16_t ds[16][MT * MT];
+  __shared__ uint16_t xs2[16][(MT + 2) * (MT + 2)];
+  const int ncg = (Cin + 15) / 16;
+  const int o0 = (blockIdx.y / ncg) * 16, c0 = (blockIdx.y % ncg) * 16;
+  const int lane = threadIdx.x, lr = lane & 15, lg = lane >> 4;
+  const long HW = (long)H * W;
+  const int ntx = W / MT, nty = H / MT;
+  const long ntiles = (long)B * ntx * nty;
+  mf_v4f acc[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) acc[k] = mf_v4f{0.f, 0.f, 0.f, 0.f};
+  float bacc = 0.f;
+  const long t_end = min(ntiles, (long)(blockIdx.x + 1) * MWG_TILES);
+  for (long tile = (long)blockIdx.x * MWG_TILES; tile < t_end; ++tile) {
+    const int b = (int)(tile / (ntx * nty));
+    const int tt = (int)(tile - (long)b * ntx * nty);
+    const int tx0 = (tt % ntx) * MT, ty0 = (tt / ntx) * MT;
+    __syncthreads();
+    for (int idx = lane; idx < 16 * MT * MT; idx += 64) {
+      const int ol = idx / (MT * MT), pp = idx - ol * MT * MT;
+      float v = 0.f;
+      if (o0 + ol < Cout) v = dy[((long)b * Cout + o0 + ol) * HW + (long)(ty0 + pp / MT) * W + tx0 + pp % MT];
+      ds[ol][pp] = to_bf(v);
+    }
+    for (int idx = lane; idx < 16 * (MT + 2) * (MT + 2); idx += 64) {
+      const int cl = idx / ((MT + 2) * (MT + 2)), pos = idx - cl * (MT + 2) * (MT + 2);
+      const int yy = pos / (MT + 2), xx = pos - yy * (MT + 2);
+      float v = 0.f;
+      if (c0 + cl < Cin) {
+        const int gy = (ty0 + yy - 1 + H) % H, gx = (tx0 + xx - 1 + W) % W;
+        v = ldf(x, ((long)b * Cin + c0 + cl) * HW + (long)gy * W + gx);
+      }
+      xs2[cl][pos] = to_bf(v);
+    }
+    __syncthreads();
+    if (c0 == 0 && lane < 16 && o0 + lane < Cout) {
+      // bias gradient from the FP32 values (not the rounded tile)
+      float s = 0.f;
+      for (int pp = 0; pp < MT * MT; ++pp)
+        s += dy[((long)b * Cout + o0 + lane) * HW + (long)(ty0 + pp / MT) * W + tx0 + pp % MT];
+      bacc += s;
+    }
+#pragma unroll
+    for (int ks = 0; ks < MT * MT / 16; ++ks) {
+      const int p0 = ks * 16 + 4 * lg;  // this lane's 4 pixels (one tile row: MT is a multiple of 4)
+      const mf_v4s a = *reinterpret_cast<const mf_v4s*>(&ds[lr][p0]);
+      const int py = p0 / MT, px = p0 - py * MT;
+#pragma unroll
+      for (int tap = 0; tap < 9; ++tap) {
+        const int ty = tap / 3, tx = tap - ty * 3;
+        const uint16_t* xr = &xs2[lr][(py + ty) * (MT + 2) + px + tx];
+        const mf_v4s bv = mf_v4s{(short)xr[0], (short)xr[1], (short)xr[2], (short)xr[3]};
+        acc[tap] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bv, acc[tap], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int o = o0 + 4 * lg + r, c = c0 + lr;
+      if (o < Cout && c < Cin) atomicAdd(&dW[((long)o * Cin + c) * 9 + tap], acc[tap][r]);
+    }
+  if (c0 == 0 && lane < 16 && o0 + lane < Cout) atomicAdd(&db[o0 + lane], bacc);
+}
+
 // ---- projection loss -------------------------------------------------------------
 // one 64-lane workgroup per (block j, chirality s, configuration b); FP64.
 // V[i][a]: prediction a at block site i, T[i][k]: normalised target k,
@@ -481,6 +658,18 @@ void forward(Cnn& N, const double2* U, int B, int H, int W, hipStream_t st) {
   hipLaunchKernelGGL((features_kernel<TS>), dim3(nb((long)B * H * W)), dim3(256), 0, st, U, N.phi.as<double>(),
                      N.act[0].as<TS>(), H, W, B);
   for (int l = 0; l < NL; ++l) {
+    if constexpr (std::is_same<TS, bf16s>::value) {  // bf16 storage: implicit GEMM on the matrix cores
+      dim3 gm((W / MT) * (H / MT), (CH[l + 1] + MOC - 1) / MOC, B);
+      if (l < NL - 1)
+        hipLaunchKernelGGL((conv3x3_mfma_kernel<bf16s, bf16s, false, true>), gm, dim3(256), 0, st,
+                           N.act[l].as<bf16s>(), N.Ws[l].as<bf16s>(), N.B32[l].as<float>(), N.act[l + 1].as<bf16s>(),
+                           nullptr, CH[l], CH[l + 1], H, W);
+      else
+        hipLaunchKernelGGL((conv3x3_mfma_kernel<bf16s, bf16s, false, false>), gm, dim3(256), 0, st,
+                           N.act[l].as<bf16s>(), N.Ws[l].as<bf16s>(), N.B32[l].as<float>(), N.act[l + 1].as<bf16s>(),
+                           nullptr, CH[l], CH[l + 1], H, W);
+      continue;
+    }
     dim3 grid((W / TILE) * (H / TILE), (CH[l + 1] + OC - 1) / OC, B);
     if (l < NL - 1)
       hipLaunchKernelGGL((conv3x3_kernel<TS, TS, TS, false, true>), grid, dim3(256), 0, st, N.act[l].as<TS>(),
@@ -511,6 +700,20 @@ double loss_and_grads(Cnn& N, const double2* U, const double2* vecs, int B, int 
     for (int l = NL - 1; l >= 0; --l) {
       HIPC(hipMemsetAsync(N.gW[l].p, 0, sizeof(float) * N.nW[l], st));
       HIPC(hipMemsetAsync(N.gB[l].p, 0, sizeof(float) * N.nB[l], st));
+      if constexpr (std::is_same<TS, bf16s>::value) {
+        const long mt = (long)B * (H / MT) * (W / MT);
+        dim3 gmw((unsigned)((mt + MWG_TILES - 1) / MWG_TILES), (unsigned)(((CH[l + 1] + 15) / 16) * ((CH[l] + 15) / 16)));
+        hipLaunchKernelGGL((conv3x3_wgrad_mfma_kernel<bf16s>), gmw, dim3(64), 0, st, N.act[l].as<bf16s>(),
+                           N.grad[l + 1].as<float>(), N.gW[l].as<float>(), N.gB[l].as<float>(), CH[l], CH[l + 1], H, W,
+                           B);
+        if (l > 0) {
+          dim3 gm((W / MT) * (H / MT), (CH[l] + MOC - 1) / MOC, B);
+          hipLaunchKernelGGL((conv3x3_mfma_kernel<float, float, true, true>), gm, dim3(256), 0, st,
+                             N.grad[l + 1].as<float>(), N.Ws[l].as<bf16s>(), (const float*)nullptr,
+                             N.grad[l].as<float>(), N.act[l].as<bf16s>(), CH[l + 1], CH[l], H, W);
+        }
+        continue;
+      }
       const long ntiles = (long)B * (H / TILE) * (W / TILE);
       dim3 gw((unsigned)((ntiles + WG_TILES - 1) / WG_TILES), (CH[l + 1] + OC - 1) / OC, (CH[l] + CC - 1) / CC);
       hipLaunchKernelGGL((conv3x3_wgrad_kernel<TS>), gw, dim3(256), 0, st, N.act[l].as<TS>(), N.grad[l + 1].as<float>(),
