@@ -268,9 +268,13 @@ typedef struct amg_batch amg_batch;
 
 /* Group n solvers (two-dimensional, same hierarchy depth, dof per level and
  * solver parameters); instance i solves nrhs[i] right-hand sides.  With
- * autotune != 0 the grid size of the reducing kernels is chosen by timing
- * one batched outer step per candidate.  The solvers must outlive the batch
- * and must not be used concurrently with it. */
+ * autotune != 0 the launch shapes are chosen jointly by timing one batched
+ * outer step per candidate: the grid of the reducing kernels (128, 256, 512,
+ * 1024 blocks) x the coarse stencil (the multi-rhs MFMA kernel for every
+ * instance, or one right-hand side per grid row); amg_batch_tuning reports
+ * every candidate.  Without autotune: 1024 blocks and the MFMA kernel (or the
+ * per-rhs stencil when the environment sets AMG_BATCH_MRHS=0).  The solvers
+ * must outlive the batch and must not be used concurrently with it. */
 amg_status amg_batch_create(amg_solver* const* solvers, const int* nrhs, int n, int autotune, void* stream,
                             amg_batch** out);
 /* Solve all instances to |chi - D psi| <= tol |chi| (true FP64 residual per
@@ -282,6 +286,13 @@ amg_status amg_batch_solve(amg_batch* b, const void* const* dev_chi, void* const
                            int max_iter, amg_solve_info* info, void* stream);
 /* The autotuned reduction grid cap and the number of batched launches per outer step. */
 amg_status amg_batch_info(const amg_batch* b, int* red_cap, int* stages_per_iteration);
+/* The same, with the coarse-stencil choice (1: multi-rhs MFMA kernel, 0: per-rhs stencil). */
+amg_status amg_batch_info2(const amg_batch* b, int* red_cap, int* mrhs, int* stages_per_iteration);
+/* The autotuner's candidates in the order timed: reduction grid cap, coarse
+ * stencil choice and ms per batched outer iteration, at most max entries
+ * written; returns the number of candidates (0 without autotune, -1 for a
+ * NULL batch). */
+int amg_batch_tuning(const amg_batch* b, int max, int* red_cap, int* mrhs, float* ms_per_iteration);
 amg_status amg_batch_destroy(amg_batch* b);
 
 /* ---- kernel timing (HIP events) -------------------------------------------

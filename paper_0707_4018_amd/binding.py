@@ -103,6 +103,8 @@ _SIGS = {
     "amg_batch_solve": (C.c_int, [_P, C.POINTER(_P), C.POINTER(_P), C.c_double, C.c_int, C.POINTER(_Info), _P]),
     "amg_batch_info": (C.c_int, [_P, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "amg_batch_destroy": (C.c_int, [_P]),
+    "amg_batch_info2": (C.c_int, [_P, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "amg_batch_tuning": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_float)]),
     "amg_profile_read": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_longlong)]),
     "amg_profile_read_kind": (C.c_int, [_P, C.c_int, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_longlong)]),
     "amg_setup_adaptive_levels": (C.c_int, [_P, C.POINTER(_Params), C.POINTER(_P), C.POINTER(C.c_int),
@@ -547,9 +549,18 @@ class Batch:
         self._h = h
 
     def info(self):
-        cap, stages = C.c_int(), C.c_int()
-        _check(load_library().amg_batch_info(self._h, C.byref(cap), C.byref(stages)), "amg_batch_info")
-        return {"red_block_cap": cap.value, "launches_per_outer_step": stages.value}
+        """The launch shapes in use (autotuned or default) and, after an
+        autotune, every candidate the tuner timed."""
+        lib = load_library()
+        cap, mrhs, stages = C.c_int(), C.c_int(), C.c_int()
+        _check(lib.amg_batch_info2(self._h, C.byref(cap), C.byref(mrhs), C.byref(stages)), "amg_batch_info2")
+        n = lib.amg_batch_tuning(self._h, 0, None, None, None)
+        caps, mr, ms = (C.c_int * max(n, 1))(), (C.c_int * max(n, 1))(), (C.c_float * max(n, 1))()
+        lib.amg_batch_tuning(self._h, n, caps, mr, ms)
+        return {"red_block_cap": cap.value, "coarse_mrhs_mfma": bool(mrhs.value),
+                "launches_per_outer_step": stages.value,
+                "tuning": [{"red_block_cap": caps[i], "coarse_mrhs_mfma": bool(mr[i]), "ms_per_outer_step": round(ms[i], 4)}
+                           for i in range(n)]}
 
     def solve(self, chis, tol: float = 1e-10, max_iter: int = 1000, raise_noconv: bool = True):
         """chis[i]: (nrhs[i], V_i, 2, 1) complex128 on the GPU; returns (psis, infos per rhs)."""

@@ -280,7 +280,7 @@ __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(const TS* __restrict
 // and B[4 (l/16) .. +3][l % 16] and receives D[4 (l/16) + r][l % 16], r < 4.
 typedef short mf_v4s __attribute__((ext_vector_type(4)));
 typedef float mf_v4f __attribute__((ext_vector_type(4)));
-constexpr int MT = 8;      // pixel tile MT x MT
+constexpr int MT = 16;     // pixel tile MT x MT
 constexpr int MOC = 32;    // output channels per block (two waves of 16)
 constexpr int MCMAX = 64;  // largest channel count
 
@@ -290,66 +290,104 @@ __device__ __forceinline__ float ldf(const bf16s* p, long i) { return bf2f(p[i].
 
 // Forward (FLIP = false): y[o] = act(bias[o] + sum_{c,tap} W[o][c][tap] x[c][p + d_tap]).
 // Data gradient (FLIP): y[c] = (1 - a^2) sum_{o,tap} W[o][c][8 - tap] dy[o][p + d_tap]
-// ("Cin" = forward Cout).  Block: an 8 x 8 pixel tile and 32 output channels;
-// wave w takes channels 16 (w & 1) .. +15 and pixel rows 4 (w >> 1) .. +3 (two
-// 16-pixel MFMA columns).  The input tile with its one-site halo and the
-// block's weights sit in LDS channel-fastest, so each operand is one 8-byte
-// read.  Cin a multiple of 4 (<= 64), Cout of 16, H and W of 8.
+// ("Cin" = forward Cout).  Block: a 16 x 16 pixel tile and 32 output
+// channels; wave w takes channels 16 (w & 1) .. +15 and pixel rows
+// 8 (w >> 1) .. +7 (eight 16-pixel MFMA columns, one per row).  The input tile
+// with its one-site halo and the block's weights sit in LDS channel-fastest,
+// so each operand is one 8-byte read.  Cin a multiple of 4 (<= 64), Cout of
+// 16, H and W of 16.
 template <typename TI, typename TO, bool FLIP, bool ACT>
 __global__ __launch_bounds__(256) void conv3x3_mfma_kernel(const TI* __restrict__ x, const bf16s* __restrict__ Wt,
                                                            const float* __restrict__ bias, TO* __restrict__ y,
                                                            const bf16s* __restrict__ actv, int Cin, int Cout, int H,
                                                            int W) {
-  __shared__ __align__(16) uint16_t xs[(MT + 2) * (MT + 2) * MCMAX];
-  __shared__ __align__(16) uint16_t ws[MOC * 9 * MCMAX];
+  // input channels staged 16 at a time (24.5 KB of LDS, six blocks per CU);
+  // channel stride MCK + 4: the 16 rows of an operand read fall in distinct
+  // LDS banks and every 4-channel group stays 8-byte aligned
+  constexpr int MCK = 16, CS = MCK + 4, SU = 8;
+  __shared__ __align__(16) uint16_t xs[(MT + 2) * (MT + 2) * CS];
+  __shared__ __align__(16) uint16_t ws[MOC * 9 * CS];
   const int b = blockIdx.z;
   const int ntx = W / MT;
   const int tx0 = (blockIdx.x % ntx) * MT, ty0 = (blockIdx.x / ntx) * MT;
   const int o0 = blockIdx.y * MOC;
   const int t = threadIdx.x;
   const long HW = (long)H * W;
-  for (int idx = t; idx < Cin * (MT + 2) * (MT + 2); idx += 256) {
-    const int c = idx / ((MT + 2) * (MT + 2)), pos = idx - c * (MT + 2) * (MT + 2);
-    const int yy = pos / (MT + 2), xx = pos - yy * (MT + 2);
-    const int gy = (ty0 + yy - 1 + H) % H, gx = (tx0 + xx - 1 + W) % W;
-    xs[pos * Cin + c] = to_bf(ldf(x, ((long)b * Cin + c) * HW + (long)gy * W + gx));
-  }
-  for (int idx = t; idx < MOC * Cin * 9; idx += 256) {
-    const int ol = idx / (Cin * 9), r = idx - ol * Cin * 9;
-    const int c = r / 9, k = r - c * 9;
-    uint16_t v = 0;
-    if (o0 + ol < Cout)
-      v = FLIP ? Wt[((long)c * Cout + o0 + ol) * 9 + (8 - k)].v : Wt[((long)(o0 + ol) * Cin + c) * 9 + k].v;
-    ws[(ol * 9 + k) * Cin + c] = v;
-  }
-  __syncthreads();
   const int wv = t >> 6, lane = t & 63;
   const int og = wv & 1, ph = wv >> 1;
   const int lr = lane & 15, lg = lane >> 4;
-  mf_v4f acc[2];
-  acc[0] = mf_v4f{0.f, 0.f, 0.f, 0.f};
-  acc[1] = acc[0];
-  for (int tap = 0; tap < 9; ++tap) {
-    const int ty = tap / 3, tx = tap - ty * 3;
-    for (int c0 = 0; c0 < Cin; c0 += 16) {
-      const int c = c0 + 4 * lg;
-      mf_v4s a = mf_v4s{0, 0, 0, 0}, bb[2] = {mf_v4s{0, 0, 0, 0}, mf_v4s{0, 0, 0, 0}};
-      if (c < Cin) {
-        a = *reinterpret_cast<const mf_v4s*>(&ws[((og * 16 + lr) * 9 + tap) * Cin + c]);
+  constexpr int NT = MT * MT / 2 / 16;  // MFMA columns per wave
+  mf_v4f acc[NT];
 #pragma unroll
-        for (int nt = 0; nt < 2; ++nt) {
-          const int pp = ph * 32 + nt * 16 + lr;
-          const int py = pp / MT, px = pp - py * MT;
-          bb[nt] = *reinterpret_cast<const mf_v4s*>(&xs[((py + ty) * (MT + 2) + px + tx) * Cin + c]);
+  for (int nt = 0; nt < NT; ++nt) acc[nt] = mf_v4f{0.f, 0.f, 0.f, 0.f};
+  for (int cb = 0; cb < Cin; cb += MCK) {
+    const int cc = min(MCK, Cin - cb);
+    __syncthreads();
+    // stage (SU loads in flight per thread before their LDS stores)
+    const int nx = cc * (MT + 2) * (MT + 2);
+    for (int i0 = t; i0 < nx; i0 += 256 * SU) {
+      float v[SU];
+      int dst[SU];
+#pragma unroll
+      for (int u = 0; u < SU; ++u) {
+        const int idx = i0 + u * 256;
+        dst[u] = -1;
+        v[u] = 0.f;
+        if (idx < nx) {
+          const int c = idx / ((MT + 2) * (MT + 2)), pos = idx - c * (MT + 2) * (MT + 2);
+          const int yy = pos / (MT + 2), xx = pos - yy * (MT + 2);
+          int gy = ty0 + yy - 1, gx = tx0 + xx - 1;
+          gy = gy < 0 ? gy + H : (gy >= H ? gy - H : gy);
+          gx = gx < 0 ? gx + W : (gx >= W ? gx - W : gx);
+          v[u] = ldf(x, ((long)b * Cin + cb + c) * HW + (long)gy * W + gx);
+          dst[u] = pos * CS + c;
         }
       }
-      acc[0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb[0], acc[0], 0, 0, 0);
-      acc[1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb[1], acc[1], 0, 0, 0);
+#pragma unroll
+      for (int u = 0; u < SU; ++u)
+        if (dst[u] >= 0) xs[dst[u]] = to_bf(v[u]);
+    }
+    const int nw = MOC * cc * 9;
+    for (int i0 = t; i0 < nw; i0 += 256 * SU) {
+      uint16_t v[SU];
+      int dst[SU];
+#pragma unroll
+      for (int u = 0; u < SU; ++u) {
+        const int idx = i0 + u * 256;
+        dst[u] = -1;
+        v[u] = 0;
+        if (idx < nw) {
+          const int ol = idx / (cc * 9), r = idx - ol * cc * 9;
+          const int c = r / 9, k = r - c * 9;
+          if (o0 + ol < Cout)
+            v[u] = FLIP ? Wt[((long)(cb + c) * Cout + o0 + ol) * 9 + (8 - k)].v
+                        : Wt[((long)(o0 + ol) * Cin + cb + c) * 9 + k].v;
+          dst[u] = (ol * 9 + k) * CS + c;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < SU; ++u)
+        if (dst[u] >= 0) ws[dst[u]] = v[u];
+    }
+    __syncthreads();
+    const int c = 4 * lg;
+    const bool on = c < cc;  // lanes past the chunk (Cin = 4) supply zeros; the MFMA runs in every lane
+    const mf_v4s z = mf_v4s{0, 0, 0, 0};
+    for (int tap = 0; tap < 9; ++tap) {
+      const int ty = tap / 3, tx = tap - ty * 3;
+      const mf_v4s a = on ? *reinterpret_cast<const mf_v4s*>(&ws[((og * 16 + lr) * 9 + tap) * CS + c]) : z;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const int pp = ph * (NT * 16) + nt * 16 + lr;
+        const int py = pp / MT, px = pp - py * MT;
+        const mf_v4s bv = on ? *reinterpret_cast<const mf_v4s*>(&xs[((py + ty) * (MT + 2) + px + tx) * CS + c]) : z;
+        acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bv, acc[nt], 0, 0, 0);
+      }
     }
   }
 #pragma unroll
-  for (int nt = 0; nt < 2; ++nt) {
-    const int pp = ph * 32 + nt * 16 + lr;
+  for (int nt = 0; nt < NT; ++nt) {
+    const int pp = ph * (NT * 16) + nt * 16 + lr;
     const int py = pp / MT, px = pp - py * MT;
     const long pix = (long)(ty0 + py) * W + tx0 + px;
 #pragma unroll
@@ -374,16 +412,16 @@ __global__ __launch_bounds__(256) void conv3x3_mfma_kernel(const TI* __restrict_
 
 // dW[o][c][tap] += sum_{b,p} dy[b][o][p] x[b][c][p + d_tap], db[o] += sum dy[b][o][p]:
 // M = o, N = c, K = pixels.  One wave per (16 output, 16 input channels) for
-// all nine taps, over a run of 8 x 8 pixel tiles; dy (FP32, rounded to bf16)
+// all nine taps, over a run of 16 x 16 pixel tiles; dy (FP32, rounded to bf16)
 // and x staged in LDS pixel-fastest; partial sums added to the FP32 gradient
 // with atomics.
-constexpr int MWG_TILES = 16;
+constexpr int MWG_TILES = 4;
 template <typename TS>
 __global__ __launch_bounds__(64) void conv3x3_wgrad_mfma_kernel(const TS* __restrict__ x, const float* __restrict__ dy,
                                                                 float* __restrict__ dW, float* __restrict__ db,
                                                                 int Cin, int Cout, int H, int W, int B) {
-  __shared__ __align__(16) uint16_t ds[16][MT * MT];
-  __shared__ uint16_t xs2[16][(MT + 2) * (MT + 2)];
+  __shared__ __align__(16) uint16_t ds[16][MT * MT + 4];  // padded rows: the 16 lanes of a read hit distinct banks
+  __shared__ uint16_t xs2[16][(MT + 2) * (MT + 2) + 2];
   const int ncg = (Cin + 15) / 16;
   const int o0 = (blockIdx.y / ncg) * 16, c0 = (blockIdx.y % ncg) * 16;
   const int lane = threadIdx.x, lr = lane & 15, lg = lane >> 4;
@@ -400,29 +438,60 @@ __global__ __launch_bounds__(64) void conv3x3_wgrad_mfma_kernel(const TS* __rest
     const int tt = (int)(tile - (long)b * ntx * nty);
     const int tx0 = (tt % ntx) * MT, ty0 = (tt / ntx) * MT;
     __syncthreads();
-    for (int idx = lane; idx < 16 * MT * MT; idx += 64) {
-      const int ol = idx / (MT * MT), pp = idx - ol * MT * MT;
-      float v = 0.f;
-      if (o0 + ol < Cout) v = dy[((long)b * Cout + o0 + ol) * HW + (long)(ty0 + pp / MT) * W + tx0 + pp % MT];
-      ds[ol][pp] = to_bf(v);
-    }
-    for (int idx = lane; idx < 16 * (MT + 2) * (MT + 2); idx += 64) {
-      const int cl = idx / ((MT + 2) * (MT + 2)), pos = idx - cl * (MT + 2) * (MT + 2);
-      const int yy = pos / (MT + 2), xx = pos - yy * (MT + 2);
-      float v = 0.f;
-      if (c0 + cl < Cin) {
-        const int gy = (ty0 + yy - 1 + H) % H, gx = (tx0 + xx - 1 + W) % W;
-        v = ldf(x, ((long)b * Cin + c0 + cl) * HW + (long)gy * W + gx);
+    // staging with SU loads in flight per lane
+    constexpr int SU = 8;
+    for (int j0 = 0; j0 < 16 * MT * MT / 64; j0 += SU) {
+      float v[SU];
+#pragma unroll
+      for (int u = 0; u < SU; ++u) {
+        const int idx = lane + 64 * (j0 + u);
+        const int ol = idx / (MT * MT), pp = idx - ol * MT * MT;
+        v[u] = (o0 + ol < Cout) ? dy[((long)b * Cout + o0 + ol) * HW + (long)(ty0 + pp / MT) * W + tx0 + pp % MT] : 0.f;
       }
-      xs2[cl][pos] = to_bf(v);
+#pragma unroll
+      for (int u = 0; u < SU; ++u) {
+        const int idx = lane + 64 * (j0 + u);
+        const int ol = idx / (MT * MT), pp = idx - ol * MT * MT;
+        ds[ol][pp] = to_bf(v[u]);
+      }
+    }
+    const int nx2 = 16 * (MT + 2) * (MT + 2);
+    for (int i0 = lane; i0 < nx2; i0 += 64 * SU) {
+      float v[SU];
+#pragma unroll
+      for (int u = 0; u < SU; ++u) {
+        const int idx = i0 + 64 * u;
+        v[u] = 0.f;
+        if (idx < nx2) {
+          const int cl = idx / ((MT + 2) * (MT + 2)), pos = idx - cl * (MT + 2) * (MT + 2);
+          const int yy = pos / (MT + 2), xx = pos - yy * (MT + 2);
+          if (c0 + cl < Cin) {
+            int gy = ty0 + yy - 1, gx = tx0 + xx - 1;
+            gy = gy < 0 ? gy + H : (gy >= H ? gy - H : gy);
+            gx = gx < 0 ? gx + W : (gx >= W ? gx - W : gx);
+            v[u] = ldf(x, ((long)b * Cin + c0 + cl) * HW + (long)gy * W + gx);
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < SU; ++u) {
+        const int idx = i0 + 64 * u;
+        if (idx < nx2) {
+          const int cl = idx / ((MT + 2) * (MT + 2)), pos = idx - cl * (MT + 2) * (MT + 2);
+          xs2[cl][pos] = to_bf(v[u]);
+        }
+      }
     }
     __syncthreads();
-    if (c0 == 0 && lane < 16 && o0 + lane < Cout) {
-      // bias gradient from the FP32 values (not the rounded tile)
-      float s = 0.f;
-      for (int pp = 0; pp < MT * MT; ++pp)
-        s += dy[((long)b * Cout + o0 + lane) * HW + (long)(ty0 + pp / MT) * W + tx0 + pp % MT];
-      bacc += s;
+    if (c0 == 0) {
+      // bias gradient from the staged tile: lane (o = lane / 4, quarter lane % 4)
+      // sums 64 pixels, then the four quarters are added
+      const int ob = lane >> 2, q = lane & 3;
+      float sb = 0.f;
+      for (int pp = q * (MT * MT / 4); pp < (q + 1) * (MT * MT / 4); ++pp) sb += bf2f(ds[ob][pp]);
+      sb += __shfl_xor(sb, 1);
+      sb += __shfl_xor(sb, 2);
+      if (q == 0) bacc += sb;  // lane 4 ob holds output channel ob's sum
     }
 #pragma unroll
     for (int ks = 0; ks < MT * MT / 16; ++ks) {
@@ -445,7 +514,7 @@ __global__ __launch_bounds__(64) void conv3x3_wgrad_mfma_kernel(const TS* __rest
       const int o = o0 + 4 * lg + r, c = c0 + lr;
       if (o < Cout && c < Cin) atomicAdd(&dW[((long)o * Cin + c) * 9 + tap], acc[tap][r]);
     }
-  if (c0 == 0 && lane < 16 && o0 + lane < Cout) atomicAdd(&db[o0 + lane], bacc);
+  if (c0 == 0 && (lane & 3) == 0 && o0 + (lane >> 2) < Cout) atomicAdd(&db[o0 + (lane >> 2)], bacc);
 }
 
 // ---- projection loss -------------------------------------------------------------

@@ -961,6 +961,12 @@ struct amg_batch {
   std::vector<Solver*> S;
   std::vector<int> nrhs;
   int n = 0, m = 0, red_cap = RED_MAX_BLOCKS;
+  int mrhs = 1;  // coarse levels on the multi-rhs MFMA kernel (1) or the per-rhs stencil (0)
+  struct Trial {
+    int red_cap, mrhs;
+    float ms;  // one batched outer iteration
+  };
+  std::vector<Trial> trials;  // the autotuner's candidates
   hipStream_t st = nullptr;
   Buf args_dev, flags_dev, gath_dev;
   double* gath_host = nullptr;
@@ -2043,21 +2049,23 @@ amg_status amg_batch_create(amg_solver* const* solvers, const int* nrhs, int n, 
     HIPC(hipHostMalloc((void**)&B->flags_host, sizeof(int) * n * RHS_MAX, hipHostMallocDefault));
     for (int i = 0; i < n; ++i) B->S[i]->outer_flags = B->flags_dev.as<int>() + (long)i * RHS_MAX;
     // one kernel choice for every instance at a stage: the multi-rhs coarse
-    // kernel for all of them (any nrhs) unless disabled
-    int batch_mrhs = 1;
-    if (const char* e = std::getenv("AMG_BATCH_MRHS")) batch_mrhs = std::atoi(e) != 0 ? 1 : (1 << 30);
+    // kernel for all of them (any nrhs) or for none
     std::vector<int> saved_mrhs(n);
     for (int i = 0; i < n; ++i) {
       saved_mrhs[i] = B->S[i]->mrhs_min;
-      B->S[i]->mrhs_min = batch_mrhs;
       // the coarsest level by GCR on every instance: an exact (dense) solve on
       // some instances and GCR on others would not merge stage by stage
       B->S[i]->no_dense = true;
     }
+    auto set_mrhs = [&](int on) {
+      for (int i = 0; i < n; ++i) B->S[i]->mrhs_min = on ? 1 : (1 << 30);
+    };
     const int saved = red_block_cap();
     if (autotune) {
-      // autotune the grid of the reducing kernels: time one outer iteration
-      // (the first direction) for every candidate on a unit source
+      // autotune the launch shapes jointly: the grid of the reducing kernels
+      // x the coarse stencil (multi-rhs MFMA kernel or one rhs per grid row);
+      // each candidate is built and one outer iteration (the first direction)
+      // timed on a unit source, three replays after one warm-up
       for (int i = 0; i < n; ++i) {
         Solver& S = *B->S[i];
         const long cnt = S.lv[0].per_rhs() * B->nrhs[i];
@@ -2065,31 +2073,39 @@ amg_status amg_batch_create(amg_solver* const* solvers, const int* nrhs, int n, 
         HIPC(hipMemcpy(S.ob.p, ones.data(), sizeof(double2) * cnt, hipMemcpyHostToDevice));
       }
       float best = 1e30f;
-      int best_cap = RED_MAX_BLOCKS;
       hipEvent_t e0, e1;
       HIPC(hipEventCreate(&e0));
       HIPC(hipEventCreate(&e1));
-      for (int cap : {128, 256, 512, 1024}) {
-        set_red_block_cap(cap);
-        batch_build(*B);
-        batch_replay(*B, B->init);
-        batch_replay(*B, B->iters[0]);
-        HIPC(hipEventRecord(e0, B->st));
-        for (int rep = 0; rep < 3; ++rep) batch_replay(*B, B->iters[0]);
-        HIPC(hipEventRecord(e1, B->st));
-        HIPC(hipEventSynchronize(e1));
-        float ms = 0.f;
-        HIPC(hipEventElapsedTime(&ms, e0, e1));
-        if (ms < best) { best = ms; best_cap = cap; }
-        auto drop = [](Batch::Seg& g) { if (g.exec) (void)hipGraphExecDestroy(g.exec); g.exec = nullptr; };
-        drop(B->init);
-        drop(B->truer);
-        for (auto& g : B->iters) drop(g);
-      }
+      for (int mr : {1, 0})
+        for (int cap : {128, 256, 512, 1024}) {
+          set_mrhs(mr);
+          set_red_block_cap(cap);
+          batch_build(*B);
+          batch_replay(*B, B->init);
+          batch_replay(*B, B->iters[0]);
+          HIPC(hipEventRecord(e0, B->st));
+          for (int rep = 0; rep < 3; ++rep) batch_replay(*B, B->iters[0]);
+          HIPC(hipEventRecord(e1, B->st));
+          HIPC(hipEventSynchronize(e1));
+          float ms = 0.f;
+          HIPC(hipEventElapsedTime(&ms, e0, e1));
+          B->trials.push_back({cap, mr, ms / 3.f});
+          if (ms < best) {
+            best = ms;
+            B->red_cap = cap;
+            B->mrhs = mr;
+          }
+          auto drop = [](Batch::Seg& g) { if (g.exec) (void)hipGraphExecDestroy(g.exec); g.exec = nullptr; };
+          drop(B->init);
+          drop(B->truer);
+          for (auto& g : B->iters) drop(g);
+        }
       (void)hipEventDestroy(e0);
       (void)hipEventDestroy(e1);
-      B->red_cap = best_cap;
+    } else if (const char* e = std::getenv("AMG_BATCH_MRHS")) {
+      B->mrhs = std::atoi(e) != 0 ? 1 : 0;
     }
+    set_mrhs(B->mrhs);
     set_red_block_cap(B->red_cap);
     batch_build(*B);
     set_red_block_cap(saved);
@@ -2145,6 +2161,26 @@ amg_status amg_batch_info(const amg_batch* B, int* red_cap, int* stages_per_iter
   AMG_TRY
   check_ptr(B, "batch");
   if (red_cap) *red_cap = B->red_cap;
+  if (stages_per_iteration) *stages_per_iteration = B->iters.empty() ? 0 : (int)B->iters[0].ops.size();
+  AMG_CATCH
+}
+
+int amg_batch_tuning(const amg_batch* B, int max, int* red_cap, int* mrhs, float* ms_per_iteration) {
+  if (!B) return -1;
+  const int n = (int)B->trials.size();
+  for (int i = 0; i < n && i < max; ++i) {
+    if (red_cap) red_cap[i] = B->trials[i].red_cap;
+    if (mrhs) mrhs[i] = B->trials[i].mrhs;
+    if (ms_per_iteration) ms_per_iteration[i] = B->trials[i].ms;
+  }
+  return n;
+}
+
+amg_status amg_batch_info2(const amg_batch* B, int* red_cap, int* mrhs, int* stages_per_iteration) {
+  AMG_TRY
+  check_ptr(B, "batch");
+  if (red_cap) *red_cap = B->red_cap;
+  if (mrhs) *mrhs = B->mrhs;
   if (stages_per_iteration) *stages_per_iteration = B->iters.empty() ? 0 : (int)B->iters[0].ops.size();
   AMG_CATCH
 }

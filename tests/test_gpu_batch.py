@@ -40,6 +40,12 @@ def test_batch_matches_single_solves(mixed):
     B = amg.Batch([s for _, _, s, _ in inst], nrhs, autotune=True)
     info = B.info()
     assert info["red_block_cap"] in (128, 256, 512, 1024) and info["launches_per_outer_step"] > 10
+    # the joint search: 4 reduction grids x 2 coarse stencils, the fastest kept
+    tr = info["tuning"]
+    assert len(tr) == 8 and {(t["red_block_cap"], t["coarse_mrhs_mfma"]) for t in tr} == {
+        (c, m) for c in (128, 256, 512, 1024) for m in (True, False)}
+    best = min(tr, key=lambda t: t["ms_per_outer_step"])
+    assert (best["red_block_cap"], best["coarse_mrhs_mfma"]) == (info["red_block_cap"], info["coarse_mrhs_mfma"])
     psis, infos = B.solve([dev(b) for _, _, _, b in inst], tol=1e-10)
     q = 0
     for (A, g, S, b), psi in zip(inst, psis):
@@ -55,6 +61,24 @@ def test_batch_matches_single_solves(mixed):
     psis2, infos2 = B.solve([dev(b) for _, _, _, b in inst], tol=1e-10)
     for p1, p2 in zip(psis, psis2):
         assert rel_err(host(p2), host(p1)) < 1e-9
+
+
+@pytest.mark.parametrize("mrhs", ["0", "1"])
+def test_batch_coarse_stencil_choices_agree(mrhs, monkeypatch):
+    """Both coarse-stencil choices the tuner picks between give the single
+    solves' answers (no autotune; the choice set through the environment)."""
+    import paper_0707_4018_amd as amg
+    monkeypatch.setenv("AMG_BATCH_MRHS", mrhs)
+    sizes, nrhs = [16, 32], [2, 1]
+    print(f"batch coarse stencil mrhs={mrhs}", flush=True)
+    inst = _instances(sizes, nrhs, True)
+    B = amg.Batch([s for _, _, s, _ in inst], nrhs, autotune=False)
+    assert B.info()["coarse_mrhs_mfma"] == (mrhs == "1") and B.info()["tuning"] == []
+    psis, infos = B.solve([dev(b) for _, _, _, b in inst], tol=1e-10)
+    for (A, g, S, b), psi in zip(inst, psis):
+        single, _ = S.solve(dev(b), tol=1e-10)
+        assert rel_err(host(psi), host(single)) < 1e-7
+    assert all(i.converged for i in infos)
 
 
 def test_batch_rejects_mismatched_solvers():
