@@ -226,9 +226,27 @@ void launch_normal_prolong(double2* out, const double2* in, const double2* P, co
                            hipStream_t st);
 void launch_normal_restrict(double2* out, const double2* in, const double2* P, const NGeom& g, int nrhs,
                             hipStream_t st);
-// out = Y in (epi 0) or b - Y in (epi 1) for the box stencil Y[V][9][M][M]
-void launch_box(double2* out, const double2* in, const double2* b, const double2* Y, int L1, int L2, int M, int nrhs,
-                int epi, hipStream_t st);
+// the box stencil Y[V][9][M][M] applied to `in` (layout lay, nrhs fields
+// lay.per_rhs() apart) with an epilogue, y = Y in:
+enum BoxEpi {
+  BOX_APPLY = 0,    // out = y
+  BOX_RESID = 1,    // out = b - y
+  BOX_SMOOTH0 = 2,  // x = c1 in, out = in - c1 y
+  BOX_SMOOTH1 = 3,  // x += c1 in, out = in - c1 y (out != in)
+  BOX_POST = 4      // x += c1 in - c2 y
+};
+struct BoxArgs {
+  double2* out = nullptr;
+  const double2* in = nullptr;
+  const double2* b = nullptr;
+  double2* x = nullptr;
+  const double2* Y = nullptr;
+  int L1 = 0, L2 = 0, M = 0;
+  Layout lay{};
+  int epi = BOX_APPLY;
+  double c1 = 0.0, c2 = 0.0;
+};
+void launch_box(const BoxArgs& a, int nrhs, hipStream_t st);
 void launch_box_dense(double2* A, const double2* Y, int L1, int L2, int M, hipStream_t st);
 void launch_probe(double2* e, int c1, int c2, int M, int p1, int p2, int q0, int nq, hipStream_t st);
 void launch_galerkin_box_scatter(double2* Y, const double2* z, int c1, int c2, int M, int p1, int p2, int q0, int nq,

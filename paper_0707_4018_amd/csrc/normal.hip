@@ -209,16 +209,48 @@ __global__ __launch_bounds__(256) void restrict_kernel(double2* __restrict__ out
 
 // ---- 9-point box stencil ------------------------------------------------------
 // Y[((j 9 + dir) M + c) M + r], dir = (d1 + 1) + 3 (d2 + 1): the M x M block
-// coupling row r of site j to column c of site j + (d1, d2).
-// out = Y in (epi 0) or out = b - Y in (epi 1); one thread per (site, row).
-__global__ __launch_bounds__(256) void box_kernel(double2* __restrict__ out, const double2* __restrict__ in,
-                                                  const double2* __restrict__ b, const double2* __restrict__ Y, int L1,
-                                                  int L2, int M, int epi) {
+// coupling row r of site j to column c of site j + (d1, d2).  Fields in any
+// Layout (fine planes or coarse [site][k]).  With y = Y in, the epilogue is
+//   BOX_APPLY   out = y
+//   BOX_RESID   out = b - y
+//   BOX_SMOOTH0 x = c1 in, out = in - c1 y              (first frozen step, in = b)
+//   BOX_SMOOTH1 x += c1 in, out = in - c1 y             (next step; out must not alias in)
+//   BOX_POST    x += c1 in - c2 y                       (x += R r with R = c1 - c2 A)
+__device__ __forceinline__ void box_epilogue(const BoxArgs& a, long ro, long off, double2 y) {
+  switch (a.epi) {
+    case BOX_APPLY: gl(a.out)[ro + off] = y; break;
+    case BOX_RESID: {
+      const double2 bv = gl(a.b)[ro + off];
+      gl(a.out)[ro + off] = make_double2(bv.x - y.x, bv.y - y.y);
+      break;
+    }
+    case BOX_SMOOTH0:
+    case BOX_SMOOTH1: {
+      const double2 v = gl(a.in)[ro + off];
+      double2 xv = a.epi == BOX_SMOOTH0 ? make_double2(0.0, 0.0) : gl(a.x)[ro + off];
+      xv.x += a.c1 * v.x;
+      xv.y += a.c1 * v.y;
+      gl(a.x)[ro + off] = xv;
+      gl(a.out)[ro + off] = make_double2(v.x - a.c1 * y.x, v.y - a.c1 * y.y);
+      break;
+    }
+    default: {  // BOX_POST
+      const double2 v = gl(a.in)[ro + off];
+      double2 xv = gl(a.x)[ro + off];
+      xv.x += a.c1 * v.x - a.c2 * y.x;
+      xv.y += a.c1 * v.y - a.c2 * y.y;
+      gl(a.x)[ro + off] = xv;
+    }
+  }
+}
+
+// one thread per (site, row)
+__global__ __launch_bounds__(256) void box_kernel(BoxArgs a) {
   const int rhs = blockIdx.y;
-  const long V = (long)L1 * L2, n = V * M;
-  gptr<double2> o = gl(out) + rhs * n;
-  gptr<const double2> x = gl(in) + rhs * n;
-  gptr<const double2> y = gl(Y);
+  const int M = a.M, L1 = a.L1, L2 = a.L2;
+  const long V = (long)L1 * L2, n = V * M, ro = rhs * a.lay.per_rhs();
+  gptr<const double2> x = gl(a.in) + ro;
+  gptr<const double2> y = gl(a.Y);
   GRID_STRIDE(i, n) {
     const long j = i / M;
     const int r = (int)(i % M);
@@ -230,43 +262,36 @@ __global__ __launch_bounds__(256) void box_kernel(double2* __restrict__ out, con
         const long nb = (long)n2 * L1 + wrapc(j1 + d1, L1);
         const int dir = (d1 + 1) + 3 * (d2 + 1);
         gptr<const double2> blk = y + (j * 9 + dir) * (long)M * M + r;
-        gptr<const double2> xn = x + nb * M;
-        for (int c = 0; c < M; ++c) cfma<double>(acc, blk[(long)c * M], xn[c]);
+        for (int c = 0; c < M; ++c) cfma<double>(acc, blk[(long)c * M], x[a.lay.off(nb, c)]);
       }
     }
-    if (epi == 1) {
-      const double2 bv = gl(b)[rhs * n + i];
-      acc.x = bv.x - acc.x;
-      acc.y = bv.y - acc.y;
-    }
-    o[i] = acc;
+    box_epilogue(a, ro, a.lay.off(j, r), acc);
   }
 }
 
-// The same for M <= 8 with one wave per site: lane l = c M + r (l < M^2)
+// The same for 3 <= M <= 8 with one wave per site: lane l = c M + r (l < M^2)
 // takes column c of row r in all nine directions (each direction's block is
 // one contiguous read of M^2 entries), and the M partial sums of a row are
 // added through LDS.
-__global__ __launch_bounds__(256) void box_wave_kernel(double2* __restrict__ out, const double2* __restrict__ in,
-                                                       const double2* __restrict__ b, const double2* __restrict__ Y,
-                                                       int L1, int L2, int M, int epi) {
+__global__ __launch_bounds__(256) void box_wave_kernel(BoxArgs a) {
   __shared__ double2 part[4][64];
   const int rhs = blockIdx.y;
-  const long V = (long)L1 * L2, n = V * M;
+  const int M = a.M, L1 = a.L1, L2 = a.L2;
+  const long V = (long)L1 * L2, ro = rhs * a.lay.per_rhs();
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const long j = (long)blockIdx.x * 4 + wv;
   const bool site = j < V;
   const int c = lane / M, r = lane - c * M;
   double2 acc = make_double2(0.0, 0.0);
   if (site && lane < M * M) {
-    gptr<const double2> x = gl(in) + rhs * n;
-    gptr<const double2> y = gl(Y) + j * 9 * (long)M * M + lane;
+    gptr<const double2> x = gl(a.in) + ro;
+    gptr<const double2> y = gl(a.Y) + j * 9 * (long)M * M + lane;
     const int j1 = (int)(j % L1), j2 = (int)(j / L1);
 #pragma unroll
     for (int dir = 0; dir < 9; ++dir) {
       const int d1 = dir % 3 - 1, d2 = dir / 3 - 1;
       const long nb = (long)wrapc(j2 + d2, L2) * L1 + wrapc(j1 + d1, L1);
-      cfma<double>(acc, y[(long)dir * M * M], x[nb * M + c]);
+      cfma<double>(acc, y[(long)dir * M * M], x[a.lay.off(nb, c)]);
     }
   }
   part[wv][lane] = acc;
@@ -278,13 +303,7 @@ __global__ __launch_bounds__(256) void box_wave_kernel(double2* __restrict__ out
       sum.x += t.x;
       sum.y += t.y;
     }
-    const long i = j * M + lane;
-    if (epi == 1) {
-      const double2 bv = gl(b)[rhs * n + i];
-      sum.x = bv.x - sum.x;
-      sum.y = bv.y - sum.y;
-    }
-    gl(out)[rhs * n + i] = sum;
+    box_epilogue(a, ro, a.lay.off(j, lane), sum);
   }
 }
 
@@ -497,16 +516,12 @@ void launch_normal_restrict(double2* out, const double2* in, const double2* P, c
                      g);
 }
 
-void launch_box(double2* out, const double2* in, const double2* b, const double2* Y, int L1, int L2, int M, int nrhs,
-                int epi, hipStream_t st) {
-  if (M <= 8) {
-    const long V = (long)L1 * L2;
-    hipLaunchKernelGGL(box_wave_kernel, dim3((unsigned)((V + 3) / 4), (unsigned)nrhs), dim3(256), 0, st, out, in, b,
-                       Y, L1, L2, M, epi);
-    return;
-  }
-  hipLaunchKernelGGL(box_kernel, dim3(nblk((long)L1 * L2 * M), (unsigned)nrhs), dim3(256), 0, st, out, in, b, Y, L1,
-                     L2, M, epi);
+void launch_box(const BoxArgs& a, int nrhs, hipStream_t st) {
+  const long V = (long)a.L1 * a.L2;
+  if (a.M >= 3 && a.M <= 8)
+    hipLaunchKernelGGL(box_wave_kernel, dim3((unsigned)((V + 3) / 4), (unsigned)nrhs), dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL(box_kernel, dim3(nblk(V * a.M), (unsigned)nrhs), dim3(256), 0, st, a);
 }
 
 void launch_box_dense(double2* A, const double2* Y, int L1, int L2, int M, hipStream_t st) {

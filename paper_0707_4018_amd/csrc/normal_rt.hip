@@ -57,8 +57,11 @@ struct NLevel {
   Buf Y;
   bool dense = false;
   Buf Ainv;
+  // level 0: A = D^dag D also stored as a 9-point box stencil (2 x 2 blocks),
+  // applied in one launch instead of D then D^dag
+  bool box = false;
   // work
-  Buf b, x, r, t, u;
+  Buf b, x, r, t, u, r2;
   Buf cr, cz, cp, cq, ct;   // CG on this level
   const double2* P() const { return g.sa ? Psa.as<double2>() : Pt.as<double2>(); }
 };
@@ -95,10 +98,33 @@ int period(int c, int pmin) {
 
 double fetch1(Normal& S, int slot, hipStream_t st) { return S.sc.fetch(slot, 1, st)[0]; }
 
+BoxArgs box_args(const NLevel& L, int epi) {
+  BoxArgs a;
+  a.Y = L.Y.as<double2>();
+  a.L1 = L.d1;
+  a.L2 = L.d2;
+  a.M = L.dof;
+  a.lay = L.lay;
+  a.epi = epi;
+  return a;
+}
+
+// the box stencil of level l (level 0 only when built) with an epilogue;
+// level 0 counts as one D and one D^dag application per field
+void box_apply(Normal& S, int l, BoxArgs a, int nrhs, hipStream_t st) {
+  launch_box(a, nrhs, st);
+  if (l == 0) {
+    S.nD += nrhs;
+    S.nDd += nrhs;
+  }
+}
+
+bool stencil_level(const Normal& S, int l) { return l > 0 || S.lv[0].box; }
+
 // out = A_l in (epi 0) or out = b - A_l in (epi 1), nrhs fields
 void apply_A(Normal& S, int l, const double2* in, double2* out, const double2* b, int epi, int nrhs, hipStream_t st) {
   NLevel& L = S.lv[l];
-  if (l == 0) {
+  if (!stencil_level(S, l)) {
     S.tD.ensure((size_t)L.n() * nrhs * sizeof(double2));
     wilson_apply<double>(*S.g, S.mass, 0, EPI_PLAIN, in, S.tD.as<double2>(), nullptr, nullptr, nrhs, S.sc.red(0), st);
     wilson_apply<double>(*S.g, S.mass, 1, epi ? EPI_RESID : EPI_PLAIN, S.tD.as<double2>(), out, b, nullptr, nrhs,
@@ -106,7 +132,11 @@ void apply_A(Normal& S, int l, const double2* in, double2* out, const double2* b
     S.nD += nrhs;
     S.nDd += nrhs;
   } else {
-    launch_box(out, in, b, L.Y.as<double2>(), L.d1, L.d2, L.dof, nrhs, epi, st);
+    BoxArgs a = box_args(L, epi ? BOX_RESID : BOX_APPLY);
+    a.in = in;
+    a.out = out;
+    a.b = b;
+    box_apply(S, l, a, nrhs, st);
   }
 }
 
@@ -116,7 +146,7 @@ void dot3(Normal& S, const double2* a, const double2* b, long n, int slot, hipSt
 
 void ensure_level_work(NLevel& L) {
   const size_t nb = (size_t)L.n() * sizeof(double2);
-  for (Buf* b : {&L.b, &L.x, &L.r, &L.t, &L.u, &L.cr, &L.cz, &L.cp, &L.cq, &L.ct}) b->ensure(nb);
+  for (Buf* b : {&L.b, &L.x, &L.r, &L.t, &L.u, &L.r2, &L.cr, &L.cz, &L.cp, &L.cq, &L.ct}) b->ensure(nb);
 }
 
 // ---- set-up pieces ----------------------------------------------------------------
@@ -207,6 +237,34 @@ void galerkin(Normal& S, int l, hipStream_t st) {
   }
 }
 
+// A_0 = D^dag D as a box stencil of 2 x 2 blocks, by probing the two Wilson
+// applications with coloured unit vectors (period >= 3), on lattices up to
+// 2^18 sites (beyond, the two stencil launches move fewer bytes than the
+// 576-byte box blocks per site)
+constexpr long FINE_BOX_MAX_SITES = 1L << 18;
+void build_fine_box(Normal& S, hipStream_t st) {
+  NLevel& L = S.lv[0];
+  L.box = false;
+  const int p1 = period(L.d1, 3), p2 = period(L.d2, 3);
+  if (L.V > FINE_BOX_MAX_SITES || p1 == 0 || p2 == 0) return;
+  const int np = p1 * p2 * 2;
+  const long n = L.n();
+  L.Y.ensure((size_t)L.V * 9 * 4 * sizeof(double2));
+  for (Buf* b : {&S.pe, &S.px, &S.py, &S.pz, &S.tD}) b->ensure((size_t)n * PROBE_CHUNK * sizeof(double2));
+  for (int q0 = 0; q0 < np; q0 += PROBE_CHUNK) {
+    const int nq = std::min(PROBE_CHUNK, np - q0);
+    launch_probe(S.pe.as<double2>(), L.d1, L.d2, 2, p1, p2, q0, nq, st);                       // [site][spin]
+    launch_convert<double, double>(S.px.as<double2>(), S.pe.as<double2>(), L.V, 2, 2, 1, nq, st);  // -> planes
+    wilson_apply<double>(*S.g, S.mass, 0, EPI_PLAIN, S.px.as<double2>(), S.tD.as<double2>(), nullptr, nullptr, nq,
+                         S.sc.red(0), st);
+    wilson_apply<double>(*S.g, S.mass, 1, EPI_PLAIN, S.tD.as<double2>(), S.py.as<double2>(), nullptr, nullptr, nq,
+                         S.sc.red(0), st);
+    launch_convert<double, double>(S.pz.as<double2>(), S.py.as<double2>(), L.V, 2, 1, 2, nq, st);  // -> [site][spin]
+    launch_galerkin_box_scatter(L.Y.as<double2>(), S.pz.as<double2>(), L.d1, L.d2, 2, p1, p2, q0, nq, st);
+  }
+  L.box = true;
+}
+
 // P and A_{l+1} of coarsening l from its first M vectors
 void build_coarsening(Normal& S, int l, int M, hipStream_t st) {
   NLevel& F = S.lv[l];
@@ -282,6 +340,37 @@ void vcycle(Normal& S, int l, int lstop, const double2* b, double2* x, hipStream
   NLevel& C = S.lv[l + 1];
   const long n = F.n();
   double2 *r = F.r.as<double2>(), *t = F.t.as<double2>();
+  if (stencil_level(S, l)) {
+    // the same five steps with the smoother's updates in the stencil's epilogue
+    BoxArgs a = box_args(F, BOX_SMOOTH0);
+    a.in = b;                                // 1. x = tau0 b, r = b - tau0 A b
+    a.out = r;
+    a.x = x;
+    a.c1 = F.tau0;
+    box_apply(S, l, a, 1, st);
+    a.epi = BOX_SMOOTH1;                     //    x += tau1 r, r2 = r - tau1 A r
+    a.in = r;
+    a.out = F.r2.as<double2>();
+    a.c1 = F.tau1;
+    box_apply(S, l, a, 1, st);
+    launch_normal_restrict(C.b.as<double2>(), F.r2.as<double2>(), F.P(), F.g, 1, st);   // 2.-3.
+    vcycle(S, l + 1, lstop, C.b.as<double2>(), C.x.as<double2>(), st);
+    launch_normal_prolong(x, C.x.as<double2>(), F.P(), F.g, 1, 1, st);                  // 4.
+    a.epi = BOX_RESID;                       // 5. r = b - A x, then x += R r
+    a.in = x;
+    a.b = b;
+    a.out = r;
+    a.x = nullptr;
+    box_apply(S, l, a, 1, st);
+    a.epi = BOX_POST;
+    a.in = r;
+    a.out = nullptr;
+    a.x = x;
+    a.c1 = F.tau0 + F.tau1;
+    a.c2 = F.tau0 * F.tau1;
+    box_apply(S, l, a, 1, st);
+    return;
+  }
   // 1. x = R^dag b: the two frozen steps from x = 0 (R = R^dag)
   apply_A(S, l, b, t, nullptr, 0, 1, st);
   launch_smooth_step(x, r, b, t, F.tau0, n, 1, st);
@@ -507,6 +596,7 @@ amg_status amg_normal_setup(const amg_gauge* g, const amg_normal_params* p, cons
   hipStream_t st = as_stream(stream);
   try {
     const int nl = (int)S->lv.size();
+    build_fine_box(*S, st);
     for (int l = 0; l + 1 < nl; ++l) {
       upload_level_inputs(*S, l, dev_vecs[l], dev_sb[l], st);
       build_coarsening(*S, l, S->lv[l].M, st);
@@ -533,6 +623,7 @@ amg_status amg_normal_setup_adaptive(const amg_gauge* g, const amg_normal_params
   hipStream_t st = as_stream(stream);
   try {
     const int nl = (int)S->lv.size();
+    build_fine_box(*S, st);
     for (int l = 0; l + 1 < nl; ++l) {
       if (nu0[l] < 0 || ncyc[l] < 0) fail(AMG_ERR_ARG, "negative nu0 / ncyc");
       upload_level_inputs(*S, l, dev_init[l], dev_sb[l], st);
@@ -554,6 +645,7 @@ amg_status amg_normal_set_mass(amg_normal* S, double mass, void* stream) {
   hipStream_t st = as_stream(stream);
   S->mass = mass;
   const int nl = (int)S->lv.size();
+  build_fine_box(*S, st);
   for (int l = 0; l + 1 < nl; ++l) build_coarsening(*S, l, S->lv[l].M, st);
   finish(*S, st);
   AMG_CATCH
