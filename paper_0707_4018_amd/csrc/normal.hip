@@ -246,6 +246,7 @@ __device__ __forceinline__ void box_epilogue(const BoxArgs& a, long ro, long off
 
 // one thread per (site, row)
 __global__ __launch_bounds__(256) void box_kernel(BoxArgs a) {
+  if (a.stop && *gl(a.stop)) return;
   const int rhs = blockIdx.y;
   const int M = a.M, L1 = a.L1, L2 = a.L2;
   const long V = (long)L1 * L2, n = V * M, ro = rhs * a.lay.per_rhs();
@@ -275,6 +276,7 @@ __global__ __launch_bounds__(256) void box_kernel(BoxArgs a) {
 // added through LDS.
 __global__ __launch_bounds__(256) void box_wave_kernel(BoxArgs a) {
   __shared__ double2 part[4][64];
+  if (a.stop && *gl(a.stop)) return;  // uniform: the whole launch returns
   const int rhs = blockIdx.y;
   const int M = a.M, L1 = a.L1, L2 = a.L2;
   const long V = (long)L1 * L2, ro = rhs * a.lay.per_rhs();
@@ -410,7 +412,8 @@ __global__ __launch_bounds__(256) void p_dense_kernel(double2* __restrict__ out,
 // ---- vector kernels ----------------------------------------------------------------
 // scal[slot] = Re <a, b>, scal[slot + 1] = Im <a, b>, scal[slot + 2] = <a, a>
 __global__ __launch_bounds__(256) void dot3_kernel(const double2* __restrict__ a, const double2* __restrict__ b, long n,
-                                                   RedArgs red) {
+                                                   RedArgs red, const int* stop) {
+  if (stop && *gl(stop)) return;
   double acc[3] = {0.0, 0.0, 0.0};
   gptr<const double2> pa = gl(a), pb = gl(b);
   GRID_STRIDE(i, n) {
@@ -425,6 +428,48 @@ __global__ __launch_bounds__(256) void dot3_kernel(const double2* __restrict__ a
     sc[red.slot] = tot[0];
     sc[red.slot + 1] = tot[1];
     sc[red.slot + 2] = tot[2];
+  }
+}
+
+// CG direction and update guarded by a device stop flag (see kernels.h)
+__global__ __launch_bounds__(256) void cgb_dir_kernel(double2* __restrict__ p, const double2* __restrict__ z, long n,
+                                                      const double* __restrict__ scal, int gnew, int gold, int fresh,
+                                                      const int* stop) {
+  if (*gl(stop)) return;
+  const double go = scal[gold];
+  const double beta = (fresh || !(go > 0.0)) ? 0.0 : scal[gnew] / go;
+  GRID_STRIDE(i, n) {
+    const double2 zi = z[i];
+    double2 pi = fresh ? make_double2(0.0, 0.0) : p[i];
+    p[i] = make_double2(zi.x + beta * pi.x, zi.y + beta * pi.y);
+  }
+}
+
+__global__ __launch_bounds__(256) void cgb_update_kernel(double2* __restrict__ x, double2* __restrict__ r,
+                                                         const double2* __restrict__ p, const double2* __restrict__ q,
+                                                         long n, RedArgs red, int gamma, int qq, int rr, double tol2,
+                                                         int* stop, int* iters) {
+  if (*gl(stop)) return;
+  gptr<double> sc = gl(red.scal);
+  const double pq = sc[qq];
+  const double a = pq > 0.0 ? sc[gamma] / pq : 0.0;
+  double acc[1] = {0.0};
+  GRID_STRIDE(i, n) {
+    const double2 pi = p[i], qi = q[i];
+    double2 xi = x[i], ri = r[i];
+    xi.x += a * pi.x;
+    xi.y += a * pi.y;
+    ri.x -= a * qi.x;
+    ri.y -= a * qi.y;
+    x[i] = xi;
+    r[i] = ri;
+    acc[0] += ri.x * ri.x + ri.y * ri.y;
+  }
+  double tot[1];
+  if (grid_reduce<1>(acc, red.part, red.ticket, 0, tot) && threadIdx.x == 0) {
+    sc[rr] = tot[0];
+    gl(iters)[0] += 1;
+    if (tot[0] <= tol2) gl(stop)[0] = 1;
   }
 }
 
@@ -550,12 +595,27 @@ void launch_normal_p_dense(double2* out, const double2* P, const NGeom& g, hipSt
   hipLaunchKernelGGL(p_dense_kernel, dim3(nblk(n)), dim3(256), 0, st, out, P, g);
 }
 
-void launch_dot3(const double2* a, const double2* b, long n, RedArgs red, hipStream_t st) {
+void launch_dot3(const double2* a, const double2* b, long n, RedArgs red, hipStream_t st, const int* stop) {
   long nb = (n + 255) / 256;
   const long cap = red_block_cap();
   if (nb > cap) nb = cap;
   if (nb < 1) nb = 1;
-  hipLaunchKernelGGL(dot3_kernel, dim3((unsigned)nb), dim3(256), 0, st, a, b, n, red);
+  hipLaunchKernelGGL(dot3_kernel, dim3((unsigned)nb), dim3(256), 0, st, a, b, n, red, stop);
+}
+
+void launch_cgb_dir(double2* p, const double2* z, long n, const double* scal, int gnew, int gold, int fresh,
+                    const int* stop, hipStream_t st) {
+  hipLaunchKernelGGL(cgb_dir_kernel, dim3(nblk(n)), dim3(256), 0, st, p, z, n, scal, gnew, gold, fresh, stop);
+}
+
+void launch_cgb_update(double2* x, double2* r, const double2* p, const double2* q, long n, RedArgs red, int gamma,
+                       int qq, int rr, double tol2, int* stop, int* iters, hipStream_t st) {
+  long nb = (n + 255) / 256;
+  const long cap = red_block_cap();
+  if (nb > cap) nb = cap;
+  if (nb < 1) nb = 1;
+  hipLaunchKernelGGL(cgb_update_kernel, dim3((unsigned)nb), dim3(256), 0, st, x, r, p, q, n, red, gamma, qq, rr, tol2,
+                     stop, iters);
 }
 
 void launch_mr_step(double2* x, double2* r, const double2* p, const double* scal, int slot, double omega, long n,

@@ -78,6 +78,7 @@ struct amg_normal {
   Buf pe, px, py, pz;        // probe buffers
   Buf gjA, gjB, gjkey, gjint;
   Buf err;
+  Buf cgflag;                // batched CG: stop flag and performed-iteration counter
   Buf io;                    // internal copies of fine fields at the C ABI
   long long nD = 0, nDd = 0;
 };
@@ -121,22 +122,30 @@ void box_apply(Normal& S, int l, BoxArgs a, int nrhs, hipStream_t st) {
 
 bool stencil_level(const Normal& S, int l) { return l > 0 || S.lv[0].box; }
 
-// out = A_l in (epi 0) or out = b - A_l in (epi 1), nrhs fields
-void apply_A(Normal& S, int l, const double2* in, double2* out, const double2* b, int epi, int nrhs, hipStream_t st) {
+// out = A_l in (epi 0) or out = b - A_l in (epi 1), nrhs fields.  stop: the
+// launches do nothing while *stop != 0 (the caller then counts the fine
+// applications that ran itself)
+void apply_A(Normal& S, int l, const double2* in, double2* out, const double2* b, int epi, int nrhs, hipStream_t st,
+             const int* stop = nullptr) {
   NLevel& L = S.lv[l];
   if (!stencil_level(S, l)) {
     S.tD.ensure((size_t)L.n() * nrhs * sizeof(double2));
-    wilson_apply<double>(*S.g, S.mass, 0, EPI_PLAIN, in, S.tD.as<double2>(), nullptr, nullptr, nrhs, S.sc.red(0), st);
+    wilson_apply<double>(*S.g, S.mass, 0, EPI_PLAIN, in, S.tD.as<double2>(), nullptr, nullptr, nrhs,
+                         S.sc.red(0, stop), st);
     wilson_apply<double>(*S.g, S.mass, 1, epi ? EPI_RESID : EPI_PLAIN, S.tD.as<double2>(), out, b, nullptr, nrhs,
-                         S.sc.red(0), st);
-    S.nD += nrhs;
-    S.nDd += nrhs;
+                         S.sc.red(0, stop), st);
+    if (!stop) {
+      S.nD += nrhs;
+      S.nDd += nrhs;
+    }
   } else {
     BoxArgs a = box_args(L, epi ? BOX_RESID : BOX_APPLY);
     a.in = in;
     a.out = out;
     a.b = b;
-    box_apply(S, l, a, nrhs, st);
+    a.stop = stop;
+    if (stop) launch_box(a, nrhs, st);
+    else box_apply(S, l, a, nrhs, st);
   }
 }
 
@@ -408,6 +417,53 @@ CgOut cg_solve(Normal& S, int l, const double2* b, double2* x, double tol, int m
   double rr = bb;
   int gcur = S_G0, gnext = S_G1;
   bool fresh = true;
+  if (lstop < 0) {
+    // plain CG: batches of CG_BATCH steps enqueued without a host round
+    // trip; the update's last block raises a device stop flag once the
+    // recursive residual is below tol, after which the rest of the batch does
+    // nothing, so iterates and count are those of the step-by-step loop
+    constexpr int CG_BATCH = 16;
+    S.cgflag.ensure(4 * sizeof(int));
+    int* stop = S.cgflag.as<int>();
+    int* cnt = stop + 1;
+    HIPC(hipMemsetAsync(stop, 0, 2 * sizeof(int), st));
+    int* hflags = reinterpret_cast<int*>(S.sc.host + 2 * RHS_MAX);
+    int counted = 0;
+    while (o.iters < maxiter) {
+      if (rr <= tol2) {
+        apply_A(S, l, x, t, b, 1, 1, st);
+        launch_norm2<double>(t, n, 1, S.sc.red(S_TT), st);
+        const double tt = fetch1(S, S_TT, st);
+        if (tt <= tol2) {
+          o.converged = true;
+          break;
+        }
+        launch_fill<double>(r, t, n, 1, st);
+        HIPC(hipMemsetAsync(stop, 0, sizeof(int), st));
+        rr = tt;
+        fresh = true;
+        ++o.restarts;
+      }
+      const int K = std::min(CG_BATCH, maxiter - o.iters);
+      for (int k = 0; k < K; ++k) {
+        launch_dot3(r, r, n, S.sc.red(gnext), st, stop);            // rho = <r, r>
+        launch_cgb_dir(p, r, n, scal, gnext, gcur, fresh ? 1 : 0, stop, st);
+        apply_A(S, l, p, q, nullptr, 0, 1, st, stop);
+        launch_dot3(p, q, n, S.sc.red(S_PQ), st, stop);
+        launch_cgb_update(x, r, p, q, n, S.sc.red(0), gnext, S_PQ, S_RR, tol2, stop, cnt, st);
+        std::swap(gcur, gnext);
+        fresh = false;
+      }
+      HIPC(hipMemcpyAsync(hflags, stop, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+      rr = fetch1(S, S_RR, st);  // (synchronises the stream)
+      o.iters = hflags[1];
+      if (l == 0) {  // fine applications that ran
+        S.nD += o.iters - counted;
+        S.nDd += o.iters - counted;
+      }
+      counted = o.iters;
+    }
+  } else
   while (o.iters < maxiter) {
     if (rr <= tol2) {
       apply_A(S, l, x, t, b, 1, 1, st);
