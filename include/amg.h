@@ -433,6 +433,9 @@ typedef struct {
   int coarse_dense_max;   /* the coarsest level (V M unknowns) must not exceed this: its */
                           /* dense Galerkin matrix is inverted (Gauss-Jordan, partial    */
                           /* pivoting); <= AMG_DENSE_MAX, default 4096                   */
+  int fine_box;               /* 1: A_0 = D^dag D also stored as a 9-point stencil of 2 x 2 */
+                              /* blocks (probed per mass) and applied in one launch, on    */
+                              /* lattices up to 2^18 sites; 0: always D then D^dag         */
   int setup_dense_max;        /* adaptive set-up: a set-up cycle's coarse level of at most */
                               /* this many unknowns is solved exactly (dense inverse),    */
   double setup_coarse_tol;    /* a larger one by CG to setup_coarse_tol (at most          */

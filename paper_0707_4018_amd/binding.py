@@ -56,7 +56,8 @@ class _NParams(C.Structure):
     _fields_ = [
         ("nlevels", C.c_int), ("block", (C.c_int * 2) * 3), ("nvec", C.c_int * 3), ("omega", C.c_double),
         ("sa_factor", C.c_double), ("power_steps", C.c_int), ("coarse_dense_max", C.c_int),
-        ("setup_dense_max", C.c_int), ("setup_coarse_tol", C.c_double), ("setup_coarse_maxiter", C.c_int),
+        ("fine_box", C.c_int), ("setup_dense_max", C.c_int), ("setup_coarse_tol", C.c_double),
+        ("setup_coarse_maxiter", C.c_int),
     ]
 
 
@@ -688,6 +689,7 @@ class NormalParams:
     sa_factor: float = 4.0 / 3.0
     power_steps: int = 20
     coarse_dense_max: int = 4096
+    fine_box: bool = True
     setup_dense_max: int = 1024
     setup_coarse_tol: float = 1e-6
     setup_coarse_maxiter: int = 20000
@@ -701,6 +703,7 @@ class NormalParams:
             p.nvec[l] = int(self.nvec[l])
         p.omega, p.sa_factor, p.power_steps = self.omega, self.sa_factor, self.power_steps
         p.coarse_dense_max, p.setup_dense_max = self.coarse_dense_max, self.setup_dense_max
+        p.fine_box = int(self.fine_box)
         p.setup_coarse_tol, p.setup_coarse_maxiter = self.setup_coarse_tol, self.setup_coarse_maxiter
         return p
 

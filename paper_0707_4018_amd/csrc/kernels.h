@@ -222,10 +222,11 @@ struct NGeom {
 size_t normal_orth_lds(const NGeom& g);
 // tentative P [Vf][dof][M] from vecs (M fields of layout lf, vstride apart); *err |= 1 on rank deficiency
 void launch_normal_orth(double2* Pt, const double2* vecs, const NGeom& g, long vstride, int* err, hipStream_t st);
+// (stop: the launch does nothing while *stop != 0)
 void launch_normal_prolong(double2* out, const double2* in, const double2* P, const NGeom& g, int nrhs, int accumulate,
-                           hipStream_t st);
+                           hipStream_t st, const int* stop = nullptr);
 void launch_normal_restrict(double2* out, const double2* in, const double2* P, const NGeom& g, int nrhs,
-                            hipStream_t st);
+                            hipStream_t st, const int* stop = nullptr);
 // the box stencil Y[V][9][M][M] applied to `in` (layout lay, nrhs fields
 // lay.per_rhs() apart) with an epilogue, y = Y in:
 enum BoxEpi {
@@ -269,9 +270,9 @@ void launch_cgb_update(double2* x, double2* r, const double2* p, const double2* 
 void launch_mr_step(double2* x, double2* r, const double2* p, const double* scal, int slot, double omega, long n,
                     hipStream_t st);
 void launch_smooth_step(double2* x, double2* r, const double2* b, const double2* t, double tau, long n, int first,
-                        hipStream_t st);
+                        hipStream_t st, const int* stop = nullptr);
 void launch_smooth_post(double2* x, const double2* r, const double2* t, double c1, double c2, long n,
-                        hipStream_t st);
+                        hipStream_t st, const int* stop = nullptr);
 void launch_axpy3(double2* y, const double2* x, const double2* t, double w, long n, hipStream_t st);
 void launch_scale_norm(double2* p, const double2* q, const double* scal, int slot, long n, hipStream_t st);
 

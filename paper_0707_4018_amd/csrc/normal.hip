@@ -130,7 +130,9 @@ __global__ __launch_bounds__(64) void orth_kernel(double2* __restrict__ P, const
 // (tentative) or 4 (smoothed, slots (a1, a2) = q & 1, q >> 1).
 // out (fine, layout lf) = [out +] P in (coarse, [J][k])
 __global__ __launch_bounds__(256) void prolong_kernel(double2* __restrict__ out, const double2* __restrict__ in,
-                                                      const double2* __restrict__ P, NGeom g, int accumulate) {
+                                                      const double2* __restrict__ P, NGeom g, int accumulate,
+                                                      const int* stop) {
+  if (stop && *gl(stop)) return;
   const int rhs = blockIdx.y;
   const int NS = g.sa ? 4 : 1, M = g.M;
   const long Vf = (long)g.f1 * g.f2, Vc = (long)g.c1 * g.c2;
@@ -166,7 +168,8 @@ __global__ __launch_bounds__(256) void prolong_kernel(double2* __restrict__ out,
 // one site for the smoothed P) are spread over the lanes, each lane keeps the
 // M partial sums, and M wave sums finish them.
 __global__ __launch_bounds__(256) void restrict_kernel(double2* __restrict__ out, const double2* __restrict__ in,
-                                                       const double2* __restrict__ P, NGeom g) {
+                                                       const double2* __restrict__ P, NGeom g, const int* stop) {
+  if (stop && *gl(stop)) return;
   const int rhs = blockIdx.y;
   const int NS = g.sa ? 4 : 1, M = g.M, w = g.sa ? 1 : 0;
   const long Vf = (long)g.f1 * g.f2, Vc = (long)g.c1 * g.c2;
@@ -494,7 +497,8 @@ __global__ __launch_bounds__(256) void mr_kernel(double2* __restrict__ x, double
 // smoother steps: first x = tau b, r = b - tau t; then x += tau r, r -= tau t
 __global__ __launch_bounds__(256) void smooth_step_kernel(double2* __restrict__ x, double2* __restrict__ r,
                                                           const double2* __restrict__ b, const double2* __restrict__ t,
-                                                          double tau, long n, int first) {
+                                                          double tau, long n, int first, const int* stop) {
+  if (stop && *gl(stop)) return;
   GRID_STRIDE(i, n) {
     const double2 ti = t[i];
     const double2 ri = first ? b[i] : r[i];
@@ -509,7 +513,8 @@ __global__ __launch_bounds__(256) void smooth_step_kernel(double2* __restrict__ 
 // x += c1 r - c2 t
 __global__ __launch_bounds__(256) void smooth_post_kernel(double2* __restrict__ x, const double2* __restrict__ r,
                                                           const double2* __restrict__ t, double c1, double c2,
-                                                          long n) {
+                                                          long n, const int* stop) {
+  if (stop && *gl(stop)) return;
   GRID_STRIDE(i, n) {
     const double2 ri = r[i], ti = t[i];
     double2 xi = x[i];
@@ -549,16 +554,16 @@ void launch_normal_orth(double2* Pt, const double2* vecs, const NGeom& g, long v
 }
 
 void launch_normal_prolong(double2* out, const double2* in, const double2* P, const NGeom& g, int nrhs, int accumulate,
-                           hipStream_t st) {
+                           hipStream_t st, const int* stop) {
   hipLaunchKernelGGL(prolong_kernel, dim3(nblk((long)g.f1 * g.f2 * g.dof), (unsigned)nrhs), dim3(256), 0, st, out, in,
-                     P, g, accumulate);
+                     P, g, accumulate, stop);
 }
 
 void launch_normal_restrict(double2* out, const double2* in, const double2* P, const NGeom& g, int nrhs,
-                            hipStream_t st) {
+                            hipStream_t st, const int* stop) {
   const long Vc = (long)g.c1 * g.c2;
   hipLaunchKernelGGL(restrict_kernel, dim3((unsigned)((Vc + 3) / 4), (unsigned)nrhs), dim3(256), 0, st, out, in, P,
-                     g);
+                     g, stop);
 }
 
 void launch_box(const BoxArgs& a, int nrhs, hipStream_t st) {
@@ -624,13 +629,13 @@ void launch_mr_step(double2* x, double2* r, const double2* p, const double* scal
 }
 
 void launch_smooth_step(double2* x, double2* r, const double2* b, const double2* t, double tau, long n, int first,
-                        hipStream_t st) {
-  hipLaunchKernelGGL(smooth_step_kernel, dim3(nblk(n)), dim3(256), 0, st, x, r, b, t, tau, n, first);
+                        hipStream_t st, const int* stop) {
+  hipLaunchKernelGGL(smooth_step_kernel, dim3(nblk(n)), dim3(256), 0, st, x, r, b, t, tau, n, first, stop);
 }
 
 void launch_smooth_post(double2* x, const double2* r, const double2* t, double c1, double c2, long n,
-                        hipStream_t st) {
-  hipLaunchKernelGGL(smooth_post_kernel, dim3(nblk(n)), dim3(256), 0, st, x, r, t, c1, c2, n);
+                        hipStream_t st, const int* stop) {
+  hipLaunchKernelGGL(smooth_post_kernel, dim3(nblk(n)), dim3(256), 0, st, x, r, t, c1, c2, n, stop);
 }
 
 void launch_axpy3(double2* y, const double2* x, const double2* t, double w, long n, hipStream_t st) {

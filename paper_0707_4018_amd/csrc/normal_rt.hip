@@ -114,7 +114,7 @@ BoxArgs box_args(const NLevel& L, int epi) {
 // level 0 counts as one D and one D^dag application per field
 void box_apply(Normal& S, int l, BoxArgs a, int nrhs, hipStream_t st) {
   launch_box(a, nrhs, st);
-  if (l == 0) {
+  if (l == 0 && !a.stop) {
     S.nD += nrhs;
     S.nDd += nrhs;
   }
@@ -144,8 +144,7 @@ void apply_A(Normal& S, int l, const double2* in, double2* out, const double2* b
     a.out = out;
     a.b = b;
     a.stop = stop;
-    if (stop) launch_box(a, nrhs, st);
-    else box_apply(S, l, a, nrhs, st);
+    box_apply(S, l, a, nrhs, st);
   }
 }
 
@@ -255,7 +254,7 @@ void build_fine_box(Normal& S, hipStream_t st) {
   NLevel& L = S.lv[0];
   L.box = false;
   const int p1 = period(L.d1, 3), p2 = period(L.d2, 3);
-  if (L.V > FINE_BOX_MAX_SITES || p1 == 0 || p2 == 0) return;
+  if (!S.p.fine_box || L.V > FINE_BOX_MAX_SITES || p1 == 0 || p2 == 0) return;
   const int np = p1 * p2 * 2;
   const long n = L.n();
   L.Y.ensure((size_t)L.V * 9 * 4 * sizeof(double2));
@@ -333,16 +332,19 @@ struct CgOut {
 
 CgOut cg_solve(Normal& S, int l, const double2* b, double2* x, double tol, int maxiter, int lstop, hipStream_t st);
 
-void coarse_solve(Normal& S, int l, const double2* b, double2* x, hipStream_t st) {
+// (stop: a batched CG's flag, only with a dense coarse level)
+void coarse_solve(Normal& S, int l, const double2* b, double2* x, hipStream_t st, const int* stop) {
   NLevel& L = S.lv[l];
-  if (L.dense) launch_dense_apply<double>(x, b, L.Ainv.as<double2>(), L.n(), 1, nullptr, st);
+  if (L.dense) launch_dense_apply<double>(x, b, L.Ainv.as<double2>(), L.n(), 1, stop, st);
+  else if (stop) fail(AMG_ERR_STATE, "a batched CG needs an exact coarsest solve");
   else cg_solve(S, l, b, x, S.p.setup_coarse_tol, S.p.setup_coarse_maxiter, -1, st);
 }
 
-// x = V b on level l, recursion down to level lstop (solved exactly)
-void vcycle(Normal& S, int l, int lstop, const double2* b, double2* x, hipStream_t st) {
+// x = V b on level l, recursion down to level lstop (solved exactly); with
+// stop, every launch does nothing while *stop != 0 and nothing is counted
+void vcycle(Normal& S, int l, int lstop, const double2* b, double2* x, hipStream_t st, const int* stop = nullptr) {
   if (l == lstop) {
-    coarse_solve(S, l, b, x, st);
+    coarse_solve(S, l, b, x, st, stop);
     return;
   }
   NLevel& F = S.lv[l];
@@ -352,6 +354,7 @@ void vcycle(Normal& S, int l, int lstop, const double2* b, double2* x, hipStream
   if (stencil_level(S, l)) {
     // the same five steps with the smoother's updates in the stencil's epilogue
     BoxArgs a = box_args(F, BOX_SMOOTH0);
+    a.stop = stop;
     a.in = b;                                // 1. x = tau0 b, r = b - tau0 A b
     a.out = r;
     a.x = x;
@@ -362,9 +365,9 @@ void vcycle(Normal& S, int l, int lstop, const double2* b, double2* x, hipStream
     a.out = F.r2.as<double2>();
     a.c1 = F.tau1;
     box_apply(S, l, a, 1, st);
-    launch_normal_restrict(C.b.as<double2>(), F.r2.as<double2>(), F.P(), F.g, 1, st);   // 2.-3.
-    vcycle(S, l + 1, lstop, C.b.as<double2>(), C.x.as<double2>(), st);
-    launch_normal_prolong(x, C.x.as<double2>(), F.P(), F.g, 1, 1, st);                  // 4.
+    launch_normal_restrict(C.b.as<double2>(), F.r2.as<double2>(), F.P(), F.g, 1, st, stop);   // 2.-3.
+    vcycle(S, l + 1, lstop, C.b.as<double2>(), C.x.as<double2>(), st, stop);
+    launch_normal_prolong(x, C.x.as<double2>(), F.P(), F.g, 1, 1, st, stop);                  // 4.
     a.epi = BOX_RESID;                       // 5. r = b - A x, then x += R r
     a.in = x;
     a.b = b;
@@ -381,19 +384,19 @@ void vcycle(Normal& S, int l, int lstop, const double2* b, double2* x, hipStream
     return;
   }
   // 1. x = R^dag b: the two frozen steps from x = 0 (R = R^dag)
-  apply_A(S, l, b, t, nullptr, 0, 1, st);
-  launch_smooth_step(x, r, b, t, F.tau0, n, 1, st);
-  apply_A(S, l, r, t, nullptr, 0, 1, st);
-  launch_smooth_step(x, r, nullptr, t, F.tau1, n, 0, st);
+  apply_A(S, l, b, t, nullptr, 0, 1, st, stop);
+  launch_smooth_step(x, r, b, t, F.tau0, n, 1, st, stop);
+  apply_A(S, l, r, t, nullptr, 0, 1, st, stop);
+  launch_smooth_step(x, r, nullptr, t, F.tau1, n, 0, st, stop);
   // 2.-3. restrict the residual, cycle below
-  launch_normal_restrict(C.b.as<double2>(), r, F.P(), F.g, 1, st);
-  vcycle(S, l + 1, lstop, C.b.as<double2>(), C.x.as<double2>(), st);
+  launch_normal_restrict(C.b.as<double2>(), r, F.P(), F.g, 1, st, stop);
+  vcycle(S, l + 1, lstop, C.b.as<double2>(), C.x.as<double2>(), st, stop);
   // 4. coarse-grid correction
-  launch_normal_prolong(x, C.x.as<double2>(), F.P(), F.g, 1, 1, st);
+  launch_normal_prolong(x, C.x.as<double2>(), F.P(), F.g, 1, 1, st, stop);
   // 5. x += R (b - A x)
-  apply_A(S, l, x, r, b, 1, 1, st);
-  apply_A(S, l, r, t, nullptr, 0, 1, st);
-  launch_smooth_post(x, r, t, F.tau0 + F.tau1, F.tau0 * F.tau1, n, st);
+  apply_A(S, l, x, r, b, 1, 1, st, stop);
+  apply_A(S, l, r, t, nullptr, 0, 1, st, stop);
+  launch_smooth_post(x, r, t, F.tau0 + F.tau1, F.tau0 * F.tau1, n, st, stop);
 }
 
 // CG on A_l x = b from x = 0; lstop >= 0: preconditioned by one V-cycle to lstop
@@ -417,53 +420,19 @@ CgOut cg_solve(Normal& S, int l, const double2* b, double2* x, double tol, int m
   double rr = bb;
   int gcur = S_G0, gnext = S_G1;
   bool fresh = true;
-  if (lstop < 0) {
-    // plain CG: batches of CG_BATCH steps enqueued without a host round
-    // trip; the update's last block raises a device stop flag once the
-    // recursive residual is below tol, after which the rest of the batch does
-    // nothing, so iterates and count are those of the step-by-step loop
-    constexpr int CG_BATCH = 16;
-    S.cgflag.ensure(4 * sizeof(int));
-    int* stop = S.cgflag.as<int>();
-    int* cnt = stop + 1;
-    HIPC(hipMemsetAsync(stop, 0, 2 * sizeof(int), st));
-    int* hflags = reinterpret_cast<int*>(S.sc.host + 2 * RHS_MAX);
-    int counted = 0;
-    while (o.iters < maxiter) {
-      if (rr <= tol2) {
-        apply_A(S, l, x, t, b, 1, 1, st);
-        launch_norm2<double>(t, n, 1, S.sc.red(S_TT), st);
-        const double tt = fetch1(S, S_TT, st);
-        if (tt <= tol2) {
-          o.converged = true;
-          break;
-        }
-        launch_fill<double>(r, t, n, 1, st);
-        HIPC(hipMemsetAsync(stop, 0, sizeof(int), st));
-        rr = tt;
-        fresh = true;
-        ++o.restarts;
-      }
-      const int K = std::min(CG_BATCH, maxiter - o.iters);
-      for (int k = 0; k < K; ++k) {
-        launch_dot3(r, r, n, S.sc.red(gnext), st, stop);            // rho = <r, r>
-        launch_cgb_dir(p, r, n, scal, gnext, gcur, fresh ? 1 : 0, stop, st);
-        apply_A(S, l, p, q, nullptr, 0, 1, st, stop);
-        launch_dot3(p, q, n, S.sc.red(S_PQ), st, stop);
-        launch_cgb_update(x, r, p, q, n, S.sc.red(0), gnext, S_PQ, S_RR, tol2, stop, cnt, st);
-        std::swap(gcur, gnext);
-        fresh = false;
-      }
-      HIPC(hipMemcpyAsync(hflags, stop, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
-      rr = fetch1(S, S_RR, st);  // (synchronises the stream)
-      o.iters = hflags[1];
-      if (l == 0) {  // fine applications that ran
-        S.nD += o.iters - counted;
-        S.nDd += o.iters - counted;
-      }
-      counted = o.iters;
-    }
-  } else
+  // Steps are enqueued in batches with no host round trip: the update's last
+  // block raises a device stop flag once the recursive residual is below
+  // tol, after which the rest of the batch does nothing, so the iterates and
+  // the count are those of the step-by-step loop; the host then confirms the
+  // residual by recomputing it (else restarts from it).
+  const int batch = lstop >= 0 ? 8 : 16;
+  const int per_step = lstop >= 0 ? 5 : 1;  // fine applications per step (outer + V-cycle's four)
+  S.cgflag.ensure(4 * sizeof(int));
+  int* stop = S.cgflag.as<int>();
+  int* cnt = stop + 1;
+  HIPC(hipMemsetAsync(stop, 0, 2 * sizeof(int), st));
+  int* hflags = reinterpret_cast<int*>(S.sc.host + 2 * RHS_MAX);
+  int counted = 0;
   while (o.iters < maxiter) {
     if (rr <= tol2) {
       apply_A(S, l, x, t, b, 1, 1, st);
@@ -474,21 +443,30 @@ CgOut cg_solve(Normal& S, int l, const double2* b, double2* x, double tol, int m
         break;
       }
       launch_fill<double>(r, t, n, 1, st);
+      HIPC(hipMemsetAsync(stop, 0, sizeof(int), st));
       rr = tt;
       fresh = true;
       ++o.restarts;
     }
-    if (lstop >= 0) vcycle(S, l, lstop, r, z, st);
-    dot3(S, r, z, n, gnext, st);   // rho = Re <r, z>
-    if (fresh) HIPC(hipMemsetAsync(scal + gcur, 0, sizeof(double), st));
-    launch_cg_pupdate(p, z, n, 1, scal, gnext, gcur, st);
-    apply_A(S, l, p, q, nullptr, 0, 1, st);
-    dot3(S, p, q, n, S_PQ, st);
-    launch_cg_update(x, r, p, q, n, 1, S.sc.red(0), gnext, S_PQ, S_RR, st);
-    std::swap(gcur, gnext);
-    fresh = false;
-    ++o.iters;
-    rr = fetch1(S, S_RR, st);
+    const int K = std::min(batch, maxiter - o.iters);
+    for (int k = 0; k < K; ++k) {
+      if (lstop >= 0) vcycle(S, l, lstop, r, z, st, stop);
+      launch_dot3(r, z, n, S.sc.red(gnext), st, stop);            // rho = Re <r, z>
+      launch_cgb_dir(p, z, n, scal, gnext, gcur, fresh ? 1 : 0, stop, st);
+      apply_A(S, l, p, q, nullptr, 0, 1, st, stop);
+      launch_dot3(p, q, n, S.sc.red(S_PQ), st, stop);
+      launch_cgb_update(x, r, p, q, n, S.sc.red(0), gnext, S_PQ, S_RR, tol2, stop, cnt, st);
+      std::swap(gcur, gnext);
+      fresh = false;
+    }
+    HIPC(hipMemcpyAsync(hflags, stop, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+    rr = fetch1(S, S_RR, st);  // (synchronises the stream)
+    o.iters = hflags[1];
+    if (l == 0) {  // fine applications of the steps that ran
+      S.nD += (long long)per_step * (o.iters - counted);
+      S.nDd += (long long)per_step * (o.iters - counted);
+    }
+    counted = o.iters;
   }
   apply_A(S, l, x, t, b, 1, 1, st);
   launch_norm2<double>(t, n, 1, S.sc.red(S_TT), st);
@@ -637,6 +615,7 @@ void amg_normal_default_params(amg_normal_params* p) {
   p->sa_factor = 4.0 / 3.0;
   p->power_steps = 20;
   p->coarse_dense_max = 4096;
+  p->fine_box = 1;
   p->setup_dense_max = 1024;
   p->setup_coarse_tol = 1e-6;
   p->setup_coarse_maxiter = 20000;

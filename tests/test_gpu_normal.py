@@ -59,18 +59,19 @@ def _rel(a, b):
     return np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b))
 
 
-CASES = [
-    (16, [(4, 4)], [4], 0.0),
-    (16, [(4, 4)], [4], SA),
-    (24, [(4, 4), (2, 2)], [4, 3], 0.0),       # M changes between levels, coarse extent 3
-    (48, [(4, 4), (4, 4)], [4, 4], SA),        # three levels, 12^2 then 3^2
+CASES = [  # (L, blocks, nvec, smoothing factor, fine D^dag D as one box stencil)
+    (16, [(4, 4)], [4], 0.0, True),
+    (16, [(4, 4)], [4], SA, True),
+    (24, [(4, 4), (2, 2)], [4, 3], 0.0, True),       # M changes between levels, coarse extent 3
+    (48, [(4, 4), (4, 4)], [4, 4], SA, True),        # three levels, 12^2 then 3^2
+    (48, [(4, 4), (4, 4)], [4, 4], SA, False),       # the same with D then D^dag (the large-lattice path)
 ]
 
 
-@pytest.fixture(scope="module", params=CASES, ids=lambda c: f"L{c[0]}-{len(c[1]) + 1}lv-sa{c[3] > 0}")
+@pytest.fixture(scope="module", params=CASES, ids=lambda c: f"L{c[0]}-{len(c[1]) + 1}lv-sa{c[3] > 0}-box{int(c[4])}")
 def given(request):
     import paper_0707_4018_amd as amg
-    L, blocks, nvec, sa = request.param
+    L, blocks, nvec, sa, fine_box = request.param
     print(f"normal MG given vectors L={L} blocks={blocks} nvec={nvec} sa={sa}", flush=True)
     m = 0.05
     U = _field(L)
@@ -78,7 +79,9 @@ def given(request):
     vecs, sb = _inputs(L, blocks, nvec)
     H = normal.build(D, (L, L), vecs, blocks, [s.ravel() for s in sb], sa=sa)
     g = _gauge(U, m)
-    S = amg.NormalMG(g, _params(blocks, nvec, sa), _cuda(sb), vecs=_cuda(vecs))
+    prm = _params(blocks, nvec, sa)
+    prm.fine_box = fine_box
+    S = amg.NormalMG(g, prm, _cuda(sb), vecs=_cuda(vecs))
     return dict(L=L, U=U, D=D, H=H, g=g, S=S, blocks=blocks, nvec=nvec, sa=sa, vecs=vecs, sb=sb, m=m)
 
 
