@@ -261,12 +261,13 @@ void launch_normal_p_dense(double2* out, const double2* P, const NGeom& g, hipSt
 void launch_dot3(const double2* a, const double2* b, long n, RedArgs red, hipStream_t st, const int* stop = nullptr);
 // CG steps that run only while *stop == 0.  Direction: p = z + (scal[gnew] /
 // scal[gold]) p (p = z when fresh).  Update: alpha = scal[gamma] / scal[qq],
-// x += alpha p, r -= alpha q, scal[rr] = |r|^2; its last block sets
-// *stop = (|r|^2 <= tol2) and counts the step in *iters.
+// x += alpha p, r -= alpha q, scal[rr] = |r|^2 (also scal[rr2] when
+// rr2 >= 0); its last block sets *stop = (|r|^2 <= tol2) and counts the step
+// in *iters.
 void launch_cgb_dir(double2* p, const double2* z, long n, const double* scal, int gnew, int gold, int fresh,
                     const int* stop, hipStream_t st);
 void launch_cgb_update(double2* x, double2* r, const double2* p, const double2* q, long n, RedArgs red, int gamma,
-                       int qq, int rr, double tol2, int* stop, int* iters, hipStream_t st);
+                       int qq, int rr, int rr2, double tol2, int* stop, int* iters, hipStream_t st);
 void launch_mr_step(double2* x, double2* r, const double2* p, const double* scal, int slot, double omega, long n,
                     hipStream_t st);
 void launch_smooth_step(double2* x, double2* r, const double2* b, const double2* t, double tau, long n, int first,

@@ -273,6 +273,34 @@ __global__ __launch_bounds__(256) void box_kernel(BoxArgs a) {
   }
 }
 
+// M = 2 (the fine D^dag D): one thread per site computes both rows, so the
+// nine neighbours' two components are loaded once
+__global__ __launch_bounds__(256) void box2_kernel(BoxArgs a) {
+  if (a.stop && *gl(a.stop)) return;
+  const int rhs = blockIdx.y;
+  const int L1 = a.L1, L2 = a.L2;
+  const long V = (long)L1 * L2, ro = rhs * a.lay.per_rhs();
+  gptr<const double2> x = gl(a.in) + ro;
+  gptr<const double2> y = gl(a.Y);
+  GRID_STRIDE(j, V) {
+    const int j1 = (int)(j % L1), j2 = (int)(j / L1);
+    double2 acc0 = make_double2(0.0, 0.0), acc1 = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int dir = 0; dir < 9; ++dir) {
+      const int d1 = dir % 3 - 1, d2 = dir / 3 - 1;
+      const long nb = (long)wrapc(j2 + d2, L2) * L1 + wrapc(j1 + d1, L1);
+      const double2 v0 = x[a.lay.off(nb, 0)], v1 = x[a.lay.off(nb, 1)];
+      gptr<const double2> blk = y + (j * 9 + dir) * 4;  // [col][row]
+      cfma<double>(acc0, blk[0], v0);
+      cfma<double>(acc0, blk[2], v1);
+      cfma<double>(acc1, blk[1], v0);
+      cfma<double>(acc1, blk[3], v1);
+    }
+    box_epilogue(a, ro, a.lay.off(j, 0), acc0);
+    box_epilogue(a, ro, a.lay.off(j, 1), acc1);
+  }
+}
+
 // The same for 3 <= M <= 8 with one wave per site: lane l = c M + r (l < M^2)
 // takes column c of row r in all nine directions (each direction's block is
 // one contiguous read of M^2 entries), and the M partial sums of a row are
@@ -450,8 +478,8 @@ __global__ __launch_bounds__(256) void cgb_dir_kernel(double2* __restrict__ p, c
 
 __global__ __launch_bounds__(256) void cgb_update_kernel(double2* __restrict__ x, double2* __restrict__ r,
                                                          const double2* __restrict__ p, const double2* __restrict__ q,
-                                                         long n, RedArgs red, int gamma, int qq, int rr, double tol2,
-                                                         int* stop, int* iters) {
+                                                         long n, RedArgs red, int gamma, int qq, int rr, int rr2,
+                                                         double tol2, int* stop, int* iters) {
   if (*gl(stop)) return;
   gptr<double> sc = gl(red.scal);
   const double pq = sc[qq];
@@ -471,6 +499,7 @@ __global__ __launch_bounds__(256) void cgb_update_kernel(double2* __restrict__ x
   double tot[1];
   if (grid_reduce<1>(acc, red.part, red.ticket, 0, tot) && threadIdx.x == 0) {
     sc[rr] = tot[0];
+    if (rr2 >= 0) sc[rr2] = tot[0];
     gl(iters)[0] += 1;
     if (tot[0] <= tol2) gl(stop)[0] = 1;
   }
@@ -570,6 +599,8 @@ void launch_box(const BoxArgs& a, int nrhs, hipStream_t st) {
   const long V = (long)a.L1 * a.L2;
   if (a.M >= 3 && a.M <= 8)
     hipLaunchKernelGGL(box_wave_kernel, dim3((unsigned)((V + 3) / 4), (unsigned)nrhs), dim3(256), 0, st, a);
+  else if (a.M == 2)
+    hipLaunchKernelGGL(box2_kernel, dim3(nblk(V), (unsigned)nrhs), dim3(256), 0, st, a);
   else
     hipLaunchKernelGGL(box_kernel, dim3(nblk(V * a.M), (unsigned)nrhs), dim3(256), 0, st, a);
 }
@@ -614,13 +645,13 @@ void launch_cgb_dir(double2* p, const double2* z, long n, const double* scal, in
 }
 
 void launch_cgb_update(double2* x, double2* r, const double2* p, const double2* q, long n, RedArgs red, int gamma,
-                       int qq, int rr, double tol2, int* stop, int* iters, hipStream_t st) {
+                       int qq, int rr, int rr2, double tol2, int* stop, int* iters, hipStream_t st) {
   long nb = (n + 255) / 256;
   const long cap = red_block_cap();
   if (nb > cap) nb = cap;
   if (nb < 1) nb = 1;
-  hipLaunchKernelGGL(cgb_update_kernel, dim3((unsigned)nb), dim3(256), 0, st, x, r, p, q, n, red, gamma, qq, rr, tol2,
-                     stop, iters);
+  hipLaunchKernelGGL(cgb_update_kernel, dim3((unsigned)nb), dim3(256), 0, st, x, r, p, q, n, red, gamma, qq, rr, rr2,
+                     tol2, stop, iters);
 }
 
 void launch_mr_step(double2* x, double2* r, const double2* p, const double* scal, int slot, double omega, long n,

@@ -433,6 +433,10 @@ CgOut cg_solve(Normal& S, int l, const double2* b, double2* x, double tol, int m
   HIPC(hipMemsetAsync(stop, 0, 2 * sizeof(int), st));
   int* hflags = reinterpret_cast<int*>(S.sc.host + 2 * RHS_MAX);
   int counted = 0;
+  // plain CG: rho = <r, r> is the |r|^2 the update reduces anyway; it goes
+  // into the slot that becomes the next step's rho
+  const bool plain = lstop < 0;
+  if (plain) launch_norm2<double>(r, n, 1, S.sc.red(gnext), st);
   while (o.iters < maxiter) {
     if (rr <= tol2) {
       apply_A(S, l, x, t, b, 1, 1, st);
@@ -443,6 +447,7 @@ CgOut cg_solve(Normal& S, int l, const double2* b, double2* x, double tol, int m
         break;
       }
       launch_fill<double>(r, t, n, 1, st);
+      if (plain) launch_norm2<double>(r, n, 1, S.sc.red(gnext), st);
       HIPC(hipMemsetAsync(stop, 0, sizeof(int), st));
       rr = tt;
       fresh = true;
@@ -450,12 +455,14 @@ CgOut cg_solve(Normal& S, int l, const double2* b, double2* x, double tol, int m
     }
     const int K = std::min(batch, maxiter - o.iters);
     for (int k = 0; k < K; ++k) {
-      if (lstop >= 0) vcycle(S, l, lstop, r, z, st, stop);
-      launch_dot3(r, z, n, S.sc.red(gnext), st, stop);            // rho = Re <r, z>
+      if (!plain) {
+        vcycle(S, l, lstop, r, z, st, stop);
+        launch_dot3(r, z, n, S.sc.red(gnext), st, stop);          // rho = Re <r, z>
+      }
       launch_cgb_dir(p, z, n, scal, gnext, gcur, fresh ? 1 : 0, stop, st);
       apply_A(S, l, p, q, nullptr, 0, 1, st, stop);
       launch_dot3(p, q, n, S.sc.red(S_PQ), st, stop);
-      launch_cgb_update(x, r, p, q, n, S.sc.red(0), gnext, S_PQ, S_RR, tol2, stop, cnt, st);
+      launch_cgb_update(x, r, p, q, n, S.sc.red(0), gnext, S_PQ, S_RR, plain ? gcur : -1, tol2, stop, cnt, st);
       std::swap(gcur, gnext);
       fresh = false;
     }
