@@ -74,7 +74,7 @@ def source():
 # solver parameters shared by the GPU run and the oracle sample
 PARAMS = dict(blocks=[(4, 4), (2, 2)], nvec=[8, 8], nu_pre=2, nu_post=2, omega=0.8,
               coarse_tol=0.2, coarse_maxiter=100, coarse_restart=10, outer_restart=16,
-              kcycle_tol=0.2, kcycle_maxiter=8)
+              kcycle_tol=0.2, kcycle_maxiter=8, coarse_jacobi=True)
 
 
 # adaptive setup: nu0 MR steps on the first vector, ncyc error-propagation sweeps per further vector
@@ -741,7 +741,8 @@ def oracle_params():
     return mg.MGParams(blocks=P["blocks"], nvec=P["nvec"], nu_pre=P["nu_pre"], nu_post=P["nu_post"],
                        omega=P["omega"], coarse_tol=P["coarse_tol"], coarse_maxiter=P["coarse_maxiter"],
                        coarse_restart=P["coarse_restart"], outer_restart=P["outer_restart"],
-                       kcycle_tol=P["kcycle_tol"], kcycle_maxiter=P["kcycle_maxiter"])
+                       kcycle_tol=P["kcycle_tol"], kcycle_maxiter=P["kcycle_maxiter"],
+                       coarse_jacobi=P["coarse_jacobi"])
 
 
 def oracle_child(mode: str, path_in: str, path_out: str):

@@ -91,6 +91,13 @@ typedef struct {
                          * (FP32 copy of the inverse for the FP32 cycle).  Larger coarsest levels
                          * use GCR (coarse_tol, coarse_maxiter, coarse_restart).  Default 4096.
                          * Batched solves (amg_batch_create) use GCR on every instance. */
+  int coarse_jacobi;    /* 1: the coarsest GCR (where not dense) is right-preconditioned by the
+                         * inverse M of each coarse site's diagonal block (levels of at most 32 dof
+                         * per site): GCR runs on the stencil of D_hat M, built at setup and after
+                         * a mass change, and the result is M y.  Its iterates are those of GCR
+                         * with the fixed preconditioner z = M r.  A level whose diagonal block is
+                         * singular keeps the plain GCR.  Not applied inside batched solves.
+                         * Default 0. */
 } amg_mg_params;
 
 #define AMG_DENSE_MAX 8192

@@ -429,6 +429,7 @@ class MGParams:
     smoother: object = None           # callable(A, b, nu, omega) -> (x, r); MR when None
     kcycle_tol: float = None          # intermediate levels: GCR to this tolerance (K-cycle); None: V-cycle
     kcycle_maxiter: int = 8
+    coarse_jacobi: bool = False       # coarsest GCR preconditioned by the inverse diagonal blocks (dof <= 32)
 
 
 @dataclass
@@ -504,7 +505,17 @@ def coarsest_solve(A: Stencil, b: np.ndarray, p: MGParams, exact: bool) -> np.nd
     gcr_coarse; the outer Krylov method is flexible)."""
     if exact:
         return dense_solve(A, b)
-    return gcr_coarse(A, b, p.coarse_tol, p.coarse_maxiter, p.coarse_restart)
+    precond = None
+    if p.coarse_jacobi and A.dof <= 32:
+        precond = lambda r: block_jacobi(A, r)
+    return gcr_coarse(A, b, p.coarse_tol, p.coarse_maxiter, p.coarse_restart, precond=precond)
+
+
+def block_jacobi(A: Stencil, r: np.ndarray) -> np.ndarray:
+    """z(x) = diag(x)^-1 r(x): each site's diagonal block of A inverted and
+    applied to r (the block-Jacobi preconditioner of the coarsest GCR; the
+    paper's coarsest solve is exact, this only speeds up its approximation)."""
+    return np.linalg.solve(A.diag, r[..., None])[..., 0]
 
 
 def vcycle(H: Hierarchy, level: int, b: np.ndarray) -> np.ndarray:

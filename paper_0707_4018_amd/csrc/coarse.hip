@@ -1182,3 +1182,156 @@ void launch_p_export(double2* out, const void* P, int pkind, const TransferGeom&
     hipLaunchKernelGGL(p_export_kernel<bf16x2>, dim3((unsigned)nb), dim3(256), 0, st, out, (const bf16x2*)P, g);
 }
 }  // namespace amg
+
+// ---- right block-Jacobi preconditioning of a coarse level ------------------
+// M(x) = A_0(x)^-1, the inverse of each site's diagonal block, and the
+// operator A M of the preconditioned system: (A M)(x, x) = 1,
+// (A M)(x, x + dir) = A_dir(x) M(x + dir).  GCR on A M y = b followed by
+// x = M y gives the iterates of GCR on A x = b with the fixed preconditioner
+// z = M r.  Blocks keep the stencil's column-major [col][row] order.
+namespace amg {
+namespace {
+constexpr int BINV_MAX = 32;
+
+// one wave per site: Gauss-Jordan with partial pivoting on [A_0 | 1] in LDS;
+// err[0] is set when a pivot column is zero (the block is singular)
+__global__ __launch_bounds__(64) void block_inverse_kernel(double2* __restrict__ Minv, const double2* __restrict__ Y,
+                                                           long V, int ndir, int nc, int* err) {
+  __shared__ double2 a[BINV_MAX][2 * BINV_MAX];
+  __shared__ double2 fac[BINV_MAX];
+  __shared__ int piv;
+  const long site = blockIdx.x;
+  if (site >= V) return;
+  const int lane = threadIdx.x;
+  const int w = 2 * nc;
+  const double2* A0 = Y + site * ndir * (long)nc * nc;
+  for (int e = lane; e < nc * w; e += 64) {
+    const int r = e / w, c = e - r * w;
+    a[r][c] = c < nc ? A0[(long)c * nc + r] : make_double2(c - nc == r ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  for (int c = 0; c < nc; ++c) {
+    if (lane == 0) {
+      int p = c;
+      double best = -1.0;
+      for (int r = c; r < nc; ++r) {
+        const double m = a[r][c].x * a[r][c].x + a[r][c].y * a[r][c].y;
+        if (m > best) { best = m; p = r; }
+      }
+      if (!(best > 0.0)) {
+        atomicOr(err, 1);
+        p = -1;
+      }
+      piv = p;
+    }
+    __syncthreads();
+    const int p = piv;
+    if (p < 0) return;  // uniform: the whole wave leaves
+    if (p != c)
+      for (int j = lane; j < w; j += 64) {
+        const double2 t = a[c][j];
+        a[c][j] = a[p][j];
+        a[p][j] = t;
+      }
+    __syncthreads();
+    const double2 d = a[c][c];
+    const double dn = 1.0 / (d.x * d.x + d.y * d.y);
+    const double2 inv = make_double2(d.x * dn, -d.y * dn);
+    __syncthreads();
+    for (int j = lane; j < w; j += 64) {
+      const double2 v = a[c][j];
+      a[c][j] = make_double2(v.x * inv.x - v.y * inv.y, v.x * inv.y + v.y * inv.x);
+    }
+    if (lane < nc && lane != c) fac[lane] = a[lane][c];
+    __syncthreads();
+    for (int e = lane; e < nc * w; e += 64) {
+      const int r = e / w, j = e - r * w;
+      if (r == c) continue;
+      const double2 f = fac[r], u = a[c][j];
+      double2 v = a[r][j];
+      v.x -= f.x * u.x - f.y * u.y;
+      v.y -= f.x * u.y + f.y * u.x;
+      a[r][j] = v;
+    }
+    __syncthreads();
+  }
+  double2* M = Minv + site * (long)nc * nc;
+  for (int e = lane; e < nc * nc; e += 64) {
+    const int col = e / nc, row = e - col * nc;
+    M[e] = a[row][nc + col];
+  }
+}
+
+// thread per entry (site, k, col, row) of A M
+__global__ __launch_bounds__(256) void jacobi_couplings_kernel(double2* __restrict__ AM, const double2* __restrict__ Y,
+                                                               const double2* __restrict__ Minv, CoarseGeom g) {
+  const int nc = g.nc, nd = g.nd, ndir = 2 * nd + 1;
+  const long per = (long)nc * nc;
+  const long total = g.V * ndir * per;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
+    const long site = i / (ndir * per);
+    const long rem = i - site * ndir * per;
+    const int k = (int)(rem / per);
+    const int col = (int)((rem - (long)k * per) / nc), row = (int)(rem - (long)k * per - (long)col * nc);
+    if (k == 0) {
+      AM[i] = make_double2(col == row ? 1.0 : 0.0, 0.0);
+      continue;
+    }
+    int x[4];
+    coords(site, g.dims, nd, x);
+    const long nb = neighbour(site, x, g.dims, nd, k - 1);
+    const double2* Ak = Y + (site * ndir + k) * per;  // [m][row]
+    const double2* Mn = Minv + nb * per + (long)col * nc;  // column col of M(nb): [m]
+    double sr = 0.0, si = 0.0;
+    for (int m = 0; m < nc; ++m) {
+      const double2 u = Ak[(long)m * nc + row], v = Mn[m];
+      sr += u.x * v.x - u.y * v.y;
+      si += u.x * v.y + u.y * v.x;
+    }
+    AM[i] = make_double2(sr, si);
+  }
+}
+
+// out(x) = M(x) in(x) for every site and right-hand side (grid y = rhs)
+template <typename T>
+__global__ __launch_bounds__(256) void block_apply_kernel(cplx<T>* __restrict__ out, const cplx<T>* __restrict__ in,
+                                                          const cplx<T>* __restrict__ M, long V, int nc) {
+  const long n = V * nc;
+  const long ro = (long)blockIdx.y * n;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const long site = i / nc;
+    const int row = (int)(i - site * nc);
+    const cplx<T>* Ms = M + site * (long)nc * nc + row;
+    const cplx<T>* v = in + ro + site * nc;
+    T sr = 0, si = 0;
+    for (int col = 0; col < nc; ++col) {
+      const cplx<T> u = Ms[(long)col * nc], w = v[col];
+      sr += u.x * w.x - u.y * w.y;
+      si += u.x * w.y + u.y * w.x;
+    }
+    out[ro + i] = mk<T>(sr, si);
+  }
+}
+}  // namespace
+
+bool block_jacobi_supported(int nc) { return nc >= 1 && nc <= BINV_MAX; }
+
+void launch_block_inverse(double2* Minv, const double2* Y, long V, int ndir, int nc, int* err, hipStream_t st) {
+  hipLaunchKernelGGL(block_inverse_kernel, dim3((unsigned)V), dim3(64), 0, st, Minv, Y, V, ndir, nc, err);
+}
+
+void launch_jacobi_couplings(double2* AM, const double2* Y, const double2* Minv, const CoarseGeom& g, hipStream_t st) {
+  long nb = (g.V * (2 * g.nd + 1) * (long)g.nc * g.nc + 255) / 256;
+  if (nb > (1L << 20)) nb = 1L << 20;
+  hipLaunchKernelGGL(jacobi_couplings_kernel, dim3((unsigned)nb), dim3(256), 0, st, AM, Y, Minv, g);
+}
+
+template <typename T>
+void launch_block_apply(cplx<T>* out, const cplx<T>* in, const cplx<T>* M, long V, int nc, int nrhs, hipStream_t st) {
+  long nb = (V * nc + 255) / 256;
+  if (nb > (1L << 20)) nb = 1L << 20;
+  hipLaunchKernelGGL(block_apply_kernel<T>, dim3((unsigned)nb, (unsigned)nrhs), dim3(256), 0, st, out, in, M, V, nc);
+}
+template void launch_block_apply<double>(double2*, const double2*, const double2*, long, int, int, hipStream_t);
+template void launch_block_apply<float>(float2*, const float2*, const float2*, long, int, int, hipStream_t);
+}  // namespace amg

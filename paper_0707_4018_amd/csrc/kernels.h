@@ -192,6 +192,14 @@ void launch_axpy(cplx<T>* y, const cplx<T>* x, double are, double aim, long n, i
 template <typename T>
 void launch_scale_inv_norm(cplx<T>* v, const double* nn, long n, int nrhs, hipStream_t st);
 void launch_diag_shift(double2* Y, const double2* M, long V, int nc, int ndir, double dm, hipStream_t st);
+// right block-Jacobi preconditioning of a coarse level (nc <= 32): Minv = the
+// inverse of each site's diagonal block (err[0] set if one is singular), AM =
+// the stencil of A M, and out = M in
+bool block_jacobi_supported(int nc);
+void launch_block_inverse(double2* Minv, const double2* Y, long V, int ndir, int nc, int* err, hipStream_t st);
+void launch_jacobi_couplings(double2* AM, const double2* Y, const double2* Minv, const CoarseGeom& g, hipStream_t st);
+template <typename T>
+void launch_block_apply(cplx<T>* out, const cplx<T>* in, const cplx<T>* M, long V, int nc, int nrhs, hipStream_t st);
 void launch_links4d_pack(double2* U64, float2* U32, const double2* canon, long V, hipStream_t st);
 // two-row (12-real) copies of SU(3) links in FP64 and FP32; *not_su3 (zero on
 // entry) becomes nonzero if some link is not unitary with unit determinant to 1e-9

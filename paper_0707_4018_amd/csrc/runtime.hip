@@ -101,6 +101,12 @@ struct Level {
   // FP32 for the FP32 cycle), valid while `dense` is set
   Buf D64, D32;
   bool dense = false;
+  // right block-Jacobi preconditioning of this level's GCR as the coarsest
+  // level: M = inverse diagonal blocks, J = the stencil of A M (both FP64,
+  // and FP32 for the FP32 cycle), JY = the GCR iterate y (x = M y); valid
+  // while `jac` is set
+  Buf MI64, MI32, J64, J32, JY64, JY32;
+  bool jac = false;
   int alloc_nrhs = 0;
   // scalar slots
   int mr_slot = 0;
@@ -125,6 +131,15 @@ struct Level {
 };
 template <> const double2* Level::Y<double>() const { return Y64.as<double2>(); }
 template <> const float2* Level::Y<float>() const { return Y32.as<float2>(); }
+template <typename T> const cplx<T>* level_J(const Level& L) {
+  return reinterpret_cast<const cplx<T>*>(Pick<T>::prec == AMG_F64 ? L.J64.p : L.J32.p);
+}
+template <typename T> const cplx<T>* level_MI(const Level& L) {
+  return reinterpret_cast<const cplx<T>*>(Pick<T>::prec == AMG_F64 ? L.MI64.p : L.MI32.p);
+}
+template <typename T> cplx<T>* level_JY(Level& L) {
+  return reinterpret_cast<cplx<T>*>(Pick<T>::prec == AMG_F64 ? L.JY64.p : L.JY32.p);
+}
 
 }  // namespace
 
@@ -144,6 +159,7 @@ struct amg_solver {
   Buf tE, tF, tS, tR, tzero;
   // Gauss-Jordan work (two N x N matrices, pivot records)
   Buf gjA, gjB, gjkey, gjint;
+  Buf jerr;  // singular-block flag of the block-Jacobi set-up
   // batched solves run the coarsest level by GCR on every instance (one
   // launch sequence for all of them)
   bool no_dense = false;
@@ -250,7 +266,7 @@ const void* Pstore(const Solver& S, int l, int& kind) {
 // operator of level l, precision T
 template <typename T>
 void op_apply(Solver& S, int l, int dagger, int epi, const cplx<T>* in, cplx<T>* out, const cplx<T>* b,
-              cplx<T>* copy_out, int nrhs, RedArgs red, hipStream_t st) {
+              cplx<T>* copy_out, int nrhs, RedArgs red, hipStream_t st, const cplx<T>* Yop = nullptr) {
   Level& L = S.lv[l];
   const bool mr_epi = epi == EPI_MRDOT || epi == EPI_MRPART;
   ProfScope ps(S, L.fine ? PK_FINE : (mr_epi && (S.prof.kind == PK_COARSE_MR || S.prof.kind < 0) ? PK_COARSE_MR
@@ -262,7 +278,7 @@ void op_apply(Solver& S, int l, int dagger, int epi, const cplx<T>* in, cplx<T>*
   } else {
     CoarseArgs<T> a;
     a.out = out; a.in = in; a.b = b; a.copy_out = copy_out;
-    a.Y = L.Y<T>();
+    a.Y = Yop ? Yop : L.Y<T>();
     a.g = L.cgeom();
     a.nrhs = nrhs;
     a.red = red;
@@ -284,6 +300,8 @@ void alloc_level_work(Level& L, int nrhs, int restart, bool coarsest, bool f32) 
   if (coarsest) {
     L.Z64.ensure(n * restart * sizeof(double2));
     L.W64.ensure(n * restart * sizeof(double2));
+    L.JY64.ensure(n * sizeof(double2));
+    if (f32) L.JY32.ensure(n * sizeof(float2));
     if (f32) {
       L.Z32.ensure(n * restart * sizeof(float2));
       L.W32.ensure(n * restart * sizeof(float2));
@@ -358,9 +376,14 @@ void vcycle(Solver& S, int l, int lstop, const cplx<T>* b, cplx<T>* x, int nrhs,
 // precond = false: the coarsest-level solve (z = r);
 // precond = true:  a K-cycle level, z = the cycle of level l down to lstop.
 template <typename T>
-void level_gcr(Solver& S, int l, int lstop, const cplx<T>* b, cplx<T>* x, int nrhs, double tol, int maxiter,
+void level_gcr(Solver& S, int l, int lstop, const cplx<T>* b, cplx<T>* x_out, int nrhs, double tol, int maxiter,
                int m, bool precond, hipStream_t st) {
   Level& L = S.lv[l];
+  // coarsest level with block-Jacobi preconditioning: GCR on (A M) y = b,
+  // then x = M y (not while a batch records its launches)
+  const bool jac = !precond && L.jac && current_recorder() == nullptr;
+  const cplx<T>* Yop = jac ? level_J<T>(L) : nullptr;
+  cplx<T>* x = jac ? level_JY<T>(L) : x_out;
   const long n = L.per_rhs();
   const long dstride = n * nrhs;
   Buf* w = L.w<T>();
@@ -378,11 +401,12 @@ void level_gcr(Solver& S, int l, int lstop, const cplx<T>* b, cplx<T>* x, int nr
     HIPC(hipMemsetAsync(S.pbar.p, 0, sizeof(unsigned) * nrhs, st));
     {
       ProfScope ps(S, PK_COARSE, l, st);
-      HIPC(launch_gcr16_persistent<T>(L.Y<T>(), L.cgeom(), b, x, r, Zb, Wb, dstride, m, maxiter, tol2, nrhs,
-                                      (int)nb, S.sc.part.as<double>(), S.pbar.as<unsigned>(), S.perr.as<int>(),
+      HIPC(launch_gcr16_persistent<T>(Yop ? Yop : L.Y<T>(), L.cgeom(), b, x, r, Zb, Wb, dstride, m, maxiter, tol2,
+                                      nrhs, (int)nb, S.sc.part.as<double>(), S.pbar.as<unsigned>(), S.perr.as<int>(),
                                       S.piters.as<int>(), st, S.pcoarse_coop));
     }
     S.nC += maxiter;  // upper bound of coarse applications (exact count is per rhs on the device)
+    if (jac) launch_block_apply<T>(x_out, x, level_MI<T>(L), L.V, L.dof, nrhs, st);
     return;
   }
   launch_fill<T>(x, nullptr, n, nrhs, st);
@@ -402,7 +426,7 @@ void level_gcr(Solver& S, int l, int lstop, const cplx<T>* b, cplx<T>* x, int nr
         launch_norm2<T>(r, n, nrhs, S.sc.red(L.gs.rr, flags), st);
         launch_set_flags(flags, S.outer_flags, S.sc.scal.as<double>(), L.gs.rr, L.gs.bb, tol2, nrhs, st);
       }
-      op_apply<T>(S, l, 0, EPI_RESID, x, r, b, nullptr, nrhs, S.sc.red(0, flags), st);
+      op_apply<T>(S, l, 0, EPI_RESID, x, r, b, nullptr, nrhs, S.sc.red(0, flags), st, Yop);
     }
     cplx<T>* Wk = Wb + (long)k * dstride;
     cplx<T>* Zk = Zb + (long)k * dstride;
@@ -416,7 +440,7 @@ void level_gcr(Solver& S, int l, int lstop, const cplx<T>* b, cplx<T>* x, int nr
       {
         ProfScope ps(S, PK_COARSE, l, st);
         CoarseArgs<T> ca;
-        ca.out = Wk; ca.in = z; ca.Y = L.Y<T>(); ca.g = L.cgeom(); ca.nrhs = nrhs; ca.red = S.sc.red(0, flags);
+        ca.out = Wk; ca.in = z; ca.Y = Yop ? Yop : L.Y<T>(); ca.g = L.cgeom(); ca.nrhs = nrhs; ca.red = S.sc.red(0, flags);
         launch_gcr16_apply_dots<T>(ca, r, Wb, dstride, k, L.gs.beta, L.gs.ww, L.gs.alpha, st);
         S.nC += 1;
       }
@@ -432,7 +456,7 @@ void level_gcr(Solver& S, int l, int lstop, const cplx<T>* b, cplx<T>* x, int nr
         vcycle<T>(S, l, lstop, r, Zk, nrhs, st);
         z = Zk;
       }
-      op_apply<T>(S, l, 0, EPI_PLAIN, z, Wk, nullptr, nullptr, nrhs, S.sc.red(0, flags), st);
+      op_apply<T>(S, l, 0, EPI_PLAIN, z, Wk, nullptr, nullptr, nrhs, S.sc.red(0, flags), st, Yop);
       const bool check_here = lag && !(k == 0 && it > 0);
       launch_gcr_dots<T>(Wb, dstride, Wk, r, k, n, nrhs, S.sc.red(0, flags), L.gs.beta, L.gs.ww, L.gs.alpha,
                          check_here ? L.gs.rr : -1, L.gs.bb, tol2, flags, st);
@@ -445,7 +469,7 @@ void level_gcr(Solver& S, int l, int lstop, const cplx<T>* b, cplx<T>* x, int nr
       vcycle<T>(S, l, lstop, r, Zk, nrhs, st);
       op_apply<T>(S, l, 0, EPI_PLAIN, Zk, Wk, nullptr, nullptr, nrhs, S.sc.red(0, flags), st);
     } else {
-      op_apply<T>(S, l, 0, EPI_PLAIN, r, Wk, nullptr, Zk, nrhs, S.sc.red(0, flags), st);
+      op_apply<T>(S, l, 0, EPI_PLAIN, r, Wk, nullptr, Zk, nrhs, S.sc.red(0, flags), st, Yop);
     }
     launch_gcr_mdot<T>(Wb, dstride, Wk, k, n, nrhs, S.sc.red(0, flags), L.gs.beta, L.gs.ww, st);
     launch_gcr_maxpy<T>(Wk, Zk, Wb, Zb, dstride, r, k, n, nrhs, S.sc.red(0, flags), L.gs.beta, L.gs.ww, L.gs.alpha,
@@ -456,6 +480,7 @@ void level_gcr(Solver& S, int l, int lstop, const cplx<T>* b, cplx<T>* x, int nr
     // changes no arithmetic, only how many empty launches are made.
     if (!recording && (it + 1) % check == 0 && it + 1 < maxiter && S.sc.all_flags(L.flag_off, nrhs, st)) break;
   }
+  if (jac) launch_block_apply<T>(x_out, x, level_MI<T>(L), L.V, L.dof, nrhs, st);
 }
 
 template <typename T>
@@ -554,6 +579,38 @@ void build_dense(Solver& S, int l, hipStream_t st) {
   L.dense = true;
 }
 
+// Block-Jacobi data of a coarse level that GCR solves as the coarsest level:
+// M = the inverse of every site's diagonal block and the stencil of A M.
+// A singular diagonal block leaves the level with plain GCR.
+void build_jacobi(Solver& S, int l, hipStream_t st) {
+  Level& L = S.lv[l];
+  L.jac = false;
+  if (!S.p.coarse_jacobi || L.fine || L.dense || !block_jacobi_supported(L.dof)) return;
+  const int ndir = L.ndir();
+  const long per = (long)L.dof_max * L.dof_max;
+  const long n_m = L.V * (long)L.dof * L.dof;
+  const bool f32 = S.p.inner_prec == AMG_F32;
+  L.MI64.ensure(L.V * per * sizeof(double2));
+  L.J64.ensure(L.V * ndir * per * sizeof(double2));
+  if (f32) {
+    L.MI32.ensure(L.V * per * sizeof(float2));
+    L.J32.ensure(L.V * ndir * per * sizeof(float2));
+  }
+  S.jerr.ensure(sizeof(int));
+  int* err = S.jerr.as<int>();
+  HIPC(hipMemsetAsync(err, 0, sizeof(int), st));
+  launch_block_inverse(L.MI64.as<double2>(), L.Y64.as<double2>(), L.V, ndir, L.dof, err, st);
+  launch_jacobi_couplings(L.J64.as<double2>(), L.Y64.as<double2>(), L.MI64.as<double2>(), L.cgeom(), st);
+  if (f32) {
+    launch_p_convert(L.MI32.p, P_F32, L.MI64.as<double2>(), n_m, st);
+    launch_p_convert(L.J32.p, P_F32, L.J64.as<double2>(), n_m * ndir, st);
+  }
+  int herr = 0;
+  HIPC(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPC(hipStreamSynchronize(st));
+  L.jac = herr == 0;
+}
+
 // Build P_l from the first L.nv raw vectors and A_{l+1} = P_l^dag A_l P_l.
 void build_transfer(Solver& S, int l, hipStream_t st) {
   Level& F = S.lv[l];
@@ -640,6 +697,7 @@ void build_transfer(Solver& S, int l, hipStream_t st) {
     launch_p_convert(C.Y32.p, P_F32, C.Y64.as<double2>(), ysz, st);
   }
   build_dense(S, l + 1, st);
+  build_jacobi(S, l + 1, st);
 }
 
 void check_params(const amg_gauge* g, const amg_mg_params* p) {
@@ -653,6 +711,7 @@ void check_params(const amg_gauge* g, const amg_mg_params* p) {
   if (p->inner_prec != AMG_F64 && p->inner_prec != AMG_F32) fail(AMG_ERR_ARG, "bad inner_prec");
   if (p->kcycle_maxiter < 0 || p->kcycle_maxiter > GCR_KMAX) fail(AMG_ERR_ARG, "kcycle_maxiter must be 0..32");
   if (p->kcycle_maxiter > 0 && !(p->kcycle_tol >= 0.0 && std::isfinite(p->kcycle_tol))) fail(AMG_ERR_ARG, "bad kcycle_tol");
+  if (p->coarse_jacobi != 0 && p->coarse_jacobi != 1) fail(AMG_ERR_ARG, "coarse_jacobi must be 0 or 1");
   if (p->coarse_dense_max < 0 || p->coarse_dense_max > AMG_DENSE_MAX)
     fail(AMG_ERR_ARG, "coarse_dense_max must be 0.." + std::to_string(AMG_DENSE_MAX));
   int dims[4];
@@ -1625,6 +1684,7 @@ amg_status amg_solver_set_mass(amg_solver* S, double mass) {
       if (S->p.inner_prec == AMG_F32)
         launch_p_convert(L.Y32.p, P_F32, L.Y64.as<double2>(), L.V * L.ndir() * (long)L.dof * L.dof, nullptr);
       if (L.dense) build_dense(*S, (int)l, nullptr);
+      build_jacobi(*S, (int)l, nullptr);
     }
     HIPC(hipStreamSynchronize(nullptr));
   }

@@ -224,3 +224,40 @@ def test_dense_coarsest_solve_is_exact():
     assert mg.Hierarchy([A, Ac], [P], p).exact == [False, True]
     p.coarse_dense_max -= 1
     assert mg.Hierarchy([A, Ac], [P], p).exact == [False, False]
+
+
+def test_block_jacobi_coarsest_gcr():
+    """The block-Jacobi preconditioned coarsest GCR: on an operator without
+    hops (block diagonal) one step is its exact inverse, site by site (numpy
+    solves of the non-symmetric blocks, so a transposed or conjugated block
+    fails); the first step on a Galerkin operator is the residual minimiser
+    along A M b with M the inverse diagonal blocks; to a tight tolerance it
+    returns the dense solution, not that of A M."""
+    rng = np.random.default_rng(5)
+    V, n = 16, 6
+    diag = 3.0 * np.eye(n) + rng.standard_normal((V, n, n)) + 1j * rng.standard_normal((V, n, n))
+    Ab = mg.Stencil((4, 4), n, diag, np.zeros((4, V, n, n), complex))
+    b = rng.standard_normal((V, n)) + 1j * rng.standard_normal((V, n))
+    pj = mg.MGParams(blocks=[(4, 4)], nvec=[3], coarse_tol=1e-14, coarse_maxiter=1, coarse_jacobi=True)
+    x = mg.coarsest_solve(Ab, b, pj, exact=False)
+    ref = np.stack([np.linalg.solve(diag[s], b[s]) for s in range(V)])
+    assert mg.norm(x - ref) < 1e-13 * mg.norm(ref)
+    x_plain = mg.coarsest_solve(Ab, b, mg.MGParams(blocks=[(4, 4)], nvec=[3], coarse_tol=1e-14, coarse_maxiter=1),
+                                exact=False)
+    assert mg.norm(x_plain - ref) > 1e-2 * mg.norm(ref)
+    # a Galerkin operator with hops
+    U = _field(8, 8, seed=6)
+    A = mg.wilson_stencil(U, 0.05)
+    P = mg.build_prolongator(_vecs(4, A.V, 2, 5), A.dims, (4, 4))
+    Ac = mg.galerkin(A, P)
+    bc = synth.gaussian_field((Ac.V, Ac.dof), synth.rng_for(99, 7))
+    Mb = np.stack([np.linalg.solve(Ac.diag[s], bc[s]) for s in range(Ac.V)])
+    w = Ac.apply(Mb)
+    alpha = mg.vdot(w, bc) / mg.vdot(w, w).real
+    x1 = mg.coarsest_solve(Ac, bc, mg.MGParams(blocks=[(4, 4)], nvec=[4], coarse_tol=0.0, coarse_maxiter=1,
+                                                coarse_jacobi=True), exact=False)
+    assert mg.norm(x1 - alpha * Mb) < 1e-13 * mg.norm(x1)
+    xt = mg.coarsest_solve(Ac, bc, mg.MGParams(blocks=[(4, 4)], nvec=[4], coarse_tol=1e-12, coarse_maxiter=400,
+                                                coarse_restart=16, coarse_jacobi=True), exact=False)
+    xd = mg.dense_solve(Ac, bc)
+    assert mg.norm(xt - xd) < 1e-9 * mg.norm(xd)
