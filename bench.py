@@ -74,7 +74,7 @@ def source():
 # solver parameters shared by the GPU run and the oracle sample
 PARAMS = dict(blocks=[(4, 4), (2, 2)], nvec=[8, 8], nu_pre=2, nu_post=2, omega=0.8,
               coarse_tol=0.2, coarse_maxiter=100, coarse_restart=10, outer_restart=16,
-              kcycle_tol=0.2, kcycle_maxiter=8, coarse_jacobi=True)
+              kcycle_tol=0.2, kcycle_maxiter=8, coarse_jacobi=True, coarse_eo=True)
 
 
 # adaptive setup: nu0 MR steps on the first vector, ncyc error-propagation sweeps per further vector
@@ -129,7 +129,7 @@ class Job:
                     # every kind on every level: per (kind, level) totals
                     if not isinstance(prof, dict):
                         prof = {}
-                    for kind in range(5):
+                    for kind in range(6):
                         for lvl in range(3):
                             ms, n = S.profile_read(kind, lvl)
                             if n:
@@ -742,7 +742,7 @@ def oracle_params():
                        omega=P["omega"], coarse_tol=P["coarse_tol"], coarse_maxiter=P["coarse_maxiter"],
                        coarse_restart=P["coarse_restart"], outer_restart=P["outer_restart"],
                        kcycle_tol=P["kcycle_tol"], kcycle_maxiter=P["kcycle_maxiter"],
-                       coarse_jacobi=P["coarse_jacobi"])
+                       coarse_jacobi=P["coarse_jacobi"], coarse_eo=P["coarse_eo"])
 
 
 def oracle_child(mode: str, path_in: str, path_out: str):
@@ -901,6 +901,13 @@ def coarse16_bytes(Vc):
     return Vc * (5 * 16 * 16 * 8 + 2 * 16 * 8)
 
 
+def eo16_bytes(Vc):
+    """One half-lattice hop of the even-odd coarsest solve (FP32): the four
+    coupling blocks of each of the Vc / 2 sites, its four neighbours' input
+    (each input site read once over the launch) and its output."""
+    return Vc // 2 * (4 * 16 * 16 * 8 + 2 * 16 * 8)
+
+
 # HBM bytes per launch of kernels measured by rocprofv3 counters (FETCH_SIZE and
 # WRITE_SIZE, each scaled by the counter's reading for a plain copy of known
 # size); keyed by (kind, level) of the headline's profile; None when the kernel
@@ -908,6 +915,8 @@ def coarse16_bytes(Vc):
 ROOF_TRAFFIC = {
     # coarse16_kernel<float> on level 2 (1024 sites, plain epilogue): FETCH 4577.9 KiB x 2 + WRITE 111.9 KiB
     (1, 2): 9490125,
+    # coarse16_kernel<float> with the MR sums on level 1 (4096 sites): FETCH 20889.8 KiB x 2 + WRITE 608.0 KiB
+    (4, 1): 43404902,
 }
 # the same for the large-lattice stencils of roofline_hbm (profiles/wilson_stencils_hbm.md)
 STENCIL_TRAFFIC = {
@@ -918,7 +927,7 @@ STENCIL_TRAFFIC = {
 }
 
 PROF_KINDS = {0: "fine Wilson stencil", 1: "coarse block stencil", 2: "restriction", 3: "prolongation",
-              4: "coarse block stencil with the MR sums"}
+              4: "coarse block stencil with the MR sums", 5: "even-odd half-lattice hop"}
 
 
 def main():
@@ -1046,16 +1055,18 @@ def main():
     out["kernel_ms_by_kind"] = {f"{PROF_KINDS[k]}, level {l}": {"ms": round(v[0], 3), "launches": v[1],
                                                                 "avg_us": round(1e3 * v[0] / v[1], 3)}
                                 for (k, l), v in sorted(prof.items())}
-    coarse = {kl: v for kl, v in prof.items() if kl[0] in (1, 4)}
+    coarse = {kl: v for kl, v in prof.items() if kl[0] in (1, 4, 5)}
     kind, lvl = max(coarse, key=lambda kl: coarse[kl][0])
     Vc = (L // 4) ** 2 // (4 ** (lvl - 1))
-    bytes_launch = coarse16_bytes(Vc)
+    bytes_launch = eo16_bytes(Vc) if kind == 5 else coarse16_bytes(Vc)
+    kname = (f"eo16_kernel ({PROF_KINDS[kind]}, level {lvl}: {Vc // 2} of {Vc} sites x 16 dof, FP32)" if kind == 5
+             else f"coarse16_kernel ({PROF_KINDS[kind]}, level {lvl}: {Vc} sites x 16 dof, FP32)")
     avg_s = coarse[(kind, lvl)][0] / coarse[(kind, lvl)][1] * 1e-3
     achieved = bytes_launch / avg_s / 1e9
     traffic = ROOF_TRAFFIC.get((kind, lvl))
     out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                       "kernel": f"coarse16_kernel ({PROF_KINDS[kind]}, level {lvl}: {Vc} sites x 16 dof, FP32)",
+                       "kernel": kname,
                        "bytes_per_launch": bytes_launch, "avg_launch_us": round(avg_s * 1e6, 3),
                        "launches": coarse[(kind, lvl)][1],
                        "cache_resident": True,

@@ -98,6 +98,11 @@ typedef struct {
                          * with the fixed preconditioner z = M r.  A level whose diagonal block is
                          * singular keeps the plain GCR.  Not applied inside batched solves.
                          * Default 0. */
+  int coarse_eo;        /* 1 (with coarse_jacobi, on 2d levels with even extents): that GCR runs on
+                         * the even sites only: with T = D_hat M split by site parity (unit
+                         * diagonal), (1 - T_eo T_oe) y_e = b_e - T_eo b_o to |r_e| <= coarse_tol |b|
+                         * (the odd residual is zero), then y_o = b_o - T_oe y_e and x = M y.
+                         * Default 0. */
 } amg_mg_params;
 
 #define AMG_DENSE_MAX 8192

@@ -430,6 +430,7 @@ class MGParams:
     kcycle_tol: float = None          # intermediate levels: GCR to this tolerance (K-cycle); None: V-cycle
     kcycle_maxiter: int = 8
     coarse_jacobi: bool = False       # coarsest GCR preconditioned by the inverse diagonal blocks (dof <= 32)
+    coarse_eo: bool = False           # with coarse_jacobi on 2d levels of even extents: even-odd reduced GCR
 
 
 @dataclass
@@ -507,8 +508,61 @@ def coarsest_solve(A: Stencil, b: np.ndarray, p: MGParams, exact: bool) -> np.nd
         return dense_solve(A, b)
     precond = None
     if p.coarse_jacobi and A.dof <= 32:
+        if p.coarse_eo and A.nd == 2 and A.dims[0] % 2 == 0 and A.dims[1] % 2 == 0:
+            return eo_jacobi_solve(A, b, p)
         precond = lambda r: block_jacobi(A, r)
     return gcr_coarse(A, b, p.coarse_tol, p.coarse_maxiter, p.coarse_restart, precond=precond)
+
+
+class _SchurOp:
+    """v_e -> v_e - T_eo T_oe v_e for the unit-diagonal operator T = A M."""
+
+    def __init__(self, hops, even, odd, V, dof):
+        self.hops, self.even, self.odd, self.V, self.dof = hops, even, odd, V, dof
+        self.napply = 0
+
+    def embed(self, v, sites):
+        f = np.zeros((self.V, self.dof), dtype=np.complex128)
+        f[sites] = v
+        return f
+
+    def apply(self, v):
+        self.napply += 1
+        t = self.hops(self.embed(v, self.even))[self.odd]            # T_oe v
+        return v - self.hops(self.embed(t, self.odd))[self.even]     # v - T_eo t
+
+
+def eo_jacobi_solve(A: Stencil, b: np.ndarray, p: MGParams) -> np.ndarray:
+    """Coarsest GCR on the even sites of the block-Jacobi preconditioned
+    system: with M the inverse diagonal blocks, T = A M has a unit diagonal;
+    split by site parity, T y = b is (1 - T_eo T_oe) y_e = b_e - T_eo b_o and
+    y_o = b_o - T_oe y_e, and x = M y.  GCR stops when the even residual
+    (the whole residual: the odd part is zero) is at most coarse_tol |b|."""
+    Minv = np.linalg.inv(A.diag)
+    Thop = [A.hop[d] @ Minv[A.nbr[d]] for d in range(2 * A.nd)]      # T(x, x + d) = A_d(x) M(x + d)
+
+    def hops(f):                                                    # (T - 1) f
+        out = np.zeros_like(f)
+        for d in range(2 * A.nd):
+            out += np.einsum("xab,xb->xa", Thop[d], f[A.nbr[d]])
+        return out
+
+    x1 = np.arange(A.V) % A.dims[0]
+    x2 = np.arange(A.V) // A.dims[0]
+    even = np.where((x1 + x2) % 2 == 0)[0]
+    odd = np.where((x1 + x2) % 2 == 1)[0]
+    S = _SchurOp(hops, even, odd, A.V, A.dof)
+    bp = b[even] - hops(S.embed(b[odd], odd))[even]
+    nb, nbp = norm(b), norm(bp)
+    if p.coarse_tol >= 1.0 or nbp == 0.0:
+        ye = np.zeros_like(bp)
+    else:
+        ye = gcr_coarse(S, bp, p.coarse_tol * nb / nbp, p.coarse_maxiter, p.coarse_restart)
+    A.napply += S.napply
+    yo = b[odd] - hops(S.embed(ye, even))[odd]
+    y = np.zeros((A.V, A.dof), dtype=np.complex128)
+    y[even], y[odd] = ye, yo
+    return np.einsum("xab,xb->xa", Minv, y)
 
 
 def block_jacobi(A: Stencil, r: np.ndarray) -> np.ndarray:

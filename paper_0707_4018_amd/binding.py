@@ -41,7 +41,7 @@ class _Params(C.Structure):
         ("coarse_tol", C.c_double), ("coarse_maxiter", C.c_int), ("coarse_restart", C.c_int),
         ("outer_restart", C.c_int), ("inner_prec", C.c_int), ("p_bf16", C.c_int),
         ("kcycle_tol", C.c_double), ("kcycle_maxiter", C.c_int), ("coarse_dense_max", C.c_int),
-        ("coarse_jacobi", C.c_int),
+        ("coarse_jacobi", C.c_int), ("coarse_eo", C.c_int),
     ]
 
 
@@ -226,6 +226,7 @@ class MGParams:
     kcycle_maxiter: int = 0
     coarse_dense_max: int = 4096
     coarse_jacobi: bool = False
+    coarse_eo: bool = False
 
     def to_c(self) -> _Params:
         p = _Params()
@@ -241,6 +242,7 @@ class MGParams:
         p.kcycle_tol, p.kcycle_maxiter = self.kcycle_tol, self.kcycle_maxiter
         p.coarse_dense_max = self.coarse_dense_max
         p.coarse_jacobi = int(self.coarse_jacobi)
+        p.coarse_eo = int(self.coarse_eo)
         return p
 
 

@@ -1335,3 +1335,243 @@ void launch_block_apply(cplx<T>* out, const cplx<T>* in, const cplx<T>* M, long 
 template void launch_block_apply<double>(double2*, const double2*, const double2*, long, int, int, hipStream_t);
 template void launch_block_apply<float>(float2*, const float2*, const float2*, long, int, int, hipStream_t);
 }  // namespace amg
+
+// ---- even-odd reduction of the block-Jacobi preconditioned coarsest level --
+// 2d coarse lattices with even extents.  With T = A M (unit diagonal) split
+// by site parity, T y = b becomes (1 - T_eo T_oe) y_e = b_e - T_eo b_o and
+// y_o = b_o - T_oe y_e.  Half-lattice fields hold the sites of one parity
+// in site order: half index h = s / 2.  Coupling blocks of one parity:
+// C[h][dir][col][row], the coupling of site s(h) to its neighbour in
+// direction dir (dir = 2 mu: +mu, 2 mu + 1: -mu).
+namespace amg {
+namespace {
+__device__ __forceinline__ long eo_site(long h, int L1, int par) {
+  const long y = h / (L1 / 2);
+  const long x = 2 * (h - y * (L1 / 2)) + ((y + par) & 1);
+  return x + y * L1;
+}
+
+__global__ __launch_bounds__(256) void eo_split_kernel(double2* __restrict__ Ce, double2* __restrict__ Co,
+                                                       const double2* __restrict__ T, int L1, int L2, int nc) {
+  const long per = (long)nc * nc;
+  const long Vh = (long)L1 * L2 / 2;
+  const long total = 2 * Vh * 4 * per;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
+    const int par = (int)(i / (Vh * 4 * per));
+    const long rem = i - (long)par * Vh * 4 * per;
+    const long h = rem / (4 * per);
+    const long e = rem - h * 4 * per;  // dir * per + col * nc + row
+    const int dir = (int)(e / per);
+    const long s = eo_site(h, L1, par);
+    (par ? Co : Ce)[rem] = T[(s * 5 + 1 + dir) * per + (e - (long)dir * per)];
+  }
+}
+
+// out(h) = sum_dir C[h][dir] in(nb_dir(s(h)))           (EPI 0)
+//        = b(h) - sum_dir C[h][dir] in(...)            (EPI 1)
+//        = b(h) - b2(h) + sum_dir C[h][dir] in(...)    (EPI 2)
+// for the sites of parity `par`; in, b are half fields (of the other / this
+// parity) or full fields when in_full / b_full.  Thread per (site, row).
+template <typename T>
+struct EoArgs {
+  cplx<T>* out;
+  const cplx<T>* in;
+  const cplx<T>* b;
+  const cplx<T>* b2;
+  const cplx<T>* C;
+  int L1, L2, nc, par, in_full, b_full;
+  int nrhs;
+};
+template <typename T, int EPI>
+__global__ __launch_bounds__(256) void eo_hop_kernel(EoArgs<T> a0, const EoArgs<T>* batch) {
+  AMG_ARGS(EoArgs<T>)
+  const int L1 = a.L1, L2 = a.L2, nc = a.nc;
+  const long Vh = (long)L1 * L2 / 2;
+  const long n = Vh * nc;
+  const int rhs = blockIdx.y;
+  const long oh = (long)rhs * n, of = 2 * oh;
+  const cplx<T>* pin = a.in + (a.in_full ? of : oh);
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const long h = i / nc;
+    const int row = (int)(i - h * nc);
+    const long s = eo_site(h, L1, a.par);
+    const int x = (int)(s % L1), y = (int)(s / L1);
+    long nb[4];
+    nb[0] = (x == L1 - 1) ? s - (L1 - 1) : s + 1;
+    nb[1] = (x == 0) ? s + (L1 - 1) : s - 1;
+    nb[2] = (y == L2 - 1) ? s - (long)(L2 - 1) * L1 : s + L1;
+    nb[3] = (y == 0) ? s + (long)(L2 - 1) * L1 : s - L1;
+    T sr = 0, si = 0;
+    for (int d = 0; d < 4; ++d) {
+      const cplx<T>* Cd = a.C + (h * 4 + d) * (long)nc * nc + row;
+      const cplx<T>* v = pin + (a.in_full ? nb[d] : nb[d] >> 1) * nc;
+      for (int col = 0; col < nc; ++col) {
+        const cplx<T> u = Cd[(long)col * nc], w = v[col];
+        sr += u.x * w.x - u.y * w.y;
+        si += u.x * w.y + u.y * w.x;
+      }
+    }
+    if (EPI == 0) {
+      a.out[oh + i] = mk<T>(sr, si);
+    } else {
+      const cplx<T> bv = a.b[a.b_full ? of + s * nc + row : oh + i];
+      if (EPI == 1) {
+        a.out[oh + i] = mk<T>(bv.x - sr, bv.y - si);
+      } else {
+        const cplx<T> b2v = a.b2[oh + i];
+        a.out[oh + i] = mk<T>(bv.x - b2v.x + sr, bv.y - b2v.y + si);
+      }
+    }
+  }
+}
+
+// The same for N_c = 16 with one wave per site in the lane layout of
+// coarse16_kernel (C16): the loads of all four directions are issued before
+// the first multiply-add, then the partial row sums are reduced across the
+// lanes that share the rows.
+template <typename T, int EPI>
+__global__ __launch_bounds__(256) void eo16_kernel(EoArgs<T> a0, const EoArgs<T>* batch) {
+  AMG_ARGS(EoArgs<T>)
+  using K = C16<T>;
+  const int L1 = a.L1, L2 = a.L2;
+  const long Vh = (long)L1 * L2 / 2;
+  const int rhs = blockIdx.y;
+  const long oh = (long)rhs * Vh * K::NC, of = 2 * oh;
+  gptr<const cplx<T>> __restrict__ pin = gl(a.in) + (a.in_full ? of : oh);
+  gptr<const cplx<T>> __restrict__ C = gl(a.C);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int cg = lane / K::LPC, rg = lane - cg * K::LPC;
+  for (long h = (long)blockIdx.x * 4 + wave; h < Vh; h += (long)gridDim.x * 4) {
+    const long s = eo_site(h, L1, a.par);
+    const int x = (int)(s % L1), y = (int)(s / L1);
+    long nb[4];
+    nb[0] = (x == L1 - 1) ? s - (L1 - 1) : s + 1;
+    nb[1] = (x == 0) ? s + (L1 - 1) : s - 1;
+    nb[2] = (y == L2 - 1) ? s - (long)(L2 - 1) * L1 : s + L1;
+    nb[3] = (y == 0) ? s + (long)(L2 - 1) * L1 : s - L1;
+    // this lane's rows of b and b2 (lanes of column group 0 write the result)
+    cplx<T> bv[K::R], b2v[K::R];
+#pragma unroll
+    for (int i = 0; i < K::R; ++i) {
+      const int row = rg * K::R + i;
+      bv[i] = mk<T>(0, 0);
+      b2v[i] = mk<T>(0, 0);
+      if (cg == 0 && EPI >= 1) bv[i] = a.b[a.b_full ? of + s * K::NC + row : oh + h * K::NC + row];
+      if (cg == 0 && EPI == 2) b2v[i] = a.b2[oh + h * K::NC + row];
+    }
+    gptr<const cplx<T>> __restrict__ Cs = C + h * 4L * K::NC * K::NC + rg * K::R;
+    cplx<T> ev[4][K::NQ], yv[4][K::NQ][K::R];
+#pragma unroll
+    for (int d = 0; d < 4; ++d)
+#pragma unroll
+      for (int q = 0; q < K::NQ; ++q) {
+        const int col = cg + K::CPI * q;
+        ev[d][q] = pin[(a.in_full ? nb[d] : nb[d] >> 1) * K::NC + col];
+#pragma unroll
+        for (int i = 0; i < K::R; ++i) yv[d][q][i] = Cs[(long)d * K::NC * K::NC + col * K::NC + i];
+      }
+    cplx<T> acc[K::R];
+#pragma unroll
+    for (int i = 0; i < K::R; ++i) acc[i] = mk<T>(0, 0);
+#pragma unroll
+    for (int d = 0; d < 4; ++d)
+#pragma unroll
+      for (int q = 0; q < K::NQ; ++q)
+#pragma unroll
+        for (int i = 0; i < K::R; ++i) cfma<T>(acc[i], yv[d][q][i], ev[d][q]);
+#pragma unroll
+    for (int i = 0; i < K::R; ++i) {
+#pragma unroll
+      for (int o = K::LPC; o < 64; o <<= 1) {
+        acc[i].x += __shfl_xor(acc[i].x, o, 64);
+        acc[i].y += __shfl_xor(acc[i].y, o, 64);
+      }
+    }
+    if (cg == 0) {
+#pragma unroll
+      for (int i = 0; i < K::R; ++i) {
+        const int row = rg * K::R + i;
+        cplx<T> v = acc[i];
+        if (EPI == 1) v = mk<T>(bv[i].x - v.x, bv[i].y - v.y);
+        if (EPI == 2) v = mk<T>(bv[i].x - b2v[i].x + v.x, bv[i].y - b2v[i].y + v.y);
+        a.out[oh + h * K::NC + row] = v;
+      }
+    }
+  }
+}
+
+// x(s) = M(s) y(s) with y split into its even and odd half fields
+template <typename T>
+__global__ __launch_bounds__(256) void eo_block_apply_kernel(cplx<T>* __restrict__ x, const cplx<T>* __restrict__ ye,
+                                                             const cplx<T>* __restrict__ yo, const cplx<T>* __restrict__ M,
+                                                             int L1, int L2, int nc) {
+  const long V = (long)L1 * L2;
+  const long n = V * nc;
+  const int rhs = blockIdx.y;
+  const long of = (long)rhs * n, oh = of / 2;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const long s = i / nc;
+    const int row = (int)(i - s * nc);
+    const int par = (int)(((s % L1) + s / L1) & 1);
+    const cplx<T>* v = (par ? yo : ye) + oh + (s >> 1) * nc;
+    const cplx<T>* Ms = M + s * (long)nc * nc + row;
+    T sr = 0, si = 0;
+    for (int col = 0; col < nc; ++col) {
+      const cplx<T> u = Ms[(long)col * nc], w = v[col];
+      sr += u.x * w.x - u.y * w.y;
+      si += u.x * w.y + u.y * w.x;
+    }
+    x[of + i] = mk<T>(sr, si);
+  }
+}
+}  // namespace
+
+bool eo_supported(int nd, const int* dims, int nc) {
+  return nd == 2 && dims[0] % 2 == 0 && dims[1] % 2 == 0 && dims[0] >= 2 && dims[1] >= 2 && nc >= 1 && nc <= 32;
+}
+
+void launch_eo_split(double2* Ce, double2* Co, const double2* T, int L1, int L2, int nc, hipStream_t st) {
+  long nb = ((long)L1 * L2 * 4 * nc * nc + 255) / 256;
+  if (nb > (1L << 20)) nb = 1L << 20;
+  hipLaunchKernelGGL(eo_split_kernel, dim3((unsigned)nb), dim3(256), 0, st, Ce, Co, T, L1, L2, nc);
+}
+
+template <typename T>
+void launch_eo_hop(cplx<T>* out, const cplx<T>* in, const cplx<T>* b, const cplx<T>* b2, const cplx<T>* C, int L1,
+                   int L2, int nc, int par, int in_full, int b_full, int epi, int nrhs, hipStream_t st) {
+  long nb = ((long)L1 * L2 / 2 * nc + 255) / 256;
+  if (nb > (1L << 20)) nb = 1L << 20;
+  const dim3 g((unsigned)nb, (unsigned)nrhs);
+  EoArgs<T> a{out, in, b, b2, C, L1, L2, nc, par, in_full, b_full, nrhs};
+  if (nc == 16) {
+    const long Vh = (long)L1 * L2 / 2;
+    long nw = (Vh + 3) / 4;
+    if (nw > (1L << 20)) nw = 1L << 20;
+    const dim3 g16((unsigned)nw, (unsigned)nrhs);
+    if (epi == 0) dispatch(eo16_kernel<T, 0>, a, g16, dim3(256), st);
+    else if (epi == 1) dispatch(eo16_kernel<T, 1>, a, g16, dim3(256), st);
+    else dispatch(eo16_kernel<T, 2>, a, g16, dim3(256), st);
+    return;
+  }
+  if (epi == 0) dispatch(eo_hop_kernel<T, 0>, a, g, dim3(256), st);
+  else if (epi == 1) dispatch(eo_hop_kernel<T, 1>, a, g, dim3(256), st);
+  else dispatch(eo_hop_kernel<T, 2>, a, g, dim3(256), st);
+}
+template void launch_eo_hop<double>(double2*, const double2*, const double2*, const double2*, const double2*, int, int,
+                                    int, int, int, int, int, int, hipStream_t);
+template void launch_eo_hop<float>(float2*, const float2*, const float2*, const float2*, const float2*, int, int, int,
+                                   int, int, int, int, int, hipStream_t);
+
+template <typename T>
+void launch_eo_block_apply(cplx<T>* x, const cplx<T>* ye, const cplx<T>* yo, const cplx<T>* M, int L1, int L2, int nc,
+                           int nrhs, hipStream_t st) {
+  long nb = ((long)L1 * L2 * nc + 255) / 256;
+  if (nb > (1L << 20)) nb = 1L << 20;
+  hipLaunchKernelGGL(eo_block_apply_kernel<T>, dim3((unsigned)nb, (unsigned)nrhs), dim3(256), 0, st, x, ye, yo, M, L1,
+                     L2, nc);
+}
+template void launch_eo_block_apply<double>(double2*, const double2*, const double2*, const double2*, int, int, int, int,
+                                            hipStream_t);
+template void launch_eo_block_apply<float>(float2*, const float2*, const float2*, const float2*, int, int, int, int,
+                                           hipStream_t);
+}  // namespace amg

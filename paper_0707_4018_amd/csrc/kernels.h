@@ -200,6 +200,17 @@ void launch_block_inverse(double2* Minv, const double2* Y, long V, int ndir, int
 void launch_jacobi_couplings(double2* AM, const double2* Y, const double2* Minv, const CoarseGeom& g, hipStream_t st);
 template <typename T>
 void launch_block_apply(cplx<T>* out, const cplx<T>* in, const cplx<T>* M, long V, int nc, int nrhs, hipStream_t st);
+// even-odd reduction of the block-Jacobi system T = A M on 2d levels with
+// even extents: coupling blocks split by parity, half-lattice hops
+// (epi 0: sum, 1: b - sum, 2: b - b2 + sum) and x = M (y_e, y_o)
+bool eo_supported(int nd, const int* dims, int nc);
+void launch_eo_split(double2* Ce, double2* Co, const double2* T, int L1, int L2, int nc, hipStream_t st);
+template <typename T>
+void launch_eo_hop(cplx<T>* out, const cplx<T>* in, const cplx<T>* b, const cplx<T>* b2, const cplx<T>* C, int L1,
+                   int L2, int nc, int par, int in_full, int b_full, int epi, int nrhs, hipStream_t st);
+template <typename T>
+void launch_eo_block_apply(cplx<T>* x, const cplx<T>* ye, const cplx<T>* yo, const cplx<T>* M, int L1, int L2, int nc,
+                           int nrhs, hipStream_t st);
 void launch_links4d_pack(double2* U64, float2* U32, const double2* canon, long V, hipStream_t st);
 // two-row (12-real) copies of SU(3) links in FP64 and FP32; *not_su3 (zero on
 // entry) becomes nonzero if some link is not unitary with unit determinant to 1e-9

@@ -107,6 +107,11 @@ struct Level {
   // while `jac` is set
   Buf MI64, MI32, J64, J32, JY64, JY32;
   bool jac = false;
+  // even-odd reduction of A M (2d levels with even extents): coupling blocks
+  // of the even and the odd sites, scratch for T_oe z and the reduced
+  // right-hand side; valid while `eo` is set
+  Buf CE64, CO64, CE32, CO32, EO64, EO32;
+  bool eo = false;
   int alloc_nrhs = 0;
   // scalar slots
   int mr_slot = 0;
@@ -139,6 +144,15 @@ template <typename T> const cplx<T>* level_MI(const Level& L) {
 }
 template <typename T> cplx<T>* level_JY(Level& L) {
   return reinterpret_cast<cplx<T>*>(Pick<T>::prec == AMG_F64 ? L.JY64.p : L.JY32.p);
+}
+template <typename T> const cplx<T>* level_CE(const Level& L) {
+  return reinterpret_cast<const cplx<T>*>(Pick<T>::prec == AMG_F64 ? L.CE64.p : L.CE32.p);
+}
+template <typename T> const cplx<T>* level_CO(const Level& L) {
+  return reinterpret_cast<const cplx<T>*>(Pick<T>::prec == AMG_F64 ? L.CO64.p : L.CO32.p);
+}
+template <typename T> cplx<T>* level_EO(Level& L) {
+  return reinterpret_cast<cplx<T>*>(Pick<T>::prec == AMG_F64 ? L.EO64.p : L.EO32.p);
 }
 
 }  // namespace
@@ -196,7 +210,7 @@ namespace {
 
 using Solver = amg_solver;
 
-enum { PK_FINE = 0, PK_COARSE = 1, PK_RESTRICT = 2, PK_PROLONG = 3, PK_COARSE_MR = 4 };
+enum { PK_FINE = 0, PK_COARSE = 1, PK_RESTRICT = 2, PK_PROLONG = 3, PK_COARSE_MR = 4, PK_EO = 5 };
 
 // event pair around one launch when the profiler watches (kind, level)
 struct ProfScope {
@@ -301,7 +315,11 @@ void alloc_level_work(Level& L, int nrhs, int restart, bool coarsest, bool f32) 
     L.Z64.ensure(n * restart * sizeof(double2));
     L.W64.ensure(n * restart * sizeof(double2));
     L.JY64.ensure(n * sizeof(double2));
-    if (f32) L.JY32.ensure(n * sizeof(float2));
+    L.EO64.ensure(n * sizeof(double2));
+    if (f32) {
+      L.JY32.ensure(n * sizeof(float2));
+      L.EO32.ensure(n * sizeof(float2));
+    }
     if (f32) {
       L.Z32.ensure(n * restart * sizeof(float2));
       L.W32.ensure(n * restart * sizeof(float2));
@@ -371,6 +389,72 @@ constexpr int kCoarseCheck = 8;  // unpreconditioned GCR iterations between flag
 template <typename T>
 void vcycle(Solver& S, int l, int lstop, const cplx<T>* b, cplx<T>* x, int nrhs, hipStream_t st);
 
+// ---- coarsest level, even-odd reduced: T = A M (block Jacobi, unit
+// diagonal) split by parity; GCR on (1 - T_eo T_oe) y_e = b_e - T_eo b_o in
+// the three-launch form of level_gcr (the Schur product is two half-lattice
+// launches), then y_o = b_o - T_oe y_e and x = M y.  Stopping test
+// |r_e| <= tol |b| on the full right-hand side: the odd residual is zero.
+template <typename T>
+void eo_gcr(Solver& S, int l, const cplx<T>* b, cplx<T>* x_out, int nrhs, double tol, int maxiter, int m,
+            hipStream_t st) {
+  Level& L = S.lv[l];
+  const int L1 = L.dims[0], L2 = L.dims[1], nc = L.dof;
+  const long n = L.per_rhs(), nh = n / 2;
+  const long dstride = nh * nrhs;
+  cplx<T>* ye = level_JY<T>(L);
+  cplx<T>* yo = ye + dstride;
+  cplx<T>* tmp = level_EO<T>(L);
+  cplx<T>* bp = tmp + dstride;
+  const cplx<T>* Ce = level_CE<T>(L);
+  const cplx<T>* Co = level_CO<T>(L);
+  Buf* w = L.w<T>();
+  cplx<T>* r = w[W_GR].as<cplx<T>>();
+  cplx<T>* Zb = L.template Zd<T>().template as<cplx<T>>();
+  cplx<T>* Wb = L.template Wd<T>().template as<cplx<T>>();
+  int* flags = S.sc.flags.as<int>() + L.flag_off;
+  const double tol2 = tol * tol;
+  auto schur = [&](const cplx<T>* v, cplx<T>* out, const cplx<T>* bb, int epi) {
+    {
+      ProfScope ps(S, PK_EO, l, st);
+      launch_eo_hop<T>(tmp, v, nullptr, nullptr, Co, L1, L2, nc, 1, 0, 0, 0, nrhs, st);  // T_oe v
+    }
+    {
+      ProfScope ps(S, PK_EO, l, st);
+      launch_eo_hop<T>(out, tmp, bb, v, Ce, L1, L2, nc, 0, 0, 0, epi, nrhs, st);
+    }
+    S.nC += 1;
+  };
+  launch_fill<T>(ye, nullptr, nh, nrhs, st);
+  {
+    ProfScope ps(S, PK_EO, l, st);
+    launch_eo_hop<T>(bp, b, b, nullptr, Ce, L1, L2, nc, 0, 1, 1, 1, nrhs, st);  // b_e - T_eo b_o
+  }
+  launch_fill<T>(r, bp, nh, nrhs, st);
+  launch_norm2<T>(b, n, nrhs, S.sc.red(L.gs.bb), st);
+  launch_set_flags(flags, S.outer_flags, S.sc.scal.as<double>(), L.gs.bb, L.gs.bb, tol2 >= 1.0 ? 1.0 : 0.0, nrhs, st);
+  for (int it = 0; it < maxiter; ++it) {
+    const int k = it % m;
+    if (k == 0 && it > 0) {
+      launch_norm2<T>(r, nh, nrhs, S.sc.red(L.gs.rr, flags), st);
+      launch_set_flags(flags, S.outer_flags, S.sc.scal.as<double>(), L.gs.rr, L.gs.bb, tol2, nrhs, st);
+      schur(ye, r, bp, 2);  // r = b' - (y_e - T_eo T_oe y_e)
+    }
+    cplx<T>* Wk = Wb + (long)k * dstride;
+    schur(r, Wk, r, 1);     // w = z - T_eo T_oe z with z = r
+    const bool check_here = !(k == 0 && it > 0);
+    launch_gcr_dots<T>(Wb, dstride, Wk, r, k, nh, nrhs, S.sc.red(0, flags), L.gs.beta, L.gs.ww, L.gs.alpha,
+                       check_here ? L.gs.rr : -1, L.gs.bb, tol2, flags, st);
+    launch_gcr_update2<T>(ye, r, r, Wb, Zb, dstride, k, nh, nrhs, S.sc.red(0, flags), L.gs.beta, L.gs.alpha, -1,
+                          L.gs.bb, tol2, flags, st);
+    if ((it + 1) % kCoarseCheck == 0 && it + 1 < maxiter && S.sc.all_flags(L.flag_off, nrhs, st)) break;
+  }
+  {
+    ProfScope ps(S, PK_EO, l, st);
+    launch_eo_hop<T>(yo, ye, b, nullptr, Co, L1, L2, nc, 1, 0, 1, 1, nrhs, st);  // b_o - T_oe y_e
+  }
+  launch_eo_block_apply<T>(x_out, ye, yo, level_MI<T>(L), L1, L2, nc, nrhs, st);
+}
+
 // ---- GCR on level l with restarts, stopping per rhs on the recursive
 // residual |r| <= tol |b| (device flags; later launches become no-ops).
 // precond = false: the coarsest-level solve (z = r);
@@ -382,6 +466,10 @@ void level_gcr(Solver& S, int l, int lstop, const cplx<T>* b, cplx<T>* x_out, in
   // coarsest level with block-Jacobi preconditioning: GCR on (A M) y = b,
   // then x = M y (not while a batch records its launches)
   const bool jac = !precond && L.jac && current_recorder() == nullptr;
+  if (jac && L.eo) {
+    eo_gcr<T>(S, l, b, x_out, nrhs, tol, maxiter, m, st);
+    return;
+  }
   const cplx<T>* Yop = jac ? level_J<T>(L) : nullptr;
   cplx<T>* x = jac ? level_JY<T>(L) : x_out;
   const long n = L.per_rhs();
@@ -585,6 +673,7 @@ void build_dense(Solver& S, int l, hipStream_t st) {
 void build_jacobi(Solver& S, int l, hipStream_t st) {
   Level& L = S.lv[l];
   L.jac = false;
+  L.eo = false;
   if (!S.p.coarse_jacobi || L.fine || L.dense || !block_jacobi_supported(L.dof)) return;
   const int ndir = L.ndir();
   const long per = (long)L.dof_max * L.dof_max;
@@ -605,10 +694,25 @@ void build_jacobi(Solver& S, int l, hipStream_t st) {
     launch_p_convert(L.MI32.p, P_F32, L.MI64.as<double2>(), n_m, st);
     launch_p_convert(L.J32.p, P_F32, L.J64.as<double2>(), n_m * ndir, st);
   }
+  L.eo = false;
+  if (S.p.coarse_eo && eo_supported(L.nd, L.dims, L.dof)) {
+    const long csz = L.V * 2 * (long)L.dof_max * L.dof_max;  // half the sites x 4 directions
+    L.CE64.ensure(csz * sizeof(double2));
+    L.CO64.ensure(csz * sizeof(double2));
+    launch_eo_split(L.CE64.as<double2>(), L.CO64.as<double2>(), L.J64.as<double2>(), L.dims[0], L.dims[1], L.dof, st);
+    if (f32) {
+      L.CE32.ensure(csz * sizeof(float2));
+      L.CO32.ensure(csz * sizeof(float2));
+      const long nsplit = L.V * 2 * (long)L.dof * L.dof;
+      launch_p_convert(L.CE32.p, P_F32, L.CE64.as<double2>(), nsplit, st);
+      launch_p_convert(L.CO32.p, P_F32, L.CO64.as<double2>(), nsplit, st);
+    }
+  }
   int herr = 0;
   HIPC(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPC(hipStreamSynchronize(st));
   L.jac = herr == 0;
+  L.eo = L.jac && S.p.coarse_eo && eo_supported(L.nd, L.dims, L.dof);
 }
 
 // Build P_l from the first L.nv raw vectors and A_{l+1} = P_l^dag A_l P_l.
@@ -712,6 +816,8 @@ void check_params(const amg_gauge* g, const amg_mg_params* p) {
   if (p->kcycle_maxiter < 0 || p->kcycle_maxiter > GCR_KMAX) fail(AMG_ERR_ARG, "kcycle_maxiter must be 0..32");
   if (p->kcycle_maxiter > 0 && !(p->kcycle_tol >= 0.0 && std::isfinite(p->kcycle_tol))) fail(AMG_ERR_ARG, "bad kcycle_tol");
   if (p->coarse_jacobi != 0 && p->coarse_jacobi != 1) fail(AMG_ERR_ARG, "coarse_jacobi must be 0 or 1");
+  if (p->coarse_eo != 0 && p->coarse_eo != 1) fail(AMG_ERR_ARG, "coarse_eo must be 0 or 1");
+  if (p->coarse_eo && !p->coarse_jacobi) fail(AMG_ERR_ARG, "coarse_eo needs coarse_jacobi");
   if (p->coarse_dense_max < 0 || p->coarse_dense_max > AMG_DENSE_MAX)
     fail(AMG_ERR_ARG, "coarse_dense_max must be 0.." + std::to_string(AMG_DENSE_MAX));
   int dims[4];
@@ -1321,6 +1427,8 @@ void amg_default_params(amg_mg_params* p) {
   p->kcycle_tol = 0.1;
   p->kcycle_maxiter = 0;
   p->coarse_dense_max = 4096;
+  p->coarse_jacobi = 0;
+  p->coarse_eo = 0;
 }
 
 amg_status amg_gauge_create(const amg_lattice* lat, const void* dev_links, double mass, void* stream,

@@ -113,19 +113,22 @@ def test_vcycle_matches_oracle(blocks, nvec, kc, dense):
     assert rel_err(x, xo) < 1e-10
 
 
+@pytest.mark.parametrize("eo", [False, True])
 @pytest.mark.parametrize("blocks,nvec,kc", [([(4, 4)], [6], 0), ([(4, 4), (2, 2)], [4, 4], 3),
                                             ([(4, 4), (2, 2)], [4, 8], 0)])
-def test_vcycle_block_jacobi_matches_oracle(blocks, nvec, kc):
+def test_vcycle_block_jacobi_matches_oracle(blocks, nvec, kc, eo):
     """The coarsest GCR right-preconditioned by the inverse diagonal blocks
     (12 steps, restart 5, no dense solve) on both sides: the HIP path runs GCR
     on the stencil of A M and returns M y.  Again after a mass change, which
-    rebuilds the block inverses and that stencil.  (On the 4^2 coarsest levels
-    of the three-level cases 12 steps solve to rounding with or without the
-    preconditioner; the two-level case's 8^2 x 12 level shows that it acts.)"""
-    print(f"vcycle block-jacobi {blocks} {nvec} kcycle {kc}", flush=True)
+    rebuilds the block inverses and that stencil.  eo: GCR on the even sites
+    of the reduced system (two half-lattice launches per step), then the odd
+    sites and M y.  (On the 4^2 coarsest levels of the three-level cases 12
+    steps solve to rounding with or without the preconditioner; the two-level
+    case's 8^2 x 12 level shows that it acts.)"""
+    print(f"vcycle block-jacobi {blocks} {nvec} kcycle {kc} eo {eo}", flush=True)
     kw = dict(coarse_tol=0.0, coarse_maxiter=12, coarse_restart=5, kcycle_tol=0.0 if kc else None,
               kcycle_maxiter=kc if kc else 8, coarse_dense_max=0)
-    U, A, H, g, S = _given(32, 32, blocks, nvec, m=0.02, coarse_jacobi=True, **kw)
+    U, A, H, g, S = _given(32, 32, blocks, nvec, m=0.02, coarse_jacobi=True, coarse_eo=eo, **kw)
     b = synth.gaussian_field((1, A.V, 2, 1), synth.rng_for(9))
     x = host(S.vcycle(dev(b)))[0].reshape(A.V, 2)
     xo = mg.vcycle(H, 0, b[0].reshape(A.V, 2))
@@ -141,9 +144,10 @@ def test_vcycle_block_jacobi_matches_oracle(blocks, nvec, kc):
 
 def test_mixed_solve_block_jacobi_near_critical():
     """Three-level mixed-precision solve near the critical mass with the
-    block-Jacobi coarsest GCR: true FP64 residual 1e-10, iteration count
-    within two of the oracle's with the same preconditioning, and fewer
-    coarse-stencil applications than without it."""
+    block-Jacobi coarsest GCR, with and without the even-odd reduction: true
+    FP64 residual 1e-10, iteration count within two of the oracle's with the
+    same coarsest solver, and fewer coarse operator applications (a reduced
+    Schur product counted as one) than without each."""
     import paper_0707_4018_amd as amg
     print("mixed solve with block-jacobi coarsest GCR, 32^2", flush=True)
     L = 32
@@ -155,19 +159,20 @@ def test_mixed_solve_block_jacobi_near_critical():
     init = [vectors(8, A.V, 2, 81), vectors(8, (L // 4) ** 2, 16, 82)]
     b = synth.gaussian_field((1, A.V, 2, 1), synth.rng_for(83))
     res = {}
-    for jac in (False, True):
-        po, pg = _params([(4, 4), (2, 2)], [8, 8], coarse_jacobi=jac, **kw)
+    for jac, eo in ((False, False), (True, False), (True, True)):
+        po, pg = _params([(4, 4), (2, 2)], [8, 8], coarse_jacobi=jac, coarse_eo=eo, **kw)
         pg.inner_prec, pg.p_bf16 = amg.F32, True
         S = amg.Solver(amg.Gauge(dev(U), m), pg, init=[dev(v) for v in init], nu0=20, ncyc=4)
         psi, info = S.solve(dev(b), tol=1e-10)
         r = mg.norm(b[0].reshape(A.V, 2) - A.apply(host(psi)[0].reshape(A.V, 2))) / mg.norm(b)
-        assert info[0].converged and r <= 1e-10, (jac, r)
-        res[jac] = info[0]
+        assert info[0].converged and r <= 1e-10, (jac, eo, r)
+        res[jac, eo] = info[0]
         if jac:
             Ho, _ = mg.adaptive_setup(A, po, init, nu0=20, ncyc=4)
             _, io = mg.mg_solve(Ho, b[0].reshape(A.V, 2), 1e-10, 200)
-            assert abs(info[0].iters - io.iters) <= 2, (info[0].iters, io.iters)
-    assert res[True].n_coarse < res[False].n_coarse, (res[True].n_coarse, res[False].n_coarse)
+            assert abs(info[0].iters - io.iters) <= 2, (eo, info[0].iters, io.iters)
+    n = {k: v.n_coarse for k, v in res.items()}
+    assert n[True, False] < n[False, False] and n[True, True] < n[True, False], n
 
 
 def _mcrit(U):

@@ -261,3 +261,51 @@ def test_block_jacobi_coarsest_gcr():
                                                 coarse_restart=16, coarse_jacobi=True), exact=False)
     xd = mg.dense_solve(Ac, bc)
     assert mg.norm(xt - xd) < 1e-9 * mg.norm(xd)
+
+
+def test_even_odd_coarsest_solve():
+    """The even-odd reduced coarsest GCR: its Schur operator equals
+    1 - T_eo T_oe taken from the sparse matrix of T = A M (M the inverse
+    diagonal blocks, so T_ee = T_oo = 1); to a tight tolerance it returns the
+    dense solution; the residual of a loose solve is at most coarse_tol |b|
+    and lies on the even sites only."""
+    import scipy.sparse as sp
+    U = _field(16, 16, seed=8)
+    A = mg.wilson_stencil(U, 0.05)
+    P = mg.build_prolongator(_vecs(4, A.V, 2, 7), A.dims, (2, 2))
+    Ac = mg.galerkin(A, P)                                   # 8 x 8 coarse sites, 8 dof
+    n = Ac.dof
+    Minv = np.linalg.inv(Ac.diag)
+    T = (Ac.to_sparse() @ sp.block_diag(list(Minv), format="csr")).toarray()
+    x1 = np.arange(Ac.V) % Ac.dims[0]
+    x2 = np.arange(Ac.V) // Ac.dims[0]
+    ev = np.where((x1 + x2) % 2 == 0)[0]
+    od = np.where((x1 + x2) % 2 == 1)[0]
+    ie = (ev[:, None] * n + np.arange(n)).ravel()
+    io = (od[:, None] * n + np.arange(n)).ravel()
+    assert np.allclose(T[np.ix_(ie, ie)], np.eye(len(ie)), atol=1e-13)
+    Sd = np.eye(len(ie)) - T[np.ix_(ie, io)] @ T[np.ix_(io, ie)]
+    b = synth.gaussian_field((Ac.V, n), synth.rng_for(99, 8))
+    # the operator the solver builds, reached through one GCR step from x = 0
+    seen = {}
+    orig = mg.gcr_coarse
+
+    def spy(op, rhs, *a, **k):
+        seen["op"] = op
+        return orig(op, rhs, *a, **k)
+    mg.gcr_coarse = spy
+    try:
+        p = mg.MGParams(blocks=[(2, 2)], nvec=[4], coarse_tol=1e-12, coarse_maxiter=500, coarse_restart=32,
+                        coarse_jacobi=True, coarse_eo=True)
+        xt = mg.coarsest_solve(Ac, b, p, exact=False)
+    finally:
+        mg.gcr_coarse = orig
+    v = synth.gaussian_field((len(ev), n), synth.rng_for(99, 9))
+    assert np.linalg.norm(seen["op"].apply(v).ravel() - Sd @ v.ravel()) < 1e-12 * np.linalg.norm(v)
+    xd = mg.dense_solve(Ac, b)
+    assert mg.norm(xt - xd) < 1e-9 * mg.norm(xd)
+    p.coarse_tol = 0.2
+    xl = mg.coarsest_solve(Ac, b, p, exact=False)
+    r = b - Ac.apply(xl)
+    assert mg.norm(r) <= 0.2 * mg.norm(b) * (1 + 1e-12)
+    assert mg.norm(r[od]) < 1e-12 * mg.norm(b)
