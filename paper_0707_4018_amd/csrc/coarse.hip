@@ -1382,7 +1382,9 @@ struct EoArgs {
   int L1, L2, nc, par, in_full, b_full;
   int nrhs;
 };
-template <typename T, int EPI>
+// NCM > 0: nc <= NCM, every load of a direction issued at once (clamped
+// column, surplus terms skipped); NCM = 0: any nc up to 32, one column at a time
+template <typename T, int EPI, int NCM>
 __global__ __launch_bounds__(256) void eo_hop_kernel(EoArgs<T> a0, const EoArgs<T>* batch) {
   AMG_ARGS(EoArgs<T>)
   const int L1 = a.L1, L2 = a.L2, nc = a.nc;
@@ -1402,13 +1404,31 @@ __global__ __launch_bounds__(256) void eo_hop_kernel(EoArgs<T> a0, const EoArgs<
     nb[2] = (y == L2 - 1) ? s - (long)(L2 - 1) * L1 : s + L1;
     nb[3] = (y == 0) ? s + (long)(L2 - 1) * L1 : s - L1;
     T sr = 0, si = 0;
+#pragma unroll 1
     for (int d = 0; d < 4; ++d) {
       const cplx<T>* Cd = a.C + (h * 4 + d) * (long)nc * nc + row;
       const cplx<T>* v = pin + (a.in_full ? nb[d] : nb[d] >> 1) * nc;
-      for (int col = 0; col < nc; ++col) {
-        const cplx<T> u = Cd[(long)col * nc], w = v[col];
-        sr += u.x * w.x - u.y * w.y;
-        si += u.x * w.y + u.y * w.x;
+      if (NCM > 0) {
+        cplx<T> cu[NCM > 0 ? NCM : 1], cw[NCM > 0 ? NCM : 1];
+#pragma unroll
+        for (int col = 0; col < NCM; ++col) {
+          const int c = col < nc ? col : nc - 1;
+          cu[col] = Cd[(long)c * nc];
+          cw[col] = v[c];
+        }
+#pragma unroll
+        for (int col = 0; col < NCM; ++col) {
+          if (col < nc) {
+            sr += cu[col].x * cw[col].x - cu[col].y * cw[col].y;
+            si += cu[col].x * cw[col].y + cu[col].y * cw[col].x;
+          }
+        }
+      } else {
+        for (int col = 0; col < nc; ++col) {
+          const cplx<T> u = Cd[(long)col * nc], w = v[col];
+          sr += u.x * w.x - u.y * w.y;
+          si += u.x * w.y + u.y * w.x;
+        }
       }
     }
     if (EPI == 0) {
@@ -1501,7 +1521,8 @@ __global__ __launch_bounds__(256) void eo16_kernel(EoArgs<T> a0, const EoArgs<T>
 }
 
 // x(s) = M(s) y(s) with y split into its even and odd half fields
-template <typename T>
+// (NCM > 0: nc <= NCM, all loads of a row issued at once)
+template <typename T, int NCM>
 __global__ __launch_bounds__(256) void eo_block_apply_kernel(cplx<T>* __restrict__ x, const cplx<T>* __restrict__ ye,
                                                              const cplx<T>* __restrict__ yo, const cplx<T>* __restrict__ M,
                                                              int L1, int L2, int nc) {
@@ -1516,10 +1537,27 @@ __global__ __launch_bounds__(256) void eo_block_apply_kernel(cplx<T>* __restrict
     const cplx<T>* v = (par ? yo : ye) + oh + (s >> 1) * nc;
     const cplx<T>* Ms = M + s * (long)nc * nc + row;
     T sr = 0, si = 0;
-    for (int col = 0; col < nc; ++col) {
-      const cplx<T> u = Ms[(long)col * nc], w = v[col];
-      sr += u.x * w.x - u.y * w.y;
-      si += u.x * w.y + u.y * w.x;
+    if (NCM > 0) {
+      cplx<T> cu[NCM > 0 ? NCM : 1], cw[NCM > 0 ? NCM : 1];
+#pragma unroll
+      for (int col = 0; col < NCM; ++col) {
+        const int c = col < nc ? col : nc - 1;
+        cu[col] = Ms[(long)c * nc];
+        cw[col] = v[c];
+      }
+#pragma unroll
+      for (int col = 0; col < NCM; ++col) {
+        if (col < nc) {
+          sr += cu[col].x * cw[col].x - cu[col].y * cw[col].y;
+          si += cu[col].x * cw[col].y + cu[col].y * cw[col].x;
+        }
+      }
+    } else {
+      for (int col = 0; col < nc; ++col) {
+        const cplx<T> u = Ms[(long)col * nc], w = v[col];
+        sr += u.x * w.x - u.y * w.y;
+        si += u.x * w.y + u.y * w.x;
+      }
     }
     x[of + i] = mk<T>(sr, si);
   }
@@ -1553,9 +1591,15 @@ void launch_eo_hop(cplx<T>* out, const cplx<T>* in, const cplx<T>* b, const cplx
     else dispatch(eo16_kernel<T, 2>, a, g16, dim3(256), st);
     return;
   }
-  if (epi == 0) dispatch(eo_hop_kernel<T, 0>, a, g, dim3(256), st);
-  else if (epi == 1) dispatch(eo_hop_kernel<T, 1>, a, g, dim3(256), st);
-  else dispatch(eo_hop_kernel<T, 2>, a, g, dim3(256), st);
+  if (nc <= 16) {
+    if (epi == 0) dispatch(eo_hop_kernel<T, 0, 16>, a, g, dim3(256), st);
+    else if (epi == 1) dispatch(eo_hop_kernel<T, 1, 16>, a, g, dim3(256), st);
+    else dispatch(eo_hop_kernel<T, 2, 16>, a, g, dim3(256), st);
+    return;
+  }
+  if (epi == 0) dispatch(eo_hop_kernel<T, 0, 0>, a, g, dim3(256), st);
+  else if (epi == 1) dispatch(eo_hop_kernel<T, 1, 0>, a, g, dim3(256), st);
+  else dispatch(eo_hop_kernel<T, 2, 0>, a, g, dim3(256), st);
 }
 template void launch_eo_hop<double>(double2*, const double2*, const double2*, const double2*, const double2*, int, int,
                                     int, int, int, int, int, int, hipStream_t);
@@ -1567,8 +1611,12 @@ void launch_eo_block_apply(cplx<T>* x, const cplx<T>* ye, const cplx<T>* yo, con
                            int nrhs, hipStream_t st) {
   long nb = ((long)L1 * L2 * nc + 255) / 256;
   if (nb > (1L << 20)) nb = 1L << 20;
-  hipLaunchKernelGGL(eo_block_apply_kernel<T>, dim3((unsigned)nb, (unsigned)nrhs), dim3(256), 0, st, x, ye, yo, M, L1,
-                     L2, nc);
+  if (nc <= 16)
+    hipLaunchKernelGGL((eo_block_apply_kernel<T, 16>), dim3((unsigned)nb, (unsigned)nrhs), dim3(256), 0, st, x, ye, yo,
+                       M, L1, L2, nc);
+  else
+    hipLaunchKernelGGL((eo_block_apply_kernel<T, 0>), dim3((unsigned)nb, (unsigned)nrhs), dim3(256), 0, st, x, ye, yo,
+                       M, L1, L2, nc);
 }
 template void launch_eo_block_apply<double>(double2*, const double2*, const double2*, const double2*, int, int, int, int,
                                             hipStream_t);
