@@ -565,7 +565,7 @@ class Batch:
         lib.amg_batch_tuning(self._h, n, caps, mr, ms)
         return {"red_block_cap": cap.value, "coarse_mrhs_mfma": bool(mrhs.value),
                 "launches_per_outer_step": stages.value,
-                "tuning": [{"red_block_cap": caps[i], "coarse_mrhs_mfma": bool(mr[i]), "ms_per_outer_step": round(ms[i], 4)}
+                "tuning": [{"red_block_cap": caps[i], "coarse_mrhs_mfma": bool(mr[i]), "ms_per_outer_step": ms[i]}
                            for i in range(n)]}
 
     def solve(self, chis, tol: float = 1e-10, max_iter: int = 1000, raise_noconv: bool = True):

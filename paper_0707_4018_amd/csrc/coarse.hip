@@ -1382,8 +1382,10 @@ struct EoArgs {
   int L1, L2, nc, par, in_full, b_full;
   int nrhs;
 };
-// NCM > 0: nc <= NCM, every load of a direction issued at once (clamped
-// column, surplus terms skipped); NCM = 0: any nc up to 32, one column at a time
+// NCM > 0: nc <= NCM; four adjacent lanes take the four directions of one
+// row, each issuing all loads of its direction at once (clamped column,
+// surplus terms skipped), and add their sums with two lane exchanges.
+// NCM = 0: any nc up to 32, one thread per row, one column at a time.
 template <typename T, int EPI, int NCM>
 __global__ __launch_bounds__(256) void eo_hop_kernel(EoArgs<T> a0, const EoArgs<T>* batch) {
   AMG_ARGS(EoArgs<T>)
@@ -1393,7 +1395,11 @@ __global__ __launch_bounds__(256) void eo_hop_kernel(EoArgs<T> a0, const EoArgs<
   const int rhs = blockIdx.y;
   const long oh = (long)rhs * n, of = 2 * oh;
   const cplx<T>* pin = a.in + (a.in_full ? of : oh);
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+  constexpr int LPR = NCM > 0 ? 4 : 1;  // lanes per row
+  // the stride is a multiple of 64, so the lanes of a row stay in one wave
+  for (long j = (long)blockIdx.x * blockDim.x + threadIdx.x; j < n * LPR; j += (long)gridDim.x * blockDim.x) {
+    const long i = j / LPR;
+    const int dl = (int)(j - i * LPR);
     const long h = i / nc;
     const int row = (int)(i - h * nc);
     const long s = eo_site(h, L1, a.par);
@@ -1404,26 +1410,33 @@ __global__ __launch_bounds__(256) void eo_hop_kernel(EoArgs<T> a0, const EoArgs<
     nb[2] = (y == L2 - 1) ? s - (long)(L2 - 1) * L1 : s + L1;
     nb[3] = (y == 0) ? s + (long)(L2 - 1) * L1 : s - L1;
     T sr = 0, si = 0;
-#pragma unroll 1
-    for (int d = 0; d < 4; ++d) {
-      const cplx<T>* Cd = a.C + (h * 4 + d) * (long)nc * nc + row;
-      const cplx<T>* v = pin + (a.in_full ? nb[d] : nb[d] >> 1) * nc;
-      if (NCM > 0) {
-        cplx<T> cu[NCM > 0 ? NCM : 1], cw[NCM > 0 ? NCM : 1];
+    if (NCM > 0) {
+      const long nbd = dl == 0 ? nb[0] : dl == 1 ? nb[1] : dl == 2 ? nb[2] : nb[3];
+      const cplx<T>* Cd = a.C + (h * 4 + dl) * (long)nc * nc + row;
+      const cplx<T>* v = pin + (a.in_full ? nbd : nbd >> 1) * nc;
+      cplx<T> cu[NCM > 0 ? NCM : 1], cw[NCM > 0 ? NCM : 1];
 #pragma unroll
-        for (int col = 0; col < NCM; ++col) {
-          const int c = col < nc ? col : nc - 1;
-          cu[col] = Cd[(long)c * nc];
-          cw[col] = v[c];
-        }
+      for (int col = 0; col < NCM; ++col) {
+        const int c = col < nc ? col : nc - 1;
+        cu[col] = Cd[(long)c * nc];
+        cw[col] = v[c];
+      }
 #pragma unroll
-        for (int col = 0; col < NCM; ++col) {
-          if (col < nc) {
-            sr += cu[col].x * cw[col].x - cu[col].y * cw[col].y;
-            si += cu[col].x * cw[col].y + cu[col].y * cw[col].x;
-          }
+      for (int col = 0; col < NCM; ++col) {
+        if (col < nc) {
+          sr += cu[col].x * cw[col].x - cu[col].y * cw[col].y;
+          si += cu[col].x * cw[col].y + cu[col].y * cw[col].x;
         }
-      } else {
+      }
+      sr += __shfl_xor(sr, 1, 64);
+      si += __shfl_xor(si, 1, 64);
+      sr += __shfl_xor(sr, 2, 64);
+      si += __shfl_xor(si, 2, 64);
+      if (dl != 0) continue;
+    } else {
+      for (int d = 0; d < 4; ++d) {
+        const cplx<T>* Cd = a.C + (h * 4 + d) * (long)nc * nc + row;
+        const cplx<T>* v = pin + (a.in_full ? nb[d] : nb[d] >> 1) * nc;
         for (int col = 0; col < nc; ++col) {
           const cplx<T> u = Cd[(long)col * nc], w = v[col];
           sr += u.x * w.x - u.y * w.y;
@@ -1577,7 +1590,7 @@ void launch_eo_split(double2* Ce, double2* Co, const double2* T, int L1, int L2,
 template <typename T>
 void launch_eo_hop(cplx<T>* out, const cplx<T>* in, const cplx<T>* b, const cplx<T>* b2, const cplx<T>* C, int L1,
                    int L2, int nc, int par, int in_full, int b_full, int epi, int nrhs, hipStream_t st) {
-  long nb = ((long)L1 * L2 / 2 * nc + 255) / 256;
+  long nb = ((long)L1 * L2 / 2 * nc * (nc <= 16 ? 4 : 1) + 255) / 256;
   if (nb > (1L << 20)) nb = 1L << 20;
   const dim3 g((unsigned)nb, (unsigned)nrhs);
   EoArgs<T> a{out, in, b, b2, C, L1, L2, nc, par, in_full, b_full, nrhs};
