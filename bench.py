@@ -915,11 +915,11 @@ def eo16_bytes(Vc):
 ROOF_TRAFFIC = {
     # coarse16_kernel<float> on level 2 (1024 sites, plain epilogue): FETCH 4577.9 KiB x 2 + WRITE 111.9 KiB
     (1, 2): 9490125,
-    # coarse16_kernel<float> with the MR sums on level 1 (4096 sites): FETCH 20888.0 KiB x 2 + WRITE 608.0 KiB
-    (4, 1): 43401216,
+    # coarse16_kernel<float> with the MR sums on level 1 (4096 sites): FETCH 20893.5 KiB x 2 + WRITE 608.0 KiB
+    (4, 1): 43412480,
     # eo16_kernel<float> on level 2 (512 sites a launch), launch-weighted over its two epilogues:
-    # b - sum (27372 launches) FETCH 2183.0 KiB x 2 + WRITE 64 KiB, sum (21960) FETCH 2148.9 KiB x 2 + WRITE 64 KiB
-    (5, 2): 4505232,
+    # b - sum (27372 launches) FETCH 2181.0 KiB x 2 + WRITE 64 KiB, sum (21960) FETCH 2148.9 KiB x 2 + WRITE 64 KiB
+    (5, 2): 4502960,
 }
 # the same for the large-lattice stencils of roofline_hbm (profiles/wilson_stencils_hbm.md)
 STENCIL_TRAFFIC = {
