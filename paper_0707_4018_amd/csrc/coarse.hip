@@ -1211,18 +1211,28 @@ __global__ __launch_bounds__(64) void block_inverse_kernel(double2* __restrict__
   }
   __syncthreads();
   for (int c = 0; c < nc; ++c) {
-    if (lane == 0) {
-      int p = c;
-      double best = -1.0;
-      for (int r = c; r < nc; ++r) {
-        const double m = a[r][c].x * a[r][c].x + a[r][c].y * a[r][c].y;
-        if (m > best) { best = m; p = r; }
+    {
+      // pivot: the largest |a[r][c]| over r >= c (lowest r among equals),
+      // a max-reduction over the lanes, one row each
+      double m = -1.0;
+      int p = nc;
+      if (lane >= c && lane < nc) {
+        m = a[lane][c].x * a[lane][c].x + a[lane][c].y * a[lane][c].y;
+        p = lane;
       }
-      if (!(best > 0.0)) {
-        atomicOr(err, 1);
-        p = -1;
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) {
+        const double mo = __shfl_xor(m, o, 64);
+        const int po = __shfl_xor(p, o, 64);
+        if (mo > m || (mo == m && po < p)) { m = mo; p = po; }
       }
-      piv = p;
+      if (lane == 0) {
+        if (!(m > 0.0)) {
+          atomicOr(err, 1);
+          p = -1;
+        }
+        piv = p;
+      }
     }
     __syncthreads();
     const int p = piv;
@@ -1604,12 +1614,17 @@ void launch_eo_hop(cplx<T>* out, const cplx<T>* in, const cplx<T>* b, const cplx
     else dispatch(eo16_kernel<T, 2>, a, g16, dim3(256), st);
     return;
   }
-  if (nc <= 16) {
-    if (epi == 0) dispatch(eo_hop_kernel<T, 0, 16>, a, g, dim3(256), st);
-    else if (epi == 1) dispatch(eo_hop_kernel<T, 1, 16>, a, g, dim3(256), st);
-    else dispatch(eo_hop_kernel<T, 2, 16>, a, g, dim3(256), st);
-    return;
+#define AMG_EOH(NCM)                                                         \
+  {                                                                          \
+    if (epi == 0) dispatch(eo_hop_kernel<T, 0, NCM>, a, g, dim3(256), st);   \
+    else if (epi == 1) dispatch(eo_hop_kernel<T, 1, NCM>, a, g, dim3(256), st); \
+    else dispatch(eo_hop_kernel<T, 2, NCM>, a, g, dim3(256), st);            \
+    return;                                                                  \
   }
+  if (nc <= 4) AMG_EOH(4)
+  if (nc <= 8) AMG_EOH(8)
+  if (nc <= 16) AMG_EOH(16)
+#undef AMG_EOH
   if (epi == 0) dispatch(eo_hop_kernel<T, 0, 0>, a, g, dim3(256), st);
   else if (epi == 1) dispatch(eo_hop_kernel<T, 1, 0>, a, g, dim3(256), st);
   else dispatch(eo_hop_kernel<T, 2, 0>, a, g, dim3(256), st);
