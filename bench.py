@@ -402,7 +402,8 @@ def wilson4d_bench(amg, torch, U0):
            "setup": f"{W4_RELAX} MR steps on D v = 0 for each random vector"}
     res = {}
     p = amg.MGParams(blocks=[(4, 4, 4, 4)], nvec=[24], nu_pre=W4_NU, nu_post=W4_NU, omega=0.8, coarse_tol=0.1,
-                     coarse_maxiter=100, coarse_restart=16, outer_restart=8, inner_prec=amg.F32, p_bf16=True)
+                     coarse_maxiter=100, coarse_restart=16, outer_restart=8, inner_prec=amg.F32, p_bf16=True,
+                     coarse_jacobi=W4_JACOBI)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     S = amg.Solver.refined(g, p, init[0], nu_ref=W4_RELAX)
@@ -461,6 +462,7 @@ def wilson4d_bench(amg, torch, U0):
 
 
 W4_RELAX = 20
+W4_JACOBI = True                   # coarsest GCR on the block-Jacobi preconditioned system (48 x 48 blocks)
 W4_GAP_NEAR = 0.03                 # (CGNR needs ~15000 iterations here; at 0.01 it has not converged after 30000)
 
 

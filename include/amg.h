@@ -92,7 +92,7 @@ typedef struct {
                          * use GCR (coarse_tol, coarse_maxiter, coarse_restart).  Default 4096.
                          * Batched solves (amg_batch_create) use GCR on every instance. */
   int coarse_jacobi;    /* 1: the coarsest GCR (where not dense) is right-preconditioned by the
-                         * inverse M of each coarse site's diagonal block (levels of at most 32 dof
+                         * inverse M of each coarse site's diagonal block (levels of at most 48 dof
                          * per site): GCR runs on the stencil of D_hat M, built at setup and after
                          * a mass change, and the result is M y.  Its iterates are those of GCR
                          * with the fixed preconditioner z = M r.  A level whose diagonal block is

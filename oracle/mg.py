@@ -429,7 +429,7 @@ class MGParams:
     smoother: object = None           # callable(A, b, nu, omega) -> (x, r); MR when None
     kcycle_tol: float = None          # intermediate levels: GCR to this tolerance (K-cycle); None: V-cycle
     kcycle_maxiter: int = 8
-    coarse_jacobi: bool = False       # coarsest GCR preconditioned by the inverse diagonal blocks (dof <= 32)
+    coarse_jacobi: bool = False       # coarsest GCR preconditioned by the inverse diagonal blocks (dof <= 48)
     coarse_eo: bool = False           # with coarse_jacobi on 2d levels of even extents: even-odd reduced GCR
 
 
@@ -507,7 +507,7 @@ def coarsest_solve(A: Stencil, b: np.ndarray, p: MGParams, exact: bool) -> np.nd
     if exact:
         return dense_solve(A, b)
     precond = None
-    if p.coarse_jacobi and A.dof <= 32:
+    if p.coarse_jacobi and A.dof <= 48:
         if p.coarse_eo and A.nd == 2 and A.dims[0] % 2 == 0 and A.dims[1] % 2 == 0:
             return eo_jacobi_solve(A, b, p)
         precond = lambda r: block_jacobi(A, r)

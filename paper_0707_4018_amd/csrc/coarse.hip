@@ -1191,14 +1191,16 @@ void launch_p_export(double2* out, const void* P, int pkind, const TransferGeom&
 // z = M r.  Blocks keep the stencil's column-major [col][row] order.
 namespace amg {
 namespace {
-constexpr int BINV_MAX = 32;
+constexpr int BINV_MAX = 48;
 
-// one wave per site: Gauss-Jordan with partial pivoting on [A_0 | 1] in LDS;
-// err[0] is set when a pivot column is zero (the block is singular)
+// one wave per site: Gauss-Jordan with partial pivoting on [A_0 | 1] in LDS
+// (nc <= BM: 32 KB for BM = 32, 72 KB for BM = 48, the 4d levels); err[0]
+// is set when a pivot column is zero (the block is singular)
+template <int BM>
 __global__ __launch_bounds__(64) void block_inverse_kernel(double2* __restrict__ Minv, const double2* __restrict__ Y,
                                                            long V, int ndir, int nc, int* err) {
-  __shared__ double2 a[BINV_MAX][2 * BINV_MAX];
-  __shared__ double2 fac[BINV_MAX];
+  __shared__ double2 a[BM][2 * BM];
+  __shared__ double2 fac[BM];
   __shared__ int piv;
   const long site = blockIdx.x;
   if (site >= V) return;
@@ -1327,7 +1329,10 @@ __global__ __launch_bounds__(256) void block_apply_kernel(cplx<T>* __restrict__ 
 bool block_jacobi_supported(int nc) { return nc >= 1 && nc <= BINV_MAX; }
 
 void launch_block_inverse(double2* Minv, const double2* Y, long V, int ndir, int nc, int* err, hipStream_t st) {
-  hipLaunchKernelGGL(block_inverse_kernel, dim3((unsigned)V), dim3(64), 0, st, Minv, Y, V, ndir, nc, err);
+  if (nc <= 32)
+    hipLaunchKernelGGL(block_inverse_kernel<32>, dim3((unsigned)V), dim3(64), 0, st, Minv, Y, V, ndir, nc, err);
+  else
+    hipLaunchKernelGGL(block_inverse_kernel<48>, dim3((unsigned)V), dim3(64), 0, st, Minv, Y, V, ndir, nc, err);
 }
 
 void launch_jacobi_couplings(double2* AM, const double2* Y, const double2* Minv, const CoarseGeom& g, hipStream_t st) {

@@ -192,7 +192,7 @@ void launch_axpy(cplx<T>* y, const cplx<T>* x, double are, double aim, long n, i
 template <typename T>
 void launch_scale_inv_norm(cplx<T>* v, const double* nn, long n, int nrhs, hipStream_t st);
 void launch_diag_shift(double2* Y, const double2* M, long V, int nc, int ndir, double dm, hipStream_t st);
-// right block-Jacobi preconditioning of a coarse level (nc <= 32): Minv = the
+// right block-Jacobi preconditioning of a coarse level (nc <= 48): Minv = the
 // inverse of each site's diagonal block (err[0] set if one is singular), AM =
 // the stencil of A M, and out = M in
 bool block_jacobi_supported(int nc);

@@ -689,6 +689,7 @@ void build_jacobi(Solver& S, int l, hipStream_t st) {
   int* err = S.jerr.as<int>();
   HIPC(hipMemsetAsync(err, 0, sizeof(int), st));
   launch_block_inverse(L.MI64.as<double2>(), L.Y64.as<double2>(), L.V, ndir, L.dof, err, st);
+  HIPC(hipGetLastError());  // (the 48-wide kernel takes 72 KB of LDS per block)
   launch_jacobi_couplings(L.J64.as<double2>(), L.Y64.as<double2>(), L.MI64.as<double2>(), L.cgeom(), st);
   if (f32) {
     launch_p_convert(L.MI32.p, P_F32, L.MI64.as<double2>(), n_m, st);
