@@ -129,7 +129,7 @@ class Job:
                     # every kind on every level: per (kind, level) totals
                     if not isinstance(prof, dict):
                         prof = {}
-                    for kind in range(6):
+                    for kind in range(7):
                         for lvl in range(3):
                             ms, n = S.profile_read(kind, lvl)
                             if n:
@@ -903,6 +903,12 @@ def coarse16_bytes(Vc):
     return Vc * (5 * 16 * 16 * 8 + 2 * 16 * 8)
 
 
+def eo_s9_bytes(Vc):
+    """One product with the even-odd reduced operator (FP32): the nine
+    blocks of each of the Vc / 2 even sites, its input and its output."""
+    return Vc // 2 * (9 * 16 * 16 * 8 + 2 * 16 * 8)
+
+
 def eo16_bytes(Vc):
     """One half-lattice hop of the even-odd coarsest solve (FP32): the four
     coupling blocks of each of the Vc / 2 sites, its four neighbours' input
@@ -915,13 +921,14 @@ def eo16_bytes(Vc):
 # size); keyed by (kind, level) of the headline's profile; None when the kernel
 # has changed since the counters were taken
 ROOF_TRAFFIC = {
-    # coarse16_kernel<float> on level 2 (1024 sites, plain epilogue): FETCH 4577.9 KiB x 2 + WRITE 111.9 KiB
-    (1, 2): 9490125,
-    # coarse16_kernel<float> with the MR sums on level 1 (4096 sites): FETCH 20893.5 KiB x 2 + WRITE 608.0 KiB
-    (4, 1): 43412480,
-    # eo16_kernel<float> on level 2 (512 sites a launch), launch-weighted over its two epilogues:
-    # b - sum (27372 launches) FETCH 2181.0 KiB x 2 + WRITE 64 KiB, sum (21960) FETCH 2148.9 KiB x 2 + WRITE 64 KiB
-    (5, 2): 4502960,
+    # coarse16_kernel<float> with the MR sums on level 1 (4096 sites): FETCH 20890.1 KiB x 2 + WRITE 608.0 KiB
+    (4, 1): 43405517,
+    # eo16_kernel<float> on level 2 (512 sites a launch; the reduced right-hand side and the odd sites):
+    # FETCH 2188.5 KiB x 2 + WRITE 64 KiB
+    (5, 2): 4547584,
+    # eo_s9_kernel<float> on level 2 (512 even sites), launch-weighted over its two epilogues:
+    # sum (21936 launches) FETCH 4726.4 KiB x 2 + WRITE 64 KiB, b - sum (24) FETCH 4767.0 KiB x 2 + WRITE 64 KiB
+    (6, 2): 9745294,
 }
 # the same for the large-lattice stencils of roofline_hbm (profiles/wilson_stencils_hbm.md)
 STENCIL_TRAFFIC = {
@@ -932,7 +939,8 @@ STENCIL_TRAFFIC = {
 }
 
 PROF_KINDS = {0: "fine Wilson stencil", 1: "coarse block stencil", 2: "restriction", 3: "prolongation",
-              4: "coarse block stencil with the MR sums", 5: "even-odd half-lattice hop"}
+              4: "coarse block stencil with the MR sums", 5: "even-odd half-lattice hop",
+              6: "even-odd reduced operator (9-point stencil of the even sites)"}
 
 
 def main():
@@ -1060,12 +1068,13 @@ def main():
     out["kernel_ms_by_kind"] = {f"{PROF_KINDS[k]}, level {l}": {"ms": round(v[0], 3), "launches": v[1],
                                                                 "avg_us": round(1e3 * v[0] / v[1], 3)}
                                 for (k, l), v in sorted(prof.items())}
-    coarse = {kl: v for kl, v in prof.items() if kl[0] in (1, 4, 5)}
+    coarse = {kl: v for kl, v in prof.items() if kl[0] in (1, 4, 5, 6)}
     kind, lvl = max(coarse, key=lambda kl: coarse[kl][0])
     Vc = (L // 4) ** 2 // (4 ** (lvl - 1))
-    bytes_launch = eo16_bytes(Vc) if kind == 5 else coarse16_bytes(Vc)
-    kname = (f"eo16_kernel ({PROF_KINDS[kind]}, level {lvl}: {Vc // 2} of {Vc} sites x 16 dof, FP32)" if kind == 5
-             else f"coarse16_kernel ({PROF_KINDS[kind]}, level {lvl}: {Vc} sites x 16 dof, FP32)")
+    bytes_launch = {5: eo16_bytes, 6: eo_s9_bytes}.get(kind, coarse16_bytes)(Vc)
+    kname = {5: f"eo16_kernel ({PROF_KINDS[kind]}, level {lvl}: {Vc // 2} of {Vc} sites x 16 dof, FP32)",
+             6: f"eo_s9_kernel ({PROF_KINDS[kind]}, level {lvl}: {Vc // 2} of {Vc} sites x 16 dof, FP32)"}.get(
+        kind, f"coarse16_kernel ({PROF_KINDS[kind]}, level {lvl}: {Vc} sites x 16 dof, FP32)")
     avg_s = coarse[(kind, lvl)][0] / coarse[(kind, lvl)][1] * 1e-3
     achieved = bytes_launch / avg_s / 1e9
     traffic = ROOF_TRAFFIC.get((kind, lvl))

@@ -315,7 +315,8 @@ amg_status amg_batch_destroy(amg_batch* b);
  * synchronises on the last event and returns the summed kernel time and the
  * number of launches since enabling.  kind: 0 fine Wilson stencil, 1 coarse
  * block stencil, 2 restriction, 3 prolongation (level = the fine side),
- * 4 coarse block stencil with the MR epilogue only. */
+ * 4 coarse block stencil with the MR epilogue only, 5 even-odd half-lattice
+ * hop, 6 even-odd reduced operator (9-point stencil of the even sites). */
 amg_status amg_profile_enable(amg_solver* s, int kind, int level, int enable);
 amg_status amg_profile_read(amg_solver* s, double* total_ms, long long* launches);
 /* kind = -1 and / or level = -1 in amg_profile_enable time every kind / level

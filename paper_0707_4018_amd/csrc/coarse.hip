@@ -1548,6 +1548,131 @@ __global__ __launch_bounds__(256) void eo16_kernel(EoArgs<T> a0, const EoArgs<T>
   }
 }
 
+// The reduced operator 1 - T_eo T_oe as a stencil on the even sites: the
+// two-hop paths from an even site end on the site itself, at (+-2, 0),
+// (0, +-2) or (+-1, +-1).  Offsets k = 0: (0, 0), 1: (2, 0), 2: (-2, 0),
+// 3: (0, 2), 4: (0, -2), 5: (1, 1), 6: (1, -1), 7: (-1, 1), 8: (-1, -1);
+// S_k(x) = [k = 0] 1 - sum over the paths (d1, d2) of offset k of
+// T_eo(x, d1) T_oe(x + d1, d2), directions d = 0: +x, 1: -x, 2: +y, 3: -y.
+// Blocks [h][k][col][row] (FP64), thread per entry.
+__constant__ int kS9Paths[9][4][2] = {
+    {{0, 1}, {1, 0}, {2, 3}, {3, 2}}, {{0, 0}, {-1, -1}, {-1, -1}, {-1, -1}}, {{1, 1}, {-1, -1}, {-1, -1}, {-1, -1}},
+    {{2, 2}, {-1, -1}, {-1, -1}, {-1, -1}}, {{3, 3}, {-1, -1}, {-1, -1}, {-1, -1}}, {{0, 2}, {2, 0}, {-1, -1}, {-1, -1}},
+    {{0, 3}, {3, 0}, {-1, -1}, {-1, -1}}, {{1, 2}, {2, 1}, {-1, -1}, {-1, -1}}, {{1, 3}, {3, 1}, {-1, -1}, {-1, -1}}};
+
+__device__ __forceinline__ long nb2d(long s, int L1, int L2, int d) {
+  const int x = (int)(s % L1), y = (int)(s / L1);
+  if (d == 0) return (x == L1 - 1) ? s - (L1 - 1) : s + 1;
+  if (d == 1) return (x == 0) ? s + (L1 - 1) : s - 1;
+  if (d == 2) return (y == L2 - 1) ? s - (long)(L2 - 1) * L1 : s + L1;
+  return (y == 0) ? s + (long)(L2 - 1) * L1 : s - L1;
+}
+
+__global__ __launch_bounds__(256) void eo_schur_build_kernel(double2* __restrict__ S9, const double2* __restrict__ Ce,
+                                                             const double2* __restrict__ Co, int L1, int L2, int nc) {
+  const long per = (long)nc * nc;
+  const long Vh = (long)L1 * L2 / 2;
+  const long total = Vh * 9 * per;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
+    const long h = i / (9 * per);
+    const long rem = i - h * 9 * per;
+    const int k = (int)(rem / per);
+    const int col = (int)((rem - (long)k * per) / nc), row = (int)(rem - (long)k * per - (long)col * nc);
+    const long s = eo_site(h, L1, 0);
+    double sr = (k == 0 && row == col) ? 1.0 : 0.0, si = 0.0;
+    for (int p = 0; p < 4; ++p) {
+      const int d1 = kS9Paths[k][p][0], d2 = kS9Paths[k][p][1];
+      if (d1 < 0) break;
+      const long ho = nb2d(s, L1, L2, d1) >> 1;  // the odd site between
+      const double2* A = Ce + (h * 4 + d1) * per;    // [m][row]
+      const double2* B = Co + (ho * 4 + d2) * per;   // [col][m]
+      for (int m = 0; m < nc; ++m) {
+        const double2 u = A[(long)m * nc + row], v = B[(long)col * nc + m];
+        sr -= u.x * v.x - u.y * v.y;
+        si -= u.x * v.y + u.y * v.x;
+      }
+    }
+    S9[i] = make_double2(sr, si);
+  }
+}
+
+// out(h) = sum_k S_k(h) in(h + offset_k)            (EPI 0)
+//        = b(h) - sum_k S_k(h) in(h + offset_k)     (EPI 1)
+// on the even half field, N_c = 16, one wave per site (C16 lane layout).
+template <typename T, int EPI>
+__global__ __launch_bounds__(256) void eo_s9_kernel(EoArgs<T> a0, const EoArgs<T>* batch) {
+  AMG_ARGS(EoArgs<T>)
+  using K = C16<T>;
+  const int L1 = a.L1, L2 = a.L2;
+  const long Vh = (long)L1 * L2 / 2;
+  const int rhs = blockIdx.y;
+  const long oh = (long)rhs * Vh * K::NC;
+  gptr<const cplx<T>> __restrict__ pin = gl(a.in) + oh;
+  gptr<const cplx<T>> __restrict__ C = gl(a.C);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int cg = lane / K::LPC, rg = lane - cg * K::LPC;
+  for (long h = (long)blockIdx.x * 4 + wave; h < Vh; h += (long)gridDim.x * 4) {
+    const long s = eo_site(h, L1, 0);
+    const int x = (int)(s % L1), y = (int)(s / L1);
+    const int xp = x + 1 == L1 ? 0 : x + 1, xm = x == 0 ? L1 - 1 : x - 1;
+    const int yp = y + 1 == L2 ? 0 : y + 1, ym = y == 0 ? L2 - 1 : y - 1;
+    const int xpp = xp + 1 == L1 ? 0 : xp + 1, xmm = xm == 0 ? L1 - 1 : xm - 1;
+    const int ypp = yp + 1 == L2 ? 0 : yp + 1, ymm = ym == 0 ? L2 - 1 : ym - 1;
+    long nb[9];
+    nb[0] = s;
+    nb[1] = xpp + (long)y * L1;
+    nb[2] = xmm + (long)y * L1;
+    nb[3] = x + (long)ypp * L1;
+    nb[4] = x + (long)ymm * L1;
+    nb[5] = xp + (long)yp * L1;
+    nb[6] = xp + (long)ym * L1;
+    nb[7] = xm + (long)yp * L1;
+    nb[8] = xm + (long)ym * L1;
+    cplx<T> bv[K::R];
+#pragma unroll
+    for (int i = 0; i < K::R; ++i) {
+      bv[i] = mk<T>(0, 0);
+      if (cg == 0 && EPI == 1) bv[i] = a.b[oh + h * K::NC + rg * K::R + i];
+    }
+    gptr<const cplx<T>> __restrict__ Cs = C + h * 9L * K::NC * K::NC + rg * K::R;
+    cplx<T> ev[9][K::NQ], yv[9][K::NQ][K::R];
+#pragma unroll
+    for (int k = 0; k < 9; ++k)
+#pragma unroll
+      for (int q = 0; q < K::NQ; ++q) {
+        const int col = cg + K::CPI * q;
+        ev[k][q] = pin[(nb[k] >> 1) * K::NC + col];
+#pragma unroll
+        for (int i = 0; i < K::R; ++i) yv[k][q][i] = Cs[(long)k * K::NC * K::NC + col * K::NC + i];
+      }
+    cplx<T> acc[K::R];
+#pragma unroll
+    for (int i = 0; i < K::R; ++i) acc[i] = mk<T>(0, 0);
+#pragma unroll
+    for (int k = 0; k < 9; ++k)
+#pragma unroll
+      for (int q = 0; q < K::NQ; ++q)
+#pragma unroll
+        for (int i = 0; i < K::R; ++i) cfma<T>(acc[i], yv[k][q][i], ev[k][q]);
+#pragma unroll
+    for (int i = 0; i < K::R; ++i) {
+#pragma unroll
+      for (int o = K::LPC; o < 64; o <<= 1) {
+        acc[i].x += __shfl_xor(acc[i].x, o, 64);
+        acc[i].y += __shfl_xor(acc[i].y, o, 64);
+      }
+    }
+    if (cg == 0) {
+#pragma unroll
+      for (int i = 0; i < K::R; ++i) {
+        cplx<T> v = acc[i];
+        if (EPI == 1) v = mk<T>(bv[i].x - v.x, bv[i].y - v.y);
+        a.out[oh + h * K::NC + rg * K::R + i] = v;
+      }
+    }
+  }
+}
+
 // x(s) = M(s) y(s) with y split into its even and odd half fields
 // (NCM > 0: nc <= NCM, all loads of a row issued at once)
 template <typename T, int NCM>
@@ -1638,6 +1763,28 @@ template void launch_eo_hop<double>(double2*, const double2*, const double2*, co
                                     int, int, int, int, int, int, hipStream_t);
 template void launch_eo_hop<float>(float2*, const float2*, const float2*, const float2*, const float2*, int, int, int,
                                    int, int, int, int, int, hipStream_t);
+
+void launch_eo_schur_build(double2* S9, const double2* Ce, const double2* Co, int L1, int L2, int nc, hipStream_t st) {
+  long nb = ((long)L1 * L2 / 2 * 9 * nc * nc + 255) / 256;
+  if (nb > (1L << 20)) nb = 1L << 20;
+  hipLaunchKernelGGL(eo_schur_build_kernel, dim3((unsigned)nb), dim3(256), 0, st, S9, Ce, Co, L1, L2, nc);
+}
+
+template <typename T>
+void launch_eo_s9(cplx<T>* out, const cplx<T>* in, const cplx<T>* b, const cplx<T>* S9, int L1, int L2, int epi,
+                  int nrhs, hipStream_t st) {
+  const long Vh = (long)L1 * L2 / 2;
+  long nw = (Vh + 3) / 4;
+  if (nw > (1L << 20)) nw = 1L << 20;
+  const dim3 g((unsigned)nw, (unsigned)nrhs);
+  EoArgs<T> a{out, in, b, nullptr, S9, L1, L2, 16, 0, 0, 0, nrhs};
+  if (epi == 0) dispatch(eo_s9_kernel<T, 0>, a, g, dim3(256), st);
+  else dispatch(eo_s9_kernel<T, 1>, a, g, dim3(256), st);
+}
+template void launch_eo_s9<double>(double2*, const double2*, const double2*, const double2*, int, int, int, int,
+                                   hipStream_t);
+template void launch_eo_s9<float>(float2*, const float2*, const float2*, const float2*, int, int, int, int,
+                                  hipStream_t);
 
 template <typename T>
 void launch_eo_block_apply(cplx<T>* x, const cplx<T>* ye, const cplx<T>* yo, const cplx<T>* M, int L1, int L2, int nc,

@@ -208,6 +208,13 @@ void launch_eo_split(double2* Ce, double2* Co, const double2* T, int L1, int L2,
 template <typename T>
 void launch_eo_hop(cplx<T>* out, const cplx<T>* in, const cplx<T>* b, const cplx<T>* b2, const cplx<T>* C, int L1,
                    int L2, int nc, int par, int in_full, int b_full, int epi, int nrhs, hipStream_t st);
+// the reduced operator 1 - T_eo T_oe as a 9-point stencil of the even sites
+// (blocks [h][9][col][row], FP64 from the FP64 couplings) and its apply for
+// N_c = 16 (epi 0: sum, 1: b - sum)
+void launch_eo_schur_build(double2* S9, const double2* Ce, const double2* Co, int L1, int L2, int nc, hipStream_t st);
+template <typename T>
+void launch_eo_s9(cplx<T>* out, const cplx<T>* in, const cplx<T>* b, const cplx<T>* S9, int L1, int L2, int epi,
+                  int nrhs, hipStream_t st);
 template <typename T>
 void launch_eo_block_apply(cplx<T>* x, const cplx<T>* ye, const cplx<T>* yo, const cplx<T>* M, int L1, int L2, int nc,
                            int nrhs, hipStream_t st);

@@ -112,6 +112,10 @@ struct Level {
   // right-hand side; valid while `eo` is set
   Buf CE64, CO64, CE32, CO32, EO64, EO32;
   bool eo = false;
+  // with 16 dof also the reduced operator as a 9-point stencil of the even
+  // sites (one launch per product instead of two)
+  Buf SE64, SE32;
+  bool s9 = false;
   int alloc_nrhs = 0;
   // scalar slots
   int mr_slot = 0;
@@ -150,6 +154,9 @@ template <typename T> const cplx<T>* level_CE(const Level& L) {
 }
 template <typename T> const cplx<T>* level_CO(const Level& L) {
   return reinterpret_cast<const cplx<T>*>(Pick<T>::prec == AMG_F64 ? L.CO64.p : L.CO32.p);
+}
+template <typename T> const cplx<T>* level_SE(const Level& L) {
+  return reinterpret_cast<const cplx<T>*>(Pick<T>::prec == AMG_F64 ? L.SE64.p : L.SE32.p);
 }
 template <typename T> cplx<T>* level_EO(Level& L) {
   return reinterpret_cast<cplx<T>*>(Pick<T>::prec == AMG_F64 ? L.EO64.p : L.EO32.p);
@@ -210,7 +217,7 @@ namespace {
 
 using Solver = amg_solver;
 
-enum { PK_FINE = 0, PK_COARSE = 1, PK_RESTRICT = 2, PK_PROLONG = 3, PK_COARSE_MR = 4, PK_EO = 5 };
+enum { PK_FINE = 0, PK_COARSE = 1, PK_RESTRICT = 2, PK_PROLONG = 3, PK_COARSE_MR = 4, PK_EO = 5, PK_EO_S9 = 6 };
 
 // event pair around one launch when the profiler watches (kind, level)
 struct ProfScope {
@@ -413,7 +420,14 @@ void eo_gcr(Solver& S, int l, const cplx<T>* b, cplx<T>* x_out, int nrhs, double
   cplx<T>* Wb = L.template Wd<T>().template as<cplx<T>>();
   int* flags = S.sc.flags.as<int>() + L.flag_off;
   const double tol2 = tol * tol;
+  // out = S v (epi 1) or bb - S v (epi 2), S = 1 - T_eo T_oe
   auto schur = [&](const cplx<T>* v, cplx<T>* out, const cplx<T>* bb, int epi) {
+    if (L.s9) {
+      ProfScope ps(S, PK_EO_S9, l, st);
+      launch_eo_s9<T>(out, v, bb, level_SE<T>(L), L1, L2, epi == 2 ? 1 : 0, nrhs, st);
+      S.nC += 1;
+      return;
+    }
     {
       ProfScope ps(S, PK_EO, l, st);
       launch_eo_hop<T>(tmp, v, nullptr, nullptr, Co, L1, L2, nc, 1, 0, 0, 0, nrhs, st);  // T_oe v
@@ -437,10 +451,10 @@ void eo_gcr(Solver& S, int l, const cplx<T>* b, cplx<T>* x_out, int nrhs, double
     if (k == 0 && it > 0) {
       launch_norm2<T>(r, nh, nrhs, S.sc.red(L.gs.rr, flags), st);
       launch_set_flags(flags, S.outer_flags, S.sc.scal.as<double>(), L.gs.rr, L.gs.bb, tol2, nrhs, st);
-      schur(ye, r, bp, 2);  // r = b' - (y_e - T_eo T_oe y_e)
+      schur(ye, r, bp, 2);  // r = b' - S y_e
     }
     cplx<T>* Wk = Wb + (long)k * dstride;
-    schur(r, Wk, r, 1);     // w = z - T_eo T_oe z with z = r
+    schur(r, Wk, r, 1);     // w = S z with z = r
     const bool check_here = !(k == 0 && it > 0);
     launch_gcr_dots<T>(Wb, dstride, Wk, r, k, nh, nrhs, S.sc.red(0, flags), L.gs.beta, L.gs.ww, L.gs.alpha,
                        check_here ? L.gs.rr : -1, L.gs.bb, tol2, flags, st);
@@ -674,6 +688,7 @@ void build_jacobi(Solver& S, int l, hipStream_t st) {
   Level& L = S.lv[l];
   L.jac = false;
   L.eo = false;
+  L.s9 = false;
   if (!S.p.coarse_jacobi || L.fine || L.dense || !block_jacobi_supported(L.dof)) return;
   const int ndir = L.ndir();
   const long per = (long)L.dof_max * L.dof_max;
@@ -708,12 +723,23 @@ void build_jacobi(Solver& S, int l, hipStream_t st) {
       launch_p_convert(L.CE32.p, P_F32, L.CE64.as<double2>(), nsplit, st);
       launch_p_convert(L.CO32.p, P_F32, L.CO64.as<double2>(), nsplit, st);
     }
+    if (L.dof == 16) {
+      const long ssz = L.V / 2 * 9 * 256;
+      L.SE64.ensure(ssz * sizeof(double2));
+      launch_eo_schur_build(L.SE64.as<double2>(), L.CE64.as<double2>(), L.CO64.as<double2>(), L.dims[0], L.dims[1],
+                            16, st);
+      if (f32) {
+        L.SE32.ensure(ssz * sizeof(float2));
+        launch_p_convert(L.SE32.p, P_F32, L.SE64.as<double2>(), ssz, st);
+      }
+    }
   }
   int herr = 0;
   HIPC(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPC(hipStreamSynchronize(st));
   L.jac = herr == 0;
   L.eo = L.jac && S.p.coarse_eo && eo_supported(L.nd, L.dims, L.dof);
+  L.s9 = L.eo && L.dof == 16;
 }
 
 // Build P_l from the first L.nv raw vectors and A_{l+1} = P_l^dag A_l P_l.
@@ -2012,7 +2038,7 @@ amg_status amg_mr(amg_solver* S, int level, int prec, int nu, const void* dev_b,
 amg_status amg_profile_enable(amg_solver* S, int kind, int level, int enable) {
   AMG_TRY
   check_ptr(S, "solver");
-  if (kind < -1 || kind > 4 || level < -1 || level >= (int)S->lv.size()) fail(AMG_ERR_ARG, "bad kind / level");
+  if (kind < -1 || kind > 6 || level < -1 || level >= (int)S->lv.size()) fail(AMG_ERR_ARG, "bad kind / level");
   S->prof.on = enable != 0;
   S->prof.kind = kind;
   S->prof.level = level;
