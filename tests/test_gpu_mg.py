@@ -609,3 +609,21 @@ def test_four_dimensional_block_jacobi_vcycle_matches_oracle(nv):
     psi, info = S2.solve(dev(b), tol=1e-10)
     res = mg.norm(b[0].reshape(A.V, 12) - A.apply(host(psi)[0].reshape(A.V, 12))) / mg.norm(b)
     assert info[0].converged and res <= 1e-10
+
+
+def test_even_odd_option_edges():
+    """coarse_eo without coarse_jacobi is rejected; a coarse lattice with odd
+    extents (20^2 / 4^2 = 5^2) keeps the block-Jacobi GCR without the
+    reduction, like the oracle, and the cycle still matches it."""
+    import paper_0707_4018_amd as amg
+    print("even-odd option edges", flush=True)
+    U = u1_config(20, 20, seed=4)
+    _, pg = _params([(4, 4)], [4], coarse_eo=True)
+    with pytest.raises(amg.AMGError) as e:
+        amg.Solver(amg.Gauge(dev(U), 0.05), pg, nullvecs=[dev(vectors(4, 400, 2, 3))])
+    assert e.value.status == 1
+    U, A, H, g, S = _given(20, 20, [(4, 4)], [4], m=0.05, coarse_tol=0.0, coarse_maxiter=8, coarse_restart=4,
+                           coarse_dense_max=0, coarse_jacobi=True, coarse_eo=True)
+    b = synth.gaussian_field((1, A.V, 2, 1), synth.rng_for(14))
+    x = host(S.vcycle(dev(b)))[0].reshape(A.V, 2)
+    assert rel_err(x, mg.vcycle(H, 0, b[0].reshape(A.V, 2))) < 1e-10
