@@ -398,9 +398,10 @@ void vcycle(Solver& S, int l, int lstop, const cplx<T>* b, cplx<T>* x, int nrhs,
 
 // ---- coarsest level, even-odd reduced: T = A M (block Jacobi, unit
 // diagonal) split by parity; GCR on (1 - T_eo T_oe) y_e = b_e - T_eo b_o in
-// the three-launch form of level_gcr (the Schur product is two half-lattice
-// launches), then y_o = b_o - T_oe y_e and x = M y.  Stopping test
-// |r_e| <= tol |b| on the full right-hand side: the odd residual is zero.
+// the three-launch form of level_gcr (the product with the reduced operator
+// is one 9-point stencil launch with 16 dof, else two half-lattice hops),
+// then y_o = b_o - T_oe y_e and x = M y.  Stopping test |r_e| <= tol |b| on
+// the full right-hand side: the odd residual is zero.
 template <typename T>
 void eo_gcr(Solver& S, int l, const cplx<T>* b, cplx<T>* x_out, int nrhs, double tol, int maxiter, int m,
             hipStream_t st) {
