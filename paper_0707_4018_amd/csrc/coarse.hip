@@ -1396,6 +1396,8 @@ struct EoArgs {
   const cplx<T>* C;
   int L1, L2, nc, par, in_full, b_full;
   int nrhs;
+  cplx<T>* out2;  // optional second copy of out
+  cplx<T>* zero;  // optional half field set to zero
 };
 // NCM > 0: nc <= NCM; four adjacent lanes take the four directions of one
 // row, each issuing all loads of its direction at once (clamped column,
@@ -1459,17 +1461,19 @@ __global__ __launch_bounds__(256) void eo_hop_kernel(EoArgs<T> a0, const EoArgs<
         }
       }
     }
-    if (EPI == 0) {
-      a.out[oh + i] = mk<T>(sr, si);
-    } else {
+    cplx<T> v = mk<T>(sr, si);
+    if (EPI >= 1) {
       const cplx<T> bv = a.b[a.b_full ? of + s * nc + row : oh + i];
       if (EPI == 1) {
-        a.out[oh + i] = mk<T>(bv.x - sr, bv.y - si);
+        v = mk<T>(bv.x - sr, bv.y - si);
       } else {
         const cplx<T> b2v = a.b2[oh + i];
-        a.out[oh + i] = mk<T>(bv.x - b2v.x + sr, bv.y - b2v.y + si);
+        v = mk<T>(bv.x - b2v.x + sr, bv.y - b2v.y + si);
       }
     }
+    a.out[oh + i] = v;
+    if (a.out2) a.out2[oh + i] = v;
+    if (a.zero) a.zero[oh + i] = mk<T>(0, 0);
   }
 }
 
@@ -1543,6 +1547,8 @@ __global__ __launch_bounds__(256) void eo16_kernel(EoArgs<T> a0, const EoArgs<T>
         if (EPI == 1) v = mk<T>(bv[i].x - v.x, bv[i].y - v.y);
         if (EPI == 2) v = mk<T>(bv[i].x - b2v[i].x + v.x, bv[i].y - b2v[i].y + v.y);
         a.out[oh + h * K::NC + row] = v;
+        if (a.out2) a.out2[oh + h * K::NC + row] = v;
+        if (a.zero) a.zero[oh + h * K::NC + row] = mk<T>(0, 0);
       }
     }
   }
@@ -1729,11 +1735,12 @@ void launch_eo_split(double2* Ce, double2* Co, const double2* T, int L1, int L2,
 
 template <typename T>
 void launch_eo_hop(cplx<T>* out, const cplx<T>* in, const cplx<T>* b, const cplx<T>* b2, const cplx<T>* C, int L1,
-                   int L2, int nc, int par, int in_full, int b_full, int epi, int nrhs, hipStream_t st) {
+                   int L2, int nc, int par, int in_full, int b_full, int epi, int nrhs, hipStream_t st, cplx<T>* out2,
+                   cplx<T>* zero) {
   long nb = ((long)L1 * L2 / 2 * nc * (nc <= 16 ? 4 : 1) + 255) / 256;
   if (nb > (1L << 20)) nb = 1L << 20;
   const dim3 g((unsigned)nb, (unsigned)nrhs);
-  EoArgs<T> a{out, in, b, b2, C, L1, L2, nc, par, in_full, b_full, nrhs};
+  EoArgs<T> a{out, in, b, b2, C, L1, L2, nc, par, in_full, b_full, nrhs, out2, zero};
   if (nc == 16) {
     const long Vh = (long)L1 * L2 / 2;
     long nw = (Vh + 3) / 4;
@@ -1760,9 +1767,9 @@ void launch_eo_hop(cplx<T>* out, const cplx<T>* in, const cplx<T>* b, const cplx
   else dispatch(eo_hop_kernel<T, 2, 0>, a, g, dim3(256), st);
 }
 template void launch_eo_hop<double>(double2*, const double2*, const double2*, const double2*, const double2*, int, int,
-                                    int, int, int, int, int, int, hipStream_t);
+                                    int, int, int, int, int, int, hipStream_t, double2*, double2*);
 template void launch_eo_hop<float>(float2*, const float2*, const float2*, const float2*, const float2*, int, int, int,
-                                   int, int, int, int, int, hipStream_t);
+                                   int, int, int, int, int, hipStream_t, float2*, float2*);
 
 void launch_eo_schur_build(double2* S9, const double2* Ce, const double2* Co, int L1, int L2, int nc, hipStream_t st) {
   long nb = ((long)L1 * L2 / 2 * 9 * nc * nc + 255) / 256;
@@ -1777,7 +1784,7 @@ void launch_eo_s9(cplx<T>* out, const cplx<T>* in, const cplx<T>* b, const cplx<
   long nw = (Vh + 3) / 4;
   if (nw > (1L << 20)) nw = 1L << 20;
   const dim3 g((unsigned)nw, (unsigned)nrhs);
-  EoArgs<T> a{out, in, b, nullptr, S9, L1, L2, 16, 0, 0, 0, nrhs};
+  EoArgs<T> a{out, in, b, nullptr, S9, L1, L2, 16, 0, 0, 0, nrhs, nullptr, nullptr};
   if (epi == 0) dispatch(eo_s9_kernel<T, 0>, a, g, dim3(256), st);
   else dispatch(eo_s9_kernel<T, 1>, a, g, dim3(256), st);
 }

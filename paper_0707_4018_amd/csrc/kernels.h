@@ -205,9 +205,11 @@ void launch_block_apply(cplx<T>* out, const cplx<T>* in, const cplx<T>* M, long 
 // (epi 0: sum, 1: b - sum, 2: b - b2 + sum) and x = M (y_e, y_o)
 bool eo_supported(int nd, const int* dims, int nc);
 void launch_eo_split(double2* Ce, double2* Co, const double2* T, int L1, int L2, int nc, hipStream_t st);
+// (out2: optional second copy of the result; zero: optional half field set to zero)
 template <typename T>
 void launch_eo_hop(cplx<T>* out, const cplx<T>* in, const cplx<T>* b, const cplx<T>* b2, const cplx<T>* C, int L1,
-                   int L2, int nc, int par, int in_full, int b_full, int epi, int nrhs, hipStream_t st);
+                   int L2, int nc, int par, int in_full, int b_full, int epi, int nrhs, hipStream_t st,
+                   cplx<T>* out2 = nullptr, cplx<T>* zero = nullptr);
 // the reduced operator 1 - T_eo T_oe as a 9-point stencil of the even sites
 // (blocks [h][9][col][row], FP64 from the FP64 couplings) and its apply for
 // N_c = 16 (epi 0: sum, 1: b - sum)

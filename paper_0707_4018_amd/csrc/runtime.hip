@@ -439,12 +439,11 @@ void eo_gcr(Solver& S, int l, const cplx<T>* b, cplx<T>* x_out, int nrhs, double
     }
     S.nC += 1;
   };
-  launch_fill<T>(ye, nullptr, nh, nrhs, st);
   {
+    // b' = b_e - T_eo b_o, also into r; y_e = 0
     ProfScope ps(S, PK_EO, l, st);
-    launch_eo_hop<T>(bp, b, b, nullptr, Ce, L1, L2, nc, 0, 1, 1, 1, nrhs, st);  // b_e - T_eo b_o
+    launch_eo_hop<T>(bp, b, b, nullptr, Ce, L1, L2, nc, 0, 1, 1, 1, nrhs, st, r, ye);
   }
-  launch_fill<T>(r, bp, nh, nrhs, st);
   launch_norm2<T>(b, n, nrhs, S.sc.red(L.gs.bb), st);
   launch_set_flags(flags, S.outer_flags, S.sc.scal.as<double>(), L.gs.bb, L.gs.bb, tol2 >= 1.0 ? 1.0 : 0.0, nrhs, st);
   for (int it = 0; it < maxiter; ++it) {
