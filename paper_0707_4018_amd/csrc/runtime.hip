@@ -828,7 +828,14 @@ void build_transfer(Solver& S, int l, hipStream_t st) {
     launch_p_convert(C.Y32.p, P_F32, C.Y64.as<double2>(), ysz, st);
   }
   build_dense(S, l + 1, st);
-  build_jacobi(S, l + 1, st);
+  // block-Jacobi data only for a level that can be the coarsest of a cycle:
+  // the last level, or the next level while the adaptive setup is still
+  // adding vectors (its sweeps stop the cycle there)
+  if (l + 2 == (int)S.lv.size() || F.nv < F.nv_max) {
+    build_jacobi(S, l + 1, st);
+  } else {
+    C.jac = C.eo = C.s9 = false;
+  }
 }
 
 void check_params(const amg_gauge* g, const amg_mg_params* p) {
@@ -1819,7 +1826,8 @@ amg_status amg_solver_set_mass(amg_solver* S, double mass) {
       if (S->p.inner_prec == AMG_F32)
         launch_p_convert(L.Y32.p, P_F32, L.Y64.as<double2>(), L.V * L.ndir() * (long)L.dof * L.dof, nullptr);
       if (L.dense) build_dense(*S, (int)l, nullptr);
-      build_jacobi(*S, (int)l, nullptr);
+      if (l + 1 == S->lv.size()) build_jacobi(*S, (int)l, nullptr);  // (solves stop at the last level)
+      else L.jac = L.eo = L.s9 = false;
     }
     HIPC(hipStreamSynchronize(nullptr));
   }
